@@ -1,0 +1,227 @@
+/*
+ * bp.h -- C ABI of the MI355X (gfx950) baryon-pasting library, libbp.so.
+ *
+ * The library implements the data-parallel hot path of the baryon-pasting
+ * method of Osato & Nagai (2022, "Baryon Pasting Algorithm: Halo-based and
+ * Particle-based Pasting Methods"):
+ *   - the per-halo ICM solve (Sec. 2: polytropic gas in the NFW potential,
+ *     central density/pressure and gas boundary r_f fixed by energy
+ *     conservation, surface pressure and gas-mass conservation),
+ *   - line-of-sight projected electron-pressure and electron-density tables
+ *     (Sec. 3.3, the integrals of the HP map equations),
+ *   - halo-based pasting (HP) of Compton-y and kSZ b onto a flat-sky map or
+ *     onto HEALPix RING pixels (Sec. 3.3, Sec. 5.2),
+ *   - HEALPix RING ang2pix (Gorski et al. 2005, the pixelisation of Sec. 5.2).
+ *
+ * Conventions (every entry point):
+ *   - Array arguments are DEVICE pointers owned by the caller (allocated on
+ *     the current HIP device); scalar arguments and structs are host memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it; entry points return before it completes unless noted.
+ *   - Return value: BP_OK (0) or a negative BP_E* code.  Argument errors are
+ *     detected synchronously before anything is enqueued; device faults
+ *     surface through HIP at the next synchronising call.  Per-halo solver
+ *     failures are reported in a status array, never by the return value.
+ *   - The library never aborts and never throws across this boundary.  It
+ *     allocates no device memory: scratch comes through `ws` (workspace).
+ *   - Maps ACCUMULATE: the caller zeroes them; successive calls (halo
+ *     batches, HP + PP) add up.
+ *
+ * Units: masses Msun/h; halo radii physical Mpc/h; distances chi comoving
+ * Mpc/h; velocities km/s; angles radians; y and b dimensionless; gas
+ * density g/cm^3; pressures erg/cm^3.
+ */
+#ifndef BP_H
+#define BP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define BP_OK             0
+#define BP_E_ARG         -1   /* invalid argument (null pointer, bad size, bad parameter) */
+#define BP_E_HIP         -2   /* a HIP runtime call failed */
+#define BP_E_WORKSPACE   -3   /* workspace too small; *ws_needed holds the required bytes */
+#define BP_E_OVERFLOW    -4   /* an index or pair count exceeds what one call can hold */
+
+/* per-halo status bits written by bp_icm_solve (0 = solved) */
+#define BP_S_NO_BRACKET    1  /* energy residual has no sign change on the x_f scan */
+#define BP_S_MULTI_ROOT    2  /* more than one sign change; the first root is used (still valid) */
+#define BP_S_NO_STAR_ROOT  4  /* stellar mass >= baryon mass: stellar radius undefined */
+#define BP_S_NONFINITE     8  /* a non-finite intermediate */
+#define BP_S_BAD_INPUT    16  /* M <= 0, c <= 0, z < 0 or non-finite input */
+
+/* ------------------------------------------------------------- parameters */
+/* Cosmology (flat LCDM without radiation, Sec. 1) and the ICM model
+ * parameters of Table 1, plus the readings the paper leaves open. */
+typedef struct {
+    double Omega_m, Omega_b, h;
+    double Gamma;          /* adiabatic index; polytropic index n = 1/(Gamma-1) */
+    double eps_DM;         /* energy transfer from dark matter */
+    double eps_star;       /* stellar feedback efficiency */
+    double f_star, S_star; /* stellar-to-halo mass relation amplitude and slope */
+    double alpha_nt, beta_nt, n_nt;   /* non-thermal pressure fraction (Sec. 2.3) */
+    double X_H;            /* hydrogen mass fraction (Sec. 3.2) */
+    double trunc_r500;     /* projected footprint radius in units of r500 (3) */
+    double field_gas_frac; /* gas mass fraction of a PP field particle (default Omega_b/Omega_m) */
+    int32_t energy_sign;   /* 0: injected energy raises the gas energy (default);
+                              1: the energy equation as printed in Sec. 2.2 */
+    int32_t reserved;
+} bp_params;
+
+/* --------------------------------------------------- ICM solution layout */
+/* bp_icm_solve writes a structure-of-arrays of doubles: field f of halo i
+ * lives at sol[f * n + i].  The caller allocates BP_SOL_NFIELDS * n doubles. */
+enum {
+    BP_SOL_M = 0,     /* M_vir [Msun/h] (copy of the input) */
+    BP_SOL_C,         /* c_vir (copy of the input) */
+    BP_SOL_Z,         /* redshift (copy of the input) */
+    BP_SOL_RVIR,      /* virial radius, physical Mpc/h */
+    BP_SOL_RS,        /* scale radius r_vir / c */
+    BP_SOL_RHOS,      /* NFW scale density [(Msun/h)/(Mpc/h)^3] */
+    BP_SOL_R500,      /* r500 [Mpc/h] */
+    BP_SOL_M500,      /* M500 [Msun/h] */
+    BP_SOL_MSTAR,     /* stellar mass F_* M_vir [Msun/h] */
+    BP_SOL_XSTAR,     /* stellar radius over r_s */
+    BP_SOL_PS,        /* surface pressure [erg/cm^3] */
+    BP_SOL_EGI,       /* initial gas energy [erg] */
+    BP_SOL_A,         /* a = ((Gamma-1)/Gamma)(rho0/P0) G M_vir / r_vir (dimensionless) */
+    BP_SOL_XF,        /* r_f / r_vir */
+    BP_SOL_RF,        /* gas boundary r_f [Mpc/h] */
+    BP_SOL_RHO0,      /* central gas density [g/cm^3] */
+    BP_SOL_P0,        /* central total gas pressure [erg/cm^3] */
+    BP_SOL_CHI,       /* comoving distance [Mpc/h] */
+    BP_SOL_DA,        /* angular-diameter distance [physical Mpc/h] */
+    BP_SOL_TAU,       /* mean Thomson optical depth to z */
+    BP_SOL_FNT,       /* non-thermal amplitude f(z) */
+    BP_SOL_RT,        /* footprint radius min(r_f, trunc_r500 r500) [Mpc/h] */
+    BP_SOL_RES_E,     /* relative residual of the energy condition at the root */
+    BP_SOL_NFIELDS
+};
+
+/* ---------------------------------------------------------- table layout */
+/* bp_profile_tables writes, per halo, BP_TAB_STRIDE floats: the projected
+ * electron-pressure shape followed by the projected electron-density shape,
+ * each in three zones (A: the part of the sight line inside r_a = min(r_vir,
+ * r_f); S: the shell r_vir < r < r_f seen at r_perp < r_vir; B: sight lines
+ * with r_perp >= r_vir).  Each zone is tabulated on a uniform grid of a
+ * variable that makes the projected profile analytic, with the edge factor
+ * divided out:
+ *   zone A:  eta  = ln(1 + acosh(r_a / r_perp)),   Y = P_e0 u g_A(eta),
+ *            u = sqrt(r_a^2 - r_perp^2)
+ *   zone S:  omega = asinh(u_v / sqrt(D)),         Y = P_e0 (S - u_v) g_S(omega),
+ *            u_v = sqrt(r_vir^2 - r_perp^2), D = r_f^2 - r_vir^2, S = sqrt(u_v^2 + D)
+ *   zone B:  zeta = acosh(r_f / r_perp),           Y = P_e0 U g_B(zeta),
+ *            U = sqrt(r_f^2 - r_perp^2)
+ * (same with n_e0 for the density).  P_e0 and n_e0 are the central electron
+ * pressure and density.  Grid end points per halo are in `meta`
+ * (BP_META_NFIELDS floats per halo, SoA: field f of halo i at meta[f*n+i]). */
+#define BP_TAB_NA     192
+#define BP_TAB_NS      32
+#define BP_TAB_NB      32
+#define BP_TAB_ZONE   (BP_TAB_NA + BP_TAB_NS + BP_TAB_NB)   /* 256 per quantity */
+#define BP_TAB_STRIDE (2 * BP_TAB_ZONE)                      /* P then n: 512 floats */
+enum {
+    BP_META_ETA_LO = 0, BP_META_ETA_HI,
+    BP_META_OM_LO, BP_META_OM_HI,
+    BP_META_ZE_LO, BP_META_ZE_HI,
+    BP_META_PE0,      /* central electron pressure [erg/cm^3] */
+    BP_META_NE0,      /* central electron density [1/cm^3] */
+    BP_META_NFIELDS
+};
+
+/* ----------------------------------------------------------------- basics */
+int bp_version(void);
+const char *bp_strerror(int code);
+
+/* ---------------------------------------------------------- ICM solve (K1) */
+/* Solve the ICM model of Sec. 2 for n halos, one GPU lane per halo, FP64.
+ *   M, c, z      : device, n doubles each (M_vir [Msun/h], c_vir, redshift).
+ *   sol          : device, BP_SOL_NFIELDS * n doubles (SoA, layout above).
+ *   status       : device, n int32 (BP_S_* bits, 0 = solved).
+ * Halo structure (Sec. 2.1): Bryan & Norman Delta_vir relative to rho_crit,
+ * NFW with the given c.  Stars (Sec. 2.2): F_* from M500, stellar radius from
+ * f_b M(<r_*) = M_*.  The gas boundary x_f = r_f/r_vir is the first sign
+ * change of the energy residual on a 47-point scan of [0.4, 5], refined to
+ * 1e-13 relative; for each trial x_f the pressure condition is solved for a
+ * and the gas-mass condition fixes rho0.  n may be 0. */
+int bp_icm_solve(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,
+                 double *sol, int32_t *status, void *stream);
+
+/* -------------------------------------------------- projection tables (K2) */
+/* Projected electron pressure and density tables (layout above) for n
+ * solved halos.  Halos with a non-zero status get all-zero tables.
+ *   sol, status : outputs of bp_icm_solve (device).
+ *   tables      : device, BP_TAB_STRIDE * n floats.
+ *   meta        : device, BP_META_NFIELDS * n floats. */
+int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                      float *tables, float *meta, void *stream);
+
+/* ----------------------------------------------------- HP flat paste (K3) */
+/* Halo-based pasting onto an npix x npix flat-sky map (Sec. 3.3):
+ *   y[p] += sigma_T/(m_e c^2) Y_P(r_perp),  b[p] += sigma_T (v/c) e^-tau Y_n(r_perp)
+ * for every halo whose footprint r_perp < R_t = min(r_f, trunc_r500 r500)
+ * contains the centre of pixel p.  Pixel (i, j) has centre ((i+1/2) pix_rad,
+ * (j+1/2) pix_rad); maps are row-major [j][i] (npix*npix floats, device),
+ * r_perp = D_A |dtheta| on the tangent plane.
+ *   theta_x, theta_y : device, n doubles [rad];  v_los: device, n doubles [km/s]
+ *   sol, status, tables, meta : outputs of the two calls above
+ *   y_map, b_map     : device float maps, ACCUMULATED
+ *   ws, ws_bytes     : device workspace.  If ws_bytes is too small nothing is
+ *                      enqueued, *ws_needed receives the size and the call
+ *                      returns BP_E_WORKSPACE.  The size depends on the
+ *                      footprints, so this call synchronises `stream` once to
+ *                      read the (halo, tile) pair count.
+ * Each map pixel is owned by one lane; contributions are added in catalogue
+ * order with Kahan compensation, so results are deterministic. */
+int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n,
+                     const double *theta_x, const double *theta_y, const double *v_los,
+                     const double *sol, const int32_t *status, const float *tables, const float *meta,
+                     float *y_map, float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed,
+                     void *stream);
+
+/* ------------------------------------------------------- HEALPix (K9, K4) */
+/* HEALPix RING pixel index of each direction (Gorski et al. 2005).
+ *   theta: colatitude in [0, pi]; phi: longitude (any real, taken mod 2 pi).
+ *   ipix : device, n int64.  nside in [1, 2^29].  Integer results are
+ *   bit-exact reproducible (FP64, fixed operation order, no contraction). */
+int bp_healpix_ang2pix_ring(int64_t nside, int64_t n, const double *theta, const double *phi,
+                            int64_t *ipix, void *stream);
+
+/* HP onto HEALPix RING pixels (Sec. 5.2 maps): as bp_hp_paste_flat with
+ * r_perp = D_A sin(psi), psi the angle between pixel centre and halo centre
+ * (psi < pi/2).  theta/phi: halo colatitude/longitude; maps have 12 nside^2
+ * floats in RING order.  Same workspace protocol. */
+int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n,
+                        const double *theta, const double *phi, const double *v_los,
+                        const double *sol, const int32_t *status, const float *tables, const float *meta,
+                        float *y_map, float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed,
+                        void *stream);
+
+/* ------------------------------------------------------------- profiling */
+/* Optional timing of the library's main kernels with HIP events recorded on
+ * the launch stream (for roofline measurement).  bp_profiling(1) enables it
+ * and clears earlier records; bp_profile_read() waits for the recorded
+ * events and returns the summed duration and number of launches of one
+ * kernel since the last bp_profiling call.  Host-side only; not thread-safe
+ * with respect to concurrent launches on several streams. */
+enum {
+    BP_PROF_ICM = 0,        /* K1 k_icm_solve */
+    BP_PROF_TABLES,         /* K2 k_tables */
+    BP_PROF_FLAT_PLAN,      /* K3 setup + pair emission + sort + tile ranges */
+    BP_PROF_FLAT_DEPOSIT,   /* K3 k_flat_deposit */
+    BP_PROF_HPX_PLAN,       /* K4 planning */
+    BP_PROF_HPX_DEPOSIT,    /* K4 k_hpx_deposit */
+    BP_PROF_NKERNELS
+};
+int bp_profiling(int enable);
+int bp_profile_read(int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BP_H */

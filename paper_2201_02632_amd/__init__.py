@@ -1,0 +1,214 @@
+"""MI355X-native baryon pasting (Osato & Nagai 2022): Python binding of libbp.so.
+
+Every step of the hot path runs in the HIP kernels of ``libbp.so``; this
+module only marshals arguments (torch tensors on the GPU for device memory,
+the current torch stream as the HIP stream).  There is no CPU fallback: if the
+library is missing the import fails.
+
+Entry points mirror include/bp.h:
+    icm_solve, profile_tables, hp_paste_flat, healpix_ang2pix_ring, hp_paste_healpix
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libbp.so not built at {LIB_PATH}: run __graft_entry__.build() "
+                      "(the HIP library is required; there is no fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- mirrors --
+BP_OK, BP_E_ARG, BP_E_HIP, BP_E_WORKSPACE, BP_E_OVERFLOW = 0, -1, -2, -3, -4
+S_NO_BRACKET, S_MULTI_ROOT, S_NO_STAR_ROOT, S_NONFINITE, S_BAD_INPUT = 1, 2, 4, 8, 16
+
+SOL_FIELDS = ["M", "C", "Z", "RVIR", "RS", "RHOS", "R500", "M500", "MSTAR", "XSTAR", "PS", "EGI",
+              "A", "XF", "RF", "RHO0", "P0", "CHI", "DA", "TAU", "FNT", "RT", "RES_E"]
+SOL = {name: k for k, name in enumerate(SOL_FIELDS)}
+SOL_NFIELDS = len(SOL_FIELDS)
+
+TAB_NA, TAB_NS, TAB_NB = 192, 32, 32
+TAB_ZONE = TAB_NA + TAB_NS + TAB_NB
+TAB_STRIDE = 2 * TAB_ZONE
+META_FIELDS = ["ETA_LO", "ETA_HI", "OM_LO", "OM_HI", "ZE_LO", "ZE_HI", "PE0", "NE0"]
+META = {name: k for k, name in enumerate(META_FIELDS)}
+META_NFIELDS = len(META_FIELDS)
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "Omega_m", "Omega_b", "h", "Gamma", "eps_DM", "eps_star", "f_star", "S_star",
+        "alpha_nt", "beta_nt", "n_nt", "X_H", "trunc_r500", "field_gas_frac")] + [
+        ("energy_sign", C.c_int32), ("reserved", C.c_int32)]
+
+
+def default_params(**kw) -> Params:
+    """Table 1 of the paper; cosmology Omega_m = 0.3, h = 0.7 with the paper's Omega_b = 0.046."""
+    d = dict(Omega_m=0.3, Omega_b=0.046, h=0.7, Gamma=1.2, eps_DM=0.0, eps_star=3.97e-6,
+             f_star=0.026, S_star=0.12, alpha_nt=0.18, beta_nt=0.5, n_nt=0.8, X_H=0.76,
+             trunc_r500=3.0, field_gas_frac=0.046 / 0.3, energy_sign=0)
+    d.update(kw)
+    p = Params()
+    for k, v in d.items():
+        setattr(p, k, v)
+    return p
+
+
+_VP = C.c_void_p
+_P = C.POINTER(Params)
+_SIGS = {
+    "bp_version": (C.c_int, []),
+    "bp_strerror": (C.c_char_p, [C.c_int]),
+    "bp_icm_solve": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_profile_tables": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
+    "bp_hp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                   _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_healpix_ang2pix_ring": (C.c_int, [C.c_int64, C.c_int64, _VP, _VP, _VP, _VP]),
+    "bp_hp_paste_healpix": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                      _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+}
+EXPORTED = list(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class BPError(RuntimeError):
+    pass
+
+
+def _check(code, what):
+    if code != BP_OK:
+        raise BPError(f"{what}: {_lib.bp_strerror(code).decode()} ({code})")
+
+
+def _ptr(t: torch.Tensor):
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def version() -> int:
+    return _lib.bp_version()
+
+
+# ------------------------------------------------------------- entry points --
+def icm_solve(params: Params, M: torch.Tensor, c: torch.Tensor, z: torch.Tensor):
+    """K1: returns (sol [SOL_NFIELDS, n] float64, status [n] int32) on the device."""
+    n = M.numel()
+    dev = M.device
+    sol = torch.empty((SOL_NFIELDS, n), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    if n:
+        _check(_lib.bp_icm_solve(C.byref(params), n, _ptr(M), _ptr(c), _ptr(z), _ptr(sol), _ptr(status),
+                                 _stream()), "bp_icm_solve")
+    return sol, status
+
+
+def profile_tables(params: Params, sol: torch.Tensor, status: torch.Tensor):
+    """K2: returns (tables [n, TAB_STRIDE] float32, meta [META_NFIELDS, n] float32)."""
+    n = status.numel()
+    dev = status.device
+    tab = torch.empty((n, TAB_STRIDE), dtype=torch.float32, device=dev)
+    meta = torch.empty((META_NFIELDS, n), dtype=torch.float32, device=dev)
+    if n:
+        _check(_lib.bp_profile_tables(C.byref(params), n, _ptr(sol), _ptr(status), _ptr(tab), _ptr(meta),
+                                      _stream()), "bp_profile_tables")
+    return tab, meta
+
+
+class Workspace:
+    """Grow-only device workspace reused across calls."""
+
+    def __init__(self, device="cuda"):
+        self.buf = None
+        self.device = device
+
+    def ensure(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes * 1.25) + 4096, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws = {}
+
+
+def _ws_for(device):
+    key = str(device)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def _with_workspace(fn, what, ws, args):
+    need = C.c_size_t(0)
+    for _ in range(3):
+        buf = ws.buf
+        ptr = C.c_void_p(buf.data_ptr()) if buf is not None else C.c_void_p(0)
+        nbytes = buf.numel() if buf is not None else 0
+        code = fn(*args, ptr, nbytes, C.byref(need), _stream())
+        if code == BP_E_WORKSPACE:
+            ws.ensure(need.value)
+            continue
+        _check(code, what)
+        return
+    raise BPError(f"{what}: workspace negotiation did not converge")
+
+
+def hp_paste_flat(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v_los, sol, status, tables, meta,
+                  y_map, b_map, ws: Workspace | None = None):
+    """K3: accumulate the HP footprints of all halos into y_map, b_map ([npix, npix] float32)."""
+    ws = ws or _ws_for(y_map.device)
+    _with_workspace(_lib.bp_hp_paste_flat, "bp_hp_paste_flat", ws,
+                    (C.byref(params), int(npix), float(pix_rad), theta_x.numel(), _ptr(theta_x), _ptr(theta_y),
+                     _ptr(v_los), _ptr(sol), _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+
+
+def hp_paste_healpix(params: Params, nside: int, theta, phi, v_los, sol, status, tables, meta, y_map, b_map,
+                     ws: Workspace | None = None):
+    """K4: accumulate the HP footprints into HEALPix RING maps (12 nside^2 float32)."""
+    ws = ws or _ws_for(y_map.device)
+    _with_workspace(_lib.bp_hp_paste_healpix, "bp_hp_paste_healpix", ws,
+                    (C.byref(params), int(nside), theta.numel(), _ptr(theta), _ptr(phi), _ptr(v_los), _ptr(sol),
+                     _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+
+
+def healpix_ang2pix_ring(nside: int, theta: torch.Tensor, phi: torch.Tensor) -> torch.Tensor:
+    n = theta.numel()
+    out = torch.empty(n, dtype=torch.int64, device=theta.device)
+    if n:
+        _check(_lib.bp_healpix_ang2pix_ring(int(nside), n, _ptr(theta), _ptr(phi), _ptr(out), _stream()),
+               "bp_healpix_ang2pix_ring")
+    return out
+
+
+def hp_flat_map(params: Params, cat: dict, npix: int, pix_rad: float, device="cuda"):
+    """Convenience: full exact HP flat path (solve, tables, paste) for a catalogue of numpy arrays."""
+    t = {k: torch.as_tensor(v, dtype=torch.float64, device=device).contiguous() for k, v in cat.items()}
+    sol, status = icm_solve(params, t["M"], t["c"], t["z"])
+    tab, meta = profile_tables(params, sol, status)
+    y = torch.zeros((npix, npix), dtype=torch.float32, device=device)
+    b = torch.zeros_like(y)
+    hp_paste_flat(params, npix, pix_rad, t["theta_x"], t["theta_y"], t["v_los"], sol, status, tab, meta, y, b)
+    return y, b, sol, status
+
+
+def hp_healpix_map(params: Params, cat: dict, nside: int, device="cuda"):
+    """Convenience: exact HP path onto HEALPix RING pixels for a catalogue (theta, phi) of numpy arrays."""
+    t = {k: torch.as_tensor(v, dtype=torch.float64, device=device).contiguous() for k, v in cat.items()}
+    sol, status = icm_solve(params, t["M"], t["c"], t["z"])
+    tab, meta = profile_tables(params, sol, status)
+    y = torch.zeros(12 * nside * nside, dtype=torch.float32, device=device)
+    b = torch.zeros_like(y)
+    hp_paste_healpix(params, nside, t["theta"], t["phi"], t["v_los"], sol, status, tab, meta, y, b)
+    return y, b, sol, status

@@ -1,0 +1,321 @@
+// K3: halo-based pasting onto a flat-sky map (Sec. 3.3 of Osato & Nagai 2022).
+//
+// The map is cut into 16x16-pixel tiles.  Every halo emits one (tile, halo)
+// pair per tile that its footprint disc touches; the pairs are stably sorted
+// by tile, so each tile's list is in catalogue order.  One wavefront owns one
+// tile: lane l holds 4 pixels (column l%16, rows l/16 + 4k) with their y and b
+// sums and Kahan compensations in registers, walks the tile's halo list
+// (halo records are wave-uniform scalar loads), and writes the tile back
+// once.  No atomics touch the maps, and the summation order is fixed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bp_device.hpp"
+#include "bp_internal.hpp"
+#include "bp_footprint.hpp"
+
+namespace bp {
+
+constexpr int kTile = 16;
+
+// Per-halo paste record in pixel units (128 bytes).
+struct __attribute__((aligned(16))) FlatRec {
+    int32_t cxi, cyi;       // integer part of the centre in pixel units
+    float cxf, cyf;         // fractional part
+    float Rt2;              // footprint radius^2 [px^2]
+    float ra, ra2, rv2;     // r_a = min(r_vir, r_f), r_a^2, r_vir^2
+    float rf, rf2, D, sqD;  // r_f, r_f^2, r_f^2 - r_vir^2, sqrt(D)
+    float r2min;            // clamp of r_perp^2 at the centre
+    float eta_lo, eta_ih;   // zone A grid start and 1/step
+    float om_lo, om_ih;     // zone S
+    float ze_lo, ze_ih;     // zone B
+    float amp_y, amp_b;     // sigma_T/(m_e c^2) P_e0 L_pix ; sigma_T n_e0 L_pix (v/c) e^-tau
+    int32_t flags;          // bit0 shell (r_f > r_vir), bit1 zone B (R_t > r_vir), bit2 valid
+    float Rt_emit;          // footprint radius used by both the pair count and the emit pass
+    double cxd, cyd;        // fractional centre in FP64 (edge-annulus recompute)
+    double ra2d, rf2d;      // r_a^2, r_f^2 in FP64
+};
+static_assert(sizeof(FlatRec) == 128, "FlatRec size");
+
+__device__ inline void tile_row_range(double cx, double cy, double Rt, int ty, int ntx, int npix, int *tx0, int *tx1) {
+    // pixel rows of this tile: centres y in [16 ty + 0.5, 16 ty + 15.5]
+    double ylo = kTile * ty + 0.5, yhi = kTile * ty + kTile - 0.5;
+    double yc = fmin(fmax(cy, ylo), yhi);
+    double dy = fabs(yc - cy);
+    double R = Rt + 1.0;  // one-pixel margin: the deposit decides membership exactly
+    if (dy > R) { *tx0 = 1; *tx1 = 0; return; }
+    double hw = sqrt(R * R - dy * dy);
+    double xl = cx - hw - 0.5, xh = cx + hw - 0.5;  // pixel index range
+    int il = (int)fmax(floor(xl), 0.0), ih = (int)fmin(floor(xh) + 1.0, (double)(npix - 1));
+    if (il > ih) { *tx0 = 1; *tx1 = 0; return; }
+    *tx0 = il / kTile;
+    *tx1 = ih / kTile;
+    (void)ntx;
+}
+
+struct FlatGeom {
+    int npix, ntx;
+    double pix;
+};
+
+// Build records and count pairs.
+__global__ void __launch_bounds__(256) k_flat_setup(bp_params P, FlatGeom Gm, int64_t n, const double *__restrict__ thx,
+                                                    const double *__restrict__ thy, const double *__restrict__ vlos,
+                                                    const double *__restrict__ sol, const int32_t *__restrict__ status,
+                                                    const float *__restrict__ meta, FlatRec *__restrict__ rec,
+                                                    uint32_t *__restrict__ cnt, unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long part[4];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t count = 0;
+    if (i < n) {
+        FlatRec r = {};
+        auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
+        auto Mt = [&](int f) { return meta[(int64_t)f * n + i]; };
+        bool ok = !(status[i] & ~BP_S_MULTI_ROOT);
+        double DA = S(BP_SOL_DA);
+        double Lpix = DA * Gm.pix;       // physical Mpc/h per pixel
+        double inv = 1.0 / Lpix;
+        double cx = thx[i] / Gm.pix, cy = thy[i] / Gm.pix;
+        double Rt = S(BP_SOL_RT) * inv;
+        ok = ok && isfinite(cx) && isfinite(cy) && Rt > 0.0 && isfinite(Rt);
+        // drop halos whose disc misses the map entirely
+        ok = ok && (cx + Rt > 0.0) && (cy + Rt > 0.0) && (cx - Rt < Gm.npix) && (cy - Rt < Gm.npix);
+        if (ok) {
+            double rv = S(BP_SOL_RVIR) * inv, rf = S(BP_SOL_RF) * inv;
+            double ra = fmin(rv, rf);
+            double cxf = floor(cx), cyf = floor(cy);
+            r.cxi = (int32_t)cxf; r.cyi = (int32_t)cyf;
+            r.cxf = (float)(cx - cxf); r.cyf = (float)(cy - cyf);
+            r.Rt2 = (float)(Rt * Rt);
+            r.ra = (float)ra; r.ra2 = (float)(ra * ra); r.rv2 = (float)(rv * rv);
+            r.rf = (float)rf; r.rf2 = (float)(rf * rf);
+            r.cxd = cx - cxf; r.cyd = cy - cyf;
+            r.ra2d = ra * ra; r.rf2d = rf * rf;
+            bool shell = rf > rv;
+            double D = shell ? rf * rf - rv * rv : 0.0;
+            r.D = (float)D; r.sqD = (float)sqrt(D);
+            r.r2min = (float)(1e-10 * ra * ra);
+            float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
+            float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
+            float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
+            r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
+            r.om_lo = olo; r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
+            r.ze_lo = zlo; r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+            double Lcm = Lpix * kMpc / P.h;
+            r.amp_y = (float)(kSigmaT / kMeC2 * (double)Mt(BP_META_PE0) * Lcm);
+            r.amp_b = (float)(kSigmaT * (double)Mt(BP_META_NE0) * Lcm * (vlos[i] * 1e5 / kC) * exp(-S(BP_SOL_TAU)));
+            bool zoneB = Rt > rv;
+            r.flags = (shell ? 1 : 0) | (zoneB ? 2 : 0) | 4;
+            // count tiles touched; the emit pass repeats this loop with the same (float) radius
+            r.Rt_emit = (float)Rt;
+            double Rtd = (double)r.Rt_emit;
+            int ty0 = (int)fmax(floor((cy - Rtd - 1.5) / kTile), 0.0);
+            int ty1 = (int)fmin(floor((cy + Rtd + 0.5) / kTile), (double)(Gm.ntx - 1));
+            for (int ty = ty0; ty <= ty1; ++ty) {
+                int a, b;
+                tile_row_range(cx, cy, Rtd, ty, Gm.ntx, Gm.npix, &a, &b);
+                if (b >= a) count += (uint32_t)(b - a + 1);
+            }
+        }
+        rec[i] = r;
+        cnt[i] = count;
+    }
+    // block total of pair counts, in 64 bits, for the overflow check
+    unsigned long long v = count;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ void __launch_bounds__(256) k_flat_emit(FlatGeom Gm, int64_t n, const double *__restrict__ thx,
+                                                   const double *__restrict__ thy, const FlatRec *__restrict__ rec,
+                                                   const uint32_t *__restrict__ off, uint32_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !(rec[i].flags & 4)) return;
+    double cx = thx[i] / Gm.pix, cy = thy[i] / Gm.pix;
+    uint32_t o = off[i], end = off[i + 1];
+    uint32_t k = o;
+    double Rtd = (double)rec[i].Rt_emit;
+    int ty0 = (int)fmax(floor((cy - Rtd - 1.5) / kTile), 0.0);
+    int ty1 = (int)fmin(floor((cy + Rtd + 0.5) / kTile), (double)(Gm.ntx - 1));
+    for (int ty = ty0; ty <= ty1 && k < end; ++ty) {
+        int a, b;
+        tile_row_range(cx, cy, Rtd, ty, Gm.ntx, Gm.npix, &a, &b);
+        for (int tx = a; tx <= b && k < end; ++tx) {
+            keys[k] = (uint32_t)(ty * Gm.ntx + tx);
+            vals[k] = (uint32_t)i;
+            ++k;
+        }
+    }
+}
+
+__global__ void k_tile_ranges(const uint32_t *__restrict__ keys, int64_t np, uint32_t *__restrict__ tstart,
+                              uint32_t *__restrict__ tend, uint32_t ntiles) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    uint32_t k = keys[i];
+    if (k >= ntiles) return;
+    if (i == 0 || keys[i - 1] != k) tstart[k] = (uint32_t)i;
+    if (i == np - 1 || keys[i + 1] != k) tend[k] = (uint32_t)(i + 1);
+}
+
+// Membership of pixel (i, j): FP32 test, re-decided in FP64 next to the edge
+// with the same expression the definition uses: D_A |theta_pix - theta_h| < R_t.
+__device__ inline bool inside_fp64(int i, int j, double pix, double thx, double thy, double DA, double Rt) {
+#pragma clang fp contract(off)
+    double dx = (i + 0.5) * pix - thx, dy = (j + 0.5) * pix - thy;
+    double rp = DA * sqrt(dx * dx + dy * dy);
+    return rp < Rt;
+}
+
+__global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, const FlatRec *__restrict__ rec,
+                                                      const float *__restrict__ tables, const uint32_t *__restrict__ vals,
+                                                      const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
+                                                      const double *__restrict__ thx, const double *__restrict__ thy,
+                                                      const double *__restrict__ sol, float *__restrict__ ymap,
+                                                      float *__restrict__ bmap, int ntiles) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
+    const uint32_t p0 = tstart[tile], p1 = tend[tile];
+    if (p0 >= p1) return;
+    const int tx = tile % Gm.ntx, ty = tile / Gm.ntx;
+    const int pi = tx * kTile + (lane & 15);
+    const int pj0 = ty * kTile + (lane >> 4);
+    float ys[4], yc[4], bs[4], bc[4];
+    bool inmap[4];
+    for (int k = 0; k < 4; ++k) {
+        int pj = pj0 + 4 * k;
+        inmap[k] = (pi < Gm.npix) && (pj < Gm.npix);
+        int64_t idx = (int64_t)pj * Gm.npix + pi;
+        ys[k] = inmap[k] ? ymap[idx] : 0.0f;
+        bs[k] = inmap[k] ? bmap[idx] : 0.0f;
+        yc[k] = 0.0f; bc[k] = 0.0f;
+    }
+    for (uint32_t p = p0; p < p1; ++p) {
+        const uint32_t h = vals[p];
+        if (h >= (uint32_t)n) continue;
+        const FlatRec R = rec[h];
+        const float *tab = tables + (int64_t)h * BP_TAB_STRIDE;
+        const float dxb = (float)(pi - R.cxi) + (0.5f - R.cxf);
+        for (int k = 0; k < 4; ++k) {
+            const int pj = pj0 + 4 * k;
+            const float dy = (float)(pj - R.cyi) + (0.5f - R.cyf);
+            const float r2 = dxb * dxb + dy * dy;
+            bool in = r2 < R.Rt2;
+            if (fabsf(r2 - R.Rt2) <= 4e-6f * R.Rt2) {
+                const double DA = sol[(int64_t)BP_SOL_DA * n + h], Rt = sol[(int64_t)BP_SOL_RT * n + h];
+                in = inside_fp64(pi, pj, Gm.pix, thx[h], thy[h], DA, Rt);
+            }
+            if (in && inmap[k]) {
+                float u2 = R.ra2 - r2, U2 = R.rf2 - r2;
+                if (u2 < 0.1f * R.ra2 || U2 < 0.1f * R.rf2) {
+                    // edge annulus: the sqrt of a small difference needs the difference in FP64
+                    double dxd = (double)(pi - R.cxi) + (0.5 - R.cxd), dyd = (double)(pj - R.cyi) + (0.5 - R.cyd);
+                    double r2d = dxd * dxd + dyd * dyd;
+                    u2 = (float)(R.ra2d - r2d);
+                    U2 = (float)(R.rf2d - r2d);
+                }
+                float vp, vn;
+                footprint_value(R, tab, r2, u2, U2, &vp, &vn);
+                kahan_add(ys[k], yc[k], R.amp_y * vp);
+                kahan_add(bs[k], bc[k], R.amp_b * vn);
+            }
+        }
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (!inmap[k]) continue;
+        int64_t idx = (int64_t)(pj0 + 4 * k) * Gm.npix + pi;
+        ymap[idx] = ys[k];
+        bmap[idx] = bs[k];
+    }
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+extern "C" int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                                const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                                const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
+                                size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!p || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed) return BP_E_ARG;
+    if (n > 0 && (!theta_x || !theta_y || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
+    if (!y_map || !b_map) return BP_E_ARG;
+    if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) { *ws_needed = 0; return BP_OK; }
+    FlatGeom Gm;
+    Gm.npix = npix;
+    Gm.ntx = (npix + kTile - 1) / kTile;
+    Gm.pix = pix_rad;
+    const int64_t ntiles = (int64_t)Gm.ntx * Gm.ntx;
+    // phase-1 layout
+    Arena A1(nullptr, 0);
+    A1.take<FlatRec>(n);
+    A1.take<uint32_t>(n + 1);
+    A1.take<uint32_t>(n + 1);
+    A1.take<unsigned long long>(1);
+    size_t phase1 = A1.used + scan_ws_bytes(n + 1);
+    if (ws_bytes < phase1 || !ws) { *ws_needed = phase1 + 64; return BP_E_WORKSPACE; }
+    Arena A(ws, ws_bytes);
+    FlatRec *rec = A.take<FlatRec>(n);
+    uint32_t *cnt = A.take<uint32_t>(n + 1);
+    uint32_t *off = A.take<uint32_t>(n + 1);
+    unsigned long long *total = A.take<unsigned long long>(1);
+    void *scan_ws = (char *)ws + A.used;
+    A.used += scan_ws_bytes(n + 1);
+    if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
+    if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_flat_setup, dim3(blocks), dim3(256), 0, s, *p, Gm, n, theta_x, theta_y, v_los, sol, status,
+                       meta, rec, cnt, total);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    unsigned long long np64 = 0;
+    if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
+    if (np64 >= 0x7fffffffULL) return BP_E_OVERFLOW;
+    const int64_t np = (int64_t)np64;
+    // phase-2 layout (after the phase-1 part)
+    size_t need = A.used;
+    {
+        Arena B(nullptr, 0);
+        B.take<uint32_t>(np);
+        B.take<uint32_t>(np);
+        B.take<uint32_t>(np);
+        B.take<uint32_t>(np);
+        B.take<uint32_t>(ntiles);
+        B.take<uint32_t>(ntiles);
+        need += B.used + radix_ws_bytes(np) + 256;
+    }
+    if (ws_bytes < need) { *ws_needed = need; return BP_E_WORKSPACE; }
+    *ws_needed = need;
+    if (np == 0) return BP_OK;
+    uint32_t *k0 = A.take<uint32_t>(np), *v0 = A.take<uint32_t>(np);
+    uint32_t *k1 = A.take<uint32_t>(np), *v1 = A.take<uint32_t>(np);
+    uint32_t *tst = A.take<uint32_t>(ntiles), *ten = A.take<uint32_t>(ntiles);
+    void *sort_ws = (char *)ws + A.used;
+    prof_begin(BP_PROF_FLAT_PLAN, s);
+    int e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_flat_emit, dim3(blocks), dim3(256), 0, s, Gm, n, theta_x, theta_y, rec, off, k0, v0);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    int bits = 1;
+    while ((1LL << bits) < ntiles) ++bits;
+    bool in1 = false;
+    e = radix_sort_u32(k0, v0, k1, v1, np, bits, sort_ws, s, &in1);
+    if (e) return e;
+    uint32_t *ks = in1 ? k1 : k0, *vs = in1 ? v1 : v0;
+    if (fill_u32(tst, 0u, ntiles, s) || fill_u32(ten, 0u, ntiles, s)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, ks, np, tst, ten,
+                       (uint32_t)ntiles);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    prof_end(BP_PROF_FLAT_PLAN, s);
+    prof_begin(BP_PROF_FLAT_DEPOSIT, s);
+    hipLaunchKernelGGL(k_flat_deposit, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, Gm, n, rec, tables, vs,
+                       tst, ten, theta_x, theta_y, sol, y_map, b_map, (int)ntiles);
+    prof_end(BP_PROF_FLAT_DEPOSIT, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}

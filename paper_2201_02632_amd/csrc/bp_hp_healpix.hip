@@ -1,0 +1,376 @@
+// K4: halo-based pasting onto HEALPix RING pixels (the all-sky maps of
+// Sec. 5.2 of Osato & Nagai 2022; pixelisation of Gorski et al. 2005).
+//
+// Tiles are 64-pixel segments of one ring.  Each halo emits one (tile, halo)
+// pair per segment that its disc can touch; pairs are stably sorted by tile
+// and one wavefront owns a tile (one pixel per lane, y/b sums and Kahan
+// compensations in registers).  Per (halo, ring) the colatitude part of the
+// haversine, sin^2(dtheta/2), is formed in FP64; per pixel only
+// sin^2(dphi/2) is evaluated in FP32:
+//   hav = sin^2(dtheta/2) + sin(theta_r) sin(theta_h) sin^2(dphi/2),
+//   r_perp = D_A sin(psi) = 2 D_A sqrt(hav (1 - hav)),  psi < pi/2  <=>  hav < 1/2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bp_device.hpp"
+#include "bp_footprint.hpp"
+#include "bp_internal.hpp"
+
+namespace bp {
+
+constexpr int kSeg = 64;
+
+struct __attribute__((aligned(16))) HpxRec {
+    double th, ph, sth;     // halo colatitude, longitude in [0, 2 pi), sin(colatitude)
+    float Rt2;              // footprint radius^2 in units of L = D_A theta_pix
+    float ra, ra2, rv2;
+    float rf, rf2, D, sqD;
+    float r2min;
+    float eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih;
+    float amp_y, amp_b;
+    int32_t flags;          // bit0 shell, bit1 zone B, bit2 valid
+    float hmax;             // haversine bound used by count and emit (same value in both)
+    double ra2d, rf2d;      // r_a^2, r_f^2 in FP64 (edge-annulus recompute)
+    float pad[2];
+};
+static_assert(sizeof(HpxRec) == 128, "HpxRec size");
+
+struct HpxGeom {
+    int64_t N;          // nside
+    int32_t nrings;     // 4N - 1
+    double pixang;      // sqrt(4 pi / (12 N^2)): the unit length is D_A * pixang
+};
+
+// ring i (1-based): number of pixels, first pixel, colatitude and phi shift (in units of the pixel step)
+__host__ __device__ inline void ring_info(int64_t N, int64_t i, int64_t *npr, int64_t *off, double *theta,
+                                          double *shift) {
+    if (i < N) {
+        *npr = 4 * i; *off = 2 * i * (i - 1);
+        *theta = 2.0 * asin((double)i / (sqrt(6.0) * (double)N));
+        *shift = 0.5;
+    } else if (i <= 3 * N) {
+        *npr = 4 * N; *off = 2 * N * (N - 1) + 4 * N * (i - N);
+        *theta = acos((double)(2 * N - i) * 2.0 / (3.0 * (double)N));
+        *shift = ((i + N) & 1) ? 1.0 : 0.5;
+    } else {
+        int64_t k = 4 * N - i;
+        *npr = 4 * k; *off = 12 * N * N - 2 * k * (k + 1);
+        *theta = kPi - 2.0 * asin((double)k / (sqrt(6.0) * (double)N));
+        *shift = 0.5;
+    }
+}
+
+// real-valued ring coordinate of colatitude t (monotone), for bracketing
+__device__ inline double ring_coord(int64_t N, double t) {
+    double z = cos(t);
+    if (z > 2.0 / 3.0) return sqrt(6.0) * (double)N * sin(0.5 * t);
+    if (z < -2.0 / 3.0) return 4.0 * (double)N - sqrt(6.0) * (double)N * cos(0.5 * t);
+    return 2.0 * (double)N - 1.5 * (double)N * z;
+}
+
+__global__ void k_ring_tiles(int64_t N, int32_t nrings, uint32_t *__restrict__ ntiles_ring) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrings) return;
+    int64_t npr, off; double th, sh;
+    ring_info(N, i + 1, &npr, &off, &th, &sh);
+    ntiles_ring[i] = (uint32_t)((npr + kSeg - 1) / kSeg);
+}
+
+// Visit the tiles a halo's disc can touch, ring by ring.  f(tile) is called in a
+// deterministic order; count and emit use this same routine.
+template <class F>
+__device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const uint32_t *__restrict__ ring_tile_off,
+                                     F &&f) {
+    double hmax = (double)R.hmax;
+    double psi = 2.0 * asin(sqrt(fmin(hmax, 1.0)));
+    double tlo = R.th - psi, thi = R.th + psi;
+    int64_t ilo = (tlo <= 0.0) ? 1 : (int64_t)floor(ring_coord(G.N, tlo)) - 1;
+    int64_t ihi = (thi >= kPi) ? 4 * G.N - 1 : (int64_t)ceil(ring_coord(G.N, thi)) + 1;
+    if (ilo < 1) ilo = 1;
+    if (ihi > 4 * G.N - 1) ihi = 4 * G.N - 1;
+    for (int64_t i = ilo; i <= ihi; ++i) {
+        int64_t npr, off; double thr, sh;
+        ring_info(G.N, i, &npr, &off, &thr, &sh);
+        double sd = sin(0.5 * (thr - R.th));
+        double A = sd * sd;
+        if (A > hmax) continue;
+        double B = sin(thr) * R.sth;
+        int64_t nt = (npr + kSeg - 1) / kSeg;
+        uint32_t base = ring_tile_off[i - 1];
+        double q = (B > 0.0) ? (hmax - A) / B : 2.0;
+        if (q >= 1.0) {
+            for (int64_t t = 0; t < nt; ++t) f(base + (uint32_t)t);
+            continue;
+        }
+        double dphi_max = 2.0 * asin(sqrt(q));
+        double step = 2.0 * kPi / (double)npr;
+        // pixel centre phi_j = (j + 1 - shift) step, j = 0..npr-1 (ring-local)
+        int64_t jlo = (int64_t)floor((R.ph - dphi_max) / step - 1.0 + sh) - 1;
+        int64_t jhi = (int64_t)floor((R.ph + dphi_max) / step - 1.0 + sh) + 2;
+        if (jhi - jlo + 1 >= npr) {
+            for (int64_t t = 0; t < nt; ++t) f(base + (uint32_t)t);
+            continue;
+        }
+        int64_t a = ((jlo % npr) + npr) % npr, b = ((jhi % npr) + npr) % npr;
+        int64_t ta = a / kSeg, tb = b / kSeg;
+        if (a <= b) {
+            for (int64_t t = ta; t <= tb; ++t) f(base + (uint32_t)t);
+        } else if (tb >= ta) {  // wrapped ranges share a tile: take the whole ring
+            for (int64_t t = 0; t < nt; ++t) f(base + (uint32_t)t);
+        } else {
+            for (int64_t t = 0; t <= tb; ++t) f(base + (uint32_t)t);
+            for (int64_t t = ta; t < nt; ++t) f(base + (uint32_t)t);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64_t n, const double *__restrict__ th,
+                                                   const double *__restrict__ ph, const double *__restrict__ vlos,
+                                                   const double *__restrict__ sol, const int32_t *__restrict__ status,
+                                                   const float *__restrict__ meta,
+                                                   const uint32_t *__restrict__ ring_tile_off, HpxRec *__restrict__ rec,
+                                                   uint32_t *__restrict__ cnt, unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long part[4];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t count = 0;
+    if (i < n) {
+        HpxRec r = {};
+        auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
+        auto Mt = [&](int f) { return meta[(int64_t)f * n + i]; };
+        double t = th[i], p = ph[i];
+        bool ok = !(status[i] & ~BP_S_MULTI_ROOT) && t >= 0.0 && t <= kPi && isfinite(p);
+        double DA = S(BP_SOL_DA);
+        double L = DA * G.pixang;
+        double inv = 1.0 / L;
+        double Rt = S(BP_SOL_RT);
+        ok = ok && Rt > 0.0 && Rt < DA;
+        if (ok) {
+            double rv = S(BP_SOL_RVIR) * inv, rf = S(BP_SOL_RF) * inv, ra = fmin(rv, rf), Rtu = Rt * inv;
+            p = p - 2.0 * kPi * floor(p / (2.0 * kPi));
+            r.th = t; r.ph = p; r.sth = sin(t);
+            r.Rt2 = (float)(Rtu * Rtu);
+            r.ra = (float)ra; r.ra2 = (float)(ra * ra); r.rv2 = (float)(rv * rv);
+            r.rf = (float)rf; r.rf2 = (float)(rf * rf);
+            r.ra2d = ra * ra; r.rf2d = rf * rf;
+            bool shell = rf > rv;
+            double D = shell ? rf * rf - rv * rv : 0.0;
+            r.D = (float)D; r.sqD = (float)sqrt(D);
+            r.r2min = (float)(1e-10 * ra * ra);
+            float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
+            float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
+            float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
+            r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
+            r.om_lo = olo; r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
+            r.ze_lo = zlo; r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+            double Lcm = L * kMpc / P.h;
+            r.amp_y = (float)(kSigmaT / kMeC2 * (double)Mt(BP_META_PE0) * Lcm);
+            r.amp_b = (float)(kSigmaT * (double)Mt(BP_META_NE0) * Lcm * (vlos[i] * 1e5 / kC) * exp(-S(BP_SOL_TAU)));
+            r.flags = (shell ? 1 : 0) | ((Rtu > rv) ? 2 : 0) | 4;
+            // haversine of the footprint's angular radius (sin psi_max = R_t / D_A), padded for rounding
+            double sp = Rt / DA;
+            double hav = (sp > 1e-4) ? 0.5 * (1.0 - cos(asin(sp))) : 0.25 * sp * sp * (1.0 + 0.25 * sp * sp);
+            r.hmax = (float)(hav * (1.0 + 1e-5) + 1e-30);
+            for_each_tile(G, r, ring_tile_off, [&](uint32_t) { ++count; });
+        }
+        rec[i] = r;
+        cnt[i] = count;
+    }
+    unsigned long long v = count;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(total, part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ void __launch_bounds__(256) k_hpx_emit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
+                                                  const uint32_t *__restrict__ ring_tile_off,
+                                                  const uint32_t *__restrict__ off, uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const HpxRec r = rec[i];
+    if (!(r.flags & 4)) return;
+    uint32_t k = off[i], end = off[i + 1];
+    for_each_tile(G, r, ring_tile_off, [&](uint32_t tile) {
+        if (k < end) { keys[k] = tile; vals[k] = (uint32_t)i; ++k; }
+    });
+}
+
+__global__ void k_hpx_ranges(const uint32_t *__restrict__ keys, int64_t np, uint32_t *__restrict__ tstart,
+                             uint32_t *__restrict__ tend, uint32_t ntiles) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    uint32_t k = keys[i];
+    if (k >= ntiles) return;
+    if (i == 0 || keys[i - 1] != k) tstart[k] = (uint32_t)i;
+    if (i == np - 1 || keys[i + 1] != k) tend[k] = (uint32_t)(i + 1);
+}
+
+// Exact membership next to the edge, in FP64 with the defining expression:
+// sin(psi) = |n_pix x n_halo|, n_pix . n_halo > 0, D_A sin(psi) < R_t.
+__device__ inline bool hpx_inside_fp64(double tp, double pp, double th, double ph, double DA, double Rt) {
+#pragma clang fp contract(off)
+    double px = sin(tp) * cos(pp), py = sin(tp) * sin(pp), pz = cos(tp);
+    double hx = sin(th) * cos(ph), hy = sin(th) * sin(ph), hz = cos(th);
+    double dot = px * hx + py * hy + pz * hz;
+    if (!(dot > 0)) return false;
+    double cx = py * hz - pz * hy, cy = pz * hx - px * hz, cz = px * hy - py * hx;
+    return DA * sqrt(cx * cx + cy * cy + cz * cz) < Rt;
+}
+
+__global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
+                                                     const float *__restrict__ tables, const uint32_t *__restrict__ vals,
+                                                     const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
+                                                     const uint32_t *__restrict__ ring_tile_off,
+                                                     const double *__restrict__ thin, const double *__restrict__ phin,
+                                                     const double *__restrict__ sol, float *__restrict__ ymap,
+                                                     float *__restrict__ bmap, uint32_t ntiles) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
+    const uint32_t p0 = tstart[tile], p1 = tend[tile];
+    if (p0 >= p1) return;
+    // ring of this tile: last ring whose first tile is <= tile
+    int lo = 0, hi = G.nrings - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (ring_tile_off[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const int64_t ring = lo + 1;
+    int64_t npr, poff; double thr, sh;
+    ring_info(G.N, ring, &npr, &poff, &thr, &sh);
+    const int64_t jl = (int64_t)(tile - ring_tile_off[lo]) * kSeg + lane;
+    const bool valid = jl < npr;
+    const int64_t pix = poff + jl;
+    // pixel-centre longitude as the pixelisation defines it: (pi/2)/(npr/4) * (j - shift), j = jl + 1
+    const double phj = 1.5707963267948966 / (double)(npr / 4) * ((double)(jl + 1) - sh);
+    const double sthr = sin(thr);
+    const float inv_pix2 = (float)(1.0 / (G.pixang * G.pixang));
+    float ys = valid ? ymap[pix] : 0.0f, bs = valid ? bmap[pix] : 0.0f, yc = 0.0f, bc = 0.0f;
+    for (uint32_t p = p0; p < p1; ++p) {
+        const uint32_t h = vals[p];
+        if (h >= (uint32_t)n) continue;
+        const HpxRec R = rec[h];
+        const double sd = sin(0.5 * (thr - R.th));
+        const float A = (float)(sd * sd), B = (float)(sthr * R.sth);
+        const float s = sinf(0.5f * (float)(phj - R.ph));
+        const float hv = A + B * s * s;
+        const float r2 = 4.0f * hv * (1.0f - hv) * inv_pix2;
+        bool in = (hv < 0.5f) && (r2 < R.Rt2);
+        if (fabsf(r2 - R.Rt2) <= 4e-6f * R.Rt2 || fabsf(hv - 0.5f) < 1e-6f) {
+            const double DA = sol[(int64_t)BP_SOL_DA * n + h], Rt = sol[(int64_t)BP_SOL_RT * n + h];
+            // pixel centre as the pixelisation defines it
+            in = hpx_inside_fp64(thr, phj, thin[h], phin[h], DA, Rt);
+        }
+        if (in && valid) {
+            float u2 = R.ra2 - r2, U2 = R.rf2 - r2;
+            if (u2 < 0.1f * R.ra2 || U2 < 0.1f * R.rf2) {
+                // edge annulus: recompute the haversine in FP64 so sqrt(r_a^2 - r^2) keeps its digits
+                double sp = sin(0.5 * (phj - R.ph));
+                double hvd = sd * sd + sthr * R.sth * sp * sp;
+                double r2d = 4.0 * hvd * (1.0 - hvd) / (G.pixang * G.pixang);
+                u2 = (float)(R.ra2d - r2d);
+                U2 = (float)(R.rf2d - r2d);
+            }
+            float vp, vn;
+            footprint_value(R, tables + (int64_t)h * BP_TAB_STRIDE, r2, u2, U2, &vp, &vn);
+            kahan_add(ys, yc, R.amp_y * vp);
+            kahan_add(bs, bc, R.amp_b * vn);
+        }
+    }
+    if (valid) { ymap[pix] = ys; bmap[pix] = bs; }
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+extern "C" int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n, const double *theta,
+                                   const double *phi, const double *v_los, const double *sol, const int32_t *status,
+                                   const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
+                                   size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!p || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
+    if (n > 0 && (!theta || !phi || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
+    if (!y_map || !b_map) return BP_E_ARG;
+    if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
+    if (n == 0) { *ws_needed = 0; return BP_OK; }
+    hipStream_t s = (hipStream_t)stream;
+    HpxGeom G;
+    G.N = nside;
+    G.nrings = (int32_t)(4 * nside - 1);
+    G.pixang = sqrt(4.0 * kPi / (12.0 * (double)nside * (double)nside));
+    Arena A1(nullptr, 0);
+    A1.take<HpxRec>(n);
+    A1.take<uint32_t>(n + 1);
+    A1.take<uint32_t>(n + 1);
+    A1.take<unsigned long long>(1);
+    A1.take<uint32_t>(G.nrings + 1);
+    A1.take<uint32_t>(G.nrings + 1);
+    size_t phase1 = A1.used + scan_ws_bytes(n + 1) + scan_ws_bytes(G.nrings + 1);
+    if (ws_bytes < phase1 || !ws) { *ws_needed = phase1 + 64; return BP_E_WORKSPACE; }
+    Arena A(ws, ws_bytes);
+    HpxRec *rec = A.take<HpxRec>(n);
+    uint32_t *cnt = A.take<uint32_t>(n + 1);
+    uint32_t *off = A.take<uint32_t>(n + 1);
+    unsigned long long *total = A.take<unsigned long long>(1);
+    uint32_t *rtiles = A.take<uint32_t>(G.nrings + 1);
+    uint32_t *roff = A.take<uint32_t>(G.nrings + 1);
+    void *scan_ws = (char *)ws + A.used;
+    A.used += scan_ws_bytes(n + 1) + scan_ws_bytes(G.nrings + 1);
+    // tiles per ring and their prefix (the total lands in roff[nrings])
+    if (fill_u32(rtiles + G.nrings, 0u, 1, s)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_ring_tiles, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, rtiles);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    int e = scan_exclusive_u32(rtiles, roff, G.nrings + 1, scan_ws, s);
+    if (e) return e;
+    if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
+    if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_hpx_setup, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status, meta,
+                       roff, rec, cnt, total);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    unsigned long long np64 = 0;
+    uint32_t ntiles32 = 0;
+    if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
+    if (hipMemcpyAsync(&ntiles32, roff + G.nrings, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return BP_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
+    if (np64 >= 0x7fffffffULL) return BP_E_OVERFLOW;
+    const int64_t np = (int64_t)np64, ntiles = ntiles32;
+    size_t need = A.used;
+    {
+        Arena B(nullptr, 0);
+        for (int q = 0; q < 4; ++q) B.take<uint32_t>(np);
+        B.take<uint32_t>(ntiles);
+        B.take<uint32_t>(ntiles);
+        need += B.used + radix_ws_bytes(np) + 256;
+    }
+    if (ws_bytes < need) { *ws_needed = need; return BP_E_WORKSPACE; }
+    *ws_needed = need;
+    if (np == 0) return BP_OK;
+    uint32_t *k0 = A.take<uint32_t>(np), *v0 = A.take<uint32_t>(np);
+    uint32_t *k1 = A.take<uint32_t>(np), *v1 = A.take<uint32_t>(np);
+    uint32_t *tst = A.take<uint32_t>(ntiles), *ten = A.take<uint32_t>(ntiles);
+    void *sort_ws = (char *)ws + A.used;
+    prof_begin(BP_PROF_HPX_PLAN, s);
+    e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, s, G, n, rec, roff, off, k0, v0);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    int bits = 1;
+    while ((1LL << bits) < ntiles) ++bits;
+    bool in1 = false;
+    e = radix_sort_u32(k0, v0, k1, v1, np, bits, sort_ws, s, &in1);
+    if (e) return e;
+    uint32_t *ks = in1 ? k1 : k0, *vs = in1 ? v1 : v0;
+    if (fill_u32(tst, 0u, ntiles, s) || fill_u32(ten, 0u, ntiles, s)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_hpx_ranges, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, ks, np, tst, ten,
+                       (uint32_t)ntiles);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    prof_end(BP_PROF_HPX_PLAN, s);
+    prof_begin(BP_PROF_HPX_DEPOSIT, s);
+    hipLaunchKernelGGL(k_hpx_deposit, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, G, n, rec, tables, vs, tst,
+                       ten, roff, theta, phi, sol, y_map, b_map, (uint32_t)ntiles);
+    prof_end(BP_PROF_HPX_DEPOSIT, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}

@@ -1,0 +1,559 @@
+// K1 (ICM boundary-condition solve) and K2 (projected profile tables).
+//
+// K1: one lane per halo, FP64 (Sec. 2 of Osato & Nagai 2022).  For a trial
+// gas boundary x_f = r_f/r_vir the polytrope integrals are polynomials in the
+// slope a, since theta = 1 - a phi(r):
+//     int 4 pi r^2 theta^n dr = sum_k C(n,k) (-a)^k mu_k,   mu_k = int 4 pi r^2 phi^k dr
+// so each x_f costs one set of moments mu_0..mu_6 (Gauss-Legendre in
+// ln(1+r/r_s) inside r_vir and ln r outside, where the integrands are
+// analytic), after which the pressure condition is a degree-6 polynomial in a
+// solved by safeguarded Newton, and the energy residual is a few Horner sums.
+//
+// K2: one workgroup per halo, one lane per table node; each node is a
+// sight-line integral evaluated by Gauss-Legendre in s with l = r_perp sinh s,
+// which removes both the sqrt edge at r_perp and the central cusp.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bp_device.hpp"
+#include "bp_internal.hpp"
+
+namespace bp {
+
+// Per-halo constants of the solve (astrophysical units).
+struct HaloSolve {
+    double c, mc, rv, rs, V2, rhos;
+    double Mg;       // f_b M - M_*  (gas mass inside r_f)
+    double Ps;       // surface pressure
+    double Egi;      // initial gas energy
+    double Einj;     // eps_DM |E_DM| + eps_* M_* c^2
+    double phi_out0; // c^2 / ((1+c) m(c)):  phi_out(r) = phi_out0 - r_vir/r
+    double cm;       // c / m(c):  phi_in(x) = cm (1 - ln(1+x)/x)
+    double gfac;     // (Gamma-1)/Gamma
+    int energy_sign;
+};
+
+__device__ inline double binom(int n, int k) {
+    const double t[8][8] = {{1}, {1, 1}, {1, 2, 1}, {1, 3, 3, 1}, {1, 4, 6, 4, 1}, {1, 5, 10, 10, 5, 1},
+                            {1, 6, 15, 20, 15, 6, 1}, {1, 7, 21, 35, 35, 21, 7, 1}};
+    return t[n][k];
+}
+
+// Moments mu_k = int_0^{r_f} 4 pi r^2 phi(r)^k dr, k = 0..6, and phi(r_f).
+__device__ void moments(const HaloSolve &H, const GaussRules &G, double xf, double mu[7], double *phif) {
+    for (int k = 0; k < 7; ++k) mu[k] = 0.0;
+    const double fourpi = 4.0 * kPi;
+    // inner part: x = r/r_s in [0, X1], substitute s = ln(1+x)
+    double X1 = (xf < 1.0 ? xf : 1.0) * H.c;
+    double S1 = log1p(X1);
+    double rs3 = H.rs * H.rs * H.rs;
+    for (int j = 0; j < 16; ++j) {
+        double s = 0.5 * S1 * (G.x16[j] + 1.0);
+        double x = expm1(s);
+        double ph = H.cm * nfw_phi_shape(x);
+        double w = 0.5 * S1 * G.w16[j] * fourpi * rs3 * x * x * (1.0 + x);
+        double pk = 1.0;
+        for (int k = 0; k < 7; ++k) { mu[k] += w * pk; pk *= ph; }
+    }
+    if (xf > 1.0) {  // outer shell r in [r_vir, r_f], substitute t = ln r
+        double t0 = log(H.rv), t1 = log(xf * H.rv);
+        double ht = 0.5 * (t1 - t0);
+        for (int j = 0; j < 16; ++j) {
+            double r = exp(t0 + ht * (G.x16[j] + 1.0));
+            double ph = H.phi_out0 - H.rv / r;
+            double w = ht * G.w16[j] * fourpi * r * r * r;
+            double pk = 1.0;
+            for (int k = 0; k < 7; ++k) { mu[k] += w * pk; pk *= ph; }
+        }
+        *phif = H.phi_out0 - 1.0 / xf;
+    } else {
+        *phif = H.cm * nfw_phi_shape(xf * H.c);
+    }
+}
+
+// I_n(a) = int 4 pi r^2 (1 - a phi)^n dr from the moments; J(a) = int 4 pi r^2 phi (1-a phi)^5 dr.
+__device__ inline double poly_I(const double mu[7], int n, double a) {
+    double s = 0.0, ak = 1.0;
+    for (int k = 0; k <= n; ++k) { s += binom(n, k) * ak * mu[k]; ak *= -a; }
+    return s;
+}
+__device__ inline double poly_J5(const double mu[7], double a) {
+    double s = 0.0, ak = 1.0;
+    for (int k = 0; k <= 5; ++k) { s += binom(5, k) * ak * mu[k + 1]; ak *= -a; }
+    return s;
+}
+
+// Pressure condition for given moments: F(a) = gfac Mg V2 (1 - a phif)^6 - Ps a I5(a) = 0
+// on (0, 1/phif).  F is a degree-6 polynomial with F(0) > 0 > F(1/phif); the
+// root is unique on this interval for the model's parameter range.
+__device__ double solve_a(const HaloSolve &H, const double mu[7], double phif, double a_guess) {
+    double C0 = H.gfac * H.Mg * H.V2;
+    // coefficients of F in powers of a
+    double f[7];
+    for (int k = 0; k < 7; ++k) {
+        double t = C0 * binom(6, k);
+        for (int q = 0; q < k; ++q) t *= -phif;
+        f[k] = t;
+    }
+    for (int k = 0; k <= 5; ++k) {  // - Ps a sum C(5,k)(-a)^k mu_k
+        double t = -H.Ps * binom(5, k) * mu[k];
+        if (k & 1) t = -t;
+        f[k + 1] += t;
+    }
+    double lo = 0.0, hi = 1.0 / phif;
+    double a = (a_guess > lo && a_guess < hi) ? a_guess : 0.5 * hi;
+    for (int it = 0; it < 100; ++it) {
+        double F = f[6], dF = 0.0;
+        for (int k = 5; k >= 0; --k) { dF = dF * a + F; F = F * a + f[k]; }
+        if (F > 0) lo = a; else hi = a;
+        double an = a - F / dF;
+        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+        if (fabs(an - a) <= 1e-15 * an || hi - lo <= 1e-15 * hi) { a = an; break; }
+        a = an;
+    }
+    return a;
+}
+
+struct Trial { double res, a, rho0, P0; };
+
+// Energy residual (Sec. 2.2) at trial x_f; also returns a, rho0, P0.
+__device__ Trial energy_trial(const HaloSolve &H, const GaussRules &G, double xf, double a_guess) {
+    double mu[7], phif;
+    moments(H, G, xf, mu, &phif);
+    Trial T;
+    T.a = solve_a(H, mu, phif, a_guess);
+    double I5 = poly_I(mu, 5, T.a), I6 = poly_I(mu, 6, T.a), J5 = poly_J5(mu, T.a);
+    T.rho0 = H.Mg / I5;
+    T.P0 = H.gfac * T.rho0 * H.V2 / T.a;
+    double Phi0 = -H.V2 * H.phi_out0;
+    double Egf = 1.5 * T.P0 * I6 + T.rho0 * (Phi0 * I5 + H.V2 * J5);
+    double rf = xf * H.rv;
+    double dEp = 4.0 * kPi / 3.0 * (H.rv * H.rv * H.rv - rf * rf * rf) * H.Ps;
+    double res = (H.energy_sign == 0) ? Egf - (H.Egi + H.Einj + dEp) : H.Egi - (Egf + H.Einj + dEp);
+    T.res = res / fabs(H.Egi);
+    return T;
+}
+
+// Jeans integral I(x): closed form for x <= 2, else quadrature in s = ln(t/x)
+// (the closed form cancels badly at large x).
+__device__ double jeans_I_dev(double x, const GaussRules &G) {
+    if (x <= 2.0) return jeans_I(x);
+    const double smax = 12.0;  // integrand ~ s e^{-4s}
+    double acc = 0.0;
+    for (int j = 0; j < 24; ++j) {
+        double s = 0.5 * smax * (G.x24[j] + 1.0);
+        double t = x * exp(s);
+        acc += G.w24[j] * nfw_m(t) * exp(-2.0 * s) / ((1.0 + t) * (1.0 + t));
+    }
+    return 0.5 * smax * acc / (x * x);
+}
+
+// Closed-form initial energy of matter in [x_lo, c] (without f_b): kinetic part
+// by parts with the Jeans equation, potential part from elementary antiderivatives.
+__device__ double energy_closed(double c, double mc, double A, double xlo, const GaussRules &G) {
+    double kin_b = c * c * c * jeans_I_dev(c, G) - (xlo > 0 ? xlo * xlo * xlo * jeans_I_dev(xlo, G) : 0.0);
+    double K = 0.5 * A * (kin_b + kin_prim(c) - kin_prim(xlo));
+    auto wprim = [&](double x) { return -log1p(x) / (1.0 + x) - 1.0 / (1.0 + x) - nfw_m(x) / (1.0 + c); };
+    double W = -A * (wprim(c) - wprim(xlo));
+    return K + W;
+}
+
+// Comoving-distance and optical-depth integrands on [0, z] by 24-point GL.
+__device__ void distances(const bp_params &P, const GaussRules &G, double z, double *chi, double *tauint) {
+    double a1 = 0.0, a2 = 0.0;
+    for (int j = 0; j < 24; ++j) {
+        double zz = 0.5 * z * (G.x24[j] + 1.0);
+        double zp = 1.0 + zz;
+        double E = sqrt(P.Omega_m * zp * zp * zp + 1.0 - P.Omega_m);
+        a1 += G.w24[j] / E;
+        a2 += G.w24[j] * zp * zp / E;
+    }
+    *chi = 0.5 * z * a1;     // in units of c/H0
+    *tauint = 0.5 * z * a2;
+}
+
+#define NSCAN 47
+
+__global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min,
+                                                  const double *__restrict__ cin, const double *__restrict__ zin,
+                                                  double *__restrict__ sol, int32_t *__restrict__ status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double M = Min[i], c = cin[i], z = zin[i];
+    auto S = [&](int f) -> double & { return sol[(int64_t)f * n + i]; };
+    for (int f = 0; f < BP_SOL_NFIELDS; ++f) S(f) = 0.0;
+    S(BP_SOL_M) = M; S(BP_SOL_C) = c; S(BP_SOL_Z) = z;
+    if (!(M > 0.0) || !(c > 0.0) || !(z >= 0.0) || !isfinite(M) || !isfinite(c) || !isfinite(z)) {
+        status[i] = BP_S_BAD_INPUT;
+        return;
+    }
+    int st = 0;
+    const double h = P.h;
+    // --- structure (Sec. 2.1) ---
+    double zp = 1.0 + z, zp3 = zp * zp * zp;
+    double E2 = P.Omega_m * zp3 + 1.0 - P.Omega_m;
+    // rho_crit today in (Msun/h)/(Mpc/h)^3: 3 (100 km/s/Mpc)^2 / (8 pi G)
+    double rho_c = 3.0 * 1e4 / (8.0 * kPi * kGastro) * E2;
+    double xbn = P.Omega_m * zp3 / E2 - 1.0;
+    double Dvir = 18.0 * kPi * kPi + 82.0 * xbn - 39.0 * xbn * xbn;
+    double rv = cbrt(3.0 * M / (4.0 * kPi * Dvir * rho_c));
+    double rs = rv / c, mc = nfw_m(c);
+    double rhos = M / (4.0 * kPi * rs * rs * rs * mc);
+    S(BP_SOL_RVIR) = rv; S(BP_SOL_RS) = rs; S(BP_SOL_RHOS) = rhos;
+
+    // --- r500: ln(3 rho_s m(x)/x^3) = ln(500 rho_c), safeguarded Newton in ln x ---
+    double target = log(500.0 * rho_c / (3.0 * rhos));
+    double llo = log(c) - 30.0, lhi = log(c), lx = log(c) - 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double x = exp(lx), m = nfw_m(x);
+        double g = log(m) - 3.0 * lx - target;      // decreasing in ln x
+        if (g > 0) llo = lx; else lhi = lx;
+        double dg = x * nfw_dm(x) / m - 3.0;
+        double ln_new = lx - g / dg;
+        if (!(ln_new > llo && ln_new < lhi)) ln_new = 0.5 * (llo + lhi);
+        if (fabs(ln_new - lx) < 1e-15 || lhi - llo < 1e-15) { lx = ln_new; break; }
+        lx = ln_new;
+    }
+    double x500 = exp(lx);
+    double r500 = x500 * rs, M500 = 4.0 * kPi * rhos * rs * rs * rs * nfw_m(x500);
+    S(BP_SOL_R500) = r500; S(BP_SOL_M500) = M500;
+
+    // --- stars (Sec. 2.2); the 3e14 Msun pivot is in Msun ---
+    double fb = P.Omega_b / P.Omega_m;
+    double Fs = P.f_star * pow(M500 / h / 3e14, -P.S_star);
+    double Mstar = Fs * M;
+    S(BP_SOL_MSTAR) = Mstar;
+    double ratio = Mstar / (fb * M);
+    if (!(ratio < 1.0)) { status[i] = BP_S_NO_STAR_ROOT; return; }
+    double mt = ratio * mc;
+    double xlo = 0.0, xhi = c, xs = (mt < 1e-3) ? sqrt(2.0 * mt) : 0.5 * c;
+    for (int it = 0; it < 200; ++it) {
+        double g = nfw_m(xs) - mt;  // increasing
+        if (g < 0) xlo = xs; else xhi = xs;
+        double xn = xs - g / nfw_dm(xs);
+        if (!(xn > xlo && xn < xhi)) xn = 0.5 * (xlo + xhi);
+        if (fabs(xn - xs) <= 1e-15 * xn || xhi - xlo <= 1e-15 * xhi) { xs = xn; break; }
+        xs = xn;
+    }
+    S(BP_SOL_XSTAR) = xs;
+
+    // --- energies and surface pressure ---
+    HaloSolve H;
+    H.c = c; H.mc = mc; H.rv = rv; H.rs = rs; H.rhos = rhos;
+    H.V2 = kGastro * M / rv;
+    H.Mg = fb * M - Mstar;
+    double A = kGastro * (M / mc) * (M / mc) / rs;  // G M0^2 / r_s
+    H.Ps = fb * 4.0 * kPi * kGastro * rhos * rhos * rs * rs * jeans_I_dev(c, G);
+    H.Egi = fb * energy_closed(c, mc, A, xs, G);
+    double EDM = energy_closed(c, mc, A, 0.0, G);
+    H.Einj = P.eps_DM * fabs(EDM) + P.eps_star * Mstar * kCkms * kCkms;
+    H.phi_out0 = c * c / ((1.0 + c) * mc);
+    H.cm = c / mc;
+    H.gfac = (P.Gamma - 1.0) / P.Gamma;
+    H.energy_sign = P.energy_sign;
+    // unit conversions to CGS
+    const double u_len = kMpc / h, u_mass = kMsun / h;
+    const double u_rho = u_mass / (u_len * u_len * u_len);
+    const double u_P = u_rho * 1e10;
+    S(BP_SOL_PS) = H.Ps * u_P;
+    S(BP_SOL_EGI) = H.Egi * u_mass * 1e10;
+
+    // --- scan x_f, then Brent on the first sign change ---
+    double xprev = 0.0, rprev = 0.0, aprev = 0.0;
+    double bx0 = 0.0, bx1 = 0.0, br0 = 0.0, br1 = 0.0, ba = 0.0;
+    int nchg = 0;
+    double aguess = 0.0;
+    for (int k = 0; k < NSCAN; ++k) {
+        double xf = 0.4 + (5.0 - 0.4) * k / (NSCAN - 1);
+        Trial T = energy_trial(H, G, xf, aguess);
+        aguess = T.a;
+        if (!isfinite(T.res)) { st |= BP_S_NONFINITE; break; }
+        if (k > 0 && ((rprev < 0) != (T.res < 0))) {
+            if (nchg == 0) { bx0 = xprev; bx1 = xf; br0 = rprev; br1 = T.res; ba = aprev; }
+            ++nchg;
+        }
+        xprev = xf; rprev = T.res; aprev = T.a;
+    }
+    if (!st && nchg == 0) st |= BP_S_NO_BRACKET;
+    if (st) { status[i] = st; return; }
+    if (nchg > 1) st |= BP_S_MULTI_ROOT;
+    // Brent's method (bisection / secant / inverse quadratic interpolation)
+    double a = bx0, b = bx1, fa = br0, fbv = br1, cc = a, fc = fa, d = b - a, e = d;
+    double xtol = 1e-13 * bx0, aguess2 = ba;
+    for (int it = 0; it < 200; ++it) {
+        if ((fbv > 0 && fc > 0) || (fbv < 0 && fc < 0)) { cc = a; fc = fa; d = b - a; e = d; }
+        if (fabs(fc) < fabs(fbv)) { a = b; b = cc; cc = a; fa = fbv; fbv = fc; fc = fa; }
+        double tol = 2.0 * 2.220446049250313e-16 * fabs(b) + 0.5 * xtol;
+        double m = 0.5 * (cc - b);
+        if (fabs(m) <= tol || fbv == 0.0) break;
+        if (fabs(e) >= tol && fabs(fa) > fabs(fbv)) {
+            double s = fbv / fa, p, q;
+            if (a == cc) { p = 2.0 * m * s; q = 1.0 - s; }
+            else {
+                double qq = fa / fc, r = fbv / fc;
+                p = s * (2.0 * m * qq * (qq - r) - (b - a) * (r - 1.0));
+                q = (qq - 1.0) * (r - 1.0) * (s - 1.0);
+            }
+            if (p > 0) q = -q; else p = -p;
+            if (2.0 * p < fmin(3.0 * m * q - fabs(tol * q), fabs(e * q))) { e = d; d = p / q; }
+            else { d = m; e = m; }
+        } else { d = m; e = m; }
+        a = b; fa = fbv;
+        b += (fabs(d) > tol) ? d : (m > 0 ? tol : -tol);
+        Trial T = energy_trial(H, G, b, aguess2);
+        aguess2 = T.a;
+        fbv = T.res;
+    }
+    double xf = b;
+    Trial T = energy_trial(H, G, xf, aguess2);
+    S(BP_SOL_A) = T.a;
+    S(BP_SOL_XF) = xf;
+    S(BP_SOL_RF) = xf * rv;
+    S(BP_SOL_RHO0) = T.rho0 * u_rho;
+    S(BP_SOL_P0) = T.P0 * u_P;
+    S(BP_SOL_RES_E) = T.res;
+
+    // --- distances, optical depth, non-thermal amplitude ---
+    double chi_u, tau_u;
+    distances(P, G, z, &chi_u, &tau_u);
+    double cH = kCkms / 100.0;  // c/H0 in Mpc/h
+    double chi = cH * chi_u;
+    S(BP_SOL_CHI) = chi;
+    S(BP_SOL_DA) = chi / zp;
+    double H0 = 100.0 * h * 1e5 / kMpc;
+    double rho_cr0 = 3.0 * H0 * H0 / (8.0 * kPi * kG);
+    double ne_bar = P.Omega_b * rho_cr0 / (2.0 / (1.0 + P.X_H) * kMp);
+    S(BP_SOL_TAU) = kSigmaT * ne_bar * (kC / H0) * tau_u;
+    double fmax = pow(4.0, -P.n_nt) / P.alpha_nt;
+    double fz = fmin(pow(zp, P.beta_nt), (fmax - 1.0) * tanh(P.beta_nt * z) + 1.0);
+    S(BP_SOL_FNT) = fz;
+    S(BP_SOL_RT) = fmin(xf * rv, P.trunc_r500 * r500);
+    if (!isfinite(T.rho0) || !isfinite(T.P0) || !isfinite(xf)) st |= BP_S_NONFINITE;
+    status[i] = st;
+}
+
+// ---------------------------------------------------------------- tables --
+// Electron pressure and density relative to their central values at radius r
+// (analytic profile, no cut at r_f: the table edge nodes need the limit).
+struct Prof {
+    double rv, rs, rf, cm, phi_out0, a, inv_r500, ant_f, n_nt;
+};
+__device__ inline void prof_eval(const Prof &Q, double r, double *pe, double *ne) {
+    double ph = (r < Q.rv) ? Q.cm * nfw_phi_shape(r / Q.rs) : Q.phi_out0 - Q.rv / r;
+    double th = 1.0 - Q.a * ph;
+    if (th < 0.0) th = 0.0;
+    double th2 = th * th, th5 = th2 * th2 * th;
+    // non-thermal fraction R_nt = alpha f(z) (r/r500)^n_nt (single precision is ample: 1 - R_nt >= ~0.3 inside R_t)
+    float rnt = (float)Q.ant_f * __expf((float)Q.n_nt * __logf((float)(r * Q.inv_r500)));
+    double fth = (rnt < 1.0f) ? 1.0 - (double)rnt : 0.0;
+    *pe = th5 * th * fth;
+    *ne = th5;
+}
+
+__global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules G, int64_t n,
+                                                         const double *__restrict__ sol,
+                                                         const int32_t *__restrict__ status,
+                                                         float *__restrict__ tab, float *__restrict__ meta) {
+    const int64_t i = blockIdx.x;
+    const int node = threadIdx.x;
+    auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
+    float *tP = tab + (int64_t)i * BP_TAB_STRIDE;
+    float *tN = tP + BP_TAB_ZONE;
+    if (status[i] & ~BP_S_MULTI_ROOT) {
+        tP[node] = 0.0f; tN[node] = 0.0f;
+        if (node < BP_META_NFIELDS) meta[(int64_t)node * n + i] = 0.0f;
+        return;
+    }
+    Prof Q;
+    Q.rv = S(BP_SOL_RVIR); Q.rs = S(BP_SOL_RS); Q.rf = S(BP_SOL_RF);
+    double c = S(BP_SOL_C), mc = nfw_m(c);
+    Q.cm = c / mc; Q.phi_out0 = c * c / ((1.0 + c) * mc);
+    Q.a = S(BP_SOL_A);
+    Q.inv_r500 = 1.0 / S(BP_SOL_R500);
+    Q.ant_f = P.alpha_nt * S(BP_SOL_FNT);
+    Q.n_nt = P.n_nt;
+    const double Rt = S(BP_SOL_RT);
+    const double ra = fmin(Q.rv, Q.rf);
+    const double rmin = 1e-5 * ra;
+    // zone ranges
+    const double eta_lo = log1p(acosh(ra / fmin(Rt, ra)));
+    const double eta_hi = log1p(acosh(ra / rmin));
+    const bool shell = Q.rf > Q.rv;
+    const double D = shell ? Q.rf * Q.rf - Q.rv * Q.rv : 0.0;
+    const double sD = sqrt(D);
+    double om_lo = 0.0, om_hi = 0.0, ze_lo = 0.0, ze_hi = 0.0;
+    if (shell) {
+        double rtop = fmin(Rt, Q.rv);
+        om_lo = asinh(sqrt(fmax(Q.rv * Q.rv - rtop * rtop, 0.0)) / sD);
+        om_hi = asinh(Q.rv / sD);
+    }
+    const bool zoneB = Rt > Q.rv;
+    if (zoneB) { ze_lo = acosh(Q.rf / Rt); ze_hi = acosh(Q.rf / Q.rv); }
+
+    double accP = 0.0, accN = 0.0;
+    if (node < BP_TAB_NA) {
+        // zone A: g_A = Y_A / (P_e0 u), Y_A = 2 int_0^xi P(r_perp cosh s) r_perp cosh s ds
+        double eta = eta_lo + (eta_hi - eta_lo) * node / (BP_TAB_NA - 1);
+        double xi = expm1(eta);
+        if (xi < 1e-7) {  // limit r_perp -> r_a
+            double pe, ne;
+            prof_eval(Q, ra, &pe, &ne);
+            accP = 2.0 * pe; accN = 2.0 * ne;
+        } else {
+            double rp = ra / cosh(xi);
+            double u = ra * tanh(xi);
+            // 16 nodes reach 1e-11 up to xi ~ 6 (sight lines off the core); 24 beyond
+            const bool wide = xi > 5.5;
+            const int ng = wide ? 24 : 16;
+            const double *gx = wide ? G.x24 : G.x16, *gw = wide ? G.w24 : G.w16;
+            for (int j = 0; j < ng; ++j) {
+                double s = 0.5 * xi * (gx[j] + 1.0);
+                double r = rp * cosh(s);
+                double pe, ne;
+                prof_eval(Q, fmin(r, ra), &pe, &ne);
+                double w = gw[j] * r;
+                accP += w * pe; accN += w * ne;
+            }
+            double f = xi / u;  // 2 * (xi/2) / u
+            accP *= f; accN *= f;
+        }
+    } else if (node < BP_TAB_NA + BP_TAB_NS) {
+        // zone S: g_S = Y_S / (P_e0 (S - u_v)), Y_S over the shell r_vir < r < r_f
+        if (shell) {
+            int k = node - BP_TAB_NA;
+            double om = om_lo + (om_hi - om_lo) * k / (BP_TAB_NS - 1);
+            double uv = sD * sinh(om);
+            double Sv = sqrt(uv * uv + D);
+            double rp = sqrt(fmax(Q.rv * Q.rv - uv * uv, 0.0));
+            rp = fmax(rp, 1e-7 * Q.rv);
+            double s0 = acosh(Q.rv / rp), s1 = acosh(Q.rf / rp);
+            double hs = 0.5 * (s1 - s0);
+            for (int j = 0; j < 12; ++j) {
+                double s = s0 + hs * (G.x12[j] + 1.0);
+                double r = fmin(fmax(rp * cosh(s), Q.rv), Q.rf);
+                double pe, ne;
+                prof_eval(Q, r, &pe, &ne);
+                double w = G.w12[j] * r;
+                accP += w * pe; accN += w * ne;
+            }
+            double f = 2.0 * hs / (D / (Sv + uv));
+            accP *= f; accN *= f;
+        }
+    } else {
+        // zone B: g_B = Y_B / (P_e0 U), sight lines with r_perp >= r_vir
+        if (zoneB) {
+            int k = node - BP_TAB_NA - BP_TAB_NS;
+            double ze = ze_lo + (ze_hi - ze_lo) * k / (BP_TAB_NB - 1);
+            if (ze < 1e-7) {
+                double pe, ne;
+                prof_eval(Q, Q.rf, &pe, &ne);
+                accP = 2.0 * pe; accN = 2.0 * ne;
+            } else {
+                double rp = Q.rf / cosh(ze);
+                double U = Q.rf * tanh(ze);
+                for (int j = 0; j < 12; ++j) {
+                    double s = 0.5 * ze * (G.x12[j] + 1.0);
+                    double r = fmax(fmin(rp * cosh(s), Q.rf), Q.rv);
+                    double pe, ne;
+                    prof_eval(Q, r, &pe, &ne);
+                    double w = G.w12[j] * r;
+                    accP += w * pe; accN += w * ne;
+                }
+                double f = ze / U;
+                accP *= f; accN *= f;
+            }
+        }
+    }
+    tP[node] = (float)accP;
+    tN[node] = (float)accN;
+    if (node == 0) {
+        const double u_len = kMpc / P.h, u_mass = kMsun / P.h;
+        double X = P.X_H;
+        double Pe0 = (2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0);
+        double ne0 = S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp);
+        (void)u_len; (void)u_mass;
+        meta[(int64_t)BP_META_ETA_LO * n + i] = (float)eta_lo;
+        meta[(int64_t)BP_META_ETA_HI * n + i] = (float)eta_hi;
+        meta[(int64_t)BP_META_OM_LO * n + i] = (float)om_lo;
+        meta[(int64_t)BP_META_OM_HI * n + i] = (float)om_hi;
+        meta[(int64_t)BP_META_ZE_LO * n + i] = (float)ze_lo;
+        meta[(int64_t)BP_META_ZE_HI * n + i] = (float)ze_hi;
+        meta[(int64_t)BP_META_PE0 * n + i] = (float)Pe0;
+        meta[(int64_t)BP_META_NE0 * n + i] = (float)ne0;
+    }
+}
+
+// ------------------------------------------------------- Gauss-Legendre --
+// Nodes and weights of the n-point rule on [-1,1] by Newton iteration on P_n.
+static void gauss_legendre(int n, double *x, double *w) {
+    for (int i = 0; i < n; ++i) {
+        double z = cos(kPi * (i + 0.75) / (n + 0.5)), pp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p1 = 1.0, p2 = 0.0;
+            for (int j = 1; j <= n; ++j) { double p3 = p2; p2 = p1; p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j; }
+            pp = n * (z * p1 - p2) / (z * z - 1.0);
+            double z1 = z;
+            z = z1 - p1 / pp;
+            if (fabs(z - z1) < 1e-16) break;
+        }
+        x[i] = -z;
+        w[i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+const GaussRules &gauss_rules() {
+    static GaussRules G;
+    static bool init = false;
+    if (!init) {
+        gauss_legendre(16, G.x16, G.w16);
+        gauss_legendre(24, G.x24, G.w24);
+        gauss_legendre(12, G.x12, G.w12);
+        init = true;
+    }
+    return G;
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+static int check_params(const bp_params *p) {
+    if (!p) return BP_E_ARG;
+    if (!(p->Omega_m > 0 && p->Omega_m <= 1.0) || !(p->Omega_b > 0 && p->Omega_b < p->Omega_m) || !(p->h > 0) ||
+        !(p->Gamma > 1.0) || !(p->alpha_nt > 0) || !(p->n_nt > 0) || !(p->trunc_r500 > 0) ||
+        !(p->X_H > 0 && p->X_H <= 1) || (p->energy_sign != 0 && p->energy_sign != 1))
+        return BP_E_ARG;
+    return BP_OK;
+}
+
+extern "C" int bp_icm_solve(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,
+                            double *sol, int32_t *status, void *stream) {
+    int e = check_params(p);
+    if (e) return e;
+    if (n < 0) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if (!M || !c || !z || !sol || !status) return BP_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffff) return BP_E_OVERFLOW;
+    prof_begin(BP_PROF_ICM, s);
+    hipLaunchKernelGGL(k_icm_solve, dim3((unsigned)blocks), dim3(64), 0, s, *p, gauss_rules(), n, M, c, z, sol,
+                       status);
+    prof_end(BP_PROF_ICM, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                                 float *tables, float *meta, void *stream) {
+    int e = check_params(p);
+    if (e) return e;
+    if (n < 0) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if (!sol || !status || !tables || !meta) return BP_E_ARG;
+    if (n > 0x7fffffff) return BP_E_OVERFLOW;
+    prof_begin(BP_PROF_TABLES, (hipStream_t)stream);
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_ZONE), 0, (hipStream_t)stream, *p, gauss_rules(),
+                       n, sol, status, tables, meta);
+    prof_end(BP_PROF_TABLES, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}

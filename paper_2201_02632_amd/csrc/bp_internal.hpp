@@ -1,0 +1,47 @@
+// Host-side helpers shared between the libbp translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bp_device.hpp"
+
+namespace bp {
+
+const GaussRules &gauss_rules();
+
+// Bump allocator over a caller-provided workspace; sizes rounded to 256 B.
+struct Arena {
+    char *base;
+    size_t cap, used;
+    explicit Arena(void *p, size_t c) : base((char *)p), cap(c), used(0) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+        T *r = (T *)(base ? base + used : nullptr);
+        used += bytes;
+        return r;
+    }
+    bool fits() const { return used <= cap && base != nullptr; }
+};
+
+// Exclusive prefix sum of n uint32 values (in != out allowed or equal).
+size_t scan_ws_bytes(int64_t n);
+int scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, void *ws, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs on key bits [0, bits).
+// Ping-pongs between (k0, v0) and (k1, v1); returns via *result_in_k1
+// whether the sorted data ended in k1/v1.
+size_t radix_ws_bytes(int64_t n);
+int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits, void *ws,
+                   hipStream_t s, bool *result_in_k1);
+
+// Optional kernel timing (bp_profiling): event pair around one launch.
+void prof_begin(int id, hipStream_t s);
+void prof_end(int id, hipStream_t s);
+
+// Fill n uint32 with a value (a kernel, safe under graph capture).
+int fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+
+}  // namespace bp

@@ -1,0 +1,41 @@
+"""Host-side checks of the C-ABI library (no GPU calls)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bp.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(bp_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2201_02632_amd as bp   # loads libbp.so; fails loudly if it is not built
+    lib = ctypes.CDLL(bp.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 6
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_mirrors_header():
+    import paper_2201_02632_amd as bp
+    src = open(HEADER).read()
+    enum = re.search(r"enum \{\s*BP_SOL_M = 0,(.*?)BP_SOL_NFIELDS", src, flags=re.S).group(1)
+    names = ["M"] + re.findall(r"BP_SOL_(\w+)", enum)
+    assert names == bp.SOL_FIELDS
+    for k, v in (("BP_TAB_NA", bp.TAB_NA), ("BP_TAB_NS", bp.TAB_NS), ("BP_TAB_NB", bp.TAB_NB)):
+        assert int(re.search(rf"#define {k}\s+(\d+)", src).group(1)) == v
+    meta = re.search(r"enum \{\s*BP_META_ETA_LO = 0,(.*?)BP_META_NFIELDS", src, flags=re.S).group(1)
+    assert ["ETA_LO"] + re.findall(r"BP_META_(\w+)", meta) == bp.META_FIELDS
+    assert bp.version() >= 100
+    assert ctypes.sizeof(bp.Params) == 14 * 8 + 8
+
+
+def test_strerror_without_gpu():
+    import paper_2201_02632_amd as bp
+    assert bp._lib.bp_strerror(bp.BP_E_WORKSPACE) == b"workspace too small"
