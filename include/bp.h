@@ -202,6 +202,43 @@ int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n,
                         float *y_map, float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed,
                         void *stream);
 
+/* ------------------------------------------------------- PP (K5-K8) */
+/* Smoothing lengths for particle-based pasting (Sec. 3.4): h_i is the
+ * distance from particle i to its k-th nearest OTHER particle in comoving
+ * Cartesian coordinates (chi theta_x, chi theta_y, chi), chi the comoving
+ * distance of the particle redshift (flat-sky small-angle frame).
+ *   theta_x, theta_y : device, n floats [rad];  z: device, n floats (0 <= z < 16)
+ *   k                : neighbour count, 1 <= k <= 64 (the paper's workloads use 32)
+ *   cell             : coarse grid cell [comoving Mpc/h]; 0 selects 2.0.  Any value
+ *                      gives the exact k-th distance; it only tunes the search.
+ *   h_comoving       : device, n floats, OUTPUT [comoving Mpc/h]; NaN for a particle
+ *                      with fewer than k neighbours within the largest search block.
+ * Workspace protocol as for the pastes (one synchronisation for the bounding box).
+ * Returns BP_E_ARG for n <= k, a redshift outside [0, 16) or a non-finite angle. */
+int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
+                           const float *z, int32_t k, double cell, float *h_comoving, void *ws, size_t ws_bytes,
+                           size_t *ws_needed, void *stream);
+
+/* Particle-based pasting onto an npix x npix flat-sky map (Sec. 3.4):
+ *   halo particle (halo_id >= 0): y_i = sigma_T/(m_e c^2) P_e(r_i) V_i / L_pix^2,
+ *       b_i = sigma_T (v_i/c) e^-tau_i n_e(r_i) V_i / L_pix^2,  V_i = M_p / rho_NFW(r_i)
+ *       (untruncated NFW density; P_e = n_e = 0 for r_i >= r_f);
+ *   field particle (halo_id < 0): y_i = 0,
+ *       b_i = sigma_T (v_i/c) (field_gas_frac M_p / (mu_e m_p)) e^-tau_i / L_pix^2;
+ *   L_pix = D_A(z_i) pix_rad.  Each amplitude is spread with the separable
+ *   integrated cubic-spline kernel of angular half-width H = h_comoving/chi:
+ *   pixel (i, j) receives amp [w((x_i+ - x)/H) - w((x_i- - x)/H)] [same in y];
+ *   pixels outside the map are dropped (no renormalisation).
+ *   r_halo: device floats, the particle's radius in its halo [physical Mpc/h];
+ *   halo_id indexes the n_halos solved halos (sol, status from bp_icm_solve).
+ *   M_p: particle mass [Msun/h].  Maps ACCUMULATE; deterministic order.
+ *   Workspace protocol as for the halo pastes (one synchronisation). */
+int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const float *theta_x,
+                     const float *theta_y, const float *z, const float *v_los, const int32_t *halo_id,
+                     const float *r_halo, const float *h_comoving, double M_p, int64_t n_halos, const double *sol,
+                     const int32_t *status, float *y_map, float *b_map, void *ws, size_t ws_bytes,
+                     size_t *ws_needed, void *stream);
+
 /* ------------------------------------------------------------- profiling */
 /* Optional timing of the library's main kernels with HIP events recorded on
  * the launch stream (for roofline measurement).  bp_profiling(1) enables it
@@ -216,6 +253,10 @@ enum {
     BP_PROF_FLAT_DEPOSIT,   /* K3 k_flat_deposit */
     BP_PROF_HPX_PLAN,       /* K4 planning */
     BP_PROF_HPX_DEPOSIT,    /* K4 k_hpx_deposit */
+    BP_PROF_PP_SORT,        /* K5 cell keys + radix sort + gather */
+    BP_PROF_PP_KNN,         /* K6 k_pp_knn */
+    BP_PROF_PP_PLAN,        /* K7 amplitudes + pair emission + sort */
+    BP_PROF_PP_DEPOSIT,     /* K8 narrow + wide deposits */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

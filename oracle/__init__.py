@@ -334,3 +334,19 @@ M_P = 1.67262192369e-24
 G_CGS = 6.67430e-8
 MSUN = 1.988409870698051e33
 MPC = 3.0856775814913673e24
+
+
+def pp_flat(p, halos, parts, M_p, npix, pix_rad, k=32):
+    """Full PP map (Sec. 3.4): smoothing lengths by brute-force k-NN in comoving
+    Cartesian coordinates, per-particle amplitudes, separable SPH deposit.
+    ``parts`` arrays may be float32 (they are promoted exactly to float64).
+    Returns y, b maps [npix, npix], comoving h, angular H."""
+    z = _f64(parts["z"])
+    tx, ty = _f64(parts["theta_x"]), _f64(parts["theta_y"])
+    chis = np.array([chi(p, zz) for zz in z])
+    X, Y, Z = chis * tx, chis * ty, chis
+    h = knn_h(X, Y, Z, k)
+    H = h / chis
+    ay, ab = pp_amplitudes(p, halos, z, parts["v_los"], parts["halo_id"], parts["r_i"], M_p, pix_rad)
+    y, b = pp_deposit(tx, ty, H, ay, ab, npix, pix_rad)
+    return y, b, h, H, ay, ab

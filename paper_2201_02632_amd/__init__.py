@@ -72,7 +72,16 @@ _SIGS = {
     "bp_healpix_ang2pix_ring": (C.c_int, [C.c_int64, C.c_int64, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_healpix": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                       _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_pp_smoothing_length": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, C.c_int32, C.c_double, _VP, _VP,
+                                         C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_pp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                   C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_size_t,
+                                   C.POINTER(C.c_size_t), _VP]),
+    "bp_profiling": (C.c_int, [C.c_int]),
+    "bp_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
+PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
+                                          "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT"])}
 EXPORTED = list(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -190,6 +199,55 @@ def healpix_ang2pix_ring(nside: int, theta: torch.Tensor, phi: torch.Tensor) -> 
         _check(_lib.bp_healpix_ang2pix_ring(int(nside), n, _ptr(theta), _ptr(phi), _ptr(out), _stream()),
                "bp_healpix_ang2pix_ring")
     return out
+
+
+def pp_smoothing_length(params: Params, theta_x, theta_y, z, k: int = 32, cell: float = 0.0,
+                        ws: Workspace | None = None) -> torch.Tensor:
+    """K5+K6: distance to the k-th nearest other particle [comoving Mpc/h] (float32 inputs)."""
+    n = theta_x.numel()
+    h = torch.empty(n, dtype=torch.float32, device=theta_x.device)
+    ws = ws or _ws_for(theta_x.device)
+    if n:
+        _with_workspace(_lib.bp_pp_smoothing_length, "bp_pp_smoothing_length", ws,
+                        (C.byref(params), n, _ptr(theta_x), _ptr(theta_y), _ptr(z), int(k), float(cell), _ptr(h)))
+    return h
+
+
+def pp_paste_flat(params: Params, npix: int, pix_rad: float, parts: dict, h, M_p: float, sol, status, y_map, b_map,
+                  ws: Workspace | None = None):
+    """K7+K8: accumulate the SPH footprints of all particles into y_map, b_map."""
+    n = parts["theta_x"].numel()
+    ws = ws or _ws_for(y_map.device)
+    nh = status.numel() if status is not None else 0
+    sp = _ptr(sol) if nh else C.c_void_p(0)
+    stp = _ptr(status) if nh else C.c_void_p(0)
+    _with_workspace(_lib.bp_pp_paste_flat, "bp_pp_paste_flat", ws,
+                    (C.byref(params), int(npix), float(pix_rad), n, _ptr(parts["theta_x"]), _ptr(parts["theta_y"]),
+                     _ptr(parts["z"]), _ptr(parts["v_los"]), _ptr(parts["halo_id"]), _ptr(parts["r_i"]), _ptr(h),
+                     float(M_p), nh, sp, stp, _ptr(y_map), _ptr(b_map)))
+
+
+def pp_flat_map(params: Params, halos: dict, parts: dict, M_p: float, npix: int, pix_rad: float, k: int = 32,
+                cell: float = 0.0, device="cuda"):
+    """Convenience: full PP path (halo solve, smoothing lengths, amplitudes, deposit) from numpy inputs."""
+    th = {kk: torch.as_tensor(v, dtype=torch.float64, device=device).contiguous() for kk, v in halos.items()}
+    tp = {kk: torch.as_tensor(v, device=device).contiguous() for kk, v in parts.items()}
+    sol, status = icm_solve(params, th["M"], th["c"], th["z"])
+    h = pp_smoothing_length(params, tp["theta_x"], tp["theta_y"], tp["z"], k, cell)
+    y = torch.zeros((npix, npix), dtype=torch.float32, device=device)
+    b = torch.zeros_like(y)
+    pp_paste_flat(params, npix, pix_rad, tp, h, M_p, sol, status, y, b)
+    return y, b, h, sol, status
+
+
+def profiling(enable: bool):
+    _lib.bp_profiling(1 if enable else 0)
+
+
+def profile_read(name: str):
+    tot, cnt = C.c_double(0), C.c_int64(0)
+    _check(_lib.bp_profile_read(PROF[name], C.byref(tot), C.byref(cnt)), "bp_profile_read")
+    return tot.value, cnt.value
 
 
 def hp_flat_map(params: Params, cat: dict, npix: int, pix_rad: float, device="cuda"):

@@ -253,7 +253,9 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
         const HpxRec R = rec[h];
         const double sd = sin(0.5 * (thr - R.th));
         const float A = (float)(sd * sd), B = (float)(sthr * R.sth);
-        const float s = sinf(0.5f * (float)(phj - R.ph));
+        double dph = phj - R.ph;                    // wrap to [-pi, pi] before rounding to FP32
+        dph = (dph > kPi) ? dph - 2.0 * kPi : ((dph < -kPi) ? dph + 2.0 * kPi : dph);
+        const float s = sinf(0.5f * (float)dph);
         const float hv = A + B * s * s;
         const float r2 = 4.0f * hv * (1.0f - hv) * inv_pix2;
         bool in = (hv < 0.5f) && (r2 < R.Rt2);

@@ -36,6 +36,8 @@ int scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, void *ws, h
 size_t radix_ws_bytes(int64_t n);
 int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits, void *ws,
                    hipStream_t s, bool *result_in_k1);
+int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits, void *ws,
+                   hipStream_t s, bool *result_in_k1);
 
 // Optional kernel timing (bp_profiling): event pair around one launch.
 void prof_begin(int id, hipStream_t s);

@@ -1,0 +1,742 @@
+// Particle-based pasting (Sec. 3.4 of Osato & Nagai 2022).
+//
+// K5  cell sort: comoving Cartesian positions (chi theta_x, chi theta_y, chi)
+//     are binned on a dense grid of coarse cells; inside a coarse cell the
+//     particles are ordered by a 30-bit Morton code of their position, so the
+//     key (coarse cell << 30 | Morton) makes every cell of every finer level a
+//     contiguous, binary-searchable run of the sorted arrays.
+// K6  kNN: one lane per particle (in sorted order, so a wavefront works on
+//     neighbouring particles).  At level l it scans the 3x3x3 block of level-l
+//     cells around the particle, keeping the k smallest squared distances in
+//     registers; the k-th distance is exact once it does not exceed the cell
+//     size (everything outside the block is at least one cell away).  The
+//     start level comes from the coarse-cell occupancy, so dense halo cores
+//     and empty voids both scan a few hundred candidates.
+// K7  per-particle signal amplitudes and angular smoothing lengths.
+// K8  separable SPH deposit: the particle's weight on pixel (i, j) is the
+//     product of one-dimensional integrated-kernel differences.  Particles are
+//     split by footprint width: narrow ones onto 16x16 tiles (one wavefront per
+//     tile), wide ones onto 64x64 tiles (one workgroup per tile, the per-axis
+//     weights staged in LDS).  Each pixel is owned by one lane and summed with
+//     Kahan compensation in a fixed order, as in the halo deposit.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include "bp_device.hpp"
+#include "bp_internal.hpp"
+
+namespace bp {
+
+// ------------------------------------------------------ cosmology tables --
+constexpr int kNZ = 16384;
+constexpr double kZmax = 16.0;
+
+// chi(z)/(c/H0) and the optical-depth integral on a uniform z grid (24-point GL per cell from the previous node)
+__global__ void k_cosmo_table(bp_params P, GaussRules G, double *__restrict__ chi_t, double *__restrict__ tau_t) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNZ) return;
+    double z = kZmax * i / (kNZ - 1);
+    double a1 = 0.0, a2 = 0.0;
+    for (int j = 0; j < 24; ++j) {
+        double zz = 0.5 * z * (G.x24[j] + 1.0), zp = 1.0 + zz;
+        double E = sqrt(P.Omega_m * zp * zp * zp + 1.0 - P.Omega_m);
+        a1 += G.w24[j] / E;
+        a2 += G.w24[j] * zp * zp / E;
+    }
+    double cH = kCkms / 100.0;
+    double H0 = 100.0 * P.h * 1e5 / kMpc;
+    double rho_cr0 = 3.0 * H0 * H0 / (8.0 * kPi * kG);
+    double ne_bar = P.Omega_b * rho_cr0 / (2.0 / (1.0 + P.X_H) * kMp);
+    chi_t[i] = cH * 0.5 * z * a1;
+    tau_t[i] = kSigmaT * ne_bar * (kC / H0) * 0.5 * z * a2;
+}
+
+// cubic Lagrange interpolation on the uniform table
+__device__ inline double table_interp(const double *__restrict__ t, double z) {
+    double s = z * ((kNZ - 1) / kZmax);
+    int i = (int)floor(s);
+    i = min(max(i, 1), kNZ - 3);
+    double f = s - i;
+    double w0 = -f * (f - 1.0) * (f - 2.0) / 6.0, w1 = (f + 1.0) * (f - 1.0) * (f - 2.0) * 0.5;
+    double w2 = -(f + 1.0) * f * (f - 2.0) * 0.5, w3 = (f + 1.0) * f * (f - 1.0) / 6.0;
+    return w0 * t[i - 1] + w1 * t[i] + w2 * t[i + 1] + w3 * t[i + 2];
+}
+
+// ------------------------------------------------------------- K5 sort --
+struct Grid {
+    double x0, y0, z0;   // origin of the coarse grid (comoving Mpc/h)
+    double cell;         // coarse cell size
+    int32_t nx, ny, nz;
+    int64_t ncells;
+};
+
+__device__ inline uint32_t spread10(uint32_t v) {  // 10 bits -> every third bit
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+__device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread10(x) | (spread10(y) << 1) | (spread10(z) << 2);
+}
+
+// positions and bounding box (min/max reduced with atomics on ordered integer images of doubles)
+__device__ inline unsigned long long dbl_order(double v) {
+    unsigned long long u = __double_as_longlong(v);
+    return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ inline double dbl_unorder(unsigned long long u) {
+    u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double(u);
+}
+
+__global__ void __launch_bounds__(256) k_pp_positions(int64_t n, const float *__restrict__ tx, const float *__restrict__ ty,
+                                                      const float *__restrict__ zz, const double *__restrict__ chi_t,
+                                                      double *__restrict__ pos, unsigned long long *__restrict__ bbox,
+                                                      int *__restrict__ bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double X = 0, Y = 0, Z = 0;
+    bool ok = false;
+    if (i < n) {
+        double z = zz[i];
+        ok = z >= 0.0 && z < kZmax - 0.01 && isfinite((double)tx[i]) && isfinite((double)ty[i]);
+        if (ok) {
+            double chi = table_interp(chi_t, z);
+            X = chi * (double)tx[i]; Y = chi * (double)ty[i]; Z = chi;
+        } else {
+            atomicOr(bad, 1);
+        }
+        pos[i] = X; pos[n + i] = Y; pos[2 * n + i] = Z;
+    }
+    // block min/max then one atomic per block
+    __shared__ unsigned long long mn[3][4], mx[3][4];
+    double v[3] = {X, Y, Z};
+    for (int a = 0; a < 3; ++a) {
+        unsigned long long lo = ok ? dbl_order(v[a]) : ~0ull, hi = ok ? dbl_order(v[a]) : 0ull;
+        for (int o = 32; o > 0; o >>= 1) {
+            unsigned long long l2 = __shfl_down(lo, o, 64), h2 = __shfl_down(hi, o, 64);
+            lo = l2 < lo ? l2 : lo;
+            hi = h2 > hi ? h2 : hi;
+        }
+        if ((threadIdx.x & 63) == 0) { mn[a][threadIdx.x >> 6] = lo; mx[a][threadIdx.x >> 6] = hi; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int a = threadIdx.x;
+        unsigned long long lo = mn[a][0], hi = mx[a][0];
+        for (int w = 1; w < 4; ++w) { lo = mn[a][w] < lo ? mn[a][w] : lo; hi = mx[a][w] > hi ? mx[a][w] : hi; }
+        atomicMin(&bbox[2 * a], lo);
+        atomicMax(&bbox[2 * a + 1], hi);
+    }
+}
+
+__global__ void k_pp_keys(int64_t n, Grid g, const double *__restrict__ pos, uint64_t *__restrict__ key,
+                          uint32_t *__restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double fx = (pos[i] - g.x0) / g.cell, fy = (pos[n + i] - g.y0) / g.cell, fz = (pos[2 * n + i] - g.z0) / g.cell;
+    int cx = min(max((int)floor(fx), 0), g.nx - 1);
+    int cy = min(max((int)floor(fy), 0), g.ny - 1);
+    int cz = min(max((int)floor(fz), 0), g.nz - 1);
+    uint32_t mx = (uint32_t)min(max((int)((fx - cx) * 1024.0), 0), 1023);
+    uint32_t my = (uint32_t)min(max((int)((fy - cy) * 1024.0), 0), 1023);
+    uint32_t mz = (uint32_t)min(max((int)((fz - cz) * 1024.0), 0), 1023);
+    uint64_t cell = ((uint64_t)cz * g.ny + cy) * g.nx + cx;
+    key[i] = (cell << 30) | morton3(mx, my, mz);
+    idx[i] = (uint32_t)i;
+}
+
+// sorted positions (FP64, structure of arrays): the k-th distance can be as small as
+// ~1e-2 Mpc/h at distances of ~1e3 Mpc/h, so differences are taken in FP64
+__global__ void k_pp_gather(int64_t n, Grid g, const double *__restrict__ pos, const uint64_t *__restrict__ key,
+                            const uint32_t *__restrict__ idx, double *__restrict__ sp, uint32_t *__restrict__ cstart,
+                            uint32_t *__restrict__ cend) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t j = idx[i];
+    uint64_t c = key[i] >> 30;
+    sp[i] = pos[j];
+    sp[n + i] = pos[n + j];
+    sp[2 * n + i] = pos[2 * n + j];
+    if (i == 0 || (key[i - 1] >> 30) != c) cstart[c] = (uint32_t)i;
+    if (i == n - 1 || (key[i + 1] >> 30) != c) cend[c] = (uint32_t)(i + 1);
+}
+
+// ------------------------------------------------------------ K6 kNN --
+constexpr int kKmax = 64;
+
+struct TopK {
+    float d[kKmax];
+    int cnt, k, worst_i;
+    float worst;
+    __device__ void init(int kk) { cnt = 0; k = kk; worst = 0.0f; worst_i = 0; }
+    __device__ void push(float v) {
+        if (cnt < k) {
+            d[cnt] = v;
+            if (v >= worst || cnt == 0) { worst = v; worst_i = cnt; }
+            ++cnt;
+        } else if (v < worst) {
+            d[worst_i] = v;
+            worst = d[0]; worst_i = 0;
+            for (int q = 1; q < k; ++q)
+                if (d[q] > worst) { worst = d[q]; worst_i = q; }
+        }
+    }
+};
+
+// first index in [lo, hi) whose key is >= target
+__device__ inline uint32_t lower_bound64(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi, uint64_t target) {
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (key[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key,
+                                                const uint32_t *__restrict__ idx, const double *__restrict__ sp,
+                                                const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ cend,
+                                                float *__restrict__ h_out, int *__restrict__ fail) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t ki = key[i];
+    const uint64_t c = ki >> 30;
+    const int cx = (int)(c % g.nx), cy = (int)((c / g.nx) % g.ny), cz = (int)(c / ((uint64_t)g.nx * g.ny));
+    const double mex = sp[i], mey = sp[n + i], mez = sp[2 * n + i];
+    // fine coordinates inside the coarse cell, recovered from the Morton code
+    uint32_t m = (uint32_t)(ki & 0x3fffffffu), fx = 0, fy = 0, fz = 0;
+    for (int b = 0; b < 10; ++b) {
+        fx |= ((m >> (3 * b)) & 1u) << b;
+        fy |= ((m >> (3 * b + 1)) & 1u) << b;
+        fz |= ((m >> (3 * b + 2)) & 1u) << b;
+    }
+    const float cellf = (float)g.cell;
+    // start level from the coarse-cell density: level-l cells have size cell * 2^(l-10)
+    uint32_t occ = cend[c] - cstart[c];
+    double hest = cbrt((double)k / (4.18879 * (double)occ)) * g.cell;   // radius holding k neighbours
+    int lev = (int)floor(log2(hest / g.cell) + 10.0);
+    lev = min(max(lev, 0), 16);
+    TopK T;
+    bool done = false;
+    for (int it = 0; it < 24 && lev <= 20; ++it, ++lev) {
+        T.init(k);
+        int64_t total = 0;
+        if (lev <= 10) {
+            const int sh = 10 - lev;                 // local cells per coarse cell, per axis: 2^sh
+            const int64_t gx = ((int64_t)cx << sh) + (fx >> lev), gy = ((int64_t)cy << sh) + (fy >> lev),
+                          gz = ((int64_t)cz << sh) + (fz >> lev);
+            const float sl = cellf / (float)(1 << sh);
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int64_t ax = gx + dx, ay = gy + dy, az = gz + dz;
+                        if (ax < 0 || ay < 0 || az < 0) continue;
+                        int64_t ccx = ax >> sh, ccy = ay >> sh, ccz = az >> sh;
+                        if (ccx >= g.nx || ccy >= g.ny || ccz >= g.nz) continue;
+                        uint64_t cc = ((uint64_t)ccz * g.ny + ccy) * g.nx + ccx;
+                        uint32_t s0 = cstart[cc], s1 = cend[cc];
+                        if (s0 >= s1) continue;
+                        uint32_t lx = (uint32_t)(ax - (ccx << sh)) << lev, ly = (uint32_t)(ay - (ccy << sh)) << lev,
+                                 lz = (uint32_t)(az - (ccz << sh)) << lev;
+                        uint64_t base = cc << 30;
+                        uint64_t klo = base | morton3(lx, ly, lz);
+                        uint64_t khi = klo + (1ull << (3 * lev));
+                        uint32_t a = lower_bound64(key, s0, s1, klo), b = lower_bound64(key, a, s1, khi);
+                        total += b - a;
+                        for (uint32_t j = a; j < b; ++j) {
+                            if (j == (uint32_t)i) continue;
+                            float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey),
+                                  ddz = (float)(sp[2 * n + j] - mez);
+                            T.push(ddx * ddx + ddy * ddy + ddz * ddz);
+                        }
+                    }
+            if (T.cnt >= k && T.worst <= sl * sl) { done = true; break; }
+        } else {
+            const int B = 1 << (lev - 10);           // coarse cells per level-l cell, per axis
+            const int bx = cx / B, by = cy / B, bz = cz / B;
+            const float sl = cellf * (float)B;
+            for (int az = (bz - 1) * B; az < (bz + 2) * B; ++az) {
+                if (az < 0 || az >= g.nz) continue;
+                for (int ay = (by - 1) * B; ay < (by + 2) * B; ++ay) {
+                    if (ay < 0 || ay >= g.ny) continue;
+                    for (int ax = (bx - 1) * B; ax < (bx + 2) * B; ++ax) {
+                        if (ax < 0 || ax >= g.nx) continue;
+                        uint64_t cc = ((uint64_t)az * g.ny + ay) * g.nx + ax;
+                        uint32_t a = cstart[cc], b = cend[cc];
+                        total += (b > a) ? b - a : 0;
+                        for (uint32_t j = a; j < b; ++j) {
+                            if (j == (uint32_t)i) continue;
+                            float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey),
+                                  ddz = (float)(sp[2 * n + j] - mez);
+                            T.push(ddx * ddx + ddy * ddy + ddz * ddz);
+                        }
+                    }
+                }
+            }
+            if (T.cnt >= k && T.worst <= sl * sl) { done = true; break; }
+        }
+        (void)total;
+    }
+    // a particle too isolated for the largest search block gets NaN and raises the failure flag
+    float h = done ? sqrtf(T.worst) : __int_as_float(0x7fc00000);
+    if (!done) atomicOr(fail, 1);
+    h_out[idx[i]] = h;
+}
+
+// ---------------------------------------------------- K7 amplitudes --
+struct PPRec {        // per-particle deposit record (40 bytes)
+    int32_t ipx, jpx; // particle position in pixel units: integer part ...
+    float fpx, fpy;   // ... and fraction, so pixel edges minus position keep their digits
+    float ih;         // pixel size / angular smoothing length
+    float ay, ab;     // y and b amplitudes (integral of the footprint)
+    int32_t i0, j0;   // first pixel column / row of the support square (clipped)
+    int32_t wh;       // width | height << 16 of the clipped support in pixels (0 = no pixels)
+};
+
+__global__ void __launch_bounds__(256) k_pp_amplitudes(bp_params P, int64_t n, int npix, double pix,
+                                                       const float *__restrict__ tx, const float *__restrict__ ty,
+                                                       const float *__restrict__ zz, const float *__restrict__ vl,
+                                                       const int32_t *__restrict__ hid, const float *__restrict__ ri,
+                                                       const float *__restrict__ hcom, double Mp, int64_t nh,
+                                                       const double *__restrict__ sol, const int32_t *__restrict__ hst,
+                                                       const double *__restrict__ chi_t, const double *__restrict__ tau_t,
+                                                       PPRec *__restrict__ rec, uint32_t *__restrict__ wide_flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    PPRec R = {};
+    const double z = zz[i];
+    const double chi = table_interp(chi_t, z);
+    const double DA = chi / (1.0 + z);
+    const double u_len = kMpc / P.h, u_mass = kMsun / P.h;
+    const double Lpix = DA * pix * u_len;                        // physical pixel size [cm]
+    const double ek = exp(-table_interp(tau_t, z));
+    const double vc = (double)vl[i] * 1e5 / kC;
+    const double mu_e = 2.0 / (1.0 + P.X_H);
+    const double Mp_g = Mp * u_mass;
+    double ay = 0.0, ab = 0.0;
+    const int32_t h = hid[i];
+    bool ok = z >= 0.0 && z < kZmax - 0.01;
+    if (h < 0) {
+        ab = kSigmaT * vc * (P.field_gas_frac * Mp_g / (mu_e * kMp)) * ek / (Lpix * Lpix);
+    } else if (h < nh && !(hst[h] & ~BP_S_MULTI_ROOT)) {
+        auto S = [&](int f) { return sol[(int64_t)f * nh + h]; };
+        const double r = ri[i];
+        const double rs = S(BP_SOL_RS), rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), c = S(BP_SOL_C);
+        const double x = r / rs;
+        const double rho_tot = S(BP_SOL_RHOS) * u_mass / (u_len * u_len * u_len) / (x * (1.0 + x) * (1.0 + x));
+        const double V = Mp_g / rho_tot;
+        if (r < rf && r > 0.0) {
+            double mc = nfw_m(c);
+            double ph = (r < rv) ? c / mc * nfw_phi_shape(x) : c * c / ((1.0 + c) * mc) - rv / r;
+            double th = 1.0 - S(BP_SOL_A) * ph;
+            if (th > 0.0) {
+                double th5 = th * th * th * th * th;
+                double Rnt = P.alpha_nt * S(BP_SOL_FNT) * pow(r / S(BP_SOL_R500), P.n_nt);
+                double Pe = (2.0 * P.X_H + 2.0) / (5.0 * P.X_H + 3.0) * S(BP_SOL_P0) * th5 * th * fmax(0.0, 1.0 - Rnt);
+                double ne = S(BP_SOL_RHO0) * th5 / (mu_e * kMp);
+                ay = kSigmaT / kMeC2 * Pe * V / (Lpix * Lpix);
+                ab = kSigmaT * vc * ek * ne * V / (Lpix * Lpix);
+            }
+        }
+    }
+    const double H = (double)hcom[i] / chi;
+    ok = ok && H > 0.0 && isfinite(H);
+    R.ay = (float)ay; R.ab = (float)ab;
+    if (ok && (ay != 0.0 || ab != 0.0)) {
+        double px = (double)tx[i] / pix, py = (double)ty[i] / pix;
+        double ipx = floor(px), jpy = floor(py);
+        R.ipx = (int32_t)fmax(fmin(ipx, 2e9), -2e9); R.jpx = (int32_t)fmax(fmin(jpy, 2e9), -2e9);
+        R.fpx = (float)(px - ipx); R.fpy = (float)(py - jpy);
+        R.ih = (float)(pix / H);
+        double x0 = ((double)tx[i] - H) / pix, x1 = ((double)tx[i] + H) / pix;
+        double y0 = ((double)ty[i] - H) / pix, y1 = ((double)ty[i] + H) / pix;
+        int i0 = (int)fmax(floor(x0), 0.0), i1 = (int)fmin(floor(x1), (double)(npix - 1));
+        int j0 = (int)fmax(floor(y0), 0.0), j1 = (int)fmin(floor(y1), (double)(npix - 1));
+        if (i1 >= i0 && j1 >= j0 && x1 >= 0.0 && y1 >= 0.0 && x0 < npix && y0 < npix) {
+            R.i0 = i0; R.j0 = j0;
+            R.wh = (i1 - i0 + 1) | ((j1 - j0 + 1) << 16);
+        }
+    }
+    rec[i] = R;
+    if (R.wh) {
+        int w = R.wh & 0xffff, hh = R.wh >> 16;
+        wide_flag[i] = (w > 24 || hh > 24) ? 1u : 0u;
+    } else {
+        wide_flag[i] = 2u;   // deposits nothing
+    }
+}
+
+// ------------------------------------------------------------ K8 deposit --
+// Normalised integral of the cubic-spline kernel along one axis (Eq. integrated_kernel),
+// evaluated as a left tail: wl(x) = w(x) for x <= 0.  w(x) = 1 - wl(-x) for x > 0.
+__device__ inline float wl(float x) {
+    if (x <= -1.0f) return 0.0f;
+    if (x <= -0.5f) { float t = 1.0f + x, t2 = t * t; return (2.0f / 3.0f) * t2 * t2; }
+    float x2 = x * x;
+    return (4.0f / 3.0f) * (0.375f + x - 2.0f * x2 * x - 1.5f * x2 * x2);
+}
+// weight of the cell [a, b] (in units of H, relative to the particle) without cancellation in the tails
+__device__ inline float cell_weight(float a, float b) {
+    if (a >= 0.0f) return wl(-a) - wl(-b);
+    if (b <= 0.0f) return wl(b) - wl(a);
+    return 1.0f - wl(a) - wl(-b);
+}
+
+constexpr int kPT = 16;   // narrow tiles: 16x16, one wavefront
+constexpr int kWT = 64;   // wide tiles: 64x64, one 256-lane workgroup
+
+__global__ void k_pp_count(int64_t n, int ntx_n, int ntx_w, const PPRec *__restrict__ rec,
+                           const uint32_t *__restrict__ wide, uint32_t *__restrict__ cnt_n, uint32_t *__restrict__ cnt_w,
+                           unsigned long long *__restrict__ totals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t a = 0, b = 0;
+    if (i < n) {
+        const PPRec R = rec[i];
+        if (wide[i] < 2) {
+            int w = R.wh & 0xffff, h = R.wh >> 16;
+            int T = wide[i] ? kWT : kPT;
+            uint32_t nt = (uint32_t)((R.i0 + w - 1) / T - R.i0 / T + 1) * (uint32_t)((R.j0 + h - 1) / T - R.j0 / T + 1);
+            if (wide[i]) b = nt; else a = nt;
+        }
+        cnt_n[i] = a;
+        cnt_w[i] = b;
+    }
+    unsigned long long va = a, vb = b;
+    for (int o = 32; o > 0; o >>= 1) { va += __shfl_down(va, o, 64); vb += __shfl_down(vb, o, 64); }
+    if ((threadIdx.x & 63) == 0) { atomicAdd(&totals[0], va); atomicAdd(&totals[1], vb); }
+    (void)ntx_n; (void)ntx_w;
+}
+
+__global__ void k_pp_emit(int64_t n, int ntx_n, int ntx_w, const PPRec *__restrict__ rec, const uint32_t *__restrict__ wide,
+                          const uint32_t *__restrict__ off_n, const uint32_t *__restrict__ off_w,
+                          uint32_t *__restrict__ kn, uint32_t *__restrict__ vn, uint32_t *__restrict__ kw,
+                          uint32_t *__restrict__ vw) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || wide[i] >= 2) return;
+    const PPRec R = rec[i];
+    const bool W = wide[i] != 0;
+    const int T = W ? kWT : kPT, ntx = W ? ntx_w : ntx_n;
+    int w = R.wh & 0xffff, h = R.wh >> 16;
+    uint32_t o = W ? off_w[i] : off_n[i];
+    uint32_t *K = W ? kw : kn, *V = W ? vw : vn;
+    for (int ty = R.j0 / T; ty <= (R.j0 + h - 1) / T; ++ty)
+        for (int tx = R.i0 / T; tx <= (R.i0 + w - 1) / T; ++tx) {
+            K[o] = (uint32_t)(ty * ntx + tx);
+            V[o] = (uint32_t)i;
+            ++o;
+        }
+}
+
+__global__ void k_pp_ranges(const uint32_t *__restrict__ keys, int64_t np, uint32_t *__restrict__ ts,
+                            uint32_t *__restrict__ te, uint32_t ntiles) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    uint32_t k = keys[i];
+    if (k >= ntiles) return;
+    if (i == 0 || keys[i - 1] != k) ts[k] = (uint32_t)i;
+    if (i == np - 1 || keys[i + 1] != k) te[k] = (uint32_t)(i + 1);
+}
+
+__device__ inline void kahan(float &s, float &c, float v) {
+    float y = v - c, t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// narrow particles: one wavefront per 16x16 tile, lane = column (l & 15) x 4 rows
+__global__ void __launch_bounds__(256) k_pp_deposit_narrow(int npix, double pix, int ntx, uint32_t ntiles,
+                                                           const PPRec *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                           const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                                                           float *__restrict__ ymap, float *__restrict__ bmap) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * 4 + wave;
+    if (tile >= ntiles) return;
+    const uint32_t p0 = ts[tile], p1 = te[tile];
+    if (p0 >= p1) return;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int pi = tx * kPT + (lane & 15), pj0 = ty * kPT + (lane >> 4);
+    float ys[4], yc[4], bs[4], bc[4];
+    for (int k = 0; k < 4; ++k) {
+        int pj = pj0 + 4 * k;
+        bool in = pi < npix && pj < npix;
+        int64_t id = (int64_t)pj * npix + pi;
+        ys[k] = in ? ymap[id] : 0.0f; bs[k] = in ? bmap[id] : 0.0f; yc[k] = 0.0f; bc[k] = 0.0f;
+    }
+    for (uint32_t p = p0; p < p1; ++p) {
+        const PPRec R = rec[vals[p]];
+        const int w = R.wh & 0xffff, h = R.wh >> 16;
+        if (pi < R.i0 || pi >= R.i0 + w) continue;
+        // x weight of this lane's column: pixel edges relative to the particle, in units of H
+        const float ex = (float)(pi - R.ipx) - R.fpx;
+        const float wx = cell_weight(ex * R.ih, (ex + 1.0f) * R.ih);
+        for (int k = 0; k < 4; ++k) {
+            const int pj = pj0 + 4 * k;
+            if (pj < R.j0 || pj >= R.j0 + h) continue;
+            const float ey = (float)(pj - R.jpx) - R.fpy;
+            const float ay = ey * R.ih, by = (ey + 1.0f) * R.ih;
+            const float f = wx * cell_weight(ay, by);
+            kahan(ys[k], yc[k], R.ay * f);
+            kahan(bs[k], bc[k], R.ab * f);
+        }
+    }
+    for (int k = 0; k < 4; ++k) {
+        int pj = pj0 + 4 * k;
+        if (pi < npix && pj < npix) {
+            int64_t id = (int64_t)pj * npix + pi;
+            ymap[id] = ys[k]; bmap[id] = bs[k];
+        }
+    }
+}
+
+// wide particles: one 256-lane workgroup per 64x64 tile; lane owns column (t & 63), rows (t >> 6) + 4k.
+// Per batch of 8 particles the 64 x- and 64 y-weights of each are staged in LDS.
+constexpr int kBatch = 8;
+__global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, int ntx, const PPRec *__restrict__ rec,
+                                                         const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ts,
+                                                         const uint32_t *__restrict__ te, float *__restrict__ ymap,
+                                                         float *__restrict__ bmap) {
+    __shared__ float wxs[kBatch][kWT], wys[kBatch][kWT];
+    __shared__ float amp[kBatch][2];
+    const uint32_t tile = blockIdx.x;
+    const uint32_t p0 = ts[tile], p1 = te[tile];
+    if (p0 >= p1) return;
+    const int t = threadIdx.x;
+    const int tx = tile % ntx, ty = tile / ntx;
+    const int pi = tx * kWT + (t & 63), pj0 = ty * kWT + (t >> 6);
+    float ys[16], yc[16], bs[16], bc[16];
+    for (int k = 0; k < 16; ++k) {
+        int pj = pj0 + 4 * k;
+        bool in = pi < npix && pj < npix;
+        int64_t id = (int64_t)pj * npix + pi;
+        ys[k] = in ? ymap[id] : 0.0f; bs[k] = in ? bmap[id] : 0.0f; yc[k] = 0.0f; bc[k] = 0.0f;
+    }
+    for (uint32_t pb = p0; pb < p1; pb += kBatch) {
+        const int nb = (int)min((uint32_t)kBatch, p1 - pb);
+        __syncthreads();
+        // stage weights: threads 0..255 cover 8 particles x (64 x-weights or 64 y-weights) in two passes
+        for (int q = t; q < kBatch * 2 * kWT; q += 256) {
+            int b = q / (2 * kWT), r = q % (2 * kWT);
+            float v = 0.0f;
+            if (b < nb) {
+                const PPRec R = rec[vals[pb + b]];
+                if (r < kWT) {
+                    int c = tx * kWT + r;
+                    int w = R.wh & 0xffff;
+                    if (c >= R.i0 && c < R.i0 + w) {
+                        float e0 = (float)(c - R.ipx) - R.fpx;
+                        v = cell_weight(e0 * R.ih, (e0 + 1.0f) * R.ih);
+                    }
+                    wxs[b][r] = v;
+                } else {
+                    int rr = r - kWT, row = ty * kWT + rr;
+                    int h = R.wh >> 16;
+                    if (row >= R.j0 && row < R.j0 + h) {
+                        float e0 = (float)(row - R.jpx) - R.fpy;
+                        v = cell_weight(e0 * R.ih, (e0 + 1.0f) * R.ih);
+                    }
+                    wys[b][rr] = v;
+                }
+                if (r == 0) { amp[b][0] = R.ay; amp[b][1] = R.ab; }
+            }
+        }
+        __syncthreads();
+        for (int b = 0; b < nb; ++b) {
+            const float wx = wxs[b][t & 63];
+            if (wx == 0.0f) continue;
+            const float a0 = amp[b][0] * wx, a1 = amp[b][1] * wx;
+            for (int k = 0; k < 16; ++k) {
+                const float wy = wys[b][(t >> 6) + 4 * k];
+                if (wy == 0.0f) continue;
+                kahan(ys[k], yc[k], a0 * wy);
+                kahan(bs[k], bc[k], a1 * wy);
+            }
+        }
+    }
+    for (int k = 0; k < 16; ++k) {
+        int pj = pj0 + 4 * k;
+        if (pi < npix && pj < npix) {
+            int64_t id = (int64_t)pj * npix + pi;
+            ymap[id] = ys[k]; bmap[id] = bs[k];
+        }
+    }
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+extern "C" int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
+                                      const float *z, int32_t k, double cell, float *h_comoving, void *ws,
+                                      size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!p || n < 0 || k < 1 || k > kKmax || !ws_needed || !(cell >= 0.0)) return BP_E_ARG;
+    if (n == 0) { *ws_needed = 0; return BP_OK; }
+    if (!theta_x || !theta_y || !z || !h_comoving) return BP_E_ARG;
+    if (n >= 0x7fffffffLL || n <= k) return n <= k ? BP_E_ARG : BP_E_OVERFLOW;
+    hipStream_t s = (hipStream_t)stream;
+    if (cell == 0.0) cell = 2.0;
+    // phase 1: tables, positions, bounding box
+    Arena A1(nullptr, 0);
+    A1.take<double>(kNZ); A1.take<double>(kNZ);
+    A1.take<double>(3 * n);
+    A1.take<unsigned long long>(8);
+    size_t phase1 = A1.used;
+    if (!ws || ws_bytes < phase1) { *ws_needed = phase1 + (size_t)n * 64 + ((size_t)1 << 20); return BP_E_WORKSPACE; }
+    Arena A(ws, ws_bytes);
+    double *chi_t = A.take<double>(kNZ), *tau_t = A.take<double>(kNZ);
+    double *pos = A.take<double>(3 * n);
+    unsigned long long *bb = A.take<unsigned long long>(8);
+    unsigned long long init[8] = {~0ull, 0ull, ~0ull, 0ull, ~0ull, 0ull, 0ull, 0ull};
+    if (hipMemcpyAsync(bb, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) return BP_E_HIP;
+    hipLaunchKernelGGL(k_cosmo_table, dim3((kNZ + 255) / 256), dim3(256), 0, s, *p, gauss_rules(), chi_t, tau_t);
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_pp_positions, dim3(blocks), dim3(256), 0, s, n, theta_x, theta_y, z, chi_t, pos, bb,
+                       (int *)(bb + 6));
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    unsigned long long hb[8];
+    if (hipMemcpyAsync(hb, bb, sizeof(hb), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
+    if (hb[6]) return BP_E_ARG;   // a redshift outside [0, 16) or a non-finite angle
+    auto un = [](unsigned long long u) {
+        u = (u & 0x8000000000000000ull) ? (u & 0x7fffffffffffffffull) : ~u;
+        double d;
+        memcpy(&d, &u, 8);
+        return d;
+    };
+    Grid g;
+    g.cell = cell;
+    g.x0 = un(hb[0]) - 1e-6 * cell; g.y0 = un(hb[2]) - 1e-6 * cell; g.z0 = un(hb[4]) - 1e-6 * cell;
+    double ex = un(hb[1]) - g.x0, ey = un(hb[3]) - g.y0, ez = un(hb[5]) - g.z0;
+    g.nx = (int)(ex / cell) + 1; g.ny = (int)(ey / cell) + 1; g.nz = (int)(ez / cell) + 1;
+    g.ncells = (int64_t)g.nx * g.ny * g.nz;
+    if (g.ncells >= (1LL << 33)) return BP_E_OVERFLOW;
+    int cbits = 1;
+    while ((1LL << cbits) < g.ncells) ++cbits;
+    // phase 2
+    size_t need = A.used;
+    {
+        Arena B(nullptr, 0);
+        B.take<uint64_t>(n); B.take<uint64_t>(n); B.take<uint32_t>(n); B.take<uint32_t>(n);
+        B.take<double>(3 * n); B.take<uint32_t>(g.ncells); B.take<uint32_t>(g.ncells); B.take<int>(1);
+        need += B.used + radix_ws_bytes(n) + 256;
+    }
+    if (ws_bytes < need) { *ws_needed = need; return BP_E_WORKSPACE; }
+    *ws_needed = need;
+    uint64_t *k0 = A.take<uint64_t>(n), *k1 = A.take<uint64_t>(n);
+    uint32_t *v0 = A.take<uint32_t>(n), *v1 = A.take<uint32_t>(n);
+    double *sp = A.take<double>(3 * n);
+    uint32_t *cs = A.take<uint32_t>(g.ncells), *ce = A.take<uint32_t>(g.ncells);
+    int *fail = A.take<int>(1);
+    void *sws = (char *)ws + A.used;
+    prof_begin(BP_PROF_PP_SORT, s);
+    hipLaunchKernelGGL(k_pp_keys, dim3(blocks), dim3(256), 0, s, n, g, pos, k0, v0);
+    bool in1 = false;
+    int e = radix_sort_u64(k0, v0, k1, v1, n, 30 + cbits, sws, s, &in1);
+    if (e) return e;
+    uint64_t *ks = in1 ? k1 : k0;
+    uint32_t *vs = in1 ? v1 : v0;
+    if (fill_u32(cs, 0u, g.ncells, s) || fill_u32(ce, 0u, g.ncells, s) || fill_u32((uint32_t *)fail, 0u, 1, s))
+        return BP_E_HIP;
+    hipLaunchKernelGGL(k_pp_gather, dim3(blocks), dim3(256), 0, s, n, g, pos, ks, vs, sp, cs, ce);
+    prof_end(BP_PROF_PP_SORT, s);
+    prof_begin(BP_PROF_PP_KNN, s);
+    hipLaunchKernelGGL(k_pp_knn, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving, fail);
+    prof_end(BP_PROF_PP_KNN, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const float *theta_x,
+                                const float *theta_y, const float *z, const float *v_los, const int32_t *halo_id,
+                                const float *r_halo, const float *h_comoving, double M_p, int64_t n_halos,
+                                const double *sol, const int32_t *status, float *y_map, float *b_map, void *ws,
+                                size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!p || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed || !(M_p > 0) || n_halos < 0)
+        return BP_E_ARG;
+    if (!y_map || !b_map) return BP_E_ARG;
+    if (n == 0) { *ws_needed = 0; return BP_OK; }
+    if (!theta_x || !theta_y || !z || !v_los || !halo_id || !r_halo || !h_comoving) return BP_E_ARG;
+    if (n_halos > 0 && (!sol || !status)) return BP_E_ARG;
+    if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
+    hipStream_t s = (hipStream_t)stream;
+    const int ntx_n = (npix + kPT - 1) / kPT, ntx_w = (npix + kWT - 1) / kWT;
+    const int64_t nt_n = (int64_t)ntx_n * ntx_n, nt_w = (int64_t)ntx_w * ntx_w;
+    Arena A1(nullptr, 0);
+    A1.take<double>(kNZ); A1.take<double>(kNZ);
+    A1.take<PPRec>(n); A1.take<uint32_t>(n);
+    A1.take<uint32_t>(n + 1); A1.take<uint32_t>(n + 1); A1.take<uint32_t>(n + 1); A1.take<uint32_t>(n + 1);
+    A1.take<unsigned long long>(2);
+    size_t phase1 = A1.used + scan_ws_bytes(n + 1);
+    if (!ws || ws_bytes < phase1) { *ws_needed = phase1 + 64; return BP_E_WORKSPACE; }
+    Arena A(ws, ws_bytes);
+    double *chi_t = A.take<double>(kNZ), *tau_t = A.take<double>(kNZ);
+    PPRec *rec = A.take<PPRec>(n);
+    uint32_t *wide = A.take<uint32_t>(n);
+    uint32_t *cn = A.take<uint32_t>(n + 1), *cw = A.take<uint32_t>(n + 1);
+    uint32_t *on = A.take<uint32_t>(n + 1), *ow = A.take<uint32_t>(n + 1);
+    unsigned long long *tot = A.take<unsigned long long>(2);
+    void *scan_ws = (char *)ws + A.used;
+    A.used += scan_ws_bytes(n + 1);
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    prof_begin(BP_PROF_PP_PLAN, s);
+    hipLaunchKernelGGL(k_cosmo_table, dim3((kNZ + 255) / 256), dim3(256), 0, s, *p, gauss_rules(), chi_t, tau_t);
+    hipLaunchKernelGGL(k_pp_amplitudes, dim3(blocks), dim3(256), 0, s, *p, n, (int)npix, pix_rad, theta_x, theta_y, z,
+                       v_los, halo_id, r_halo, h_comoving, M_p, n_halos, sol, status, chi_t, tau_t, rec, wide);
+    if (hipMemsetAsync(tot, 0, 2 * sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
+    if (fill_u32(cn + n, 0u, 1, s) || fill_u32(cw + n, 0u, 1, s)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_pp_count, dim3(blocks), dim3(256), 0, s, n, ntx_n, ntx_w, rec, wide, cn, cw, tot);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    unsigned long long ht[2];
+    if (hipMemcpyAsync(ht, tot, sizeof(ht), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
+    if (ht[0] >= 0x7fffffffULL || ht[1] >= 0x7fffffffULL) return BP_E_OVERFLOW;
+    const int64_t pn = (int64_t)ht[0], pw = (int64_t)ht[1];
+    size_t need = A.used;
+    {
+        Arena B(nullptr, 0);
+        for (int q = 0; q < 4; ++q) B.take<uint32_t>(pn);
+        for (int q = 0; q < 4; ++q) B.take<uint32_t>(pw);
+        B.take<uint32_t>(nt_n); B.take<uint32_t>(nt_n); B.take<uint32_t>(nt_w); B.take<uint32_t>(nt_w);
+        need += B.used + radix_ws_bytes(pn > pw ? pn : pw) + 256;
+    }
+    if (ws_bytes < need) { *ws_needed = need; return BP_E_WORKSPACE; }
+    *ws_needed = need;
+    uint32_t *kn0 = A.take<uint32_t>(pn), *vn0 = A.take<uint32_t>(pn), *kn1 = A.take<uint32_t>(pn),
+             *vn1 = A.take<uint32_t>(pn);
+    uint32_t *kw0 = A.take<uint32_t>(pw), *vw0 = A.take<uint32_t>(pw), *kw1 = A.take<uint32_t>(pw),
+             *vw1 = A.take<uint32_t>(pw);
+    uint32_t *tsn = A.take<uint32_t>(nt_n), *ten = A.take<uint32_t>(nt_n);
+    uint32_t *tsw = A.take<uint32_t>(nt_w), *tew = A.take<uint32_t>(nt_w);
+    void *sort_ws = (char *)ws + A.used;
+    int e = scan_exclusive_u32(cn, on, n + 1, scan_ws, s);
+    if (!e) e = scan_exclusive_u32(cw, ow, n + 1, scan_ws, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_pp_emit, dim3(blocks), dim3(256), 0, s, n, ntx_n, ntx_w, rec, wide, on, ow, kn0, vn0, kw0,
+                       vw0);
+    bool in1 = false;
+    int bits_n = 1, bits_w = 1;
+    while ((1LL << bits_n) < nt_n) ++bits_n;
+    while ((1LL << bits_w) < nt_w) ++bits_w;
+    e = radix_sort_u32(kn0, vn0, kn1, vn1, pn, bits_n, sort_ws, s, &in1);
+    if (e) return e;
+    uint32_t *ksn = in1 ? kn1 : kn0, *vsn = in1 ? vn1 : vn0;
+    e = radix_sort_u32(kw0, vw0, kw1, vw1, pw, bits_w, sort_ws, s, &in1);
+    if (e) return e;
+    uint32_t *ksw = in1 ? kw1 : kw0, *vsw = in1 ? vw1 : vw0;
+    if (fill_u32(tsn, 0u, nt_n, s) || fill_u32(ten, 0u, nt_n, s) || fill_u32(tsw, 0u, nt_w, s) ||
+        fill_u32(tew, 0u, nt_w, s))
+        return BP_E_HIP;
+    if (pn) hipLaunchKernelGGL(k_pp_ranges, dim3((unsigned)((pn + 255) / 256)), dim3(256), 0, s, ksn, pn, tsn, ten,
+                               (uint32_t)nt_n);
+    if (pw) hipLaunchKernelGGL(k_pp_ranges, dim3((unsigned)((pw + 255) / 256)), dim3(256), 0, s, ksw, pw, tsw, tew,
+                               (uint32_t)nt_w);
+    prof_end(BP_PROF_PP_PLAN, s);
+    prof_begin(BP_PROF_PP_DEPOSIT, s);
+    if (pn) hipLaunchKernelGGL(k_pp_deposit_narrow, dim3((unsigned)((nt_n + 3) / 4)), dim3(256), 0, s, (int)npix,
+                               pix_rad, ntx_n, (uint32_t)nt_n, rec, vsn, tsn, ten, y_map, b_map);
+    if (pw) hipLaunchKernelGGL(k_pp_deposit_wide, dim3((unsigned)nt_w), dim3(256), 0, s, (int)npix, pix_rad, ntx_w,
+                               rec, vsw, tsw, tew, y_map, b_map);
+    prof_end(BP_PROF_PP_DEPOSIT, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}

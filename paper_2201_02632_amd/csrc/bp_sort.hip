@@ -94,7 +94,8 @@ int scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, void *ws, h
 }
 
 // ---------------------------------------------------------------- radix --
-__global__ void __launch_bounds__(256) k_radix_hist(const uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
+template <class K>
+__global__ void __launch_bounds__(256) k_radix_hist(const K *__restrict__ keys, uint32_t *__restrict__ hist,
                                                     int64_t n, int shift, int nb) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -102,14 +103,15 @@ __global__ void __launch_bounds__(256) k_radix_hist(const uint32_t *__restrict__
     int64_t base = (int64_t)blockIdx.x * kChunk;
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + (int64_t)k * 256 + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+template <class K>
+__global__ void __launch_bounds__(256) k_radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                       K *__restrict__ kout, uint32_t *__restrict__ vout,
                                                        const uint32_t *__restrict__ offs, int64_t n, int shift, int nb) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
@@ -122,8 +124,9 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const uint32_t *__restric
         __syncthreads();
         int64_t idx = start + (int64_t)round * 256 + t;
         bool valid = idx < n;
-        uint32_t key = valid ? kin[idx] : 0u, val = valid ? vin[idx] : 0u;
-        uint32_t d = (key >> shift) & 255u;
+        K key = valid ? kin[idx] : (K)0;
+        uint32_t val = valid ? vin[idx] : 0u;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t mask = __ballot(valid);
         for (int bit = 0; bit < 8; ++bit) {
             uint64_t bb = __ballot((d >> bit) & 1u);
@@ -150,8 +153,9 @@ size_t radix_ws_bytes(int64_t n) {
     return 2 * hist + scan_ws_bytes(nb * 256) + 256;
 }
 
-int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits, void *ws,
-                   hipStream_t s, bool *result_in_k1) {
+template <class K>
+static int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, int bits, void *ws, hipStream_t s,
+                           bool *result_in_k1) {
     *result_in_k1 = false;
     if (n <= 1 || bits <= 0) return BP_OK;
     int64_t nb = (n + kChunk - 1) / kChunk;
@@ -160,19 +164,30 @@ int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64
     uint32_t *hist = A.take<uint32_t>(nb * 256);
     uint32_t *offs = A.take<uint32_t>(nb * 256);
     void *sws = (char *)ws + A.used;
-    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    K *ki = k0, *ko = k1;
+    uint32_t *vi = v0, *vo = v1;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(256), 0, s, ki, hist, n, shift, (int)nb);
+        hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, ki, hist, n, shift, (int)nb);
         int e = scan_exclusive_u32(hist, offs, nb * 256, sws, s);
         if (e) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(256), 0, s, ki, vi, ko, vo, offs, n, shift,
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(256), 0, s, ki, vi, ko, vo, offs, n, shift,
                            (int)nb);
         if (hipGetLastError() != hipSuccess) return BP_E_HIP;
-        uint32_t *tk = ki, *tv = vi;
-        ki = ko; vi = vo; ko = tk; vo = tv;
+        K *tk = ki; ki = ko; ko = tk;
+        uint32_t *tv = vi; vi = vo; vo = tv;
         *result_in_k1 = !*result_in_k1;
     }
     return BP_OK;
+}
+
+int radix_sort_u32(uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, int64_t n, int bits, void *ws,
+                   hipStream_t s, bool *result_in_k1) {
+    return radix_sort_impl<uint32_t>(k0, v0, k1, v1, n, bits, ws, s, result_in_k1);
+}
+
+int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits, void *ws,
+                   hipStream_t s, bool *result_in_k1) {
+    return radix_sort_impl<uint64_t>(k0, v0, k1, v1, n, bits, ws, s, result_in_k1);
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {

@@ -92,3 +92,137 @@ def surrogate_training(n, seed=4):
 
 def subsample(cat, idx):
     return {k: np.asarray(v)[idx] for k, v in cat.items()}
+
+
+# ---------------------------------------------------------------- particles --
+# Light-cone particles for particle-based pasting.  The generator places
+# particles with its own rough distance-redshift relation (trapezoidal
+# integration of a flat LCDM H(z)); the method itself recomputes every
+# distance from the particle redshift, so these approximations only shape the
+# synthetic input.
+_C_KMS = 299792.458
+
+
+def _chi_table(om=0.3, zmax=5.0, n=20001):
+    z = np.linspace(0.0, zmax, n)
+    f = 1.0 / np.sqrt(om * (1 + z) ** 3 + 1 - om)
+    chi = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(z))]) * _C_KMS / 100.0
+    return z, chi
+
+
+def _nfw_inverse_cdf(u, c, iters=60):
+    """x with m(x)/m(c) = u (bisection), m(x) = ln(1+x) - x/(1+x)."""
+    m = lambda x: np.log1p(x) - x / (1 + x)  # noqa: E731
+    target = u * m(c)
+    lo = np.zeros_like(u)
+    hi = np.array(c, dtype=np.float64) * np.ones_like(u)
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        big = m(mid) > target
+        hi = np.where(big, mid, hi)
+        lo = np.where(big, lo, mid)
+    return 0.5 * (lo + hi)
+
+
+def _random_rotations(rng, n):
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1)], 1)
+
+
+def pp_lightcone(n_halos, n_halo_particles, n_field, field_deg, zr=(0.05, 1.5), logM=(12.5, 15.5),
+                 mass_function="powerlaw", field_cell=2.0, om=0.3, seed=3):
+    """Halo catalogue plus particles for particle-based pasting.
+
+    Halo particles: N_h proportional to M_vir (one particle mass M_p for all);
+    ellipsoidal radius drawn from the NFW enclosed-mass profile inside an
+    approximate virial radius, direction isotropic scaled by volume-preserving
+    axis ratios b/a, c/a ~ U[0.5, 1], random orientation; velocity = halo bulk
+    N(0, 300) + internal N(0, sigma) with sigma = sqrt(G M / (2 r_vir)).
+    Field particles: lognormal density on a comoving grid of ``field_cell``
+    Mpc/h (sigma_ln rho = 1, white), Poisson counts, uniform within cells,
+    velocities N(0, 300).
+
+    Returns (halos, particles, M_p); particles are float32 except halo_id (int32).
+    """
+    rng = np.random.default_rng(seed)
+    side = field_deg * DEG
+    M = _masses(rng, n_halos, logM[0], logM[1], mass_function)
+    zh = rng.uniform(zr[0], zr[1], size=n_halos)
+    c = _concentration(rng, M, zh)
+    halos = dict(M=M, c=c, z=zh, theta_x=rng.uniform(0, side, n_halos), theta_y=rng.uniform(0, side, n_halos),
+                 v_los=rng.normal(0.0, 300.0, n_halos))
+    M_p = float(M.sum() / max(n_halo_particles, 1))
+    Nh = np.floor(M / M_p + rng.uniform(size=n_halos)).astype(np.int64)
+    hid = np.repeat(np.arange(n_halos, dtype=np.int32), Nh)
+    zt, chit = _chi_table(om)
+    # generator-side halo size: 200 rho_crit(z) overdensity (input shaping only)
+    E2 = om * (1 + zh) ** 3 + 1 - om
+    rho_c = 2.775e11 * E2
+    rv = (3 * M / (4 * np.pi * 200 * rho_c)) ** (1.0 / 3.0)
+    chih = np.interp(zh, zt, chit)
+    DA = chih / (1 + zh)
+    x = _nfw_inverse_cdf(rng.uniform(size=hid.size), c[hid])
+    r_e = x * (rv / c)[hid]
+    q = np.sort(rng.uniform(0.5, 1.0, size=(n_halos, 2)), axis=1)[:, ::-1]      # b/a >= c/a
+    axes = np.stack([np.ones(n_halos), q[:, 0], q[:, 1]], 1) / np.cbrt(q[:, 0] * q[:, 1])[:, None]
+    rot = _random_rotations(rng, n_halos)
+    nvec = rng.normal(size=(hid.size, 3))
+    nvec /= np.linalg.norm(nvec, axis=1, keepdims=True)
+    off = np.einsum("nij,nj->ni", rot[hid], nvec * axes[hid]) * r_e[:, None]    # physical Mpc/h
+    tx = halos["theta_x"][hid] + off[:, 0] / DA[hid]
+    ty = halos["theta_y"][hid] + off[:, 1] / DA[hid]
+    dchi = off[:, 2] * (1 + zh[hid])
+    zp = np.interp(chih[hid] + dchi, chit, zt)
+    sig = np.sqrt(4.30091e-9 * M / (2 * rv))
+    v = halos["v_los"][hid] + rng.normal(size=hid.size) * sig[hid]
+    parts = [dict(theta_x=tx, theta_y=ty, z=zp, v_los=v, halo_id=hid, r_i=r_e)]
+    if n_field > 0:
+        chi0, chi1 = np.interp(zr, zt, chit)
+        nx = int(np.ceil(side * chi1 / field_cell))
+        nz = int(np.ceil((chi1 - chi0) / field_cell))
+        lam = None
+        fx, fy, fz = [], [], []
+        # expected counts proportional to exp(g - 1/2) on cells whose centre lies in the cone
+        ix = np.arange(nx)
+        for kz in range(nz):
+            zc = chi0 + (kz + 0.5) * field_cell
+            g = rng.normal(size=(nx, nx))
+            xc = (ix + 0.5) * field_cell
+            inside = (xc[:, None] < side * zc) & (xc[None, :] < side * zc)
+            w = np.exp(g - 0.5) * inside
+            fx.append(w)
+        W = np.stack(fx, 0)
+        lam = n_field / W.sum()
+        cnt = rng.poisson(lam * W)
+        kz, kx, ky = np.nonzero(cnt)
+        nn = cnt[kz, kx, ky]
+        X = (np.repeat(kx, nn) + rng.uniform(size=nn.sum())) * field_cell
+        Y = (np.repeat(ky, nn) + rng.uniform(size=nn.sum())) * field_cell
+        Z = chi0 + (np.repeat(kz, nn) + rng.uniform(size=nn.sum())) * field_cell
+        keep = (X < side * Z) & (Y < side * Z) & (Z < chi1)
+        X, Y, Z = X[keep], Y[keep], Z[keep]
+        nf = X.size
+        parts.append(dict(theta_x=X / Z, theta_y=Y / Z, z=np.interp(Z, chit, zt), v_los=rng.normal(0, 300.0, nf),
+                          halo_id=np.full(nf, -1, dtype=np.int32), r_i=np.zeros(nf)))
+    P = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    out = {k: (v.astype(np.int32) if k == "halo_id" else v.astype(np.float32)) for k, v in P.items()}
+    return halos, out, M_p
+
+
+def pp_small(seed=3):
+    """CPU-sized particle workload: 0.4x0.4 deg, 96^2 pixels, 60 halos, ~6000 halo and ~3000 field particles."""
+    halos, parts, M_p = pp_lightcone(60, 6000, 3000, 0.4, zr=(0.05, 0.4), logM=(12.5, 14.5), field_cell=2.0,
+                                     seed=seed)
+    return halos, parts, M_p, 96, 0.4 * DEG / 96
+
+
+def pp_large(seed=3, n_particles=200_000_000):
+    """GPU-sized: 5x5 deg, 4096^2 pixels, z in [0.05,1.5]; 60% of the particles in 2e5 halos, 40% field."""
+    halos, parts, M_p = pp_lightcone(200_000, int(0.6 * n_particles), int(0.4 * n_particles), 5.0,
+                                     zr=(0.05, 1.5), seed=seed)
+    return halos, parts, M_p, 4096, 5.0 * DEG / 4096
