@@ -239,6 +239,80 @@ int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n
                      const int32_t *status, float *y_map, float *b_map, void *ws, size_t ws_bytes,
                      size_t *ws_needed, void *stream);
 
+/* ------------------------------------------------- surrogate (K10-K12) */
+/* A multilayer perceptron maps normalised (log10 M, ln c, z) to the projected
+ * electron pressure and density of the halo on a fixed grid of 64 impact
+ * parameters each, plus three scalars, replacing the boundary-condition solve
+ * and the table integrals (an addition to the paper's method).
+ *   q-grid   : q_k = (1 - cos(pi k / 63)) / 2, k = 0..63, r_perp = q R_t.
+ *   outputs  : y[0..63]   = ln( Y_P(q_k R_t) / (P_e0 R_t E_k) ),
+ *              y[64..127] = ln( Y_n(q_k R_t) / (n_e0 R_t E_k) ),  E_k = sqrt(1 - (q_k R_t / r_f)^2)
+ *              y[128] = ln x_f, y[129] = ln(P_e0 / erg cm^-3), y[130] = ln(n_e0 / cm^-3)
+ *              (standardised: the network predicts (y - mean) / std).
+ *   layers   : 3 -> 256 -> 256 -> 256 -> 144 (131 used), SiLU; the first layer
+ *              in FP32, the others BF16 on MFMA with FP32 accumulation.
+ * Parameter vector (FP32 master, BF16 compute copy), BP_MLP_NPARAMS floats:
+ *   W1 [256][16] (inputs padded to 16, columns >= 3 stay 0), b1[256],
+ *   W2 [256][256], b2, W3 [256][256], b3, W4 [144][256], b4[144]. */
+#define BP_MLP_NIN    3
+#define BP_MLP_IN    16
+#define BP_MLP_HID  256
+#define BP_MLP_OUT  144
+#define BP_MLP_NOUT 131
+#define BP_MLP_NQ    64
+#define BP_S_OUT_OF_DOMAIN 32   /* status bit: outside the surrogate's training domain */
+
+int64_t bp_mlp_nparams(void);
+size_t bp_mlp_act_bytes(int64_t n);
+size_t bp_mlp_backward_ws_bytes(int64_t n);
+/* forward: x [n][16] FP32 features (bp_surrogate_features), y [n][144] FP32;
+ * act (bp_mlp_act_bytes(n) bytes) receives the activations backward needs. */
+int bp_mlp_forward(const float *w, const uint16_t *w_bf16, int64_t n, const float *x, float *y, void *act,
+                   void *stream);
+/* backward: dy [n][144] = dL/dy; grad receives dL/dw (BP_MLP_NPARAMS floats,
+ * overwritten).  Deterministic (fixed-order reductions). */
+int bp_mlp_backward(const float *w, const uint16_t *w_bf16, int64_t n, const float *x, const void *act,
+                    const float *dy, float *grad, void *ws, size_t ws_bytes, void *stream);
+/* Adam step on the FP32 master weights; refreshes the BF16 copy. */
+int bp_mlp_adam(int64_t np, float *w, float *m, float *v, const float *g, uint16_t *w_bf16, float lr, float beta1,
+                float beta2, float eps, int64_t step, void *stream);
+int bp_mlp_to_bf16(int64_t np, const float *w, uint16_t *w_bf16, void *stream);
+
+/* Halo structure without the boundary-condition solve (r_vir, r500, stars,
+ * distances, optical depth, f(z)): the cheap part of bp_icm_solve that the
+ * surrogate path keeps exact.  Same layout; A, XF, RF, RHO0, P0, RT, RES_E
+ * are left 0 and status carries BP_S_OUT_OF_DOMAIN for halos outside
+ * log10 M in [12.5, 15.5], c in [2, 15], z in [0.05, 3]. */
+int bp_halo_structure(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,
+                      double *sol, int32_t *status, void *stream);
+/* Network features [n][16] from (M, c, z). */
+int bp_surrogate_features(int64_t n, const double *M, const double *c, const double *z, float *x, void *stream);
+/* Training targets [n][144] (standardisation not applied) from an exact solve
+ * and its tables (halos with a non-zero status get NaN rows). */
+int bp_surrogate_targets(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                         const float *tables, const float *meta, float *targets, void *stream);
+/* Column mean and standard deviation of targets over n rows (FP64 sums). */
+int bp_surrogate_stats(int64_t n, const float *targets, float *mean, float *std, void *stream);
+/* Gather rows: out[i] = in[idx[i]] (cols floats per row). */
+int bp_gather_rows(int64_t n, int32_t cols, const float *in, const int64_t *idx, float *out, void *stream);
+/* MSE loss over the 131 used outputs against standardised targets:
+ * dy = 2 (y - (t - mean)/std) / (n * 131); loss_rows[i] = row sum of squares. */
+int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const float *mean, const float *std, float *dy,
+                     float *loss_rows, void *stream);
+/* Apply the network output: completes sol (XF, RF, RT) for in-domain halos
+ * whose structure came from bp_halo_structure, writes q-tables
+ * [n][2*BP_MLP_NQ] (G values, not logs) and meta (PE0, NE0; grid fields 0). */
+int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
+                       double *sol, const int32_t *status, float *qtables, float *meta, void *stream);
+/* HP flat paste from surrogate q-tables: as bp_hp_paste_flat with
+ * Y_P(r_perp) = P_e0 R_t E(r_perp) G_P(q), q = r_perp / R_t, cubic interpolation
+ * in s = acos(1 - 2q)/pi on the 64 nodes.  Halos whose status is non-zero are
+ * skipped (paste them with the exact path). */
+int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                       const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                       const float *qtables, const float *meta, float *y_map, float *b_map, void *ws,
+                       size_t ws_bytes, size_t *ws_needed, void *stream);
+
 /* ------------------------------------------------------------- profiling */
 /* Optional timing of the library's main kernels with HIP events recorded on
  * the launch stream (for roofline measurement).  bp_profiling(1) enables it
@@ -257,6 +331,10 @@ enum {
     BP_PROF_PP_KNN,         /* K6 k_pp_knn */
     BP_PROF_PP_PLAN,        /* K7 amplitudes + pair emission + sort */
     BP_PROF_PP_DEPOSIT,     /* K8 narrow + wide deposits */
+    BP_PROF_MLP_FWD,        /* K10 surrogate forward */
+    BP_PROF_MLP_BWD,        /* K11 surrogate backward */
+    BP_PROF_SURR_APPLY,     /* K10 epilogue: tables from the network output */
+    BP_PROF_FLATQ_DEPOSIT,  /* K3 deposit from surrogate tables */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

@@ -77,11 +77,31 @@ _SIGS = {
     "bp_pp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                    C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_size_t,
                                    C.POINTER(C.c_size_t), _VP]),
+    "bp_mlp_nparams": (C.c_int64, []),
+    "bp_mlp_act_bytes": (C.c_size_t, [C.c_int64]),
+    "bp_mlp_backward_ws_bytes": (C.c_size_t, [C.c_int64]),
+    "bp_mlp_forward": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP, _VP, _VP]),
+    "bp_mlp_backward": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_size_t, _VP]),
+    "bp_mlp_adam": (C.c_int, [C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_float, C.c_float, C.c_float, C.c_float,
+                              C.c_int64, _VP]),
+    "bp_mlp_to_bf16": (C.c_int, [C.c_int64, _VP, _VP, _VP]),
+    "bp_halo_structure": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_features": (C.c_int, [C.c_int64, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_targets": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_stats": (C.c_int, [C.c_int64, _VP, _VP, _VP, _VP]),
+    "bp_gather_rows": (C.c_int, [C.c_int64, C.c_int32, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_mse": (C.c_int, [C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_apply": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                     _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_profiling": (C.c_int, [C.c_int]),
     "bp_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
-                                          "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT"])}
+                                          "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT", "MLP_FWD", "MLP_BWD",
+                                          "SURR_APPLY", "FLATQ_DEPOSIT"])}
+MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
+S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -181,6 +201,15 @@ def hp_paste_flat(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v
     _with_workspace(_lib.bp_hp_paste_flat, "bp_hp_paste_flat", ws,
                     (C.byref(params), int(npix), float(pix_rad), theta_x.numel(), _ptr(theta_x), _ptr(theta_y),
                      _ptr(v_los), _ptr(sol), _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+
+
+def hp_paste_flat_q(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v_los, sol, status, qtables, meta,
+                    y_map, b_map, ws: Workspace | None = None):
+    """K3 with surrogate q-tables (halos with a non-zero status are skipped)."""
+    ws = ws or _ws_for(y_map.device)
+    _with_workspace(_lib.bp_hp_paste_flat_q, "bp_hp_paste_flat_q", ws,
+                    (C.byref(params), int(npix), float(pix_rad), theta_x.numel(), _ptr(theta_x), _ptr(theta_y),
+                     _ptr(v_los), _ptr(sol), _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
 
 
 def hp_paste_healpix(params: Params, nside: int, theta, phi, v_los, sol, status, tables, meta, y_map, b_map,

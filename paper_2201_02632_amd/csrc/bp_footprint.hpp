@@ -68,4 +68,20 @@ __device__ inline void footprint_value(const Rec &R, const float *__restrict__ t
 }
 
 
+// Surrogate tables: 64 nodes per quantity at q_k = (1 - cos(pi k/63))/2, q = r_perp/R_t,
+// interpolated in s = acos(1 - 2q)/pi.  R.eta_lo holds R_t and R.eta_ih 1/R_t (record units).
+// Y = P_e0 R_t E G(q) with E = sqrt(1 - r_perp^2 / r_f^2) = sqrt(U2) / r_f.
+template <class Rec>
+__device__ inline void footprint_value_q(const Rec &R, const float *__restrict__ tab, float r2, float U2, float *vp,
+                                         float *vn) {
+    float q = fminf(sqrtf(r2) * R.eta_ih, 1.0f);
+    float sidx = acosf(1.0f - 2.0f * q) * (63.0f / 3.14159265358979f);
+    float gp, gn;
+    lagr4x2(tab, tab + BP_MLP_NQ, BP_MLP_NQ, sidx, &gp, &gn);
+    float E = sqrtf(fmaxf(U2, 0.0f)) / R.rf;
+    float f = R.eta_lo * E;
+    *vp = gp * f;
+    *vn = gn * f;
+}
+
 }  // namespace bp

@@ -58,7 +58,8 @@ struct FlatGeom {
     double pix;
 };
 
-// Build records and count pairs.
+// Build records and count pairs.  kQ: tables are the surrogate's q-grid (meta holds only PE0, NE0).
+template <bool kQ>
 __global__ void __launch_bounds__(256) k_flat_setup(bp_params P, FlatGeom Gm, int64_t n, const double *__restrict__ thx,
                                                     const double *__restrict__ thy, const double *__restrict__ vlos,
                                                     const double *__restrict__ sol, const int32_t *__restrict__ status,
@@ -95,12 +96,17 @@ __global__ void __launch_bounds__(256) k_flat_setup(bp_params P, FlatGeom Gm, in
             double D = shell ? rf * rf - rv * rv : 0.0;
             r.D = (float)D; r.sqD = (float)sqrt(D);
             r.r2min = (float)(1e-10 * ra * ra);
-            float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
-            float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
-            float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
-            r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
-            r.om_lo = olo; r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
-            r.ze_lo = zlo; r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+            if (!kQ) {
+                float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
+                float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
+                float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
+                r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
+                r.om_lo = olo; r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
+                r.ze_lo = zlo; r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+            } else {
+                r.eta_lo = (float)Rt;       // q-grid: R_t in pixels and its inverse
+                r.eta_ih = (float)(1.0 / Rt);
+            }
             double Lcm = Lpix * kMpc / P.h;
             r.amp_y = (float)(kSigmaT / kMeC2 * (double)Mt(BP_META_PE0) * Lcm);
             r.amp_b = (float)(kSigmaT * (double)Mt(BP_META_NE0) * Lcm * (vlos[i] * 1e5 / kC) * exp(-S(BP_SOL_TAU)));
@@ -170,6 +176,7 @@ __device__ inline bool inside_fp64(int i, int j, double pix, double thx, double 
     return rp < Rt;
 }
 
+template <bool kQ>
 __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, const FlatRec *__restrict__ rec,
                                                       const float *__restrict__ tables, const uint32_t *__restrict__ vals,
                                                       const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
@@ -198,7 +205,7 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
         const uint32_t h = vals[p];
         if (h >= (uint32_t)n) continue;
         const FlatRec R = rec[h];
-        const float *tab = tables + (int64_t)h * BP_TAB_STRIDE;
+        const float *tab = tables + (int64_t)h * (kQ ? 2 * BP_MLP_NQ : BP_TAB_STRIDE);
         const float dxb = (float)(pi - R.cxi) + (0.5f - R.cxf);
         for (int k = 0; k < 4; ++k) {
             const int pj = pj0 + 4 * k;
@@ -219,7 +226,8 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
                     U2 = (float)(R.rf2d - r2d);
                 }
                 float vp, vn;
-                footprint_value(R, tab, r2, u2, U2, &vp, &vn);
+                if (kQ) footprint_value_q(R, tab, r2, U2, &vp, &vn);
+                else footprint_value(R, tab, r2, u2, U2, &vp, &vn);
                 kahan_add(ys[k], yc[k], R.amp_y * vp);
                 kahan_add(bs[k], bc[k], R.amp_b * vn);
             }
@@ -237,7 +245,8 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
 
 using namespace bp;
 
-extern "C" int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+template <bool kQ>
+static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
                                 const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
                                 const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
                                 size_t ws_bytes, size_t *ws_needed, void *stream) {
@@ -270,7 +279,7 @@ extern "C" int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad
     if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
     if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_flat_setup, dim3(blocks), dim3(256), 0, s, *p, Gm, n, theta_x, theta_y, v_los, sol, status,
+    hipLaunchKernelGGL(k_flat_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, Gm, n, theta_x, theta_y, v_los, sol, status,
                        meta, rec, cnt, total);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long np64 = 0;
@@ -313,9 +322,25 @@ extern "C" int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad
                        (uint32_t)ntiles);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     prof_end(BP_PROF_FLAT_PLAN, s);
-    prof_begin(BP_PROF_FLAT_DEPOSIT, s);
-    hipLaunchKernelGGL(k_flat_deposit, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, Gm, n, rec, tables, vs,
+    prof_begin(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
+    hipLaunchKernelGGL(k_flat_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, Gm, n, rec, tables, vs,
                        tst, ten, theta_x, theta_y, sol, y_map, b_map, (int)ntiles);
-    prof_end(BP_PROF_FLAT_DEPOSIT, s);
+    prof_end(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                                const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                                const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
+                                size_t ws_bytes, size_t *ws_needed, void *stream) {
+    return paste_flat_impl<false>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, tables, meta, y_map,
+                                  b_map, ws, ws_bytes, ws_needed, stream);
+}
+
+extern "C" int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                                  const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                                  const float *qtables, const float *meta, float *y_map, float *b_map, void *ws,
+                                  size_t ws_bytes, size_t *ws_needed, void *stream) {
+    return paste_flat_impl<true>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, qtables, meta, y_map,
+                                 b_map, ws, ws_bytes, ws_needed, stream);
 }

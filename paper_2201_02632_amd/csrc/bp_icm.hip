@@ -174,6 +174,7 @@ __device__ void distances(const bp_params &P, const GaussRules &G, double z, dou
 
 #define NSCAN 47
 
+template <bool kStructureOnly>
 __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min,
                                                   const double *__restrict__ cin, const double *__restrict__ zin,
                                                   double *__restrict__ sol, int32_t *__restrict__ status) {
@@ -217,6 +218,24 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
     double x500 = exp(lx);
     double r500 = x500 * rs, M500 = 4.0 * kPi * rhos * rs * rs * rs * nfw_m(x500);
     S(BP_SOL_R500) = r500; S(BP_SOL_M500) = M500;
+    if (kStructureOnly) {
+        // the surrogate replaces everything from here to the tables; keep the exact geometry
+        double chi_u, tau_u;
+        distances(P, G, z, &chi_u, &tau_u);
+        double cH = kCkms / 100.0, chi = cH * chi_u;
+        S(BP_SOL_CHI) = chi;
+        S(BP_SOL_DA) = chi / zp;
+        double H0 = 100.0 * h * 1e5 / kMpc;
+        double rho_cr0 = 3.0 * H0 * H0 / (8.0 * kPi * kG);
+        double ne_bar = P.Omega_b * rho_cr0 / (2.0 / (1.0 + P.X_H) * kMp);
+        S(BP_SOL_TAU) = kSigmaT * ne_bar * (kC / H0) * tau_u;
+        double fmax = pow(4.0, -P.n_nt) / P.alpha_nt;
+        S(BP_SOL_FNT) = fmin(pow(zp, P.beta_nt), (fmax - 1.0) * tanh(P.beta_nt * z) + 1.0);
+        double lm = log10(M);
+        bool in = lm >= 12.5 && lm <= 15.5 && c >= 2.0 && c <= 15.0 && z >= 0.05 && z <= 3.0;
+        status[i] = in ? 0 : BP_S_OUT_OF_DOMAIN;
+        return;
+    }
 
     // --- stars (Sec. 2.2); the 3e14 Msun pivot is in Msun ---
     double fb = P.Omega_b / P.Omega_m;
@@ -537,7 +556,7 @@ extern "C" int bp_icm_solve(const bp_params *p, int64_t n, const double *M, cons
     int64_t blocks = (n + 63) / 64;
     if (blocks > 0x7fffffff) return BP_E_OVERFLOW;
     prof_begin(BP_PROF_ICM, s);
-    hipLaunchKernelGGL(k_icm_solve, dim3((unsigned)blocks), dim3(64), 0, s, *p, gauss_rules(), n, M, c, z, sol,
+    hipLaunchKernelGGL(k_icm_solve<false>, dim3((unsigned)blocks), dim3(64), 0, s, *p, gauss_rules(), n, M, c, z, sol,
                        status);
     prof_end(BP_PROF_ICM, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
@@ -555,5 +574,19 @@ extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *so
     hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_ZONE), 0, (hipStream_t)stream, *p, gauss_rules(),
                        n, sol, status, tables, meta);
     prof_end(BP_PROF_TABLES, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_halo_structure(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,
+                                 double *sol, int32_t *status, void *stream) {
+    int e = check_params(p);
+    if (e) return e;
+    if (n < 0) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if (!M || !c || !z || !sol || !status) return BP_E_ARG;
+    int64_t blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffff) return BP_E_OVERFLOW;
+    hipLaunchKernelGGL(k_icm_solve<true>, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, *p, gauss_rules(),
+                       n, M, c, z, sol, status);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -1,0 +1,317 @@
+// K10-K12: the profile-table surrogate network, forward, backward and Adam.
+//
+// Network (inputs normalised (log10 M, ln c, z)):
+//   z1 = W1 x + b1                       FP32 (3 inputs: VALU)
+//   h1 = bf16(silu(z1))
+//   z2 = W2 h1 + b2, h2 = bf16(silu(z2)) BF16 MFMA, FP32 accumulation
+//   z3 = W3 h2 + b3, h3 = bf16(silu(z3))
+//   y  = W4 h3 + b4                      FP32 output
+// The hidden-layer products run on v_mfma_f32_16x16x16_bf16: a workgroup
+// computes a 64x64 output tile with four wavefronts (2x2 blocks of 16x16
+// each), staging 64x16 slices of both operands in LDS per K step.  Weight
+// gradients reduce over the batch with split-K partial tiles summed in a
+// fixed order, so training is deterministic.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bp_device.hpp"
+#include "bp_internal.hpp"
+
+namespace bp {
+
+typedef short sx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+// round-to-nearest-even FP32 -> BF16 (NaN kept quiet)
+__device__ inline uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu(float z) {
+    float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+enum { EPI_BIAS_SILU = 0, EPI_BIAS = 1, EPI_DSILU = 2, EPI_PARTIAL = 3 };
+
+struct GemmArgs {
+    int64_t M, N, K;
+    const uint16_t *A; int64_t a_m, a_k;   // A(m,k) = A[m*a_m + k*a_k]
+    const uint16_t *B; int64_t b_k, b_n;   // B(k,n) = B[k*b_k + n*b_n]
+    const float *bias;                      // EPI_BIAS*: [N]
+    float *Z; int64_t ldz;                  // EPI_BIAS_SILU: pre-activation out (optional); EPI_DSILU: in
+    uint16_t *H; int64_t ldh;               // bf16 output (EPI_BIAS_SILU, EPI_DSILU)
+    float *F; int64_t ldf;                  // fp32 output (EPI_BIAS: y; EPI_DSILU: g*silu'(z) optional; PARTIAL)
+    int64_t kchunk;                         // split-K chunk (PARTIAL), else K
+};
+
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+    __shared__ uint16_t As[64][17];   // [m][k] (+1 pad)
+    __shared__ uint16_t Bs[16][65];   // [k][n]
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+    const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t ke = min(g.K, kb + g.kchunk);
+    fx4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
+        // stage A (64x16) and B (16x64): 1024 elements each, 4 per thread
+        for (int q = 0; q < 4; ++q) {
+            int e = t + 256 * q;
+            int am = e >> 4, ak = e & 15;
+            int64_t gm = m0 + am, gk = k0 + ak;
+            As[am][ak] = (gm < g.M && gk < ke) ? g.A[gm * g.a_m + gk * g.a_k] : (uint16_t)0;
+            int bk = e >> 6, bn = e & 63;
+            int64_t gk2 = k0 + bk, gn = n0 + bn;
+            Bs[bk][bn] = (gk2 < ke && gn < g.N) ? g.B[gk2 * g.b_k + gn * g.b_n] : (uint16_t)0;
+        }
+        __syncthreads();
+        for (int bi = 0; bi < 2; ++bi) {
+            sx4 af;
+            for (int j = 0; j < 4; ++j) af[j] = (short)As[wm + 16 * bi + (lane & 15)][4 * (lane >> 4) + j];
+            for (int bj = 0; bj < 2; ++bj) {
+                sx4 bf;
+                for (int j = 0; j < 4; ++j) bf[j] = (short)Bs[4 * (lane >> 4) + j][wn + 16 * bj + (lane & 15)];
+                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc[bi][bj], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds D[4*(lane>>4)+j][lane&15] of each 16x16 block
+    for (int bi = 0; bi < 2; ++bi)
+        for (int bj = 0; bj < 2; ++bj)
+            for (int j = 0; j < 4; ++j) {
+                int64_t m = m0 + wm + 16 * bi + 4 * (lane >> 4) + j;
+                int64_t n = n0 + wn + 16 * bj + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[bi][bj][j];
+                if (EPI == EPI_BIAS_SILU) {
+                    float z = v + g.bias[n];
+                    if (g.Z) g.Z[m * g.ldz + n] = z;
+                    g.H[m * g.ldh + n] = f2bf(silu(z));
+                } else if (EPI == EPI_BIAS) {
+                    g.F[m * g.ldf + n] = v + g.bias[n];
+                } else if (EPI == EPI_DSILU) {
+                    float d = v * dsilu(g.Z[m * g.ldz + n]);
+                    if (g.F) g.F[m * g.ldf + n] = d;
+                    g.H[m * g.ldh + n] = f2bf(d);
+                } else {
+                    g.F[(int64_t)blockIdx.z * g.M * g.N + m * g.N + n] = v;
+                }
+            }
+}
+
+static int launch_gemm(int epi, const GemmArgs &g, int ksplit, hipStream_t s) {
+    if ((g.M + 63) / 64 > 0x7fffffffLL) return BP_E_OVERFLOW;
+    dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64), (unsigned)ksplit);
+    switch (epi) {
+        case EPI_BIAS_SILU: hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS_SILU>, grid, dim3(256), 0, s, g); break;
+        case EPI_BIAS: hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS>, grid, dim3(256), 0, s, g); break;
+        case EPI_DSILU: hipLaunchKernelGGL(k_gemm_bf16<EPI_DSILU>, grid, dim3(256), 0, s, g); break;
+        default: hipLaunchKernelGGL(k_gemm_bf16<EPI_PARTIAL>, grid, dim3(256), 0, s, g); break;
+    }
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+// first layer in FP32: z1 = W1 x + b1, h1 = bf16(silu(z1)); x has BP_MLP_IN columns (only BP_MLP_NIN used)
+__global__ void k_layer1(int64_t n, const float *__restrict__ W1, const float *__restrict__ b1,
+                         const float *__restrict__ x, float *__restrict__ Z1, uint16_t *__restrict__ H1) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * BP_MLP_HID) return;
+    int64_t m = e / BP_MLP_HID;
+    int o = (int)(e % BP_MLP_HID);
+    float z = b1[o];
+    for (int k = 0; k < BP_MLP_NIN; ++k) z += W1[o * BP_MLP_IN + k] * x[m * BP_MLP_IN + k];
+    if (Z1) Z1[e] = z;
+    H1[e] = f2bf(silu(z));
+}
+
+// sum over split-K partials in fixed order: out[i] = sum_s part[s][i]
+__global__ void k_reduce_partials(int64_t count, int ks, const float *__restrict__ part, float *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int q = 0; q < ks; ++q) s += part[(int64_t)q * count + i];
+    out[i] = s;
+}
+
+// column sums over the batch (bias gradients), fixed order
+__global__ void k_colsum(int64_t n, int cols, int64_t ld, const float *__restrict__ a, float *__restrict__ out) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.0f;
+    for (int64_t m = 0; m < n; ++m) s += a[m * ld + c];
+    out[c] = s;
+}
+
+// dW1 = d1^T x (K = batch) in FP32, one thread per weight, fixed order
+__global__ void k_dw1(int64_t n, const float *__restrict__ d1, const float *__restrict__ x, float *__restrict__ gW1) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= BP_MLP_HID * BP_MLP_IN) return;
+    int o = e / BP_MLP_IN, k = e % BP_MLP_IN;
+    float s = 0.0f;
+    if (k < BP_MLP_NIN)
+        for (int64_t m = 0; m < n; ++m) s += d1[m * BP_MLP_HID + o] * x[m * BP_MLP_IN + k];
+    gW1[e] = s;
+}
+
+__global__ void k_to_bf16(int64_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = f2bf(a[i]);
+}
+
+__global__ void k_adam(int64_t n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, uint16_t *__restrict__ wb, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi; v[i] = vi;
+    float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+}
+
+// parameter offsets in the flat parameter vector
+struct Off { int64_t W1, b1, W2, b2, W3, b3, W4, b4, total; };
+static Off offsets() {
+    Off o;
+    o.W1 = 0; o.b1 = o.W1 + BP_MLP_HID * BP_MLP_IN;
+    o.W2 = o.b1 + BP_MLP_HID; o.b2 = o.W2 + BP_MLP_HID * BP_MLP_HID;
+    o.W3 = o.b2 + BP_MLP_HID; o.b3 = o.W3 + BP_MLP_HID * BP_MLP_HID;
+    o.W4 = o.b3 + BP_MLP_HID; o.b4 = o.W4 + BP_MLP_OUT * BP_MLP_HID;
+    o.total = o.b4 + BP_MLP_OUT;
+    return o;
+}
+
+// activation buffer layout (per sample): z1 z2 z3 (fp32) and h1 h2 h3 (bf16)
+static size_t act_bytes(int64_t n) { return (size_t)n * BP_MLP_HID * (3 * 4 + 3 * 2) + 1024; }
+
+}  // namespace bp
+
+using namespace bp;
+
+extern "C" int64_t bp_mlp_nparams(void) { return offsets().total; }
+extern "C" size_t bp_mlp_act_bytes(int64_t n) { return n < 0 ? 0 : act_bytes(n); }
+
+extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, const float *x, float *y, void *act,
+                              void *stream) {
+    if (n < 0 || !w || !wb || !x || !y || !act) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Off o = offsets();
+    float *Z1 = (float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
+    uint16_t *H1 = (uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
+    prof_begin(BP_PROF_MLP_FWD, s);
+    int64_t e = n * BP_MLP_HID;
+    hipLaunchKernelGGL(k_layer1, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, n, w + o.W1, w + o.b1, x, Z1, H1);
+    GemmArgs g = {};
+    g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID;
+    // hidden layers: A = h (row-major [n][256]), B(k, n') = W[n'][k]
+    g.N = BP_MLP_HID; g.A = H1; g.a_m = BP_MLP_HID; g.a_k = 1; g.B = wb + o.W2; g.b_k = 1; g.b_n = BP_MLP_HID;
+    g.bias = w + o.b2; g.Z = Z2; g.ldz = BP_MLP_HID; g.H = H2; g.ldh = BP_MLP_HID;
+    int r = launch_gemm(EPI_BIAS_SILU, g, 1, s);
+    if (r) return r;
+    g.A = H2; g.B = wb + o.W3; g.bias = w + o.b3; g.Z = Z3; g.H = H3;
+    r = launch_gemm(EPI_BIAS_SILU, g, 1, s);
+    if (r) return r;
+    g.N = BP_MLP_OUT; g.A = H3; g.B = wb + o.W4; g.bias = w + o.b4; g.F = y; g.ldf = BP_MLP_OUT; g.Z = nullptr;
+    r = launch_gemm(EPI_BIAS, g, 1, s);
+    prof_end(BP_PROF_MLP_FWD, s);
+    return r;
+}
+
+extern "C" size_t bp_mlp_backward_ws_bytes(int64_t n) {
+    int ks = (int)((n + 511) / 512);
+    if (ks < 1) ks = 1;
+    return (size_t)n * BP_MLP_OUT * 2 + (size_t)n * BP_MLP_HID * (2 + 4) * 2 +
+           (size_t)ks * BP_MLP_HID * BP_MLP_HID * 4 + 4096;
+}
+
+extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
+                               const float *dy, float *grad, void *ws, size_t ws_bytes, void *stream) {
+    if (n <= 0 || !w || !wb || !x || !act || !dy || !grad || !ws) return BP_E_ARG;
+    if (ws_bytes < bp_mlp_backward_ws_bytes(n)) return BP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Off o = offsets();
+    const float *Z1 = (const float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
+    const uint16_t *H1 = (const uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
+    const int ks = (int)((n + 511) / 512);
+    const int64_t kchunk = (((n + ks - 1) / ks + 15) / 16) * 16;
+    Arena A(ws, ws_bytes);
+    uint16_t *G4 = A.take<uint16_t>(n * BP_MLP_OUT);
+    uint16_t *Gb = A.take<uint16_t>(n * BP_MLP_HID), *Gc = A.take<uint16_t>(n * BP_MLP_HID);
+    float *Df = A.take<float>(n * BP_MLP_HID), *Dg = A.take<float>(n * BP_MLP_HID);
+    float *part = A.take<float>((int64_t)ks * BP_MLP_HID * BP_MLP_HID);
+    prof_begin(BP_PROF_MLP_BWD, s);
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * BP_MLP_OUT + 255) / 256)), dim3(256), 0, s, n * BP_MLP_OUT, dy,
+                       G4);
+    // output layer: dW4 = g4^T h3, db4 = sum dy
+    auto wgrad = [&](const uint16_t *Gt, int64_t ldg, int64_t rows, const uint16_t *Hin, int64_t gw_off) -> int {
+        GemmArgs g = {};
+        g.M = rows; g.N = BP_MLP_HID; g.K = n; g.kchunk = kchunk;
+        g.A = Gt; g.a_m = 1; g.a_k = ldg;          // A(m=o, k=s) = G[s][o]
+        g.B = Hin; g.b_k = BP_MLP_HID; g.b_n = 1;  // B(k=s, n=i) = h[s][i]
+        g.F = part;
+        int r = launch_gemm(EPI_PARTIAL, g, ks, s);
+        if (r) return r;
+        int64_t cnt = rows * BP_MLP_HID;
+        hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, ks, part,
+                           grad + gw_off);
+        return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+    };
+    int r = wgrad(G4, BP_MLP_OUT, BP_MLP_OUT, H3, o.W4);
+    if (r) return r;
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_OUT), 0, s, n, BP_MLP_OUT, (int64_t)BP_MLP_OUT, dy, grad + o.b4);
+    // dh3 = g4 W4 ; d3 = dh3 * silu'(z3)
+    auto dgrad = [&](const uint16_t *Gin, int64_t kdim, const uint16_t *W, const float *Z, uint16_t *Gout,
+                     float *Dout) -> int {
+        GemmArgs g = {};
+        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = kdim;
+        g.A = Gin; g.a_m = kdim; g.a_k = 1;               // A(s, o) = G[s][o]
+        g.B = W; g.b_k = BP_MLP_HID; g.b_n = 1;           // B(o, i) = W[o][i]
+        g.Z = (float *)Z; g.ldz = BP_MLP_HID; g.H = Gout; g.ldh = BP_MLP_HID; g.F = Dout; g.ldf = BP_MLP_HID;
+        return launch_gemm(EPI_DSILU, g, 1, s);
+    };
+    r = dgrad(G4, BP_MLP_OUT, wb + o.W4, Z3, Gb, Df);
+    if (r) return r;
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_HID), 0, s, n, BP_MLP_HID, (int64_t)BP_MLP_HID, Df, grad + o.b3);
+    r = wgrad(Gb, BP_MLP_HID, BP_MLP_HID, H2, o.W3);
+    if (r) return r;
+    r = dgrad(Gb, BP_MLP_HID, wb + o.W3, Z2, Gc, Dg);
+    if (r) return r;
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_HID), 0, s, n, BP_MLP_HID, (int64_t)BP_MLP_HID, Dg, grad + o.b2);
+    r = wgrad(Gc, BP_MLP_HID, BP_MLP_HID, H1, o.W2);
+    if (r) return r;
+    r = dgrad(Gc, BP_MLP_HID, wb + o.W2, Z1, Gb, Df);   // d1 in Df (fp32); its bf16 copy is unused
+    if (r) return r;
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_HID), 0, s, n, BP_MLP_HID, (int64_t)BP_MLP_HID, Df, grad + o.b1);
+    hipLaunchKernelGGL(k_dw1, dim3((BP_MLP_HID * BP_MLP_IN + 255) / 256), dim3(256), 0, s, n, Df, x, grad + o.W1);
+    prof_end(BP_PROF_MLP_BWD, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_mlp_adam(int64_t np, float *w, float *m, float *v, const float *g, uint16_t *wb, float lr, float b1,
+                           float b2, float eps, int64_t step, void *stream) {
+    if (np <= 0 || !w || !m || !v || !g || !wb || step < 1) return BP_E_ARG;
+    float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, (hipStream_t)stream, np, w, m, v, g,
+                       wb, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_mlp_to_bf16(int64_t np, const float *w, uint16_t *wb, void *stream) {
+    if (np <= 0 || !w || !wb) return BP_E_ARG;
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, (hipStream_t)stream, np, w, wb);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}

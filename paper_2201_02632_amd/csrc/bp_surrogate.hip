@@ -1,0 +1,210 @@
+// Surrogate data path: network features, training targets from the exact
+// solve, column statistics, batch gathering, the loss gradient, and the
+// inference epilogue that turns network outputs into deposit tables.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bp_device.hpp"
+#include "bp_footprint.hpp"
+#include "bp_internal.hpp"
+
+namespace bp {
+
+// normalised inputs: log10 M in [12.5, 15.5], ln c in [ln 2, ln 15], z in [0.05, 3] -> about [-1, 1]
+__global__ void k_features(int64_t n, const double *__restrict__ M, const double *__restrict__ c,
+                           const double *__restrict__ z, float *__restrict__ x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double lc0 = 0.5 * (log(2.0) + log(15.0)), lch = 0.5 * (log(15.0) - log(2.0));
+    float *r = x + i * BP_MLP_IN;
+    r[0] = (float)((log10(M[i]) - 14.0) / 1.5);
+    r[1] = (float)((log(c[i]) - lc0) / lch);
+    r[2] = (float)((z[i] - 1.525) / 1.475);
+    for (int k = 3; k < BP_MLP_IN; ++k) r[k] = 0.0f;
+}
+
+__host__ __device__ inline double qnode(int k) { return 0.5 * (1.0 - cos(kPi * k / (BP_MLP_NQ - 1))); }
+
+// record in units of R_t for evaluating the exact zone tables at q = r_perp / R_t
+struct UnitRec {
+    float Rt2, ra, ra2, rv2, rf, rf2, D, sqD, r2min;
+    float eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih;
+    int32_t flags;
+};
+
+// one thread per (halo, q node); thread k = 0 also writes the scalars and padding
+__global__ void k_targets(int64_t n, const double *__restrict__ sol, const int32_t *__restrict__ status,
+                          const float *__restrict__ tables, const float *__restrict__ meta, float *__restrict__ t) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * BP_MLP_NQ) return;
+    int64_t i = e / BP_MLP_NQ;
+    int k = (int)(e % BP_MLP_NQ);
+    float *row = t + i * BP_MLP_OUT;
+    auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
+    auto Mt = [&](int f) { return meta[(int64_t)f * n + i]; };
+    if (status[i] & ~BP_S_MULTI_ROOT) {
+        const float nanv = __int_as_float(0x7fc00000);
+        row[k] = nanv; row[BP_MLP_NQ + k] = nanv;
+        if (k == 0)
+            for (int q = 2 * BP_MLP_NQ; q < BP_MLP_OUT; ++q) row[q] = q < BP_MLP_NOUT ? nanv : 0.0f;
+        return;
+    }
+    const double Rt = S(BP_SOL_RT), rv = S(BP_SOL_RVIR) / Rt, rf = S(BP_SOL_RF) / Rt, ra = fmin(rv, rf);
+    UnitRec R;
+    R.Rt2 = 1.0f;
+    R.ra = (float)ra; R.ra2 = (float)(ra * ra); R.rv2 = (float)(rv * rv);
+    R.rf = (float)rf; R.rf2 = (float)(rf * rf);
+    const bool shell = rf > rv;
+    const double D = shell ? rf * rf - rv * rv : 0.0;
+    R.D = (float)D; R.sqD = (float)sqrt(D);
+    R.r2min = (float)(1e-10 * ra * ra);
+    float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI), olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI),
+          zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
+    R.eta_lo = elo; R.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
+    R.om_lo = olo; R.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
+    R.ze_lo = zlo; R.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+    R.flags = (shell ? 1 : 0) | ((1.0 > rv) ? 2 : 0) | 4;
+    double q = qnode(k);
+    if (k == BP_MLP_NQ - 1) q = 1.0 - 1e-6;   // the edge node: the limit from inside
+    double r2 = q * q;
+    float vp, vn;
+    footprint_value(R, tables + i * BP_TAB_STRIDE, (float)r2, (float)(ra * ra - r2), (float)(rf * rf - r2), &vp, &vn);
+    double E = sqrt(fmax(1.0 - r2 / (rf * rf), 0.0));
+    row[k] = (float)log((double)vp / E);
+    row[BP_MLP_NQ + k] = (float)log((double)vn / E);
+    if (k == 0) {
+        row[2 * BP_MLP_NQ + 0] = (float)log(S(BP_SOL_XF));
+        row[2 * BP_MLP_NQ + 1] = (float)log((double)Mt(BP_META_PE0));
+        row[2 * BP_MLP_NQ + 2] = (float)log((double)Mt(BP_META_NE0));
+        for (int q2 = BP_MLP_NOUT; q2 < BP_MLP_OUT; ++q2) row[q2] = 0.0f;
+    }
+}
+
+// column mean and standard deviation over rows with finite values (FP64 sums, fixed order)
+__global__ void k_stats(int64_t n, const float *__restrict__ t, float *__restrict__ mean, float *__restrict__ sd) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= BP_MLP_OUT) return;
+    double s = 0.0, s2 = 0.0;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        float v = t[i * BP_MLP_OUT + c];
+        if (!isfinite(v)) continue;
+        s += v; s2 += (double)v * v; ++cnt;
+    }
+    double mu = cnt ? s / cnt : 0.0;
+    double var = cnt ? s2 / cnt - mu * mu : 0.0;
+    mean[c] = (float)mu;
+    sd[c] = (c < BP_MLP_NOUT && var > 1e-20) ? (float)sqrt(var) : 1.0f;
+}
+
+__global__ void k_gather(int64_t n, int cols, const float *__restrict__ in, const int64_t *__restrict__ idx,
+                         float *__restrict__ out) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * cols) return;
+    int64_t i = e / cols;
+    int c = (int)(e % cols);
+    out[e] = in[idx[i] * cols + c];
+}
+
+// loss gradient for the standardised targets; rows with a non-finite target contribute nothing
+__global__ void k_mse(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
+                      const float *__restrict__ mean, const float *__restrict__ sd, float *__restrict__ dy,
+                      float *__restrict__ loss) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ok = true;
+    for (int c = 0; c < BP_MLP_NOUT; ++c) ok = ok && isfinite(t[i * BP_MLP_OUT + c]);
+    float acc = 0.0f;
+    const float scale = 2.0f / ((float)n * (float)BP_MLP_NOUT);
+    for (int c = 0; c < BP_MLP_OUT; ++c) {
+        float d = 0.0f;
+        if (ok && c < BP_MLP_NOUT) {
+            float ts = (t[i * BP_MLP_OUT + c] - mean[c]) / sd[c];
+            float r = y[i * BP_MLP_OUT + c] - ts;
+            acc += r * r;
+            d = scale * r;
+        }
+        dy[i * BP_MLP_OUT + c] = d;
+    }
+    loss[i] = acc;
+}
+
+// network output -> sol (XF, RF, RT), q-tables (G values) and meta (PE0, NE0)
+__global__ void k_apply(bp_params P, int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
+                        const float *__restrict__ sd, double *__restrict__ sol, const int32_t *__restrict__ status,
+                        float *__restrict__ qt, float *__restrict__ meta) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * 2 * BP_MLP_NQ) return;
+    int64_t i = e / (2 * BP_MLP_NQ);
+    int k = (int)(e % (2 * BP_MLP_NQ));
+    if (status[i]) return;
+    const float *row = y + i * BP_MLP_OUT;
+    qt[i * 2 * BP_MLP_NQ + k] = __expf(row[k] * sd[k] + mean[k]);
+    if (k == 0) {
+        const int c0 = 2 * BP_MLP_NQ;
+        double xf = exp((double)(row[c0] * sd[c0] + mean[c0]));
+        double rv = sol[(int64_t)BP_SOL_RVIR * n + i];
+        sol[(int64_t)BP_SOL_XF * n + i] = xf;
+        sol[(int64_t)BP_SOL_RF * n + i] = xf * rv;
+        sol[(int64_t)BP_SOL_RT * n + i] = fmin(xf * rv, P.trunc_r500 * sol[(int64_t)BP_SOL_R500 * n + i]);
+        meta[(int64_t)BP_META_PE0 * n + i] = expf(row[c0 + 1] * sd[c0 + 1] + mean[c0 + 1]);
+        meta[(int64_t)BP_META_NE0 * n + i] = expf(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2]);
+        for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
+    }
+}
+
+}  // namespace bp
+
+using namespace bp;
+
+static inline unsigned nblk(int64_t work) { return (unsigned)((work + 255) / 256); }
+
+extern "C" int bp_surrogate_features(int64_t n, const double *M, const double *c, const double *z, float *x,
+                                     void *stream) {
+    if (n < 0 || (n > 0 && (!M || !c || !z || !x))) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    hipLaunchKernelGGL(k_features, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, n, M, c, z, x);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_targets(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                                    const float *tables, const float *meta, float *targets, void *stream) {
+    if (!p || n < 0 || (n > 0 && (!sol || !status || !tables || !meta || !targets))) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    hipLaunchKernelGGL(k_targets, dim3(nblk(n * BP_MLP_NQ)), dim3(256), 0, (hipStream_t)stream, n, sol, status, tables,
+                       meta, targets);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_stats(int64_t n, const float *targets, float *mean, float *std, void *stream) {
+    if (n <= 0 || !targets || !mean || !std) return BP_E_ARG;
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(BP_MLP_OUT), 0, (hipStream_t)stream, n, targets, mean, std);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_gather_rows(int64_t n, int32_t cols, const float *in, const int64_t *idx, float *out, void *stream) {
+    if (n < 0 || cols <= 0 || (n > 0 && (!in || !idx || !out))) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(n * cols)), dim3(256), 0, (hipStream_t)stream, n, cols, in, idx, out);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const float *mean, const float *std,
+                                float *dy, float *loss_rows, void *stream) {
+    if (n <= 0 || !y || !targets || !mean || !std || !dy || !loss_rows) return BP_E_ARG;
+    hipLaunchKernelGGL(k_mse, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, n, y, targets, mean, std, dy,
+                       loss_rows);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
+                                  double *sol, const int32_t *status, float *qtables, float *meta, void *stream) {
+    if (!p || n < 0 || (n > 0 && (!y || !mean || !std || !sol || !status || !qtables || !meta))) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    prof_begin(BP_PROF_SURR_APPLY, s);
+    hipLaunchKernelGGL(k_apply, dim3(nblk(n * 2 * BP_MLP_NQ)), dim3(256), 0, s, *p, n, y, mean, std, sol, status,
+                       qtables, meta);
+    prof_end(BP_PROF_SURR_APPLY, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}

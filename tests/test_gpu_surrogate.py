@@ -1,0 +1,181 @@
+"""GPU checks of the profile-table surrogate: network gradients against the FP64
+oracle, training targets against the oracle's line-of-sight integrals, and the
+trained surrogate against the exact path (accuracy, fallback, what it gains)."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_02632_amd as bp
+    return bp
+
+
+def test_mlp_forward_backward_vs_oracle(bp):
+    import torch
+
+    from oracle import mlp
+    from paper_2201_02632_amd.surrogate import Surrogate
+    S = Surrogate(seed=5)
+    rng = np.random.default_rng(1)
+    # non-zero biases so every term is exercised
+    w = S.w.cpu().numpy().astype(np.float64)
+    L = S._layout()
+    for name in ("b1", "b2", "b3", "b4"):
+        off, n = L[name]
+        w[off:off + n] = rng.normal(0, 0.1, n)
+    S.w.copy_(torch.from_numpy(w.astype(np.float32)))
+    bp._check(bp._lib.bp_mlp_to_bf16(S.np, bp._ptr(S.w), bp._ptr(S.wb), bp._stream()), "to_bf16")
+    n = 200
+    x = np.zeros((n, 16), np.float32)
+    x[:, :3] = rng.uniform(-1, 1, (n, 3))
+    dy = rng.normal(size=(n, 144)).astype(np.float32)
+    xt = torch.as_tensor(x, device="cuda")
+    y, act = S.forward(xt)
+    g, _ = S.backward(xt, act, torch.as_tensor(dy, device="cuda"))
+    torch.cuda.synchronize()
+    w32 = S.w.cpu().numpy().astype(np.float64)
+    yo, cache = mlp.forward(w32, x)
+    go = mlp.backward(w32, cache, dy)
+    # scale of each output / gradient entry: the same sums with absolute values
+    ya, ca = mlp.forward(np.abs(w32), np.abs(x))
+    ga = mlp.backward(np.abs(w32), ca, np.abs(dy))
+    ey = np.max(np.abs(y.cpu().numpy() - yo) / (ya + 1e-30))
+    eg = np.max(np.abs(g.cpu().numpy() - go) / (ga + 1e-30))
+    print(f"MLP forward err {ey:.2e}, gradient err {eg:.2e} (relative to the sum of |terms|)")
+    assert ey < 2e-3 and eg < 2e-3
+    # median agreement is far tighter than the rare bf16 rounding-boundary flips allow at the max
+    assert np.median(np.abs(g.cpu().numpy() - go) / (ga + 1e-30)) < 1e-5
+
+
+def test_targets_match_oracle_los(bp, orc):
+    import torch
+
+    from paper_2201_02632_amd.surrogate import Surrogate
+    S = Surrogate()
+    M = np.array([3.16e15, 1e14, 3e12, 1e13, 10 ** 15.5])
+    c = np.array([4.0, 5.0, 8.0, 6.0, 15.0])
+    z = np.array([1.0, 0.5, 0.1, 2.0, 0.05])
+    _, t = S.training_set(M, c, z)
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64)
+    p = orc.default_params()
+    u = orc.MPC / p.h
+    for i in range(len(M)):
+        h = orc.solve_halo(p, M[i], c[i], z[i])
+        Pe0, ne0 = orc.profile(p, h, 1e-12)
+        assert abs(math.exp(t[i, 128]) / h.x_f - 1) < 1e-7
+        assert abs(math.exp(t[i, 129]) / Pe0 - 1) < 2e-6
+        for k in range(0, 64, 3):
+            q = 0.5 * (1 - math.cos(math.pi * k / 63)) if k < 63 else 1 - 1e-6
+            rp = q * h.R_t
+            E = math.sqrt(max(1 - (rp / h.r_f) ** 2, 0))
+            ty, tb = orc.los(p, h, rp)
+            Gp = ty / (orc.SIGMA_T / orc.ME_C2) / u / (Pe0 * h.R_t * E)
+            Gn = tb / orc.SIGMA_T / u / (ne0 * h.R_t * E)
+            assert abs(math.exp(t[i, k]) / Gp - 1) < 5e-6, (i, k)
+            assert abs(math.exp(t[i, 64 + k]) / Gn - 1) < 5e-6, (i, k)
+
+
+def integrated(G, E, q):
+    """2 pi int_0^1 G(q) E(q) q dq on the q nodes (trapezoid in s, where the nodes are uniform)."""
+    s = np.linspace(0, 1, 64)
+    dqds = 0.5 * math.pi * np.sin(math.pi * s)
+    f = G * E * q * dqds
+    return 2 * math.pi * np.trapezoid(f, s, axis=-1)
+
+
+@pytest.fixture(scope="module")
+def trained(bp):
+    import time
+
+    import torch
+
+    from paper_2201_02632_amd.surrogate import Surrogate
+    from paper_2201_02632_amd.synth import surrogate_training
+    S = Surrogate(seed=0)
+    tr = surrogate_training(200_000, seed=4)
+    x, t = S.training_set(tr["M"], tr["c"], tr["z"])
+    S.set_stats(t)
+    t0 = time.time()
+    hist = S.fit(x, t, steps=4000, batch=4096, lr=2e-3, lr_end=1e-5, log_every=1000)
+    torch.cuda.synchronize()
+    print(f"surrogate trained: {time.time() - t0:.1f} s, loss history {hist}", flush=True)
+    return S
+
+
+def test_surrogate_accuracy_and_gain(bp, trained):
+    import torch
+
+    from paper_2201_02632_amd.synth import surrogate_training
+    S = trained
+    te = surrogate_training(20_000, seed=44)
+    x, t = S.training_set(te["M"], te["c"], te["z"])
+    y, _ = S.forward(x)
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64)
+    ok = np.all(np.isfinite(t[:, :131]), axis=1)
+    yv = y.cpu().numpy().astype(np.float64) * S.std.cpu().numpy() + S.mean.cpu().numpy()
+    q = 0.5 * (1 - np.cos(np.pi * np.arange(64) / 63))
+    xf_t, xf_p = np.exp(t[ok, 128]), np.exp(yv[ok, 128])
+    # E(q) needs r_f / R_t: use the exact r_f with each table (the geometry is common to both)
+    M, c, z = te["M"][ok], te["c"][ok], te["z"][ok]
+    sol, st = bp.icm_solve(S.params, *(torch.as_tensor(a, dtype=torch.float64, device="cuda") for a in (M, c, z)))
+    sol = sol.cpu().numpy()
+    rf_over_Rt = sol[bp.SOL["RF"]] / sol[bp.SOL["RT"]]
+    E = np.sqrt(np.clip(1 - (q[None, :] / rf_over_Rt[:, None]) ** 2, 0, None))
+    Yt = np.exp(t[ok, 129])[:, None] * integrated(np.exp(t[ok, :64]), E, q)[:, None]
+    Yp = np.exp(yv[ok, 129])[:, None] * integrated(np.exp(yv[ok, :64]), E, q)[:, None]
+    err_Y = np.abs(Yp / Yt - 1).ravel()
+    err_G = np.abs(np.exp(yv[ok, :128] - t[ok, :128]) - 1)
+    # the method without the network: the training-set mean table for every halo
+    mean = S.mean.cpu().numpy()
+    Ym = np.exp(mean[129]) * integrated(np.exp(mean[None, :64]), E, q)
+    err_mean = np.abs(Ym / Yt.ravel() - 1)
+    print(f"held-out {ok.sum()} halos: integrated-Y err median {np.median(err_Y):.2e} p99 {np.quantile(err_Y, .99):.2e} "
+          f"max {err_Y.max():.2e}; table err median {np.median(err_G):.2e} p99 {np.quantile(err_G, .99):.2e}; "
+          f"x_f err max {np.max(np.abs(xf_p / xf_t - 1)):.2e}; mean-table baseline integrated-Y err median "
+          f"{np.median(err_mean):.2e}")
+    assert np.median(err_Y) < 2e-3
+    assert np.median(err_mean) > 30 * np.median(err_Y)
+
+
+def test_surrogate_paste_vs_exact_and_fallback(bp, trained):
+    import torch
+
+    from paper_2201_02632_amd.synth import hp_flat_small
+    S = trained
+    cat, npix, pix = hp_flat_small(1)
+    # push some halos out of the training domain: they must go through the exact path
+    cat = dict(cat)
+    cat["c"] = cat["c"].copy()
+    cat["c"][:50] = 1.5
+    dev = {k: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous() for k, v in cat.items()}
+    ye, be, _, _ = bp.hp_flat_map(S.params, cat, npix, pix)
+    ys = torch.zeros_like(ye)
+    bs = torch.zeros_like(be)
+    nout = S.paste_flat(dev, npix, pix, ys, bs)
+    torch.cuda.synchronize()
+    assert nout >= 50
+    ye, ys = ye.cpu().double().numpy(), ys.cpu().double().numpy()
+    Yerr = abs(ys.sum() / ye.sum() - 1)
+    rel = np.abs(ys - ye) / (np.abs(ye) + 1e-6 * np.abs(ye).max())
+    print(f"surrogate map vs exact: integrated-Y err {Yerr:.2e}, per-pixel median {np.median(rel):.2e} "
+          f"p99 {np.quantile(rel, 0.99):.2e} max {rel.max():.2e}; {nout} halos through the exact fallback")
+    assert Yerr < 1e-3
+    # fallback halos alone reproduce the exact map bit for bit
+    sub = {k: v[:50] for k, v in cat.items()}
+    ye2, _, _, _ = bp.hp_flat_map(S.params, sub, npix, pix)
+    ys2 = torch.zeros_like(ye2)
+    bs2 = torch.zeros_like(ye2)
+    S.paste_flat({k: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous() for k, v in sub.items()},
+                 npix, pix, ys2, bs2)
+    torch.cuda.synchronize()
+    assert torch.equal(ys2, ye2)
