@@ -247,7 +247,8 @@ int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n
  *   q-grid   : q_k = (1 - cos(pi k / 63)) / 2, k = 0..63, r_perp = q R_t.
  *   outputs  : y[0..63]   = ln( Y_P(q_k R_t) / (P_e0 R_t E_k) ),
  *              y[64..127] = ln( Y_n(q_k R_t) / (n_e0 R_t E_k) ),  E_k = sqrt(1 - (q_k R_t / r_f)^2)
- *              y[128] = ln x_f, y[129] = ln(P_e0 / erg cm^-3), y[130] = ln(n_e0 / cm^-3)
+ *              y[128] = ln x_f, y[129] = ln(P_e0 / P_s), y[130] = ln(n_e0 / n_s) with P_s the surface
+ *              pressure and n_s = f_b (3 M_vir / (4 pi r_vir^3)) / (mu_e m_p)
  *              (standardised: the network predicts (y - mean) / std).
  *   layers   : 3 -> 256 -> 256 -> 256 -> 144 (131 used), SiLU; the first layer
  *              in FP32, the others BF16 on MFMA with FP32 accumulation.
@@ -304,6 +305,17 @@ int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const floa
  * [n][2*BP_MLP_NQ] (G values, not logs) and meta (PE0, NE0; grid fields 0). */
 int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
                        double *sol, const int32_t *status, float *qtables, float *meta, void *stream);
+/* Device-side training loop: `steps` Adam steps on batches of `batch` rows drawn
+ * from (x, targets) by a counter-based hash of (seed, step0 + k, row) -- no host
+ * synchronisation.  Learning rate follows a cosine from lr0 to lr1 over the
+ * call; the Adam step counter continues from step0.  loss_rows (nullable,
+ * batch floats) receives the last batch's per-row weighted squared error.
+ * Workspace: bp_surrogate_train_ws_bytes(batch). */
+size_t bp_surrogate_train_ws_bytes(int64_t batch);
+int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *grad, const float *mean,
+                       const float *std, int64_t ndata, const float *x, const float *targets, int64_t steps,
+                       int64_t batch, float lr0, float lr1, uint64_t seed, int64_t step0, float *loss_rows, void *ws,
+                       size_t ws_bytes, void *stream);
 /* HP flat paste from surrogate q-tables: as bp_hp_paste_flat with
  * Y_P(r_perp) = P_e0 R_t E(r_perp) G_P(q), q = r_perp / R_t, cubic interpolation
  * in s = acos(1 - 2q)/pi on the 64 nodes.  Halos whose status is non-zero are

@@ -94,6 +94,9 @@ _SIGS = {
     "bp_surrogate_apply": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_surrogate_train_ws_bytes": (C.c_size_t, [C.c_int64]),
+    "bp_surrogate_train": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_int64, _VP, _VP, C.c_int64, C.c_int64,
+                                     C.c_float, C.c_float, C.c_uint64, C.c_int64, _VP, _VP, C.c_size_t, _VP]),
     "bp_profiling": (C.c_int, [C.c_int]),
     "bp_profile_read": (C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }

@@ -231,6 +231,11 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
         S(BP_SOL_TAU) = kSigmaT * ne_bar * (kC / H0) * tau_u;
         double fmax = pow(4.0, -P.n_nt) / P.alpha_nt;
         S(BP_SOL_FNT) = fmin(pow(zp, P.beta_nt), (fmax - 1.0) * tanh(P.beta_nt * z) + 1.0);
+        // surface pressure (the surrogate predicts the central pressure relative to it)
+        const double fb0 = P.Omega_b / P.Omega_m;
+        const double u_len0 = kMpc / h, u_mass0 = kMsun / h;
+        S(BP_SOL_PS) = fb0 * 4.0 * kPi * kGastro * rhos * rhos * rs * rs * jeans_I_dev(c, G) * u_mass0 /
+                       (u_len0 * u_len0 * u_len0) * 1e10;
         double lm = log10(M);
         bool in = lm >= 12.5 && lm <= 15.5 && c >= 2.0 && c <= 15.0 && z >= 0.05 && z <= 3.0;
         status[i] = in ? 0 : BP_S_OUT_OF_DOMAIN;

@@ -7,6 +7,12 @@
 
 #include "bp_device.hpp"
 
+extern "C" {
+size_t bp_mlp_act_bytes(int64_t n);
+size_t bp_mlp_backward_ws_bytes(int64_t n);
+int64_t bp_mlp_nparams(void);
+}
+
 namespace bp {
 
 const GaussRules &gauss_rules();

@@ -50,47 +50,84 @@ struct GemmArgs {
     int64_t kchunk;                         // split-K chunk (PARTIAL), else K
 };
 
+// 128x64 output tile per workgroup; wavefront w owns rows 32w..32w+31 (2x4 blocks of 16x16).
+// K advances 32 at a time; both operands are staged in LDS with k contiguous (B transposed),
+// so each MFMA fragment is a single 8-byte LDS read.  All vectorised operand dimensions in this
+// library are multiples of 8 (K, the 256/144 layer widths); the batch dimension M is guarded per row.
+constexpr int kBM = 128, kBN = 64, kBK = 32, kLdk = kBK + 8;   // +8 bf16 of padding per row
+
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-    __shared__ uint16_t As[64][17];   // [m][k] (+1 pad)
-    __shared__ uint16_t Bs[16][65];   // [k][n]
+    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kLdk];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kLdk];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+    const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * kBN;
     const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
     const int64_t ke = min(g.K, kb + g.kchunk);
-    fx4 acc[2][2];
+    fx4 acc[2][4];
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-    for (int64_t k0 = kb; k0 < ke; k0 += 16) {
-        // stage A (64x16) and B (16x64): 1024 elements each, 4 per thread
-        for (int q = 0; q < 4; ++q) {
-            int e = t + 256 * q;
-            int am = e >> 4, ak = e & 15;
-            int64_t gm = m0 + am, gk = k0 + ak;
-            As[am][ak] = (gm < g.M && gk < ke) ? g.A[gm * g.a_m + gk * g.a_k] : (uint16_t)0;
-            int bk = e >> 6, bn = e & 63;
-            int64_t gk2 = k0 + bk, gn = n0 + bn;
-            Bs[bk][bn] = (gk2 < ke && gn < g.N) ? g.B[gk2 * g.b_k + gn * g.b_n] : (uint16_t)0;
+        for (int b = 0; b < 4; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
+        // ---- stage A tile (128 x 32) into As[m][k]
+        if (g.a_k == 1) {
+            // rows contiguous in k: thread t loads 16 elements of row t/2
+            int am = t >> 1, ak = (t & 1) * 16;
+            int64_t gm = m0 + am;
+            for (int h = 0; h < 2; ++h) {
+                int64_t gk = k0 + ak + 8 * h;
+                u16x8 v = zero8;
+                if (gm < g.M && gk < ke) v = *(const u16x8 *)(g.A + gm * g.a_m + gk);
+                *(u16x8 *)&As[am][ak + 8 * h] = v;
+            }
+        } else {
+            // columns contiguous in m (a_m == 1): thread t loads 8 m-values at k = t/8 ... twice
+            for (int h = 0; h < 2; ++h) {
+                int e = t + 256 * h;
+                int ak = e >> 4, am = (e & 15) * 8;
+                int64_t gk = k0 + ak, gm = m0 + am;
+                u16x8 v = zero8;
+                if (gk < ke && gm + 7 < g.M) v = *(const u16x8 *)(g.A + gk * g.a_k + gm);
+                else if (gk < ke)
+                    for (int j = 0; j < 8; ++j) v[j] = (gm + j < g.M) ? g.A[gk * g.a_k + gm + j] : (uint16_t)0;
+                for (int j = 0; j < 8; ++j) As[am + j][ak] = v[j];
+            }
+        }
+        // ---- stage B tile (32 x 64) into Bs[n][k]
+        if (g.b_k == 1) {
+            int bn = t >> 2, bk = (t & 3) * 8;
+            int64_t gn = n0 + bn, gk = k0 + bk;
+            u16x8 v = zero8;
+            if (gn < g.N && gk < ke) v = *(const u16x8 *)(g.B + gn * g.b_n + gk);
+            *(u16x8 *)&Bs[bn][bk] = v;
+        } else {
+            int bk = t >> 3, bn = (t & 7) * 8;
+            int64_t gk = k0 + bk, gn = n0 + bn;
+            u16x8 v = zero8;
+            if (gk < ke && gn < g.N) v = *(const u16x8 *)(g.B + gk * g.b_k + gn);
+            for (int j = 0; j < 8; ++j) Bs[bn + j][bk] = v[j];
         }
         __syncthreads();
-        for (int bi = 0; bi < 2; ++bi) {
-            sx4 af;
-            for (int j = 0; j < 4; ++j) af[j] = (short)As[wm + 16 * bi + (lane & 15)][4 * (lane >> 4) + j];
-            for (int bj = 0; bj < 2; ++bj) {
-                sx4 bf;
-                for (int j = 0; j < 4; ++j) bf[j] = (short)Bs[4 * (lane >> 4) + j][wn + 16 * bj + (lane & 15)];
-                acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc[bi][bj], 0, 0, 0);
-            }
+        for (int ks = 0; ks < kBK; ks += 16) {
+            sx4 af[2], bfr[4];
+            for (int bi = 0; bi < 2; ++bi)
+                af[bi] = *(const sx4 *)&As[32 * w + 16 * bi + (lane & 15)][ks + 4 * (lane >> 4)];
+            for (int bj = 0; bj < 4; ++bj)
+                bfr[bj] = *(const sx4 *)&Bs[16 * bj + (lane & 15)][ks + 4 * (lane >> 4)];
+            for (int bi = 0; bi < 2; ++bi)
+                for (int bj = 0; bj < 4; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[bi], bfr[bj], acc[bi][bj], 0, 0, 0);
         }
         __syncthreads();
     }
     // epilogue: lane holds D[4*(lane>>4)+j][lane&15] of each 16x16 block
     for (int bi = 0; bi < 2; ++bi)
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < 4; ++bj)
             for (int j = 0; j < 4; ++j) {
-                int64_t m = m0 + wm + 16 * bi + 4 * (lane >> 4) + j;
-                int64_t n = n0 + wn + 16 * bj + (lane & 15);
+                int64_t m = m0 + 32 * w + 16 * bi + 4 * (lane >> 4) + j;
+                int64_t n = n0 + 16 * bj + (lane & 15);
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[bi][bj][j];
                 if (EPI == EPI_BIAS_SILU) {
@@ -110,8 +147,13 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
 }
 
 static int launch_gemm(int epi, const GemmArgs &g, int ksplit, hipStream_t s) {
-    if ((g.M + 63) / 64 > 0x7fffffffLL) return BP_E_OVERFLOW;
-    dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64), (unsigned)ksplit);
+    if ((g.M + kBM - 1) / kBM > 0x7fffffffLL) return BP_E_OVERFLOW;
+    // the vectorised staging needs 16-byte aligned rows along the contiguous dimension
+    if ((g.a_k == 1 && (g.a_m % 8)) || (g.a_k != 1 && (g.a_k % 8 || g.a_m != 1)) || (g.b_k == 1 && (g.b_n % 8)) ||
+        (g.b_k != 1 && (g.b_k % 8 || g.b_n != 1)) || (g.kchunk % kBK) ||
+        ((g.a_k == 1 || g.b_k == 1) && (g.K % 8)) || (g.N % 8))
+        return BP_E_ARG;
+    dim3 grid((unsigned)((g.M + kBM - 1) / kBM), (unsigned)((g.N + kBN - 1) / kBN), (unsigned)ksplit);
     switch (epi) {
         case EPI_BIAS_SILU: hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS_SILU>, grid, dim3(256), 0, s, g); break;
         case EPI_BIAS: hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS>, grid, dim3(256), 0, s, g); break;
@@ -143,24 +185,48 @@ __global__ void k_reduce_partials(int64_t count, int ks, const float *__restrict
     out[i] = s;
 }
 
-// column sums over the batch (bias gradients), fixed order
-__global__ void k_colsum(int64_t n, int cols, int64_t ld, const float *__restrict__ a, float *__restrict__ out) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
-    float s = 0.0f;
-    for (int64_t m = 0; m < n; ++m) s += a[m * ld + c];
-    out[c] = s;
+// Batch reductions in two fixed-order stages.  Stage 1: block (bx, y) covers 64 columns and the rows
+// [64 y, 64 y + 64); its four waves take every fourth row and are combined in wave order, giving
+// part[y][j][c] = sum_m a[m][c] * (j == 0 ? 1 : x[m][j - 1]).  Stage 2 sums the chunks in order.
+constexpr int kRowChunk = 64;
+template <int kSums>
+__global__ __launch_bounds__(256) void k_colsum_part(int64_t n, int cols, const float *__restrict__ a,
+                                                     const float *__restrict__ x, float *__restrict__ part) {
+    __shared__ float red[4][kSums][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int64_t m0 = (int64_t)blockIdx.y * kRowChunk, m1 = min(n, m0 + kRowChunk);
+    float acc[kSums];
+#pragma unroll
+    for (int j = 0; j < kSums; ++j) acc[j] = 0.0f;
+    if (c < cols)
+        for (int64_t m = m0 + w; m < m1; m += 4) {
+            float v = a[m * cols + c];
+            acc[0] += v;
+#pragma unroll
+            for (int j = 1; j < kSums; ++j) acc[j] += v * x[m * BP_MLP_IN + j - 1];
+        }
+#pragma unroll
+    for (int j = 0; j < kSums; ++j) red[w][j][lane] = acc[j];
+    __syncthreads();
+    if (w == 0 && c < cols)
+#pragma unroll
+        for (int j = 0; j < kSums; ++j)
+            part[((int64_t)blockIdx.y * kSums + j) * cols + c] =
+                ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
 }
-
-// dW1 = d1^T x (K = batch) in FP32, one thread per weight, fixed order
-__global__ void k_dw1(int64_t n, const float *__restrict__ d1, const float *__restrict__ x, float *__restrict__ gW1) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= BP_MLP_HID * BP_MLP_IN) return;
-    int o = e / BP_MLP_IN, k = e % BP_MLP_IN;
-    float s = 0.0f;
-    if (k < BP_MLP_NIN)
-        for (int64_t m = 0; m < n; ++m) s += d1[m * BP_MLP_HID + o] * x[m * BP_MLP_IN + k];
-    gW1[e] = s;
+// stage 2 for the first layer: part[y][0][o] -> db1[o], part[y][1 + k][o] -> dW1[o][k] (padded k are 0)
+__global__ void k_reduce_layer1(int nchunk, const float *__restrict__ part, float *__restrict__ gb1,
+                                float *__restrict__ gW1) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= BP_MLP_HID) return;
+    float acc[1 + BP_MLP_NIN] = {};
+    for (int y = 0; y < nchunk; ++y)
+#pragma unroll
+        for (int j = 0; j <= BP_MLP_NIN; ++j) acc[j] += part[((int64_t)y * (1 + BP_MLP_NIN) + j) * BP_MLP_HID + o];
+    gb1[o] = acc[0];
+#pragma unroll
+    for (int k = 0; k < BP_MLP_IN; ++k) gW1[o * BP_MLP_IN + k] = k < BP_MLP_NIN ? acc[1 + k] : 0.0f;
 }
 
 __global__ void k_to_bf16(int64_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
@@ -216,7 +282,7 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
     int64_t e = n * BP_MLP_HID;
     hipLaunchKernelGGL(k_layer1, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, n, w + o.W1, w + o.b1, x, Z1, H1);
     GemmArgs g = {};
-    g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID;
+    g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID;   // K = 256: one chunk
     // hidden layers: A = h (row-major [n][256]), B(k, n') = W[n'][k]
     g.N = BP_MLP_HID; g.A = H1; g.a_m = BP_MLP_HID; g.a_k = 1; g.B = wb + o.W2; g.b_k = 1; g.b_n = BP_MLP_HID;
     g.bias = w + o.b2; g.Z = Z2; g.ldz = BP_MLP_HID; g.H = H2; g.ldh = BP_MLP_HID;
@@ -231,11 +297,22 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
     return r;
 }
 
+// split-K factor of the weight-gradient GEMMs (K = batch): about 128 rows per slice, so that a
+// 4096-row batch already gives 256 workgroups
+static int wgrad_splits(int64_t n) {
+    int64_t ks = (n + 127) / 128;
+    return (int)(ks < 1 ? 1 : ks > 64 ? 64 : ks);
+}
+
+static size_t part_floats(int64_t n) {
+    int64_t ks = wgrad_splits(n);
+    int64_t nchunk = (n + kRowChunk - 1) / kRowChunk;
+    int64_t a = ks * BP_MLP_HID * BP_MLP_HID, b = nchunk * BP_MLP_HID * (1 + BP_MLP_NIN);
+    return (size_t)(a > b ? a : b);
+}
+
 extern "C" size_t bp_mlp_backward_ws_bytes(int64_t n) {
-    int ks = (int)((n + 511) / 512);
-    if (ks < 1) ks = 1;
-    return (size_t)n * BP_MLP_OUT * 2 + (size_t)n * BP_MLP_HID * (2 + 4) * 2 +
-           (size_t)ks * BP_MLP_HID * BP_MLP_HID * 4 + 4096;
+    return (size_t)n * BP_MLP_OUT * 2 + (size_t)n * BP_MLP_HID * (2 + 4) * 2 + part_floats(n) * 4 + 4096;
 }
 
 extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
@@ -246,13 +323,13 @@ extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, co
     Off o = offsets();
     const float *Z1 = (const float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
     const uint16_t *H1 = (const uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
-    const int ks = (int)((n + 511) / 512);
-    const int64_t kchunk = (((n + ks - 1) / ks + 15) / 16) * 16;
+    const int ks = wgrad_splits(n);
+    const int64_t kchunk = (((n + ks - 1) / ks + 31) / 32) * 32;
     Arena A(ws, ws_bytes);
     uint16_t *G4 = A.take<uint16_t>(n * BP_MLP_OUT);
     uint16_t *Gb = A.take<uint16_t>(n * BP_MLP_HID), *Gc = A.take<uint16_t>(n * BP_MLP_HID);
     float *Df = A.take<float>(n * BP_MLP_HID), *Dg = A.take<float>(n * BP_MLP_HID);
-    float *part = A.take<float>((int64_t)ks * BP_MLP_HID * BP_MLP_HID);
+    float *part = A.take<float>((int64_t)part_floats(n));
     prof_begin(BP_PROF_MLP_BWD, s);
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * BP_MLP_OUT + 255) / 256)), dim3(256), 0, s, n * BP_MLP_OUT, dy,
                        G4);
@@ -270,14 +347,23 @@ extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, co
                            grad + gw_off);
         return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
     };
+    const int nchunk = (int)((n + kRowChunk - 1) / kRowChunk);
+    auto colsum = [&](const float *a, int cols, float *out) -> int {
+        hipLaunchKernelGGL(k_colsum_part<1>, dim3((cols + 63) / 64, nchunk), dim3(256), 0, s, n, cols, a,
+                           (const float *)nullptr, part);
+        hipLaunchKernelGGL(k_reduce_partials, dim3((cols + 255) / 256), dim3(256), 0, s, (int64_t)cols, nchunk, part,
+                           out);
+        return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+    };
     int r = wgrad(G4, BP_MLP_OUT, BP_MLP_OUT, H3, o.W4);
     if (r) return r;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_OUT), 0, s, n, BP_MLP_OUT, (int64_t)BP_MLP_OUT, dy, grad + o.b4);
+    r = colsum(dy, BP_MLP_OUT, grad + o.b4);
+    if (r) return r;
     // dh3 = g4 W4 ; d3 = dh3 * silu'(z3)
     auto dgrad = [&](const uint16_t *Gin, int64_t kdim, const uint16_t *W, const float *Z, uint16_t *Gout,
                      float *Dout) -> int {
         GemmArgs g = {};
-        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = kdim;
+        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = ((kdim + 31) / 32) * 32;
         g.A = Gin; g.a_m = kdim; g.a_k = 1;               // A(s, o) = G[s][o]
         g.B = W; g.b_k = BP_MLP_HID; g.b_n = 1;           // B(o, i) = W[o][i]
         g.Z = (float *)Z; g.ldz = BP_MLP_HID; g.H = Gout; g.ldh = BP_MLP_HID; g.F = Dout; g.ldf = BP_MLP_HID;
@@ -285,18 +371,22 @@ extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, co
     };
     r = dgrad(G4, BP_MLP_OUT, wb + o.W4, Z3, Gb, Df);
     if (r) return r;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_HID), 0, s, n, BP_MLP_HID, (int64_t)BP_MLP_HID, Df, grad + o.b3);
+    r = colsum(Df, BP_MLP_HID, grad + o.b3);
+    if (r) return r;
     r = wgrad(Gb, BP_MLP_HID, BP_MLP_HID, H2, o.W3);
     if (r) return r;
     r = dgrad(Gb, BP_MLP_HID, wb + o.W3, Z2, Gc, Dg);
     if (r) return r;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_HID), 0, s, n, BP_MLP_HID, (int64_t)BP_MLP_HID, Dg, grad + o.b2);
+    r = colsum(Dg, BP_MLP_HID, grad + o.b2);
+    if (r) return r;
     r = wgrad(Gc, BP_MLP_HID, BP_MLP_HID, H1, o.W2);
     if (r) return r;
     r = dgrad(Gc, BP_MLP_HID, wb + o.W2, Z1, Gb, Df);   // d1 in Df (fp32); its bf16 copy is unused
     if (r) return r;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(BP_MLP_HID), 0, s, n, BP_MLP_HID, (int64_t)BP_MLP_HID, Df, grad + o.b1);
-    hipLaunchKernelGGL(k_dw1, dim3((BP_MLP_HID * BP_MLP_IN + 255) / 256), dim3(256), 0, s, n, Df, x, grad + o.W1);
+    // db1 and dW1 in one pass over d1
+    hipLaunchKernelGGL(k_colsum_part<1 + BP_MLP_NIN>, dim3(BP_MLP_HID / 64, nchunk), dim3(256), 0, s, n, BP_MLP_HID,
+                       Df, x, part);
+    hipLaunchKernelGGL(k_reduce_layer1, dim3(1), dim3(BP_MLP_HID), 0, s, nchunk, part, grad + o.b1, grad + o.W1);
     prof_end(BP_PROF_MLP_BWD, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -32,8 +32,18 @@ struct UnitRec {
     int32_t flags;
 };
 
+// electron-density scale [1/cm^3]: the cosmic baryon share of the mean density inside r_vir, as
+// fully ionised electrons.  The network predicts n_e0 relative to it (and P_e0 relative to the
+// surface pressure), which keeps the amplitude targets within a narrow range.
+__device__ inline double ne_scale(const bp_params &P, double M, double rv) {
+    const double u_len = kMpc / P.h, u_mass = kMsun / P.h;
+    const double r = rv * u_len;
+    const double rho = M * u_mass / (4.0 * kPi / 3.0 * r * r * r);
+    return (P.Omega_b / P.Omega_m) * rho / (2.0 / (1.0 + P.X_H) * kMp);
+}
+
 // one thread per (halo, q node); thread k = 0 also writes the scalars and padding
-__global__ void k_targets(int64_t n, const double *__restrict__ sol, const int32_t *__restrict__ status,
+__global__ void k_targets(bp_params P, int64_t n, const double *__restrict__ sol, const int32_t *__restrict__ status,
                           const float *__restrict__ tables, const float *__restrict__ meta, float *__restrict__ t) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * BP_MLP_NQ) return;
@@ -74,8 +84,8 @@ __global__ void k_targets(int64_t n, const double *__restrict__ sol, const int32
     row[BP_MLP_NQ + k] = (float)log((double)vn / E);
     if (k == 0) {
         row[2 * BP_MLP_NQ + 0] = (float)log(S(BP_SOL_XF));
-        row[2 * BP_MLP_NQ + 1] = (float)log((double)Mt(BP_META_PE0));
-        row[2 * BP_MLP_NQ + 2] = (float)log((double)Mt(BP_META_NE0));
+        row[2 * BP_MLP_NQ + 1] = (float)log((double)Mt(BP_META_PE0) / S(BP_SOL_PS));
+        row[2 * BP_MLP_NQ + 2] = (float)log((double)Mt(BP_META_NE0) / ne_scale(P, S(BP_SOL_M), S(BP_SOL_RVIR)));
         for (int q2 = BP_MLP_NOUT; q2 < BP_MLP_OUT; ++q2) row[q2] = 0.0f;
     }
 }
@@ -106,27 +116,65 @@ __global__ void k_gather(int64_t n, int cols, const float *__restrict__ in, cons
     out[e] = in[idx[i] * cols + c];
 }
 
-// loss gradient for the standardised targets; rows with a non-finite target contribute nothing
+// counter-based batch sampling (SplitMix64 of seed, step, row): row i of the batch is data row
+// (hash >> 11) mod n_data
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__global__ void k_gather_rand(int64_t nb, int64_t ndata, uint64_t seed, int64_t step, const float *__restrict__ x,
+                              const float *__restrict__ t, float *__restrict__ xb, float *__restrict__ tb) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nb * (BP_MLP_IN + BP_MLP_OUT)) return;
+    int64_t i = e / (BP_MLP_IN + BP_MLP_OUT);
+    int c = (int)(e % (BP_MLP_IN + BP_MLP_OUT));
+    uint64_t hsh = splitmix64(seed ^ splitmix64((uint64_t)step * 0x100000001B3ull + (uint64_t)i));
+    int64_t r = (int64_t)((hsh >> 11) % (uint64_t)ndata);
+    if (c < BP_MLP_IN) xb[i * BP_MLP_IN + c] = x[r * BP_MLP_IN + c];
+    else tb[i * BP_MLP_OUT + (c - BP_MLP_IN)] = t[r * BP_MLP_OUT + (c - BP_MLP_IN)];
+}
+
+// loss gradient for the standardised targets, one wave per row (lanes stride the columns);
+// rows with a non-finite target contribute nothing
 __global__ void k_mse(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
                       const float *__restrict__ mean, const float *__restrict__ sd, float *__restrict__ dy,
                       float *__restrict__ loss) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bool ok = true;
-    for (int c = 0; c < BP_MLP_NOUT; ++c) ok = ok && isfinite(t[i * BP_MLP_OUT + c]);
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i >= n) return;   // whole wave leaves together
+    constexpr int kPer = (BP_MLP_OUT + 63) / 64;
+    // weights: 1 per table entry, kAuxWeight for each of x_f, P_e0, n_e0 (they scale the whole footprint)
+    const float kAuxWeight = 16.0f;
+    const float wsum = 2.0f * BP_MLP_NQ + 3.0f * kAuxWeight;
+    const float scale = 2.0f / ((float)n * wsum);
+    float tv[kPer];
+    bool fin = true;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        int c = lane + 64 * j;
+        tv[j] = c < BP_MLP_NOUT ? t[i * BP_MLP_OUT + c] : 0.0f;
+        fin = fin && isfinite(tv[j]);
+    }
+    const bool ok = __all(fin);
     float acc = 0.0f;
-    const float scale = 2.0f / ((float)n * (float)BP_MLP_NOUT);
-    for (int c = 0; c < BP_MLP_OUT; ++c) {
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        int c = lane + 64 * j;
+        if (c >= BP_MLP_OUT) break;
         float d = 0.0f;
         if (ok && c < BP_MLP_NOUT) {
-            float ts = (t[i * BP_MLP_OUT + c] - mean[c]) / sd[c];
-            float r = y[i * BP_MLP_OUT + c] - ts;
-            acc += r * r;
-            d = scale * r;
+            float wc = (c >= 2 * BP_MLP_NQ) ? kAuxWeight : 1.0f;
+            float r = y[i * BP_MLP_OUT + c] - (tv[j] - mean[c]) / sd[c];
+            acc += wc * r * r;
+            d = scale * wc * r;
         }
         dy[i * BP_MLP_OUT + c] = d;
     }
-    loss[i] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) loss[i] = acc;
 }
 
 // network output -> sol (XF, RF, RT), q-tables (G values) and meta (PE0, NE0)
@@ -147,8 +195,10 @@ __global__ void k_apply(bp_params P, int64_t n, const float *__restrict__ y, con
         sol[(int64_t)BP_SOL_XF * n + i] = xf;
         sol[(int64_t)BP_SOL_RF * n + i] = xf * rv;
         sol[(int64_t)BP_SOL_RT * n + i] = fmin(xf * rv, P.trunc_r500 * sol[(int64_t)BP_SOL_R500 * n + i]);
-        meta[(int64_t)BP_META_PE0 * n + i] = expf(row[c0 + 1] * sd[c0 + 1] + mean[c0 + 1]);
-        meta[(int64_t)BP_META_NE0 * n + i] = expf(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2]);
+        meta[(int64_t)BP_META_PE0 * n + i] =
+            (float)(sol[(int64_t)BP_SOL_PS * n + i] * exp((double)(row[c0 + 1] * sd[c0 + 1] + mean[c0 + 1])));
+        meta[(int64_t)BP_META_NE0 * n + i] =
+            (float)(ne_scale(P, sol[(int64_t)BP_SOL_M * n + i], rv) * exp((double)(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2])));
         for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
     }
 }
@@ -171,8 +221,8 @@ extern "C" int bp_surrogate_targets(const bp_params *p, int64_t n, const double 
                                     const float *tables, const float *meta, float *targets, void *stream) {
     if (!p || n < 0 || (n > 0 && (!sol || !status || !tables || !meta || !targets))) return BP_E_ARG;
     if (n == 0) return BP_OK;
-    hipLaunchKernelGGL(k_targets, dim3(nblk(n * BP_MLP_NQ)), dim3(256), 0, (hipStream_t)stream, n, sol, status, tables,
-                       meta, targets);
+    hipLaunchKernelGGL(k_targets, dim3(nblk(n * BP_MLP_NQ)), dim3(256), 0, (hipStream_t)stream, *p, n, sol, status,
+                       tables, meta, targets);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
@@ -192,7 +242,7 @@ extern "C" int bp_gather_rows(int64_t n, int32_t cols, const float *in, const in
 extern "C" int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const float *mean, const float *std,
                                 float *dy, float *loss_rows, void *stream) {
     if (n <= 0 || !y || !targets || !mean || !std || !dy || !loss_rows) return BP_E_ARG;
-    hipLaunchKernelGGL(k_mse, dim3(nblk(n)), dim3(256), 0, (hipStream_t)stream, n, y, targets, mean, std, dy,
+    hipLaunchKernelGGL(k_mse, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, (hipStream_t)stream, n, y, targets, mean, std, dy,
                        loss_rows);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
@@ -206,5 +256,44 @@ extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y,
     hipLaunchKernelGGL(k_apply, dim3(nblk(n * 2 * BP_MLP_NQ)), dim3(256), 0, s, *p, n, y, mean, std, sol, status,
                        qtables, meta);
     prof_end(BP_PROF_SURR_APPLY, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" size_t bp_surrogate_train_ws_bytes(int64_t batch) {
+    if (batch <= 0) return 0;
+    return (size_t)batch * (BP_MLP_IN + 3 * BP_MLP_OUT + 1) * 4 + bp_mlp_act_bytes(batch) +
+           bp_mlp_backward_ws_bytes(batch) + 8 * 256;
+}
+
+extern "C" int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *grad, const float *mean,
+                                  const float *std, int64_t ndata, const float *x, const float *targets, int64_t steps,
+                                  int64_t batch, float lr0, float lr1, uint64_t seed, int64_t step0, float *loss_rows,
+                                  void *ws, size_t ws_bytes, void *stream) {
+    if (!w || !w_bf16 || !m || !v || !grad || !mean || !std || !x || !targets || !ws || ndata <= 0 || steps < 0 ||
+        batch <= 0 || step0 < 0)
+        return BP_E_ARG;
+    if (ws_bytes < bp_surrogate_train_ws_bytes(batch)) return BP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Arena A(ws, ws_bytes);
+    float *xb = A.take<float>(batch * BP_MLP_IN), *tb = A.take<float>(batch * BP_MLP_OUT);
+    float *y = A.take<float>(batch * BP_MLP_OUT), *dy = A.take<float>(batch * BP_MLP_OUT);
+    float *loss = loss_rows ? loss_rows : A.take<float>(batch);
+    void *act = A.take<char>(bp_mlp_act_bytes(batch));
+    size_t bwb = bp_mlp_backward_ws_bytes(batch);
+    void *bws = A.take<char>(bwb);
+    const int64_t np = bp_mlp_nparams();
+    for (int64_t k = 0; k < steps; ++k) {
+        hipLaunchKernelGGL(k_gather_rand, dim3(nblk(batch * (BP_MLP_IN + BP_MLP_OUT))), dim3(256), 0, s, batch, ndata,
+                           seed, step0 + k, x, targets, xb, tb);
+        int e = bp_mlp_forward(w, w_bf16, batch, xb, y, act, stream);
+        if (e) return e;
+        hipLaunchKernelGGL(k_mse, dim3((unsigned)((batch + 3) / 4)), dim3(256), 0, s, batch, y, tb, mean, std, dy, loss);
+        e = bp_mlp_backward(w, w_bf16, batch, xb, act, dy, grad, bws, bwb, stream);
+        if (e) return e;
+        double frac = steps > 1 ? (double)k / (double)(steps - 1) : 1.0;
+        float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(kPi * frac)));
+        e = bp_mlp_adam(np, w, m, v, grad, w_bf16, lr, 0.9f, 0.999f, 1e-8f, step0 + k + 1, stream);
+        if (e) return e;
+    }
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -131,28 +131,29 @@ class Surrogate:
         _check(_lib.bp_surrogate_stats(t.shape[0], _ptr(t), _ptr(self.mean), _ptr(self.std), _stream()), "stats")
 
     def fit(self, x, t, steps, batch=4096, lr=2e-3, lr_end=2e-5, seed=0, log_every=0):
-        """Adam on the MSE of standardised targets with a cosine learning-rate decay."""
+        """Adam on the weighted MSE of standardised targets with a cosine learning-rate decay,
+        run as a device-side loop (one library call per logging interval)."""
         n = x.shape[0]
-        gen = torch.Generator(device=self.dev).manual_seed(seed)
-        xb = torch.empty((batch, MLP_IN), dtype=torch.float32, device=self.dev)
-        tb = torch.empty((batch, MLP_OUT), dtype=torch.float32, device=self.dev)
-        dy = torch.empty((batch, MLP_OUT), dtype=torch.float32, device=self.dev)
+        need = int(_lib.bp_surrogate_train_ws_bytes(batch))
+        ws = torch.empty(need, dtype=torch.uint8, device=self.dev)
         loss = torch.empty(batch, dtype=torch.float32, device=self.dev)
-        act = torch.empty(int(_lib.bp_mlp_act_bytes(batch)), dtype=torch.uint8, device=self.dev)
-        ws = None
+        chunk = log_every if log_every else steps
         hist = []
-        for k in range(steps):
-            idx = torch.randint(0, n, (batch,), generator=gen, device=self.dev)
-            _check(_lib.bp_gather_rows(batch, MLP_IN, _ptr(x), _ptr(idx), _ptr(xb), _stream()), "gather")
-            _check(_lib.bp_gather_rows(batch, MLP_OUT, _ptr(t), _ptr(idx), _ptr(tb), _stream()), "gather")
-            y, _ = self.forward(xb, act)
-            _check(_lib.bp_surrogate_mse(batch, _ptr(y), _ptr(tb), _ptr(self.mean), _ptr(self.std), _ptr(dy),
-                                         _ptr(loss), _stream()), "mse")
-            _, ws = self.backward(xb, act, dy, ws)
-            frac = k / max(steps - 1, 1)
-            self.adam(lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac)))
-            if log_every and (k % log_every == 0 or k == steps - 1):
-                hist.append((k, float(loss.sum().item()) / (batch * 131)))
+        done = 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            # one cosine over the whole fit: each chunk covers its slice of the schedule
+            f0, f1 = done / max(steps - 1, 1), (done + k - 1) / max(steps - 1, 1)
+            l0 = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * f0))
+            l1 = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * f1))
+            _check(_lib.bp_surrogate_train(_ptr(self.w), _ptr(self.wb), _ptr(self.m), _ptr(self.v), _ptr(self.g),
+                                           _ptr(self.mean), _ptr(self.std), n, _ptr(x), _ptr(t), k, batch,
+                                           float(l0), float(l1), int(seed) & 0xFFFFFFFFFFFFFFFF, self.step,
+                                           _ptr(loss), _ptr(ws), ws.numel(), _stream()), "bp_surrogate_train")
+            self.step += k
+            done += k
+            if log_every:
+                hist.append((done, float(loss.sum().item()) / (batch * 176)))
         return hist
 
     # -- inference -------------------------------------------------------------

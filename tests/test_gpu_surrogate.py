@@ -72,7 +72,7 @@ def test_targets_match_oracle_los(bp, orc):
         h = orc.solve_halo(p, M[i], c[i], z[i])
         Pe0, ne0 = orc.profile(p, h, 1e-12)
         assert abs(math.exp(t[i, 128]) / h.x_f - 1) < 1e-7
-        assert abs(math.exp(t[i, 129]) / Pe0 - 1) < 2e-6
+        assert abs(math.exp(t[i, 129]) / (Pe0 / h.P_s) - 1) < 2e-6
         for k in range(0, 64, 3):
             q = 0.5 * (1 - math.cos(math.pi * k / 63)) if k < 63 else 1 - 1e-6
             rp = q * h.R_t
@@ -105,7 +105,7 @@ def trained(bp):
     x, t = S.training_set(tr["M"], tr["c"], tr["z"])
     S.set_stats(t)
     t0 = time.time()
-    hist = S.fit(x, t, steps=4000, batch=4096, lr=2e-3, lr_end=1e-5, log_every=1000)
+    hist = S.fit(x, t, steps=20000, batch=4096, lr=2e-3, lr_end=1e-5, log_every=5000)
     torch.cuda.synchronize()
     print(f"surrogate trained: {time.time() - t0:.1f} s, loss history {hist}", flush=True)
     return S
