@@ -67,6 +67,19 @@ def cpu_baseline(sample_n=60, seed=102):
                       f"full footprints on the 4096^2 map, single thread ({dt:.1f} s)"}
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """Plain device-to-device copies of a known size: each launch reads and writes exactly
+    nbytes, which fixes the scale of the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +87,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-halos", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="run the warmup and timed steps, print per-kernel times and stop (for hardware-counter "
+                         "passes under a profiler: no reporting kernels after the steps)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB device copies (reference reading for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
@@ -81,6 +99,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import paper_2201_02632_amd as bp
     from paper_2201_02632_amd.synth import hp_flat_large
@@ -120,6 +142,10 @@ def main():
         bp._lib.bp_profile_read(kid, C.byref(tot), C.byref(cnt))
         kt[name] = tot.value / max(cnt.value, 1)
     bp._lib.bp_profiling(0)
+    if args.profile_pass:
+        print(json.dumps({"profile_pass": True, "ms_per_step": round(ms, 3),
+                          "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}), flush=True)
+        return
     nsolved = int((st == 0).sum().item())
     nfp = footprint_pixel_count(t, sol, st, bp, npix, pix)
     # dominant kernel: the longest per-launch duration

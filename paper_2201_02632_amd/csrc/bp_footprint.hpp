@@ -32,37 +32,61 @@ __device__ inline void kahan_add(float &s, float &c, float v) {
     s = t;
 }
 
+// Hardware transcendental approximations (about 1 ulp): the table coordinates they feed are
+// smooth functions sampled at ~1e-2 spacing, so their rounding moves a pixel's value by
+// well under 1e-6 relative.
+__device__ inline float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float hw_ln(float x) { return 0.693147180559945f * __builtin_amdgcn_logf(x); }
+
 // Projected profile at squared impact parameter r2 (in the record's length
 // unit), in units of the central electron pressure / density times that
 // length.  u2 = r_a^2 - r2 and U2 = r_f^2 - r2 are passed in so the caller can
 // form them without cancellation next to the footprint edge.
+//   zone A (r < r_a):  Y = u g_A(eta),  eta = ln(1 + acosh(r_a / r)),  u = sqrt(r_a^2 - r^2)
+//                      plus, for a gas shell beyond r_vir, (S - u) g_S(omega)
+//   zone B (r >= r_a): Y = U g_B(zeta), zeta = acosh(r_f / r),        U = sqrt(r_f^2 - r^2)
+// A and B share one interpolation with a per-lane table offset, so a wave that straddles r_a
+// does not run both branches.
+struct FootRec {
+    float ra, rf, r2min, D, isqD, eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih;
+    int flags;
+};
+
+// The fields of a wave-uniform record, read once per (tile, halo) pair: readfirstlane is
+// convergent, so the compiler keeps these reads outside the per-pixel branches.
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+template <class Rec>
+__device__ inline FootRec foot_uniform(const Rec &R) {
+    FootRec F;
+    F.ra = uni(R.ra); F.rf = uni(R.rf); F.r2min = uni(R.r2min); F.D = uni(R.D); F.isqD = uni(R.isqD);
+    F.eta_lo = uni(R.eta_lo); F.eta_ih = uni(R.eta_ih); F.om_lo = uni(R.om_lo); F.om_ih = uni(R.om_ih);
+    F.ze_lo = uni(R.ze_lo); F.ze_ih = uni(R.ze_ih);
+    F.flags = __builtin_amdgcn_readfirstlane(R.flags);
+    return F;
+}
+
 template <class Rec>
 __device__ inline void footprint_value(const Rec &R, const float *__restrict__ tab, float r2, float u2, float U2,
                                        float *vp, float *vn) {
-    const float *tP = tab, *tN = tab + BP_TAB_ZONE;
-    float P = 0.0f, N = 0.0f;
-    if (u2 > 0.0f) {
-        float u = sqrtf(u2);
-        float rr2 = fmaxf(r2, R.r2min);
-        float xi = __logf(R.ra + u) - 0.5f * __logf(rr2);
-        float eta = log1pf(fmaxf(xi, 0.0f));
-        float gp, gn;
-        lagr4x2(tP, tN, BP_TAB_NA, (eta - R.eta_lo) * R.eta_ih, &gp, &gn);
-        P = gp * u; N = gn * u;
-        if (R.flags & 1) {
-            float S = sqrtf(u * u + R.D);
-            float om = __logf((u + S) / R.sqD);
-            float sp, sn;
-            lagr4x2(tP + BP_TAB_NA, tN + BP_TAB_NA, BP_TAB_NS, (om - R.om_lo) * R.om_ih, &sp, &sn);
-            float e = R.D / (S + u);
-            P += sp * e; N += sn * e;
-        }
-    } else {
-        float U = sqrtf(fmaxf(U2, 0.0f));
-        float ze = __logf(R.rf + U) - 0.5f * __logf(r2);
-        float gp, gn;
-        lagr4x2(tP + BP_TAB_NA + BP_TAB_NS, tN + BP_TAB_NA + BP_TAB_NS, BP_TAB_NB, (ze - R.ze_lo) * R.ze_ih, &gp, &gn);
-        P = gp * U; N = gn * U;
+    const bool zA = u2 > 0.0f;
+    const float w = hw_sqrt(fmaxf(zA ? u2 : U2, 0.0f));                 // u or U
+    const float acs = hw_ln(((zA ? R.ra : R.rf) + w) * hw_rsq(fmaxf(r2, R.r2min)));   // acosh(r_{a,f} / r)
+    const float eta = hw_ln(1.0f + fmaxf(acs, 0.0f));
+    const float sidx = zA ? (eta - R.eta_lo) * R.eta_ih : (acs - R.ze_lo) * R.ze_ih;
+    const int off = zA ? 0 : BP_TAB_NA + BP_TAB_NS;
+    const int nn = zA ? BP_TAB_NA : BP_TAB_NB;
+    float gp, gn;
+    lagr4x2(tab + off, tab + BP_TAB_ZONE + off, nn, sidx, &gp, &gn);
+    float P = gp * w, N = gn * w;
+    if ((R.flags & 1) && zA) {
+        const float S = hw_sqrt(w * w + R.D);
+        const float om = hw_ln((w + S) * R.isqD);
+        float sp, sn;
+        lagr4x2(tab + BP_TAB_NA, tab + BP_TAB_ZONE + BP_TAB_NA, BP_TAB_NS, (om - R.om_lo) * R.om_ih, &sp, &sn);
+        const float e = R.D * hw_rcp(S + w);
+        P += sp * e; N += sn * e;
     }
     *vp = P; *vn = N;
 }

@@ -18,13 +18,13 @@ namespace bp {
 
 constexpr int kTile = 16;
 
-// Per-halo paste record in pixel units (128 bytes).
+// Per-halo paste record in pixel units (160 bytes; read by each wave as scalar loads).
 struct __attribute__((aligned(16))) FlatRec {
     int32_t cxi, cyi;       // integer part of the centre in pixel units
     float cxf, cyf;         // fractional part
     float Rt2;              // footprint radius^2 [px^2]
     float ra, ra2, rv2;     // r_a = min(r_vir, r_f), r_a^2, r_vir^2
-    float rf, rf2, D, sqD;  // r_f, r_f^2, r_f^2 - r_vir^2, sqrt(D)
+    float rf, rf2, D, isqD; // r_f, r_f^2, r_f^2 - r_vir^2, 1/sqrt(D) (0 without a shell)
     float r2min;            // clamp of r_perp^2 at the centre
     float eta_lo, eta_ih;   // zone A grid start and 1/step
     float om_lo, om_ih;     // zone S
@@ -34,8 +34,10 @@ struct __attribute__((aligned(16))) FlatRec {
     float Rt_emit;          // footprint radius used by both the pair count and the emit pass
     double cxd, cyd;        // fractional centre in FP64 (edge-annulus recompute)
     double ra2d, rf2d;      // r_a^2, r_f^2 in FP64
+    double thx, thy;        // centre [rad] and, below, D_A and R_t [Mpc/h]: the exact membership test
+    double DA, Rt;
 };
-static_assert(sizeof(FlatRec) == 128, "FlatRec size");
+static_assert(sizeof(FlatRec) == 160, "FlatRec size");
 
 __device__ inline void tile_row_range(double cx, double cy, double Rt, int ty, int ntx, int npix, int *tx0, int *tx1) {
     // pixel rows of this tile: centres y in [16 ty + 0.5, 16 ty + 15.5]
@@ -92,9 +94,11 @@ __global__ void __launch_bounds__(256) k_flat_setup(bp_params P, FlatGeom Gm, in
             r.rf = (float)rf; r.rf2 = (float)(rf * rf);
             r.cxd = cx - cxf; r.cyd = cy - cyf;
             r.ra2d = ra * ra; r.rf2d = rf * rf;
+            r.thx = thx[i]; r.thy = thy[i];
+            r.DA = DA; r.Rt = S(BP_SOL_RT);
             bool shell = rf > rv;
             double D = shell ? rf * rf - rv * rv : 0.0;
-            r.D = (float)D; r.sqD = (float)sqrt(D);
+            r.D = (float)D; r.isqD = D > 0.0 ? (float)(1.0 / sqrt(D)) : 0.0f;
             r.r2min = (float)(1e-10 * ra * ra);
             if (!kQ) {
                 float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
@@ -180,10 +184,9 @@ template <bool kQ>
 __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, const FlatRec *__restrict__ rec,
                                                       const float *__restrict__ tables, const uint32_t *__restrict__ vals,
                                                       const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
-                                                      const double *__restrict__ thx, const double *__restrict__ thy,
-                                                      const double *__restrict__ sol, float *__restrict__ ymap,
-                                                      float *__restrict__ bmap, int ntiles) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                                                      float *__restrict__ ymap, float *__restrict__ bmap, int ntiles) {
+    // the tile, its pair range and every halo record are wave-uniform (scalar registers)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int tile = blockIdx.x * 4 + wave;
     if (tile >= ntiles) return;
     const uint32_t p0 = tstart[tile], p1 = tend[tile];
@@ -193,6 +196,7 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
     const int pj0 = ty * kTile + (lane >> 4);
     float ys[4], yc[4], bs[4], bc[4];
     bool inmap[4];
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
         int pj = pj0 + 4 * k;
         inmap[k] = (pi < Gm.npix) && (pj < Gm.npix);
@@ -202,20 +206,21 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
         yc[k] = 0.0f; bc[k] = 0.0f;
     }
     for (uint32_t p = p0; p < p1; ++p) {
-        const uint32_t h = vals[p];
+        const uint32_t h = __builtin_amdgcn_readfirstlane(vals[p]);
         if (h >= (uint32_t)n) continue;
-        const FlatRec R = rec[h];
+        const FlatRec &R = rec[h];
+        const FootRec F = foot_uniform(R);
         const float *tab = tables + (int64_t)h * (kQ ? 2 * BP_MLP_NQ : BP_TAB_STRIDE);
         const float dxb = (float)(pi - R.cxi) + (0.5f - R.cxf);
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int pj = pj0 + 4 * k;
             const float dy = (float)(pj - R.cyi) + (0.5f - R.cyf);
             const float r2 = dxb * dxb + dy * dy;
             bool in = r2 < R.Rt2;
-            if (fabsf(r2 - R.Rt2) <= 4e-6f * R.Rt2) {
-                const double DA = sol[(int64_t)BP_SOL_DA * n + h], Rt = sol[(int64_t)BP_SOL_RT * n + h];
-                in = inside_fp64(pi, pj, Gm.pix, thx[h], thy[h], DA, Rt);
-            }
+            // the FP32 distance is good to ~1e-6 relative: decide pixels that close to the edge
+            // with the FP64 formula of the definition
+            if (fabsf(r2 - R.Rt2) <= 4e-6f * R.Rt2) in = inside_fp64(pi, pj, Gm.pix, R.thx, R.thy, R.DA, R.Rt);
             if (in && inmap[k]) {
                 float u2 = R.ra2 - r2, U2 = R.rf2 - r2;
                 if (u2 < 0.1f * R.ra2 || U2 < 0.1f * R.rf2) {
@@ -227,12 +232,13 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
                 }
                 float vp, vn;
                 if (kQ) footprint_value_q(R, tab, r2, U2, &vp, &vn);
-                else footprint_value(R, tab, r2, u2, U2, &vp, &vn);
+                else footprint_value(F, tab, r2, u2, U2, &vp, &vn);
                 kahan_add(ys[k], yc[k], R.amp_y * vp);
                 kahan_add(bs[k], bc[k], R.amp_b * vn);
             }
         }
     }
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (!inmap[k]) continue;
         int64_t idx = (int64_t)(pj0 + 4 * k) * Gm.npix + pi;
@@ -324,7 +330,7 @@ static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int
     prof_end(BP_PROF_FLAT_PLAN, s);
     prof_begin(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
     hipLaunchKernelGGL(k_flat_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, Gm, n, rec, tables, vs,
-                       tst, ten, theta_x, theta_y, sol, y_map, b_map, (int)ntiles);
+                       tst, ten, y_map, b_map, (int)ntiles);
     prof_end(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

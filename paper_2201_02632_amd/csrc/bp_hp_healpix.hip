@@ -24,7 +24,7 @@ struct __attribute__((aligned(16))) HpxRec {
     double th, ph, sth;     // halo colatitude, longitude in [0, 2 pi), sin(colatitude)
     float Rt2;              // footprint radius^2 in units of L = D_A theta_pix
     float ra, ra2, rv2;
-    float rf, rf2, D, sqD;
+    float rf, rf2, D, isqD;
     float r2min;
     float eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih;
     float amp_y, amp_b;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
             r.ra2d = ra * ra; r.rf2d = rf * rf;
             bool shell = rf > rv;
             double D = shell ? rf * rf - rv * rv : 0.0;
-            r.D = (float)D; r.sqD = (float)sqrt(D);
+            r.D = (float)D; r.isqD = D > 0.0 ? (float)(1.0 / sqrt(D)) : 0.0f;
             r.r2min = (float)(1e-10 * ra * ra);
             float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
             float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
                                                      const double *__restrict__ thin, const double *__restrict__ phin,
                                                      const double *__restrict__ sol, float *__restrict__ ymap,
                                                      float *__restrict__ bmap, uint32_t ntiles) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the tile, its pair range and every halo record are wave-uniform (scalar registers)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + wave;
     if (tile >= ntiles) return;
     const uint32_t p0 = tstart[tile], p1 = tend[tile];
@@ -248,9 +249,10 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
     const float inv_pix2 = (float)(1.0 / (G.pixang * G.pixang));
     float ys = valid ? ymap[pix] : 0.0f, bs = valid ? bmap[pix] : 0.0f, yc = 0.0f, bc = 0.0f;
     for (uint32_t p = p0; p < p1; ++p) {
-        const uint32_t h = vals[p];
+        const uint32_t h = __builtin_amdgcn_readfirstlane(vals[p]);
         if (h >= (uint32_t)n) continue;
-        const HpxRec R = rec[h];
+        const HpxRec &R = rec[h];
+        const FootRec F = foot_uniform(R);
         const double sd = sin(0.5 * (thr - R.th));
         const float A = (float)(sd * sd), B = (float)(sthr * R.sth);
         double dph = phj - R.ph;                    // wrap to [-pi, pi] before rounding to FP32
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
                 U2 = (float)(R.rf2d - r2d);
             }
             float vp, vn;
-            footprint_value(R, tables + (int64_t)h * BP_TAB_STRIDE, r2, u2, U2, &vp, &vn);
+            footprint_value(F, tables + (int64_t)h * BP_TAB_STRIDE, r2, u2, U2, &vp, &vn);
             kahan_add(ys, yc, R.amp_y * vp);
             kahan_add(bs, bc, R.amp_b * vn);
         }

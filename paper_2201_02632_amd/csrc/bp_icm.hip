@@ -359,19 +359,32 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
 // ---------------------------------------------------------------- tables --
 // Electron pressure and density relative to their central values at radius r
 // (analytic profile, no cut at r_f: the table edge nodes need the limit).
+// Line-of-sight integrand in FP32: the radius, the NFW potential shape and the polytrope are
+// formed from FP64-derived constants; FP32 rounding of theta = 1 - a phi enters P ~ theta^6 as
+// ~2e-6 / theta relative, well inside the deposit tolerance, and the GL sums are kept in FP64.
 struct Prof {
-    double rv, rs, rf, cm, phi_out0, a, inv_r500, ant_f, n_nt;
+    float rv, inv_rs, rf, cm, phi_out0, a, inv_r500, ant_f, n_nt;
 };
-__device__ inline void prof_eval(const Prof &Q, double r, double *pe, double *ne) {
-    double ph = (r < Q.rv) ? Q.cm * nfw_phi_shape(r / Q.rs) : Q.phi_out0 - Q.rv / r;
-    double th = 1.0 - Q.a * ph;
-    if (th < 0.0) th = 0.0;
-    double th2 = th * th, th5 = th2 * th2 * th;
-    // non-thermal fraction R_nt = alpha f(z) (r/r500)^n_nt (single precision is ample: 1 - R_nt >= ~0.3 inside R_t)
-    float rnt = (float)Q.ant_f * __expf((float)Q.n_nt * __logf((float)(r * Q.inv_r500)));
-    double fth = (rnt < 1.0f) ? 1.0 - (double)rnt : 0.0;
+__device__ inline void prof_eval(const Prof &Q, float r, float *pe, float *ne) {
+    float ph;
+    if (r < Q.rv) {
+        float x = r * Q.inv_rs;
+        float sh = (x < 1e-3f) ? x * (0.5f + x * (-1.0f / 3.0f + x * (0.25f + x * -0.2f))) : 1.0f - log1pf(x) / x;
+        ph = Q.cm * sh;
+    } else {
+        ph = Q.phi_out0 - Q.rv / r;
+    }
+    float th = fmaxf(1.0f - Q.a * ph, 0.0f);
+    float th2 = th * th, th5 = th2 * th2 * th;
+    // non-thermal fraction R_nt = alpha f(z) (r/r500)^n_nt
+    float rnt = Q.ant_f * __expf(Q.n_nt * __logf(r * Q.inv_r500));
+    float fth = (rnt < 1.0f) ? 1.0f - rnt : 0.0f;
     *pe = th5 * th * fth;
     *ne = th5;
+}
+__device__ inline float cosh_f(float s) {
+    float e = __expf(s);
+    return 0.5f * (e + 1.0f / e);
 }
 
 __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules G, int64_t n,
@@ -388,31 +401,32 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
         if (node < BP_META_NFIELDS) meta[(int64_t)node * n + i] = 0.0f;
         return;
     }
+    const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF);
+    const double c = S(BP_SOL_C), mc = nfw_m(c);
     Prof Q;
-    Q.rv = S(BP_SOL_RVIR); Q.rs = S(BP_SOL_RS); Q.rf = S(BP_SOL_RF);
-    double c = S(BP_SOL_C), mc = nfw_m(c);
-    Q.cm = c / mc; Q.phi_out0 = c * c / ((1.0 + c) * mc);
-    Q.a = S(BP_SOL_A);
-    Q.inv_r500 = 1.0 / S(BP_SOL_R500);
-    Q.ant_f = P.alpha_nt * S(BP_SOL_FNT);
-    Q.n_nt = P.n_nt;
+    Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
+    Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
+    Q.a = (float)S(BP_SOL_A);
+    Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
+    Q.ant_f = (float)(P.alpha_nt * S(BP_SOL_FNT));
+    Q.n_nt = (float)P.n_nt;
     const double Rt = S(BP_SOL_RT);
-    const double ra = fmin(Q.rv, Q.rf);
+    const double ra = fmin(rv, rf);
     const double rmin = 1e-5 * ra;
     // zone ranges
     const double eta_lo = log1p(acosh(ra / fmin(Rt, ra)));
     const double eta_hi = log1p(acosh(ra / rmin));
-    const bool shell = Q.rf > Q.rv;
-    const double D = shell ? Q.rf * Q.rf - Q.rv * Q.rv : 0.0;
+    const bool shell = rf > rv;
+    const double D = shell ? rf * rf - rv * rv : 0.0;
     const double sD = sqrt(D);
     double om_lo = 0.0, om_hi = 0.0, ze_lo = 0.0, ze_hi = 0.0;
     if (shell) {
-        double rtop = fmin(Rt, Q.rv);
-        om_lo = asinh(sqrt(fmax(Q.rv * Q.rv - rtop * rtop, 0.0)) / sD);
-        om_hi = asinh(Q.rv / sD);
+        double rtop = fmin(Rt, rv);
+        om_lo = asinh(sqrt(fmax(rv * rv - rtop * rtop, 0.0)) / sD);
+        om_hi = asinh(rv / sD);
     }
-    const bool zoneB = Rt > Q.rv;
-    if (zoneB) { ze_lo = acosh(Q.rf / Rt); ze_hi = acosh(Q.rf / Q.rv); }
+    const bool zoneB = Rt > rv;
+    if (zoneB) { ze_lo = acosh(rf / Rt); ze_hi = acosh(rf / rv); }
 
     double accP = 0.0, accN = 0.0;
     if (node < BP_TAB_NA) {
@@ -420,22 +434,22 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
         double eta = eta_lo + (eta_hi - eta_lo) * node / (BP_TAB_NA - 1);
         double xi = expm1(eta);
         if (xi < 1e-7) {  // limit r_perp -> r_a
-            double pe, ne;
-            prof_eval(Q, ra, &pe, &ne);
+            float pe, ne;
+            prof_eval(Q, (float)ra, &pe, &ne);
             accP = 2.0 * pe; accN = 2.0 * ne;
         } else {
-            double rp = ra / cosh(xi);
-            double u = ra * tanh(xi);
+            const double rp = ra / cosh(xi);
+            const double u = ra * tanh(xi);
             // 16 nodes reach 1e-11 up to xi ~ 6 (sight lines off the core); 24 beyond
             const bool wide = xi > 5.5;
             const int ng = wide ? 24 : 16;
             const double *gx = wide ? G.x24 : G.x16, *gw = wide ? G.w24 : G.w16;
+            const float rpf = (float)rp, raf = (float)ra, hx = (float)(0.5 * xi);
             for (int j = 0; j < ng; ++j) {
-                double s = 0.5 * xi * (gx[j] + 1.0);
-                double r = rp * cosh(s);
-                double pe, ne;
-                prof_eval(Q, fmin(r, ra), &pe, &ne);
-                double w = gw[j] * r;
+                float r = fminf(rpf * cosh_f(hx * (float)(gx[j] + 1.0)), raf);
+                float pe, ne;
+                prof_eval(Q, r, &pe, &ne);
+                double w = gw[j] * (double)r;
                 accP += w * pe; accN += w * ne;
             }
             double f = xi / u;  // 2 * (xi/2) / u
@@ -448,16 +462,17 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
             double om = om_lo + (om_hi - om_lo) * k / (BP_TAB_NS - 1);
             double uv = sD * sinh(om);
             double Sv = sqrt(uv * uv + D);
-            double rp = sqrt(fmax(Q.rv * Q.rv - uv * uv, 0.0));
-            rp = fmax(rp, 1e-7 * Q.rv);
-            double s0 = acosh(Q.rv / rp), s1 = acosh(Q.rf / rp);
+            double rp = sqrt(fmax(rv * rv - uv * uv, 0.0));
+            rp = fmax(rp, 1e-7 * rv);
+            double s0 = acosh(rv / rp), s1 = acosh(rf / rp);
             double hs = 0.5 * (s1 - s0);
+            const float rpf = (float)rp;
             for (int j = 0; j < 12; ++j) {
-                double s = s0 + hs * (G.x12[j] + 1.0);
-                double r = fmin(fmax(rp * cosh(s), Q.rv), Q.rf);
-                double pe, ne;
+                float sj = (float)(s0 + hs * (G.x12[j] + 1.0));
+                float r = fminf(fmaxf(rpf * cosh_f(sj), Q.rv), Q.rf);
+                float pe, ne;
                 prof_eval(Q, r, &pe, &ne);
-                double w = G.w12[j] * r;
+                double w = G.w12[j] * (double)r;
                 accP += w * pe; accN += w * ne;
             }
             double f = 2.0 * hs / (D / (Sv + uv));
@@ -469,18 +484,18 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
             int k = node - BP_TAB_NA - BP_TAB_NS;
             double ze = ze_lo + (ze_hi - ze_lo) * k / (BP_TAB_NB - 1);
             if (ze < 1e-7) {
-                double pe, ne;
+                float pe, ne;
                 prof_eval(Q, Q.rf, &pe, &ne);
                 accP = 2.0 * pe; accN = 2.0 * ne;
             } else {
-                double rp = Q.rf / cosh(ze);
-                double U = Q.rf * tanh(ze);
+                const double rp = rf / cosh(ze);
+                const double U = rf * tanh(ze);
+                const float rpf = (float)rp, hz = (float)(0.5 * ze);
                 for (int j = 0; j < 12; ++j) {
-                    double s = 0.5 * ze * (G.x12[j] + 1.0);
-                    double r = fmax(fmin(rp * cosh(s), Q.rf), Q.rv);
-                    double pe, ne;
+                    float r = fmaxf(fminf(rpf * cosh_f(hz * (float)(G.x12[j] + 1.0)), Q.rf), Q.rv);
+                    float pe, ne;
                     prof_eval(Q, r, &pe, &ne);
-                    double w = G.w12[j] * r;
+                    double w = G.w12[j] * (double)r;
                     accP += w * pe; accN += w * ne;
                 }
                 double f = ze / U;

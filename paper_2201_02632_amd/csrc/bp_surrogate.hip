@@ -27,7 +27,7 @@ __host__ __device__ inline double qnode(int k) { return 0.5 * (1.0 - cos(kPi * k
 
 // record in units of R_t for evaluating the exact zone tables at q = r_perp / R_t
 struct UnitRec {
-    float Rt2, ra, ra2, rv2, rf, rf2, D, sqD, r2min;
+    float Rt2, ra, ra2, rv2, rf, rf2, D, isqD, r2min;
     float eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih;
     int32_t flags;
 };
@@ -66,7 +66,7 @@ __global__ void k_targets(bp_params P, int64_t n, const double *__restrict__ sol
     R.rf = (float)rf; R.rf2 = (float)(rf * rf);
     const bool shell = rf > rv;
     const double D = shell ? rf * rf - rv * rv : 0.0;
-    R.D = (float)D; R.sqD = (float)sqrt(D);
+    R.D = (float)D; R.isqD = D > 0.0 ? (float)(1.0 / sqrt(D)) : 0.0f;
     R.r2min = (float)(1e-10 * ra * ra);
     float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI), olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI),
           zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
