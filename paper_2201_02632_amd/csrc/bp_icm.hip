@@ -365,26 +365,40 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
 struct Prof {
     float rv, inv_rs, rf, cm, phi_out0, a, inv_r500, ant_f, n_nt;
 };
-__device__ inline void prof_eval(const Prof &Q, float r, float *pe, float *ne) {
-    float ph;
-    if (r < Q.rv) {
-        float x = r * Q.inv_rs;
-        float sh = (x < 1e-3f) ? x * (0.5f + x * (-1.0f / 3.0f + x * (0.25f + x * -0.2f))) : 1.0f - log1pf(x) / x;
-        ph = Q.cm * sh;
-    } else {
-        ph = Q.phi_out0 - Q.rv / r;
+__device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ inline float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// NFW potential shape 1 - ln(1+x)/x in FP32 without cancellation.  Below x = 2, with
+// s = x/(2+x) and t = s^2, ln(1+x) = 2 atanh(s) gives 1 - ln(1+x)/x = (x - 2 t B(t))/(2+x),
+// B(t) = sum_k t^k/(2k+3), every term positive (t <= 1/4, truncated after t^9: < 5e-8).
+// Above, ln(1+x)/x <= 0.55 and the hardware logarithm keeps ~2e-7.
+__device__ inline float nfw_shape_f(float x) {
+    if (x < 2.0f) {
+        const float r = hw_rcp(2.0f + x);
+        const float sx = x * r, t = sx * sx;
+        float B = 1.0f / 21.0f;
+        B = fmaf(t, B, 1.0f / 19.0f); B = fmaf(t, B, 1.0f / 17.0f); B = fmaf(t, B, 1.0f / 15.0f);
+        B = fmaf(t, B, 1.0f / 13.0f); B = fmaf(t, B, 1.0f / 11.0f); B = fmaf(t, B, 1.0f / 9.0f);
+        B = fmaf(t, B, 1.0f / 7.0f);  B = fmaf(t, B, 1.0f / 5.0f);  B = fmaf(t, B, 1.0f / 3.0f);
+        return (x - 2.0f * t * B) * r;
     }
-    float th = fmaxf(1.0f - Q.a * ph, 0.0f);
-    float th2 = th * th, th5 = th2 * th2 * th;
+    return 1.0f - 0.693147180559945f * hw_log2(1.0f + x) * hw_rcp(x);
+}
+
+__device__ inline void prof_eval(const Prof &Q, float r, float *pe, float *ne) {
+    const float ph = (r < Q.rv) ? Q.cm * nfw_shape_f(r * Q.inv_rs) : Q.phi_out0 - Q.rv * hw_rcp(r);
+    const float th = fmaxf(1.0f - Q.a * ph, 0.0f);
+    const float th2 = th * th, th5 = th2 * th2 * th;
     // non-thermal fraction R_nt = alpha f(z) (r/r500)^n_nt
-    float rnt = Q.ant_f * __expf(Q.n_nt * __logf(r * Q.inv_r500));
-    float fth = (rnt < 1.0f) ? 1.0f - rnt : 0.0f;
+    const float rnt = Q.ant_f * hw_exp2(Q.n_nt * hw_log2(r * Q.inv_r500));
+    const float fth = (rnt < 1.0f) ? 1.0f - rnt : 0.0f;
     *pe = th5 * th * fth;
     *ne = th5;
 }
 __device__ inline float cosh_f(float s) {
-    float e = __expf(s);
-    return 0.5f * (e + 1.0f / e);
+    const float e = hw_exp2(1.44269504088896f * s);
+    return 0.5f * (e + hw_rcp(e));
 }
 
 __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules G, int64_t n,
@@ -401,32 +415,46 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
         if (node < BP_META_NFIELDS) meta[(int64_t)node * n + i] = 0.0f;
         return;
     }
-    const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF);
-    const double c = S(BP_SOL_C), mc = nfw_m(c);
-    Prof Q;
-    Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
-    Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
-    Q.a = (float)S(BP_SOL_A);
-    Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
-    Q.ant_f = (float)(P.alpha_nt * S(BP_SOL_FNT));
-    Q.n_nt = (float)P.n_nt;
-    const double Rt = S(BP_SOL_RT);
+    // per-halo constants: one lane computes them, the block shares them through LDS
+    __shared__ double shd[8];
+    __shared__ Prof shq;
+    if (node == 0) {
+        const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF);
+        const double c = S(BP_SOL_C), mc = nfw_m(c);
+        Prof Q;
+        Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
+        Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
+        Q.a = (float)S(BP_SOL_A);
+        Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
+        Q.ant_f = (float)(P.alpha_nt * S(BP_SOL_FNT));
+        Q.n_nt = (float)P.n_nt;
+        shq = Q;
+        const double Rt = S(BP_SOL_RT);
+        const double ra = fmin(rv, rf);
+        // zone ranges; the innermost sight line r_perp = 1e-5 r_a has the same eta for every halo
+        const double eta_lo = log1p(acosh(ra / fmin(Rt, ra)));
+        const bool shell = rf > rv;
+        const double D = shell ? rf * rf - rv * rv : 0.0;
+        const double sD = sqrt(D);
+        double om_lo = 0.0, om_hi = 0.0, ze_lo = 0.0, ze_hi = 0.0;
+        if (shell) {
+            double rtop = fmin(Rt, rv);
+            om_lo = asinh(sqrt(fmax(rv * rv - rtop * rtop, 0.0)) / sD);
+            om_hi = asinh(rv / sD);
+        }
+        if (Rt > rv) { ze_lo = acosh(rf / Rt); ze_hi = acosh(rf / rv); }
+        shd[0] = eta_lo; shd[1] = om_lo; shd[2] = om_hi; shd[3] = ze_lo; shd[4] = ze_hi;
+        shd[5] = rv; shd[6] = rf; shd[7] = Rt;
+    }
+    __syncthreads();
+    const Prof Q = shq;
+    const double eta_lo = shd[0], eta_hi = G.eta_top, om_lo = shd[1], om_hi = shd[2], ze_lo = shd[3], ze_hi = shd[4];
+    const double rv = shd[5], rf = shd[6], Rt = shd[7];
     const double ra = fmin(rv, rf);
-    const double rmin = 1e-5 * ra;
-    // zone ranges
-    const double eta_lo = log1p(acosh(ra / fmin(Rt, ra)));
-    const double eta_hi = log1p(acosh(ra / rmin));
     const bool shell = rf > rv;
     const double D = shell ? rf * rf - rv * rv : 0.0;
     const double sD = sqrt(D);
-    double om_lo = 0.0, om_hi = 0.0, ze_lo = 0.0, ze_hi = 0.0;
-    if (shell) {
-        double rtop = fmin(Rt, rv);
-        om_lo = asinh(sqrt(fmax(rv * rv - rtop * rtop, 0.0)) / sD);
-        om_hi = asinh(rv / sD);
-    }
     const bool zoneB = Rt > rv;
-    if (zoneB) { ze_lo = acosh(rf / Rt); ze_hi = acosh(rf / rv); }
 
     double accP = 0.0, accN = 0.0;
     if (node < BP_TAB_NA) {
@@ -438,15 +466,18 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
             prof_eval(Q, (float)ra, &pe, &ne);
             accP = 2.0 * pe; accN = 2.0 * ne;
         } else {
-            const double rp = ra / cosh(xi);
-            const double u = ra * tanh(xi);
+            // cosh and tanh of xi from one expm1 (no cancellation for small xi)
+            const double em = expm1(xi), e = 1.0 + em, q = e * e + 1.0;
+            const double rp = ra * (2.0 * e / q);
+            const double u = ra * (em * (2.0 + em) / q);
             // 16 nodes reach 1e-11 up to xi ~ 6 (sight lines off the core); 24 beyond
             const bool wide = xi > 5.5;
             const int ng = wide ? 24 : 16;
-            const double *gx = wide ? G.x24 : G.x16, *gw = wide ? G.w24 : G.w16;
-            const float rpf = (float)rp, raf = (float)ra, hx = (float)(0.5 * xi);
+            const float *gu = wide ? G.u24 : G.u16;
+            const double *gw = wide ? G.w24 : G.w16;
+            const float rpf = (float)rp, raf = (float)ra, xif = (float)xi;
             for (int j = 0; j < ng; ++j) {
-                float r = fminf(rpf * cosh_f(hx * (float)(gx[j] + 1.0)), raf);
+                float r = fminf(rpf * cosh_f(xif * gu[j]), raf);
                 float pe, ne;
                 prof_eval(Q, r, &pe, &ne);
                 double w = gw[j] * (double)r;
@@ -488,11 +519,12 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
                 prof_eval(Q, Q.rf, &pe, &ne);
                 accP = 2.0 * pe; accN = 2.0 * ne;
             } else {
-                const double rp = rf / cosh(ze);
-                const double U = rf * tanh(ze);
-                const float rpf = (float)rp, hz = (float)(0.5 * ze);
+                const double em = expm1(ze), e = 1.0 + em, q = e * e + 1.0;
+                const double rp = rf * (2.0 * e / q);
+                const double U = rf * (em * (2.0 + em) / q);
+                const float rpf = (float)rp, zef = (float)ze;
                 for (int j = 0; j < 12; ++j) {
-                    float r = fmaxf(fminf(rpf * cosh_f(hz * (float)(G.x12[j] + 1.0)), Q.rf), Q.rv);
+                    float r = fmaxf(fminf(rpf * cosh_f(zef * G.u12[j]), Q.rf), Q.rv);
                     float pe, ne;
                     prof_eval(Q, r, &pe, &ne);
                     double w = G.w12[j] * (double)r;
@@ -547,6 +579,10 @@ const GaussRules &gauss_rules() {
         gauss_legendre(16, G.x16, G.w16);
         gauss_legendre(24, G.x24, G.w24);
         gauss_legendre(12, G.x12, G.w12);
+        for (int j = 0; j < 16; ++j) G.u16[j] = (float)(0.5 * (G.x16[j] + 1.0));
+        for (int j = 0; j < 24; ++j) G.u24[j] = (float)(0.5 * (G.x24[j] + 1.0));
+        for (int j = 0; j < 12; ++j) G.u12[j] = (float)(0.5 * (G.x12[j] + 1.0));
+        G.eta_top = log1p(acosh(1e5));
         init = true;
     }
     return G;
