@@ -19,9 +19,33 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3
-PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# FP32 VALU issue peak: 256 CUs x 4 SIMDs x 32 lanes per cycle x 2.4 GHz = 78.6e12 lane-operations/s
+# (an FMA counts once; the published fp32 vector figure, 157.3 TFLOP/s, is this rate with an FMA
+# counted as two flops).
+PEAK_VALU_TOPS = 78.6
+# Algorithmic operations per footprint pixel of the exact-table deposit (zone A or B pixel):
+# geometry 5, u^2/U^2 2, sqrt 2, acosh argument and log 6, eta 4, grid coordinate 2,
+# cell and fraction 6, cubic Lagrange weights 15, two 4-tap sums 8, edge factor 2,
+# amplitudes 2, two Kahan updates 8.
+DEPOSIT_OPS_PER_PX = 62
+# HBM bytes per deposit launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99995, WRITE x 1.0).
+# Valid only for the deposit sources they were measured on.
+DEPOSIT_TRAFFIC = {"bytes": 2588237009,
+                   "sources_sha256": {"bp_hp_flat.hip": "3418e443a380fad27868f7c0dbf63056cd96a49e941dc09f5b1e5c0ae833f8f8",
+                                      "bp_footprint.hpp": "8ce9f547ae9be71dc9f36c95a0b9af232ea559400289132fb5d2fa6b3f85035a"}}
+
+
+def deposit_traffic():
+    """The recorded HBM bytes per deposit launch, or None once the deposit sources have changed."""
+    import hashlib
+    for name, digest in DEPOSIT_TRAFFIC["sources_sha256"].items():
+        path = os.path.join(ROOT, "paper_2201_02632_amd", "csrc", name)
+        with open(path, "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != digest:
+                return None
+    return DEPOSIT_TRAFFIC["bytes"]
 
 
 def footprint_pixel_count(cat_dev, sol, st, bp, npix, pix):
@@ -148,24 +172,18 @@ def main():
         return
     nsolved = int((st == 0).sum().item())
     nfp = footprint_pixel_count(t, sol, st, bp, npix, pix)
-    # dominant kernel: the longest per-launch duration
+    # dominant kernel: the longest per-launch duration; the deposit is VALU-bound by design
+    # (its algorithmic HBM bytes are ~1/40 of what its ALU work takes at peak)
     dom = max(kt, key=kt.get)
-    # Algorithmic work per unit (derivation in the design notes):
-    #   deposit: 96 FP32 flops per footprint pixel (y and b: geometry, zone variables,
-    #            two 4-point interpolations of P and n, edge factor, Kahan updates)
-    #   tables : 512 nodes x ~22 GL points x 60 FP64 flops per halo
-    #   solve  : 67 energy trials x 32 nodes x 45 FP64 flops per halo
-    work = {"flat_deposit": (nfp * 96.0, PEAK_FP32_TFLOPS),
-            "tables": (nsolved * 512 * 22 * 60.0, PEAK_FP64_TFLOPS),
-            "icm_solve": (nsolved * 67 * 32 * 45.0, PEAK_FP64_TFLOPS),
-            "flat_plan": (None, None)}
-    flops, peak = work[dom]
-    if flops is None:
-        roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+    roof = None
+    if dom == "flat_deposit":
+        ach = DEPOSIT_OPS_PER_PX * nfp / (kt[dom] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                "frac": round(ach / PEAK_VALU_TOPS, 4), "traffic": deposit_traffic(), "kernel": dom,
+                "ops_per_unit": DEPOSIT_OPS_PER_PX, "units": nfp, "unit_name": "footprint pixel"}
     else:
-        ach = flops / (kt[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None, "kernel": dom}
+        roof = {"bound": "alu", "achieved": None, "peak": PEAK_VALU_TOPS, "unit": "Tops/s", "frac": None,
+                "traffic": None, "kernel": dom}
     out = {
         "metric": "halos/s & particles/s pasted into y/kSZ maps; surrogate vs exact at ≤1e-3 err",
         "value": round(n / (ms * 1e-3), 1),
