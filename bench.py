@@ -91,6 +91,145 @@ def cpu_baseline(sample_n=60, seed=102):
                       f"full footprints on the 4096^2 map, single thread ({dt:.1f} s)"}
 
 
+def kernel_times(bp, names, steps):
+    """Milliseconds per step in each of the library's HIP-event profiling slots."""
+    import ctypes as C
+    out = {}
+    for name in names:
+        tot, cnt = C.c_double(0), C.c_int64(0)
+        bp._lib.bp_profile_read(bp.PROF[name], C.byref(tot), C.byref(cnt))
+        out[name] = round(tot.value / steps, 4)
+    return out
+
+
+def timed(fn, steps, warmup, bp=None):
+    """Host wall time per call of fn over `steps` synchronised calls after `warmup` calls; the
+    library's kernel profiling covers exactly the timed calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    if bp is not None:
+        bp._lib.bp_profiling(1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def map_errors(g, o):
+    """Integrated-Y error and per-pixel relative errors |g-o| / (|o| + 1e-6 max|o|)."""
+    g64, o64 = g.double(), o.double()
+    rel = (g64 - o64).abs() / (o64.abs() + 1e-6 * o64.abs().max())
+    q = rel.flatten()
+    q = q[torch_quantile_sample(q)]
+    return {"integrated_Y_err": float(abs(g64.sum() / o64.sum() - 1)), "pixel_max": float(rel.max()),
+            "pixel_median": float(q.median()), "pixel_p99": float(q.quantile(0.99))}
+
+
+def torch_quantile_sample(q, n=1 << 22):
+    """A fixed strided subset of the pixels for quantiles (torch.quantile caps its input size)."""
+    import torch
+    step = max(1, q.numel() // n)
+    return torch.arange(0, q.numel(), step, device=q.device)
+
+
+def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_steps):
+    """Surrogate vs exact HP paste of the same catalogue: 4096^2 pixels over 5x5 deg, the 5e5-halo
+    recipe scaled to n_halos.  The network is trained first (exact solves of n_train halos over the
+    training domain, then Adam on the GPU)."""
+    import torch
+
+    from paper_2201_02632_amd.surrogate import Surrogate
+    from paper_2201_02632_amd.synth import hp_flat_large, surrogate_training
+    S = Surrogate(params=params, seed=0)
+    t0 = time.perf_counter()
+    tr = surrogate_training(n_train, seed=4)
+    x, t = S.training_set(tr["M"], tr["c"], tr["z"])
+    S.set_stats(t)
+    hist = S.fit(x, t, steps=train_steps, batch=4096, lr=2e-3, lr_end=1e-5, log_every=max(train_steps // 4, 1))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del x, t
+    print(f"# surrogate trained in {train_s:.1f} s on {n_train} exact solves", file=sys.stderr, flush=True)
+    cat, npix, pix = hp_flat_large(n=n_halos, seed=6)
+    d = {k: torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous() for k, v in cat.items()}
+    del cat
+    ye = torch.zeros((npix, npix), dtype=torch.float32, device=dev)
+    be = torch.zeros_like(ye)
+    ys = torch.zeros_like(ye)
+    bs = torch.zeros_like(ye)
+    ws = bp.Workspace(dev)
+
+    def exact():
+        ye.zero_(); be.zero_()
+        sol, st = bp.icm_solve(params, d["M"], d["c"], d["z"])
+        tab, meta = bp.profile_tables(params, sol, st)
+        bp.hp_paste_flat(params, npix, pix, d["theta_x"], d["theta_y"], d["v_los"], sol, st, tab, meta, ye, be, ws=ws)
+
+    nout = [0]
+
+    def surrogate():
+        ys.zero_(); bs.zero_()
+        nout[0] = S.paste_flat(d, npix, pix, ys, bs, ws)
+
+    ms_exact = timed(exact, steps, warmup, bp)
+    k_exact = kernel_times(bp, ("ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT"), steps)
+    print(f"# exact path on {n_halos} halos: {ms_exact:.1f} ms", file=sys.stderr, flush=True)
+    ms_sur = timed(surrogate, steps, warmup, bp)
+    k_sur = kernel_times(bp, ("MLP_FWD", "SURR_APPLY", "FLAT_PLAN", "FLATQ_DEPOSIT", "ICM", "TABLES", "FLAT_DEPOSIT"),
+                         steps)
+    bp._lib.bp_profiling(0)
+    print(f"# surrogate path: {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    err_y = map_errors(ys, ye)
+    err_b = map_errors(bs, be)
+    return {"workload": f"HP flat-sky 5x5 deg, 4096^2 pixels, {n_halos} halos (log10 M in [12.5,15.5], "
+                        "dN/dlnM ~ M^-0.9, z in [0.1,1]); surrogate trained on "
+                        f"{n_train} exact solves over log10 M in [12.5,15.5], c in [2,15], z in [0.05,3]",
+            "exact_halos_per_s": round(n_halos / (ms_exact * 1e-3), 1), "exact_ms": round(ms_exact, 2),
+            "surrogate_halos_per_s": round(n_halos / (ms_sur * 1e-3), 1), "surrogate_ms": round(ms_sur, 2),
+            "speedup": round(ms_exact / ms_sur, 3), "fallback_halos": int(nout[0]),
+            "y_err": err_y, "b_err": err_b, "train_s": round(train_s, 1), "train_steps": train_steps,
+            "train_loss": hist[-1][1] if hist else None,
+            "kernel_ms_exact": k_exact, "kernel_ms_surrogate": k_sur, "dtype": "bf16 MFMA (fp32 accumulate) + f32 deposit"}
+
+
+def pp_section(bp, params, dev, steps, warmup, n_particles):
+    """Particle-based pasting of a 5x5 deg light cone onto 4096^2 pixels: 60% of the particles in
+    2e5 halos (NFW, triaxial), 40% field particles on a lognormal grid; 32-NN smoothing lengths."""
+    import torch
+
+    from paper_2201_02632_amd.synth import pp_large_device
+    t0 = time.perf_counter()
+    halos, parts, M_p, npix, pix = pp_large_device(n_particles=n_particles, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    n = parts["theta_x"].numel()
+    print(f"# PP: {n} particles drawn in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    th = {k: torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous() for k, v in halos.items()}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol, st = bp.icm_solve(params, th["M"], th["c"], th["z"])
+    torch.cuda.synchronize()
+    solve_ms = (time.perf_counter() - t1) * 1e3
+    y = torch.zeros((npix, npix), dtype=torch.float32, device=dev)
+    b = torch.zeros_like(y)
+    ws = bp.Workspace(dev)
+
+    def step():
+        h = bp.pp_smoothing_length(params, parts["theta_x"], parts["theta_y"], parts["z"], 32, 0.0, ws=ws)
+        bp.pp_paste_flat(params, npix, pix, parts, h, M_p, sol, st, y, b, ws=ws)
+
+    ms = timed(step, steps, warmup, bp)
+    kt = kernel_times(bp, ("PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT"), steps)
+    bp._lib.bp_profiling(0)
+    return {"workload": f"PP flat-sky 5x5 deg, 4096^2 pixels, z in [0.05,1.5]: {n} FP32 particles, 60% in 2e5 "
+                        "triaxial NFW halos, 40% lognormal field; 32-NN smoothing, cubic-spline kernel",
+            "particles_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 2), "n_particles": n,
+            "halo_solve_ms": round(solve_ms, 2), "kernel_ms": kt, "generation_s": round(gen_s, 1)}
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """Plain device-to-device copies of a known size: each launch reads and writes exactly
     nbytes, which fixes the scale of the FETCH_SIZE / WRITE_SIZE counters."""
@@ -114,6 +253,13 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the warmup and timed steps, print per-kernel times and stop (for hardware-counter "
                          "passes under a profiler: no reporting kernels after the steps)")
+    ap.add_argument("--sections", default="surrogate,pp",
+                    help="extra measured sections after the headline one: surrogate, pp (comma list, or none)")
+    ap.add_argument("--extra-steps", type=int, default=2)
+    ap.add_argument("--sur-halos", type=int, default=10_000_000)
+    ap.add_argument("--sur-train", type=int, default=1_000_000)
+    ap.add_argument("--sur-steps", type=int, default=20_000)
+    ap.add_argument("--pp-particles", type=int, default=200_000_000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (reference reading for HBM byte counters)")
     args = ap.parse_args()
@@ -199,6 +345,16 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         "roofline": roof,
     }
+    del t, y, b, ws, sol, st
+    torch.cuda.empty_cache()
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
+    if "surrogate" in sections:
+        out["surrogate"] = surrogate_section(bp, params, dev, args.extra_steps, 1, args.sur_halos, args.sur_train,
+                                             args.sur_steps)
+        torch.cuda.empty_cache()
+    if "pp" in sections:
+        out["pp"] = pp_section(bp, params, dev, args.extra_steps, 1, args.pp_particles)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -296,8 +296,10 @@ int bp_surrogate_targets(const bp_params *p, int64_t n, const double *sol, const
 int bp_surrogate_stats(int64_t n, const float *targets, float *mean, float *std, void *stream);
 /* Gather rows: out[i] = in[idx[i]] (cols floats per row). */
 int bp_gather_rows(int64_t n, int32_t cols, const float *in, const int64_t *idx, float *out, void *stream);
-/* MSE loss over the 131 used outputs against standardised targets:
- * dy = 2 (y - (t - mean)/std) / (n * 131); loss_rows[i] = row sum of squares. */
+/* Weighted MSE over the 131 used outputs against standardised targets, weight
+ * w_c = 1 for the 128 table entries and 16 for each of ln x_f, ln(P_e0/P_s),
+ * ln(n_e0/n_scale):  dy = 2 w_c (y - (t - mean)/std) / (n * sum_c w_c);
+ * loss_rows[i] = sum_c w_c r_c^2.  Rows with a non-finite target get dy = 0. */
 int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const float *mean, const float *std, float *dy,
                      float *loss_rows, void *stream);
 /* Apply the network output: completes sol (XF, RF, RT) for in-domain halos

@@ -168,22 +168,29 @@ __global__ void k_pp_gather(int64_t n, Grid g, const double *__restrict__ pos, c
 // ------------------------------------------------------------ K6 kNN --
 constexpr int kKmax = 64;
 
+// The k smallest values seen so far, ascending, in registers: K/16 16-wide vectors indexed only
+// by compile-time constants (a runtime index would push the array into scratch memory).  The
+// lowest K - k slots hold -inf and never move, so the last slot is always the k-th smallest
+// (+inf until k values have arrived).  Insertion shifts the larger entries up by one, branch-free.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+template <int K>
 struct TopK {
-    float d[kKmax];
-    int cnt, k, worst_i;
-    float worst;
-    __device__ void init(int kk) { cnt = 0; k = kk; worst = 0.0f; worst_i = 0; }
-    __device__ void push(float v) {
-        if (cnt < k) {
-            d[cnt] = v;
-            if (v >= worst || cnt == 0) { worst = v; worst_i = cnt; }
-            ++cnt;
-        } else if (v < worst) {
-            d[worst_i] = v;
-            worst = d[0]; worst_i = 0;
-            for (int q = 1; q < k; ++q)
-                if (d[q] > worst) { worst = d[q]; worst_i = q; }
+    static_assert(K % 16 == 0, "K must be a multiple of 16");
+    f32x16 v[K / 16];
+    __device__ void init(int k) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q >> 4][q & 15] = (q < K - k) ? -__builtin_inff() : __builtin_inff();
+    }
+    __device__ float at(int q) const { return v[q >> 4][q & 15]; }
+    __device__ float kth() const { return at(K - 1); }
+    __device__ void push(float x) {
+        if (!(x < kth())) return;
+#pragma unroll
+        for (int q = K - 1; q > 0; --q) {
+            const float lo = at(q - 1), cur = at(q);
+            v[q >> 4][q & 15] = (x < lo) ? lo : ((x < cur) ? x : cur);
         }
+        v[0][0] = fminf(v[0][0], x);
     }
 };
 
@@ -196,6 +203,18 @@ __device__ inline uint32_t lower_bound64(const uint64_t *__restrict__ key, uint3
     return lo;
 }
 
+// One lane per particle, in sorted (cell, Morton) order.  Level-l cells have size cell * 2^(l-10):
+// level 10 is the coarse grid, finer levels are aligned Morton blocks inside a coarse cell, and
+// coarser ones are blocks of 2^(l-10) coarse cells per axis.  Cells are scanned in Chebyshev shells
+// r = 0, 1, 2, ... around the particle's own cell, skipping cells farther than the current k-th
+// distance.  After shell r every particle not yet scanned is at least (r + m) cells away, m being
+// the particle's distance to its own cell's faces, so the k-th distance is final once it is no
+// larger.  The start level makes a cell about the radius that holds k particles at the density of
+// the particle's coarse cell; a search that needs more than kShells shells restarts one level up.
+constexpr int kShells = 8;
+constexpr int kMaxLevel = 20;
+
+template <int K>
 __global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key,
                                                 const uint32_t *__restrict__ idx, const double *__restrict__ sp,
                                                 const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ cend,
@@ -213,75 +232,95 @@ __global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const 
         fy |= ((m >> (3 * b + 1)) & 1u) << b;
         fz |= ((m >> (3 * b + 2)) & 1u) << b;
     }
-    const float cellf = (float)g.cell;
-    // start level from the coarse-cell density: level-l cells have size cell * 2^(l-10)
-    uint32_t occ = cend[c] - cstart[c];
-    double hest = cbrt((double)k / (4.18879 * (double)occ)) * g.cell;   // radius holding k neighbours
-    int lev = (int)floor(log2(hest / g.cell) + 10.0);
-    lev = min(max(lev, 0), 16);
-    TopK T;
+    const uint32_t occ = cend[c] - cstart[c];
+    const double hest = cbrt((double)k / (4.18879 * (double)occ)) * g.cell;   // radius holding k neighbours
+    TopK<K> T;
     bool done = false;
-    for (int it = 0; it < 24 && lev <= 20; ++it, ++lev) {
-        T.init(k);
-        int64_t total = 0;
+    for (int lev = min(max((int)rint(log2(hest / g.cell)) + 10, 0), kMaxLevel); lev <= kMaxLevel && !done; ++lev) {
+        // this level's cell grid: size s, the particle's cell (gx, gy, gz), extent (nxl, nyl, nzl)
+        const double s = ldexp(g.cell, lev - 10);
+        int64_t gx, gy, gz, nxl, nyl, nzl;
         if (lev <= 10) {
-            const int sh = 10 - lev;                 // local cells per coarse cell, per axis: 2^sh
-            const int64_t gx = ((int64_t)cx << sh) + (fx >> lev), gy = ((int64_t)cy << sh) + (fy >> lev),
-                          gz = ((int64_t)cz << sh) + (fz >> lev);
-            const float sl = cellf / (float)(1 << sh);
-            for (int dz = -1; dz <= 1; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        int64_t ax = gx + dx, ay = gy + dy, az = gz + dz;
-                        if (ax < 0 || ay < 0 || az < 0) continue;
-                        int64_t ccx = ax >> sh, ccy = ay >> sh, ccz = az >> sh;
-                        if (ccx >= g.nx || ccy >= g.ny || ccz >= g.nz) continue;
-                        uint64_t cc = ((uint64_t)ccz * g.ny + ccy) * g.nx + ccx;
-                        uint32_t s0 = cstart[cc], s1 = cend[cc];
-                        if (s0 >= s1) continue;
-                        uint32_t lx = (uint32_t)(ax - (ccx << sh)) << lev, ly = (uint32_t)(ay - (ccy << sh)) << lev,
-                                 lz = (uint32_t)(az - (ccz << sh)) << lev;
-                        uint64_t base = cc << 30;
-                        uint64_t klo = base | morton3(lx, ly, lz);
-                        uint64_t khi = klo + (1ull << (3 * lev));
-                        uint32_t a = lower_bound64(key, s0, s1, klo), b = lower_bound64(key, a, s1, khi);
-                        total += b - a;
-                        for (uint32_t j = a; j < b; ++j) {
-                            if (j == (uint32_t)i) continue;
-                            float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey),
-                                  ddz = (float)(sp[2 * n + j] - mez);
-                            T.push(ddx * ddx + ddy * ddy + ddz * ddz);
-                        }
-                    }
-            if (T.cnt >= k && T.worst <= sl * sl) { done = true; break; }
+            const int sh = 10 - lev;
+            gx = ((int64_t)cx << sh) + (fx >> lev); gy = ((int64_t)cy << sh) + (fy >> lev);
+            gz = ((int64_t)cz << sh) + (fz >> lev);
+            nxl = (int64_t)g.nx << sh; nyl = (int64_t)g.ny << sh; nzl = (int64_t)g.nz << sh;
         } else {
-            const int B = 1 << (lev - 10);           // coarse cells per level-l cell, per axis
-            const int bx = cx / B, by = cy / B, bz = cz / B;
-            const float sl = cellf * (float)B;
-            for (int az = (bz - 1) * B; az < (bz + 2) * B; ++az) {
-                if (az < 0 || az >= g.nz) continue;
-                for (int ay = (by - 1) * B; ay < (by + 2) * B; ++ay) {
-                    if (ay < 0 || ay >= g.ny) continue;
-                    for (int ax = (bx - 1) * B; ax < (bx + 2) * B; ++ax) {
-                        if (ax < 0 || ax >= g.nx) continue;
-                        uint64_t cc = ((uint64_t)az * g.ny + ay) * g.nx + ax;
-                        uint32_t a = cstart[cc], b = cend[cc];
-                        total += (b > a) ? b - a : 0;
-                        for (uint32_t j = a; j < b; ++j) {
-                            if (j == (uint32_t)i) continue;
-                            float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey),
-                                  ddz = (float)(sp[2 * n + j] - mez);
-                            T.push(ddx * ddx + ddy * ddy + ddz * ddz);
+            const int up = lev - 10;
+            gx = cx >> up; gy = cy >> up; gz = cz >> up;
+            nxl = ((int64_t)g.nx + (1 << up) - 1) >> up; nyl = ((int64_t)g.ny + (1 << up) - 1) >> up;
+            nzl = ((int64_t)g.nz + (1 << up) - 1) >> up;
+        }
+        // position inside the own cell, in cell units (cell membership came from the same FP64 positions)
+        const float ux = fminf(fmaxf((float)((mex - g.x0) / s - (double)gx), 0.0f), 1.0f);
+        const float uy = fminf(fmaxf((float)((mey - g.y0) / s - (double)gy), 0.0f), 1.0f);
+        const float uz = fminf(fmaxf((float)((mez - g.z0) / s - (double)gz), 0.0f), 1.0f);
+        const float mface = fminf(fminf(fminf(ux, 1.0f - ux), fminf(uy, 1.0f - uy)), fminf(uz, 1.0f - uz));
+        const float s2 = (float)(s * s);
+        // all particles of a contiguous sorted range
+        auto scan = [&](uint32_t a0, uint32_t b0) {
+            for (uint32_t j = a0; j < b0; ++j) {
+                if (j == (uint32_t)i) continue;
+                const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
+                T.push(ddx * ddx + ddy * ddy + ddz * ddz);
+            }
+        };
+        T.init(k);
+        for (int r = 0; r <= kShells && !done; ++r) {
+            const float kth2 = T.kth();
+            for (int dz = -r; dz <= r; ++dz) {
+                const int64_t az = gz + dz;
+                if (az < 0 || az >= nzl) continue;
+                const float ez = dz > 0 ? dz - uz : (dz < 0 ? uz - dz - 1 : 0.0f);
+                for (int dy = -r; dy <= r; ++dy) {
+                    const int64_t ay = gy + dy;
+                    if (ay < 0 || ay >= nyl) continue;
+                    const float ey = dy > 0 ? dy - uy : (dy < 0 ? uy - dy - 1 : 0.0f);
+                    const bool face = (dz == -r || dz == r || dy == -r || dy == r);
+                    const int step = (face || r == 0) ? 1 : 2 * r;
+                    for (int dx = -r; dx <= r; dx += step) {
+                        const int64_t ax = gx + dx;
+                        if (ax < 0 || ax >= nxl) continue;
+                        const float ex = dx > 0 ? dx - ux : (dx < 0 ? ux - dx - 1 : 0.0f);
+                        // cannot hold a closer particle (the factor absorbs FP32 rounding of both sides)
+                        if ((ex * ex + ey * ey + ez * ez) * s2 * 0.999998f >= kth2) continue;
+                        if (lev <= 10) {
+                            const int sh = 10 - lev;
+                            const int64_t ccx = ax >> sh, ccy = ay >> sh, ccz = az >> sh;
+                            const uint64_t cc = ((uint64_t)ccz * g.ny + ccy) * g.nx + ccx;
+                            uint32_t a0 = cstart[cc], b0 = cend[cc];
+                            if (a0 >= b0) continue;
+                            if (lev < 10) {
+                                const uint32_t lx = (uint32_t)(ax - (ccx << sh)) << lev,
+                                               ly = (uint32_t)(ay - (ccy << sh)) << lev,
+                                               lz = (uint32_t)(az - (ccz << sh)) << lev;
+                                const uint64_t klo = (cc << 30) | morton3(lx, ly, lz);
+                                const uint64_t khi = klo + (1ull << (3 * lev));
+                                const uint32_t a1 = lower_bound64(key, a0, b0, klo);
+                                b0 = lower_bound64(key, a1, b0, khi);
+                                a0 = a1;
+                            }
+                            scan(a0, b0);
+                        } else {
+                            const int up = lev - 10;
+                            const int64_t x1 = min((ax + 1) << up, (int64_t)g.nx), y1 = min((ay + 1) << up, (int64_t)g.ny),
+                                          z1 = min((az + 1) << up, (int64_t)g.nz);
+                            for (int64_t qz = az << up; qz < z1; ++qz)
+                                for (int64_t qy = ay << up; qy < y1; ++qy)
+                                    for (int64_t qx = ax << up; qx < x1; ++qx) {
+                                        const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + qx;
+                                        scan(cstart[cc], cend[cc]);
+                                    }
                         }
                     }
                 }
             }
-            if (T.cnt >= k && T.worst <= sl * sl) { done = true; break; }
+            const float bound = ((float)r + mface) * (float)s * 0.999999f;
+            done = T.kth() <= bound * bound;   // +inf (not done) until k neighbours are known
         }
-        (void)total;
     }
-    // a particle too isolated for the largest search block gets NaN and raises the failure flag
-    float h = done ? sqrtf(T.worst) : __int_as_float(0x7fc00000);
+    // a particle too isolated for the largest search gets NaN and raises the failure flag
+    const float h = done ? sqrtf(T.kth()) : __int_as_float(0x7fc00000);
     if (!done) atomicOr(fail, 1);
     h_out[idx[i]] = h;
 }
@@ -642,7 +681,15 @@ extern "C" int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float
     hipLaunchKernelGGL(k_pp_gather, dim3(blocks), dim3(256), 0, s, n, g, pos, ks, vs, sp, cs, ce);
     prof_end(BP_PROF_PP_SORT, s);
     prof_begin(BP_PROF_PP_KNN, s);
-    hipLaunchKernelGGL(k_pp_knn, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving, fail);
+    if (k <= 16)
+        hipLaunchKernelGGL(k_pp_knn<16>, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving,
+                           fail);
+    else if (k <= 32)
+        hipLaunchKernelGGL(k_pp_knn<32>, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving,
+                           fail);
+    else
+        hipLaunchKernelGGL(k_pp_knn<64>, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving,
+                           fail);
     prof_end(BP_PROF_PP_KNN, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

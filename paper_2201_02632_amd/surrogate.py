@@ -101,6 +101,17 @@ class Surrogate:
                "bp_mlp_forward")
         return y, act
 
+    def predict(self, x, chunk=1 << 20):
+        """Network outputs for many rows, in chunks that share one activation buffer."""
+        n = x.shape[0]
+        y = torch.empty((n, MLP_OUT), dtype=torch.float32, device=self.dev)
+        act = torch.empty(int(_lib.bp_mlp_act_bytes(min(n, chunk))), dtype=torch.uint8, device=self.dev)
+        for s0 in range(0, n, chunk):
+            k = min(chunk, n - s0)
+            _check(_lib.bp_mlp_forward(_ptr(self.w), _ptr(self.wb), k, _ptr(x[s0:s0 + k]), _ptr(y[s0:s0 + k]),
+                                       _ptr(act), _stream()), "bp_mlp_forward")
+        return y
+
     def backward(self, x, act, dy, ws=None):
         n = x.shape[0]
         need = int(_lib.bp_mlp_backward_ws_bytes(n))
@@ -166,7 +177,7 @@ class Surrogate:
         _check(_lib.bp_halo_structure(C.byref(self.params), n, _ptr(M), _ptr(c), _ptr(z), _ptr(sol), _ptr(st),
                                       _stream()), "bp_halo_structure")
         x = self.features(M, c, z)
-        y, _ = self.forward(x)
+        y = self.predict(x)
         qt = torch.zeros((n, 2 * MLP_NQ), dtype=torch.float32, device=self.dev)
         meta = torch.zeros((META_NFIELDS, n), dtype=torch.float32, device=self.dev)
         _check(_lib.bp_surrogate_apply(C.byref(self.params), n, _ptr(y), _ptr(self.mean), _ptr(self.std), _ptr(sol),

@@ -226,3 +226,123 @@ def pp_large(seed=3, n_particles=200_000_000):
     halos, parts, M_p = pp_lightcone(200_000, int(0.6 * n_particles), int(0.4 * n_particles), 5.0,
                                      zr=(0.05, 1.5), seed=seed)
     return halos, parts, M_p, 4096, 5.0 * DEG / 4096
+
+
+# ------------------------------------------------- device-side particle draws --
+# The same light-cone recipe as ``pp_lightcone``, drawn with torch on the
+# device so that 2e8-particle workloads take seconds instead of minutes.  The
+# halo catalogue still comes from numpy (it is small); the particle draws use a
+# seeded ``torch.Generator`` on the target device, so they differ from the
+# numpy draws of ``pp_lightcone`` but are reproducible on the same device.
+def _interp_t(x, xp, fp):
+    """Linear interpolation on an increasing table (torch)."""
+    import torch
+    i = torch.clamp(torch.searchsorted(xp, x), 1, xp.numel() - 1)
+    x0, x1 = xp[i - 1], xp[i]
+    w = (x - x0) / (x1 - x0)
+    return fp[i - 1] + w * (fp[i] - fp[i - 1])
+
+
+def _nfw_inverse_cdf_t(u, c, iters=60):
+    import torch
+    m = lambda x: torch.log1p(x) - x / (1 + x)  # noqa: E731
+    target = u * m(c)
+    lo = torch.zeros_like(u)
+    hi = c.clone()
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        big = m(mid) > target
+        hi = torch.where(big, mid, hi)
+        lo = torch.where(big, lo, mid)
+    return 0.5 * (lo + hi)
+
+
+def pp_lightcone_device(n_halos, n_halo_particles, n_field, field_deg, zr=(0.05, 1.5), logM=(12.5, 15.5),
+                        mass_function="powerlaw", field_cell=2.0, om=0.3, seed=3, device="cuda", chunk=1 << 24):
+    """``pp_lightcone`` with the particles drawn on ``device``.  Returns (halos as numpy float64,
+    particles as device tensors: float32 theta_x, theta_y, z, v_los, r_i and int32 halo_id, M_p)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    side = field_deg * DEG
+    M = _masses(rng, n_halos, logM[0], logM[1], mass_function)
+    zh = rng.uniform(zr[0], zr[1], size=n_halos)
+    c = _concentration(rng, M, zh)
+    halos = dict(M=M, c=c, z=zh, theta_x=rng.uniform(0, side, n_halos), theta_y=rng.uniform(0, side, n_halos),
+                 v_los=rng.normal(0.0, 300.0, n_halos))
+    M_p = float(M.sum() / max(n_halo_particles, 1))
+    Nh = np.floor(M / M_p + rng.uniform(size=n_halos)).astype(np.int64)
+    zt, chit = _chi_table(om)
+    E2 = om * (1 + zh) ** 3 + 1 - om
+    rv = (3 * M / (4 * np.pi * 200 * 2.775e11 * E2)) ** (1.0 / 3.0)
+    chih = np.interp(zh, zt, chit)
+    DA = chih / (1 + zh)
+    q = np.sort(rng.uniform(0.5, 1.0, size=(n_halos, 2)), axis=1)[:, ::-1]
+    axes = np.stack([np.ones(n_halos), q[:, 0], q[:, 1]], 1) / np.cbrt(q[:, 0] * q[:, 1])[:, None]
+    rot = _random_rotations(rng, n_halos)
+    sig = np.sqrt(4.30091e-9 * M / (2 * rv))
+    f64 = dict(dtype=torch.float64, device=device)
+    T = {k: torch.as_tensor(np.ascontiguousarray(v), **f64) for k, v in
+         dict(c=c, rs=rv / c, DA=DA, chih=chih, zh=zh, tx=halos["theta_x"], ty=halos["theta_y"], v=halos["v_los"],
+              sig=sig, axes=axes, rot=rot).items()}
+    zt_t, chit_t = torch.as_tensor(zt, **f64), torch.as_tensor(chit, **f64)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    hid_all = torch.repeat_interleave(torch.arange(n_halos, device=device, dtype=torch.int64),
+                                      torch.as_tensor(Nh, device=device))
+    nh_tot = hid_all.numel()
+    out = {k: [] for k in ("theta_x", "theta_y", "z", "v_los", "halo_id", "r_i")}
+    for s0 in range(0, nh_tot, chunk):
+        hid = hid_all[s0:s0 + chunk]
+        n = hid.numel()
+        x = _nfw_inverse_cdf_t(torch.rand(n, generator=g, **f64), T["c"][hid])
+        r_e = x * T["rs"][hid]
+        nvec = torch.randn((n, 3), generator=g, **f64)
+        nvec /= torch.linalg.norm(nvec, dim=1, keepdim=True)
+        off = torch.bmm(T["rot"][hid], (nvec * T["axes"][hid]).unsqueeze(-1)).squeeze(-1) * r_e[:, None]
+        out["theta_x"].append((T["tx"][hid] + off[:, 0] / T["DA"][hid]).float())
+        out["theta_y"].append((T["ty"][hid] + off[:, 1] / T["DA"][hid]).float())
+        dchi = off[:, 2] * (1 + T["zh"][hid])
+        out["z"].append(_interp_t(T["chih"][hid] + dchi, chit_t, zt_t).float())
+        out["v_los"].append((T["v"][hid] + torch.randn(n, generator=g, **f64) * T["sig"][hid]).float())
+        out["halo_id"].append(hid.to(torch.int32))
+        out["r_i"].append(r_e.float())
+        del x, r_e, nvec, off, dchi
+    if n_field > 0:
+        chi0, chi1 = np.interp(zr, zt, chit)
+        nx = int(np.ceil(side * chi1 / field_cell))
+        nz = int(np.ceil((chi1 - chi0) / field_cell))
+        zc = chi0 + (torch.arange(nz, **f64) + 0.5) * field_cell
+        xc = (torch.arange(nx, **f64) + 0.5) * field_cell
+        inside = (xc[None, :, None] < side * zc[:, None, None]) & (xc[None, None, :] < side * zc[:, None, None])
+        W = torch.exp(torch.randn((nz, nx, nx), generator=g, **f64) - 0.5) * inside
+        cnt = torch.poisson(W * (n_field / W.sum()), generator=g).to(torch.int64)
+        del W, inside
+        idx = torch.nonzero(cnt.reshape(-1)).squeeze(1)
+        nn = cnt.reshape(-1)[idx]
+        cell = torch.repeat_interleave(idx, nn)
+        del cnt, idx, nn
+        kz, rem = cell // (nx * nx), cell % (nx * nx)
+        kx, ky = rem // nx, rem % nx
+        nf = cell.numel()
+        X = (kx.to(torch.float64) + torch.rand(nf, generator=g, **f64)) * field_cell
+        Y = (ky.to(torch.float64) + torch.rand(nf, generator=g, **f64)) * field_cell
+        Z = chi0 + (kz.to(torch.float64) + torch.rand(nf, generator=g, **f64)) * field_cell
+        del cell, kz, rem, kx, ky
+        keep = (X < side * Z) & (Y < side * Z) & (Z < chi1)
+        X, Y, Z = X[keep], Y[keep], Z[keep]
+        nf = X.numel()
+        out["theta_x"].append((X / Z).float())
+        out["theta_y"].append((Y / Z).float())
+        out["z"].append(_interp_t(Z, chit_t, zt_t).float())
+        out["v_los"].append((torch.randn(nf, generator=g, **f64) * 300.0).float())
+        out["halo_id"].append(torch.full((nf,), -1, dtype=torch.int32, device=device))
+        out["r_i"].append(torch.zeros(nf, dtype=torch.float32, device=device))
+    parts = {k: torch.cat(v).contiguous() for k, v in out.items()}
+    return halos, parts, M_p
+
+
+def pp_large_device(seed=3, n_particles=200_000_000, device="cuda"):
+    """``pp_large`` drawn on the device: 5x5 deg, 4096^2 pixels, 60% of the particles in 2e5 halos."""
+    halos, parts, M_p = pp_lightcone_device(200_000, int(0.6 * n_particles), int(0.4 * n_particles), 5.0,
+                                            zr=(0.05, 1.5), seed=seed, device=device)
+    return halos, parts, M_p, 4096, 5.0 * DEG / 4096
