@@ -118,6 +118,7 @@ def lib():
             "orc_W_sph": (C.c_double, [C.c_double]),
             "orc_w_sph": (C.c_double, [C.c_double]),
             "orc_knn_h": (None, [C.c_int64, _D, _D, _D, C.c_int, _D]),
+            "orc_knn_h_query": (None, [C.c_int64, _I64, C.c_int64, _D, _D, _D, C.c_int, _D]),
             "orc_pp_amplitudes": (None, [P, C.c_int64, _D, _D, _I32, _D, C.c_double, C.c_double,
                                          H, _D, _D]),
             "orc_pp_deposit": (None, [C.c_int64, _D, _D, _D, _D, _D, C.c_int, C.c_double, _D, _D]),
@@ -304,6 +305,15 @@ def knn_h(X, Y, Z, k=32):
     X, Y, Z = _f64(X), _f64(Y), _f64(Z)
     h = np.empty(len(X))
     lib().orc_knn_h(len(X), _dp(X), _dp(Y), _dp(Z), int(k), _dp(h))
+    return h
+
+
+def knn_h_query(qidx, X, Y, Z, k=32):
+    """k-th nearest other point of X[qidx] among all points (brute force per query)."""
+    X, Y, Z = _f64(X), _f64(Y), _f64(Z)
+    q = np.ascontiguousarray(qidx, dtype=np.int64)
+    h = np.empty(len(q))
+    lib().orc_knn_h_query(len(q), q.ctypes.data_as(_I64), len(X), _dp(X), _dp(Y), _dp(Z), int(k), _dp(h))
     return h
 
 

@@ -1043,6 +1043,27 @@ void orc_knn_h(int64_t n, const double *X, const double *Y, const double *Z, int
     free(d);
 }
 
+/* The same smoothing length for a subset of the points only (qidx[a] indexes
+ * X, Y, Z): brute force over all n points for each query.  For checks on
+ * samples of large particle sets, given every point that can be a neighbour. */
+void orc_knn_h_query(int64_t nq, const int64_t *qidx, int64_t n, const double *X, const double *Y,
+                     const double *Z, int k, double *h)
+{
+    double *d = malloc(sizeof(double) * (n > 1 ? n - 1 : 1));
+    for (int64_t a = 0; a < nq; a++) {
+        int64_t i = qidx[a], m = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            d[m++] = dx * dx + dy * dy + dz * dz;
+        }
+        if (m < k) { h[a] = NAN; continue; }
+        qsort(d, m, sizeof(double), cmp_double);
+        h[a] = sqrt(d[k - 1]);
+    }
+    free(d);
+}
+
 /* Per-particle signal amplitudes (Sec. 3.4).
  * Halo particle (halo_id >= 0):
  *   y_i = sigma_T/(m_e c^2) P_e(r_i) V_i / L_pix^2,

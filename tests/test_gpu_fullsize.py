@@ -1,0 +1,154 @@
+"""Parity at the benchmark sizes, in the benchmark's launch configuration, on outputs the oracle can
+compute one at a time.
+
+HP flat (5e5 halos, 4096^2 pixels over 5x5 deg): the whole catalogue is pasted exactly as the
+benchmark does it; a few sampled pixels are then recomputed by the oracle from every halo that can
+reach them.  Which halos can reach a pixel is decided by a loose bound (below), so the oracle sees a
+superset of the covering halos and applies its own R_t cut."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_02632_amd as bp
+    return bp
+
+
+def reach_bound_rad(M, z, om=0.3):
+    """An upper bound on each halo's footprint radius in radians: R_t <= 3 R500, and R500 is below
+    the radius at which the whole virial mass would have a mean density of 500 rho_c (because
+    M500 < M_vir); divided by a lower bound on D_A."""
+    zz = np.linspace(0.0, 1.2, 120001)
+    f = 1.0 / np.sqrt(om * (1 + zz) ** 3 + 1 - om)
+    chi = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(zz))]) * 2997.92458
+    DA_low = 0.999 * np.interp(z, zz, chi) / (1 + z)
+    rho_c = 2.775e11 * (om * (1 + z) ** 3 + 1 - om)          # (Msun/h) / (Mpc/h)^3
+    r500_max = (3 * M / (4 * math.pi * 500.0 * rho_c)) ** (1.0 / 3.0)
+    return 3.0 * r500_max / DA_low
+
+
+def test_hp_flat_fullsize_sampled_pixels(bp, orc):
+    import torch
+
+    from paper_2201_02632_amd.synth import hp_flat_large, subsample
+    cat, npix, pix = hp_flat_large()
+    dev = torch.device("cuda")
+    t = {k: torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous() for k, v in cat.items()}
+    params = bp.default_params()
+    ws = bp.Workspace(dev)
+    y = torch.zeros((npix, npix), dtype=torch.float32, device=dev)
+    b = torch.zeros_like(y)
+    sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
+    tab, meta = bp.profile_tables(params, sol, st)
+    bp.hp_paste_flat(params, npix, pix, t["theta_x"], t["theta_y"], t["v_los"], sol, st, tab, meta, y, b, ws=ws)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    b = b.cpu().numpy()
+    print(f"pasted {len(cat['M'])} halos onto {npix}^2 pixels", flush=True)
+
+    rng = np.random.default_rng(20)
+    pi = list(rng.integers(0, npix, 6))
+    pj = list(rng.integers(0, npix, 6))
+    big = int(np.argmax(cat["M"]))                               # the brightest footprint's centre
+    pi += [int(cat["theta_x"][big] / pix), 0, npix - 1]
+    pj += [int(cat["theta_y"][big] / pix), 0, npix // 2]
+    pi = np.array(pi, dtype=np.int32)
+    pj = np.array(pj, dtype=np.int32)
+
+    bound = reach_bound_rad(cat["M"], cat["z"])
+    cand = np.zeros(len(cat["M"]), dtype=bool)
+    for i, j in zip(pi, pj):
+        dx = (i + 0.5) * pix - cat["theta_x"]
+        dy = (j + 0.5) * pix - cat["theta_y"]
+        cand |= dx * dx + dy * dy < bound * bound
+    idx = np.nonzero(cand)[0]
+    print(f"oracle: {len(idx)} candidate halos for {len(pi)} pixels", flush=True)
+    sub = subsample(cat, idx)
+    p = orc.default_params()
+    halos = orc.solve_halos(p, sub["M"], sub["c"], sub["z"])
+    oy, ob = orc.hp_flat_pixels(p, halos, sub, pix, pi, pj)
+    _, obabs = orc.hp_flat_pixels(p, halos, dict(sub, v_los=np.abs(sub["v_los"])), pix, pi, pj)
+    gy = y[pj, pi].astype(np.float64)
+    gb = b[pj, pi].astype(np.float64)
+    ey = np.abs(gy - oy) / (np.abs(oy) + 1e-6 * np.abs(oy).max())
+    eb = np.abs(gb - ob) / (obabs + 1e-6 * obabs.max())
+    print("pixel  y_gpu  y_oracle  rel_err_y  rel_err_b")
+    for k in range(len(pi)):
+        print(f"({pi[k]},{pj[k]}) {gy[k]:.6e} {oy[k]:.6e} {ey[k]:.2e} {eb[k]:.2e}")
+    assert np.all(oy > 0), "every sampled pixel should lie inside some footprint"
+    assert ey.max() < 1e-5 and eb.max() < 1e-5
+
+
+def _chi_table(om=0.3, zmax=2.0, n=200001):
+    zz = np.linspace(0.0, zmax, n)
+    f = 1.0 / np.sqrt(om * (1 + zz) ** 3 + 1 - om)
+    chi = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(zz))]) * 2997.92458
+    return zz, chi
+
+
+def test_pp_fullsize_sampled_smoothing_lengths(bp, orc):
+    """32-NN smoothing lengths of the 2e8-particle light cone (the benchmark's draws and call),
+    checked on query particles in two comoving boxes: one around a random field particle and one
+    around the most massive halo's centre (the densest core).  Candidate neighbours are every
+    particle in a box three times wider; each query's oracle distance must stay inside it."""
+    import torch
+
+    from paper_2201_02632_amd.synth import pp_large_device
+    halos, parts, M_p, npix, pix = pp_large_device(device="cuda")
+    h = bp.pp_smoothing_length(bp.default_params(), parts["theta_x"], parts["theta_y"], parts["z"], 32)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy().astype(np.float64)
+    tx = parts["theta_x"].cpu().numpy()
+    ty = parts["theta_y"].cpu().numpy()
+    zp = parts["z"].cpu().numpy()
+    hid = parts["halo_id"].cpu().numpy()
+    del parts
+    torch.cuda.empty_cache()
+    n = len(zp)
+    print(f"{n} particles; GPU smoothing lengths done", flush=True)
+    zz, chit = _chi_table()
+    p = orc.default_params()
+    rng = np.random.default_rng(21)
+    big = int(np.argmax(halos["M"]))
+    centres = []
+    field = np.nonzero(hid < 0)[0]
+    j0 = int(field[rng.integers(0, len(field))])
+    centres.append((float(tx[j0]), float(ty[j0]), float(zp[j0]), 6.0))          # field: ~2 Mpc/h spacing
+    centres.append((float(halos["theta_x"][big]), float(halos["theta_y"][big]), float(halos["z"][big]), 1.0))
+    worst = 0.0
+    for (cx, cy, cz, L) in centres:
+        chic = float(np.interp(cz, zz, chit))
+        # loose angular / redshift preselection of a 3L-wide box, then the box itself
+        R = 3.0 * L
+        ang = 1.05 * R / (chic - R)
+        zlo, zhi = np.interp([chic - 1.05 * R, chic + 1.05 * R], chit, zz)
+        sel = np.nonzero((np.abs(tx - cx) < ang) & (np.abs(ty - cy) < ang) & (zp > zlo) & (zp < zhi))[0]
+        chi_s = np.array([orc.chi(p, float(z)) for z in zp[sel]])
+        X = chi_s * tx[sel].astype(np.float64)
+        Y = chi_s * ty[sel].astype(np.float64)
+        Z = chi_s
+        c0 = np.array([chic * cx, chic * cy, chic])
+        off = np.abs(np.stack([X, Y, Z], 1) - c0)
+        inner = np.max(off, axis=1) < L                                          # query particles
+        box = np.max(off, axis=1) < R
+        cand = np.nonzero(box)[0]
+        q_all = np.nonzero(inner[cand])[0]
+        q = rng.choice(q_all, min(200, len(q_all)), replace=False)
+        ho = orc.knn_h_query(q, X[cand], Y[cand], Z[cand], 32)
+        # every true neighbour lies inside the candidate box
+        margin = R - np.max(off[cand][q], axis=1)
+        assert np.all(ho < margin), "candidate box too small for the sampled queries"
+        hg = h[sel][cand][q]
+        err = np.max(np.abs(hg / ho - 1))
+        worst = max(worst, err)
+        print(f"box L={L}: {len(cand)} candidates, {len(q)} queries, h {ho.min():.3g}-{ho.max():.3g} Mpc/h, "
+              f"max rel err {err:.2e}", flush=True)
+        assert np.all(np.isfinite(hg)) and err < 2e-6

@@ -306,6 +306,12 @@ def test_knn_brute_force_vs_kdtree(orc):
     h = orc.knn_h(X[:, 0], X[:, 1], X[:, 2], 32)
     d, _ = cKDTree(X).query(X, k=33)
     assert np.allclose(h, d[:, 32], rtol=1e-14, atol=0)
+    # the query-subset form (used on samples of large sets) against the same tree
+    q = rng.choice(len(X), 40, replace=False)
+    for k in (1, 7, 32, 64):
+        hq = orc.knn_h_query(q, X[:, 0], X[:, 1], X[:, 2], k)
+        dq, _ = cKDTree(X).query(X[q], k=k + 1)
+        assert np.allclose(hq, dq[:, k], rtol=1e-14, atol=0), k
 
 
 def test_pp_weights_sum_to_one_and_sign(orc, params):
