@@ -73,7 +73,7 @@ def footprint_pixel_count(cat_dev, sol, st, bp, npix, pix):
     return int(total.item())
 
 
-def cpu_baseline(sample_n=60, seed=102):
+def cpu_baseline(sample_n=400, seed=102):
     """The FP64 oracle, single-threaded, on a fixed random sample of the same catalogue."""
     import numpy as np
 
@@ -118,13 +118,17 @@ def timed(fn, steps, warmup, bp=None):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def map_errors(g, o):
-    """Integrated-Y error and per-pixel relative errors |g-o| / (|o| + 1e-6 max|o|)."""
+def map_errors(g, o, scale=None):
+    """Errors of map g against map o: the integrated error |sum g - sum o| / sum scale and the
+    per-pixel |g - o| / (scale + 1e-6 max scale), with scale = |o| by default.  For a kSZ map,
+    whose halo contributions of both signs cancel, scale is the map of |contributions| (the same
+    paste with |v|)."""
     g64, o64 = g.double(), o.double()
-    rel = (g64 - o64).abs() / (o64.abs() + 1e-6 * o64.abs().max())
+    sc = o64.abs() if scale is None else scale.double()
+    rel = (g64 - o64).abs() / (sc + 1e-6 * sc.max())
     q = rel.flatten()
     q = q[torch_quantile_sample(q)]
-    return {"integrated_Y_err": float(abs(g64.sum() / o64.sum() - 1)), "pixel_max": float(rel.max()),
+    return {"integrated_err": float(abs(g64.sum() - o64.sum()) / sc.sum()), "pixel_max": float(rel.max()),
             "pixel_median": float(q.median()), "pixel_p99": float(q.quantile(0.99))}
 
 
@@ -182,8 +186,16 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
                          steps)
     bp._lib.bp_profiling(0)
     print(f"# surrogate path: {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    # scale of the kSZ map: the exact paste with |v| (outside the timed region)
+    vabs = d["v_los"].abs()
+    yabs = torch.zeros_like(ye)
+    babs = torch.zeros_like(ye)
+    sol, st = bp.icm_solve(params, d["M"], d["c"], d["z"])
+    tab, meta = bp.profile_tables(params, sol, st)
+    bp.hp_paste_flat(params, npix, pix, d["theta_x"], d["theta_y"], vabs, sol, st, tab, meta, yabs, babs, ws=ws)
+    del sol, st, tab, meta, yabs
     err_y = map_errors(ys, ye)
-    err_b = map_errors(bs, be)
+    err_b = map_errors(bs, be, babs)
     return {"workload": f"HP flat-sky 5x5 deg, 4096^2 pixels, {n_halos} halos (log10 M in [12.5,15.5], "
                         "dN/dlnM ~ M^-0.9, z in [0.1,1]); surrogate trained on "
                         f"{n_train} exact solves over log10 M in [12.5,15.5], c in [2,15], z in [0.05,3]",
@@ -192,7 +204,70 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
             "speedup": round(ms_exact / ms_sur, 3), "fallback_halos": int(nout[0]),
             "y_err": err_y, "b_err": err_b, "train_s": round(train_s, 1), "train_steps": train_steps,
             "train_loss": hist[-1][1] if hist else None,
-            "kernel_ms_exact": k_exact, "kernel_ms_surrogate": k_sur, "dtype": "bf16 MFMA (fp32 accumulate) + f32 deposit"}
+            "kernel_ms_exact": k_exact, "kernel_ms_surrogate": k_sur,
+            "dtype": "bf16 MFMA (fp32 accumulate) + f32 deposit"}, S
+
+
+def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur):
+    """All-sky HP onto HEALPix RING pixels: n_halos isotropic halos (log10 M in [12.5,15.5] with
+    dN/dlnM ~ M^-0.9, z in [0.01,3]) in device-resident batches, surrogate tables (exact fallback
+    outside the training domain) against the exact solve, both with the FP32 Kahan deposit."""
+    import torch
+
+    from paper_2201_02632_amd.synth import sky_catalogue
+    t0 = time.perf_counter()
+    batches = []
+    for k in range(0, n_halos, batch):
+        cat = sky_catalogue(min(batch, n_halos - k), seed=5000 + k // batch)
+        batches.append({kk: torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous() for kk, v in cat.items()})
+        del cat
+    gen_s = time.perf_counter() - t0
+    print(f"# all-sky: {n_halos} halos in {len(batches)} batches drawn in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    npx = 12 * nside * nside
+    ye = torch.zeros(npx, dtype=torch.float32, device=dev)
+    be = torch.zeros_like(ye)
+    ys = torch.zeros_like(ye)
+    bs = torch.zeros_like(ye)
+    ws = bp.Workspace(dev)
+    nout = [0]
+
+    def exact(vkey="v_los", y=ye, b=be):
+        y.zero_(); b.zero_()
+        for d in batches:
+            sol, st = bp.icm_solve(params, d["M"], d["c"], d["z"])
+            tab, meta = bp.profile_tables(params, sol, st)
+            v = d[vkey] if vkey == "v_los" else d["v_los"].abs()
+            bp.hp_paste_healpix(params, nside, d["theta"], d["phi"], v, sol, st, tab, meta, y, b, ws=ws)
+            del sol, st, tab, meta
+
+    def surrogate():
+        ys.zero_(); bs.zero_()
+        nout[0] = 0
+        for d in batches:
+            nout[0] += sur.paste_healpix(d, nside, ys, bs, ws)
+
+    ms_sur = timed(surrogate, steps, warmup, bp)
+    k_sur = kernel_times(bp, ("MLP_FWD", "SURR_APPLY", "HPX_PLAN", "HPXQ_DEPOSIT", "ICM", "TABLES", "HPX_DEPOSIT"),
+                         steps)
+    print(f"# all-sky surrogate path: {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    ms_exact = timed(exact, steps, warmup, bp)
+    k_exact = kernel_times(bp, ("ICM", "TABLES", "HPX_PLAN", "HPX_DEPOSIT"), steps)
+    bp._lib.bp_profiling(0)
+    print(f"# all-sky exact path: {ms_exact:.1f} ms", file=sys.stderr, flush=True)
+    yabs = torch.zeros_like(ye)
+    babs = torch.zeros_like(ye)
+    exact("abs", yabs, babs)
+    del yabs
+    err_y = map_errors(ys, ye)
+    err_b = map_errors(bs, be, babs)
+    return {"workload": f"all-sky HP, HEALPix N_side {nside} RING ({npx} pixels), {n_halos} halos isotropic on the "
+                        "sphere (log10 M in [12.5,15.5], dN/dlnM ~ M^-0.9, z in [0.01,3]), batches of "
+                        f"{batch}; surrogate tables with exact fallback vs exact solve",
+            "surrogate_halos_per_s": round(n_halos / (ms_sur * 1e-3), 1), "surrogate_ms": round(ms_sur, 2),
+            "exact_halos_per_s": round(n_halos / (ms_exact * 1e-3), 1), "exact_ms": round(ms_exact, 2),
+            "speedup": round(ms_exact / ms_sur, 3), "fallback_halos": int(nout[0]),
+            "y_err": err_y, "b_err": err_b, "kernel_ms_surrogate": k_sur, "kernel_ms_exact": k_exact,
+            "generation_s": round(gen_s, 1)}
 
 
 def pp_section(bp, params, dev, steps, warmup, n_particles):
@@ -253,8 +328,12 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the warmup and timed steps, print per-kernel times and stop (for hardware-counter "
                          "passes under a profiler: no reporting kernels after the steps)")
-    ap.add_argument("--sections", default="surrogate,pp",
-                    help="extra measured sections after the headline one: surrogate, pp (comma list, or none)")
+    ap.add_argument("--sections", default="surrogate,allsky,pp",
+                    help="extra measured sections after the headline one: surrogate, allsky, pp (comma list, or "
+                         "none)")
+    ap.add_argument("--sky-halos", type=int, default=100_000_000)
+    ap.add_argument("--sky-batch", type=int, default=10_000_000)
+    ap.add_argument("--nside", type=int, default=8192)
     ap.add_argument("--extra-steps", type=int, default=2)
     ap.add_argument("--sur-halos", type=int, default=10_000_000)
     ap.add_argument("--sur-train", type=int, default=1_000_000)
@@ -348,9 +427,16 @@ def main():
     del t, y, b, ws, sol, st
     torch.cuda.empty_cache()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
-    if "surrogate" in sections:
-        out["surrogate"] = surrogate_section(bp, params, dev, args.extra_steps, 1, args.sur_halos, args.sur_train,
-                                             args.sur_steps)
+    sur = None
+    if "surrogate" in sections or "allsky" in sections:
+        res, sur = surrogate_section(bp, params, dev, args.extra_steps, 1, args.sur_halos, args.sur_train,
+                                     args.sur_steps)
+        if "surrogate" in sections:
+            out["surrogate"] = res
+        torch.cuda.empty_cache()
+    if "allsky" in sections:
+        out["allsky"] = allsky_section(bp, params, dev, args.extra_steps, 1, args.sky_halos, args.nside,
+                                       args.sky_batch, sur)
         torch.cuda.empty_cache()
     if "pp" in sections:
         out["pp"] = pp_section(bp, params, dev, args.extra_steps, 1, args.pp_particles)

@@ -326,6 +326,12 @@ int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_rad, int64_t
                        const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
                        const float *qtables, const float *meta, float *y_map, float *b_map, void *ws,
                        size_t ws_bytes, size_t *ws_needed, void *stream);
+/* The same for HEALPix RING maps (bp_hp_paste_healpix with surrogate q-tables; same arguments,
+ * layouts, workspace protocol and errors as bp_hp_paste_healpix, tables as bp_hp_paste_flat_q). */
+int bp_hp_paste_healpix_q(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
+                          const double *v_los, const double *sol, const int32_t *status, const float *qtables,
+                          const float *meta, float *y_map, float *b_map, void *ws, size_t ws_bytes,
+                          size_t *ws_needed, void *stream);
 
 /* ------------------------------------------------------------- profiling */
 /* Optional timing of the library's main kernels with HIP events recorded on
@@ -349,6 +355,7 @@ enum {
     BP_PROF_MLP_BWD,        /* K11 surrogate backward */
     BP_PROF_SURR_APPLY,     /* K10 epilogue: tables from the network output */
     BP_PROF_FLATQ_DEPOSIT,  /* K3 deposit from surrogate tables */
+    BP_PROF_HPXQ_DEPOSIT,   /* K4 deposit from surrogate tables */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

@@ -94,6 +94,8 @@ _SIGS = {
     "bp_surrogate_apply": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_hp_paste_healpix_q": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                        _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_surrogate_train_ws_bytes": (C.c_size_t, [C.c_int64]),
     "bp_surrogate_train": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_int64, _VP, _VP, C.c_int64, C.c_int64,
                                      C.c_float, C.c_float, C.c_uint64, C.c_int64, _VP, _VP, C.c_size_t, _VP]),
@@ -102,7 +104,7 @@ _SIGS = {
 }
 PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
                                           "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT", "MLP_FWD", "MLP_BWD",
-                                          "SURR_APPLY", "FLATQ_DEPOSIT"])}
+                                          "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT"])}
 MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
 S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
@@ -213,6 +215,15 @@ def hp_paste_flat_q(params: Params, npix: int, pix_rad: float, theta_x, theta_y,
     _with_workspace(_lib.bp_hp_paste_flat_q, "bp_hp_paste_flat_q", ws,
                     (C.byref(params), int(npix), float(pix_rad), theta_x.numel(), _ptr(theta_x), _ptr(theta_y),
                      _ptr(v_los), _ptr(sol), _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+
+
+def hp_paste_healpix_q(params: Params, nside: int, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map,
+                       ws: Workspace | None = None):
+    """K4 with surrogate q-tables (halos with a non-zero status are skipped)."""
+    ws = ws or _ws_for(y_map.device)
+    _with_workspace(_lib.bp_hp_paste_healpix_q, "bp_hp_paste_healpix_q", ws,
+                    (C.byref(params), int(nside), theta.numel(), _ptr(theta), _ptr(phi), _ptr(v_los), _ptr(sol),
+                     _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
 
 
 def hp_paste_healpix(params: Params, nside: int, theta, phi, v_los, sol, status, tables, meta, y_map, b_map,

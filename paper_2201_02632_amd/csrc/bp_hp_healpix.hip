@@ -124,6 +124,8 @@ __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const ui
     }
 }
 
+// Build records and count pairs.  kQ: tables are the surrogate's q-grid (meta holds only PE0, NE0).
+template <bool kQ>
 __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64_t n, const double *__restrict__ th,
                                                    const double *__restrict__ ph, const double *__restrict__ vlos,
                                                    const double *__restrict__ sol, const int32_t *__restrict__ status,
@@ -156,12 +158,19 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
             double D = shell ? rf * rf - rv * rv : 0.0;
             r.D = (float)D; r.isqD = D > 0.0 ? (float)(1.0 / sqrt(D)) : 0.0f;
             r.r2min = (float)(1e-10 * ra * ra);
-            float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
-            float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
-            float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
-            r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
-            r.om_lo = olo; r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
-            r.ze_lo = zlo; r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+            if (!kQ) {
+                float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
+                float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
+                float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
+                r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
+                r.om_lo = olo;
+                r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
+                r.ze_lo = zlo;
+                r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+            } else {
+                r.eta_lo = (float)Rtu;           // q-grid: R_t in record units and its inverse
+                r.eta_ih = (float)(1.0 / Rtu);
+            }
             double Lcm = L * kMpc / P.h;
             r.amp_y = (float)(kSigmaT / kMeC2 * (double)Mt(BP_META_PE0) * Lcm);
             r.amp_b = (float)(kSigmaT * (double)Mt(BP_META_NE0) * Lcm * (vlos[i] * 1e5 / kC) * exp(-S(BP_SOL_TAU)));
@@ -218,6 +227,7 @@ __device__ inline bool hpx_inside_fp64(double tp, double pp, double th, double p
     return DA * sqrt(cx * cx + cy * cy + cz * cz) < Rt;
 }
 
+template <bool kQ>
 __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
                                                      const float *__restrict__ tables, const uint32_t *__restrict__ vals,
                                                      const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
@@ -277,7 +287,8 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
                 U2 = (float)(R.rf2d - r2d);
             }
             float vp, vn;
-            footprint_value(F, tables + (int64_t)h * BP_TAB_STRIDE, r2, u2, U2, &vp, &vn);
+            if (kQ) footprint_value_q(R, tables + (int64_t)h * 2 * BP_MLP_NQ, r2, U2, &vp, &vn);
+            else footprint_value(F, tables + (int64_t)h * BP_TAB_STRIDE, r2, u2, U2, &vp, &vn);
             kahan_add(ys, yc, R.amp_y * vp);
             kahan_add(bs, bc, R.amp_b * vn);
         }
@@ -289,10 +300,11 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
 
 using namespace bp;
 
-extern "C" int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n, const double *theta,
-                                   const double *phi, const double *v_los, const double *sol, const int32_t *status,
-                                   const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
-                                   size_t ws_bytes, size_t *ws_needed, void *stream) {
+template <bool kQ>
+static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
+                              const double *v_los, const double *sol, const int32_t *status, const float *tables,
+                              const float *meta, float *y_map, float *b_map, void *ws, size_t ws_bytes,
+                              size_t *ws_needed, void *stream) {
     if (!p || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta || !phi || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
@@ -330,8 +342,8 @@ extern "C" int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n,
     if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
     if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_hpx_setup, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status, meta,
-                       roff, rec, cnt, total);
+    hipLaunchKernelGGL(k_hpx_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status,
+                       meta, roff, rec, cnt, total);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long np64 = 0;
     uint32_t ntiles32 = 0;
@@ -372,9 +384,25 @@ extern "C" int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n,
                        (uint32_t)ntiles);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     prof_end(BP_PROF_HPX_PLAN, s);
-    prof_begin(BP_PROF_HPX_DEPOSIT, s);
-    hipLaunchKernelGGL(k_hpx_deposit, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, G, n, rec, tables, vs, tst,
-                       ten, roff, theta, phi, sol, y_map, b_map, (uint32_t)ntiles);
-    prof_end(BP_PROF_HPX_DEPOSIT, s);
+    prof_begin(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
+    hipLaunchKernelGGL(k_hpx_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, G, n, rec, tables, vs,
+                       tst, ten, roff, theta, phi, sol, y_map, b_map, (uint32_t)ntiles);
+    prof_end(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n, const double *theta,
+                                   const double *phi, const double *v_los, const double *sol, const int32_t *status,
+                                   const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
+                                   size_t ws_bytes, size_t *ws_needed, void *stream) {
+    return paste_healpix_impl<false>(p, nside, n, theta, phi, v_los, sol, status, tables, meta, y_map, b_map, ws,
+                                     ws_bytes, ws_needed, stream);
+}
+
+extern "C" int bp_hp_paste_healpix_q(const bp_params *p, int64_t nside, int64_t n, const double *theta,
+                                     const double *phi, const double *v_los, const double *sol,
+                                     const int32_t *status, const float *qtables, const float *meta, float *y_map,
+                                     float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
+    return paste_healpix_impl<true>(p, nside, n, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map, ws,
+                                    ws_bytes, ws_needed, stream);
 }

@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 from . import (MLP_IN, MLP_OUT, S_OUT_OF_DOMAIN, SOL_NFIELDS, META_NFIELDS, MLP_NQ, _check, _lib, _ptr, _stream,
-               Workspace, default_params, hp_paste_flat, hp_paste_flat_q, icm_solve, profile_tables)
+               Workspace, default_params, hp_paste_flat, hp_paste_flat_q, hp_paste_healpix, hp_paste_healpix_q,
+               icm_solve, profile_tables)
 
 
 def _f64(a, dev):
@@ -184,17 +185,33 @@ class Surrogate:
                                        _ptr(st), _ptr(qt), _ptr(meta), _stream()), "bp_surrogate_apply")
         return sol, st, qt, meta
 
-    def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None):
-        """Surrogate HP paste with exact fallback for halos outside the training domain."""
-        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"])
-        hp_paste_flat_q(self.params, npix, pix_rad, cat_dev["theta_x"], cat_dev["theta_y"], cat_dev["v_los"], sol,
-                        st, qt, meta, y_map, b_map, ws)
+    def _fallback(self, cat_dev, st, paste):
+        """Halos the network does not cover (non-zero status) through the exact solve and tables."""
         out = torch.nonzero(st != 0).flatten()
         nout = int(out.numel())
         if nout:
             sub = {k: v.index_select(0, out).contiguous() for k, v in cat_dev.items()}
             s2, st2 = icm_solve(self.params, sub["M"], sub["c"], sub["z"])
             tb2, mt2 = profile_tables(self.params, s2, st2)
-            hp_paste_flat(self.params, npix, pix_rad, sub["theta_x"], sub["theta_y"], sub["v_los"], s2, st2, tb2, mt2,
-                          y_map, b_map, ws)
+            paste(sub, s2, st2, tb2, mt2)
         return nout
+
+    def paste_healpix(self, cat_dev, nside, y_map, b_map, ws: Workspace | None = None):
+        """Surrogate HP paste onto HEALPix RING maps, exact fallback for halos outside the training domain.
+        cat_dev holds M, c, z, theta, phi, v_los."""
+        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"])
+        hp_paste_healpix_q(self.params, nside, cat_dev["theta"], cat_dev["phi"], cat_dev["v_los"], sol, st, qt, meta,
+                           y_map, b_map, ws)
+        del sol, qt, meta
+        return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_healpix(
+            self.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map, ws))
+
+    def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None):
+        """Surrogate HP paste with exact fallback for halos outside the training domain."""
+        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"])
+        hp_paste_flat_q(self.params, npix, pix_rad, cat_dev["theta_x"], cat_dev["theta_y"], cat_dev["v_los"], sol,
+                        st, qt, meta, y_map, b_map, ws)
+        del sol, qt, meta
+        return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_flat(
+            self.params, npix, pix_rad, sub["theta_x"], sub["theta_y"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map,
+            ws))
