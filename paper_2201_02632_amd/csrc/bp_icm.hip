@@ -39,36 +39,53 @@ __device__ inline double binom(int n, int k) {
     return t[n][k];
 }
 
-// Moments mu_k = int_0^{r_f} 4 pi r^2 phi(r)^k dr, k = 0..6, and phi(r_f).
-__device__ void moments(const HaloSolve &H, const GaussRules &G, double xf, double mu[7], double *phif) {
-    for (int k = 0; k < 7; ++k) mu[k] = 0.0;
+// Moments mu_k = int_0^{r_f} 4 pi r^2 phi(r)^k dr, k = 0..6, in pieces.
+// Inner part (r < r_vir): x = r/r_s, integrated in s = ln(1+x) by Gauss-Legendre, accumulated
+// into mu over [Xa, Xb].
+template <int NG>
+__device__ inline void inner_moments(const HaloSolve &H, const double *gx, const double *gw, double Xa, double Xb,
+                                     double mu[7]) {
     const double fourpi = 4.0 * kPi;
-    // inner part: x = r/r_s in [0, X1], substitute s = ln(1+x)
-    double X1 = (xf < 1.0 ? xf : 1.0) * H.c;
-    double S1 = log1p(X1);
-    double rs3 = H.rs * H.rs * H.rs;
-    for (int j = 0; j < 16; ++j) {
-        double s = 0.5 * S1 * (G.x16[j] + 1.0);
-        double x = expm1(s);
+    const double Sa = log1p(Xa), Sb = log1p(Xb), hs = 0.5 * (Sb - Sa);
+    const double rs3 = H.rs * H.rs * H.rs;
+    for (int j = 0; j < NG; ++j) {
+        double x = expm1(Sa + hs * (gx[j] + 1.0));
         double ph = H.cm * nfw_phi_shape(x);
-        double w = 0.5 * S1 * G.w16[j] * fourpi * rs3 * x * x * (1.0 + x);
+        double w = hs * gw[j] * fourpi * rs3 * x * x * (1.0 + x);
         double pk = 1.0;
         for (int k = 0; k < 7; ++k) { mu[k] += w * pk; pk *= ph; }
     }
-    if (xf > 1.0) {  // outer shell r in [r_vir, r_f], substitute t = ln r
-        double t0 = log(H.rv), t1 = log(xf * H.rv);
-        double ht = 0.5 * (t1 - t0);
-        for (int j = 0; j < 16; ++j) {
-            double r = exp(t0 + ht * (G.x16[j] + 1.0));
-            double ph = H.phi_out0 - H.rv / r;
-            double w = ht * G.w16[j] * fourpi * r * r * r;
-            double pk = 1.0;
-            for (int k = 0; k < 7; ++k) { mu[k] += w * pk; pk *= ph; }
+}
+
+// Outer shell r_vir < r < r_f = x_f r_vir (x_f > 1), where phi = A - r_vir/r, A = phi_out0, in closed
+// form: with u = r/r_vir, int 4 pi r^2 (A - 1/u)^k dr = 4 pi r_vir^3 sum_j C(k,j) A^(k-j) (-1)^j L_j,
+// L_j = int_1^{x_f} u^(2-j) du, each written with d = x_f - 1 (exact) so nothing cancels.
+__device__ inline void outer_moments(const HaloSolve &H, double xf, double mu[7]) {
+    const double d = xf - 1.0, q = xf * xf + xf + 1.0, ix = 1.0 / xf;
+    double L[7];
+    L[0] = d * q / 3.0;                    // (x^3 - 1)/3
+    L[1] = 0.5 * d * (xf + 1.0);           // (x^2 - 1)/2
+    L[2] = d;                              // x - 1
+    L[3] = log1p(d);                       // ln x
+    L[4] = d * ix;                         // 1 - 1/x
+    L[5] = 0.5 * d * (xf + 1.0) * ix * ix; // (1 - 1/x^2)/2
+    L[6] = d * q * ix * ix * ix / 3.0;     // (1 - 1/x^3)/3
+    const double c0 = 4.0 * kPi * H.rv * H.rv * H.rv, A = H.phi_out0;
+    double Ap[7];
+    Ap[0] = 1.0;
+    for (int k = 1; k < 7; ++k) Ap[k] = Ap[k - 1] * A;
+    for (int k = 0; k < 7; ++k) {
+        double t = 0.0;
+        for (int j = 0; j <= k; ++j) {
+            double term = binom(k, j) * Ap[k - j] * L[j];
+            t += (j & 1) ? -term : term;
         }
-        *phif = H.phi_out0 - 1.0 / xf;
-    } else {
-        *phif = H.cm * nfw_phi_shape(xf * H.c);
+        mu[k] += c0 * t;
     }
+}
+
+__device__ inline double phi_at(const HaloSolve &H, double xf) {
+    return xf > 1.0 ? H.phi_out0 - 1.0 / xf : H.cm * nfw_phi_shape(xf * H.c);
 }
 
 // I_n(a) = int 4 pi r^2 (1 - a phi)^n dr from the moments; J(a) = int 4 pi r^2 phi (1-a phi)^5 dr.
@@ -116,10 +133,9 @@ __device__ double solve_a(const HaloSolve &H, const double mu[7], double phif, d
 
 struct Trial { double res, a, rho0, P0; };
 
-// Energy residual (Sec. 2.2) at trial x_f; also returns a, rho0, P0.
-__device__ Trial energy_trial(const HaloSolve &H, const GaussRules &G, double xf, double a_guess) {
-    double mu[7], phif;
-    moments(H, G, xf, mu, &phif);
+// Energy residual (Sec. 2.2) at trial x_f from the moments of [0, r_f]; also returns a, rho0, P0.
+__device__ Trial energy_trial(const HaloSolve &H, const double mu[7], double xf, double a_guess) {
+    const double phif = phi_at(H, xf);
     Trial T;
     T.a = solve_a(H, mu, phif, a_guess);
     double I5 = poly_I(mu, 5, T.a), I6 = poly_I(mu, 6, T.a), J5 = poly_J5(mu, T.a);
@@ -150,8 +166,9 @@ __device__ double jeans_I_dev(double x, const GaussRules &G) {
 
 // Closed-form initial energy of matter in [x_lo, c] (without f_b): kinetic part
 // by parts with the Jeans equation, potential part from elementary antiderivatives.
-__device__ double energy_closed(double c, double mc, double A, double xlo, const GaussRules &G) {
-    double kin_b = c * c * c * jeans_I_dev(c, G) - (xlo > 0 ? xlo * xlo * xlo * jeans_I_dev(xlo, G) : 0.0);
+// Ic = jeans_I_dev(c), shared by the callers.
+__device__ double energy_closed(double c, double mc, double A, double xlo, double Ic, const GaussRules &G) {
+    double kin_b = c * c * c * Ic - (xlo > 0 ? xlo * xlo * xlo * jeans_I_dev(xlo, G) : 0.0);
     double K = 0.5 * A * (kin_b + kin_prim(c) - kin_prim(xlo));
     auto wprim = [&](double x) { return -log1p(x) / (1.0 + x) - 1.0 / (1.0 + x) - nfw_m(x) / (1.0 + c); };
     double W = -A * (wprim(c) - wprim(xlo));
@@ -267,9 +284,10 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
     H.V2 = kGastro * M / rv;
     H.Mg = fb * M - Mstar;
     double A = kGastro * (M / mc) * (M / mc) / rs;  // G M0^2 / r_s
-    H.Ps = fb * 4.0 * kPi * kGastro * rhos * rhos * rs * rs * jeans_I_dev(c, G);
-    H.Egi = fb * energy_closed(c, mc, A, xs, G);
-    double EDM = energy_closed(c, mc, A, 0.0, G);
+    const double Ic = jeans_I_dev(c, G);
+    H.Ps = fb * 4.0 * kPi * kGastro * rhos * rhos * rs * rs * Ic;
+    H.Egi = fb * energy_closed(c, mc, A, xs, Ic, G);
+    double EDM = energy_closed(c, mc, A, 0.0, Ic, G);
     H.Einj = P.eps_DM * fabs(EDM) + P.eps_star * Mstar * kCkms * kCkms;
     H.phi_out0 = c * c / ((1.0 + c) * mc);
     H.cm = c / mc;
@@ -283,24 +301,64 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
     S(BP_SOL_EGI) = H.Egi * u_mass * 1e10;
 
     // --- scan x_f, then Brent on the first sign change ---
+    // Moments of [0, r_f]: the inner part is carried along the increasing scan points up to
+    // x_f = 1 (GL16 on the first piece, GL8 on each step), frozen at r_vir beyond, where the
+    // outer shell has a closed form.  A Brent trial starts from the moments at its bracket's
+    // lower end.
+    double mu_cur[7] = {0, 0, 0, 0, 0, 0, 0}, x_cur = 0.4;
+    inner_moments<16>(H, G.x16, G.w16, 0.0, 0.4 * c, mu_cur);
+    double mu_vir[7];
+    bool have_vir = false;
+    auto moments_at = [&](const double base[7], double xbase, double xf, double mu[7]) {
+        if (xf <= 1.0) {
+            for (int k = 0; k < 7; ++k) mu[k] = base[k];
+            if (xf > xbase) inner_moments<8>(H, G.x8, G.w8, xbase * c, xf * c, mu);
+        } else {
+            if (!have_vir) {
+                for (int k = 0; k < 7; ++k) mu_vir[k] = mu_cur[k];
+                if (x_cur < 1.0) inner_moments<8>(H, G.x8, G.w8, x_cur * c, c, mu_vir);
+                have_vir = true;
+            }
+            for (int k = 0; k < 7; ++k) mu[k] = mu_vir[k];
+            outer_moments(H, xf, mu);
+        }
+    };
     double xprev = 0.0, rprev = 0.0, aprev = 0.0;
     double bx0 = 0.0, bx1 = 0.0, br0 = 0.0, br1 = 0.0, ba = 0.0;
+    double mu_prev[7] = {0, 0, 0, 0, 0, 0, 0}, mu_b[7] = {0, 0, 0, 0, 0, 0, 0};
     int nchg = 0;
     double aguess = 0.0;
     for (int k = 0; k < NSCAN; ++k) {
         double xf = 0.4 + (5.0 - 0.4) * k / (NSCAN - 1);
-        Trial T = energy_trial(H, G, xf, aguess);
+        double mu[7];
+        if (xf <= 1.0) {
+            moments_at(mu_cur, x_cur, xf, mu);
+            for (int q = 0; q < 7; ++q) mu_cur[q] = mu[q];
+            x_cur = xf;
+        } else {
+            moments_at(mu_cur, x_cur, xf, mu);
+        }
+        Trial T = energy_trial(H, mu, xf, aguess);
         aguess = T.a;
         if (!isfinite(T.res)) { st |= BP_S_NONFINITE; break; }
         if (k > 0 && ((rprev < 0) != (T.res < 0))) {
-            if (nchg == 0) { bx0 = xprev; bx1 = xf; br0 = rprev; br1 = T.res; ba = aprev; }
+            if (nchg == 0) {
+                bx0 = xprev; bx1 = xf; br0 = rprev; br1 = T.res; ba = aprev;
+                for (int q = 0; q < 7; ++q) mu_b[q] = mu_prev[q];
+            }
             ++nchg;
         }
         xprev = xf; rprev = T.res; aprev = T.a;
+        for (int q = 0; q < 7; ++q) mu_prev[q] = mu[q];
     }
     if (!st && nchg == 0) st |= BP_S_NO_BRACKET;
     if (st) { status[i] = st; return; }
     if (nchg > 1) st |= BP_S_MULTI_ROOT;
+    auto trial_at = [&](double xf, double ag) {
+        double mu[7];
+        moments_at(mu_b, bx0, xf, mu);
+        return energy_trial(H, mu, xf, ag);
+    };
     // Brent's method (bisection / secant / inverse quadratic interpolation)
     double a = bx0, b = bx1, fa = br0, fbv = br1, cc = a, fc = fa, d = b - a, e = d;
     double xtol = 1e-13 * bx0, aguess2 = ba;
@@ -324,12 +382,12 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
         } else { d = m; e = m; }
         a = b; fa = fbv;
         b += (fabs(d) > tol) ? d : (m > 0 ? tol : -tol);
-        Trial T = energy_trial(H, G, b, aguess2);
+        Trial T = trial_at(b, aguess2);
         aguess2 = T.a;
         fbv = T.res;
     }
     double xf = b;
-    Trial T = energy_trial(H, G, xf, aguess2);
+    Trial T = trial_at(xf, aguess2);
     S(BP_SOL_A) = T.a;
     S(BP_SOL_XF) = xf;
     S(BP_SOL_RF) = xf * rv;
@@ -579,6 +637,7 @@ const GaussRules &gauss_rules() {
         gauss_legendre(16, G.x16, G.w16);
         gauss_legendre(24, G.x24, G.w24);
         gauss_legendre(12, G.x12, G.w12);
+        gauss_legendre(8, G.x8, G.w8);
         for (int j = 0; j < 16; ++j) G.u16[j] = (float)(0.5 * (G.x16[j] + 1.0));
         for (int j = 0; j < 24; ++j) G.u24[j] = (float)(0.5 * (G.x24[j] + 1.0));
         for (int j = 0; j < 12; ++j) G.u12[j] = (float)(0.5 * (G.x12[j] + 1.0));
