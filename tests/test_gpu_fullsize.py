@@ -152,3 +152,64 @@ def test_pp_fullsize_sampled_smoothing_lengths(bp, orc):
         print(f"box L={L}: {len(cand)} candidates, {len(q)} queries, h {ho.min():.3g}-{ho.max():.3g} Mpc/h, "
               f"max rel err {err:.2e}", flush=True)
         assert np.all(np.isfinite(hg)) and err < 2e-6
+
+
+def test_hp_healpix_fullsize_sampled_pixels(bp, orc):
+    """All-sky HP at N_side 8192 (805M RING pixels): the first 1e7-halo batch of the all-sky benchmark
+    (z in [0.01, 3]) pasted by the exact path, checked at sampled pixels (random, the pixel under the
+    largest footprint's centre, the first pixel of the first ring and of an equatorial ring)."""
+    import torch
+
+    from paper_2201_02632_amd.synth import sky_catalogue, subsample
+    nside = 8192
+    cat = sky_catalogue(10_000_000, seed=5000)
+    dev = torch.device("cuda")
+    t = {k: torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous() for k, v in cat.items()}
+    params = bp.default_params()
+    npx = 12 * nside * nside
+    y = torch.zeros(npx, dtype=torch.float32, device=dev)
+    b = torch.zeros_like(y)
+    sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
+    tab, meta = bp.profile_tables(params, sol, st)
+    bp.hp_paste_healpix(params, nside, t["theta"], t["phi"], t["v_los"], sol, st, tab, meta, y, b, ws=bp.Workspace(dev))
+    torch.cuda.synchronize()
+    del sol, tab, meta
+    # reach bound per halo, as for the flat map (z up to 3)
+    om = 0.3
+    zz = np.linspace(0.0, 3.2, 320001)
+    f = 1.0 / np.sqrt(om * (1 + zz) ** 3 + 1 - om)
+    chi = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(zz))]) * 2997.92458
+    DA_low = 0.999 * np.interp(cat["z"], zz, chi) / (1 + cat["z"])
+    rho_c = 2.775e11 * (om * (1 + cat["z"]) ** 3 + 1 - om)
+    bound = np.minimum(3.0 * (3 * cat["M"] / (4 * math.pi * 500.0 * rho_c)) ** (1.0 / 3.0) / DA_low, 1.5)
+    rng = np.random.default_rng(22)
+    pix = list(rng.integers(0, npx, 6))
+    big = int(np.argmax(bound))
+    pix.append(int(orc.ang2pix_ring(nside, [cat["theta"][big]], [cat["phi"][big]])[0]))
+    pix += [0, 2 * nside * (nside - 1) + 4 * nside * nside]      # ring 1 start; an equatorial ring start
+    pix = np.array(pix, dtype=np.int64)
+    pth, pph = orc.pix2ang_ring(nside, pix)
+    st_np = st.cpu().numpy()
+    cand = np.zeros(len(cat["M"]), dtype=bool)
+    st_ok = (st_np & ~2) == 0
+    sth, cth = np.sin(cat["theta"]), np.cos(cat["theta"])
+    for a, ph in zip(pth, pph):
+        cosd = np.sin(a) * sth * np.cos(cat["phi"] - ph) + np.cos(a) * cth
+        cand |= np.arccos(np.clip(cosd, -1.0, 1.0)) < 1.01 * bound
+    cand &= st_ok
+    idx = np.nonzero(cand)[0]
+    print(f"oracle: {len(idx)} candidate halos for {len(pix)} pixels", flush=True)
+    sub = subsample(cat, idx)
+    p = orc.default_params()
+    halos = orc.solve_halos(p, sub["M"], sub["c"], sub["z"])
+    oy, ob = orc.hp_healpix_pixels(p, halos, sub, nside, pix)
+    _, obabs = orc.hp_healpix_pixels(p, halos, dict(sub, v_los=np.abs(sub["v_los"])), nside, pix)
+    gy = y[torch.as_tensor(pix, device=dev)].cpu().numpy().astype(np.float64)
+    gb = b[torch.as_tensor(pix, device=dev)].cpu().numpy().astype(np.float64)
+    scale_y = np.abs(oy).max()
+    ey = np.abs(gy - oy) / (np.abs(oy) + 1e-6 * scale_y)
+    eb = np.abs(gb - ob) / (obabs + 1e-6 * max(obabs.max(), 1e-300))
+    for k in range(len(pix)):
+        print(f"pix {pix[k]}: y {gy[k]:.6e} oracle {oy[k]:.6e} rel {ey[k]:.2e}  b rel {eb[k]:.2e}")
+    assert oy[6] > 0, "the largest footprint's centre pixel must be covered"
+    assert ey.max() < 1e-5 and eb.max() < 1e-5
