@@ -296,6 +296,12 @@ int bp_surrogate_targets(const bp_params *p, int64_t n, const double *sol, const
 int bp_surrogate_stats(int64_t n, const float *targets, float *mean, float *std, void *stream);
 /* Gather rows: out[i] = in[idx[i]] (cols floats per row). */
 int bp_gather_rows(int64_t n, int32_t cols, const float *in, const int64_t *idx, float *out, void *stream);
+/* Inference-only forward pass (same network and arithmetic as bp_mlp_forward, all four layers in
+ * one kernel, activations kept on chip; nothing but y is written).
+ *   w, w_bf16 : device parameters as for bp_mlp_forward;  x : device [n][BP_MLP_IN] floats
+ *   y         : device [n][BP_MLP_OUT] floats, OUTPUT, 16-byte aligned
+ * Returns BP_E_ARG for null or misaligned pointers. */
+int bp_mlp_infer(const float *w, const uint16_t *w_bf16, int64_t n, const float *x, float *y, void *stream);
 /* Weighted MSE over the 131 used outputs against standardised targets, weight
  * w_c = 1 for the 128 table entries and 16 for each of ln x_f, ln(P_e0/P_s),
  * ln(n_e0/n_scale):  dy = 2 w_c (y - (t - mean)/std) / (n * sum_c w_c);

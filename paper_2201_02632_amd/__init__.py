@@ -92,6 +92,7 @@ _SIGS = {
     "bp_gather_rows": (C.c_int, [C.c_int64, C.c_int32, _VP, _VP, _VP, _VP]),
     "bp_surrogate_mse": (C.c_int, [C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_surrogate_apply": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_mlp_infer": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP, _VP]),
     "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_hp_paste_healpix_q": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,

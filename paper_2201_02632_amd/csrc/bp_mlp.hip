@@ -22,18 +22,15 @@ namespace bp {
 typedef short sx4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
 
-// round-to-nearest-even FP32 -> BF16 (NaN kept quiet)
-__device__ inline uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// round-to-nearest-even FP32 -> BF16 (gfx950 converts in hardware, v_cvt_pk_bf16_f32)
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware exponential and reciprocal (about 1 ulp each)
+__device__ inline float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigmoid(z); }
 __device__ inline float dsilu(float z) {
-    float s = 1.0f / (1.0f + __expf(-z));
+    float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -295,6 +292,143 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
     r = launch_gemm(EPI_BIAS, g, 1, s);
     prof_end(BP_PROF_MLP_FWD, s);
     return r;
+}
+
+// ------------------------------------------------------------ fused inference --
+// All four layers for a block of 64 rows in one kernel; activations never leave the CU.
+// Each layer is computed transposed, out^T = W h^T: the weights are the MFMA A operand and the
+// activations the B operand.  With v_mfma_f32_16x16x16bf16 a lane's accumulator holds outputs
+// (4 (l/16) + j, l % 16) of a 16x16 block, i.e. four consecutive features of one row -- the same
+// (k, n) positions it reads as B of the next layer -- so each wavefront keeps its 16 rows'
+// activations in its own LDS rows (BF16, written by the epilogue, read as B fragments) and never
+// needs a transpose.  The weights stream through LDS in 16-column k-slices, double-buffered and
+// shared by the four wavefronts.  The k order of every sum is that of bp_mlp_forward.
+constexpr int kFR = 16;                 // rows per wavefront
+constexpr int kFBM = 4 * kFR;           // rows per workgroup
+constexpr int kFKB = BP_MLP_HID / 16;   // 16-wide k slices of a hidden-layer input
+constexpr int kFLd = 20;                // LDS row stride of a weight k-slice in bf16 (16 + 4)
+constexpr int kFALd = BP_MLP_HID + 4;   // LDS row stride of the activations in bf16 (256 + 4)
+
+__device__ inline sx4 pack_bf4(float a, float b, float c, float d) {
+    sx4 r;
+    r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
+    return r;
+}
+
+// One layer: acc[ob] = sum_k W[16 ob + .][k] h[row][k] over the wavefront's 16 rows (held in act).
+template <int NOB>
+__device__ inline void fused_layer(const uint16_t *__restrict__ W, const uint16_t *__restrict__ act,
+                                   fx4 (&acc)[NOB], uint16_t *__restrict__ wsl, int t, int lane) {
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob) acc[ob] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+    constexpr int kRows = NOB * 16;                  // weight rows (output features)
+    constexpr int kBuf = BP_MLP_HID * kFLd;          // one k slice, room for 256 rows
+    // thread t < kRows moves row t of a k slice: 16 bf16 = two 16-byte loads
+    uint4 st0 = {0, 0, 0, 0}, st1 = {0, 0, 0, 0};
+    auto fetch = [&](int kb) {
+        if (t < kRows) {
+            const uint4 *src = (const uint4 *)(W + (int64_t)t * BP_MLP_HID + kb * 16);
+            st0 = src[0]; st1 = src[1];
+        }
+    };
+    auto put = [&](int buf) {
+        if (t < kRows) {
+            uint2 *dst = (uint2 *)(wsl + buf * kBuf + t * kFLd);
+            dst[0] = uint2{st0.x, st0.y}; dst[1] = uint2{st0.z, st0.w};
+            dst[2] = uint2{st1.x, st1.y}; dst[3] = uint2{st1.z, st1.w};
+        }
+    };
+    fetch(0);
+    put(0);
+    __syncthreads();
+    const uint16_t *bsrc = act + (lane & 15) * kFALd + 4 * (lane >> 4);
+    for (int kb = 0; kb < kFKB; ++kb) {
+        if (kb + 1 < kFKB) fetch(kb + 1);
+        const sx4 bfr = *(const sx4 *)(bsrc + 16 * kb);
+        const uint16_t *sl = wsl + (kb & 1) * kBuf + (lane & 15) * kFLd + 4 * (lane >> 4);
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob) {
+            const sx4 a = *(const sx4 *)(sl + ob * 16 * kFLd);
+            acc[ob] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr, acc[ob], 0, 0, 0);
+        }
+        if (kb + 1 < kFKB) put((kb + 1) & 1);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_infer(int64_t n, const float *__restrict__ w,
+                                                   const uint16_t *__restrict__ wb, const float *__restrict__ x,
+                                                   float *__restrict__ y, int64_t oW1, int64_t ob1, int64_t oW2,
+                                                   int64_t ob2, int64_t oW3, int64_t ob3, int64_t oW4, int64_t ob4) {
+    __shared__ __attribute__((aligned(16))) uint16_t wsl[2 * BP_MLP_HID * kFLd];
+    __shared__ __attribute__((aligned(16))) uint16_t acts[4 * kFR * kFALd];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint16_t *act = acts + wv * kFR * kFALd;
+    const int64_t row = (int64_t)blockIdx.x * kFBM + wv * kFR + (lane & 15);
+    // this lane's slot in the activation rows: row l%16, features 4 (l/16) + 16 kb .. + 3
+    uint16_t *aslot = act + (lane & 15) * kFALd + 4 * (lane >> 4);
+    // layer 1 (FP32)
+    {
+        const float *W1 = w + oW1, *b1 = w + ob1;
+        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+        if (row < n) { x0 = x[row * BP_MLP_IN]; x1 = x[row * BP_MLP_IN + 1]; x2 = x[row * BP_MLP_IN + 2]; }
+        for (int kb = 0; kb < kFKB; ++kb) {
+            float h[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = 16 * kb + 4 * (lane >> 4) + j;
+                float z = b1[o];
+                z += W1[o * BP_MLP_IN] * x0;
+                z += W1[o * BP_MLP_IN + 1] * x1;
+                z += W1[o * BP_MLP_IN + 2] * x2;
+                h[j] = silu(z);
+            }
+            *(sx4 *)(aslot + 16 * kb) = pack_bf4(h[0], h[1], h[2], h[3]);
+        }
+    }
+    // hidden layers 2 and 3
+    fx4 acc[kFKB];
+    for (int layer = 0; layer < 2; ++layer) {
+        const uint16_t *W = wb + (layer == 0 ? oW2 : oW3);
+        const float *bias = w + (layer == 0 ? ob2 : ob3);
+        fused_layer<kFKB>(W, act, acc, wsl, t, lane);
+#pragma unroll
+        for (int ob = 0; ob < kFKB; ++ob) {
+            const int o = 16 * ob + 4 * (lane >> 4);
+            const fx4 v = acc[ob];
+            *(sx4 *)(aslot + 16 * ob) = pack_bf4(silu(v[0] + bias[o]), silu(v[1] + bias[o + 1]),
+                                                 silu(v[2] + bias[o + 2]), silu(v[3] + bias[o + 3]));
+        }
+    }
+    // output layer (144 features = 9 blocks)
+    constexpr int kOB = BP_MLP_OUT / 16;
+    fx4 out[kOB];
+    fused_layer<kOB>(wb + oW4, act, out, wsl, t, lane);
+    if (row < n) {
+        const float *b4 = w + ob4;
+#pragma unroll
+        for (int ob = 0; ob < kOB; ++ob) {
+            const int o = 16 * ob + 4 * (lane >> 4);
+            const fx4 v = out[ob];
+            *(float4 *)(y + row * BP_MLP_OUT + o) = float4{v[0] + b4[o], v[1] + b4[o + 1], v[2] + b4[o + 2],
+                                                           v[3] + b4[o + 3]};
+        }
+    }
+}
+
+extern "C" int bp_mlp_infer(const float *w, const uint16_t *wb, int64_t n, const float *x, float *y, void *stream) {
+    if (n < 0 || !w || !wb || !x || !y) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if ((((uintptr_t)y) & 15) || (((uintptr_t)wb) & 15)) return BP_E_ARG;   // 16-byte vector access
+    const int64_t blocks = (n + kFBM - 1) / kFBM;
+    if (blocks > 0x7fffffffLL) return BP_E_OVERFLOW;
+    hipStream_t s = (hipStream_t)stream;
+    Off o = offsets();
+    prof_begin(BP_PROF_MLP_FWD, s);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, s, n, w, wb, x, y, o.W1, o.b1, o.W2, o.b2,
+                       o.W3, o.b3, o.W4, o.b4);
+    prof_end(BP_PROF_MLP_FWD, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
 // split-K factor of the weight-gradient GEMMs (K = batch): about 128 rows per slice, so that a

@@ -102,15 +102,11 @@ class Surrogate:
                "bp_mlp_forward")
         return y, act
 
-    def predict(self, x, chunk=1 << 20):
-        """Network outputs for many rows, in chunks that share one activation buffer."""
+    def predict(self, x):
+        """Network outputs for many rows: the fused inference kernel (no activations stored)."""
         n = x.shape[0]
         y = torch.empty((n, MLP_OUT), dtype=torch.float32, device=self.dev)
-        act = torch.empty(int(_lib.bp_mlp_act_bytes(min(n, chunk))), dtype=torch.uint8, device=self.dev)
-        for s0 in range(0, n, chunk):
-            k = min(chunk, n - s0)
-            _check(_lib.bp_mlp_forward(_ptr(self.w), _ptr(self.wb), k, _ptr(x[s0:s0 + k]), _ptr(y[s0:s0 + k]),
-                                       _ptr(act), _stream()), "bp_mlp_forward")
+        _check(_lib.bp_mlp_infer(_ptr(self.w), _ptr(self.wb), n, _ptr(x), _ptr(y), _stream()), "bp_mlp_infer")
         return y
 
     def backward(self, x, act, dy, ws=None):
