@@ -139,7 +139,7 @@ def torch_quantile_sample(q, n=1 << 22):
     return torch.arange(0, q.numel(), step, device=q.device)
 
 
-def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_steps):
+def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_steps, profile_pass=False):
     """Surrogate vs exact HP paste of the same catalogue: 4096^2 pixels over 5x5 deg, the 5e5-halo
     recipe scaled to n_halos.  The network is trained first (exact solves of n_train halos over the
     training domain, then Adam on the GPU)."""
@@ -152,7 +152,8 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
     tr = surrogate_training(n_train, seed=4)
     x, t = S.training_set(tr["M"], tr["c"], tr["z"])
     S.set_stats(t)
-    hist = S.fit(x, t, steps=train_steps, batch=4096, lr=2e-3, lr_end=1e-5, log_every=max(train_steps // 4, 1))
+    hist = S.fit(x, t, steps=train_steps, batch=4096, lr=2e-3, lr_end=1e-5,
+                 log_every=0 if profile_pass else max(train_steps // 4, 1))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del x, t
@@ -186,6 +187,9 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
                          steps)
     bp._lib.bp_profiling(0)
     print(f"# surrogate path: {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    if profile_pass:
+        return {"exact_ms": round(ms_exact, 2), "surrogate_ms": round(ms_sur, 2), "kernel_ms_exact": k_exact,
+                "kernel_ms_surrogate": k_sur}, S
     # scale of the kSZ map: the exact paste with |v| (outside the timed region)
     vabs = d["v_los"].abs()
     yabs = torch.zeros_like(ye)
@@ -208,7 +212,7 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
             "dtype": "bf16 MFMA (fp32 accumulate) + f32 deposit"}, S
 
 
-def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur):
+def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, profile_pass=False):
     """All-sky HP onto HEALPix RING pixels: n_halos isotropic halos (log10 M in [12.5,15.5] with
     dN/dlnM ~ M^-0.9, z in [0.01,3]) in device-resident batches, surrogate tables (exact fallback
     outside the training domain) against the exact solve, both with the FP32 Kahan deposit."""
@@ -254,6 +258,9 @@ def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur):
     k_exact = kernel_times(bp, ("ICM", "TABLES", "HPX_PLAN", "HPX_DEPOSIT"), steps)
     bp._lib.bp_profiling(0)
     print(f"# all-sky exact path: {ms_exact:.1f} ms", file=sys.stderr, flush=True)
+    if profile_pass:
+        return {"exact_ms": round(ms_exact, 2), "surrogate_ms": round(ms_sur, 2), "kernel_ms_exact": k_exact,
+                "kernel_ms_surrogate": k_sur}
     yabs = torch.zeros_like(ye)
     babs = torch.zeros_like(ye)
     exact("abs", yabs, babs)
@@ -326,8 +333,8 @@ def main():
     ap.add_argument("--n-halos", type=int, default=500_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
-                    help="run the warmup and timed steps, print per-kernel times and stop (for hardware-counter "
-                         "passes under a profiler: no reporting kernels after the steps)")
+                    help="run the warmup and timed steps of each section, print per-kernel times and stop (for "
+                         "hardware-counter passes under a profiler: no error maps or other reporting kernels)")
     ap.add_argument("--sections", default="surrogate,allsky,pp",
                     help="extra measured sections after the headline one: surrogate, allsky, pp (comma list, or "
                          "none)")
@@ -392,8 +399,22 @@ def main():
         kt[name] = tot.value / max(cnt.value, 1)
     bp._lib.bp_profiling(0)
     if args.profile_pass:
-        print(json.dumps({"profile_pass": True, "ms_per_step": round(ms, 3),
-                          "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}), flush=True)
+        res = {"profile_pass": True, "ms_per_step": round(ms, 3), "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}
+        del t, y, b, ws, sol, st
+        torch.cuda.empty_cache()
+        secs = [x for x in args.sections.split(",") if x and x != "none"]
+        if "surrogate" in secs or "allsky" in secs:
+            r, sur = surrogate_section(bp, params, dev, args.extra_steps, 1, args.sur_halos, args.sur_train,
+                                       args.sur_steps, profile_pass=True)
+            res["surrogate"] = r
+            torch.cuda.empty_cache()
+            if "allsky" in secs:
+                res["allsky"] = allsky_section(bp, params, dev, args.extra_steps, 1, args.sky_halos, args.nside,
+                                               args.sky_batch, sur, profile_pass=True)
+                torch.cuda.empty_cache()
+        if "pp" in secs:
+            res["pp"] = pp_section(bp, params, dev, args.extra_steps, 1, args.pp_particles)
+        print(json.dumps(res), flush=True)
         return
     nsolved = int((st == 0).sum().item())
     nfp = footprint_pixel_count(t, sol, st, bp, npix, pix)

@@ -31,9 +31,10 @@ struct __attribute__((aligned(16))) HpxRec {
     int32_t flags;          // bit0 shell, bit1 zone B, bit2 valid
     float hmax;             // haversine bound used by count and emit (same value in both)
     double ra2d, rf2d;      // r_a^2, r_f^2 in FP64 (edge-annulus recompute)
+    double sh2, ch2;        // sin and cos of half the colatitude
     float pad[2];
 };
-static_assert(sizeof(HpxRec) == 128, "HpxRec size");
+static_assert(sizeof(HpxRec) == 144, "HpxRec size");
 
 struct HpxGeom {
     int64_t N;          // nside
@@ -150,6 +151,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
             double rv = S(BP_SOL_RVIR) * inv, rf = S(BP_SOL_RF) * inv, ra = fmin(rv, rf), Rtu = Rt * inv;
             p = p - 2.0 * kPi * floor(p / (2.0 * kPi));
             r.th = t; r.ph = p; r.sth = sin(t);
+            r.sh2 = sin(0.5 * t); r.ch2 = cos(0.5 * t);
             r.Rt2 = (float)(Rtu * Rtu);
             r.ra = (float)ra; r.ra2 = (float)(ra * ra); r.rv2 = (float)(rv * rv);
             r.rf = (float)rf; r.rf2 = (float)(rf * rf);
@@ -254,8 +256,9 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
     const bool valid = jl < npr;
     const int64_t pix = poff + jl;
     // pixel-centre longitude as the pixelisation defines it: (pi/2)/(npr/4) * (j - shift), j = jl + 1
-    const double phj = 1.5707963267948966 / (double)(npr / 4) * ((double)(jl + 1) - sh);
-    const double sthr = sin(thr);
+    const double step = 1.5707963267948966 / (double)(npr / 4);
+    const double phj = step * ((double)(jl + 1) - sh);
+    const double sthr = sin(thr), st2 = sin(0.5 * thr), ct2 = cos(0.5 * thr);
     const float inv_pix2 = (float)(1.0 / (G.pixang * G.pixang));
     float ys = valid ? ymap[pix] : 0.0f, bs = valid ? bmap[pix] : 0.0f, yc = 0.0f, bc = 0.0f;
     for (uint32_t p = p0; p < p1; ++p) {
@@ -263,11 +266,19 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
         if (h >= (uint32_t)n) continue;
         const HpxRec &R = rec[h];
         const FootRec F = foot_uniform(R);
-        const double sd = sin(0.5 * (thr - R.th));
+        // haversine of the angle to the halo: hv = sin^2(dtheta/2) + sin(theta_r) sin(theta_h) sin^2(dphi/2),
+        // sin(dtheta/2) from the half-angle sines and cosines (wave-uniform)
+        const double sd = st2 * R.ch2 - ct2 * R.sh2;
         const float A = (float)(sd * sd), B = (float)(sthr * R.sth);
-        double dph = phj - R.ph;                    // wrap to [-pi, pi] before rounding to FP32
+        // dphi wrapped to [-pi, pi] in FP64 before it is rounded to FP32 (a small angle must not be
+        // carried as 2 pi minus itself)
+        double dph = phj - R.ph;
         dph = (dph > kPi) ? dph - 2.0 * kPi : ((dph < -kPi) ? dph + 2.0 * kPi : dph);
-        const float s = sinf(0.5f * (float)dph);
+        const float xh = (float)(0.5 * dph);
+        const float x2 = xh * xh;
+        // sin(x) by its odd series below |x| = 0.1 (error < 2e-11 relative), sinf above
+        const float s = (fabsf(xh) < 0.1f) ? xh * (1.0f + x2 * (-1.0f / 6.0f + x2 * (1.0f / 120.0f - x2 * (1.0f / 5040.0f))))
+                                           : sinf(xh);
         const float hv = A + B * s * s;
         const float r2 = 4.0f * hv * (1.0f - hv) * inv_pix2;
         bool in = (hv < 0.5f) && (r2 < R.Rt2);
