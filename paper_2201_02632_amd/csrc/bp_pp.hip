@@ -97,39 +97,45 @@ __global__ void __launch_bounds__(256) k_pp_positions(int64_t n, const float *__
                                                       const float *__restrict__ zz, const double *__restrict__ chi_t,
                                                       double *__restrict__ pos, unsigned long long *__restrict__ bbox,
                                                       int *__restrict__ bad) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double X = 0, Y = 0, Z = 0;
-    bool ok = false;
-    if (i < n) {
+    // grid-stride over particles with a capped grid, so the bounding box costs one atomic per block and axis
+    unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+    int nbad = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double z = zz[i];
-        ok = z >= 0.0 && z < kZmax - 0.01 && isfinite((double)tx[i]) && isfinite((double)ty[i]);
+        double X = 0, Y = 0, Z = 0;
+        const bool ok = z >= 0.0 && z < kZmax - 0.01 && isfinite((double)tx[i]) && isfinite((double)ty[i]);
         if (ok) {
             double chi = table_interp(chi_t, z);
             X = chi * (double)tx[i]; Y = chi * (double)ty[i]; Z = chi;
+            const unsigned long long o[3] = {dbl_order(X), dbl_order(Y), dbl_order(Z)};
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = o[a] < lo[a] ? o[a] : lo[a];
+                hi[a] = o[a] > hi[a] ? o[a] : hi[a];
+            }
         } else {
-            atomicOr(bad, 1);
+            nbad = 1;
         }
         pos[i] = X; pos[n + i] = Y; pos[2 * n + i] = Z;
     }
-    // block min/max then one atomic per block
+    if (nbad) atomicOr(bad, 1);
     __shared__ unsigned long long mn[3][4], mx[3][4];
-    double v[3] = {X, Y, Z};
     for (int a = 0; a < 3; ++a) {
-        unsigned long long lo = ok ? dbl_order(v[a]) : ~0ull, hi = ok ? dbl_order(v[a]) : 0ull;
+        unsigned long long l = lo[a], h = hi[a];
         for (int o = 32; o > 0; o >>= 1) {
-            unsigned long long l2 = __shfl_down(lo, o, 64), h2 = __shfl_down(hi, o, 64);
-            lo = l2 < lo ? l2 : lo;
-            hi = h2 > hi ? h2 : hi;
+            unsigned long long l2 = __shfl_down(l, o, 64), h2 = __shfl_down(h, o, 64);
+            l = l2 < l ? l2 : l;
+            h = h2 > h ? h2 : h;
         }
-        if ((threadIdx.x & 63) == 0) { mn[a][threadIdx.x >> 6] = lo; mx[a][threadIdx.x >> 6] = hi; }
+        if ((threadIdx.x & 63) == 0) { mn[a][threadIdx.x >> 6] = l; mx[a][threadIdx.x >> 6] = h; }
     }
     __syncthreads();
     if (threadIdx.x < 3) {
         int a = threadIdx.x;
-        unsigned long long lo = mn[a][0], hi = mx[a][0];
-        for (int w = 1; w < 4; ++w) { lo = mn[a][w] < lo ? mn[a][w] : lo; hi = mx[a][w] > hi ? mx[a][w] : hi; }
-        atomicMin(&bbox[2 * a], lo);
-        atomicMax(&bbox[2 * a + 1], hi);
+        unsigned long long l = mn[a][0], h = mx[a][0];
+        for (int w = 1; w < 4; ++w) { l = mn[a][w] < l ? mn[a][w] : l; h = mx[a][w] > h ? mx[a][w] : h; }
+        atomicMin(&bbox[2 * a], l);
+        atomicMax(&bbox[2 * a + 1], h);
     }
 }
 
@@ -443,10 +449,32 @@ __global__ void k_pp_count(int64_t n, int ntx_n, int ntx_w, const PPRec *__restr
         cnt_n[i] = a;
         cnt_w[i] = b;
     }
+    // per-block totals (64-bit) into totals[2 * block]; k_sum_partials2 adds them up
+    __shared__ unsigned long long sa[4], sb[4];
     unsigned long long va = a, vb = b;
     for (int o = 32; o > 0; o >>= 1) { va += __shfl_down(va, o, 64); vb += __shfl_down(vb, o, 64); }
-    if ((threadIdx.x & 63) == 0) { atomicAdd(&totals[0], va); atomicAdd(&totals[1], vb); }
+    if ((threadIdx.x & 63) == 0) { sa[threadIdx.x >> 6] = va; sb[threadIdx.x >> 6] = vb; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        totals[2 * blockIdx.x] = sa[0] + sa[1] + sa[2] + sa[3];
+        totals[2 * blockIdx.x + 1] = sb[0] + sb[1] + sb[2] + sb[3];
+    }
     (void)ntx_n; (void)ntx_w;
+}
+
+// out[c] = sum over blocks of partial[2 b + c], c = 0, 1 (one workgroup, fixed order per lane)
+__global__ void __launch_bounds__(256) k_sum_partials2(int64_t nblocks, const unsigned long long *__restrict__ partial,
+                                                       unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long s0[256], s1[256];
+    unsigned long long a = 0, b = 0;
+    for (int64_t i = threadIdx.x; i < nblocks; i += 256) { a += partial[2 * i]; b += partial[2 * i + 1]; }
+    s0[threadIdx.x] = a; s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) { s0[threadIdx.x] += s0[threadIdx.x + w]; s1[threadIdx.x] += s1[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = s0[0]; out[1] = s1[0]; }
 }
 
 __global__ void k_pp_emit(int64_t n, int ntx_n, int ntx_w, const PPRec *__restrict__ rec, const uint32_t *__restrict__ wide,
@@ -579,18 +607,36 @@ __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, i
                     wys[b][rr] = v;
                 }
                 if (r == 0) { amp[b][0] = R.ay; amp[b][1] = R.ab; }
+            } else {                      // unused slot of the last batch: zero weights
+                if (r < kWT) wxs[b][r] = 0.0f; else wys[b][r - kWT] = 0.0f;
+                if (r == 0) { amp[b][0] = 0.0f; amp[b][1] = 0.0f; }
             }
         }
         __syncthreads();
-        for (int b = 0; b < nb; ++b) {
+        // per pixel: the batch's contributions summed in order in FP32, then one compensated
+        // update of the pixel's running sum per batch (unused batch slots have zero weights)
+        float ax[kBatch], bx[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
             const float wx = wxs[b][t & 63];
-            if (wx == 0.0f) continue;
-            const float a0 = amp[b][0] * wx, a1 = amp[b][1] * wx;
-            for (int k = 0; k < 16; ++k) {
-                const float wy = wys[b][(t >> 6) + 4 * k];
-                if (wy == 0.0f) continue;
-                kahan(ys[k], yc[k], a0 * wy);
-                kahan(bs[k], bc[k], a1 * wy);
+            ax[b] = amp[b][0] * wx;
+            bx[b] = amp[b][1] * wx;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int rr = (t >> 6) + 4 * k;
+            float sy = 0.0f, sb = 0.0f;
+            bool any = false;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const float wy = wys[b][rr];
+                any = any || (wy != 0.0f);
+                sy = fmaf(ax[b], wy, sy);
+                sb = fmaf(bx[b], wy, sb);
+            }
+            if (any) {
+                kahan(ys[k], yc[k], sy);
+                kahan(bs[k], bc[k], sb);
             }
         }
     }
@@ -631,7 +677,8 @@ extern "C" int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float
     if (hipMemcpyAsync(bb, init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess) return BP_E_HIP;
     hipLaunchKernelGGL(k_cosmo_table, dim3((kNZ + 255) / 256), dim3(256), 0, s, *p, gauss_rules(), chi_t, tau_t);
     unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_pp_positions, dim3(blocks), dim3(256), 0, s, n, theta_x, theta_y, z, chi_t, pos, bb,
+    hipLaunchKernelGGL(k_pp_positions, dim3(blocks < 4096u ? blocks : 4096u), dim3(256), 0, s, n, theta_x, theta_y, z,
+                       chi_t, pos, bb,
                        (int *)(bb + 6));
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long hb[8];
@@ -714,6 +761,7 @@ extern "C" int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad
     A1.take<PPRec>(n); A1.take<uint32_t>(n);
     A1.take<uint32_t>(n + 1); A1.take<uint32_t>(n + 1); A1.take<uint32_t>(n + 1); A1.take<uint32_t>(n + 1);
     A1.take<unsigned long long>(2);
+    A1.take<unsigned long long>(2 * ((n + 255) / 256));
     size_t phase1 = A1.used + scan_ws_bytes(n + 1);
     if (!ws || ws_bytes < phase1) { *ws_needed = phase1 + 64; return BP_E_WORKSPACE; }
     Arena A(ws, ws_bytes);
@@ -723,6 +771,7 @@ extern "C" int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad
     uint32_t *cn = A.take<uint32_t>(n + 1), *cw = A.take<uint32_t>(n + 1);
     uint32_t *on = A.take<uint32_t>(n + 1), *ow = A.take<uint32_t>(n + 1);
     unsigned long long *tot = A.take<unsigned long long>(2);
+    unsigned long long *tot_part = A.take<unsigned long long>(2 * ((n + 255) / 256));
     void *scan_ws = (char *)ws + A.used;
     A.used += scan_ws_bytes(n + 1);
     unsigned blocks = (unsigned)((n + 255) / 256);
@@ -730,9 +779,10 @@ extern "C" int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad
     hipLaunchKernelGGL(k_cosmo_table, dim3((kNZ + 255) / 256), dim3(256), 0, s, *p, gauss_rules(), chi_t, tau_t);
     hipLaunchKernelGGL(k_pp_amplitudes, dim3(blocks), dim3(256), 0, s, *p, n, (int)npix, pix_rad, theta_x, theta_y, z,
                        v_los, halo_id, r_halo, h_comoving, M_p, n_halos, sol, status, chi_t, tau_t, rec, wide);
-    if (hipMemsetAsync(tot, 0, 2 * sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
+
     if (fill_u32(cn + n, 0u, 1, s) || fill_u32(cw + n, 0u, 1, s)) return BP_E_HIP;
-    hipLaunchKernelGGL(k_pp_count, dim3(blocks), dim3(256), 0, s, n, ntx_n, ntx_w, rec, wide, cn, cw, tot);
+    hipLaunchKernelGGL(k_pp_count, dim3(blocks), dim3(256), 0, s, n, ntx_n, ntx_w, rec, wide, cn, cw, tot_part);
+    hipLaunchKernelGGL(k_sum_partials2, dim3(1), dim3(256), 0, s, (int64_t)blocks, tot_part, tot);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long ht[2];
     if (hipMemcpyAsync(ht, tot, sizeof(ht), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
