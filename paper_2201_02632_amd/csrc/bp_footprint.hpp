@@ -8,18 +8,21 @@
 
 namespace bp {
 
-// Two tables (P and n) sampled at the same position.
+// Two tables (P and n) sampled at the same position: cubic Lagrange through nodes i-1 .. i+2,
+// with the weights written through a = f(f-1) and (f+1)(f-2) = a - 2.
 __device__ inline void lagr4x2(const float *__restrict__ tp, const float *__restrict__ tn, int n, float s, float *vp,
                                float *vn) {
     float fi = floorf(s);
     int i = (int)fi;
     i = min(max(i, 1), n - 3);
-    float f = s - (float)i;
-    float fm1 = f - 1.0f, fm2 = f - 2.0f, fp1 = f + 1.0f;
-    float w0 = -f * fm1 * fm2 * (1.0f / 6.0f);
-    float w1 = fp1 * fm1 * fm2 * 0.5f;
-    float w2 = -fp1 * f * fm2 * 0.5f;
-    float w3 = fp1 * f * fm1 * (1.0f / 6.0f);
+    const float f = s - (float)i;
+    const float fm1 = f - 1.0f;
+    const float a = f * fm1;
+    const float t = a * (-1.0f / 6.0f), u = (a - 2.0f) * 0.5f;
+    const float w0 = t * (f - 2.0f);     // -f (f-1) (f-2) / 6
+    const float w3 = -t * (f + 1.0f);    //  (f+1) f (f-1) / 6
+    const float w1 = u * fm1;            //  (f+1) (f-1) (f-2) / 2
+    const float w2 = -u * f;             // -(f+1) f (f-2) / 2
     const float *p = tp + i - 1, *q = tn + i - 1;
     *vp = w0 * p[0] + w1 * p[1] + w2 * p[2] + w3 * p[3];
     *vn = w0 * q[0] + w1 * q[1] + w2 * q[2] + w3 * q[3];
@@ -38,7 +41,6 @@ __device__ inline void kahan_add(float &s, float &c, float v) {
 __device__ inline float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline float hw_ln(float x) { return 0.693147180559945f * __builtin_amdgcn_logf(x); }
 
 // Projected profile at squared impact parameter r2 (in the record's length
 // unit), in units of the central electron pressure / density times that
@@ -48,11 +50,25 @@ __device__ inline float hw_ln(float x) { return 0.693147180559945f * __builtin_a
 //                      plus, for a gas shell beyond r_vir, (S - u) g_S(omega)
 //   zone B (r >= r_a): Y = U g_B(zeta), zeta = acosh(r_f / r),        U = sqrt(r_f^2 - r^2)
 // A and B share one interpolation with a per-lane table offset, so a wave that straddles r_a
-// does not run both branches.
+// does not run both branches.  The grid coordinates are kept in log2 units (set_zone_grids), so
+// each logarithm is one hardware log2 with no rescaling.
 struct FootRec {
     float ra, rf, r2min, D, isqD, eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih;
     int flags;
 };
+
+// Zone grids of a table in log2 units: a coordinate c on [lo, hi] with N nodes becomes
+// (c / ln 2 - lo / ln 2) * ((N - 1) ln 2 / (hi - lo)).
+template <class Rec>
+__host__ __device__ inline void set_zone_grids(Rec &r, float elo, float ehi, float olo, float ohi, float zlo, float zhi) {
+    const double l2e = 1.4426950408889634;   // 1 / ln 2
+    r.eta_lo = (float)((double)elo * l2e);
+    r.eta_ih = (float)((BP_TAB_NA - 1) / (((double)ehi - (double)elo) * l2e));
+    r.om_lo = (float)((double)olo * l2e);
+    r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / (((double)ohi - (double)olo) * l2e)) : 0.0f;
+    r.ze_lo = (float)((double)zlo * l2e);
+    r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / (((double)zhi - (double)zlo) * l2e)) : 0.0f;
+}
 
 // The fields of a wave-uniform record, read once per (tile, halo) pair: readfirstlane is
 // convergent, so the compiler keeps these reads outside the per-pixel branches.
@@ -70,19 +86,21 @@ __device__ inline FootRec foot_uniform(const Rec &R) {
 template <class Rec>
 __device__ inline void footprint_value(const Rec &R, const float *__restrict__ tab, float r2, float u2, float U2,
                                        float *vp, float *vn) {
+    const float kLn2 = 0.693147180559945f;
     const bool zA = u2 > 0.0f;
-    const float w = hw_sqrt(fmaxf(zA ? u2 : U2, 0.0f));                 // u or U
-    const float acs = hw_ln(((zA ? R.ra : R.rf) + w) * hw_rsq(fmaxf(r2, R.r2min)));   // acosh(r_{a,f} / r)
-    const float eta = hw_ln(1.0f + fmaxf(acs, 0.0f));
-    const float sidx = zA ? (eta - R.eta_lo) * R.eta_ih : (acs - R.ze_lo) * R.ze_ih;
+    const float w = hw_sqrt(fmaxf(zA ? u2 : U2, 0.0f));                          // u or U
+    // log2 of (r_{a,f} + w) / r = acosh(r_{a,f} / r) / ln 2
+    const float L = __builtin_amdgcn_logf(((zA ? R.ra : R.rf) + w) * hw_rsq(fmaxf(r2, R.r2min)));
+    const float eta = __builtin_amdgcn_logf(fmaf(kLn2, fmaxf(L, 0.0f), 1.0f));   // eta / ln 2
+    const float sidx = zA ? (eta - R.eta_lo) * R.eta_ih : (L - R.ze_lo) * R.ze_ih;
     const int off = zA ? 0 : BP_TAB_NA + BP_TAB_NS;
     const int nn = zA ? BP_TAB_NA : BP_TAB_NB;
     float gp, gn;
     lagr4x2(tab + off, tab + BP_TAB_ZONE + off, nn, sidx, &gp, &gn);
     float P = gp * w, N = gn * w;
     if ((R.flags & 1) && zA) {
-        const float S = hw_sqrt(w * w + R.D);
-        const float om = hw_ln((w + S) * R.isqD);
+        const float S = hw_sqrt(fmaf(w, w, R.D));
+        const float om = __builtin_amdgcn_logf((w + S) * R.isqD);                 // asinh(u / sqrt(D)) / ln 2
         float sp, sn;
         lagr4x2(tab + BP_TAB_NA, tab + BP_TAB_ZONE + BP_TAB_NA, BP_TAB_NS, (om - R.om_lo) * R.om_ih, &sp, &sn);
         const float e = R.D * hw_rcp(S + w);

@@ -3,10 +3,12 @@
 // The map is cut into 16x16-pixel tiles.  Every halo emits one (tile, halo)
 // pair per tile that its footprint disc touches; the pairs are stably sorted
 // by tile, so each tile's list is in catalogue order.  One wavefront owns one
-// tile: lane l holds 4 pixels (column l%16, rows l/16 + 4k) with their y and b
-// sums and Kahan compensations in registers, walks the tile's halo list
-// (halo records are wave-uniform scalar loads), and writes the tile back
-// once.  No atomics touch the maps, and the summation order is fixed.
+// tile: lane l holds one pixel of each 8x8 quadrant (column l%8, row l/8) with
+// its y and b sums and Kahan compensations in registers, walks the tile's halo
+// list (halo records are wave-uniform scalar loads), and writes the tile back
+// once.  A quadrant the disc misses costs only the membership test: its
+// profile evaluation is branched over for the whole wave.  No atomics touch
+// the maps, and the summation order is fixed.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -18,26 +20,29 @@ namespace bp {
 
 constexpr int kTile = 16;
 
-// Per-halo paste record in pixel units (160 bytes; read by each wave as scalar loads).
+// Per-halo paste record in pixel units (176 bytes; read by each wave as scalar loads).
 struct __attribute__((aligned(16))) FlatRec {
     int32_t cxi, cyi;       // integer part of the centre in pixel units
-    float cxf, cyf;         // fractional part
+    float hx, hy;           // 0.5 minus the fractional part: pixel (i, j) sits at (i - cxi + hx, j - cyi + hy)
     float Rt2;              // footprint radius^2 [px^2]
-    float ra, ra2, rv2;     // r_a = min(r_vir, r_f), r_a^2, r_vir^2
+    float Rt2_band;         // 4e-6 Rt2: FP32 distances this close to the edge are re-decided in FP64
+    float ra, ra2;          // r_a = min(r_vir, r_f), r_a^2
     float rf, rf2, D, isqD; // r_f, r_f^2, r_f^2 - r_vir^2, 1/sqrt(D) (0 without a shell)
+    float ra2_edge, rf2_edge;  // 0.1 r_a^2, 0.1 r_f^2: below these u^2 and U^2 are formed in FP64
     float r2min;            // clamp of r_perp^2 at the centre
-    float eta_lo, eta_ih;   // zone A grid start and 1/step
+    float eta_lo, eta_ih;   // zone A grid start and 1/step (log2 units)
     float om_lo, om_ih;     // zone S
     float ze_lo, ze_ih;     // zone B
     float amp_y, amp_b;     // sigma_T/(m_e c^2) P_e0 L_pix ; sigma_T n_e0 L_pix (v/c) e^-tau
     int32_t flags;          // bit0 shell (r_f > r_vir), bit1 zone B (R_t > r_vir), bit2 valid
     float Rt_emit;          // footprint radius used by both the pair count and the emit pass
+    float pad[3];
     double cxd, cyd;        // fractional centre in FP64 (edge-annulus recompute)
     double ra2d, rf2d;      // r_a^2, r_f^2 in FP64
     double thx, thy;        // centre [rad] and, below, D_A and R_t [Mpc/h]: the exact membership test
     double DA, Rt;
 };
-static_assert(sizeof(FlatRec) == 160, "FlatRec size");
+static_assert(sizeof(FlatRec) == 176, "FlatRec size");
 
 __device__ inline void tile_row_range(double cx, double cy, double Rt, int ty, int ntx, int npix, int *tx0, int *tx1) {
     // pixel rows of this tile: centres y in [16 ty + 0.5, 16 ty + 15.5]
@@ -88,10 +93,12 @@ __global__ void __launch_bounds__(256) k_flat_setup(bp_params P, FlatGeom Gm, in
             double ra = fmin(rv, rf);
             double cxf = floor(cx), cyf = floor(cy);
             r.cxi = (int32_t)cxf; r.cyi = (int32_t)cyf;
-            r.cxf = (float)(cx - cxf); r.cyf = (float)(cy - cyf);
+            r.hx = 0.5f - (float)(cx - cxf); r.hy = 0.5f - (float)(cy - cyf);
             r.Rt2 = (float)(Rt * Rt);
-            r.ra = (float)ra; r.ra2 = (float)(ra * ra); r.rv2 = (float)(rv * rv);
+            r.Rt2_band = 4e-6f * r.Rt2;
+            r.ra = (float)ra; r.ra2 = (float)(ra * ra);
             r.rf = (float)rf; r.rf2 = (float)(rf * rf);
+            r.ra2_edge = 0.1f * r.ra2; r.rf2_edge = 0.1f * r.rf2;
             r.cxd = cx - cxf; r.cyd = cy - cyf;
             r.ra2d = ra * ra; r.rf2d = rf * rf;
             r.thx = thx[i]; r.thy = thy[i];
@@ -104,9 +111,7 @@ __global__ void __launch_bounds__(256) k_flat_setup(bp_params P, FlatGeom Gm, in
                 float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
                 float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
                 float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
-                r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
-                r.om_lo = olo; r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
-                r.ze_lo = zlo; r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+                set_zone_grids(r, elo, ehi, olo, ohi, zlo, zhi);
             } else {
                 r.eta_lo = (float)Rt;       // q-grid: R_t in pixels and its inverse
                 r.eta_ih = (float)(1.0 / Rt);
@@ -192,18 +197,19 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
     const uint32_t p0 = tstart[tile], p1 = tend[tile];
     if (p0 >= p1) return;
     const int tx = tile % Gm.ntx, ty = tile / Gm.ntx;
-    const int pi = tx * kTile + (lane & 15);
-    const int pj0 = ty * kTile + (lane >> 4);
+    // pass q covers the 8x8 quadrant (q & 1, q >> 1) of the tile; lane l holds its pixel (l % 8, l / 8)
+    const int X0 = tx * kTile, Y0 = ty * kTile;
+    const int li = lane & 7, lj = lane >> 3;
     float ys[4], yc[4], bs[4], bc[4];
     bool inmap[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        int pj = pj0 + 4 * k;
-        inmap[k] = (pi < Gm.npix) && (pj < Gm.npix);
+    for (int q = 0; q < 4; ++q) {
+        const int pi = X0 + 8 * (q & 1) + li, pj = Y0 + 8 * (q >> 1) + lj;
+        inmap[q] = (pi < Gm.npix) && (pj < Gm.npix);
         int64_t idx = (int64_t)pj * Gm.npix + pi;
-        ys[k] = inmap[k] ? ymap[idx] : 0.0f;
-        bs[k] = inmap[k] ? bmap[idx] : 0.0f;
-        yc[k] = 0.0f; bc[k] = 0.0f;
+        ys[q] = inmap[q] ? ymap[idx] : 0.0f;
+        bs[q] = inmap[q] ? bmap[idx] : 0.0f;
+        yc[q] = 0.0f; bc[q] = 0.0f;
     }
     for (uint32_t p = p0; p < p1; ++p) {
         const uint32_t h = __builtin_amdgcn_readfirstlane(vals[p]);
@@ -211,20 +217,29 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
         const FlatRec &R = rec[h];
         const FootRec F = foot_uniform(R);
         const float *tab = tables + (int64_t)h * (kQ ? 2 * BP_MLP_NQ : BP_TAB_STRIDE);
-        const float dxb = (float)(pi - R.cxi) + (0.5f - R.cxf);
+        const int ox = X0 - R.cxi, oy = Y0 - R.cyi;   // tile corner relative to the centre pixel
+        float sx[2], dys[2];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int pj = pj0 + 4 * k;
-            const float dy = (float)(pj - R.cyi) + (0.5f - R.cyf);
-            const float r2 = dxb * dxb + dy * dy;
+        for (int c = 0; c < 2; ++c) {
+            const float dx = (float)(ox + 8 * c + li) + R.hx;
+            sx[c] = dx * dx;
+            dys[c] = (float)(oy + 8 * c + lj) + R.hy;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int qx = q & 1, qy = q >> 1;
+            const int pi = X0 + 8 * qx + li, pj = Y0 + 8 * qy + lj;
+            const float dy = dys[qy];
+            const float r2 = fmaf(dy, dy, sx[qx]);
             bool in = r2 < R.Rt2;
             // the FP32 distance is good to ~1e-6 relative: decide pixels that close to the edge
             // with the FP64 formula of the definition
-            if (fabsf(r2 - R.Rt2) <= 4e-6f * R.Rt2) in = inside_fp64(pi, pj, Gm.pix, R.thx, R.thy, R.DA, R.Rt);
-            if (in && inmap[k]) {
+            if (fabsf(r2 - R.Rt2) <= R.Rt2_band) in = inside_fp64(pi, pj, Gm.pix, R.thx, R.thy, R.DA, R.Rt);
+            if (in && inmap[q]) {
                 float u2 = R.ra2 - r2, U2 = R.rf2 - r2;
-                if (u2 < 0.1f * R.ra2 || U2 < 0.1f * R.rf2) {
-                    // edge annulus: the sqrt of a small difference needs the difference in FP64
+                // next to r_a (inside) or r_f the square root of a small difference needs the
+                // difference in FP64; in zone B only the sign of u^2 is used
+                if ((u2 > 0.0f && u2 < R.ra2_edge) || U2 < R.rf2_edge) {
                     double dxd = (double)(pi - R.cxi) + (0.5 - R.cxd), dyd = (double)(pj - R.cyi) + (0.5 - R.cyd);
                     double r2d = dxd * dxd + dyd * dyd;
                     u2 = (float)(R.ra2d - r2d);
@@ -233,17 +248,18 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
                 float vp, vn;
                 if (kQ) footprint_value_q(R, tab, r2, U2, &vp, &vn);
                 else footprint_value(F, tab, r2, u2, U2, &vp, &vn);
-                kahan_add(ys[k], yc[k], R.amp_y * vp);
-                kahan_add(bs[k], bc[k], R.amp_b * vn);
+                kahan_add(ys[q], yc[q], R.amp_y * vp);
+                kahan_add(bs[q], bc[q], R.amp_b * vn);
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (!inmap[k]) continue;
-        int64_t idx = (int64_t)(pj0 + 4 * k) * Gm.npix + pi;
-        ymap[idx] = ys[k];
-        bmap[idx] = bs[k];
+    for (int q = 0; q < 4; ++q) {
+        if (!inmap[q]) continue;
+        const int pi = X0 + 8 * (q & 1) + li, pj = Y0 + 8 * (q >> 1) + lj;
+        int64_t idx = (int64_t)pj * Gm.npix + pi;
+        ymap[idx] = ys[q];
+        bmap[idx] = bs[q];
     }
 }
 

@@ -164,11 +164,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
                 float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI);
                 float olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI);
                 float zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
-                r.eta_lo = elo; r.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
-                r.om_lo = olo;
-                r.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
-                r.ze_lo = zlo;
-                r.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+                set_zone_grids(r, elo, ehi, olo, ohi, zlo, zhi);
             } else {
                 r.eta_lo = (float)Rtu;           // q-grid: R_t in record units and its inverse
                 r.eta_ih = (float)(1.0 / Rtu);
@@ -289,8 +285,9 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
         }
         if (in && valid) {
             float u2 = R.ra2 - r2, U2 = R.rf2 - r2;
-            if (u2 < 0.1f * R.ra2 || U2 < 0.1f * R.rf2) {
-                // edge annulus: recompute the haversine in FP64 so sqrt(r_a^2 - r^2) keeps its digits
+            if ((u2 > 0.0f && u2 < 0.1f * R.ra2) || U2 < 0.1f * R.rf2) {
+                // next to r_a (inside) or r_f: recompute the haversine in FP64 so the square root of the
+                // small difference keeps its digits; in zone B only the sign of u^2 is used
                 double sp = sin(0.5 * (phj - R.ph));
                 double hvd = sd * sd + sthr * R.sth * sp * sp;
                 double r2d = 4.0 * hvd * (1.0 - hvd) / (G.pixang * G.pixang);

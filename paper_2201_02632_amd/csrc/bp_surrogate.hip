@@ -70,9 +70,7 @@ __global__ void k_targets(bp_params P, int64_t n, const double *__restrict__ sol
     R.r2min = (float)(1e-10 * ra * ra);
     float elo = Mt(BP_META_ETA_LO), ehi = Mt(BP_META_ETA_HI), olo = Mt(BP_META_OM_LO), ohi = Mt(BP_META_OM_HI),
           zlo = Mt(BP_META_ZE_LO), zhi = Mt(BP_META_ZE_HI);
-    R.eta_lo = elo; R.eta_ih = (float)((BP_TAB_NA - 1) / ((double)ehi - (double)elo));
-    R.om_lo = olo; R.om_ih = (ohi > olo) ? (float)((BP_TAB_NS - 1) / ((double)ohi - (double)olo)) : 0.0f;
-    R.ze_lo = zlo; R.ze_ih = (zhi > zlo) ? (float)((BP_TAB_NB - 1) / ((double)zhi - (double)zlo)) : 0.0f;
+    set_zone_grids(R, elo, ehi, olo, ohi, zlo, zhi);
     R.flags = (shell ? 1 : 0) | ((1.0 > rv) ? 2 : 0) | 4;
     double q = qnode(k);
     if (k == BP_MLP_NQ - 1) q = 1.0 - 1e-6;   // the edge node: the limit from inside
