@@ -459,35 +459,36 @@ __device__ inline float cosh_f(float s) {
     return 0.5f * (e + hw_rcp(e));
 }
 
-__global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules G, int64_t n,
-                                                         const double *__restrict__ sol,
-                                                         const int32_t *__restrict__ status,
-                                                         float *__restrict__ tab, float *__restrict__ meta) {
-    const int64_t i = blockIdx.x;
-    const int node = threadIdx.x;
+// Zone-A node geometry shared by every halo whose footprint reaches r_a (eta_lo = 0, the usual
+// case): per node k, xi = acosh(r_a / r_perp), r_perp / r_a, u / r_a and xi / (u / r_a).  The grid
+// end is the single-precision eta_top the deposit reads back, so nodes sit where it looks for them.
+// Every launch writes the same values (a function of constants only).
+__device__ double g_nodeA[BP_TAB_NA][4];
+
+__global__ void __launch_bounds__(BP_TAB_NA) k_node_geom(double eta_hi) {
+    const int k = threadIdx.x;
+    const double eta = eta_hi * k / (BP_TAB_NA - 1);
+    const double xi = expm1(eta);
+    // cosh and tanh of xi from one expm1 (no cancellation for small xi)
+    const double em = expm1(xi), e = 1.0 + em, q = e * e + 1.0;
+    const double c1 = 2.0 * e / q, c2 = em * (2.0 + em) / q;
+    g_nodeA[k][0] = xi;
+    g_nodeA[k][1] = c1;
+    g_nodeA[k][2] = c2;
+    g_nodeA[k][3] = xi > 0.0 ? xi / c2 : 0.0;
+}
+
+// Per-halo grid ranges and central values (one lane per halo): the zone ranges in eta, omega and
+// zeta, P_e0 and n_e0.  Written to meta, from which the table kernel and the deposits read them.
+__global__ void __launch_bounds__(256) k_table_setup(bp_params P, GaussRules G, int64_t n,
+                                                     const double *__restrict__ sol, const int32_t *__restrict__ status,
+                                                     float *__restrict__ meta) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
     auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
-    float *tP = tab + (int64_t)i * BP_TAB_STRIDE;
-    float *tN = tP + BP_TAB_ZONE;
-    if (status[i] & ~BP_S_MULTI_ROOT) {
-        tP[node] = 0.0f; tN[node] = 0.0f;
-        if (node < BP_META_NFIELDS) meta[(int64_t)node * n + i] = 0.0f;
-        return;
-    }
-    // per-halo constants: one lane computes them, the block shares them through LDS
-    __shared__ double shd[8];
-    __shared__ Prof shq;
-    if (node == 0) {
-        const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF);
-        const double c = S(BP_SOL_C), mc = nfw_m(c);
-        Prof Q;
-        Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
-        Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
-        Q.a = (float)S(BP_SOL_A);
-        Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
-        Q.ant_f = (float)(P.alpha_nt * S(BP_SOL_FNT));
-        Q.n_nt = (float)P.n_nt;
-        shq = Q;
-        const double Rt = S(BP_SOL_RT);
+    float m[BP_META_NFIELDS] = {};
+    if (!(status[i] & ~BP_S_MULTI_ROOT)) {
+        const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), Rt = S(BP_SOL_RT);
         const double ra = fmin(rv, rf);
         // zone ranges; the innermost sight line r_perp = 1e-5 r_a has the same eta for every halo
         const double eta_lo = log1p(acosh(ra / fmin(Rt, ra)));
@@ -501,13 +502,48 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
             om_hi = asinh(rv / sD);
         }
         if (Rt > rv) { ze_lo = acosh(rf / Rt); ze_hi = acosh(rf / rv); }
-        shd[0] = eta_lo; shd[1] = om_lo; shd[2] = om_hi; shd[3] = ze_lo; shd[4] = ze_hi;
-        shd[5] = rv; shd[6] = rf; shd[7] = Rt;
+        const double X = P.X_H;
+        m[BP_META_ETA_LO] = (float)eta_lo;
+        m[BP_META_ETA_HI] = (float)G.eta_top;
+        m[BP_META_OM_LO] = (float)om_lo;
+        m[BP_META_OM_HI] = (float)om_hi;
+        m[BP_META_ZE_LO] = (float)ze_lo;
+        m[BP_META_ZE_HI] = (float)ze_hi;
+        m[BP_META_PE0] = (float)((2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0));
+        m[BP_META_NE0] = (float)(S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp));
     }
-    __syncthreads();
-    const Prof Q = shq;
-    const double eta_lo = shd[0], eta_hi = G.eta_top, om_lo = shd[1], om_hi = shd[2], ze_lo = shd[3], ze_hi = shd[4];
-    const double rv = shd[5], rf = shd[6], Rt = shd[7];
+    for (int f = 0; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = m[f];
+}
+
+// One block per halo, one table node per thread.  Node positions come from the single-precision
+// grid ranges in meta (the values the deposits interpolate with).
+__global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(GaussRules G, int64_t n, const double *__restrict__ sol,
+                                                         const int32_t *__restrict__ status,
+                                                         const float *__restrict__ meta, float *__restrict__ tab,
+                                                         double ant, float n_nt) {
+    const int64_t i = blockIdx.x;
+    const int node = threadIdx.x;
+    auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
+    auto Mt = [&](int f) { return (double)meta[(int64_t)f * n + i]; };
+    float *tP = tab + (int64_t)i * BP_TAB_STRIDE;
+    float *tN = tP + BP_TAB_ZONE;
+    if (status[i] & ~BP_S_MULTI_ROOT) {
+        tP[node] = 0.0f; tN[node] = 0.0f;
+        return;
+    }
+    // per-halo constants (wave-uniform)
+    const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), Rt = S(BP_SOL_RT);
+    const double c = S(BP_SOL_C), mc = nfw_m(c);
+    Prof Q;
+    Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
+    Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
+    Q.a = (float)S(BP_SOL_A);
+    Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
+    Q.ant_f = (float)(ant * S(BP_SOL_FNT));
+    Q.n_nt = n_nt;
+    const double eta_lo = Mt(BP_META_ETA_LO), eta_hi = Mt(BP_META_ETA_HI);
+    const double om_lo = Mt(BP_META_OM_LO), om_hi = Mt(BP_META_OM_HI);
+    const double ze_lo = Mt(BP_META_ZE_LO), ze_hi = Mt(BP_META_ZE_HI);
     const double ra = fmin(rv, rf);
     const bool shell = rf > rv;
     const double D = shell ? rf * rf - rv * rv : 0.0;
@@ -517,17 +553,24 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
     double accP = 0.0, accN = 0.0;
     if (node < BP_TAB_NA) {
         // zone A: g_A = Y_A / (P_e0 u), Y_A = 2 int_0^xi P(r_perp cosh s) r_perp cosh s ds
-        double eta = eta_lo + (eta_hi - eta_lo) * node / (BP_TAB_NA - 1);
-        double xi = expm1(eta);
+        double xi, rp, f;
+        if (eta_lo == 0.0) {
+            xi = g_nodeA[node][0];
+            rp = ra * g_nodeA[node][1];
+            f = g_nodeA[node][3] / ra;   // 2 * (xi/2) / u
+        } else {
+            const double eta = eta_lo + (eta_hi - eta_lo) * node / (BP_TAB_NA - 1);
+            xi = expm1(eta);
+            // cosh and tanh of xi from one expm1 (no cancellation for small xi)
+            const double em = expm1(xi), e = 1.0 + em, q = e * e + 1.0;
+            rp = ra * (2.0 * e / q);
+            f = xi / (ra * (em * (2.0 + em) / q));
+        }
         if (xi < 1e-7) {  // limit r_perp -> r_a
             float pe, ne;
             prof_eval(Q, (float)ra, &pe, &ne);
             accP = 2.0 * pe; accN = 2.0 * ne;
         } else {
-            // cosh and tanh of xi from one expm1 (no cancellation for small xi)
-            const double em = expm1(xi), e = 1.0 + em, q = e * e + 1.0;
-            const double rp = ra * (2.0 * e / q);
-            const double u = ra * (em * (2.0 + em) / q);
             // 16 nodes reach 1e-11 up to xi ~ 6 (sight lines off the core); 24 beyond
             const bool wide = xi > 5.5;
             const int ng = wide ? 24 : 16;
@@ -541,7 +584,6 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
                 double w = gw[j] * (double)r;
                 accP += w * pe; accN += w * ne;
             }
-            double f = xi / u;  // 2 * (xi/2) / u
             accP *= f; accN *= f;
         }
     } else if (node < BP_TAB_NA + BP_TAB_NS) {
@@ -595,21 +637,6 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(bp_params P, GaussRules 
     }
     tP[node] = (float)accP;
     tN[node] = (float)accN;
-    if (node == 0) {
-        const double u_len = kMpc / P.h, u_mass = kMsun / P.h;
-        double X = P.X_H;
-        double Pe0 = (2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0);
-        double ne0 = S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp);
-        (void)u_len; (void)u_mass;
-        meta[(int64_t)BP_META_ETA_LO * n + i] = (float)eta_lo;
-        meta[(int64_t)BP_META_ETA_HI * n + i] = (float)eta_hi;
-        meta[(int64_t)BP_META_OM_LO * n + i] = (float)om_lo;
-        meta[(int64_t)BP_META_OM_HI * n + i] = (float)om_hi;
-        meta[(int64_t)BP_META_ZE_LO * n + i] = (float)ze_lo;
-        meta[(int64_t)BP_META_ZE_HI * n + i] = (float)ze_hi;
-        meta[(int64_t)BP_META_PE0 * n + i] = (float)Pe0;
-        meta[(int64_t)BP_META_NE0 * n + i] = (float)ne0;
-    }
 }
 
 // ------------------------------------------------------- Gauss-Legendre --
@@ -685,10 +712,14 @@ extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *so
     if (n == 0) return BP_OK;
     if (!sol || !status || !tables || !meta) return BP_E_ARG;
     if (n > 0x7fffffff) return BP_E_OVERFLOW;
-    prof_begin(BP_PROF_TABLES, (hipStream_t)stream);
-    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_ZONE), 0, (hipStream_t)stream, *p, gauss_rules(),
-                       n, sol, status, tables, meta);
-    prof_end(BP_PROF_TABLES, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    const GaussRules G = gauss_rules();
+    prof_begin(BP_PROF_TABLES, s);
+    hipLaunchKernelGGL(k_node_geom, dim3(1), dim3(BP_TAB_NA), 0, s, (double)(float)G.eta_top);
+    hipLaunchKernelGGL(k_table_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, *p, G, n, sol, status, meta);
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_ZONE), 0, s, G, n, sol, status, meta, tables,
+                       p->alpha_nt, (float)p->n_nt);
+    prof_end(BP_PROF_TABLES, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
