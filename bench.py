@@ -32,9 +32,9 @@ DEPOSIT_OPS_PER_PX = 62
 # HBM bytes per deposit launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99995, WRITE x 1.0).
 # Valid only for the deposit sources they were measured on.
-DEPOSIT_TRAFFIC = {"bytes": 2588237009,
-                   "sources_sha256": {"bp_hp_flat.hip": "3418e443a380fad27868f7c0dbf63056cd96a49e941dc09f5b1e5c0ae833f8f8",
-                                      "bp_footprint.hpp": "8ce9f547ae9be71dc9f36c95a0b9af232ea559400289132fb5d2fa6b3f85035a"}}
+DEPOSIT_TRAFFIC = {"bytes": 2766008447,
+                   "sources_sha256": {"bp_hp_flat.hip": "a977c8b93b476740819387a5d26b3644417df726bc70fa53ac350f24960c236a",
+                                      "bp_footprint.hpp": "35d33ce511c89eeb488fa21835c5972f0abce7925ab5fc191d6c0b4f649086a7"}}
 
 
 def deposit_traffic():
