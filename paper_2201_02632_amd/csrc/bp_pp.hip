@@ -221,7 +221,7 @@ constexpr int kShells = 8;
 constexpr int kMaxLevel = 20;
 
 template <int K>
-__global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 32 ? 4 : 2))) k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key,
                                                 const uint32_t *__restrict__ idx, const double *__restrict__ sp,
                                                 const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ cend,
                                                 float *__restrict__ h_out, int *__restrict__ fail) {
@@ -245,17 +245,18 @@ __global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const 
     for (int lev = min(max((int)rint(log2(hest / g.cell)) + 10, 0), kMaxLevel); lev <= kMaxLevel && !done; ++lev) {
         // this level's cell grid: size s, the particle's cell (gx, gy, gz), extent (nxl, nyl, nzl)
         const double s = ldexp(g.cell, lev - 10);
-        int64_t gx, gy, gz, nxl, nyl, nzl;
+        // (int: at most 2^10 times the coarse cells of an axis)
+        int gx, gy, gz, nxl, nyl, nzl;
         if (lev <= 10) {
             const int sh = 10 - lev;
-            gx = ((int64_t)cx << sh) + (fx >> lev); gy = ((int64_t)cy << sh) + (fy >> lev);
-            gz = ((int64_t)cz << sh) + (fz >> lev);
-            nxl = (int64_t)g.nx << sh; nyl = (int64_t)g.ny << sh; nzl = (int64_t)g.nz << sh;
+            gx = (cx << sh) + (int)(fx >> lev); gy = (cy << sh) + (int)(fy >> lev);
+            gz = (cz << sh) + (int)(fz >> lev);
+            nxl = g.nx << sh; nyl = g.ny << sh; nzl = g.nz << sh;
         } else {
             const int up = lev - 10;
             gx = cx >> up; gy = cy >> up; gz = cz >> up;
-            nxl = ((int64_t)g.nx + (1 << up) - 1) >> up; nyl = ((int64_t)g.ny + (1 << up) - 1) >> up;
-            nzl = ((int64_t)g.nz + (1 << up) - 1) >> up;
+            nxl = (g.nx + (1 << up) - 1) >> up; nyl = (g.ny + (1 << up) - 1) >> up;
+            nzl = (g.nz + (1 << up) - 1) >> up;
         }
         // position inside the own cell, in cell units (cell membership came from the same FP64 positions)
         const float ux = fminf(fmaxf((float)((mex - g.x0) / s - (double)gx), 0.0f), 1.0f);
@@ -275,24 +276,24 @@ __global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const 
         for (int r = 0; r <= kShells && !done; ++r) {
             const float kth2 = T.kth();
             for (int dz = -r; dz <= r; ++dz) {
-                const int64_t az = gz + dz;
+                const int az = gz + dz;
                 if (az < 0 || az >= nzl) continue;
                 const float ez = dz > 0 ? dz - uz : (dz < 0 ? uz - dz - 1 : 0.0f);
                 for (int dy = -r; dy <= r; ++dy) {
-                    const int64_t ay = gy + dy;
+                    const int ay = gy + dy;
                     if (ay < 0 || ay >= nyl) continue;
                     const float ey = dy > 0 ? dy - uy : (dy < 0 ? uy - dy - 1 : 0.0f);
                     const bool face = (dz == -r || dz == r || dy == -r || dy == r);
                     const int step = (face || r == 0) ? 1 : 2 * r;
                     for (int dx = -r; dx <= r; dx += step) {
-                        const int64_t ax = gx + dx;
+                        const int ax = gx + dx;
                         if (ax < 0 || ax >= nxl) continue;
                         const float ex = dx > 0 ? dx - ux : (dx < 0 ? ux - dx - 1 : 0.0f);
                         // cannot hold a closer particle (the factor absorbs FP32 rounding of both sides)
                         if ((ex * ex + ey * ey + ez * ez) * s2 * 0.999998f >= kth2) continue;
                         if (lev <= 10) {
                             const int sh = 10 - lev;
-                            const int64_t ccx = ax >> sh, ccy = ay >> sh, ccz = az >> sh;
+                            const int ccx = ax >> sh, ccy = ay >> sh, ccz = az >> sh;
                             const uint64_t cc = ((uint64_t)ccz * g.ny + ccy) * g.nx + ccx;
                             uint32_t a0 = cstart[cc], b0 = cend[cc];
                             if (a0 >= b0) continue;
@@ -309,11 +310,11 @@ __global__ void __launch_bounds__(256) k_pp_knn(int64_t n, Grid g, int k, const 
                             scan(a0, b0);
                         } else {
                             const int up = lev - 10;
-                            const int64_t x1 = min((ax + 1) << up, (int64_t)g.nx), y1 = min((ay + 1) << up, (int64_t)g.ny),
-                                          z1 = min((az + 1) << up, (int64_t)g.nz);
-                            for (int64_t qz = az << up; qz < z1; ++qz)
-                                for (int64_t qy = ay << up; qy < y1; ++qy)
-                                    for (int64_t qx = ax << up; qx < x1; ++qx) {
+                            const int x1 = min((ax + 1) << up, g.nx), y1 = min((ay + 1) << up, g.ny),
+                                      z1 = min((az + 1) << up, g.nz);
+                            for (int qz = az << up; qz < z1; ++qz)
+                                for (int qy = ay << up; qy < y1; ++qy)
+                                    for (int qx = ax << up; qx < x1; ++qx) {
                                         const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + qx;
                                         scan(cstart[cc], cend[cc]);
                                     }
