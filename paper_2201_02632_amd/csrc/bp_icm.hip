@@ -124,9 +124,12 @@ __device__ double solve_a(const HaloSolve &H, const double mu[7], double phif, d
         for (int k = 5; k >= 0; --k) { dF = dF * a + F; F = F * a + f[k]; }
         if (F > 0) lo = a; else hi = a;
         double an = a - F / dF;
-        if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
-        if (fabs(an - a) <= 1e-15 * an || hi - lo <= 1e-15 * hi) { a = an; break; }
+        const bool newton = an > lo && an < hi;
+        if (!newton) an = 0.5 * (lo + hi);
+        // a Newton step below 1e-9 relative leaves an error of order its square (the root is simple)
+        const bool conv = newton ? fabs(an - a) <= 1e-9 * an : hi - lo <= 1e-15 * hi;
         a = an;
+        if (conv) break;
     }
     return a;
 }
@@ -339,7 +342,8 @@ __global__ void __launch_bounds__(64) k_icm_solve(bp_params P, GaussRules G, int
             moments_at(mu_cur, x_cur, xf, mu);
         }
         Trial T = energy_trial(H, mu, xf, aguess);
-        aguess = T.a;
+        // the next point starts from the linear extrapolation of a along the uniform scan
+        aguess = k > 0 ? 2.0 * T.a - aprev : T.a;
         if (!isfinite(T.res)) { st |= BP_S_NONFINITE; break; }
         if (k > 0 && ((rprev < 0) != (T.res < 0))) {
             if (nchg == 0) {
