@@ -32,7 +32,8 @@ struct GaussRules {
     double x24[24], w24[24];
     double x12[12], w12[12];
     double x8[8], w8[8];
-    float u16[16], u24[24], u12[12], u8[8];   // (x + 1) / 2 in FP32: nodes on [0, 1]
+    double x20[20], w20[20];
+    float u16[16], u12[12], u8[8], u20[20];   // (x + 1) / 2 in FP32: nodes on [0, 1]
     double eta_top;                    // ln(1 + acosh(1e5)): zone-A grid end (r_perp = 1e-5 r_a)
 };
 

@@ -577,10 +577,11 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(GaussRules G, int64_t n,
         } else {
             // Gauss-Legendre order by the length xi of the s-interval: the worst relative error
             // over the benchmark's halo population stays below 1e-9 with 8 points up to xi = 1.4,
-            // 12 up to 4.6, 16 up to 7.6 and 24 beyond (sight lines through the core)
-            const int ng = xi > 7.6 ? 24 : (xi > 4.6 ? 16 : (xi > 1.4 ? 12 : 8));
-            const float *gu = ng == 24 ? G.u24 : (ng == 16 ? G.u16 : (ng == 12 ? G.u12 : G.u8));
-            const double *gw = ng == 24 ? G.w24 : (ng == 16 ? G.w16 : (ng == 12 ? G.w12 : G.w8));
+            // 12 up to 4.6 and 16 up to 7.6, and below 1e-8 with 20 beyond (sight lines within
+            // 1e-3 r_a of the centre)
+            const int ng = xi > 7.6 ? 20 : (xi > 4.6 ? 16 : (xi > 1.4 ? 12 : 8));
+            const float *gu = ng == 20 ? G.u20 : (ng == 16 ? G.u16 : (ng == 12 ? G.u12 : G.u8));
+            const double *gw = ng == 20 ? G.w20 : (ng == 16 ? G.w16 : (ng == 12 ? G.w12 : G.w8));
             const float rpf = (float)rp, raf = (float)ra, xif = (float)xi;
             for (int j = 0; j < ng; ++j) {
                 float r = fminf(rpf * cosh_f(xif * gu[j]), raf);
@@ -672,10 +673,11 @@ const GaussRules &gauss_rules() {
         gauss_legendre(24, G.x24, G.w24);
         gauss_legendre(12, G.x12, G.w12);
         gauss_legendre(8, G.x8, G.w8);
+        gauss_legendre(20, G.x20, G.w20);
         for (int j = 0; j < 16; ++j) G.u16[j] = (float)(0.5 * (G.x16[j] + 1.0));
-        for (int j = 0; j < 24; ++j) G.u24[j] = (float)(0.5 * (G.x24[j] + 1.0));
         for (int j = 0; j < 12; ++j) G.u12[j] = (float)(0.5 * (G.x12[j] + 1.0));
         for (int j = 0; j < 8; ++j) G.u8[j] = (float)(0.5 * (G.x8[j] + 1.0));
+        for (int j = 0; j < 20; ++j) G.u20[j] = (float)(0.5 * (G.x20[j] + 1.0));
         G.eta_top = log1p(acosh(1e5));
         init = true;
     }
