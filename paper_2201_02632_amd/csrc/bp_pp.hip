@@ -566,7 +566,9 @@ __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, i
                                                          const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ts,
                                                          const uint32_t *__restrict__ te, float *__restrict__ ymap,
                                                          float *__restrict__ bmap) {
-    __shared__ float wxs[kBatch][kWT], wys[kBatch][kWT];
+    // x-weights by particle; y-weights by row, a row's batch contiguous (16-byte reads)
+    __shared__ float wxs[kBatch][kWT];
+    __shared__ __attribute__((aligned(16))) float wys[kWT][kBatch];
     __shared__ float amp[kBatch][2];
     const uint32_t tile = blockIdx.x;
     const uint32_t p0 = ts[tile], p1 = te[tile];
@@ -605,11 +607,11 @@ __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, i
                         float e0 = (float)(row - R.jpx) - R.fpy;
                         v = cell_weight(e0 * R.ih, (e0 + 1.0f) * R.ih);
                     }
-                    wys[b][rr] = v;
+                    wys[rr][b] = v;
                 }
                 if (r == 0) { amp[b][0] = R.ay; amp[b][1] = R.ab; }
             } else {                      // unused slot of the last batch: zero weights
-                if (r < kWT) wxs[b][r] = 0.0f; else wys[b][r - kWT] = 0.0f;
+                if (r < kWT) wxs[b][r] = 0.0f; else wys[r - kWT][b] = 0.0f;
                 if (r == 0) { amp[b][0] = 0.0f; amp[b][1] = 0.0f; }
             }
         }
@@ -625,20 +627,22 @@ __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, i
         }
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            const int rr = (t >> 6) + 4 * k;
+            const int rr = (t >> 6) + 4 * k;   // wave-uniform: the row's weights are broadcast reads
+            float wy[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; b += 4) {
+                const float4 w4 = *reinterpret_cast<const float4 *>(&wys[rr][b]);
+                wy[b] = w4.x; wy[b + 1] = w4.y; wy[b + 2] = w4.z; wy[b + 3] = w4.w;
+            }
             float sy = 0.0f, sb = 0.0f;
-            bool any = false;
 #pragma unroll
             for (int b = 0; b < kBatch; ++b) {
-                const float wy = wys[b][rr];
-                any = any || (wy != 0.0f);
-                sy = fmaf(ax[b], wy, sy);
-                sb = fmaf(bx[b], wy, sb);
+                sy = fmaf(ax[b], wy[b], sy);
+                sb = fmaf(bx[b], wy[b], sb);
             }
-            if (any) {
-                kahan(ys[k], yc[k], sy);
-                kahan(bs[k], bc[k], sb);
-            }
+            // rows that no particle of the batch reaches add an exact zero
+            kahan(ys[k], yc[k], sy);
+            kahan(bs[k], bc[k], sb);
         }
     }
     for (int k = 0; k < 16; ++k) {
