@@ -110,18 +110,34 @@ __device__ inline void footprint_value(const Rec &R, const float *__restrict__ t
 }
 
 
+// acos on [-1, 1] from the Hastings approximation of Abramowitz & Stegun 4.4.46 (absolute error
+// below 2e-8 on [0, 1]): acos(x) = sqrt(1 - x) P(x) for x >= 0, pi - acos(-x) below.  Written for
+// x = 1 - 2q, q in [0, 1], where 1 - x = 2q and 1 + x = 2 (1 - q) keep their digits.
+__device__ inline float acos_1m2q(float q) {
+    const bool hi = q > 0.5f;
+    const float x = hi ? 2.0f * q - 1.0f : 1.0f - 2.0f * q;      // |1 - 2q|
+    const float t = hi ? 2.0f * (1.0f - q) : 2.0f * q;           // 1 - |1 - 2q|
+    float p = -0.0012624911f;
+    p = fmaf(p, x, 0.0066700901f); p = fmaf(p, x, -0.0170881256f); p = fmaf(p, x, 0.0308918810f);
+    p = fmaf(p, x, -0.0501743046f); p = fmaf(p, x, 0.0889789874f); p = fmaf(p, x, -0.2145988016f);
+    p = fmaf(p, x, 1.5707963050f);
+    const float a = hw_sqrt(t) * p;
+    return hi ? 3.14159265358979f - a : a;
+}
+
 // Surrogate tables: 64 nodes per quantity at q_k = (1 - cos(pi k/63))/2, q = r_perp/R_t,
 // interpolated in s = acos(1 - 2q)/pi.  R.eta_lo holds R_t and R.eta_ih 1/R_t (record units).
-// Y = P_e0 R_t E G(q) with E = sqrt(1 - r_perp^2 / r_f^2) = sqrt(U2) / r_f.
+// Y = P_e0 R_t E G(q) with E = sqrt(1 - r_perp^2 / r_f^2) = sqrt(U2) / r_f.  The surrogate's own
+// error (~1e-3) sets the precision here: hardware square roots and reciprocal.
 template <class Rec>
 __device__ inline void footprint_value_q(const Rec &R, const float *__restrict__ tab, float r2, float U2, float *vp,
                                          float *vn) {
-    float q = fminf(sqrtf(r2) * R.eta_ih, 1.0f);
-    float sidx = acosf(1.0f - 2.0f * q) * (63.0f / 3.14159265358979f);
+    const float q = fminf(hw_sqrt(r2) * R.eta_ih, 1.0f);
+    const float sidx = acos_1m2q(q) * (63.0f / 3.14159265358979f);
     float gp, gn;
     lagr4x2(tab, tab + BP_MLP_NQ, BP_MLP_NQ, sidx, &gp, &gn);
-    float E = sqrtf(fmaxf(U2, 0.0f)) / R.rf;
-    float f = R.eta_lo * E;
+    const float E = hw_sqrt(fmaxf(U2, 0.0f)) * hw_rcp(R.rf);
+    const float f = R.eta_lo * E;
     *vp = gp * f;
     *vn = gn * f;
 }
