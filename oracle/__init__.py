@@ -119,6 +119,8 @@ def lib():
             "orc_w_sph": (C.c_double, [C.c_double]),
             "orc_knn_h": (None, [C.c_int64, _D, _D, _D, C.c_int, _D]),
             "orc_knn_h_query": (None, [C.c_int64, _I64, C.c_int64, _D, _D, _D, C.c_int, _D]),
+            "orc_neff_h_query": (None, [C.c_int64, _I64, C.c_int64, _D, _D, _D, C.c_double, _D]),
+            "orc_neff_at": (C.c_double, [C.c_int64, _D, _D, _D, C.c_int64, C.c_double]),
             "orc_pp_amplitudes": (None, [P, C.c_int64, _D, _D, _I32, _D, C.c_double, C.c_double,
                                          H, _D, _D]),
             "orc_pp_deposit": (None, [C.c_int64, _D, _D, _D, _D, _D, C.c_int, C.c_double, _D, _D]),
@@ -315,6 +317,22 @@ def knn_h_query(qidx, X, Y, Z, k=32):
     h = np.empty(len(q))
     lib().orc_knn_h_query(len(q), q.ctypes.data_as(_I64), len(X), _dp(X), _dp(Y), _dp(Z), int(k), _dp(h))
     return h
+
+
+def neff_h_query(qidx, X, Y, Z, n_ngb=64.0):
+    """Smoothing length of X[qidx] with effective neighbour number n_ngb (Sec. 3.4): the root of
+    (32/3) sum_j W(r_ij / h) = n_ngb over all points, the point itself included."""
+    X, Y, Z = _f64(X), _f64(Y), _f64(Z)
+    q = np.ascontiguousarray(qidx, dtype=np.int64)
+    h = np.empty(len(q))
+    lib().orc_neff_h_query(len(q), q.ctypes.data_as(_I64), len(X), _dp(X), _dp(Y), _dp(Z), float(n_ngb), _dp(h))
+    return h
+
+
+def neff_at(X, Y, Z, i, h):
+    """N_eff(h) = (32/3) sum_j W(|x_j - x_i| / h) of point i."""
+    X, Y, Z = _f64(X), _f64(Y), _f64(Z)
+    return lib().orc_neff_at(len(X), _dp(X), _dp(Y), _dp(Z), int(i), float(h))
 
 
 def pp_amplitudes(p, halos, z, v, halo_id, r_i, M_p, pix_rad):

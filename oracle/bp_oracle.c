@@ -1064,6 +1064,57 @@ void orc_knn_h_query(int64_t nq, const int64_t *qidx, int64_t n, const double *X
     free(d);
 }
 
+/* Smoothing length from the effective neighbour number (Sec. 3.4, with the
+ * cubic-spline kernel of Eq. SPH_kernel): h solves
+ *     N_eff(h) = (4 pi / 3) h^3 sum_j W(r_ij, h) = n_ngb,
+ * W = 8/(pi h^3) orc_W_sph(r/h).  reading: the sum runs over every particle,
+ * the particle itself included (the standard SPH density estimate), so that
+ * N_eff(h) = (32/3) sum_j orc_W_sph(r_ij / h).  N_eff is continuous and
+ * non-decreasing in h; the root is found by bisection on the sorted distances
+ * of every point to the query (brute force, O(n log n) per query).  NaN when
+ * even all n points cannot reach n_ngb ((32/3) n <= n_ngb). */
+static double neff_sum(const double *d, int64_t m, double h)
+{
+    double s = 0.0;
+    for (int64_t j = 0; j < m && d[j] < h; j++) s += orc_W_sph(d[j] / h);
+    return 32.0 / 3.0 * s;
+}
+void orc_neff_h_query(int64_t nq, const int64_t *qidx, int64_t n, const double *X, const double *Y,
+                      const double *Z, double n_ngb, double *h)
+{
+    double *d = malloc(sizeof(double) * (n > 0 ? n : 1));
+    for (int64_t a = 0; a < nq; a++) {
+        int64_t i = qidx[a];
+        for (int64_t j = 0; j < n; j++) {
+            double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+            d[j] = sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        qsort(d, n, sizeof(double), cmp_double);
+        /* N_eff rises to (32/3) n as h grows: no root unless that exceeds n_ngb; otherwise
+         * double the upper end from twice the largest distance until it brackets the root */
+        if (32.0 / 3.0 * (double)n <= n_ngb) { h[a] = NAN; continue; }
+        double lo = 0.0, hi = 2.0 * d[n - 1] + 1e-300;
+        while (neff_sum(d, n, hi) < n_ngb) hi *= 2.0;
+        for (int it = 0; it < 400 && hi - lo > 1e-15 * hi; it++) {
+            double mid = 0.5 * (lo + hi);
+            if (neff_sum(d, n, mid) < n_ngb) lo = mid; else hi = mid;
+        }
+        h[a] = 0.5 * (lo + hi);
+    }
+    free(d);
+}
+
+/* N_eff(h) of one point: the quantity the smoothing length sets to n_ngb. */
+double orc_neff_at(int64_t n, const double *X, const double *Y, const double *Z, int64_t i, double h)
+{
+    double s = 0.0;
+    for (int64_t j = 0; j < n; j++) {
+        double dx = X[j] - X[i], dy = Y[j] - Y[i], dz = Z[j] - Z[i];
+        s += orc_W_sph(sqrt(dx * dx + dy * dy + dz * dz) / h);
+    }
+    return 32.0 / 3.0 * s;
+}
+
 /* Per-particle signal amplitudes (Sec. 3.4).
  * Halo particle (halo_id >= 0):
  *   y_i = sigma_T/(m_e c^2) P_e(r_i) V_i / L_pix^2,

@@ -357,3 +357,53 @@ def test_pp_amplitudes_definitions(orc, params):
     ref = orc.SIGMA_T * 400e5 / orc.C_CGS * fb * Mp * orc.MSUN / params.h / (2 / (1 + params.X_H) * orc.M_P) \
         * math.exp(-orc.tau(params, 0.7)) / Lf ** 2
     assert ay[4] == 0 and abs(ab[4] / ref - 1) < 1e-13
+
+
+# ---------------------------------------------------------- effective-neighbour smoothing length --
+# h solves N_eff(h) = (4 pi/3) h^3 sum_j W(r_ij, h) = (32/3) sum_j W_shape(r_ij/h), self included
+# (Sec. 3.4, Eq. SPH_kernel; reading: the standard SPH density sum).
+
+def _sphere(m, d, rng):
+    v = rng.normal(size=(m, 3))
+    v *= d / np.linalg.norm(v, axis=1)[:, None]
+    return np.vstack([np.zeros((1, 3)), v])       # the query at the origin, m points at distance d
+
+
+def test_neff_sphere_closed_forms(orc):
+    """m points at one distance d: N_eff = (32/3)(1 + m W(d/h)) = 64 gives W(d/h) = 5/m.  m = 10 lands
+    on the inner branch (1 - 6x^2 + 6x^3 = 1/2, a cubic solved by numpy), m = 40 on the outer one
+    (2 (1 - x)^3 = 1/8, x = 1 - 16^(-1/3)).  Dropping the self term, or the 32/3, moves both."""
+    rng = np.random.default_rng(41)
+    d = 0.37
+    P = _sphere(10, d, rng)
+    roots = np.roots([6.0, -6.0, 0.0, 0.5])
+    x = [r.real for r in roots if abs(r.imag) < 1e-12 and 0.0 < r.real < 0.5]
+    assert len(x) == 1
+    h = orc.neff_h_query([0], P[:, 0], P[:, 1], P[:, 2], 64.0)[0]
+    assert abs(h / (d / x[0]) - 1) < 1e-12
+    P = _sphere(40, d, rng)
+    h = orc.neff_h_query([0], P[:, 0], P[:, 1], P[:, 2], 64.0)[0]
+    assert abs(h / (d / (1.0 - 16.0 ** (-1.0 / 3.0))) - 1) < 1e-12
+
+
+def test_neff_lattice_continuum_limit(orc):
+    """On a simple cubic lattice the kernel-weighted count tends to the number of points in the
+    sphere, (4 pi/3)(h/a)^3 (the kernel integrates to one): within 1e-3 at N = 64, 200, 500."""
+    g = np.arange(-10, 11, dtype=np.float64)
+    X, Y, Z = [v.ravel() for v in np.meshgrid(g, g, g, indexing="ij")]
+    i0 = int(np.nonzero((X == 0) & (Y == 0) & (Z == 0))[0][0])
+    for N in (64.0, 200.0, 500.0):
+        h = orc.neff_h_query([i0], X, Y, Z, N)[0]
+        assert abs(h / (3 * N / (4 * np.pi)) ** (1.0 / 3.0) - 1) < 1e-3
+
+
+def test_neff_scaling_and_root(orc):
+    """Scaling every position by s scales h by s; at the returned h the count is n_ngb."""
+    rng = np.random.default_rng(42)
+    X, Y, Z = rng.random((3, 3000))
+    q = [0, 17, 999]
+    h = orc.neff_h_query(q, X, Y, Z, 64.0)
+    hs = orc.neff_h_query(q, 3.7 * X, 3.7 * Y, 3.7 * Z, 64.0)
+    assert np.all(np.abs(hs / (3.7 * h) - 1) < 1e-12)
+    for i, hh in zip(q, h):
+        assert abs(orc.neff_at(X, Y, Z, i, hh) - 64.0) < 1e-9
