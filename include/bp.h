@@ -219,6 +219,18 @@ int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, 
                            const float *z, int32_t k, double cell, float *h_comoving, void *ws, size_t ws_bytes,
                            size_t *ws_needed, void *stream);
 
+/* Smoothing length from the effective neighbour number (Sec. 3.4: h is set so that the effective
+ * number of particles within it is n_ngb, 64 in the paper): per particle, h solves
+ *     N_eff(h) = (4 pi / 3) h^3 sum_j W(|x_i - x_j|, h) = n_ngb,
+ * W the cubic spline of Eq. SPH_kernel with support h, the sum over every particle including i
+ * itself (the SPH density sum), i.e. (32/3) sum_j w(r_ij / h).  Positions, units, workspace and
+ * errors as bp_pp_smoothing_length (which runs first, for the 32-NN distance that seeds a
+ * bracketed Newton iteration on h, converged to 1e-6 relative).  n_ngb in (32/3, 1024]
+ * (BP_E_ARG otherwise); n > 32.  A particle whose root is not found writes NaN. */
+int bp_pp_smoothing_length_eff(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
+                               const float *z, double n_ngb, double cell, float *h_comoving, void *ws,
+                               size_t ws_bytes, size_t *ws_needed, void *stream);
+
 /* Particle-based pasting onto an npix x npix flat-sky map (Sec. 3.4):
  *   halo particle (halo_id >= 0): y_i = sigma_T/(m_e c^2) P_e(r_i) V_i / L_pix^2,
  *       b_i = sigma_T (v_i/c) e^-tau_i n_e(r_i) V_i / L_pix^2,  V_i = M_p / rho_NFW(r_i)
@@ -362,6 +374,7 @@ enum {
     BP_PROF_SURR_APPLY,     /* K10 epilogue: tables from the network output */
     BP_PROF_FLATQ_DEPOSIT,  /* K3 deposit from surrogate tables */
     BP_PROF_HPXQ_DEPOSIT,   /* K4 deposit from surrogate tables */
+    BP_PROF_PP_NEFF,        /* K6b k_pp_neff */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

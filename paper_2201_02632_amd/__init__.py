@@ -74,6 +74,8 @@ _SIGS = {
                                       _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_pp_smoothing_length": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, C.c_int32, C.c_double, _VP, _VP,
                                          C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_pp_smoothing_length_eff": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, C.c_double, C.c_double, _VP, _VP,
+                                             C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_pp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                    C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_size_t,
                                    C.POINTER(C.c_size_t), _VP]),
@@ -105,7 +107,7 @@ _SIGS = {
 }
 PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
                                           "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT", "MLP_FWD", "MLP_BWD",
-                                          "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT"])}
+                                          "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT", "PP_NEFF"])}
 MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
 S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
@@ -254,6 +256,19 @@ def pp_smoothing_length(params: Params, theta_x, theta_y, z, k: int = 32, cell: 
     if n:
         _with_workspace(_lib.bp_pp_smoothing_length, "bp_pp_smoothing_length", ws,
                         (C.byref(params), n, _ptr(theta_x), _ptr(theta_y), _ptr(z), int(k), float(cell), _ptr(h)))
+    return h
+
+
+def pp_smoothing_length_eff(params: Params, theta_x, theta_y, z, n_ngb: float = 64.0, cell: float = 0.0,
+                            ws: Workspace | None = None) -> torch.Tensor:
+    """K5+K6+K6b: smoothing length with effective neighbour number n_ngb [comoving Mpc/h]."""
+    n = theta_x.numel()
+    h = torch.empty(n, dtype=torch.float32, device=theta_x.device)
+    ws = ws or _ws_for(theta_x.device)
+    if n:
+        _with_workspace(_lib.bp_pp_smoothing_length_eff, "bp_pp_smoothing_length_eff", ws,
+                        (C.byref(params), n, _ptr(theta_x), _ptr(theta_y), _ptr(z), float(n_ngb), float(cell),
+                         _ptr(h)))
     return h
 
 

@@ -332,6 +332,140 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 3
     h_out[idx[i]] = h;
 }
 
+// ----------------------------------- K6b smoothing length from the effective neighbour number --
+// h solves N_eff(h) = (4 pi/3) h^3 sum_j W(r_ij, h) = (32/3) sum_j w(r_ij/h) = n_ngb (Sec. 3.4,
+// Eq. SPH_kernel), the particle itself included (the standard SPH density sum).  N_eff is continuous,
+// non-decreasing and once differentiable in h.  Newton on h, kept inside a bracket, starts from the
+// k-NN distance scaled to the target count; each evaluation sums the kernel and its h-derivative over
+// the particles of every cell within h, on the level whose cells are between h/2 and h wide.
+__device__ inline void wsph_slope(float x, float &w, float &sl) {   // w(x) and -x w'(x)
+    if (x < 0.5f) {
+        const float x2 = x * x;
+        w = fmaf(6.0f * x2, x - 1.0f, 1.0f);
+        sl = x2 * fmaf(-18.0f, x, 12.0f);
+    } else if (x < 1.0f) {
+        const float t = 1.0f - x;
+        w = 2.0f * t * t * t;
+        sl = 6.0f * x * t * t;
+    } else {
+        w = 0.0f; sl = 0.0f;
+    }
+}
+
+constexpr int kNeffIter = 60;
+constexpr int kNeffMaxShell = 4;
+
+__global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, float seed_scale,
+                                                 const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
+                                                 const double *__restrict__ sp, const uint32_t *__restrict__ cstart,
+                                                 const uint32_t *__restrict__ cend, float *__restrict__ h_io,
+                                                 int *__restrict__ fail) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t ki = key[i];
+    const uint64_t c = ki >> 30;
+    const int cx = (int)(c % g.nx), cy = (int)((c / g.nx) % g.ny), cz = (int)(c / ((uint64_t)g.nx * g.ny));
+    const double mex = sp[i], mey = sp[n + i], mez = sp[2 * n + i];
+    uint32_t m = (uint32_t)(ki & 0x3fffffffu), fx = 0, fy = 0, fz = 0;
+    for (int b = 0; b < 10; ++b) {
+        fx |= ((m >> (3 * b)) & 1u) << b;
+        fy |= ((m >> (3 * b + 1)) & 1u) << b;
+        fz |= ((m >> (3 * b + 2)) & 1u) << b;
+    }
+    const uint32_t oi = idx[i];
+    float h = h_io[oi] * seed_scale;
+    bool ok = h > 0.0f && isfinite(h);
+    float lo = 0.0f, hi = __builtin_inff();
+    bool conv = false;
+    for (int it = 0; it < kNeffIter && ok && !conv; ++it) {
+        // N_eff(h) and dN_eff/dh over the cells within h (cells h/2 to h wide: at most 2 cells out)
+        const int lev = min(max((int)ceilf(log2f(h / (float)g.cell)) + 9, 0), kMaxLevel);
+        const double s = ldexp(g.cell, lev - 10);
+        int gx, gy, gz, nxl, nyl, nzl;
+        if (lev <= 10) {
+            const int sh = 10 - lev;
+            gx = (cx << sh) + (int)(fx >> lev); gy = (cy << sh) + (int)(fy >> lev); gz = (cz << sh) + (int)(fz >> lev);
+            nxl = g.nx << sh; nyl = g.ny << sh; nzl = g.nz << sh;
+        } else {
+            const int up = lev - 10;
+            gx = cx >> up; gy = cy >> up; gz = cz >> up;
+            nxl = (g.nx + (1 << up) - 1) >> up; nyl = (g.ny + (1 << up) - 1) >> up; nzl = (g.nz + (1 << up) - 1) >> up;
+        }
+        const float ux = fminf(fmaxf((float)((mex - g.x0) / s - (double)gx), 0.0f), 1.0f);
+        const float uy = fminf(fmaxf((float)((mey - g.y0) / s - (double)gy), 0.0f), 1.0f);
+        const float uz = fminf(fmaxf((float)((mez - g.z0) / s - (double)gz), 0.0f), 1.0f);
+        const float sf = (float)s, h2 = h * h, ih = 1.0f / h;
+        const int rmax = (int)ceilf(h / sf);
+        if (rmax > kNeffMaxShell) { ok = false; break; }
+        float sw = 0.0f, ss = 0.0f;
+        auto scan = [&](uint32_t a0, uint32_t b0) {
+            for (uint32_t j = a0; j < b0; ++j) {
+                const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
+                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                if (r2 < h2) {
+                    float w, sl;
+                    wsph_slope(sqrtf(r2) * ih, w, sl);
+                    sw += w; ss += sl;
+                }
+            }
+        };
+        for (int dz = -rmax; dz <= rmax; ++dz) {
+            const int az = gz + dz;
+            if (az < 0 || az >= nzl) continue;
+            const float ez = dz > 0 ? dz - uz : (dz < 0 ? uz - dz - 1 : 0.0f);
+            for (int dy = -rmax; dy <= rmax; ++dy) {
+                const int ay = gy + dy;
+                if (ay < 0 || ay >= nyl) continue;
+                const float ey = dy > 0 ? dy - uy : (dy < 0 ? uy - dy - 1 : 0.0f);
+                for (int dx = -rmax; dx <= rmax; ++dx) {
+                    const int ax = gx + dx;
+                    if (ax < 0 || ax >= nxl) continue;
+                    const float ex = dx > 0 ? dx - ux : (dx < 0 ? ux - dx - 1 : 0.0f);
+                    // no particle of the cell within h (the factor absorbs FP32 rounding)
+                    if ((ex * ex + ey * ey + ez * ez) * sf * sf * 0.999998f >= h2) continue;
+                    if (lev <= 10) {
+                        const int sh = 10 - lev;
+                        const int ccx = ax >> sh, ccy = ay >> sh, ccz = az >> sh;
+                        const uint64_t cc = ((uint64_t)ccz * g.ny + ccy) * g.nx + ccx;
+                        uint32_t a0 = cstart[cc], b0 = cend[cc];
+                        if (a0 >= b0) continue;
+                        if (lev < 10) {
+                            const uint32_t lx = (uint32_t)(ax - (ccx << sh)) << lev, ly = (uint32_t)(ay - (ccy << sh)) << lev,
+                                           lz = (uint32_t)(az - (ccz << sh)) << lev;
+                            const uint64_t klo = (cc << 30) | morton3(lx, ly, lz);
+                            const uint64_t khi = klo + (1ull << (3 * lev));
+                            const uint32_t a1 = lower_bound64(key, a0, b0, klo);
+                            b0 = lower_bound64(key, a1, b0, khi);
+                            a0 = a1;
+                        }
+                        scan(a0, b0);
+                    } else {
+                        const int up = lev - 10;
+                        const int x1 = min((ax + 1) << up, g.nx), y1 = min((ay + 1) << up, g.ny), z1 = min((az + 1) << up, g.nz);
+                        for (int qz = az << up; qz < z1; ++qz)
+                            for (int qy = ay << up; qy < y1; ++qy)
+                                for (int qx = ax << up; qx < x1; ++qx) {
+                                    const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + qx;
+                                    scan(cstart[cc], cend[cc]);
+                                }
+                    }
+                }
+            }
+        }
+        const float F = (32.0f / 3.0f) * sw, dF = (32.0f / 3.0f) * ss * ih;
+        if (F < nngb) lo = h; else hi = h;
+        float hn = dF > 0.0f ? h - (F - nngb) / dF : 2.0f * h;
+        const bool newton = hn > lo && hn < hi && hn <= 2.0f * h;
+        if (!newton) hn = isinf(hi) ? 2.0f * h : 0.5f * (lo + hi);
+        // a Newton step below 1e-6 relative: N_eff is differentiable, the remaining error its square
+        conv = newton && fabsf(hn - h) <= 1e-6f * h;
+        if (!newton && !isinf(hi) && hi - lo <= 1e-6f * hi) conv = true;
+        h = hn;
+    }
+    if (!(ok && conv)) atomicOr(fail, 1);
+    h_io[oi] = (ok && conv) ? h : __int_as_float(0x7fc00000);
+}
+
 // ---------------------------------------------------- K7 amplitudes --
 struct PPRec {        // per-particle deposit record (40 bytes)
     int32_t ipx, jpx; // particle position in pixel units: integer part ...
@@ -658,9 +792,10 @@ __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, i
 
 using namespace bp;
 
-extern "C" int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
-                                      const float *z, int32_t k, double cell, float *h_comoving, void *ws,
-                                      size_t ws_bytes, size_t *ws_needed, void *stream) {
+// k-NN distance (n_ngb == 0) or, from it, the effective-neighbour smoothing length (n_ngb > 0)
+static int smoothing_length_impl(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
+                                 const float *z, int32_t k, double n_ngb, double cell, float *h_comoving, void *ws,
+                                 size_t ws_bytes, size_t *ws_needed, void *stream) {
     if (!p || n < 0 || k < 1 || k > kKmax || !ws_needed || !(cell >= 0.0)) return BP_E_ARG;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     if (!theta_x || !theta_y || !z || !h_comoving) return BP_E_ARG;
@@ -743,7 +878,30 @@ extern "C" int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float
         hipLaunchKernelGGL(k_pp_knn<64>, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving,
                            fail);
     prof_end(BP_PROF_PP_KNN, s);
+    if (n_ngb > 0.0) {
+        // seed: the k-NN distance scaled by (n_ngb / k)^(1/3), the uniform-density ratio
+        const float seed = (float)cbrt(n_ngb / (double)k);
+        prof_begin(BP_PROF_PP_NEFF, s);
+        hipLaunchKernelGGL(k_pp_neff, dim3(blocks), dim3(256), 0, s, n, g, (float)n_ngb, seed, ks, vs, sp, cs, ce,
+                           h_comoving, fail);
+        prof_end(BP_PROF_PP_NEFF, s);
+    }
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
+                                      const float *z, int32_t k, double cell, float *h_comoving, void *ws,
+                                      size_t ws_bytes, size_t *ws_needed, void *stream) {
+    return smoothing_length_impl(p, n, theta_x, theta_y, z, k, 0.0, cell, h_comoving, ws, ws_bytes, ws_needed,
+                                 stream);
+}
+
+extern "C" int bp_pp_smoothing_length_eff(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
+                                          const float *z, double n_ngb, double cell, float *h_comoving, void *ws,
+                                          size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (!(n_ngb > 32.0 / 3.0 + 1e-3) || !(n_ngb <= 1024.0)) return BP_E_ARG;
+    return smoothing_length_impl(p, n, theta_x, theta_y, z, 32, n_ngb, cell, h_comoving, ws, ws_bytes, ws_needed,
+                                 stream);
 }
 
 extern "C" int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const float *theta_x,

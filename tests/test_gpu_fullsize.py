@@ -95,7 +95,8 @@ def _chi_table(om=0.3, zmax=2.0, n=200001):
 
 
 def test_pp_fullsize_sampled_smoothing_lengths(bp, orc):
-    """32-NN smoothing lengths of the 2e8-particle light cone (the benchmark's draws and call),
+    """32-NN smoothing lengths of the 2e8-particle light cone (the benchmark's draws and call), and
+    the smoothing lengths with effective neighbour number 64 of the same particles,
     checked on query particles in two comoving boxes: one around a random field particle and one
     around the most massive halo's centre (the densest core).  Candidate neighbours are every
     particle in a box three times wider; each query's oracle distance must stay inside it."""
@@ -106,6 +107,10 @@ def test_pp_fullsize_sampled_smoothing_lengths(bp, orc):
     h = bp.pp_smoothing_length(bp.default_params(), parts["theta_x"], parts["theta_y"], parts["z"], 32)
     torch.cuda.synchronize()
     h = h.cpu().numpy().astype(np.float64)
+    # the effective-neighbour smoothing length (N_eff = 64) on the same particles
+    he = bp.pp_smoothing_length_eff(bp.default_params(), parts["theta_x"], parts["theta_y"], parts["z"], 64.0)
+    torch.cuda.synchronize()
+    he = he.cpu().numpy().astype(np.float64)
     tx = parts["theta_x"].cpu().numpy()
     ty = parts["theta_y"].cpu().numpy()
     zp = parts["z"].cpu().numpy()
@@ -152,6 +157,14 @@ def test_pp_fullsize_sampled_smoothing_lengths(bp, orc):
         print(f"box L={L}: {len(cand)} candidates, {len(q)} queries, h {ho.min():.3g}-{ho.max():.3g} Mpc/h, "
               f"max rel err {err:.2e}", flush=True)
         assert np.all(np.isfinite(hg)) and err < 2e-6
+        # effective neighbour number 64: every particle within h lies inside the candidate box
+        hoe = orc.neff_h_query(q, X[cand], Y[cand], Z[cand], 64.0)
+        assert np.all(hoe < margin), "candidate box too small for the sampled queries"
+        hge = he[sel][cand][q]
+        erre = np.max(np.abs(hge / hoe - 1))
+        print(f"box L={L}: N_eff = 64 smoothing h {hoe.min():.3g}-{hoe.max():.3g} Mpc/h, max rel err {erre:.2e}",
+              flush=True)
+        assert np.all(np.isfinite(hge)) and erre < 2e-6
 
 
 def test_hp_healpix_fullsize_sampled_pixels(bp, orc):

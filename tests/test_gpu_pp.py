@@ -79,6 +79,55 @@ def test_knn_density_contrast(bp, orc):
     assert np.max(np.abs(h / h_o - 1)) < 2e-6
 
 
+@pytest.mark.parametrize("cell", [0.0, 6.0])
+def test_neff_smoothing_matches_oracle(bp, orc, small_case, cell):
+    """Smoothing length from the effective neighbour number 64 (Sec. 3.4) against the oracle's
+    bisection over every particle, on 1,500 sampled particles of the small light cone."""
+    import torch
+    pr = small_case["parts"]
+    p = orc.default_params()
+    tx, ty, z = (np.asarray(pr[k], dtype=np.float32) for k in ("theta_x", "theta_y", "z"))
+    chi = np.array([orc.chi(p, float(zz)) for zz in z])
+    X, Y, Z = chi * tx.astype(np.float64), chi * ty.astype(np.float64), chi
+    h = bp.pp_smoothing_length_eff(bp.default_params(), T(tx), T(ty), T(z), 64.0, cell)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy().astype(np.float64)
+    q = np.random.default_rng(31).choice(len(z), 1500, replace=False)
+    ho = orc.neff_h_query(q, X, Y, Z, 64.0)
+    err = np.max(np.abs(h[q] / ho - 1))
+    print(f"N_eff smoothing cell={cell}: max rel err {err:.2e}; h/h_32NN median {np.median(h / small_case['h']):.3f}")
+    assert np.all(np.isfinite(h)) and err < 2e-6
+
+
+def test_neff_density_contrast_and_args(bp, orc):
+    """The same on clustered blobs (1e4 x denser) over a sparse background, every point; and the
+    argument range of the effective neighbour number."""
+    import torch
+    rng = np.random.default_rng(10)
+    chi0 = 800.0
+    pts = [rng.uniform([0, 0, chi0], [40, 40, chi0 + 40], size=(3000, 3))]
+    for c in rng.uniform([5, 5, chi0 + 5], [35, 35, chi0 + 35], size=(5, 3)):
+        pts.append(c + rng.normal(scale=0.05, size=(400, 3)))
+    P = np.concatenate(pts)
+    p = orc.default_params()
+    zs = np.linspace(0.2, 0.35, 4001)
+    chis = np.array([orc.chi(p, z) for z in zs])
+    z = np.interp(P[:, 2], chis, zs).astype(np.float32)
+    tx = (P[:, 0] / P[:, 2]).astype(np.float32)
+    ty = (P[:, 1] / P[:, 2]).astype(np.float32)
+    chi_exact = np.array([orc.chi(p, float(zz)) for zz in z])
+    X, Y, Z = chi_exact * tx, chi_exact * ty, chi_exact
+    h = bp.pp_smoothing_length_eff(bp.default_params(), T(tx), T(ty), T(z), 64.0)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy().astype(np.float64)
+    ho = orc.neff_h_query(np.arange(len(z)), X, Y, Z, 64.0)
+    assert ho.max() / ho.min() > 30
+    assert np.max(np.abs(h / ho - 1)) < 2e-6
+    for bad in (10.0, 2000.0, float("nan")):
+        with pytest.raises(RuntimeError):
+            bp.pp_smoothing_length_eff(bp.default_params(), T(tx), T(ty), T(z), bad)
+
+
 def test_pp_map_parity(bp, small_case):
     import torch
     c = small_case
