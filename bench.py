@@ -306,10 +306,21 @@ def pp_section(bp, params, dev, steps, warmup, n_particles):
     ms = timed(step, steps, warmup, bp)
     kt = kernel_times(bp, ("PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT"), steps)
     bp._lib.bp_profiling(0)
+
+    # the paper's own smoothing length (effective neighbour number 64) on the same particles,
+    # timed on its own: sort + 32-NN seed + Newton on the kernel-weighted count
+    def neff():
+        bp.pp_smoothing_length_eff(params, parts["theta_x"], parts["theta_y"], parts["z"], 64.0, 0.0, ws=ws)
+
+    ms_neff = timed(neff, 1, 1, bp)
+    kt_neff = kernel_times(bp, ("PP_SORT", "PP_KNN", "PP_NEFF"), 1)
+    bp._lib.bp_profiling(0)
     return {"workload": f"PP flat-sky 5x5 deg, 4096^2 pixels, z in [0.05,1.5]: {n} FP32 particles, 60% in 2e5 "
                         "triaxial NFW halos, 40% lognormal field; 32-NN smoothing, cubic-spline kernel",
             "particles_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 2), "n_particles": n,
-            "halo_solve_ms": round(solve_ms, 2), "kernel_ms": kt, "generation_s": round(gen_s, 1)}
+            "halo_solve_ms": round(solve_ms, 2), "kernel_ms": kt, "generation_s": round(gen_s, 1),
+            "smoothing_neff64": {"ms": round(ms_neff, 2), "particles_per_s": round(n / (ms_neff * 1e-3), 1),
+                                 "kernel_ms": kt_neff}}
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):

@@ -335,20 +335,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 3
 // ----------------------------------- K6b smoothing length from the effective neighbour number --
 // h solves N_eff(h) = (4 pi/3) h^3 sum_j W(r_ij, h) = (32/3) sum_j w(r_ij/h) = n_ngb (Sec. 3.4,
 // Eq. SPH_kernel), the particle itself included (the standard SPH density sum).  N_eff is continuous,
-// non-decreasing and once differentiable in h.  Newton on h, kept inside a bracket, starts from the
-// k-NN distance scaled to the target count; each evaluation sums the kernel and its h-derivative over
+// non-decreasing and once differentiable in h.  Halley's iteration on h, kept inside a bracket, starts
+// from the k-NN distance scaled to the target count; each evaluation sums the kernel and its h-derivatives over
 // the particles of every cell within h, on the level whose cells are between h/2 and h wide.
-__device__ inline void wsph_slope(float x, float &w, float &sl) {   // w(x) and -x w'(x)
+// w(x), g(x) = -x w'(x) and g(x) + x g'(x), which give N_eff and its first two h-derivatives:
+// dN/dh = (32/3) sum g / h,  d2N/dh2 = -(32/3) sum (g + x g') / h^2
+__device__ inline void wsph_slope(float x, float &w, float &g, float &c) {
     if (x < 0.5f) {
         const float x2 = x * x;
         w = fmaf(6.0f * x2, x - 1.0f, 1.0f);
-        sl = x2 * fmaf(-18.0f, x, 12.0f);
+        g = x2 * fmaf(-18.0f, x, 12.0f);
+        c = x2 * fmaf(-72.0f, x, 36.0f);
     } else if (x < 1.0f) {
         const float t = 1.0f - x;
         w = 2.0f * t * t * t;
-        sl = 6.0f * x * t * t;
+        g = 6.0f * x * t * t;
+        c = 12.0f * x * t * (1.0f - 2.0f * x);
     } else {
-        w = 0.0f; sl = 0.0f;
+        w = 0.0f; g = 0.0f; c = 0.0f;
     }
 }
 
@@ -397,15 +401,15 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
         const float sf = (float)s, h2 = h * h, ih = 1.0f / h;
         const int rmax = (int)ceilf(h / sf);
         if (rmax > kNeffMaxShell) { ok = false; break; }
-        float sw = 0.0f, ss = 0.0f;
+        float sw = 0.0f, ss = 0.0f, sc = 0.0f;
         auto scan = [&](uint32_t a0, uint32_t b0) {
             for (uint32_t j = a0; j < b0; ++j) {
                 const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
                 const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                 if (r2 < h2) {
-                    float w, sl;
-                    wsph_slope(sqrtf(r2) * ih, w, sl);
-                    sw += w; ss += sl;
+                    float w, gs, cs;
+                    wsph_slope(sqrtf(r2) * ih, w, gs, cs);
+                    sw += w; ss += gs; sc += cs;
                 }
             }
         };
@@ -452,14 +456,16 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
                 }
             }
         }
-        const float F = (32.0f / 3.0f) * sw, dF = (32.0f / 3.0f) * ss * ih;
+        const float F = (32.0f / 3.0f) * sw, dF = (32.0f / 3.0f) * ss * ih, d2F = -(32.0f / 3.0f) * sc * ih * ih;
         if (F < nngb) lo = h; else hi = h;
-        float hn = dF > 0.0f ? h - (F - nngb) / dF : 2.0f * h;
-        const bool newton = hn > lo && hn < hi && hn <= 2.0f * h;
-        if (!newton) hn = isinf(hi) ? 2.0f * h : 0.5f * (lo + hi);
-        // a Newton step below 1e-6 relative: N_eff is differentiable, the remaining error its square
-        conv = newton && fabsf(hn - h) <= 1e-6f * h;
-        if (!newton && !isinf(hi) && hi - lo <= 1e-6f * hi) conv = true;
+        // Halley's step (third-order; the second derivative jumps only where a neighbour crosses h/2)
+        const float Fm = F - nngb, den = 2.0f * dF * dF - Fm * d2F;
+        float hn = (dF > 0.0f && den > 0.0f) ? h - 2.0f * Fm * dF / den : 2.0f * h;
+        const bool step = hn > lo && hn < hi && hn <= 2.0f * h;
+        if (!step) hn = isinf(hi) ? 2.0f * h : 0.5f * (lo + hi);
+        // a step below 1e-6 relative: the remaining error is of the order of its square or less
+        conv = step && fabsf(hn - h) <= 1e-6f * h;
+        if (!step && !isinf(hi) && hi - lo <= 1e-6f * hi) conv = true;
         h = hn;
     }
     if (!(ok && conv)) atomicOr(fail, 1);
