@@ -30,11 +30,11 @@ PEAK_VALU_TOPS = 78.6
 # amplitudes 2, two Kahan updates 8.
 DEPOSIT_OPS_PER_PX = 62
 # HBM bytes per deposit launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99995, WRITE x 1.0).
+# dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99994, WRITE x 1.0).
 # Valid only for the deposit sources they were measured on.
-DEPOSIT_TRAFFIC = {"bytes": 2766008447,
+DEPOSIT_TRAFFIC = {"bytes": 2764357289,
                    "sources_sha256": {"bp_hp_flat.hip": "a977c8b93b476740819387a5d26b3644417df726bc70fa53ac350f24960c236a",
-                                      "bp_footprint.hpp": "35d33ce511c89eeb488fa21835c5972f0abce7925ab5fc191d6c0b4f649086a7"}}
+                                      "bp_footprint.hpp": "374420bbded5ba853b5cd3a269dd4630a7c515106c295c3df380ba07f8f94c80"}}
 
 
 def deposit_traffic():
