@@ -124,6 +124,8 @@ def lib():
             "orc_pp_amplitudes": (None, [P, C.c_int64, _D, _D, _I32, _D, C.c_double, C.c_double,
                                          H, _D, _D]),
             "orc_pp_deposit": (None, [C.c_int64, _D, _D, _D, _D, _D, C.c_int, C.c_double, _D, _D]),
+            "orc_pp_healpix_ngp": (None, [P, C.c_int64, _D, _D, _D, _D, C.c_double, C.c_int64, _I64, _D]),
+            "orc_pp_healpix_ngp_map": (None, [P, C.c_int64, _D, _D, _D, _D, C.c_double, C.c_int64, _D, _D]),
             "orc_sizeof_halo": (C.c_int, []),
             "orc_sizeof_params": (C.c_int, []),
         }
@@ -352,6 +354,27 @@ def pp_deposit(thx, thy, H, amp_y, amp_b, npix, pix_rad):
     b = np.zeros(npix * npix)
     lib().orc_pp_deposit(len(arrs[0]), *[_dp(a) for a in arrs], int(npix), float(pix_rad), _dp(y), _dp(b))
     return y.reshape(npix, npix), b.reshape(npix, npix)
+
+
+def pp_healpix_ngp(p, theta, phi, z, v, M_p, nside):
+    """Per-particle (RING pixel, kSZ amplitude) of the all-sky nearest-pixel paste (App. A)."""
+    arrs = [_f64(a) for a in (theta, phi, z, v)]
+    n = len(arrs[0])
+    pix = np.empty(n, dtype=np.int64)
+    amp = np.empty(n)
+    lib().orc_pp_healpix_ngp(C.byref(p), n, *[_dp(a) for a in arrs], float(M_p), int(nside),
+                             pix.ctypes.data_as(_I64), _dp(amp))
+    return pix, amp
+
+
+def pp_healpix_ngp_map(p, theta, phi, z, v, M_p, nside):
+    """All-sky kSZ map by nearest-pixel assignment (App. A) and the per-pixel sum of |b_i|."""
+    arrs = [_f64(a) for a in (theta, phi, z, v)]
+    b = np.zeros(12 * nside * nside)
+    babs = np.zeros(12 * nside * nside)
+    lib().orc_pp_healpix_ngp_map(C.byref(p), len(arrs[0]), *[_dp(a) for a in arrs], float(M_p), int(nside),
+                                 _dp(b), _dp(babs))
+    return b, babs
 
 
 # constants used by the tests' closed forms (the oracle's own copies, CODATA 2018 / IAU)

@@ -1185,6 +1185,48 @@ void orc_pp_deposit(int64_t n, const double *thx, const double *thy, const doubl
     }
 }
 
+/* All-sky particle kSZ by nearest-pixel assignment (App. A, continuous light cone):
+ * every particle is a field particle (Eq. field_b, field_y) and its whole amplitude goes to
+ * one HEALPix RING pixel.
+ * Reading: the nearest pixel is the pixel that contains the particle's direction (the
+ * HEALPix ang2pix assignment), and the pixel area at the particle is L_pix^2 = D_A^2 Omega_pix
+ * with the equal pixel solid angle Omega_pix = 4 pi / (12 N_side^2).
+ * Outputs per particle: pix[i] (RING index, -1 for a colatitude outside [0, pi] or a
+ * non-finite angle, which then deposits nothing) and amp[i] = b_i. */
+void orc_pp_healpix_ngp(const orc_params *p, int64_t n, const double *theta, const double *phi,
+                        const double *zp, const double *v, double M_p, int64_t nside,
+                        int64_t *pix, double *amp)
+{
+    double omega_pix = 4.0 * ORC_PI / (12.0 * (double)nside * (double)nside);
+    int32_t field = -1;
+    double zero = 0.0, ay;
+    for (int64_t i = 0; i < n; i++) {
+        int ok = theta[i] >= 0.0 && theta[i] <= ORC_PI && isfinite(phi[i]);
+        pix[i] = ok ? orc_ang2pix_ring(nside, theta[i], phi[i]) : -1;
+        orc_pp_amplitudes(p, 1, &zp[i], &v[i], &field, &zero, M_p, sqrt(omega_pix), NULL, &ay, &amp[i]);
+        if (!ok) amp[i] = 0.0;
+    }
+}
+
+/* The map itself: b_map[pix] += b_i in particle order (b_map has 12 N_side^2 entries and
+ * ACCUMULATES); babs_map (may be NULL) receives sum |b_i| per pixel, the scale of the
+ * rounding error of any summation order. */
+void orc_pp_healpix_ngp_map(const orc_params *p, int64_t n, const double *theta, const double *phi,
+                            const double *zp, const double *v, double M_p, int64_t nside,
+                            double *b_map, double *babs_map)
+{
+    int64_t *pix = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    double *amp = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    orc_pp_healpix_ngp(p, n, theta, phi, zp, v, M_p, nside, pix, amp);
+    for (int64_t i = 0; i < n; i++) {
+        if (pix[i] < 0) continue;
+        b_map[pix[i]] += amp[i];
+        if (babs_map) babs_map[pix[i]] += fabs(amp[i]);
+    }
+    free(pix);
+    free(amp);
+}
+
 /* size of orc_halo for the binding to check its mirror */
 int orc_sizeof_halo(void) { return (int)sizeof(orc_halo); }
 int orc_sizeof_params(void) { return (int)sizeof(orc_params); }

@@ -407,3 +407,86 @@ def test_neff_scaling_and_root(orc):
     assert np.all(np.abs(hs / (3.7 * h) - 1) < 1e-12)
     for i, hh in zip(q, h):
         assert abs(orc.neff_at(X, Y, Z, i, hh) - 64.0) < 1e-9
+
+
+# ------------------------------------------------------ all-sky nearest-pixel kSZ (App. A) --
+def _ring_centres(N):
+    """RING-ordered pixel centres (z = cos theta, phi) from the closed forms of Gorski et al. (2005):
+    polar rings z = 1 - i^2/(3N^2), phi = pi/(2i) (j - 1/2); belt rings z = 4/3 - 2i/(3N) with
+    4N centres spaced pi/(2N), starting at phi = 0 on rings with i - N odd and half a spacing later
+    on the others (so the four equatorial base pixels of N = 1 sit at phi = 0, pi/2, pi, 3pi/2 and
+    the polar ones at pi/4 + k pi/2); the south cap mirrors the north."""
+    zs, phis = [], []
+    for i in range(1, 4 * N):
+        if i < N or i > 3 * N:
+            k = i if i < N else 4 * N - i
+            z = 1 - k * k / (3.0 * N * N)
+            z = z if i < N else -z
+            j = np.arange(1, 4 * k + 1)
+            phi = math.pi / (2 * k) * (j - 0.5)
+        else:
+            z = 4.0 / 3 - 2.0 * i / (3 * N)
+            j = np.arange(1, 4 * N + 1)
+            phi = math.pi / (2 * N) * (j - (1.0 if (i - N) % 2 else 0.5))
+        zs.append(np.full(len(j), z))
+        phis.append(phi)
+    return np.concatenate(zs), np.concatenate(phis)
+
+
+def _unit(z, phi):
+    s = np.sqrt(np.maximum(0.0, 1 - z * z))
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z], axis=1)
+
+
+@pytest.mark.parametrize("N", [1, 4, 8])
+def test_ngp_pixel_is_nearest_centre(orc, params, N):
+    # directions within a tenth of a pixel of a pixel centre land in that pixel, which is also the
+    # pixel with the nearest centre found by brute force over all 12 N^2 centres
+    zc, phic = _ring_centres(N)
+    assert len(zc) == 12 * N * N
+    rng = np.random.default_rng(11)
+    pick = rng.integers(0, len(zc), 600)
+    c = _unit(zc[pick], phic[pick])
+    t = rng.normal(size=c.shape)
+    t -= (t * c).sum(1)[:, None] * c
+    t /= np.linalg.norm(t, axis=1)[:, None]
+    d = 0.1 * math.sqrt(4 * math.pi / (12 * N * N)) * rng.random(len(pick))[:, None]
+    u = c * np.cos(d) + t * np.sin(d)
+    theta = np.arccos(np.clip(u[:, 2], -1, 1))
+    phi = np.arctan2(u[:, 1], u[:, 0])
+    pix, _ = orc.pp_healpix_ngp(params, theta, phi, np.full(len(pick), 0.5), np.full(len(pick), 100.0), 1e10, N)
+    nearest = np.argmax(u @ _unit(zc, phic).T, axis=1)
+    assert np.array_equal(pix, pick)
+    assert np.array_equal(pix, nearest)
+
+
+def test_ngp_amplitude_and_map_invariants(orc, params):
+    # b_i = sigma_T (v/c) (f_gas M_p/(mu_e m_p)) e^-tau / (D_A^2 Omega_pix), Omega_pix = 4 pi/(12 N^2)
+    # (Eq. field_b with the HEALPix pixel area); the whole amplitude in one pixel
+    N, Mp = 16, 3.1e10
+    rng = np.random.default_rng(5)
+    n = 400
+    theta = np.arccos(rng.uniform(-1, 1, n))
+    phi = rng.uniform(-4, 10, n)
+    z = rng.uniform(0.01, 3.7, n)
+    v = rng.normal(0, 300, n)
+    theta[:3] = [0.0, math.pi, -0.1]                  # both poles are valid; a negative colatitude is not
+    pix, amp = orc.pp_healpix_ngp(params, theta, phi, z, v, Mp, N)
+    u = orc.MPC / params.h
+    fb = params.Omega_b / params.Omega_m
+    omega = math.pi / (3 * N * N)
+    for i in (0, 1, 7, 100):
+        ref = orc.SIGMA_T * v[i] * 1e5 / orc.C_CGS * fb * Mp * orc.MSUN / params.h \
+            / (2 / (1 + params.X_H) * orc.M_P) * math.exp(-orc.tau(params, z[i])) / ((orc.D_A(params, z[i]) * u) ** 2 * omega)
+        assert abs(amp[i] / ref - 1) < 1e-13
+    assert pix[0] < 4 and 12 * N * N - 4 <= pix[1] < 12 * N * N       # first and last ring hold 4 pixels
+    assert pix[2] == -1 and amp[2] == 0
+    b, babs = orc.pp_healpix_ngp_map(params, theta, phi, z, v, Mp, N)
+    assert abs(b.sum() - amp.sum()) < 1e-12 * np.abs(amp).sum()
+    assert abs(babs.sum() - np.abs(amp).sum()) < 1e-12 * np.abs(amp).sum()
+    b2, _ = orc.pp_healpix_ngp_map(params, theta, phi, z, -v, Mp, N)
+    assert np.array_equal(b2, -b)
+    # the map is additive over particle subsets
+    bA, _ = orc.pp_healpix_ngp_map(params, theta[:150], phi[:150], z[:150], v[:150], Mp, N)
+    bB, _ = orc.pp_healpix_ngp_map(params, theta[150:], phi[150:], z[150:], v[150:], Mp, N)
+    assert np.allclose(bA + bB, b, rtol=0, atol=1e-13 * np.abs(amp).max())
