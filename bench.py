@@ -323,6 +323,42 @@ def pp_section(bp, params, dev, steps, warmup, n_particles):
                                  "kernel_ms": kt_neff}}
 
 
+def ngp_section(bp, params, dev, steps, warmup, n_particles, nside):
+    """All-sky particle kSZ by nearest-pixel assignment (App. A): one call pastes a batch of
+    n_particles of a continuous light cone to z = 3.741 onto HEALPix N_side pixels."""
+    import torch
+
+    from paper_2201_02632_amd.synth import ALLSKY_MP, allsky_lightcone_device
+    t0 = time.perf_counter()
+    parts = allsky_lightcone_device(n_particles, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    n = parts["theta"].numel()
+    print(f"# NGP: {n} particles drawn in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    npx = 12 * nside * nside
+    b = torch.zeros(npx, dtype=torch.float32, device=dev)
+    ws = bp.Workspace(dev)
+
+    def step():
+        bp.pp_paste_healpix_ngp(params, nside, parts["theta"], parts["phi"], parts["z"], parts["v_los"], ALLSKY_MP,
+                                b, ws=ws)
+
+    ms = timed(step, steps, warmup, bp)
+    kt = kernel_times(bp, ("NGP_PLAN", "NGP_DEPOSIT"), steps)
+    bp._lib.bp_profiling(0)
+    # algorithmic HBM bytes: the four input floats of every particle once, the map read and written once
+    alg = 16 * n + 8 * npx
+    gbs = alg / (ms * 1e-3) / 1e9
+    del parts, ws
+    return {"workload": f"all-sky PP kSZ, nearest HEALPix pixel (N_side {nside}, RING): {n} FP32 particles of a "
+                        "continuous light cone to z = 3.741 (uniform in comoving volume, half in 1000-particle "
+                        "clumps)", "particles_per_s": round(n / (ms * 1e-3), 1), "ms_per_step": round(ms, 3),
+            "n_particles": n, "kernel_ms": kt, "generation_s": round(gen_s, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "whole step",
+                         "bytes_per_unit": 16, "units": n, "unit_name": "particle (+ 8 B per map pixel)"}}
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """Plain device-to-device copies of a known size: each launch reads and writes exactly
     nbytes, which fixes the scale of the FETCH_SIZE / WRITE_SIZE counters."""
@@ -346,9 +382,9 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the warmup and timed steps of each section, print per-kernel times and stop (for "
                          "hardware-counter passes under a profiler: no error maps or other reporting kernels)")
-    ap.add_argument("--sections", default="surrogate,allsky,pp",
-                    help="extra measured sections after the headline one: surrogate, allsky, pp (comma list, or "
-                         "none)")
+    ap.add_argument("--sections", default="surrogate,allsky,pp,ngp",
+                    help="extra measured sections after the headline one: surrogate, allsky, pp, ngp (comma list, "
+                         "or none)")
     ap.add_argument("--sky-halos", type=int, default=100_000_000)
     ap.add_argument("--sky-batch", type=int, default=10_000_000)
     ap.add_argument("--nside", type=int, default=8192)
@@ -357,6 +393,8 @@ def main():
     ap.add_argument("--sur-train", type=int, default=1_000_000)
     ap.add_argument("--sur-steps", type=int, default=20_000)
     ap.add_argument("--pp-particles", type=int, default=200_000_000)
+    ap.add_argument("--ngp-particles", type=int, default=1_000_000_000)
+    ap.add_argument("--ngp-nside", type=int, default=1024)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (reference reading for HBM byte counters)")
     args = ap.parse_args()
@@ -425,6 +463,9 @@ def main():
                 torch.cuda.empty_cache()
         if "pp" in secs:
             res["pp"] = pp_section(bp, params, dev, args.extra_steps, 1, args.pp_particles)
+            torch.cuda.empty_cache()
+        if "ngp" in secs:
+            res["ngp"] = ngp_section(bp, params, dev, args.extra_steps, 1, args.ngp_particles, args.ngp_nside)
         print(json.dumps(res), flush=True)
         return
     nsolved = int((st == 0).sum().item())
@@ -472,6 +513,9 @@ def main():
         torch.cuda.empty_cache()
     if "pp" in sections:
         out["pp"] = pp_section(bp, params, dev, args.extra_steps, 1, args.pp_particles)
+        torch.cuda.empty_cache()
+    if "ngp" in sections:
+        out["ngp"] = ngp_section(bp, params, dev, args.extra_steps, 1, args.ngp_particles, args.ngp_nside)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)

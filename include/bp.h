@@ -251,6 +251,26 @@ int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n
                      const int32_t *status, float *y_map, float *b_map, void *ws, size_t ws_bytes,
                      size_t *ws_needed, void *stream);
 
+/* All-sky particle kSZ by nearest-pixel assignment (App. A, the continuous light cone): every
+ * particle is a field particle (Eq. field_b),
+ *     b_i = sigma_T (v_i/c) (field_gas_frac M_p / (mu_e m_p)) e^-tau_i / L_pix^2,
+ *     L_pix^2 = D_A(z_i)^2 Omega_pix,  Omega_pix = 4 pi / (12 nside^2),
+ * and the whole b_i goes to the RING pixel that contains the direction (theta_i, phi_i), the
+ * pixel bp_healpix_ang2pix_ring gives for the FP64 images of the two floats.
+ *   nside      : 1 .. 2048
+ *   theta, phi : device, n floats [rad]; colatitude in [0, pi] (the float nearest pi lies above pi
+ *                and is rejected), longitude any finite value
+ *   z          : device, n floats in [0, 16);  v_los: device, n floats [km/s];  M_p [Msun/h] > 0
+ *   b_map      : device, 12 nside^2 floats in RING order; ACCUMULATES: each call adds, per pixel,
+ *                the FP64 sum of its particles' amplitudes, rounded once to FP32.  The order of the
+ *                FP64 sum is not fixed, so two calls can differ by one FP32 rounding of a pixel.
+ * Workspace protocol as for the pastes (about 12 n bytes); one synchronisation, after which the
+ * map is written.  Returns BP_E_ARG for an invalid argument or any invalid particle (the map is
+ * then unchanged), BP_E_OVERFLOW for n >= 2^31 - 1. */
+int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_t n, const float *theta, const float *phi,
+                            const float *z, const float *v_los, double M_p, float *b_map, void *ws,
+                            size_t ws_bytes, size_t *ws_needed, void *stream);
+
 /* ------------------------------------------------- surrogate (K10-K12) */
 /* A multilayer perceptron maps normalised (log10 M, ln c, z) to the projected
  * electron pressure and density of the halo on a fixed grid of 64 impact
@@ -375,6 +395,8 @@ enum {
     BP_PROF_FLATQ_DEPOSIT,  /* K3 deposit from surrogate tables */
     BP_PROF_HPXQ_DEPOSIT,   /* K4 deposit from surrogate tables */
     BP_PROF_PP_NEFF,        /* K6b k_pp_neff */
+    BP_PROF_NGP_PLAN,       /* K13 pixel indices + tile counting sort + amplitudes */
+    BP_PROF_NGP_DEPOSIT,    /* K13 k_ngp_deposit */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

@@ -79,6 +79,8 @@ _SIGS = {
     "bp_pp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                    C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, C.c_size_t,
                                    C.POINTER(C.c_size_t), _VP]),
+    "bp_pp_paste_healpix_ngp": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, C.c_double, _VP, _VP,
+                                          C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_mlp_nparams": (C.c_int64, []),
     "bp_mlp_act_bytes": (C.c_size_t, [C.c_int64]),
     "bp_mlp_backward_ws_bytes": (C.c_size_t, [C.c_int64]),
@@ -107,7 +109,8 @@ _SIGS = {
 }
 PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
                                           "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT", "MLP_FWD", "MLP_BWD",
-                                          "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT", "PP_NEFF"])}
+                                          "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT", "PP_NEFF", "NGP_PLAN",
+                                          "NGP_DEPOSIT"])}
 MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
 S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
@@ -284,6 +287,20 @@ def pp_paste_flat(params: Params, npix: int, pix_rad: float, parts: dict, h, M_p
                     (C.byref(params), int(npix), float(pix_rad), n, _ptr(parts["theta_x"]), _ptr(parts["theta_y"]),
                      _ptr(parts["z"]), _ptr(parts["v_los"]), _ptr(parts["halo_id"]), _ptr(parts["r_i"]), _ptr(h),
                      float(M_p), nh, sp, stp, _ptr(y_map), _ptr(b_map)))
+
+
+def pp_paste_healpix_ngp(params: Params, nside: int, theta, phi, z, v_los, M_p: float, b_map,
+                         ws: Workspace | None = None):
+    """K13: accumulate the nearest-pixel kSZ of field particles into b_map (12 nside^2 float32, RING)."""
+    n = theta.numel()
+    for t in (theta, phi, z, v_los, b_map):
+        assert t.dtype == torch.float32, "float32 tensors expected"
+    assert phi.numel() == n and z.numel() == n and v_los.numel() == n
+    assert b_map.numel() == 12 * nside * nside or not 1 <= nside <= 2048, "b_map must hold 12 nside^2 pixels"
+    ws = ws or _ws_for(b_map.device)
+    _with_workspace(_lib.bp_pp_paste_healpix_ngp, "bp_pp_paste_healpix_ngp", ws,
+                    (C.byref(params), int(nside), n, _ptr(theta), _ptr(phi), _ptr(z), _ptr(v_los), float(M_p),
+                     _ptr(b_map)))
 
 
 def pp_flat_map(params: Params, halos: dict, parts: dict, M_p: float, npix: int, pix_rad: float, k: int = 32,

@@ -49,6 +49,9 @@ int radix_sort_u64(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64
 void prof_begin(int id, hipStream_t s);
 void prof_end(int id, hipStream_t s);
 
+// chi(z) and tau(z) on the uniform grid of bp_cosmo.hpp (kNZ doubles each).
+int cosmo_tables(const bp_params &P, double *chi_t, double *tau_t, hipStream_t s);
+
 // Fill n uint32 with a value (a kernel, safe under graph capture).
 int fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 

@@ -23,15 +23,13 @@
 #include <math.h>
 #include <string.h>
 
+#include "bp_cosmo.hpp"
 #include "bp_device.hpp"
 #include "bp_internal.hpp"
 
 namespace bp {
 
 // ------------------------------------------------------ cosmology tables --
-constexpr int kNZ = 16384;
-constexpr double kZmax = 16.0;
-
 // chi(z)/(c/H0) and the optical-depth integral on a uniform z grid (24-point GL per cell from the previous node)
 __global__ void k_cosmo_table(bp_params P, GaussRules G, double *__restrict__ chi_t, double *__restrict__ tau_t) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,15 +50,9 @@ __global__ void k_cosmo_table(bp_params P, GaussRules G, double *__restrict__ ch
     tau_t[i] = kSigmaT * ne_bar * (kC / H0) * 0.5 * z * a2;
 }
 
-// cubic Lagrange interpolation on the uniform table
-__device__ inline double table_interp(const double *__restrict__ t, double z) {
-    double s = z * ((kNZ - 1) / kZmax);
-    int i = (int)floor(s);
-    i = min(max(i, 1), kNZ - 3);
-    double f = s - i;
-    double w0 = -f * (f - 1.0) * (f - 2.0) / 6.0, w1 = (f + 1.0) * (f - 1.0) * (f - 2.0) * 0.5;
-    double w2 = -(f + 1.0) * f * (f - 2.0) * 0.5, w3 = (f + 1.0) * f * (f - 1.0) / 6.0;
-    return w0 * t[i - 1] + w1 * t[i] + w2 * t[i + 1] + w3 * t[i + 2];
+int cosmo_tables(const bp_params &P, double *chi_t, double *tau_t, hipStream_t s) {
+    hipLaunchKernelGGL(k_cosmo_table, dim3((kNZ + 255) / 256), dim3(256), 0, s, P, gauss_rules(), chi_t, tau_t);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
 // ------------------------------------------------------------- K5 sort --

@@ -346,3 +346,59 @@ def pp_large_device(seed=3, n_particles=200_000_000, device="cuda"):
     halos, parts, M_p = pp_lightcone_device(200_000, int(0.6 * n_particles), int(0.4 * n_particles), 5.0,
                                             zr=(0.05, 1.5), seed=seed, device=device)
     return halos, parts, M_p, 4096, 5.0 * DEG / 4096
+
+
+# ------------------------------------------------- all-sky continuous light cone --
+# Stand-in for the continuous light-cone output of App. A (all sky to z = 3.741, a 1 Gpc/h box of
+# 512^3 particles replicated around the observer; particles recorded where they cross the past
+# light cone).  Positions are uniform in comoving volume inside chi(z_max), a fraction of them in
+# Gaussian clumps; the particle mass is that of the 512^3-in-(1 Gpc/h)^3 run.
+ALLSKY_ZMAX = 3.741
+ALLSKY_MP = 0.3 * 2.775e11 * 1000.0 ** 3 / 512 ** 3          # Omega_m rho_crit0 V / N  [Msun/h]
+_PI_BELOW_F32 = float(np.nextafter(np.float32(np.pi), np.float32(0.0)))
+
+
+def allsky_lightcone_device(n, zmax=ALLSKY_ZMAX, clustered=0.5, per_clump=1000, clump_sigma=1.0, v_sigma=300.0,
+                            om=0.3, seed=7, device="cuda", chunk=1 << 25):
+    """``n`` particles of an all-sky light cone to ``zmax``: float32 device tensors theta (colatitude,
+    at most the float just below pi), phi in (-pi, pi], z and v_los [km/s].  A fraction ``clustered``
+    sits in clumps of ``per_clump`` particles (isotropic Gaussian, comoving sigma ``clump_sigma``
+    Mpc/h) whose centres are uniform in volume; the rest is uniform in volume.  Velocities are
+    N(0, v_sigma) per particle plus an N(0, v_sigma) bulk shared by a clump.  Particle order is
+    clump members first, then the uniform part, both in draw order."""
+    import torch
+    zt, chit = _chi_table(om, zmax=max(5.0, zmax + 1.0))
+    f64 = dict(dtype=torch.float64, device=device)
+    zt_t, chit_t = torch.as_tensor(zt, **f64), torch.as_tensor(chit, **f64)
+    chi_max = float(np.interp(zmax, zt, chit))
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    n_cl = int(round(clustered * n))
+    n_clumps = max(1, -(-n_cl // per_clump)) if n_cl else 0
+
+    def ball(m):
+        r = chi_max * torch.rand(m, generator=g, **f64) ** (1.0 / 3.0)
+        u = torch.randn((m, 3), generator=g, **f64)
+        return u / torch.linalg.norm(u, dim=1, keepdim=True) * r[:, None]
+
+    centres = ball(n_clumps) if n_clumps else None
+    bulk = torch.randn(n_clumps, generator=g, **f64) * v_sigma if n_clumps else None
+    out = {k: [] for k in ("theta", "phi", "z", "v_los")}
+    for s0 in range(0, n, chunk):
+        m = min(chunk, n - s0)
+        v = torch.randn(m, generator=g, **f64) * v_sigma
+        ncl = max(0, min(m, n_cl - s0))
+        X = torch.empty((m, 3), **f64)
+        if ncl:
+            cid = torch.arange(s0, s0 + ncl, device=device) // per_clump
+            X[:ncl] = centres[cid] + torch.randn((ncl, 3), generator=g, **f64) * clump_sigma
+            v[:ncl] += bulk[cid]
+        if m > ncl:
+            X[ncl:] = ball(m - ncl)
+        r = torch.linalg.norm(X, dim=1).clamp_min(1e-9)
+        out["theta"].append(torch.acos((X[:, 2] / r).clamp(-1.0, 1.0)).float().clamp(0.0, _PI_BELOW_F32))
+        out["phi"].append(torch.atan2(X[:, 1], X[:, 0]).float())
+        out["z"].append(_interp_t(r, chit_t, zt_t).float())
+        out["v_los"].append(v.float())
+        del X, r, v
+    return {k: torch.cat(v).contiguous() for k, v in out.items()}

@@ -1,0 +1,144 @@
+"""GPU parity of the all-sky nearest-pixel particle kSZ paste (K13, App. A) against the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5      # per pixel, relative to the pixel's sum of |b_i| (the scale of any rounding in the sum)
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_02632_amd as bp
+    return bp
+
+
+def draw(n, seed, **kw):
+    from paper_2201_02632_amd.synth import allsky_lightcone_device
+    p = allsky_lightcone_device(n, seed=seed, device="cpu", **kw)
+    return {k: v.numpy() for k, v in p.items()}
+
+
+def gpu_map(bp, params, nside, parts, M_p, b=None):
+    import torch
+    t = {k: torch.as_tensor(v, device="cuda").contiguous() for k, v in parts.items()}
+    if b is None:
+        b = torch.zeros(12 * nside * nside, dtype=torch.float32, device="cuda")
+    bp.pp_paste_healpix_ngp(params, nside, t["theta"], t["phi"], t["z"], t["v_los"], M_p, b)
+    torch.cuda.synchronize()
+    return b
+
+
+def check(g, o, oabs):
+    g = g.cpu().numpy().astype(np.float64)
+    err = np.abs(g - o)
+    bad = err > TOL * oabs + 1e-30
+    assert not bad.any(), f"{bad.sum()} pixels off, worst {np.max(err / (oabs + 1e-300)):.3e}"
+    return float(np.max(err / np.where(oabs > 0, oabs, np.inf)))
+
+
+@pytest.mark.parametrize("nside,n,seed", [(1, 3000, 1), (3, 20000, 2), (64, 200000, 3), (100, 150000, 4),
+                                          (1024, 300000, 5)])
+def test_ngp_matches_oracle(bp, orc, nside, n, seed):
+    from paper_2201_02632_amd.synth import ALLSKY_MP
+    print(f"ngp parity nside={nside} n={n} seed={seed}", flush=True)
+    parts = draw(n, seed)
+    p = orc.default_params()
+    o, oabs = orc.pp_healpix_ngp_map(p, parts["theta"], parts["phi"], parts["z"], parts["v_los"], ALLSKY_MP, nside)
+    g = gpu_map(bp, bp.default_params(), nside, parts, ALLSKY_MP)
+    err = check(g, o, oabs)
+    print(f"ngp nside={nside} n={n}: max err / sum|b| {err:.2e}; pixels hit {np.count_nonzero(oabs)}")
+    # with every amplitude positive, the hit pixels are exactly the oracle's (pixel indices bit-exact)
+    pos = dict(parts, v_los=np.abs(parts["v_los"]) + 1.0)
+    gp = gpu_map(bp, bp.default_params(), nside, pos, ALLSKY_MP).cpu().numpy()
+    op, _ = orc.pp_healpix_ngp_map(p, pos["theta"], pos["phi"], pos["z"], pos["v_los"], ALLSKY_MP, nside)
+    assert np.array_equal(gp > 0, op > 0)
+
+
+def test_ngp_accumulates_and_sign(bp, orc):
+    from paper_2201_02632_amd.synth import ALLSKY_MP
+    nside = 32
+    parts = draw(50000, 6)
+    params = bp.default_params()
+    b1 = gpu_map(bp, params, nside, parts, ALLSKY_MP)
+    b2 = gpu_map(bp, params, nside, parts, ALLSKY_MP, b1.clone())
+    p = orc.default_params()
+    o, oabs = orc.pp_healpix_ngp_map(p, parts["theta"], parts["phi"], parts["z"], parts["v_los"], ALLSKY_MP, nside)
+    check(b2, 2 * o, 2 * oabs)
+    bn = gpu_map(bp, params, nside, dict(parts, v_los=-parts["v_los"]), ALLSKY_MP)
+    check(bn, -o, oabs)
+    # a pixel's sum does not depend on how the particles are ordered or split between calls
+    perm = np.random.default_rng(0).permutation(len(parts["z"]))
+    sh = {k: v[perm] for k, v in parts.items()}
+    half = len(perm) // 2
+    bs = gpu_map(bp, params, nside, {k: v[:half] for k, v in sh.items()}, ALLSKY_MP)
+    bs = gpu_map(bp, params, nside, {k: v[half:] for k, v in sh.items()}, ALLSKY_MP, bs)
+    check(bs, o, oabs)
+
+
+def test_ngp_poles_and_single_particles(bp, orc):
+    from paper_2201_02632_amd.synth import ALLSKY_MP
+    p = orc.default_params()
+    th = np.array([0.0, np.float32(np.pi) - np.float32(3e-7), 1.5707964, 0.7], np.float32)
+    ph = np.array([0.0, -3.0, 6.2831855, -1e4], np.float32)
+    parts = dict(theta=th, phi=ph, z=np.array([0.01, 3.7, 15.9, 0.001], np.float32),
+                 v_los=np.array([100.0, -300.0, 50.0, 1.0], np.float32))
+    for nside in (1, 2, 2048):
+        o, oabs = orc.pp_healpix_ngp_map(p, th, ph, parts["z"], parts["v_los"], ALLSKY_MP, nside)
+        g = gpu_map(bp, bp.default_params(), nside, parts, ALLSKY_MP)
+        check(g, o, oabs)
+        one = gpu_map(bp, bp.default_params(), nside, {k: v[:1] for k, v in parts.items()}, ALLSKY_MP)
+        assert np.count_nonzero(one.cpu().numpy()) == 1
+
+
+def test_ngp_invalid_inputs_leave_map_unchanged(bp):
+    import torch
+    from paper_2201_02632_amd.synth import ALLSKY_MP
+    params = bp.default_params()
+    parts = draw(5000, 8)
+    nside = 16
+    ref = gpu_map(bp, params, nside, parts, ALLSKY_MP)
+    for key, idx, val in (("theta", 17, -0.01), ("theta", 4000, np.float32(np.pi)), ("theta", 5, np.nan),
+                          ("phi", 99, np.inf), ("z", 2500, 16.0), ("z", 3, -0.5)):
+        bad = {k: v.copy() for k, v in parts.items()}
+        bad[key][idx] = val
+        b = ref.clone()
+        with pytest.raises(bp.BPError):
+            gpu_map(bp, params, nside, bad, ALLSKY_MP, b)
+        assert torch.equal(b, ref), key
+    x = torch.zeros(10, dtype=torch.float32, device="cuda")
+    for ns in (0, 4096):
+        with pytest.raises(bp.BPError):
+            bp.pp_paste_healpix_ngp(params, ns, x, x, x, x, ALLSKY_MP, torch.zeros(12, device="cuda"))
+    e = torch.zeros(0, dtype=torch.float32, device="cuda")
+    b = ref.clone()
+    bp.pp_paste_healpix_ngp(params, nside, e, e, e, e, ALLSKY_MP, b)
+    assert torch.equal(b, ref)
+
+
+@pytest.mark.parametrize("nside", [1, 5, 1024, 2048])
+def test_ngp_directions_next_to_pixel_edges(bp, orc, nside):
+    # directions within ~1e-6 of the cap/belt boundary |z| = 2/3, of belt ring edges and of the
+    # meridians that bound pixels in the caps: every particle must land in the oracle's pixel
+    # (a wrong neighbour would move a whole amplitude and break the per-pixel bound)
+    from paper_2201_02632_amd.synth import ALLSKY_MP
+    rng = np.random.default_rng(nside)
+    m = 60000
+    zb = np.concatenate([np.full(m, 2.0 / 3), np.full(m, -2.0 / 3),
+                         1 - (rng.integers(1, nside + 1, m) ** 2) / (3.0 * nside * nside),
+                         4.0 / 3 - 2.0 * rng.integers(nside, 3 * nside + 1, m) / (3.0 * nside)])
+    z = np.clip(zb + rng.normal(0, 1e-6, len(zb)), -1, 1)
+    theta = np.arccos(z)
+    phi = np.concatenate([rng.uniform(-np.pi, np.pi, 2 * m),
+                          rng.integers(0, 8 * nside, 2 * m) * np.pi / (4 * nside) + rng.normal(0, 1e-6, 2 * m)])
+    parts = dict(theta=np.minimum(theta, np.pi - 1e-6).astype(np.float32), phi=phi.astype(np.float32),
+                 z=rng.uniform(0.05, 3.7, len(z)).astype(np.float32),
+                 v_los=rng.normal(0, 300, len(z)).astype(np.float32))
+    p = orc.default_params()
+    o, oabs = orc.pp_healpix_ngp_map(p, parts["theta"], parts["phi"], parts["z"], parts["v_los"], ALLSKY_MP, nside)
+    g = gpu_map(bp, bp.default_params(), nside, parts, ALLSKY_MP)
+    err = check(g, o, oabs)
+    print(f"ngp edges nside={nside}: max err / sum|b| {err:.2e}")
