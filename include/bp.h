@@ -271,6 +271,15 @@ int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_t n, const 
                             const float *z, const float *v_los, double M_p, float *b_map, void *ws,
                             size_t ws_bytes, size_t *ws_needed, void *stream);
 
+/* Self-check of the error bounds behind bp_pp_paste_healpix_ngp's bit-exact pixel indices: over
+ * every float colatitude in [0, pi) it measures, against FP64 cos, sin and sqrt, the largest error of
+ * the FP32 hardware cos(theta) and of the cap factor N sin(theta) sqrt(3 / (1 + |cos theta|))
+ * (divided by N, where |cos theta| > 0.66).  bounds (host, 4 doubles, OUTPUT): measured z error,
+ * measured cap-factor error / N, then the two bounds the paste assumes.  A measured value above
+ * its bound would mean the paste's pixel indices can differ from the FP64 assignment.
+ * nside in [1, 2048]; synchronises the stream; allocates 8 bytes of device memory. */
+int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *stream);
+
 /* ------------------------------------------------- surrogate (K10-K12) */
 /* A multilayer perceptron maps normalised (log10 M, ln c, z) to the projected
  * electron pressure and density of the halo on a fixed grid of 64 impact

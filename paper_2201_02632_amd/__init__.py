@@ -81,6 +81,7 @@ _SIGS = {
                                    C.POINTER(C.c_size_t), _VP]),
     "bp_pp_paste_healpix_ngp": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, C.c_double, _VP, _VP,
                                           C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_pp_healpix_ngp_selfcheck": (C.c_int, [C.c_int64, C.POINTER(C.c_double), _VP]),
     "bp_mlp_nparams": (C.c_int64, []),
     "bp_mlp_act_bytes": (C.c_size_t, [C.c_int64]),
     "bp_mlp_backward_ws_bytes": (C.c_size_t, [C.c_int64]),
@@ -301,6 +302,14 @@ def pp_paste_healpix_ngp(params: Params, nside: int, theta, phi, z, v_los, M_p: 
     _with_workspace(_lib.bp_pp_paste_healpix_ngp, "bp_pp_paste_healpix_ngp", ws,
                     (C.byref(params), int(nside), n, _ptr(theta), _ptr(phi), _ptr(z), _ptr(v_los), float(M_p),
                      _ptr(b_map)))
+
+
+def pp_healpix_ngp_selfcheck(nside: int = 1024):
+    """Measured (z error, cap-factor error / N) of the nearest-pixel paste's FP32 screen and the
+    bounds it assumes, over every float colatitude."""
+    out = (C.c_double * 4)()
+    _check(_lib.bp_pp_healpix_ngp_selfcheck(int(nside), out, _stream()), "bp_pp_healpix_ngp_selfcheck")
+    return {"z_err": out[0], "tmp_err_per_n": out[1], "z_bound": out[2], "tmp_bound_per_n": out[3]}
 
 
 def pp_flat_map(params: Params, halos: dict, parts: dict, M_p: float, npix: int, pix_rad: float, k: int = 32,

@@ -6,7 +6,7 @@
 // The map is cut into tiles of 8192 consecutive RING pixels (a strip of about two rings), small
 // enough that one workgroup holds a tile's FP64 sums in LDS.  The particles are bucketed by tile
 // with a one-digit counting sort, so no pass uses global atomics:
-//   pix      one lane per particle: ang2pix with the trigonometry in FP32 and an error bound; the
+//   pix      one lane per particle: ang2pix with hardware trigonometry and an error bound; the
 //            few directions too close to a pixel edge for that bound are queued in LDS and run
 //            through the FP64 reference, so every index equals the pixelisation entry point's.
 //            Each block counts its chunk per tile in LDS and writes one row of a [block][tile]
@@ -20,6 +20,7 @@
 //            tile's pixels adding each sum to the FP32 map (one rounding per pixel and call).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <string.h>
 
 #include "bp_cosmo.hpp"
 #include "bp_device.hpp"
@@ -35,48 +36,67 @@ constexpr int kGroup = 64;                 // blocks per group of the column sca
 constexpr int kDepThreads = 1024;
 constexpr uint32_t kNoPix = 0xffffffffu;
 
-// RING pixel of one direction with the costly FP64 steps (cos, sin, square root) in FP32.  The
-// FP64 reference computes a few floors of FP64 quantities; here the quantities that depend on
-// cos(theta) or sin(theta) carry an error bound, and the result is the reference's whenever every
-// floor argument lies farther than its bound from an integer and |z| is not within its bound of
-// 2/3.  Otherwise the function returns false and the caller runs the FP64 reference.  The bounds
-// assume FP32 cosf/sinf within 8 ulp and sqrtf/division within 2 ulp; the slack is about 4x.
-constexpr float kZErr = 5e-7f;       // |cosf(theta) - cos(theta)|
-constexpr double kTmpRel = 1.5e-6;   // relative error of N sin(theta) sqrt(3 / (1 + |z|)) in FP32
+// RING pixel of one direction without FP64 trigonometry.  The FP64 reference takes a few floors of
+// FP64 quantities; here cos(theta) and the cap factor N sin(theta) sqrt(3 / (1 + |z|)) come from the
+// hardware sine and cosine, tt = phi / (pi/2) from one FP32 product, and each floor argument
+// carries an error bound.  The result is the reference's whenever every argument lies farther than
+// its bound from an integer and |z| farther than its bound from 2/3; otherwise the function
+// returns false and the caller runs the FP64 reference.  The trigonometric bounds hold over every
+// float in [0, pi] with a margin of about 4 (bp_pp_healpix_ngp_selfcheck measures them); the tt
+// bound is that of two FP32 roundings.
+constexpr float kZErr = 1e-6f;        // |z_hw - cos(theta)|
+constexpr double kTmpAbs = 1.5e-6;    // |tmp_hw - tmp| / N, tmp = N sin(theta) sqrt(3 / (1 + |z|))
+constexpr double kTmpRel = 2e-7;      // the final product by N
+constexpr double kTtRel = 2.5e-7;     // |tt_f32 - tt| / |tt|
 
 __device__ inline double dist_int(double x) { return fabs(x - rint(x)); }
 
-__device__ inline bool ang2pix_ring_fast(int64_t N, float thf, float phf, int64_t &pix) {
+__device__ inline void ngp_trig(int N, float thf, float &zf, float &tmpf) {
 #pragma clang fp contract(off)
-    const double halfpi = 1.5707963267948966;
-    const float zf = cosf(thf), zaf = fabsf(zf);
-    double tt = (double)phf / halfpi;
-    const double q = floor(tt / 4.0);
-    tt = tt - 4.0 * q;
-    if (tt >= 4.0) tt = 0.0;
+    zf = __cosf(thf);
+    tmpf = (float)N * (__sinf(thf) * __fsqrt_rn(3.0f / (1.0f + fabsf(zf))));
+}
+
+// N <= 2048 here, so every ring and pixel index fits in 32 bits and the reference's modulo
+// reductions reduce to one conditional add or subtract over the ranges they can take
+__device__ inline bool ang2pix_ring_fast(int N, float thf, float phf, int &pix) {
+#pragma clang fp contract(off)
+    float zf, tmpf;
+    ngp_trig(N, thf, zf, tmpf);
+    const float zaf = fabsf(zf);
+    const float ttf = phf * 0.636619772f;                       // phi / (pi/2)
+    const double ett = fabs((double)ttf) * kTtRel + 1e-300;
+    const double t4 = (double)ttf * 0.25;
+    if (dist_int(t4) <= 0.25 * ett + 1e-15) return false;      // the wrap below must match
+    const double tt = (double)ttf - 4.0 * floor(t4);             // exact; |tt - tt_ref| <= ett
     if (fabsf(zaf - 0.6666667f) <= 2.0f * kZErr) return false;
     if (zaf <= 0.6666667f) {
+        // belt: a in [N/2, 9N/2), |b| <= N/2, so both floors lie in [0, 5N) and ip in [-N/2, 9N/2 + 1)
         const double a = (double)N * (0.5 + tt);
         const double b = (double)N * ((double)zf * 0.75);
-        const double eb = (double)N * (0.75 * (double)kZErr) + 1e-9;
+        const double eb = (double)N * (0.75 * (double)kZErr + ett) + 1e-9;
         const double x1 = a - b, x2 = a + b;
         if (dist_int(x1) <= eb || dist_int(x2) <= eb) return false;
-        const int64_t asc = (int64_t)floor(x1), dsc = (int64_t)floor(x2);
-        const int64_t ir = N + 1 + asc - dsc;
-        const int64_t odd = 1 - (ir & 1);
-        int64_t ip = (asc + dsc - N + odd + 1) / 2;
-        ip = ((ip % (4 * N)) + 4 * N) % (4 * N);
+        const int asc = (int)floor(x1), dsc = (int)floor(x2);
+        const int ir = N + 1 + asc - dsc;
+        const int odd = 1 - (ir & 1);
+        int ip = (asc + dsc - N + odd + 1) / 2;
+        if (ip < 0) ip += 4 * N;
+        else if (ip >= 4 * N) ip -= 4 * N;
         pix = 2 * N * (N - 1) + (ir - 1) * 4 * N + ip;
         return true;
     }
+    // caps: tt in [0, 4), so floor(tt ir) lies in [0, 4 ir]
+    if (dist_int(tt) <= ett + 1e-15) return false;
     const double tf = tt - floor(tt);
-    const float tmpf = (float)N * (sinf(thf) * sqrtf(3.0f / (1.0f + zaf)));
-    const double ec = (double)tmpf * kTmpRel + 1e-9;
+    const double ec = (double)N * kTmpAbs + (double)tmpf * (kTmpRel + 1.01 * ett) + 1e-9;
     const double x1 = tf * (double)tmpf, x2 = (1.0 - tf) * (double)tmpf;
     if (dist_int(x1) <= ec || dist_int(x2) <= ec) return false;
-    const int64_t ir = (int64_t)floor(x1) + (int64_t)floor(x2) + 1;
-    int64_t ip = (int64_t)floor(tt * (double)ir);
-    ip = ((ip % (4 * ir)) + 4 * ir) % (4 * ir);
+    const int ir = (int)floor(x1) + (int)floor(x2) + 1;
+    const double xi = tt * (double)ir;
+    if (dist_int(xi) <= (double)ir * ett + 1e-9) return false;
+    int ip = (int)floor(xi);
+    if (ip >= 4 * ir) ip -= 4 * ir;
     pix = zf > 0.0f ? 2 * ir * (ir - 1) + ip : 12 * N * N - 2 * ir * (ir + 1) + ip;
     return true;
 }
@@ -121,8 +141,8 @@ __global__ void __launch_bounds__(256) k_ngp_pix(int64_t N, int64_t n, int64_t c
             if (i >= i1) break;
             uint32_t p = kNoPix;
             if ((double)t[u] >= 0.0 && (double)t[u] <= kPi && isfinite(f[u])) {
-                int64_t pp;
-                if (!ang2pix_ring_fast(N, t[u], f[u], pp)) {
+                int pp;
+                if (!ang2pix_ring_fast((int)N, t[u], f[u], pp)) {
                     queue[atomicAdd(&qn, 1)] = (uint32_t)(i - i0);   // at most 256 kU per round: fits
                     continue;
                 }
@@ -205,38 +225,88 @@ __global__ void k_ngp_gtable(const double *__restrict__ chi_t, const double *__r
     G[k] = (float)(r * r * exp(-table_interp(tau_t, z)));
 }
 
-// amp_k = sigma_T (1 km/s / c) f_gas M_p / (mu_e m_p) / ((Mpc/h)^2 Omega_pix)
-__global__ void __launch_bounds__(256) k_ngp_scatter(int64_t n, int64_t chunk, const uint32_t *__restrict__ pix,
-                                                     const float *__restrict__ zz, const float *__restrict__ vl,
-                                                     const float *__restrict__ Gt, float amp_k, int ntiles,
-                                                     const uint32_t *__restrict__ offsets, uint2 *__restrict__ ent,
-                                                     uint32_t *__restrict__ bad) {
-    extern __shared__ uint32_t cur[];
-    __shared__ float G[kNG];
+// Exclusive prefix sum of c[0..m) in place over a block of kSortThreads lanes (m <= 12 kSortThreads);
+// returns the total.  Each lane sums a contiguous run of c, the lanes scan their run sums with
+// wavefront shuffles and the wavefront totals through LDS.
+constexpr int kSortThreads = 512;
+constexpr int kSortPer = 8;   // 4096-particle sub-chunks: two blocks per CU (timed against 1024 .. 8192)
+
+__device__ inline uint32_t block_exclusive_scan(uint32_t *c, int m, uint32_t *wtot) {
+    const int per = (m + kSortThreads - 1) / kSortThreads;
+    const int b0 = threadIdx.x * per, b1 = min(m, b0 + per);
+    uint32_t run = 0;
+    for (int k = b0; k < b1; ++k) run += c[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kSortThreads / 64; ++w) {
+        before += w < wave ? wtot[w] : 0u;
+        total += wtot[w];
+    }
+    uint32_t x = before + inc - run;
+    for (int k = b0; k < b1; ++k) {
+        const uint32_t v = c[k];
+        c[k] = x;
+        x += v;
+    }
+    return total;
+}
+
+// amp_k = sigma_T (1 km/s / c) f_gas M_p / (mu_e m_p) / ((Mpc/h)^2 Omega_pix).
+// The block walks its chunk in sub-chunks of PER * kSortThreads particles; each sub-chunk is
+// counting-sorted by tile in LDS before it is written, so consecutive lanes store consecutive slots
+// of a tile's segment instead of 64 unrelated cache lines per wavefront store.
+template <int PER>
+__global__ void __launch_bounds__(kSortThreads) k_ngp_scatter(int64_t n, int64_t chunk,
+                                                              const uint32_t *__restrict__ pix,
+                                                              const float *__restrict__ zz,
+                                                              const float *__restrict__ vl,
+                                                              const float *__restrict__ Gt, float amp_k, int ntiles,
+                                                              const uint32_t *__restrict__ offsets,
+                                                              uint2 *__restrict__ ent, uint32_t *__restrict__ bad) {
+    constexpr int S = PER * kSortThreads;
+    extern __shared__ uint32_t lds[];
+    float *G = (float *)lds;                              // kNG
+    uint32_t *cur = lds + kNG;                            // ntiles: next slot of this block in each tile
+    uint32_t *cnt = cur + ntiles;                         // ntiles: counts, then offsets, of a sub-chunk
+    uint2 *sent = (uint2 *)(cnt + ntiles + (ntiles & 1)); // S entries in tile order
+    uint32_t *sslot = (uint32_t *)(sent + S);             // S global slots
+    __shared__ uint32_t wtot[kSortThreads / 64];
     const uint32_t *row = offsets + (int64_t)blockIdx.x * ntiles;
-    for (int t = threadIdx.x; t < ntiles; t += 256) cur[t] = row[t];
-    for (int k = threadIdx.x; k < kNG; k += 256) G[k] = Gt[k];
+    for (int t = threadIdx.x; t < ntiles; t += kSortThreads) {
+        cur[t] = row[t];
+        cnt[t] = 0u;
+    }
+    for (int k = threadIdx.x; k < kNG; k += kSortThreads) G[k] = Gt[k];
     __syncthreads();
     const float gs = (float)((kNG - 1) / kZmax);
     const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
     int nb = 0;
-    for (int64_t base = i0 + threadIdx.x; base < i1; base += 256 * kU) {
-        uint32_t p[kU];
-        float z[kU], v[kU];
+    for (int64_t sub = i0; sub < i1; sub += S) {          // the same trip count on every lane
+        uint32_t tl[PER], rk[PER];
+        uint2 e[PER];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int64_t i = base + u * 256;
-            const bool in = i < i1;
-            p[u] = in ? pix[i] : kNoPix;
-            z[u] = in ? zz[i] : 0.0f;
-            v[u] = in ? vl[i] : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            if (p[u] == kNoPix) continue;
+        for (int u = 0; u < PER; ++u) {
+            const int64_t i = sub + u * kSortThreads + threadIdx.x;
+            uint32_t p = kNoPix;
+            float z = 0.0f, v = 0.0f;
+            if (i < i1) {
+                p = pix[i];
+                z = zz[i];
+                v = vl[i];
+            }
+            tl[u] = kNoPix;
+            if (p == kNoPix) continue;
             float a = 0.0f;
-            if (z[u] >= 0.0f && (double)z[u] < kZmax - 0.01) {
-                const float s = z[u] * gs;
+            if (z >= 0.0f && (double)z < kZmax - 0.01) {
+                const float s = z * gs;
                 const int j = min(max((int)s, 1), kNG - 3);
                 const float x = s - (float)j;
                 const float w0 = -x * (x - 1.0f) * (x - 2.0f) * (1.0f / 6.0f);
@@ -244,15 +314,47 @@ __global__ void __launch_bounds__(256) k_ngp_scatter(int64_t n, int64_t chunk, c
                 const float w2 = -(x + 1.0f) * x * (x - 2.0f) * 0.5f;
                 const float w3 = (x + 1.0f) * x * (x - 1.0f) * (1.0f / 6.0f);
                 const float g = w0 * G[j - 1] + w1 * G[j] + w2 * G[j + 1] + w3 * G[j + 2];
-                a = amp_k * v[u] * g / (z[u] * z[u]);
+                a = amp_k * v * g / (z * z);
             } else {
                 nb = 1;
             }
-            const uint32_t slot = atomicAdd(&cur[p[u] >> kTileBits], 1u);
-            ent[slot] = make_uint2(p[u] & (kTilePix - 1), __float_as_uint(a));
+            tl[u] = p >> kTileBits;
+            e[u] = make_uint2(p & (kTilePix - 1), __float_as_uint(a));
         }
+#pragma unroll
+        for (int u = 0; u < PER; ++u)
+            if (tl[u] != kNoPix) rk[u] = atomicAdd(&cnt[tl[u]], 1u);
+        __syncthreads();
+        const uint32_t m = block_exclusive_scan(cnt, ntiles, wtot);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (tl[u] == kNoPix) continue;
+            const uint32_t k = cnt[tl[u]] + rk[u];
+            sent[k] = e[u];
+            sslot[k] = cur[tl[u]] + rk[u];
+        }
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < m; k += kSortThreads) ent[sslot[k]] = sent[k];
+        // advance the cursors by this sub-chunk's counts and clear the counters
+        uint32_t adv[(6144 + kSortThreads - 1) / kSortThreads];
+        int na = 0;
+        for (int t = threadIdx.x; t < ntiles; t += kSortThreads)
+            adv[na++] = (t + 1 < ntiles ? cnt[t + 1] : m) - cnt[t];
+        __syncthreads();
+        na = 0;
+        for (int t = threadIdx.x; t < ntiles; t += kSortThreads) {
+            cur[t] += adv[na++];
+            cnt[t] = 0u;
+        }
+        __syncthreads();
     }
     if (nb) atomicOr(bad, 1u);
+}
+
+size_t scatter_lds_bytes(int per, int ntiles) {
+    return sizeof(float) * kNG + sizeof(uint32_t) * (2 * (size_t)ntiles + (ntiles & 1)) +
+           (size_t)per * kSortThreads * (sizeof(uint2) + sizeof(uint32_t));
 }
 
 __global__ void __launch_bounds__(kDepThreads) k_ngp_deposit(int64_t npix, const uint32_t *__restrict__ beg,
@@ -263,9 +365,13 @@ __global__ void __launch_bounds__(kDepThreads) k_ngp_deposit(int64_t npix, const
     if (e0 == e1) return;
     for (int k = threadIdx.x; k < kTilePix; k += kDepThreads) acc[k] = 0.0;
     __syncthreads();
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kDepThreads) {
-        const uint2 q = ent[e];
-        unsafeAtomicAdd(&acc[q.x], (double)__uint_as_float(q.y));
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kDepThreads * kU) {
+        uint2 q[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) q[u] = e + u * kDepThreads < e1 ? ent[e + u * kDepThreads] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (e + u * kDepThreads < e1) unsafeAtomicAdd(&acc[q[u].x], (double)__uint_as_float(q[u].y));
     }
     __syncthreads();
     const int64_t p0 = (int64_t)t << kTileBits;
@@ -276,9 +382,55 @@ __global__ void __launch_bounds__(kDepThreads) k_ngp_deposit(int64_t npix, const
     }
 }
 
+// Over every float theta in [0, pi): max |z_hw - cos| and max |tmp_hw - tmp| / N where |cos| > 0.66,
+// against FP64 cos, sin and sqrt (as ordered integers of the non-negative float errors)
+__global__ void k_ngp_trig_check(int N, uint32_t last, uint32_t *__restrict__ out) {
+    uint32_t mz = 0u, mt = 0u;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= last; k += gridDim.x * blockDim.x) {
+        const float t = __uint_as_float(k);
+        float zf, tmpf;
+        ngp_trig(N, t, zf, tmpf);
+        const double zd = cos((double)t);
+        mz = max(mz, __float_as_uint((float)fabs((double)zf - zd)));
+        if (fabs(zd) > 0.66) {
+            const double td = (double)N * (sin((double)t) * sqrt(3.0 / (1.0 + fabs(zd))));
+            mt = max(mt, __float_as_uint((float)(fabs((double)tmpf - td) / (double)N)));
+        }
+    }
+    atomicMax(&out[0], mz);
+    atomicMax(&out[1], mt);
+}
+
 }  // namespace bp
 
 using namespace bp;
+
+extern "C" int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *stream) {
+    if (nside < 1 || nside > 2048 || !bounds) return BP_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *d = nullptr;
+    if (hipMallocAsync((void **)&d, 2 * sizeof(uint32_t), s) != hipSuccess) return BP_E_HIP;
+    int e = fill_u32(d, 0u, 2, s);
+    const float pi_below = 3.14159250f;   // the largest float below pi
+    uint32_t last;
+    memcpy(&last, &pi_below, sizeof(last));
+    if (!e) {
+        hipLaunchKernelGGL(k_ngp_trig_check, dim3(4096), dim3(256), 0, s, (int)nside, last, d);
+        if (hipGetLastError() != hipSuccess) e = BP_E_HIP;
+    }
+    uint32_t h[2] = {0u, 0u};
+    if (!e && hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) e = BP_E_HIP;
+    if (!e && hipStreamSynchronize(s) != hipSuccess) e = BP_E_HIP;
+    hipFreeAsync(d, s);
+    if (e) return e;
+    float f[2];
+    memcpy(f, h, sizeof(f));
+    bounds[0] = f[0];
+    bounds[1] = f[1];
+    bounds[2] = kZErr;
+    bounds[3] = kTmpAbs;
+    return BP_OK;
+}
 
 extern "C" int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_t n, const float *theta,
                                        const float *phi, const float *z, const float *v_los, double M_p,
@@ -337,8 +489,12 @@ extern "C" int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_
     if (e) return e;
     hipLaunchKernelGGL(k_ngp_offsets, dim3(tiles_x, (unsigned)ngroups), dim3(256), 0, s, nblk, ntiles, counts, gs,
                        beg);
-    hipLaunchKernelGGL(k_ngp_scatter, dim3((unsigned)nblk), dim3(256), lds, s, n, chunk, pix, z, v_los, Gt, amp_k,
-                       ntiles, counts, ent, bad);
+    const size_t slds = scatter_lds_bytes(kSortPer, ntiles);   // above 64 KB: raise the kernel's limit
+    if (hipFuncSetAttribute((const void *)k_ngp_scatter<kSortPer>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)slds) != hipSuccess)
+        return BP_E_HIP;
+    hipLaunchKernelGGL(k_ngp_scatter<kSortPer>, dim3((unsigned)nblk), dim3(kSortThreads), slds, s, n, chunk, pix, z,
+                       v_los, Gt, amp_k, ntiles, counts, ent, bad);
     prof_end(BP_PROF_NGP_PLAN, s);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     uint32_t hbad = 0;

@@ -142,3 +142,13 @@ def test_ngp_directions_next_to_pixel_edges(bp, orc, nside):
     g = gpu_map(bp, bp.default_params(), nside, parts, ALLSKY_MP)
     err = check(g, o, oabs)
     print(f"ngp edges nside={nside}: max err / sum|b| {err:.2e}")
+
+
+@pytest.mark.parametrize("nside", [1, 1024, 2047])
+def test_ngp_screen_bounds_hold_on_every_float(bp, nside):
+    # the FP32 screen of the pixel assignment is exact only while its trigonometric errors stay
+    # inside the bounds it assumes; this measures them over all 1.08e9 floats in [0, pi)
+    r = bp.pp_healpix_ngp_selfcheck(nside)
+    print(f"ngp screen nside={nside}: {r}")
+    assert 0 < r["z_err"] <= 0.5 * r["z_bound"]
+    assert 0 < r["tmp_err_per_n"] <= 0.5 * r["tmp_bound_per_n"]
