@@ -226,3 +226,53 @@ def test_hp_healpix_fullsize_sampled_pixels(bp, orc):
         print(f"pix {pix[k]}: y {gy[k]:.6e} oracle {oy[k]:.6e} rel {ey[k]:.2e}  b rel {eb[k]:.2e}")
     assert oy[6] > 0, "the largest footprint's centre pixel must be covered"
     assert ey.max() < 1e-5 and eb.max() < 1e-5
+
+
+def test_ngp_fullsize_whole_rings(bp, orc):
+    # the all-sky nearest-pixel paste as the benchmark runs it (1e9 particles of the continuous light
+    # cone, N_side 1024); every pixel of seven rings (polar, cap, the cap/belt boundary, belt,
+    # equator, south) is recomputed by the oracle from the particles whose colatitude lies within
+    # 3e-3 rad of the ring (a pixel reaches at most one ring spacing, < 1e-3 rad, from its ring)
+    import torch
+
+    from paper_2201_02632_amd.synth import ALLSKY_MP, allsky_lightcone_device
+    N, n = 1024, 1_000_000_000
+    dev = torch.device("cuda")
+    parts = allsky_lightcone_device(n, device=dev)
+    b = torch.zeros(12 * N * N, dtype=torch.float32, device=dev)
+    bp.pp_paste_healpix_ngp(bp.default_params(), N, parts["theta"], parts["phi"], parts["z"], parts["v_los"],
+                            ALLSKY_MP, b)
+    torch.cuda.synchronize()
+    b = b.cpu().numpy().astype(np.float64)
+    host = {k: v.cpu().numpy() for k, v in parts.items()}
+    del parts
+    torch.cuda.empty_cache()
+    print(f"pasted {n} particles onto N_side {N}", flush=True)
+    p = orc.default_params()
+
+    def ring_pixels(i):
+        if i < N:
+            return 2 * i * (i - 1), 4 * i
+        if i <= 3 * N:
+            return 2 * N * (N - 1) + (i - N) * 4 * N, 4 * N
+        k = 4 * N - i
+        return 12 * N * N - 2 * k * (k + 1), 4 * k
+
+    worst = 0.0
+    for ring in (1, 300, N - 1, N, 2 * N - 7, 2 * N, 4 * N - 2):
+        p0, m = ring_pixels(ring)
+        th_ring = orc.pix2ang_ring(N, [p0])[0][0]
+        sel = np.nonzero(np.abs(host["theta"] - np.float32(th_ring)) < np.float32(3e-3))[0]
+        pix, amp = orc.pp_healpix_ngp(p, host["theta"][sel], host["phi"][sel], host["z"][sel], host["v_los"][sel],
+                                      ALLSKY_MP, N)
+        inring = (pix >= p0) & (pix < p0 + m)
+        o = np.zeros(m)
+        oabs = np.zeros(m)
+        np.add.at(o, pix[inring] - p0, amp[inring])
+        np.add.at(oabs, pix[inring] - p0, np.abs(amp[inring]))
+        g = b[p0:p0 + m]
+        err = np.abs(g - o)
+        assert np.all(err <= 1e-5 * oabs + 1e-30), f"ring {ring}: worst {np.max(err / (oabs + 1e-300)):.3e}"
+        worst = max(worst, float(np.max(err / np.where(oabs > 0, oabs, np.inf))))
+        print(f"ring {ring}: {m} pixels, {inring.sum()} particles, {len(sel)} candidates", flush=True)
+    print(f"ngp full size: max err / sum|b| {worst:.2e}")
