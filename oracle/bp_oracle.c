@@ -40,6 +40,7 @@
 #define ORC_MSUN      1.988409870698051e33  /* solar mass [g]               */
 #define ORC_MPC       3.0856775814913673e24 /* megaparsec [cm]              */
 #define ORC_PI        3.14159265358979323846
+#define ORC_KB        1.380649e-16          /* Boltzmann constant [erg/K]   */
 
 /* status codes (bit flags, 0 = converged) */
 #define ORC_OK            0
@@ -57,6 +58,7 @@ typedef struct {
     double X_H;                             /* hydrogen mass fraction (Sec. 3.2) */
     double trunc_r500;                      /* projected footprint cut, units of r500 */
     double field_gas_frac;                  /* gas fraction of a field particle */
+    double field_T;                         /* field gas temperature [K] for its tSZ (0: none) */
     int    energy_sign;                     /* 0: feedback adds gas energy; 1: as printed */
     int    pad_;
 } orc_params;
@@ -1124,6 +1126,9 @@ double orc_neff_at(int64_t n, const double *X, const double *Y, const double *Z,
  * Field particle (halo_id < 0):
  *   y_i = 0,  b_i = sigma_T (v_i/c) (f_gas M_p / (mu_e m_p)) e^-tau_i / L_pix^2
  *   (reading: f_gas = field_gas_frac, default the cosmic baryon fraction).
+ *   With field_T > 0 the field gas carries the pressure P_e = n_e k_B T (the filament extension
+ *   that Sec. 3.4 leaves open; reading: electrons at the gas temperature, and, like the halo tSZ
+ *   term, no e^-tau):  y_i = sigma_T/(m_e c^2) k_B T (f_gas M_p / (mu_e m_p)) / L_pix^2.
  * L_pix = D_A(z_i) pix is the physical pixel size at the particle.
  * Inputs: z_i, v_i [km/s], r_i [physical Mpc/h], M_p [Msun/h]. */
 void orc_pp_amplitudes(const orc_params *p, int64_t n, const double *zp, const double *v,
@@ -1138,8 +1143,9 @@ void orc_pp_amplitudes(const orc_params *p, int64_t n, const double *zp, const d
         double ek = exp(-orc_tau(p, zp[i]));
         double vc = v[i] * 1e5 / ORC_C;
         if (halo_id[i] < 0) {
-            amp_y[i] = 0.0;
-            amp_b[i] = ORC_SIGMA_T * vc * (p->field_gas_frac * Mp_g / (mu_e * ORC_MP)) * ek / (Lpix * Lpix);
+            double Ne = p->field_gas_frac * Mp_g / (mu_e * ORC_MP);
+            amp_y[i] = ORC_SIGMA_T / ORC_ME_C2 * (ORC_KB * p->field_T) * Ne / (Lpix * Lpix);
+            amp_b[i] = ORC_SIGMA_T * vc * Ne * ek / (Lpix * Lpix);
             continue;
         }
         const orc_halo *o = &halos[halo_id[i]];

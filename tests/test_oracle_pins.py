@@ -490,3 +490,25 @@ def test_ngp_amplitude_and_map_invariants(orc, params):
     bA, _ = orc.pp_healpix_ngp_map(params, theta[:150], phi[:150], z[:150], v[:150], Mp, N)
     bB, _ = orc.pp_healpix_ngp_map(params, theta[150:], phi[150:], z[150:], v[150:], Mp, N)
     assert np.allclose(bA + bB, b, rtol=0, atol=1e-13 * np.abs(amp).max())
+
+
+def test_field_tsz_amplitude(orc, params):
+    # filament extension of Eq. field_y: P_e = n_e k_B T, so y_i / b_i = (k_B T / m_e c^2) / ((v/c) e^-tau)
+    # for the same particle (same electron count and pixel area); T = 0 is the paper's y = 0
+    import copy
+    p = copy.copy(params)
+    z, v = np.array([0.3, 1.1]), np.array([250.0, -80.0])
+    hid = np.array([-1, -1], dtype=np.int32)
+    pix = 1e-4
+    ay0, ab0 = orc.pp_amplitudes(p, None, z, v, hid, np.zeros(2), 2e9, pix)
+    assert np.all(ay0 == 0)
+    p.field_T = 1e4
+    ay, ab = orc.pp_amplitudes(p, None, z, v, hid, np.zeros(2), 2e9, pix)
+    kB, mec2, c = 1.380649e-16, 8.1871057769e-7, 2.99792458e10
+    for i in range(2):
+        ratio = (kB * 1e4 / mec2) / (v[i] * 1e5 / c * math.exp(-orc.tau(p, z[i])))
+        assert abs(ay[i] / ab[i] / ratio - 1) < 1e-13
+    assert np.array_equal(ab, ab0)
+    p.field_T = 3e4
+    ay3, _ = orc.pp_amplitudes(p, None, z, v, hid, np.zeros(2), 2e9, pix)
+    assert np.allclose(ay3, 3 * ay, rtol=1e-14, atol=0)
