@@ -68,6 +68,9 @@ typedef struct {
     double X_H;            /* hydrogen mass fraction (Sec. 3.2) */
     double trunc_r500;     /* projected footprint radius in units of r500 (3) */
     double field_gas_frac; /* gas mass fraction of a PP field particle (default Omega_b/Omega_m) */
+    double field_T;        /* temperature [K] of PP field gas for its tSZ term: 0 (default) keeps the
+                              paper's y = 0 for field particles (Eq. field_y); > 0 gives filament gas
+                              the pressure n_e k_B T (the extension Sec. 3.4 points to) */
     int32_t energy_sign;   /* 0: injected energy raises the gas energy (default);
                               1: the energy equation as printed in Sec. 2.2 */
     int32_t reserved;
@@ -235,7 +238,8 @@ int bp_pp_smoothing_length_eff(const bp_params *p, int64_t n, const float *theta
  *   halo particle (halo_id >= 0): y_i = sigma_T/(m_e c^2) P_e(r_i) V_i / L_pix^2,
  *       b_i = sigma_T (v_i/c) e^-tau_i n_e(r_i) V_i / L_pix^2,  V_i = M_p / rho_NFW(r_i)
  *       (untruncated NFW density; P_e = n_e = 0 for r_i >= r_f);
- *   field particle (halo_id < 0): y_i = 0,
+ *   field particle (halo_id < 0): y_i = sigma_T/(m_e c^2) k_B field_T (field_gas_frac M_p / (mu_e m_p)) / L_pix^2
+ *       (0 for the default field_T = 0),
  *       b_i = sigma_T (v_i/c) (field_gas_frac M_p / (mu_e m_p)) e^-tau_i / L_pix^2;
  *   L_pix = D_A(z_i) pix_rad.  Each amplitude is spread with the separable
  *   integrated cubic-spline kernel of angular half-width H = h_comoving/chi:

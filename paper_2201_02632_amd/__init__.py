@@ -44,7 +44,7 @@ META_NFIELDS = len(META_FIELDS)
 class Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "Omega_m", "Omega_b", "h", "Gamma", "eps_DM", "eps_star", "f_star", "S_star",
-        "alpha_nt", "beta_nt", "n_nt", "X_H", "trunc_r500", "field_gas_frac")] + [
+        "alpha_nt", "beta_nt", "n_nt", "X_H", "trunc_r500", "field_gas_frac", "field_T")] + [
         ("energy_sign", C.c_int32), ("reserved", C.c_int32)]
 
 
@@ -52,7 +52,7 @@ def default_params(**kw) -> Params:
     """Table 1 of the paper; cosmology Omega_m = 0.3, h = 0.7 with the paper's Omega_b = 0.046."""
     d = dict(Omega_m=0.3, Omega_b=0.046, h=0.7, Gamma=1.2, eps_DM=0.0, eps_star=3.97e-6,
              f_star=0.026, S_star=0.12, alpha_nt=0.18, beta_nt=0.5, n_nt=0.8, X_H=0.76,
-             trunc_r500=3.0, field_gas_frac=0.046 / 0.3, energy_sign=0)
+             trunc_r500=3.0, field_gas_frac=0.046 / 0.3, field_T=0.0, energy_sign=0)
     d.update(kw)
     p = Params()
     for k, v in d.items():

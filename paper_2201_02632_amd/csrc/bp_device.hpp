@@ -21,6 +21,7 @@ constexpr double kMp = 1.67262192369e-24;         // g
 constexpr double kG = 6.67430e-8;                 // cm^3 g^-1 s^-2
 constexpr double kMsun = 1.988409870698051e33;    // g
 constexpr double kMpc = 3.0856775814913673e24;    // cm
+constexpr double kKB = 1.380649e-16;              // erg/K
 constexpr double kPi = 3.141592653589793238462643;
 constexpr double kCkms = kC * 1e-5;               // km/s
 // G in Mpc (km/s)^2 / Msun; with masses in Msun/h and lengths in Mpc/h the h cancels in G M / r

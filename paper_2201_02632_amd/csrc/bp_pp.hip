@@ -498,7 +498,10 @@ __global__ void __launch_bounds__(256) k_pp_amplitudes(bp_params P, int64_t n, i
     const int32_t h = hid[i];
     bool ok = z >= 0.0 && z < kZmax - 0.01;
     if (h < 0) {
-        ab = kSigmaT * vc * (P.field_gas_frac * Mp_g / (mu_e * kMp)) * ek / (Lpix * Lpix);
+        // field gas: Eq. field_b; its tSZ (P_e = n_e k_B T) only when a field temperature is set
+        const double Ne = P.field_gas_frac * Mp_g / (mu_e * kMp);
+        ay = kSigmaT / kMeC2 * (kKB * P.field_T) * Ne / (Lpix * Lpix);
+        ab = kSigmaT * vc * Ne * ek / (Lpix * Lpix);
     } else if (h < nh && !(hst[h] & ~BP_S_MULTI_ROOT)) {
         auto S = [&](int f) { return sol[(int64_t)f * nh + h]; };
         const double r = ri[i];

@@ -33,7 +33,7 @@ def test_binding_mirrors_header():
     meta = re.search(r"enum \{\s*BP_META_ETA_LO = 0,(.*?)BP_META_NFIELDS", src, flags=re.S).group(1)
     assert ["ETA_LO"] + re.findall(r"BP_META_(\w+)", meta) == bp.META_FIELDS
     assert bp.version() >= 100
-    assert ctypes.sizeof(bp.Params) == 14 * 8 + 8
+    assert ctypes.sizeof(bp.Params) == 15 * 8 + 8
 
 
 def test_strerror_without_gpu():

@@ -173,3 +173,25 @@ def test_pp_edge_inputs(bp):
     xx = T(np.linspace(0, 1e-3, 100).astype(np.float32))
     with pytest.raises(bp.BPError):
         bp.pp_smoothing_length(params, xx, xx, zz, 32)
+
+
+def test_pp_field_tsz_parity(bp, orc, small_case):
+    # filament gas (field particles) with the pressure n_e k_B T at the field temperature 1e4 K
+    import torch
+    c = small_case
+    p = orc.default_params()
+    p.field_T = 1e4
+    sol = orc.solve_halos(p, c["halos"]["M"], c["halos"]["c"], c["halos"]["z"])
+    yo, bo, _, _, ay, _ = orc.pp_flat(p, sol, c["parts"], c["M_p"], c["npix"], c["pix"])
+    field = c["parts"]["halo_id"] < 0
+    assert np.all(ay[field] > 0)
+    y, b, _, _, _ = bp.pp_flat_map(bp.default_params(field_T=1e4), c["halos"], c["parts"], c["M_p"], c["npix"],
+                                   c["pix"])
+    torch.cuda.synchronize()
+    y, b = y.cpu().numpy(), b.cpu().numpy()
+    ey, eb = rel_err(y, yo), rel_err(b, bo, c["babs"])
+    dY = y.astype(np.float64).sum() - c["y"].sum()          # the field particles' share of integrated y
+    print(f"PP field tSZ: max rel err y {ey:.2e} b {eb:.2e}; field share of Y {dY / y.sum():.3e}")
+    assert ey < 1e-5 and eb < 1e-5
+    assert abs(y.astype(np.float64).sum() / yo.sum() - 1) < 1e-6
+    assert dY > 0
