@@ -512,3 +512,46 @@ def test_field_tsz_amplitude(orc, params):
     p.field_T = 3e4
     ay3, _ = orc.pp_amplitudes(p, None, z, v, hid, np.zeros(2), 2e9, pix)
     assert np.allclose(ay3, 3 * ay, rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------- flat-sky power spectrum (Sec. 5.3) --
+def test_spectrum_parseval_and_cosine():
+    from oracle import spectrum as S
+    rng = np.random.default_rng(3)
+    n, d = 64, 2e-4
+    f = rng.normal(size=(n, n))
+    lb, cl, cnt = S.flat_power_spectrum(f, d, np.array([0.0, 1e12]))
+    assert cnt[0] == n * n
+    assert abs(cl[0] * cnt[0] / (d * d * (f * f).sum()) - 1) < 1e-12        # Parseval
+    # one cosine of wave vector (a, b): power d^2 N^2 / 4 on each of the modes +-(a, b), nothing else
+    a, b = 5, 3
+    x = np.arange(n)
+    g = np.cos(2 * math.pi * (a * x[None, :] + b * x[:, None]) / n)
+    L = n * d
+    l0 = 2 * math.pi / L * math.hypot(a, b)
+    lb, cl, cnt = S.flat_power_spectrum(g, d, np.array([0.999 * l0, 1.001 * l0]))
+    same = sum(1 for i in range(-n // 2, n // 2) for j in range(-n // 2, n // 2) if i * i + j * j == a * a + b * b)
+    assert cnt[0] == same
+    assert abs(cl[0] * cnt[0] / (2 * d * d * n * n / 4) - 1) < 1e-12
+    assert abs(lb[0] / l0 - 1) < 1e-14
+
+
+def test_spectrum_white_noise_and_mode_counts():
+    from oracle import spectrum as S
+    rng = np.random.default_rng(4)
+    n, d, sig = 256, 1e-4, 2.5
+    f = rng.normal(0, sig, size=(n, n))
+    edges = S.log_edges(30, 1e2, 1e5)
+    lb, cl, cnt = S.flat_power_spectrum(f, d, edges)
+    # white noise: every mode has expected power d^2 sigma^2
+    big = cnt >= 1000
+    assert big.sum() >= 5
+    assert np.all(np.abs(cl[big] / (d * d * sig * sig) - 1) < 5 / np.sqrt(cnt[big]))
+    # annuli inside the Nyquist square hold about pi (|k|^2 range) modes (Gauss circle problem)
+    t = S.thresholds(edges, n, d)
+    inside = np.sqrt(t[1:]) < n / 2
+    expect = math.pi * (t[1:] - t[:-1])
+    ok = inside & (expect > 50)
+    assert ok.sum() >= 5
+    assert np.all(np.abs(cnt[ok] - expect[ok]) < 4 * np.sqrt(t[1:][ok]) + 4)
+    assert np.all((lb[cnt > 0] >= edges[:-1][cnt > 0]) & (lb[cnt > 0] < edges[1:][cnt > 0]))
