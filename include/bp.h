@@ -284,6 +284,22 @@ int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_t n, const 
  * nside in [1, 2048]; synchronises the stream; allocates 8 bytes of device memory. */
 int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *stream);
 
+/* Flat-sky angular power spectrum of an npix x npix map (Sec. 5.3: FFT of the flat-sky maps in
+ * logarithmic multipole bins, 30 over 10^2 < ell < 10^5 in the paper):
+ *     F(ell) = d^2 sum_x f(x) exp(-i ell.x),  ell = 2 pi (kx, ky) / (N d),  kx, ky in [-N/2, N/2),
+ *     C_b = mean over the modes of bin b of |F(ell)|^2 / (N d)^2,  ell_b = their mean |ell|.
+ * Mode (kx, ky) is in bin b when t_b <= kx^2 + ky^2 < t_{b+1}, t_b = (edges[b] N d / (2 pi))^2 in
+ * FP64 (so the assignment of modes to bins is exact).  No apodisation, mean subtraction or window.
+ *   npix      : power of two, 2 .. 4096;  d = pix_rad [rad];  map: device, npix*npix floats, row-major
+ *   edges     : HOST, nbins + 1 increasing finite values >= 0 [ell];  nbins in [1, 64]
+ *   ell, cl   : device, nbins doubles each, OUTPUT (0 for an empty bin);  nmodes: device, nbins int64
+ * Transforms in FP64.  Workspace protocol as for the pastes (about 32 npix^2 bytes); no
+ * synchronisation.  Per-bin sums are formed in LDS in an unfixed order, so repeated calls agree to
+ * about 1e-15 relative. */
+int bp_flat_power_spectrum(int32_t npix, double pix_rad, const float *map, int32_t nbins, const double *edges,
+                           double *ell, double *cl, int64_t *nmodes, void *ws, size_t ws_bytes, size_t *ws_needed,
+                           void *stream);
+
 /* ------------------------------------------------- surrogate (K10-K12) */
 /* A multilayer perceptron maps normalised (log10 M, ln c, z) to the projected
  * electron pressure and density of the halo on a fixed grid of 64 impact
@@ -410,6 +426,7 @@ enum {
     BP_PROF_PP_NEFF,        /* K6b k_pp_neff */
     BP_PROF_NGP_PLAN,       /* K13 pixel indices + tile counting sort + amplitudes */
     BP_PROF_NGP_DEPOSIT,    /* K13 k_ngp_deposit */
+    BP_PROF_SPECTRUM,       /* K14 flat-sky power spectrum */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

@@ -82,6 +82,8 @@ _SIGS = {
     "bp_pp_paste_healpix_ngp": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, C.c_double, _VP, _VP,
                                           C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_pp_healpix_ngp_selfcheck": (C.c_int, [C.c_int64, C.POINTER(C.c_double), _VP]),
+    "bp_flat_power_spectrum": (C.c_int, [C.c_int32, C.c_double, _VP, C.c_int32, C.POINTER(C.c_double), _VP, _VP,
+                                         _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_mlp_nparams": (C.c_int64, []),
     "bp_mlp_act_bytes": (C.c_size_t, [C.c_int64]),
     "bp_mlp_backward_ws_bytes": (C.c_size_t, [C.c_int64]),
@@ -111,7 +113,7 @@ _SIGS = {
 PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
                                           "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT", "MLP_FWD", "MLP_BWD",
                                           "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT", "PP_NEFF", "NGP_PLAN",
-                                          "NGP_DEPOSIT"])}
+                                          "NGP_DEPOSIT", "SPECTRUM"])}
 MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
 S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
@@ -310,6 +312,21 @@ def pp_healpix_ngp_selfcheck(nside: int = 1024):
     out = (C.c_double * 4)()
     _check(_lib.bp_pp_healpix_ngp_selfcheck(int(nside), out, _stream()), "bp_pp_healpix_ngp_selfcheck")
     return {"z_err": out[0], "tmp_err_per_n": out[1], "z_bound": out[2], "tmp_bound_per_n": out[3]}
+
+
+def flat_power_spectrum(m, pix_rad: float, edges, ws: Workspace | None = None):
+    """K14: (ell_b, C_b, n_b) of a square float32 device map in the bins given by edges (ell)."""
+    assert m.dtype == torch.float32 and m.dim() == 2 and m.shape[0] == m.shape[1]
+    e = [float(x) for x in edges]
+    nb = len(e) - 1
+    ell = torch.empty(nb, dtype=torch.float64, device=m.device)
+    cl = torch.empty_like(ell)
+    nm = torch.empty(nb, dtype=torch.int64, device=m.device)
+    ws = ws or _ws_for(m.device)
+    _with_workspace(_lib.bp_flat_power_spectrum, "bp_flat_power_spectrum", ws,
+                    (int(m.shape[0]), float(pix_rad), _ptr(m), nb, (C.c_double * len(e))(*e), _ptr(ell), _ptr(cl),
+                     _ptr(nm)))
+    return ell, cl, nm
 
 
 def pp_flat_map(params: Params, halos: dict, parts: dict, M_p: float, npix: int, pix_rad: float, k: int = 32,

@@ -276,3 +276,24 @@ def test_ngp_fullsize_whole_rings(bp, orc):
         worst = max(worst, float(np.max(err / np.where(oabs > 0, oabs, np.inf))))
         print(f"ring {ring}: {m} pixels, {inring.sum()} particles, {len(sel)} candidates", flush=True)
     print(f"ngp full size: max err / sum|b| {worst:.2e}")
+
+
+def test_spectrum_fullsize_headline_maps(bp):
+    # the paper's estimator (30 log bins over 10^2 < ell < 10^5) on the benchmark's 4096^2 y and b maps
+    import torch
+
+    from oracle import spectrum as S
+    from paper_2201_02632_amd.synth import hp_flat_large
+    cat, npix, pix = hp_flat_large()
+    y, b, _, _ = bp.hp_flat_map(bp.default_params(), cat, npix, pix)
+    torch.cuda.synchronize()
+    edges = S.log_edges(30, 1e2, 1e5)
+    for name, m in (("y", y), ("b", b)):
+        ell, cl, nm = bp.flat_power_spectrum(m, pix, edges)
+        torch.cuda.synchronize()
+        lo, co, no = S.flat_power_spectrum(m.cpu().numpy(), pix, edges)
+        assert np.array_equal(nm.cpu().numpy(), no)
+        e = float(np.max(np.abs(cl.cpu().numpy()[no > 0] / co[no > 0] - 1)))
+        assert e < 1e-9
+        assert np.all(np.abs(ell.cpu().numpy()[no > 0] / lo[no > 0] - 1) < 1e-12)
+        print(f"{name} spectrum 4096^2: {int((no > 0).sum())} bins, max rel err {e:.2e}", flush=True)
