@@ -359,6 +359,24 @@ def ngp_section(bp, params, dev, steps, warmup, n_particles, nside):
                          "bytes_per_unit": 16, "units": n, "unit_name": "particle (+ 8 B per map pixel)"}}
 
 
+def spectrum_section(bp, m, pix, steps, warmup):
+    """The paper's flat-sky statistic (30 log bins over 10^2 < ell < 10^5) of one 4096^2 map."""
+    import numpy as np
+    edges = np.logspace(2.0, 5.0, 31)
+    ws = bp.Workspace(m.device)
+
+    def step():
+        bp.flat_power_spectrum(m, pix, edges, ws=ws)
+
+    ms = timed(step, steps, warmup, bp)
+    kt = kernel_times(bp, ("SPECTRUM",), steps)
+    bp._lib.bp_profiling(0)
+    n = m.shape[0]
+    return {"workload": f"flat-sky power spectrum of the headline {n}^2 y map: FP64 FFT, 30 log bins over "
+                        "1e2 < ell < 1e5", "ms_per_map": round(ms, 3), "kernel_ms": kt,
+            "modes_per_s": round(n * n / (ms * 1e-3), 1)}
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """Plain device-to-device copies of a known size: each launch reads and writes exactly
     nbytes, which fixes the scale of the FETCH_SIZE / WRITE_SIZE counters."""
@@ -382,9 +400,9 @@ def main():
     ap.add_argument("--profile-pass", action="store_true",
                     help="run the warmup and timed steps of each section, print per-kernel times and stop (for "
                          "hardware-counter passes under a profiler: no error maps or other reporting kernels)")
-    ap.add_argument("--sections", default="surrogate,allsky,pp,ngp",
-                    help="extra measured sections after the headline one: surrogate, allsky, pp, ngp (comma list, "
-                         "or none)")
+    ap.add_argument("--sections", default="spectrum,surrogate,allsky,pp,ngp",
+                    help="extra measured sections after the headline one: spectrum, surrogate, allsky, pp, ngp "
+                         "(comma list, or none)")
     ap.add_argument("--sky-halos", type=int, default=100_000_000)
     ap.add_argument("--sky-batch", type=int, default=10_000_000)
     ap.add_argument("--nside", type=int, default=8192)
@@ -449,6 +467,8 @@ def main():
     bp._lib.bp_profiling(0)
     if args.profile_pass:
         res = {"profile_pass": True, "ms_per_step": round(ms, 3), "kernel_ms": {k: round(v, 4) for k, v in kt.items()}}
+        if "spectrum" in args.sections.split(","):
+            res["spectrum"] = spectrum_section(bp, y, pix, args.extra_steps, 1)
         del t, y, b, ws, sol, st
         torch.cuda.empty_cache()
         secs = [x for x in args.sections.split(",") if x and x != "none"]
@@ -497,6 +517,8 @@ def main():
         "kernel_ms": {k: round(v, 4) for k, v in kt.items()},
         "roofline": roof,
     }
+    if "spectrum" in args.sections.split(","):
+        out["spectrum"] = spectrum_section(bp, y, pix, args.extra_steps, 1)
     del t, y, b, ws, sol, st
     torch.cuda.empty_cache()
     sections = [x for x in args.sections.split(",") if x and x != "none"]

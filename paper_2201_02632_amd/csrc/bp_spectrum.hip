@@ -10,7 +10,7 @@
 //   columns  the column transforms; each workgroup bins its column's powers in LDS (FP64 sums,
 //            weight 2 for 0 < kx < N/2, whose mirror -kx is not stored) and writes one row of
 //            per-column partial sums
-//   bins     one lane per bin sums the columns' partials in column order.
+//   bins     one workgroup per bin sums the columns' partials in a fixed order.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -116,21 +116,37 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_cols_power(int N, int logN,
     for (int b = threadIdx.x; b < 3 * nb; b += kFftThreads) part[(int64_t)kx * 3 * nb + b] = acc[b];
 }
 
-// bins: C_b = d^2 / N^2 * sum P / n_b,  ell_b = 2 pi / (N d) * sum |k| / n_b
-__global__ void k_spectrum_bins(int H, int nb, const double *__restrict__ part, double norm, double kscale,
-                                double *__restrict__ ell, double *__restrict__ cl, int64_t *__restrict__ nmodes) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
+// bins: C_b = d^2 / N^2 * sum P / n_b,  ell_b = 2 pi / (N d) * sum |k| / n_b.  One workgroup per bin;
+// lane l sums the columns l, l + 256, ... in order, then a fixed tree over the lanes.
+__global__ void __launch_bounds__(256) k_spectrum_bins(int H, int nb, const double *__restrict__ part, double norm,
+                                                       double kscale, double *__restrict__ ell,
+                                                       double *__restrict__ cl, int64_t *__restrict__ nmodes) {
+    __shared__ double r[3][256];
+    const int b = blockIdx.x;
     double sp = 0.0, sn = 0.0, sk = 0.0;
-    for (int kx = 0; kx < H; ++kx) {
+    for (int kx = threadIdx.x; kx < H; kx += 256) {
         const double *q = part + (int64_t)kx * 3 * nb + 3 * b;
         sp += q[0];
         sn += q[1];
         sk += q[2];
     }
-    nmodes[b] = (int64_t)sn;
-    cl[b] = sn > 0.0 ? norm * sp / sn : 0.0;
-    ell[b] = sn > 0.0 ? kscale * sk / sn : 0.0;
+    r[0][threadIdx.x] = sp;
+    r[1][threadIdx.x] = sn;
+    r[2][threadIdx.x] = sk;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int c = 0; c < 3; ++c) r[c][threadIdx.x] += r[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sp = r[0][0];
+        sn = r[1][0];
+        sk = r[2][0];
+        nmodes[b] = (int64_t)sn;
+        cl[b] = sn > 0.0 ? norm * sp / sn : 0.0;
+        ell[b] = sn > 0.0 ? kscale * sk / sn : 0.0;
+    }
 }
 
 }  // namespace bp
@@ -168,7 +184,7 @@ extern "C" int bp_flat_power_spectrum(int32_t npix, double pix_rad, const float 
     hipLaunchKernelGGL(k_fft_rows, dim3(N), dim3(kFftThreads), 0, s, N, logN, map, tw, rows);
     hipLaunchKernelGGL(k_transpose_c, dim3((H + 31) / 32, (N + 31) / 32), dim3(256), 0, s, N, H, rows, cols);
     hipLaunchKernelGGL(k_fft_cols_power, dim3(H), dim3(kFftThreads), 0, s, N, logN, cols, tw, bins, part);
-    hipLaunchKernelGGL(k_spectrum_bins, dim3((nbins + 63) / 64), dim3(64), 0, s, H, nbins, part,
+    hipLaunchKernelGGL(k_spectrum_bins, dim3(nbins), dim3(256), 0, s, H, nbins, part,
                        pix_rad * pix_rad / ((double)N * (double)N), 2.0 * kPi / ((double)N * pix_rad), ell, cl,
                        nmodes);
     prof_end(BP_PROF_SPECTRUM, s);
