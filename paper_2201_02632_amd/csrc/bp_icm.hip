@@ -524,12 +524,10 @@ __global__ void __launch_bounds__(256) k_table_setup(bp_params P, GaussRules G, 
 
 // One block per halo, one table node per thread.  Node positions come from the single-precision
 // grid ranges in meta (the values the deposits interpolate with).
-__global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(GaussRules G, int64_t n, const double *__restrict__ sol,
-                                                         const int32_t *__restrict__ status,
-                                                         const float *__restrict__ meta, float *__restrict__ tab,
-                                                         double ant, float n_nt) {
-    const int64_t i = blockIdx.x;
-    const int node = threadIdx.x;
+// One table node (both quantities) of halo i.
+__device__ inline void table_node(const GaussRules &G, int64_t n, const double *__restrict__ sol,
+                                  const int32_t *__restrict__ status, const float *__restrict__ meta,
+                                  float *__restrict__ tab, double ant, float n_nt, int64_t i, int node) {
     auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
     auto Mt = [&](int f) { return (double)meta[(int64_t)f * n + i]; };
     float *tP = tab + (int64_t)i * BP_TAB_STRIDE;
@@ -650,6 +648,28 @@ __global__ void __launch_bounds__(BP_TAB_ZONE) k_tables(GaussRules G, int64_t n,
     tN[node] = (float)accN;
 }
 
+// Zone A: one 192-lane block per halo (three wavefronts, all running the same zone's code).
+__global__ void __launch_bounds__(BP_TAB_NA) k_tables(GaussRules G, int64_t n, const double *__restrict__ sol,
+                                                      const int32_t *__restrict__ status,
+                                                      const float *__restrict__ meta, float *__restrict__ tab,
+                                                      double ant, float n_nt) {
+    table_node(G, n, sol, status, meta, tab, ant, n_nt, blockIdx.x, threadIdx.x);
+}
+
+static_assert(BP_TAB_NS == 32 && BP_TAB_NB == 32, "k_tables_sb maps 32 nodes of each zone to half a wavefront");
+
+// Zones S and B in their own launch: wavefront 0 of a block takes the 32 shell nodes of two halos,
+// wavefront 1 their 32 outer nodes, so no wavefront runs both zones' code one after the other.
+__global__ void __launch_bounds__(128) k_tables_sb(GaussRules G, int64_t n, const double *__restrict__ sol,
+                                                   const int32_t *__restrict__ status,
+                                                   const float *__restrict__ meta, float *__restrict__ tab,
+                                                   double ant, float n_nt) {
+    const int64_t i = 2 * (int64_t)blockIdx.x + ((threadIdx.x >> 5) & 1);
+    if (i >= n) return;
+    const int zone = threadIdx.x >> 6;                  // 0: S, 1: B
+    table_node(G, n, sol, status, meta, tab, ant, n_nt, i, BP_TAB_NA + zone * BP_TAB_NS + (threadIdx.x & 31));
+}
+
 // ------------------------------------------------------- Gauss-Legendre --
 // Nodes and weights of the n-point rule on [-1,1] by Newton iteration on P_n.
 static void gauss_legendre(int n, double *x, double *w) {
@@ -730,8 +750,10 @@ extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *so
     prof_begin(BP_PROF_TABLES, s);
     hipLaunchKernelGGL(k_node_geom, dim3(1), dim3(BP_TAB_NA), 0, s, (double)(float)G.eta_top);
     hipLaunchKernelGGL(k_table_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, *p, G, n, sol, status, meta);
-    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_ZONE), 0, s, G, n, sol, status, meta, tables,
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_NA), 0, s, G, n, sol, status, meta, tables,
                        p->alpha_nt, (float)p->n_nt);
+    hipLaunchKernelGGL(k_tables_sb, dim3((unsigned)((n + 1) / 2)), dim3(128), 0, s, G, n, sol, status, meta,
+                       tables, p->alpha_nt, (float)p->n_nt);
     prof_end(BP_PROF_TABLES, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
