@@ -35,6 +35,8 @@ struct GaussRules {
     double x8[8], w8[8];
     double x20[20], w20[20];
     float u16[16], u12[12], u8[8], u20[20];   // (x + 1) / 2 in FP32: nodes on [0, 1]
+    double w6[6], w10[10], w14[14];           // further zone-A orders (weights; nodes only as u)
+    float u6[6], u10[10], u14[14];
     double eta_top;                    // ln(1 + acosh(1e5)): zone-A grid end (r_perp = 1e-5 r_a)
 };
 
