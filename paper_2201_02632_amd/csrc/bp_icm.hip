@@ -198,9 +198,9 @@ __device__ void distances(const bp_params &P, const GaussRules &G, double z, dou
 // few waves deep per SIMD, and at the unconstrained 262 VGPRs a single resident wave leaves every
 // FP64 latency exposed (2.47 ms against 1.81 ms for 5e5 halos; three waves spill 110 VGPRs, 1.97 ms).
 template <bool kStructureOnly>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min,
-                                                  const double *__restrict__ cin, const double *__restrict__ zin,
-                                                  double *__restrict__ sol, int32_t *__restrict__ status) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min, const double *__restrict__ cin,
+            const double *__restrict__ zin, double *__restrict__ sol, int32_t *__restrict__ status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double M = Min[i], c = cin[i], z = zin[i];

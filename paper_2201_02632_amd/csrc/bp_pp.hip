@@ -213,10 +213,10 @@ constexpr int kShells = 8;
 constexpr int kMaxLevel = 20;
 
 template <int K>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 32 ? 4 : 2))) k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key,
-                                                const uint32_t *__restrict__ idx, const double *__restrict__ sp,
-                                                const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ cend,
-                                                float *__restrict__ h_out, int *__restrict__ fail) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 32 ? 4 : 2)))
+k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
+         const double *__restrict__ sp, const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ cend,
+         float *__restrict__ h_out, int *__restrict__ fail) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t ki = key[i];
