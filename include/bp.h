@@ -228,7 +228,8 @@ int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, 
  * W the cubic spline of Eq. SPH_kernel with support h, the sum over every particle including i
  * itself (the SPH density sum), i.e. (32/3) sum_j w(r_ij / h).  Positions, units, workspace and
  * errors as bp_pp_smoothing_length (which runs first, for the 32-NN distance that seeds a
- * bracketed Halley iteration on h, converged to 1e-6 relative).  n_ngb in (32/3, 1024]
+ * bracketed Halley iteration on h, stopped after a step below 1e-3 relative,
+ * which leaves an error of order 1e-9).  n_ngb in (32/3, 1024]
  * (BP_E_ARG otherwise); n > 32.  A particle whose root is not found writes NaN. */
 int bp_pp_smoothing_length_eff(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
                                const float *z, double n_ngb, double cell, float *h_comoving, void *ws,
