@@ -86,9 +86,16 @@ def cpu_baseline(sample_n=400, seed=102):
     t0 = time.perf_counter()
     oracle.hp_flat(p, sub, npix, pix)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": sample_n / dt, "unit": "halos/s", "cores": 1, "kind": "oracle",
             "sample": f"{sample_n} random halos (seed {seed}) of the 5e5-halo catalogue: FP64 solve and "
-                      f"full footprints on the 4096^2 map, single thread ({dt:.1f} s)"}
+                      f"full footprints on the 4096^2 map, single thread ({dt:.1f} s)",
+            "host": {"cpu_model": model, "logical_cpus": os.cpu_count()}}
 
 
 def kernel_times(bp, names, steps):
