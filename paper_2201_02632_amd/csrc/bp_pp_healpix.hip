@@ -421,7 +421,7 @@ extern "C" int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *
     uint32_t h[2] = {0u, 0u};
     if (!e && hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) e = BP_E_HIP;
     if (!e && hipStreamSynchronize(s) != hipSuccess) e = BP_E_HIP;
-    hipFreeAsync(d, s);
+    (void)hipFreeAsync(d, s);
     if (e) return e;
     float f[2];
     memcpy(f, h, sizeof(f));
