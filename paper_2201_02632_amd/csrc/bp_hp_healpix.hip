@@ -69,6 +69,27 @@ __device__ inline double ring_coord(int64_t N, double t) {
     return 2.0 * (double)N - 1.5 * (double)N * z;
 }
 
+// Per-ring quantities the tile walk needs, computed once per call (nrings <= 32767).
+struct RingRec {
+    double th, sth, st2, ct2;   // colatitude, sin(theta), sin(theta/2), cos(theta/2)
+    int32_t npr;                // pixels in the ring (<= 4N <= 32768)
+    float shift;                // pixel-centre phase: phi_j = (j + 1 - shift) 2 pi / npr
+    uint32_t tile0;             // first tile of the ring
+    int32_t pad;
+};
+
+__global__ void k_ring_table(int64_t N, int32_t nrings, const uint32_t *__restrict__ ring_tile_off,
+                             RingRec *__restrict__ rt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrings) return;
+    int64_t npr, off; double th, sh;
+    ring_info(N, i + 1, &npr, &off, &th, &sh);
+    RingRec r;
+    r.th = th; r.sth = sin(th); r.st2 = sin(0.5 * th); r.ct2 = cos(0.5 * th);
+    r.npr = (int32_t)npr; r.shift = (float)sh; r.tile0 = ring_tile_off[i]; r.pad = 0;
+    rt[i] = r;
+}
+
 __global__ void k_ring_tiles(int64_t N, int32_t nrings, uint32_t *__restrict__ ntiles_ring) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrings) return;
@@ -78,10 +99,10 @@ __global__ void k_ring_tiles(int64_t N, int32_t nrings, uint32_t *__restrict__ n
 }
 
 // Visit the tiles a halo's disc can touch, ring by ring.  f(tile) is called in a
-// deterministic order; count and emit use this same routine.
+// deterministic order; count and emit use this same routine.  The ring quantities come from the
+// per-call ring table, and sin((theta_r - theta_h)/2) from the half-angle sines and cosines.
 template <class F>
-__device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const uint32_t *__restrict__ ring_tile_off,
-                                     F &&f) {
+__device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const RingRec *__restrict__ rtab, F &&f) {
     double hmax = (double)R.hmax;
     double psi = 2.0 * asin(sqrt(fmin(hmax, 1.0)));
     double tlo = R.th - psi, thi = R.th + psi;
@@ -89,38 +110,41 @@ __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const ui
     int64_t ihi = (thi >= kPi) ? 4 * G.N - 1 : (int64_t)ceil(ring_coord(G.N, thi)) + 1;
     if (ilo < 1) ilo = 1;
     if (ihi > 4 * G.N - 1) ihi = 4 * G.N - 1;
-    for (int64_t i = ilo; i <= ihi; ++i) {
-        int64_t npr, off; double thr, sh;
-        ring_info(G.N, i, &npr, &off, &thr, &sh);
-        double sd = sin(0.5 * (thr - R.th));
-        double A = sd * sd;
+    for (int i = (int)ilo; i <= (int)ihi; ++i) {
+        const RingRec &Rg = rtab[i - 1];
+        const double sd = Rg.st2 * R.ch2 - Rg.ct2 * R.sh2;
+        const double A = sd * sd;
         if (A > hmax) continue;
-        double B = sin(thr) * R.sth;
-        int64_t nt = (npr + kSeg - 1) / kSeg;
-        uint32_t base = ring_tile_off[i - 1];
-        double q = (B > 0.0) ? (hmax - A) / B : 2.0;
+        const double B = Rg.sth * R.sth;
+        const int npr = Rg.npr;
+        const int nt = (npr + kSeg - 1) / kSeg;
+        const uint32_t base = Rg.tile0;
+        const double q = (B > 0.0) ? (hmax - A) / B : 2.0;
         if (q >= 1.0) {
-            for (int64_t t = 0; t < nt; ++t) f(base + (uint32_t)t);
+            for (int t = 0; t < nt; ++t) f(base + (uint32_t)t);
             continue;
         }
-        double dphi_max = 2.0 * asin(sqrt(q));
-        double step = 2.0 * kPi / (double)npr;
-        // pixel centre phi_j = (j + 1 - shift) step, j = 0..npr-1 (ring-local)
-        int64_t jlo = (int64_t)floor((R.ph - dphi_max) / step - 1.0 + sh) - 1;
-        int64_t jhi = (int64_t)floor((R.ph + dphi_max) / step - 1.0 + sh) + 2;
+        const double dphi_max = 2.0 * asin(sqrt(q));
+        const double step = 2.0 * kPi / (double)npr;
+        // pixel centre phi_j = (j + 1 - shift) step, j = 0..npr-1 (ring-local); |j| < 2 npr here
+        const double sh = (double)Rg.shift;
+        const int jlo = (int)floor((R.ph - dphi_max) / step - 1.0 + sh) - 1;
+        const int jhi = (int)floor((R.ph + dphi_max) / step - 1.0 + sh) + 2;
         if (jhi - jlo + 1 >= npr) {
-            for (int64_t t = 0; t < nt; ++t) f(base + (uint32_t)t);
+            for (int t = 0; t < nt; ++t) f(base + (uint32_t)t);
             continue;
         }
-        int64_t a = ((jlo % npr) + npr) % npr, b = ((jhi % npr) + npr) % npr;
-        int64_t ta = a / kSeg, tb = b / kSeg;
+        int a = jlo % npr, b = jhi % npr;
+        if (a < 0) a += npr;
+        if (b < 0) b += npr;
+        const int ta = a / kSeg, tb = b / kSeg;
         if (a <= b) {
-            for (int64_t t = ta; t <= tb; ++t) f(base + (uint32_t)t);
+            for (int t = ta; t <= tb; ++t) f(base + (uint32_t)t);
         } else if (tb >= ta) {  // wrapped ranges share a tile: take the whole ring
-            for (int64_t t = 0; t < nt; ++t) f(base + (uint32_t)t);
+            for (int t = 0; t < nt; ++t) f(base + (uint32_t)t);
         } else {
-            for (int64_t t = 0; t <= tb; ++t) f(base + (uint32_t)t);
-            for (int64_t t = ta; t < nt; ++t) f(base + (uint32_t)t);
+            for (int t = 0; t <= tb; ++t) f(base + (uint32_t)t);
+            for (int t = ta; t < nt; ++t) f(base + (uint32_t)t);
         }
     }
 }
@@ -131,7 +155,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
                                                    const double *__restrict__ ph, const double *__restrict__ vlos,
                                                    const double *__restrict__ sol, const int32_t *__restrict__ status,
                                                    const float *__restrict__ meta,
-                                                   const uint32_t *__restrict__ ring_tile_off, HpxRec *__restrict__ rec,
+                                                   const RingRec *__restrict__ rtab, HpxRec *__restrict__ rec,
                                                    uint32_t *__restrict__ cnt, unsigned long long *__restrict__ total) {
     __shared__ unsigned long long part[4];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,7 +201,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
             double sp = Rt / DA;
             double hav = (sp > 1e-4) ? 0.5 * (1.0 - cos(asin(sp))) : 0.25 * sp * sp * (1.0 + 0.25 * sp * sp);
             r.hmax = (float)(hav * (1.0 + 1e-5) + 1e-30);
-            for_each_tile(G, r, ring_tile_off, [&](uint32_t) { ++count; });
+            for_each_tile(G, r, rtab, [&](uint32_t) { ++count; });
         }
         rec[i] = r;
         cnt[i] = count;
@@ -190,7 +214,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
 }
 
 __global__ void __launch_bounds__(256) k_hpx_emit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
-                                                  const uint32_t *__restrict__ ring_tile_off,
+                                                  const RingRec *__restrict__ rtab,
                                                   const uint32_t *__restrict__ off, uint32_t *__restrict__ keys,
                                                   uint32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -198,7 +222,7 @@ __global__ void __launch_bounds__(256) k_hpx_emit(HpxGeom G, int64_t n, const Hp
     const HpxRec r = rec[i];
     if (!(r.flags & 4)) return;
     uint32_t k = off[i], end = off[i + 1];
-    for_each_tile(G, r, ring_tile_off, [&](uint32_t tile) {
+    for_each_tile(G, r, rtab, [&](uint32_t tile) {
         if (k < end) { keys[k] = tile; vals[k] = (uint32_t)i; ++k; }
     });
 }
@@ -330,6 +354,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     A1.take<unsigned long long>(1);
     A1.take<uint32_t>(G.nrings + 1);
     A1.take<uint32_t>(G.nrings + 1);
+    A1.take<RingRec>(G.nrings);
     size_t phase1 = A1.used + scan_ws_bytes(n + 1) + scan_ws_bytes(G.nrings + 1);
     if (ws_bytes < phase1 || !ws) { *ws_needed = phase1 + 64; return BP_E_WORKSPACE; }
     Arena A(ws, ws_bytes);
@@ -339,6 +364,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     unsigned long long *total = A.take<unsigned long long>(1);
     uint32_t *rtiles = A.take<uint32_t>(G.nrings + 1);
     uint32_t *roff = A.take<uint32_t>(G.nrings + 1);
+    RingRec *rtab = A.take<RingRec>(G.nrings);
     void *scan_ws = (char *)ws + A.used;
     A.used += scan_ws_bytes(n + 1) + scan_ws_bytes(G.nrings + 1);
     // tiles per ring and their prefix (the total lands in roff[nrings])
@@ -347,11 +373,12 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     int e = scan_exclusive_u32(rtiles, roff, G.nrings + 1, scan_ws, s);
     if (e) return e;
+    hipLaunchKernelGGL(k_ring_table, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, roff, rtab);
     if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
     if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_hpx_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status,
-                       meta, roff, rec, cnt, total);
+                       meta, rtab, rec, cnt, total);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long np64 = 0;
     uint32_t ntiles32 = 0;
@@ -379,7 +406,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     prof_begin(BP_PROF_HPX_PLAN, s);
     e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, s);
     if (e) return e;
-    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, s, G, n, rec, roff, off, k0, v0);
+    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, s, G, n, rec, rtab, off, k0, v0);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     int bits = 1;
     while ((1LL << bits) < ntiles) ++bits;
