@@ -89,20 +89,37 @@ __global__ void k_targets(bp_params P, int64_t n, const double *__restrict__ sol
 }
 
 // column mean and standard deviation over rows with finite values (FP64 sums, fixed order)
-__global__ void k_stats(int64_t n, const float *__restrict__ t, float *__restrict__ mean, float *__restrict__ sd) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= BP_MLP_OUT) return;
+// One workgroup per column: lane l sums rows l, l + 256, ... in order, then a fixed tree over the
+// lanes (FP64 sums; non-finite targets are skipped).
+__global__ void __launch_bounds__(256) k_stats(int64_t n, const float *__restrict__ t, float *__restrict__ mean,
+                                               float *__restrict__ sd) {
+    __shared__ double rs[256], rs2[256];
+    __shared__ int64_t rc[256];
+    const int c = blockIdx.x;
     double s = 0.0, s2 = 0.0;
     int64_t cnt = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
         float v = t[i * BP_MLP_OUT + c];
         if (!isfinite(v)) continue;
         s += v; s2 += (double)v * v; ++cnt;
     }
-    double mu = cnt ? s / cnt : 0.0;
-    double var = cnt ? s2 / cnt - mu * mu : 0.0;
-    mean[c] = (float)mu;
-    sd[c] = (c < BP_MLP_NOUT && var > 1e-20) ? (float)sqrt(var) : 1.0f;
+    rs[threadIdx.x] = s; rs2[threadIdx.x] = s2; rc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+            rs2[threadIdx.x] += rs2[threadIdx.x + w];
+            rc[threadIdx.x] += rc[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t m = rc[0];
+        const double mu = m ? rs[0] / m : 0.0;
+        const double var = m ? rs2[0] / m - mu * mu : 0.0;
+        mean[c] = (float)mu;
+        sd[c] = (c < BP_MLP_NOUT && var > 1e-20) ? (float)sqrt(var) : 1.0f;
+    }
 }
 
 __global__ void k_gather(int64_t n, int cols, const float *__restrict__ in, const int64_t *__restrict__ idx,
@@ -226,7 +243,7 @@ extern "C" int bp_surrogate_targets(const bp_params *p, int64_t n, const double 
 
 extern "C" int bp_surrogate_stats(int64_t n, const float *targets, float *mean, float *std, void *stream) {
     if (n <= 0 || !targets || !mean || !std) return BP_E_ARG;
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(BP_MLP_OUT), 0, (hipStream_t)stream, n, targets, mean, std);
+    hipLaunchKernelGGL(k_stats, dim3(BP_MLP_OUT), dim3(256), 0, (hipStream_t)stream, n, targets, mean, std);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
