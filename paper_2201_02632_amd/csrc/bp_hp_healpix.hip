@@ -1,11 +1,15 @@
 // K4: halo-based pasting onto HEALPix RING pixels (the all-sky maps of
 // Sec. 5.2 of Osato & Nagai 2022; pixelisation of Gorski et al. 2005).
 //
-// Tiles are 64-pixel segments of one ring.  Each halo emits one (tile, halo)
-// pair per segment that its disc can touch; pairs are stably sorted by tile
-// and one wavefront owns a tile (one pixel per lane, y/b sums and Kahan
-// compensations in registers).  Per (halo, ring) the colatitude part of the
-// haversine, sin^2(dtheta/2), is formed in FP64; per pixel only
+// Tiles are two-dimensional: the rings are taken in bands of eight, and a band
+// is cut in longitude into tiles of width 8 * 2 pi / n_max (n_max: the largest
+// pixel count among the band's rings), so that a tile holds at most eight
+// pixels of each of its rings (exactly eight in the equatorial belt, fewer in
+// the shorter rings of a polar band).  Each halo emits one (tile, halo) pair
+// per tile that its disc can touch; pairs are stably sorted by tile and one
+// wavefront owns a tile (lane = ring of the band * 8 + pixel, y/b sums and
+// Kahan compensations in registers).  Per (halo, ring) the colatitude part of
+// the haversine, sin^2(dtheta/2), is formed in FP64; per pixel only
 // sin^2(dphi/2) is evaluated in FP32:
 //   hav = sin^2(dtheta/2) + sin(theta_r) sin(theta_h) sin^2(dphi/2),
 //   r_perp = D_A sin(psi) = 2 D_A sqrt(hav (1 - hav)),  psi < pi/2  <=>  hav < 1/2.
@@ -18,7 +22,8 @@
 
 namespace bp {
 
-constexpr int kSeg = 64;
+constexpr int kBand = 8;     // rings per band
+constexpr int kTw = 8;       // pixels of the longest ring per tile
 
 struct __attribute__((aligned(16))) HpxRec {
     double th, ph, sth;     // halo colatitude, longitude in [0, 2 pi), sin(colatitude)
@@ -69,40 +74,62 @@ __device__ inline double ring_coord(int64_t N, double t) {
     return 2.0 * (double)N - 1.5 * (double)N * z;
 }
 
-// Per-ring quantities the tile walk needs, computed once per call (nrings <= 32767).
+// Per-ring quantities the tile walk and the deposit need, computed once per call (nrings <= 32767).
 struct RingRec {
     double th, sth, st2, ct2;   // colatitude, sin(theta), sin(theta/2), cos(theta/2)
     int32_t npr;                // pixels in the ring (<= 4N <= 32768)
-    float shift;                // pixel-centre phase: phi_j = (j + 1 - shift) 2 pi / npr
-    uint32_t tile0;             // first tile of the ring
-    int32_t pad;
+    float shift;                // pixel-centre phase: phi_j = (j + 1 - shift) 2 pi / npr, shift 1 or 1/2
+    int32_t nmax;               // largest pixel count among the rings of this ring's band
+    uint32_t poff;              // first pixel of the ring (< 12 N^2 <= 805,306,368)
 };
 
-__global__ void k_ring_table(int64_t N, int32_t nrings, const uint32_t *__restrict__ ring_tile_off,
-                             RingRec *__restrict__ rt) {
+// largest pixel count among the rings of band b (rings kBand b + 1 .. kBand b + kBand, 1-based)
+__device__ inline int32_t band_nmax(int64_t N, int32_t nrings, int b) {
+    int64_t m = 0;
+    for (int i = kBand * b + 1; i <= min(kBand * b + kBand, nrings); ++i) {
+        int64_t npr, off; double th, sh;
+        ring_info(N, i, &npr, &off, &th, &sh);
+        m = max(m, npr);
+    }
+    return (int32_t)m;
+}
+
+__global__ void k_ring_table(int64_t N, int32_t nrings, RingRec *__restrict__ rt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrings) return;
     int64_t npr, off; double th, sh;
     ring_info(N, i + 1, &npr, &off, &th, &sh);
     RingRec r;
     r.th = th; r.sth = sin(th); r.st2 = sin(0.5 * th); r.ct2 = cos(0.5 * th);
-    r.npr = (int32_t)npr; r.shift = (float)sh; r.tile0 = ring_tile_off[i]; r.pad = 0;
+    r.npr = (int32_t)npr; r.shift = (float)sh; r.nmax = band_nmax(N, nrings, i / kBand); r.poff = (uint32_t)off;
     rt[i] = r;
 }
 
-__global__ void k_ring_tiles(int64_t N, int32_t nrings, uint32_t *__restrict__ ntiles_ring) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrings) return;
-    int64_t npr, off; double th, sh;
-    ring_info(N, i + 1, &npr, &off, &th, &sh);
-    ntiles_ring[i] = (uint32_t)((npr + kSeg - 1) / kSeg);
+// tiles per band: ceil(n_max / 8)
+__global__ void k_band_tiles(int64_t N, int32_t nrings, int32_t nbands, uint32_t *__restrict__ ntiles_band) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbands) return;
+    ntiles_band[b] = (uint32_t)((band_nmax(N, nrings, b) + kTw - 1) / kTw);
 }
 
-// Visit the tiles a halo's disc can touch, ring by ring.  f(tile) is called in a
-// deterministic order; count and emit use this same routine.  The ring quantities come from the
-// per-call ring table, and sin((theta_r - theta_h)/2) from the half-angle sines and cosines.
+// First pixel of tile t in a ring: tile t holds the pixels whose centres satisfy
+// 8 t <= (j + 1 - shift) nmax / npr < 8 t + 8, i.e. j >= 8 t npr / nmax - 1 + shift.  Integer
+// arithmetic (2 shift is 1 or 2), so that neighbouring tiles agree on every boundary pixel; a tile
+// then holds at most ceil(8 npr / nmax) <= 8 pixels of the ring.
+__host__ __device__ inline int64_t tile_first_pixel(int64_t t, int64_t npr, int64_t nmax, int s2) {
+    const int64_t a = 16 * t * npr + (int64_t)(s2 - 2) * nmax, d = 2 * nmax;
+    return a >= 0 ? (a + d - 1) / d : -((-a) / d);
+}
+
+// Visit the tiles a halo's disc can touch.  For each ring the disc reaches, the longitudes of
+// its pixels that can be members lie within dphi_max of the halo (padded by two pixel steps for
+// rounding); per band the union of these intervals (they all contain the halo's longitude) is
+// cut into the band's tiles.  f(tile) is called in a deterministic order; count and emit use this
+// same routine.  sin((theta_r - theta_h)/2) comes from the half-angle sines and cosines.
 template <class F>
-__device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const RingRec *__restrict__ rtab, F &&f) {
+__device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const RingRec *__restrict__ rtab,
+                                     const uint32_t *__restrict__ btile0, F &&f) {
+    const double kTwoPi = 2.0 * kPi;
     double hmax = (double)R.hmax;
     double psi = 2.0 * asin(sqrt(fmin(hmax, 1.0)));
     double tlo = R.th - psi, thi = R.th + psi;
@@ -110,43 +137,51 @@ __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const Ri
     int64_t ihi = (thi >= kPi) ? 4 * G.N - 1 : (int64_t)ceil(ring_coord(G.N, thi)) + 1;
     if (ilo < 1) ilo = 1;
     if (ihi > 4 * G.N - 1) ihi = 4 * G.N - 1;
+    int band = -1;
+    bool any = false, whole = false;
+    double flo = 0.0, fhi = 0.0;
+    auto flush = [&]() {
+        if (!any) return;
+        const int nmax = rtab[kBand * band].nmax;
+        const int T = (nmax + kTw - 1) / kTw;
+        const uint32_t base = btile0[band];
+        if (!whole && fhi - flo < kTwoPi) {
+            const double tpr = (double)nmax / (kTw * kTwoPi);   // tiles per radian
+            auto tl = [&](double x) { return (int)fmin(fmax(floor(x * tpr), 0.0), (double)(T - 1)); };
+            if (flo >= 0.0 && fhi < kTwoPi) {
+                for (int t = tl(flo); t <= tl(fhi); ++t) f(base + (uint32_t)t);
+                return;
+            }
+            // the interval wraps through phi = 0: [lo1, T) and [0, hi2]
+            const int lo1 = tl(flo < 0.0 ? flo + kTwoPi : flo), hi2 = tl(flo < 0.0 ? fhi : fhi - kTwoPi);
+            if (hi2 < lo1) {
+                for (int t = 0; t <= hi2; ++t) f(base + (uint32_t)t);
+                for (int t = lo1; t < T; ++t) f(base + (uint32_t)t);
+                return;
+            }
+        }
+        for (int t = 0; t < T; ++t) f(base + (uint32_t)t);
+    };
     for (int i = (int)ilo; i <= (int)ihi; ++i) {
+        const int b = (i - 1) / kBand;
+        if (b != band) {
+            flush();
+            band = b; any = false; whole = false;
+        }
         const RingRec &Rg = rtab[i - 1];
         const double sd = Rg.st2 * R.ch2 - Rg.ct2 * R.sh2;
         const double A = sd * sd;
         if (A > hmax) continue;
         const double B = Rg.sth * R.sth;
-        const int npr = Rg.npr;
-        const int nt = (npr + kSeg - 1) / kSeg;
-        const uint32_t base = Rg.tile0;
         const double q = (B > 0.0) ? (hmax - A) / B : 2.0;
-        if (q >= 1.0) {
-            for (int t = 0; t < nt; ++t) f(base + (uint32_t)t);
-            continue;
-        }
-        const double dphi_max = 2.0 * asin(sqrt(q));
-        const double step = 2.0 * kPi / (double)npr;
-        // pixel centre phi_j = (j + 1 - shift) step, j = 0..npr-1 (ring-local); |j| < 2 npr here
-        const double sh = (double)Rg.shift;
-        const int jlo = (int)floor((R.ph - dphi_max) / step - 1.0 + sh) - 1;
-        const int jhi = (int)floor((R.ph + dphi_max) / step - 1.0 + sh) + 2;
-        if (jhi - jlo + 1 >= npr) {
-            for (int t = 0; t < nt; ++t) f(base + (uint32_t)t);
-            continue;
-        }
-        int a = jlo % npr, b = jhi % npr;
-        if (a < 0) a += npr;
-        if (b < 0) b += npr;
-        const int ta = a / kSeg, tb = b / kSeg;
-        if (a <= b) {
-            for (int t = ta; t <= tb; ++t) f(base + (uint32_t)t);
-        } else if (tb >= ta) {  // wrapped ranges share a tile: take the whole ring
-            for (int t = 0; t < nt; ++t) f(base + (uint32_t)t);
-        } else {
-            for (int t = 0; t <= tb; ++t) f(base + (uint32_t)t);
-            for (int t = ta; t < nt; ++t) f(base + (uint32_t)t);
-        }
+        if (q >= 1.0) { whole = true; any = true; continue; }
+        const double w = 2.0 * asin(sqrt(q)) + 2.0 * kTwoPi / (double)Rg.npr;
+        const double lo = R.ph - w, hi = R.ph + w;
+        if (!any) { flo = lo; fhi = hi; }
+        else { flo = fmin(flo, lo); fhi = fmax(fhi, hi); }
+        any = true;
     }
+    flush();
 }
 
 // Build records and count pairs.  kQ: tables are the surrogate's q-grid (meta holds only PE0, NE0).
@@ -155,7 +190,8 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
                                                    const double *__restrict__ ph, const double *__restrict__ vlos,
                                                    const double *__restrict__ sol, const int32_t *__restrict__ status,
                                                    const float *__restrict__ meta,
-                                                   const RingRec *__restrict__ rtab, HpxRec *__restrict__ rec,
+                                                   const RingRec *__restrict__ rtab,
+                                                   const uint32_t *__restrict__ btile0, HpxRec *__restrict__ rec,
                                                    uint32_t *__restrict__ cnt, unsigned long long *__restrict__ total) {
     __shared__ unsigned long long part[4];
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,7 +237,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
             double sp = Rt / DA;
             double hav = (sp > 1e-4) ? 0.5 * (1.0 - cos(asin(sp))) : 0.25 * sp * sp * (1.0 + 0.25 * sp * sp);
             r.hmax = (float)(hav * (1.0 + 1e-5) + 1e-30);
-            for_each_tile(G, r, rtab, [&](uint32_t) { ++count; });
+            for_each_tile(G, r, rtab, btile0, [&](uint32_t) { ++count; });
         }
         rec[i] = r;
         cnt[i] = count;
@@ -215,6 +251,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
 
 __global__ void __launch_bounds__(256) k_hpx_emit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
                                                   const RingRec *__restrict__ rtab,
+                                                  const uint32_t *__restrict__ btile0,
                                                   const uint32_t *__restrict__ off, uint32_t *__restrict__ keys,
                                                   uint32_t *__restrict__ vals) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,7 +259,7 @@ __global__ void __launch_bounds__(256) k_hpx_emit(HpxGeom G, int64_t n, const Hp
     const HpxRec r = rec[i];
     if (!(r.flags & 4)) return;
     uint32_t k = off[i], end = off[i + 1];
-    for_each_tile(G, r, rtab, [&](uint32_t tile) {
+    for_each_tile(G, r, rtab, btile0, [&](uint32_t tile) {
         if (k < end) { keys[k] = tile; vals[k] = (uint32_t)i; ++k; }
     });
 }
@@ -253,7 +290,8 @@ template <bool kQ>
 __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
                                                      const float *__restrict__ tables, const uint32_t *__restrict__ vals,
                                                      const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
-                                                     const uint32_t *__restrict__ ring_tile_off,
+                                                     const uint32_t *__restrict__ btile0, int32_t nbands,
+                                                     const RingRec *__restrict__ rtab,
                                                      const double *__restrict__ thin, const double *__restrict__ phin,
                                                      const double *__restrict__ sol, float *__restrict__ ymap,
                                                      float *__restrict__ bmap, uint32_t ntiles) {
@@ -263,22 +301,27 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
     if (tile >= ntiles) return;
     const uint32_t p0 = tstart[tile], p1 = tend[tile];
     if (p0 >= p1) return;
-    // ring of this tile: last ring whose first tile is <= tile
-    int lo = 0, hi = G.nrings - 1;
+    // band of this tile: last band whose first tile is <= tile
+    int lo = 0, hi = nbands - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (ring_tile_off[mid] <= tile) lo = mid; else hi = mid - 1;
+        if (btile0[mid] <= tile) lo = mid; else hi = mid - 1;
     }
-    const int64_t ring = lo + 1;
-    int64_t npr, poff; double thr, sh;
-    ring_info(G.N, ring, &npr, &poff, &thr, &sh);
-    const int64_t jl = (int64_t)(tile - ring_tile_off[lo]) * kSeg + lane;
-    const bool valid = jl < npr;
-    const int64_t pix = poff + jl;
+    const int64_t t = tile - btile0[lo];
+    // lane = 8 * (ring within the band) + (pixel within the tile's run of that ring)
+    const int ring = kBand * lo + 1 + (lane >> 3);
+    const RingRec Rr = rtab[min(ring, G.nrings) - 1];
+    const int64_t npr = Rr.npr;
+    const int s2 = (Rr.shift == 1.0f) ? 2 : 1;
+    const int64_t j0 = tile_first_pixel(t, npr, Rr.nmax, s2), j1 = tile_first_pixel(t + 1, npr, Rr.nmax, s2);
+    const int64_t jl = j0 + (lane & 7);
+    const bool valid = ring <= G.nrings && jl < min(j1, npr);
+    const int64_t pix = (int64_t)Rr.poff + jl;
+    const double thr = Rr.th, sh = (double)Rr.shift;
     // pixel-centre longitude as the pixelisation defines it: (pi/2)/(npr/4) * (j - shift), j = jl + 1
     const double step = 1.5707963267948966 / (double)(npr / 4);
     const double phj = step * ((double)(jl + 1) - sh);
-    const double sthr = sin(thr), st2 = sin(0.5 * thr), ct2 = cos(0.5 * thr);
+    const double sthr = Rr.sth, st2 = Rr.st2, ct2 = Rr.ct2;
     const float inv_pix2 = (float)(1.0 / (G.pixang * G.pixang));
     float ys = valid ? ymap[pix] : 0.0f, bs = valid ? bmap[pix] : 0.0f, yc = 0.0f, bc = 0.0f;
     for (uint32_t p = p0; p < p1; ++p) {
@@ -287,7 +330,7 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
         const HpxRec &R = rec[h];
         const FootRec F = foot_uniform(R);
         // haversine of the angle to the halo: hv = sin^2(dtheta/2) + sin(theta_r) sin(theta_h) sin^2(dphi/2),
-        // sin(dtheta/2) from the half-angle sines and cosines (wave-uniform)
+        // sin(dtheta/2) from the half-angle sines and cosines of the lane's ring
         const double sd = st2 * R.ch2 - ct2 * R.sh2;
         const float A = (float)(sd * sd), B = (float)(sthr * R.sth);
         // dphi wrapped to [-pi, pi] in FP64 before it is rounded to FP32 (a small angle must not be
@@ -347,43 +390,44 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     G.N = nside;
     G.nrings = (int32_t)(4 * nside - 1);
     G.pixang = sqrt(4.0 * kPi / (12.0 * (double)nside * (double)nside));
+    const int32_t nbands = (G.nrings + kBand - 1) / kBand;
     Arena A1(nullptr, 0);
     A1.take<HpxRec>(n);
     A1.take<uint32_t>(n + 1);
     A1.take<uint32_t>(n + 1);
     A1.take<unsigned long long>(1);
-    A1.take<uint32_t>(G.nrings + 1);
-    A1.take<uint32_t>(G.nrings + 1);
+    A1.take<uint32_t>(nbands + 1);
+    A1.take<uint32_t>(nbands + 1);
     A1.take<RingRec>(G.nrings);
-    size_t phase1 = A1.used + scan_ws_bytes(n + 1) + scan_ws_bytes(G.nrings + 1);
+    size_t phase1 = A1.used + scan_ws_bytes(n + 1) + scan_ws_bytes(nbands + 1);
     if (ws_bytes < phase1 || !ws) { *ws_needed = phase1 + 64; return BP_E_WORKSPACE; }
     Arena A(ws, ws_bytes);
     HpxRec *rec = A.take<HpxRec>(n);
     uint32_t *cnt = A.take<uint32_t>(n + 1);
     uint32_t *off = A.take<uint32_t>(n + 1);
     unsigned long long *total = A.take<unsigned long long>(1);
-    uint32_t *rtiles = A.take<uint32_t>(G.nrings + 1);
-    uint32_t *roff = A.take<uint32_t>(G.nrings + 1);
+    uint32_t *btiles = A.take<uint32_t>(nbands + 1);
+    uint32_t *btile0 = A.take<uint32_t>(nbands + 1);
     RingRec *rtab = A.take<RingRec>(G.nrings);
     void *scan_ws = (char *)ws + A.used;
-    A.used += scan_ws_bytes(n + 1) + scan_ws_bytes(G.nrings + 1);
-    // tiles per ring and their prefix (the total lands in roff[nrings])
-    if (fill_u32(rtiles + G.nrings, 0u, 1, s)) return BP_E_HIP;
-    hipLaunchKernelGGL(k_ring_tiles, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, rtiles);
+    A.used += scan_ws_bytes(n + 1) + scan_ws_bytes(nbands + 1);
+    // tiles per band and their prefix (the total lands in btile0[nbands])
+    if (fill_u32(btiles + nbands, 0u, 1, s)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_band_tiles, dim3((nbands + 255) / 256), dim3(256), 0, s, G.N, G.nrings, nbands, btiles);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
-    int e = scan_exclusive_u32(rtiles, roff, G.nrings + 1, scan_ws, s);
+    int e = scan_exclusive_u32(btiles, btile0, nbands + 1, scan_ws, s);
     if (e) return e;
-    hipLaunchKernelGGL(k_ring_table, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, roff, rtab);
+    hipLaunchKernelGGL(k_ring_table, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, rtab);
     if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
     if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_hpx_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status,
-                       meta, rtab, rec, cnt, total);
+                       meta, rtab, btile0, rec, cnt, total);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long np64 = 0;
     uint32_t ntiles32 = 0;
     if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
-    if (hipMemcpyAsync(&ntiles32, roff + G.nrings, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (hipMemcpyAsync(&ntiles32, btile0 + nbands, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
         return BP_E_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
     if (np64 >= 0x7fffffffULL) return BP_E_OVERFLOW;
@@ -406,7 +450,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     prof_begin(BP_PROF_HPX_PLAN, s);
     e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, s);
     if (e) return e;
-    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, s, G, n, rec, rtab, off, k0, v0);
+    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, s, G, n, rec, rtab, btile0, off, k0, v0);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     int bits = 1;
     while ((1LL << bits) < ntiles) ++bits;
@@ -421,7 +465,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     prof_end(BP_PROF_HPX_PLAN, s);
     prof_begin(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
     hipLaunchKernelGGL(k_hpx_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, G, n, rec, tables, vs,
-                       tst, ten, roff, theta, phi, sol, y_map, b_map, (uint32_t)ntiles);
+                       tst, ten, btile0, nbands, rtab, theta, phi, sol, y_map, b_map, (uint32_t)ntiles);
     prof_end(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
