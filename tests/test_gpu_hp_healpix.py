@@ -57,6 +57,29 @@ def test_hp_healpix_vs_oracle(bp, orc, nside, n, seed):
     assert ey < 1e-5 and eb < 1e-5 and Yerr < 1e-6
 
 
+@pytest.mark.parametrize("nside,n,zlo,zhi,seed", [(1, 60, 0.002, 0.004, 7), (3, 60, 0.002, 0.006, 8),
+                                                   (13, 120, 0.003, 0.02, 9), (100, 60, 0.01, 0.05, 10)])
+def test_hp_healpix_small_and_odd_nside(bp, orc, nside, n, zlo, zhi, seed):
+    # few and short rings: a partial last band of rings, polar bands whose rings hold fewer pixels
+    # than the band's longest one, and (odd N_side) a last tile half as wide as the others
+    import torch
+    cat = sky_case(seed, n, nside)
+    cat["z"] = np.random.default_rng(seed + 100).uniform(zlo, zhi, n)
+    print(f"healpix small nside={nside} n={n} seed={seed}", flush=True)
+    y, b, _, _ = bp.hp_healpix_map(bp.default_params(), cat, nside)
+    torch.cuda.synchronize()
+    p = orc.default_params()
+    yo, bo, _ = orc.hp_healpix(p, cat, nside)
+    _, babs, _ = orc.hp_healpix(p, dict(cat, v_los=np.abs(cat["v_los"])), nside)
+    assert (yo > 0).sum() >= 4
+    yg = y.cpu().numpy()
+    assert np.array_equal(yg > 0, yo > 0)
+    ey = rel_err(yg, yo)
+    eb = rel_err(b.cpu().numpy(), bo, babs)
+    print(f"nside={nside}: pixels hit {(yo > 0).sum()}, max rel err y {ey:.2e} b {eb:.2e}")
+    assert ey < 1e-5 and eb < 1e-5
+
+
 def test_hp_healpix_sign_and_determinism(bp):
     import torch
     cat = sky_case(3, 20, 256)
