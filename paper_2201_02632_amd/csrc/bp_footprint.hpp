@@ -8,12 +8,14 @@
 
 namespace bp {
 
-// Two tables (P and n) sampled at the same position: cubic Lagrange through nodes i-1 .. i+2,
-// with the weights written through a = f(f-1) and (f+1)(f-2) = a - 2.
-__device__ inline void lagr4x2(const float *__restrict__ tp, const float *__restrict__ tn, int n, float s, float *vp,
+// Two tables (P at tab[base ..], n at tab[nofs + base ..]) sampled at the same position: cubic
+// Lagrange through nodes i-1 .. i+2, with the weights written through a = f(f-1) and
+// (f+1)(f-2) = a - 2.  tab is the halo's (wave-uniform) table pointer and the node index a 32-bit
+// offset from it, so the loads take the scalar-base form.
+__device__ inline void lagr4x2(const float *__restrict__ tab, int nofs, int base, int n, float s, float *vp,
                                float *vn) {
-    float fi = floorf(s);
-    int i = (int)fi;
+    // truncation instead of floor: the two differ only for s < 0, where the clamp gives 1 either way
+    int i = (int)s;
     i = min(max(i, 1), n - 3);
     const float f = s - (float)i;
     const float fm1 = f - 1.0f;
@@ -23,9 +25,17 @@ __device__ inline void lagr4x2(const float *__restrict__ tp, const float *__rest
     const float w3 = -t * (f + 1.0f);    //  (f+1) f (f-1) / 6
     const float w1 = u * fm1;            //  (f+1) (f-1) (f-2) / 2
     const float w2 = -u * f;             // -(f+1) f (f-2) / 2
-    const float *p = tp + i - 1, *q = tn + i - 1;
+    const unsigned k = (unsigned)(base + i - 1);
+    const float *p = tab + k, *q = tab + nofs + k;
     *vp = w0 * p[0] + w1 * p[1] + w2 * p[2] + w3 * p[3];
     *vn = w0 * q[0] + w1 * q[1] + w2 * q[2] + w3 * q[3];
+}
+
+// max(x, y) for y >= +0 and x not a NaN, as one integer max: non-negative floats order like their
+// bit patterns, and a negative float (sign bit set) is below all of them.  fmaxf costs a second
+// instruction here, which quiets a possible signalling NaN first.
+__device__ inline float fmax_nn(float x, float y) {
+    return __int_as_float(max(__float_as_int(x), __float_as_int(y)));
 }
 
 __device__ inline void kahan_add(float &s, float &c, float v) {
@@ -88,21 +98,21 @@ __device__ inline void footprint_value(const Rec &R, const float *__restrict__ t
                                        float *vp, float *vn) {
     const float kLn2 = 0.693147180559945f;
     const bool zA = u2 > 0.0f;
-    const float w = hw_sqrt(fmaxf(zA ? u2 : U2, 0.0f));                          // u or U
+    const float w = hw_sqrt(fmax_nn(zA ? u2 : U2, 0.0f));                        // u or U
     // log2 of (r_{a,f} + w) / r = acosh(r_{a,f} / r) / ln 2
-    const float L = __builtin_amdgcn_logf(((zA ? R.ra : R.rf) + w) * hw_rsq(fmaxf(r2, R.r2min)));
-    const float eta = __builtin_amdgcn_logf(fmaf(kLn2, fmaxf(L, 0.0f), 1.0f));   // eta / ln 2
+    const float L = __builtin_amdgcn_logf(((zA ? R.ra : R.rf) + w) * hw_rsq(fmax_nn(r2, R.r2min)));
+    const float eta = __builtin_amdgcn_logf(fmaf(kLn2, fmax_nn(L, 0.0f), 1.0f));   // eta / ln 2
     const float sidx = zA ? (eta - R.eta_lo) * R.eta_ih : (L - R.ze_lo) * R.ze_ih;
     const int off = zA ? 0 : BP_TAB_NA + BP_TAB_NS;
     const int nn = zA ? BP_TAB_NA : BP_TAB_NB;
     float gp, gn;
-    lagr4x2(tab + off, tab + BP_TAB_ZONE + off, nn, sidx, &gp, &gn);
+    lagr4x2(tab, BP_TAB_ZONE, off, nn, sidx, &gp, &gn);
     float P = gp * w, N = gn * w;
     if ((R.flags & 1) && zA) {
         const float S = hw_sqrt(fmaf(w, w, R.D));
         const float om = __builtin_amdgcn_logf((w + S) * R.isqD);                 // asinh(u / sqrt(D)) / ln 2
         float sp, sn;
-        lagr4x2(tab + BP_TAB_NA, tab + BP_TAB_ZONE + BP_TAB_NA, BP_TAB_NS, (om - R.om_lo) * R.om_ih, &sp, &sn);
+        lagr4x2(tab, BP_TAB_ZONE, BP_TAB_NA, BP_TAB_NS, (om - R.om_lo) * R.om_ih, &sp, &sn);
         const float e = R.D * hw_rcp(S + w);
         P += sp * e; N += sn * e;
     }
@@ -135,8 +145,8 @@ __device__ inline void footprint_value_q(const Rec &R, const float *__restrict__
     const float q = fminf(hw_sqrt(r2) * R.eta_ih, 1.0f);
     const float sidx = acos_1m2q(q) * (63.0f / 3.14159265358979f);
     float gp, gn;
-    lagr4x2(tab, tab + BP_MLP_NQ, BP_MLP_NQ, sidx, &gp, &gn);
-    const float E = hw_sqrt(fmaxf(U2, 0.0f)) * hw_rcp(R.rf);
+    lagr4x2(tab, BP_MLP_NQ, 0, BP_MLP_NQ, sidx, &gp, &gn);
+    const float E = hw_sqrt(fmax_nn(U2, 0.0f)) * hw_rcp(R.rf);
     const float f = R.eta_lo * E;
     *vp = gp * f;
     *vn = gn * f;
