@@ -44,6 +44,33 @@ struct __attribute__((aligned(16))) FlatRec {
 };
 static_assert(sizeof(FlatRec) == 176, "FlatRec size");
 
+// The first 96 bytes of a record: every field a pair needs outside the FP64 edge re-tests.
+struct FlatHead {
+    int32_t cxi, cyi;
+    float hx, hy, Rt2, Rt2_band, ra, ra2, rf, rf2, D, isqD, ra2_edge, rf2_edge, r2min;
+    float eta_lo, eta_ih, om_lo, om_ih, ze_lo, ze_ih, amp_y, amp_b;
+    int32_t flags;
+};
+static_assert(sizeof(FlatHead) == 96 && offsetof(FlatRec, flags) == 92, "FlatHead mirrors FlatRec");
+
+// Load a record head into scalar registers in one batch.  The empty asm statement takes the 24
+// words as opaque inputs and outputs, so the compiler issues all their loads before one wait and
+// keeps the values, instead of splitting the loads around register reuse and reloading fields
+// later (each split costs a scalar-memory round trip per pair).
+__device__ inline FlatHead load_head(const FlatRec *rec, uint32_t h) {
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(rec + h);
+    uint32_t w[24];
+#pragma unroll
+    for (int j = 0; j < 24; ++j) w[j] = __builtin_amdgcn_readfirstlane(p[j]);
+    asm volatile("" : "+s"(w[0]), "+s"(w[1]), "+s"(w[2]), "+s"(w[3]), "+s"(w[4]), "+s"(w[5]), "+s"(w[6]),
+                 "+s"(w[7]), "+s"(w[8]), "+s"(w[9]), "+s"(w[10]), "+s"(w[11]));
+    asm volatile("" : "+s"(w[12]), "+s"(w[13]), "+s"(w[14]), "+s"(w[15]), "+s"(w[16]), "+s"(w[17]),
+                 "+s"(w[18]), "+s"(w[19]), "+s"(w[20]), "+s"(w[21]), "+s"(w[22]), "+s"(w[23]));
+    FlatHead H;
+    __builtin_memcpy(&H, w, sizeof(H));
+    return H;
+}
+
 __device__ inline void tile_row_range(double cx, double cy, double Rt, int ty, int ntx, int npix, int *tx0, int *tx1) {
     // pixel rows of this tile: centres y in [16 ty + 0.5, 16 ty + 15.5]
     double ylo = kTile * ty + 0.5, yhi = kTile * ty + kTile - 0.5;
@@ -214,7 +241,8 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
     for (uint32_t p = p0; p < p1; ++p) {
         const uint32_t h = __builtin_amdgcn_readfirstlane(vals[p]);
         if (h >= (uint32_t)n) continue;
-        const FlatRec &R = rec[h];
+        const FlatRec &RF = rec[h];
+        const FlatHead R = load_head(rec, h);
         const FootRec F = foot_uniform(R);
         const float *tab = tables + (int64_t)h * (kQ ? 2 * BP_MLP_NQ : BP_TAB_STRIDE);
         const int ox = X0 - R.cxi, oy = Y0 - R.cyi;   // tile corner relative to the centre pixel
@@ -234,16 +262,16 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
             bool in = r2 < R.Rt2;
             // the FP32 distance is good to ~1e-6 relative: decide pixels that close to the edge
             // with the FP64 formula of the definition
-            if (fabsf(r2 - R.Rt2) <= R.Rt2_band) in = inside_fp64(pi, pj, Gm.pix, R.thx, R.thy, R.DA, R.Rt);
+            if (fabsf(r2 - R.Rt2) <= R.Rt2_band) in = inside_fp64(pi, pj, Gm.pix, RF.thx, RF.thy, RF.DA, RF.Rt);
             if (in && inmap[q]) {
                 float u2 = R.ra2 - r2, U2 = R.rf2 - r2;
                 // next to r_a (inside) or r_f the square root of a small difference needs the
                 // difference in FP64; in zone B only the sign of u^2 is used
                 if ((u2 > 0.0f && u2 < R.ra2_edge) || U2 < R.rf2_edge) {
-                    double dxd = (double)(pi - R.cxi) + (0.5 - R.cxd), dyd = (double)(pj - R.cyi) + (0.5 - R.cyd);
+                    double dxd = (double)(pi - R.cxi) + (0.5 - RF.cxd), dyd = (double)(pj - R.cyi) + (0.5 - RF.cyd);
                     double r2d = dxd * dxd + dyd * dyd;
-                    u2 = (float)(R.ra2d - r2d);
-                    U2 = (float)(R.rf2d - r2d);
+                    u2 = (float)(RF.ra2d - r2d);
+                    U2 = (float)(RF.rf2d - r2d);
                 }
                 float vp, vn;
                 if (kQ) footprint_value_q(R, tab, r2, U2, &vp, &vn);
