@@ -134,6 +134,11 @@ enum {
     BP_META_ZE_LO, BP_META_ZE_HI,
     BP_META_PE0,      /* central electron pressure [erg/cm^3] */
     BP_META_NE0,      /* central electron density [1/cm^3] */
+    /* constants of the electron profile shape that the table integrals evaluate (FP32, from sol;
+     * lengths in physical Mpc/h): r_vir, 1/r_s, r_f, c/m(c), c^2/((1+c) m(c)), the polytropic
+     * slope a, 1/r500 and alpha_nt f(z) */
+    BP_META_PR_RV, BP_META_PR_INV_RS, BP_META_PR_RF, BP_META_PR_CM, BP_META_PR_PHI_OUT0,
+    BP_META_PR_A, BP_META_PR_INV_R500, BP_META_PR_ANT_F,
     BP_META_NFIELDS
 };
 

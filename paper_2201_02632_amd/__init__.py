@@ -36,7 +36,8 @@ SOL_NFIELDS = len(SOL_FIELDS)
 TAB_NA, TAB_NS, TAB_NB = 192, 32, 32
 TAB_ZONE = TAB_NA + TAB_NS + TAB_NB
 TAB_STRIDE = 2 * TAB_ZONE
-META_FIELDS = ["ETA_LO", "ETA_HI", "OM_LO", "OM_HI", "ZE_LO", "ZE_HI", "PE0", "NE0"]
+META_FIELDS = ["ETA_LO", "ETA_HI", "OM_LO", "OM_HI", "ZE_LO", "ZE_HI", "PE0", "NE0", "PR_RV", "PR_INV_RS",
+               "PR_RF", "PR_CM", "PR_PHI_OUT0", "PR_A", "PR_INV_R500", "PR_ANT_F"]
 META = {name: k for k, name in enumerate(META_FIELDS)}
 META_NFIELDS = len(META_FIELDS)
 

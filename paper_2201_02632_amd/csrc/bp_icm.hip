@@ -486,7 +486,9 @@ __global__ void __launch_bounds__(BP_TAB_NA) k_node_geom(double eta_hi) {
 }
 
 // Per-halo grid ranges and central values (one lane per halo): the zone ranges in eta, omega and
-// zeta, P_e0 and n_e0.  Written to meta, from which the table kernel and the deposits read them.
+// zeta, P_e0 and n_e0, and the profile-shape constants of the table integrals.  Written to meta,
+// from which the table kernels and the deposits read them: computing the constants here, once per
+// halo, keeps their FP64 logarithm and divisions out of every wavefront of the table kernels.
 __global__ void __launch_bounds__(256) k_table_setup(bp_params P, GaussRules G, int64_t n,
                                                      const double *__restrict__ sol, const int32_t *__restrict__ status,
                                                      float *__restrict__ meta) {
@@ -518,6 +520,15 @@ __global__ void __launch_bounds__(256) k_table_setup(bp_params P, GaussRules G, 
         m[BP_META_ZE_HI] = (float)ze_hi;
         m[BP_META_PE0] = (float)((2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0));
         m[BP_META_NE0] = (float)(S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp));
+        const double c = S(BP_SOL_C), mc = nfw_m(c);
+        m[BP_META_PR_RV] = (float)rv;
+        m[BP_META_PR_INV_RS] = (float)(1.0 / S(BP_SOL_RS));
+        m[BP_META_PR_RF] = (float)rf;
+        m[BP_META_PR_CM] = (float)(c / mc);
+        m[BP_META_PR_PHI_OUT0] = (float)(c * c / ((1.0 + c) * mc));
+        m[BP_META_PR_A] = (float)S(BP_SOL_A);
+        m[BP_META_PR_INV_R500] = (float)(1.0 / S(BP_SOL_R500));
+        m[BP_META_PR_ANT_F] = (float)(P.alpha_nt * S(BP_SOL_FNT));
     }
     for (int f = 0; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = m[f];
 }
@@ -527,7 +538,7 @@ __global__ void __launch_bounds__(256) k_table_setup(bp_params P, GaussRules G, 
 // One table node (both quantities) of halo i.
 __device__ inline void table_node(const GaussRules &G, int64_t n, const double *__restrict__ sol,
                                   const int32_t *__restrict__ status, const float *__restrict__ meta,
-                                  float *__restrict__ tab, double ant, float n_nt, int64_t i, int node) {
+                                  float *__restrict__ tab, float n_nt, int64_t i, int node) {
     auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
     auto Mt = [&](int f) { return (double)meta[(int64_t)f * n + i]; };
     float *tP = tab + (int64_t)i * BP_TAB_STRIDE;
@@ -536,15 +547,15 @@ __device__ inline void table_node(const GaussRules &G, int64_t n, const double *
         tP[node] = 0.0f; tN[node] = 0.0f;
         return;
     }
-    // per-halo constants (wave-uniform)
+    // per-halo constants (wave-uniform); the profile-shape ones come from meta
     const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), Rt = S(BP_SOL_RT);
-    const double c = S(BP_SOL_C), mc = nfw_m(c);
+    auto Mf = [&](int f) { return meta[(int64_t)f * n + i]; };
     Prof Q;
-    Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
-    Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
-    Q.a = (float)S(BP_SOL_A);
-    Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
-    Q.ant_f = (float)(ant * S(BP_SOL_FNT));
+    Q.rv = Mf(BP_META_PR_RV); Q.inv_rs = Mf(BP_META_PR_INV_RS); Q.rf = Mf(BP_META_PR_RF);
+    Q.cm = Mf(BP_META_PR_CM); Q.phi_out0 = Mf(BP_META_PR_PHI_OUT0);
+    Q.a = Mf(BP_META_PR_A);
+    Q.inv_r500 = Mf(BP_META_PR_INV_R500);
+    Q.ant_f = Mf(BP_META_PR_ANT_F);
     Q.n_nt = n_nt;
     const double eta_lo = Mt(BP_META_ETA_LO), eta_hi = Mt(BP_META_ETA_HI);
     const double om_lo = Mt(BP_META_OM_LO), om_hi = Mt(BP_META_OM_HI);
@@ -655,8 +666,8 @@ __device__ inline void table_node(const GaussRules &G, int64_t n, const double *
 __global__ void __launch_bounds__(BP_TAB_NA) k_tables(GaussRules G, int64_t n, const double *__restrict__ sol,
                                                       const int32_t *__restrict__ status,
                                                       const float *__restrict__ meta, float *__restrict__ tab,
-                                                      double ant, float n_nt) {
-    table_node(G, n, sol, status, meta, tab, ant, n_nt, blockIdx.x, threadIdx.x);
+                                                      float n_nt) {
+    table_node(G, n, sol, status, meta, tab, n_nt, blockIdx.x, threadIdx.x);
 }
 
 static_assert(BP_TAB_NS == 32 && BP_TAB_NB == 32, "k_tables_sb maps 32 nodes of each zone to half a wavefront");
@@ -666,11 +677,11 @@ static_assert(BP_TAB_NS == 32 && BP_TAB_NB == 32, "k_tables_sb maps 32 nodes of 
 __global__ void __launch_bounds__(128) k_tables_sb(GaussRules G, int64_t n, const double *__restrict__ sol,
                                                    const int32_t *__restrict__ status,
                                                    const float *__restrict__ meta, float *__restrict__ tab,
-                                                   double ant, float n_nt) {
+                                                   float n_nt) {
     const int64_t i = 2 * (int64_t)blockIdx.x + ((threadIdx.x >> 5) & 1);
     if (i >= n) return;
     const int zone = threadIdx.x >> 6;                  // 0: S, 1: B
-    table_node(G, n, sol, status, meta, tab, ant, n_nt, i, BP_TAB_NA + zone * BP_TAB_NS + (threadIdx.x & 31));
+    table_node(G, n, sol, status, meta, tab, n_nt, i, BP_TAB_NA + zone * BP_TAB_NS + (threadIdx.x & 31));
 }
 
 // ------------------------------------------------------- Gauss-Legendre --
@@ -761,9 +772,9 @@ extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *so
     hipLaunchKernelGGL(k_node_geom, dim3(1), dim3(BP_TAB_NA), 0, s, (double)(float)G.eta_top);
     hipLaunchKernelGGL(k_table_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, *p, G, n, sol, status, meta);
     hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_NA), 0, s, G, n, sol, status, meta, tables,
-                       p->alpha_nt, (float)p->n_nt);
+                       (float)p->n_nt);
     hipLaunchKernelGGL(k_tables_sb, dim3((unsigned)((n + 1) / 2)), dim3(128), 0, s, G, n, sol, status, meta,
-                       tables, p->alpha_nt, (float)p->n_nt);
+                       tables, (float)p->n_nt);
     prof_end(BP_PROF_TABLES, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
