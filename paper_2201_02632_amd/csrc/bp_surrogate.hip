@@ -215,6 +215,7 @@ __global__ void k_apply(bp_params P, int64_t n, const float *__restrict__ y, con
         meta[(int64_t)BP_META_NE0 * n + i] =
             (float)(ne_scale(P, sol[(int64_t)BP_SOL_M * n + i], rv) * exp((double)(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2])));
         for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
+        for (int f = BP_META_PR_RV; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = 0.0f;
     }
 }
 

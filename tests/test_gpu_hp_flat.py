@@ -94,6 +94,35 @@ def test_icm_bad_inputs(bp):
         bp.icm_solve(bp.default_params(Gamma=1.0), T(M), T(c), T(z))
 
 
+def test_meta_profile_constants(bp):
+    # the profile-shape constants the table kernels read from meta are the FP32 values of their
+    # definitions from the solve's FP64 fields (computed once per halo in the set-up kernel)
+    import torch
+    params = bp.default_params()
+    rng = np.random.default_rng(7)
+    n = 3000
+    M = 10 ** rng.uniform(12.5, 15.5, n)
+    c = rng.uniform(2.0, 15.0, n)
+    z = rng.uniform(0.05, 3.0, n)
+    sol, st = bp.icm_solve(params, T(M), T(c), T(z))
+    _, meta = bp.profile_tables(params, sol, st)
+    torch.cuda.synchronize()
+    S, m, st = sol.cpu().numpy(), meta.cpu().numpy(), st.cpu().numpy()
+    ok = (st & ~bp.S_MULTI_ROOT) == 0
+    assert ok.sum() > 0.9 * n
+    F = lambda name: S[bp.SOL[name]][ok]
+    cc = F("C")
+    mc = np.log1p(cc) - cc / (1.0 + cc)
+    expect = {"PR_RV": F("RVIR"), "PR_INV_RS": 1.0 / F("RS"), "PR_RF": F("RF"), "PR_CM": cc / mc,
+              "PR_PHI_OUT0": cc * cc / ((1.0 + cc) * mc), "PR_A": F("A"), "PR_INV_R500": 1.0 / F("R500"),
+              "PR_ANT_F": params.alpha_nt * F("FNT")}
+    for name, v in expect.items():
+        g = m[bp.META[name]][ok].astype(np.float64)
+        # one FP32 rounding of the same FP64 value, up to the last bit of the FP64 expression
+        assert np.all(np.abs(g - v) <= 1.2e-7 * np.abs(v)), name
+    assert np.all(m[bp.META["PR_RV"]:, ~ok] == 0.0)
+
+
 def test_tables_against_los(bp, orc):
     import torch
     params = bp.default_params()
