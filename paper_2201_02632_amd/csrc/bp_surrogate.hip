@@ -192,10 +192,9 @@ __global__ void k_mse(int64_t n, const float *__restrict__ y, const float *__res
     if (lane == 0) loss[i] = acc;
 }
 
-// network output -> sol (XF, RF, RT), q-tables (G values) and meta (PE0, NE0)
-__global__ void k_apply(bp_params P, int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
-                        const float *__restrict__ sd, double *__restrict__ sol, const int32_t *__restrict__ status,
-                        float *__restrict__ qt, float *__restrict__ meta) {
+// network output -> q-tables (G values): one thread per (halo, q node), pure streaming
+__global__ void k_apply_q(int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
+                          const float *__restrict__ sd, const int32_t *__restrict__ status, float *__restrict__ qt) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * 2 * BP_MLP_NQ) return;
     int64_t i = e / (2 * BP_MLP_NQ);
@@ -203,20 +202,28 @@ __global__ void k_apply(bp_params P, int64_t n, const float *__restrict__ y, con
     if (status[i]) return;
     const float *row = y + i * BP_MLP_OUT;
     qt[i * 2 * BP_MLP_NQ + k] = __expf(row[k] * sd[k] + mean[k]);
-    if (k == 0) {
-        const int c0 = 2 * BP_MLP_NQ;
-        double xf = exp((double)(row[c0] * sd[c0] + mean[c0]));
-        double rv = sol[(int64_t)BP_SOL_RVIR * n + i];
-        sol[(int64_t)BP_SOL_XF * n + i] = xf;
-        sol[(int64_t)BP_SOL_RF * n + i] = xf * rv;
-        sol[(int64_t)BP_SOL_RT * n + i] = fmin(xf * rv, P.trunc_r500 * sol[(int64_t)BP_SOL_R500 * n + i]);
-        meta[(int64_t)BP_META_PE0 * n + i] =
-            (float)(sol[(int64_t)BP_SOL_PS * n + i] * exp((double)(row[c0 + 1] * sd[c0 + 1] + mean[c0 + 1])));
-        meta[(int64_t)BP_META_NE0 * n + i] =
-            (float)(ne_scale(P, sol[(int64_t)BP_SOL_M * n + i], rv) * exp((double)(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2])));
-        for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
-        for (int f = BP_META_PR_RV; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = 0.0f;
-    }
+}
+
+// network output -> sol (XF, RF, RT) and meta (PE0, NE0): one thread per halo.  A launch of its
+// own, so that this FP64 work does not run on one lane of a wavefront while the other 63 wait.
+__global__ void k_apply_halo(bp_params P, int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
+                             const float *__restrict__ sd, double *__restrict__ sol,
+                             const int32_t *__restrict__ status, float *__restrict__ meta) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || status[i]) return;
+    const float *row = y + i * BP_MLP_OUT;
+    const int c0 = 2 * BP_MLP_NQ;
+    double xf = exp((double)(row[c0] * sd[c0] + mean[c0]));
+    double rv = sol[(int64_t)BP_SOL_RVIR * n + i];
+    sol[(int64_t)BP_SOL_XF * n + i] = xf;
+    sol[(int64_t)BP_SOL_RF * n + i] = xf * rv;
+    sol[(int64_t)BP_SOL_RT * n + i] = fmin(xf * rv, P.trunc_r500 * sol[(int64_t)BP_SOL_R500 * n + i]);
+    meta[(int64_t)BP_META_PE0 * n + i] =
+        (float)(sol[(int64_t)BP_SOL_PS * n + i] * exp((double)(row[c0 + 1] * sd[c0 + 1] + mean[c0 + 1])));
+    meta[(int64_t)BP_META_NE0 * n + i] =
+        (float)(ne_scale(P, sol[(int64_t)BP_SOL_M * n + i], rv) * exp((double)(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2])));
+    for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
+    for (int f = BP_META_PR_RV; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = 0.0f;
 }
 
 }  // namespace bp
@@ -269,8 +276,8 @@ extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y,
     if (n == 0) return BP_OK;
     hipStream_t s = (hipStream_t)stream;
     prof_begin(BP_PROF_SURR_APPLY, s);
-    hipLaunchKernelGGL(k_apply, dim3(nblk(n * 2 * BP_MLP_NQ)), dim3(256), 0, s, *p, n, y, mean, std, sol, status,
-                       qtables, meta);
+    hipLaunchKernelGGL(k_apply_q, dim3(nblk(n * 2 * BP_MLP_NQ)), dim3(256), 0, s, n, y, mean, std, status, qtables);
+    hipLaunchKernelGGL(k_apply_halo, dim3(nblk(n)), dim3(256), 0, s, *p, n, y, mean, std, sol, status, meta);
     prof_end(BP_PROF_SURR_APPLY, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
