@@ -378,7 +378,8 @@ int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const floa
 /* Apply the network output: completes sol (XF, RF, RT) for in-domain halos
  * whose structure came from bp_halo_structure, writes q-tables
  * [n][2*BP_MLP_NQ] (G values, not logs) and meta (PE0, NE0; the grid and
- * profile-constant fields 0). */
+ * profile-constant fields 0).  y, mean, std and qtables must be 16-byte
+ * aligned (as every device allocation is); otherwise BP_E_ARG. */
 int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
                        double *sol, const int32_t *status, float *qtables, float *meta, void *stream);
 /* Device-side training loop: `steps` Adam steps on batches of `batch` rows drawn

@@ -192,16 +192,26 @@ __global__ void k_mse(int64_t n, const float *__restrict__ y, const float *__res
     if (lane == 0) loss[i] = acc;
 }
 
-// network output -> q-tables (G values): one thread per (halo, q node), pure streaming
+// network output -> q-tables (G values): one thread per (halo, 4 q nodes), 16-byte loads and
+// stores (rows of BP_MLP_OUT and 2 BP_MLP_NQ floats keep every group of four aligned)
+static_assert(BP_MLP_OUT % 4 == 0 && (2 * BP_MLP_NQ) % 4 == 0, "16-byte groups");
 __global__ void k_apply_q(int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
                           const float *__restrict__ sd, const int32_t *__restrict__ status, float *__restrict__ qt) {
+    constexpr int G4 = 2 * BP_MLP_NQ / 4;
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * 2 * BP_MLP_NQ) return;
-    int64_t i = e / (2 * BP_MLP_NQ);
-    int k = (int)(e % (2 * BP_MLP_NQ));
+    if (e >= n * G4) return;
+    int64_t i = e / G4;
+    int k = 4 * (int)(e % G4);
     if (status[i]) return;
-    const float *row = y + i * BP_MLP_OUT;
-    qt[i * 2 * BP_MLP_NQ + k] = __expf(row[k] * sd[k] + mean[k]);
+    const float4 r = *reinterpret_cast<const float4 *>(y + i * BP_MLP_OUT + k);
+    const float4 s = *reinterpret_cast<const float4 *>(sd + k);
+    const float4 m = *reinterpret_cast<const float4 *>(mean + k);
+    float4 g;
+    g.x = __expf(r.x * s.x + m.x);
+    g.y = __expf(r.y * s.y + m.y);
+    g.z = __expf(r.z * s.z + m.z);
+    g.w = __expf(r.w * s.w + m.w);
+    *reinterpret_cast<float4 *>(qt + i * 2 * BP_MLP_NQ + k) = g;
 }
 
 // network output -> sol (XF, RF, RT) and meta (PE0, NE0): one thread per halo.  A launch of its
@@ -274,9 +284,10 @@ extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y,
                                   double *sol, const int32_t *status, float *qtables, float *meta, void *stream) {
     if (!p || n < 0 || (n > 0 && (!y || !mean || !std || !sol || !status || !qtables || !meta))) return BP_E_ARG;
     if (n == 0) return BP_OK;
+    if (((uintptr_t)y | (uintptr_t)mean | (uintptr_t)std | (uintptr_t)qtables) & 15) return BP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     prof_begin(BP_PROF_SURR_APPLY, s);
-    hipLaunchKernelGGL(k_apply_q, dim3(nblk(n * 2 * BP_MLP_NQ)), dim3(256), 0, s, n, y, mean, std, status, qtables);
+    hipLaunchKernelGGL(k_apply_q, dim3(nblk(n * 2 * BP_MLP_NQ / 4)), dim3(256), 0, s, n, y, mean, std, status, qtables);
     hipLaunchKernelGGL(k_apply_halo, dim3(nblk(n)), dim3(256), 0, s, *p, n, y, mean, std, sol, status, meta);
     prof_end(BP_PROF_SURR_APPLY, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
