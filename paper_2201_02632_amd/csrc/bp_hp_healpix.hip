@@ -124,8 +124,8 @@ __host__ __device__ inline int64_t tile_first_pixel(int64_t t, int64_t npr, int6
 // Visit the tiles a halo's disc can touch.  For each ring the disc reaches, the longitudes of
 // its pixels that can be members lie within dphi_max of the halo (padded by two pixel steps for
 // rounding); per band the union of these intervals (they all contain the halo's longitude) is
-// cut into the band's tiles.  f(tile) is called in a deterministic order; count and emit use this
-// same routine.  sin((theta_r - theta_h)/2) comes from the half-angle sines and cosines.
+// cut into the band's tiles.  f(first, last) is called for runs of consecutive tiles (inclusive)
+// in a deterministic order; count and emit use this same routine.  sin((theta_r - theta_h)/2) comes from the half-angle sines and cosines.
 template <class F>
 __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const RingRec *__restrict__ rtab,
                                      const uint32_t *__restrict__ btile0, F &&f) {
@@ -149,18 +149,18 @@ __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const Ri
             const double tpr = (double)nmax / (kTw * kTwoPi);   // tiles per radian
             auto tl = [&](double x) { return (int)fmin(fmax(floor(x * tpr), 0.0), (double)(T - 1)); };
             if (flo >= 0.0 && fhi < kTwoPi) {
-                for (int t = tl(flo); t <= tl(fhi); ++t) f(base + (uint32_t)t);
+                f(base + (uint32_t)tl(flo), base + (uint32_t)tl(fhi));
                 return;
             }
             // the interval wraps through phi = 0: [lo1, T) and [0, hi2]
             const int lo1 = tl(flo < 0.0 ? flo + kTwoPi : flo), hi2 = tl(flo < 0.0 ? fhi : fhi - kTwoPi);
             if (hi2 < lo1) {
-                for (int t = 0; t <= hi2; ++t) f(base + (uint32_t)t);
-                for (int t = lo1; t < T; ++t) f(base + (uint32_t)t);
+                f(base, base + (uint32_t)hi2);
+                f(base + (uint32_t)lo1, base + (uint32_t)(T - 1));
                 return;
             }
         }
-        for (int t = 0; t < T; ++t) f(base + (uint32_t)t);
+        f(base, base + (uint32_t)(T - 1));
     };
     for (int i = (int)ilo; i <= (int)ihi; ++i) {
         const int b = (i - 1) / kBand;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256) k_hpx_setup(bp_params P, HpxGeom G, int64
             double sp = Rt / DA;
             double hav = (sp > 1e-4) ? 0.5 * (1.0 - cos(asin(sp))) : 0.25 * sp * sp * (1.0 + 0.25 * sp * sp);
             r.hmax = (float)(hav * (1.0 + 1e-5) + 1e-30);
-            for_each_tile(G, r, rtab, btile0, [&](uint32_t) { ++count; });
+            for_each_tile(G, r, rtab, btile0, [&](uint32_t a, uint32_t b) { if (b >= a) count += b - a + 1; });
         }
         rec[i] = r;
         cnt[i] = count;
@@ -259,8 +259,8 @@ __global__ void __launch_bounds__(256) k_hpx_emit(HpxGeom G, int64_t n, const Hp
     const HpxRec r = rec[i];
     if (!(r.flags & 4)) return;
     uint32_t k = off[i], end = off[i + 1];
-    for_each_tile(G, r, rtab, btile0, [&](uint32_t tile) {
-        if (k < end) { keys[k] = tile; vals[k] = (uint32_t)i; ++k; }
+    for_each_tile(G, r, rtab, btile0, [&](uint32_t a, uint32_t b) {
+        for (uint32_t tile = a; tile <= b && k < end; ++tile) { keys[k] = tile; vals[k] = (uint32_t)i; ++k; }
     });
 }
 
