@@ -424,8 +424,8 @@ def main():
                     help="only run plain 1 GiB device copies (reference reading for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
-                                   "design notes but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only: the library has no multi-GPU path "
+                                   "(no sharding or collectives)", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
