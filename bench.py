@@ -32,7 +32,7 @@ DEPOSIT_OPS_PER_PX = 62
 # HBM bytes per deposit launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99994, WRITE x 1.0).
 # Valid only for the deposit sources they were measured on.
-DEPOSIT_TRAFFIC = {"bytes": 2687001578,
+DEPOSIT_TRAFFIC = {"bytes": 2683816617,
                    "sources_sha256": {"bp_hp_flat.hip": "cf34621bcd32c6473760a4457cdd1b18d78b1a3dd9f7be635cd7abf6c0d2545b",
                                       "bp_footprint.hpp": "42c816bea0bc9eadcecc24576c949ee7c9eb52d8ea63cbea0813c080b6544c4f"}}
 
