@@ -39,3 +39,19 @@ def test_binding_mirrors_header():
 def test_strerror_without_gpu():
     import paper_2201_02632_amd as bp
     assert bp._lib.bp_strerror(bp.BP_E_WORKSPACE) == b"workspace too small"
+
+
+def test_argument_checks_before_any_device_call():
+    # entry points reject bad arguments on the host, before touching memory or the GPU: here
+    # misaligned table pointers (the q-table assembly uses 16-byte accesses) and empty inputs
+    import paper_2201_02632_amd as bp
+    p = bp.default_params()
+    ok, odd = 0x10000, 0x10004            # never dereferenced: the checks return first
+    args = dict(y=ok, mean=ok, std=ok, sol=ok, status=ok, qtables=ok, meta=ok)
+    call = lambda a, n=1: bp._lib.bp_surrogate_apply(ctypes.byref(p), n, a["y"], a["mean"], a["std"], a["sol"],
+                                                     a["status"], a["qtables"], a["meta"], None)
+    for key in ("y", "mean", "std", "qtables"):
+        assert call(dict(args, **{key: odd})) == bp.BP_E_ARG, key
+    assert call(dict(args, y=None)) == bp.BP_E_ARG
+    assert call(args, n=-1) == bp.BP_E_ARG
+    assert call(dict(args, y=odd), n=0) == bp.BP_OK      # nothing to do, nothing checked
