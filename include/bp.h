@@ -60,7 +60,9 @@ extern "C" {
  * parameters of Table 1, plus the readings the paper leaves open. */
 typedef struct {
     double Omega_m, Omega_b, h;
-    double Gamma;          /* adiabatic index; polytropic index n = 1/(Gamma-1) */
+    double Gamma;          /* adiabatic index, fixed at the paper's 1.2 (Sec. 2.1, Table 1): the kernels are
+                              written for the polytropic index n = 1/(Gamma-1) = 5, and every entry point
+                              taking bp_params returns BP_E_ARG for any other value */
     double eps_DM;         /* energy transfer from dark matter */
     double eps_star;       /* stellar feedback efficiency */
     double f_star, S_star; /* stellar-to-halo mass relation amplitude and slope */
@@ -287,8 +289,9 @@ int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_t n, const 
  * (divided by N, where |cos theta| > 0.66).  bounds (host, 4 doubles, OUTPUT): measured z error,
  * measured cap-factor error / N, then the two bounds the paste assumes.  A measured value above
  * its bound would mean the paste's pixel indices can differ from the FP64 assignment.
- * nside in [1, 2048]; synchronises the stream; allocates 8 bytes of device memory. */
-int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *stream);
+ * nside in [1, 2048].  Workspace protocol as for the pastes (256 bytes); synchronises the stream. */
+int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *ws, size_t ws_bytes, size_t *ws_needed,
+                                void *stream);
 
 /* Flat-sky angular power spectrum of an npix x npix map (Sec. 5.3: FFT of the flat-sky maps in
  * logarithmic multipole bins, 30 over 10^2 < ell < 10^5 in the paper):

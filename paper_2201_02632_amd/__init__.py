@@ -82,7 +82,8 @@ _SIGS = {
                                    C.POINTER(C.c_size_t), _VP]),
     "bp_pp_paste_healpix_ngp": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, C.c_double, _VP, _VP,
                                           C.c_size_t, C.POINTER(C.c_size_t), _VP]),
-    "bp_pp_healpix_ngp_selfcheck": (C.c_int, [C.c_int64, C.POINTER(C.c_double), _VP]),
+    "bp_pp_healpix_ngp_selfcheck": (C.c_int, [C.c_int64, C.POINTER(C.c_double), _VP, C.c_size_t,
+                                              C.POINTER(C.c_size_t), _VP]),
     "bp_flat_power_spectrum": (C.c_int, [C.c_int32, C.c_double, _VP, C.c_int32, C.POINTER(C.c_double), _VP, _VP,
                                          _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_mlp_nparams": (C.c_int64, []),
@@ -307,11 +308,12 @@ def pp_paste_healpix_ngp(params: Params, nside: int, theta, phi, z, v_los, M_p: 
                      _ptr(b_map)))
 
 
-def pp_healpix_ngp_selfcheck(nside: int = 1024):
+def pp_healpix_ngp_selfcheck(nside: int = 1024, ws: Workspace | None = None):
     """Measured (z error, cap-factor error / N) of the nearest-pixel paste's FP32 screen and the
     bounds it assumes, over every float colatitude."""
     out = (C.c_double * 4)()
-    _check(_lib.bp_pp_healpix_ngp_selfcheck(int(nside), out, _stream()), "bp_pp_healpix_ngp_selfcheck")
+    ws = ws or _ws_for(torch.device("cuda", torch.cuda.current_device()))
+    _with_workspace(_lib.bp_pp_healpix_ngp_selfcheck, "bp_pp_healpix_ngp_selfcheck", ws, (int(nside), out))
     return {"z_err": out[0], "tmp_err_per_n": out[1], "z_bound": out[2], "tmp_bound_per_n": out[3]}
 
 

@@ -300,7 +300,7 @@ static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int
                                 const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
                                 const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
                                 size_t ws_bytes, size_t *ws_needed, void *stream) {
-    if (!p || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed) return BP_E_ARG;
+    if (check_params(p) || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta_x || !theta_y || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
     if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;

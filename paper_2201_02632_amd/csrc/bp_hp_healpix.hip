@@ -380,7 +380,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
                               const double *v_los, const double *sol, const int32_t *status, const float *tables,
                               const float *meta, float *y_map, float *b_map, void *ws, size_t ws_bytes,
                               size_t *ws_needed, void *stream) {
-    if (!p || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
+    if (check_params(p) || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta || !phi || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
     if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;

@@ -732,11 +732,19 @@ const GaussRules &gauss_rules() {
 
 using namespace bp;
 
-static int check_params(const bp_params *p) {
+// The kernels are written for the paper's adiabatic index Gamma = 1.2 (Sec. 2.1, Table 1), i.e. the
+// polytropic index n = 1/(Gamma - 1) = 5: the moment expansion of the gas-mass and pressure
+// conditions (binomials of order 5 and 6), the table integrand theta^5 and theta^6 and the particle
+// amplitudes use it as a constant.  Any other Gamma is an argument error, not a silent misfit.
+int bp::check_params(const bp_params *p) {
     if (!p) return BP_E_ARG;
     if (!(p->Omega_m > 0 && p->Omega_m <= 1.0) || !(p->Omega_b > 0 && p->Omega_b < p->Omega_m) || !(p->h > 0) ||
-        !(p->Gamma > 1.0) || !(p->alpha_nt > 0) || !(p->n_nt > 0) || !(p->trunc_r500 > 0) ||
-        !(p->X_H > 0 && p->X_H <= 1) || (p->energy_sign != 0 && p->energy_sign != 1))
+        p->Gamma != 1.2 || !(p->alpha_nt > 0) || !(p->n_nt > 0) || !(p->trunc_r500 > 0) ||
+        !(p->X_H > 0 && p->X_H <= 1) || (p->energy_sign != 0 && p->energy_sign != 1) ||
+        !(p->field_gas_frac >= 0 && p->field_gas_frac <= 1) || !(p->field_T >= 0 && p->field_T < 1e12) ||
+        !(p->eps_DM >= 0 && p->eps_DM < 1e3) || !(p->eps_star >= 0 && p->eps_star < 1e3) ||
+        !(p->f_star >= 0 && p->f_star < 1e3) || !(p->S_star > -1e3 && p->S_star < 1e3) ||
+        !(p->beta_nt > -1e3 && p->beta_nt < 1e3))
         return BP_E_ARG;
     return BP_OK;
 }

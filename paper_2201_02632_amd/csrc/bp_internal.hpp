@@ -17,6 +17,10 @@ namespace bp {
 
 const GaussRules &gauss_rules();
 
+// Validate the model parameters (every entry point that takes bp_params): BP_OK or BP_E_ARG.
+// Gamma must be the paper's 1.2, the polytropic index the kernels are written for.
+int check_params(const bp_params *p);
+
 // Bump allocator over a caller-provided workspace; sizes rounded to 256 B.
 struct Arena {
     char *base;

@@ -474,7 +474,7 @@ struct PPRec {        // per-particle deposit record (40 bytes)
     float ih;         // pixel size / angular smoothing length
     float ay, ab;     // y and b amplitudes (integral of the footprint)
     int32_t i0, j0;   // first pixel column / row of the support square (clipped)
-    int32_t wh;       // width | height << 16 of the clipped support in pixels (0 = no pixels)
+    uint32_t wh;      // width | height << 16 of the clipped support in pixels (0 = no pixels; npix <= 65535)
 };
 
 __global__ void __launch_bounds__(256) k_pp_amplitudes(bp_params P, int64_t n, int npix, double pix,
@@ -541,7 +541,7 @@ __global__ void __launch_bounds__(256) k_pp_amplitudes(bp_params P, int64_t n, i
         int j0 = (int)fmax(floor(y0), 0.0), j1 = (int)fmin(floor(y1), (double)(npix - 1));
         if (i1 >= i0 && j1 >= j0 && x1 >= 0.0 && y1 >= 0.0 && x0 < npix && y0 < npix) {
             R.i0 = i0; R.j0 = j0;
-            R.wh = (i1 - i0 + 1) | ((j1 - j0 + 1) << 16);
+            R.wh = (uint32_t)(i1 - i0 + 1) | ((uint32_t)(j1 - j0 + 1) << 16);
         }
     }
     rec[i] = R;
@@ -800,7 +800,7 @@ using namespace bp;
 static int smoothing_length_impl(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
                                  const float *z, int32_t k, double n_ngb, double cell, float *h_comoving, void *ws,
                                  size_t ws_bytes, size_t *ws_needed, void *stream) {
-    if (!p || n < 0 || k < 1 || k > kKmax || !ws_needed || !(cell >= 0.0)) return BP_E_ARG;
+    if (check_params(p) || n < 0 || k < 1 || k > kKmax || !ws_needed || !(cell >= 0.0)) return BP_E_ARG;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     if (!theta_x || !theta_y || !z || !h_comoving) return BP_E_ARG;
     if (n >= 0x7fffffffLL || n <= k) return n <= k ? BP_E_ARG : BP_E_OVERFLOW;
@@ -913,7 +913,9 @@ extern "C" int bp_pp_paste_flat(const bp_params *p, int32_t npix, double pix_rad
                                 const float *r_halo, const float *h_comoving, double M_p, int64_t n_halos,
                                 const double *sol, const int32_t *status, float *y_map, float *b_map, void *ws,
                                 size_t ws_bytes, size_t *ws_needed, void *stream) {
-    if (!p || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed || !(M_p > 0) || n_halos < 0)
+    // npix <= 65535: a particle's clipped footprint width and height share one 32-bit word (16 bits each)
+    if (check_params(p) || npix <= 0 || npix > 65535 || !(pix_rad > 0) || n < 0 || !ws_needed || !(M_p > 0) ||
+        n_halos < 0)
         return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
     if (n == 0) { *ws_needed = 0; return BP_OK; }

@@ -405,11 +405,14 @@ __global__ void k_ngp_trig_check(int N, uint32_t last, uint32_t *__restrict__ ou
 
 using namespace bp;
 
-extern "C" int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *stream) {
-    if (nside < 1 || nside > 2048 || !bounds) return BP_E_ARG;
+extern "C" int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *ws, size_t ws_bytes,
+                                           size_t *ws_needed, void *stream) {
+    if (nside < 1 || nside > 2048 || !bounds || !ws_needed) return BP_E_ARG;
+    const size_t need = 256;   // two uint32 maxima, rounded as the workspace arena rounds
+    *ws_needed = need;
+    if (!ws || ws_bytes < need) return BP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    uint32_t *d = nullptr;
-    if (hipMallocAsync((void **)&d, 2 * sizeof(uint32_t), s) != hipSuccess) return BP_E_HIP;
+    uint32_t *d = (uint32_t *)ws;
     int e = fill_u32(d, 0u, 2, s);
     const float pi_below = 3.14159250f;   // the largest float below pi
     uint32_t last;
@@ -421,7 +424,6 @@ extern "C" int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *
     uint32_t h[2] = {0u, 0u};
     if (!e && hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess) e = BP_E_HIP;
     if (!e && hipStreamSynchronize(s) != hipSuccess) e = BP_E_HIP;
-    (void)hipFreeAsync(d, s);
     if (e) return e;
     float f[2];
     memcpy(f, h, sizeof(f));
@@ -435,7 +437,7 @@ extern "C" int bp_pp_healpix_ngp_selfcheck(int64_t nside, double *bounds, void *
 extern "C" int bp_pp_paste_healpix_ngp(const bp_params *p, int64_t nside, int64_t n, const float *theta,
                                        const float *phi, const float *z, const float *v_los, double M_p,
                                        float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
-    if (!p || nside < 1 || nside > 2048 || n < 0 || !ws_needed || !(M_p > 0) || !b_map) return BP_E_ARG;
+    if (check_params(p) || nside < 1 || nside > 2048 || n < 0 || !ws_needed || !(M_p > 0) || !b_map) return BP_E_ARG;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     if (!theta || !phi || !z || !v_los) return BP_E_ARG;
     if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;

@@ -252,7 +252,7 @@ extern "C" int bp_surrogate_features(int64_t n, const double *M, const double *c
 
 extern "C" int bp_surrogate_targets(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
                                     const float *tables, const float *meta, float *targets, void *stream) {
-    if (!p || n < 0 || (n > 0 && (!sol || !status || !tables || !meta || !targets))) return BP_E_ARG;
+    if (check_params(p) || n < 0 || (n > 0 && (!sol || !status || !tables || !meta || !targets))) return BP_E_ARG;
     if (n == 0) return BP_OK;
     hipLaunchKernelGGL(k_targets, dim3(nblk(n * BP_MLP_NQ)), dim3(256), 0, (hipStream_t)stream, *p, n, sol, status,
                        tables, meta, targets);
@@ -282,7 +282,8 @@ extern "C" int bp_surrogate_mse(int64_t n, const float *y, const float *targets,
 
 extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
                                   double *sol, const int32_t *status, float *qtables, float *meta, void *stream) {
-    if (!p || n < 0 || (n > 0 && (!y || !mean || !std || !sol || !status || !qtables || !meta))) return BP_E_ARG;
+    if (check_params(p) || n < 0 || (n > 0 && (!y || !mean || !std || !sol || !status || !qtables || !meta)))
+        return BP_E_ARG;
     if (n == 0) return BP_OK;
     if (((uintptr_t)y | (uintptr_t)mean | (uintptr_t)std | (uintptr_t)qtables) & 15) return BP_E_ARG;
     hipStream_t s = (hipStream_t)stream;

@@ -55,3 +55,56 @@ def test_argument_checks_before_any_device_call():
     assert call(dict(args, y=None)) == bp.BP_E_ARG
     assert call(args, n=-1) == bp.BP_E_ARG
     assert call(dict(args, y=odd), n=0) == bp.BP_OK      # nothing to do, nothing checked
+
+
+def test_gamma_other_than_the_papers_is_rejected():
+    # the kernels are written for Gamma = 1.2 (polytropic index 5, Sec. 2.1); every entry point that takes
+    # the parameters refuses another value before it looks at its other arguments.  With n = 0 and
+    # Gamma = 1.2 each call has nothing to do and succeeds.
+    import paper_2201_02632_amd as bp
+    L = bp._lib
+    need = ctypes.c_size_t(0)
+    fake = 0x10000                         # never dereferenced: n = 0 or the checks return first
+    for gamma in (1.2, 4.0 / 3.0, 1.2000000000000002, 1.0, float("nan")):
+        p = bp.default_params(Gamma=gamma)
+        codes = [
+            L.bp_icm_solve(ctypes.byref(p), 0, fake, fake, fake, fake, fake, None),
+            L.bp_halo_structure(ctypes.byref(p), 0, fake, fake, fake, fake, fake, None),
+            L.bp_profile_tables(ctypes.byref(p), 0, fake, fake, fake, fake, None),
+            L.bp_hp_paste_flat(ctypes.byref(p), 64, 1e-4, 0, fake, fake, fake, fake, fake, fake, fake, fake, fake,
+                               None, 0, ctypes.byref(need), None),
+            L.bp_hp_paste_healpix(ctypes.byref(p), 16, 0, fake, fake, fake, fake, fake, fake, fake, fake, fake, None,
+                                  0, ctypes.byref(need), None),
+            L.bp_pp_paste_flat(ctypes.byref(p), 64, 1e-4, 0, fake, fake, fake, fake, fake, fake, fake, 1e10, 0, None,
+                               None, fake, fake, None, 0, ctypes.byref(need), None),
+            L.bp_pp_paste_healpix_ngp(ctypes.byref(p), 16, 0, fake, fake, fake, fake, 1e10, fake, None, 0,
+                                      ctypes.byref(need), None),
+            L.bp_surrogate_targets(ctypes.byref(p), 0, fake, fake, fake, fake, fake, None),
+            L.bp_surrogate_apply(ctypes.byref(p), 0, fake, fake, fake, fake, fake, fake, fake, None),
+        ]
+        want = bp.BP_OK if gamma == 1.2 else bp.BP_E_ARG
+        assert codes == [want] * len(codes), (gamma, codes)
+
+
+def test_pp_paste_map_side_limit():
+    # a particle footprint's width and height share one 32-bit word, 16 bits each: 65535 is the largest side
+    import paper_2201_02632_amd as bp
+    p = bp.default_params()
+    need = ctypes.c_size_t(0)
+    fake = 0x10000
+    call = lambda npix: bp._lib.bp_pp_paste_flat(ctypes.byref(p), npix, 1e-6, 0, fake, fake, fake, fake, fake, fake,
+                                                 fake, 1e10, 0, None, None, fake, fake, None, 0, ctypes.byref(need),
+                                                 None)
+    assert call(65535) == bp.BP_OK          # n = 0: nothing to do
+    assert call(65536) == bp.BP_E_ARG
+    assert call(0) == bp.BP_E_ARG
+
+
+def test_ngp_selfcheck_asks_for_its_workspace():
+    # the self-check allocates nothing: its two device words come through the workspace protocol
+    import paper_2201_02632_amd as bp
+    out = (ctypes.c_double * 4)()
+    need = ctypes.c_size_t(0)
+    assert bp._lib.bp_pp_healpix_ngp_selfcheck(1024, out, None, 0, ctypes.byref(need), None) == bp.BP_E_WORKSPACE
+    assert need.value >= 8
+    assert bp._lib.bp_pp_healpix_ngp_selfcheck(4096, out, None, 0, ctypes.byref(need), None) == bp.BP_E_ARG
