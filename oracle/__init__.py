@@ -105,6 +105,7 @@ def lib():
             "orc_energy_residual_at": (C.c_double, [P, H, C.c_double]),
             "orc_profile": (None, [P, H, C.c_double, _D, _D]),
             "orc_los": (None, [P, H, C.c_double, _D, _D]),
+            "orc_los_model": (C.c_double, [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]),
             "orc_hp_flat": (C.c_int, [P, C.c_int64, _D, _D, _D, _D, _D, _D, C.c_int, C.c_double,
                                       _D, _D, H]),
             "orc_hp_flat_solved": (None, [P, C.c_int64, H, _D, _D, _D, C.c_int, C.c_double, _D, _D]),
@@ -220,6 +221,13 @@ def los(p, h: Halo, rperp):
     ty, tb = C.c_double(), C.c_double()
     lib().orc_los(C.byref(p), C.byref(h), float(rperp), C.byref(ty), C.byref(tb))
     return ty.value, tb.value
+
+
+def los_model(kind, par1, par2, rmax, rperp):
+    """2 int f dl along the sight line at impact parameter rperp through a model profile ending at rmax
+    (kind 0: uniform sphere; 1: beta model, par1 = beta, par2 = core radius; 2: 1 inside par1, par2
+    outside), by the same integration as the halo projection."""
+    return lib().orc_los_model(int(kind), float(par1), float(par2), float(rmax), float(rperp))
 
 
 def hp_flat(p, cat, npix, pix_rad):

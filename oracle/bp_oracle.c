@@ -716,12 +716,44 @@ void orc_profile(const orc_params *p, const orc_halo *o, double r_mpch, double *
     electrons_at(&pc, r_mpch * ORC_MPC / p->h, Pe, ne);
 }
 
-static double los_integrand(double l, void *vctx)
+static double los_integrand(double r, void *vctx)
 {
     const struct prof_ctx *pc = (const struct prof_ctx *)vctx;
     double Pe, ne;
-    electrons_at(pc, sqrt(pc->rperp2_cm + l * l), &Pe, &ne);
+    electrons_at(pc, r, &Pe, &ne);
     return pc->which == 0 ? Pe : ne;
+}
+
+/* Sight line through a spherical profile f(r) at impact parameter rp, out to
+ * the radius rmax where the profile ends (Sec. 3.3: each map value is the
+ * integral of the gas quantity along the line of sight):
+ *     2 int_0^sqrt(rmax^2 - rp^2) f(sqrt(rp^2 + l^2)) dl.
+ * The line is split where it crosses any of the nr radii in (rp, rmax), so
+ * that each piece has a smooth integrand (kinks of the profile). */
+struct los_ctx { orc_fn f; void *ctx; double rp2; };
+static double los_line(double l, void *vctx)
+{
+    const struct los_ctx *lc = (const struct los_ctx *)vctx;
+    return lc->f(sqrt(lc->rp2 + l * l), lc->ctx);
+}
+static double los_integral(orc_fn f, void *ctx, double rp, double rmax, const double *radii, int nr)
+{
+    if (!(rp < rmax)) return 0.0;
+    struct los_ctx lc = {f, ctx, rp * rp};
+    double L = sqrt(rmax * rmax - rp * rp);
+    double brk[10]; int nb = 0;
+    brk[nb++] = 0.0;
+    for (int k = 0; k < nr && k < 8; k++) {
+        if (!(radii[k] > rp && radii[k] < rmax)) continue;
+        double cut = sqrt(radii[k] * radii[k] - rp * rp);
+        int j = nb;                               /* insertion keeps the cuts increasing */
+        while (j > 1 && brk[j - 1] > cut) { brk[j] = brk[j - 1]; j--; }
+        brk[j] = cut; nb++;
+    }
+    brk[nb++] = L;
+    double s = 0.0;
+    for (int k = 0; k + 1 < nb; k++) s += quad(los_line, &lc, brk[k], brk[k + 1], 1e-12, 0.0);
+    return 2.0 * s;
 }
 
 /* Line-of-sight integrals through one halo at impact parameter r_perp (HP,
@@ -736,26 +768,33 @@ void orc_los(const orc_params *p, const orc_halo *o, double rperp_mpch, double *
     struct prof_ctx pc; prof_init(&pc, p, o);
     double u = ORC_MPC / p->h;
     double rp = rperp_mpch * u, rf = o->r_f * u;
-    *ty = 0; *tb = 0;
-    if (!(rp < rf)) return;
-    pc.rperp2_cm = rp * rp;
-    double L = sqrt(rf * rf - rp * rp);
-    double brk[4]; int nb = 0;
-    brk[nb++] = 0.0;
     double radii[2] = {o->r_vir * u, o->r_nt * u};
-    double cuts[2]; int nc = 0;
-    for (int k = 0; k < 2; k++)
-        if (radii[k] > rp && radii[k] < rf) cuts[nc++] = sqrt(radii[k] * radii[k] - rp * rp);
-    if (nc == 2 && cuts[0] > cuts[1]) { double t = cuts[0]; cuts[0] = cuts[1]; cuts[1] = t; }
-    for (int k = 0; k < nc; k++) brk[nb++] = cuts[k];
-    brk[nb++] = L;
-    double sy = 0, sb = 0;
-    for (int k = 0; k + 1 < nb; k++) {
-        pc.which = 0; sy += quad(los_integrand, &pc, brk[k], brk[k + 1], 1e-12, 0.0);
-        pc.which = 1; sb += quad(los_integrand, &pc, brk[k], brk[k + 1], 1e-12, 0.0);
-    }
-    *ty = ORC_SIGMA_T / ORC_ME_C2 * 2.0 * sy;
-    *tb = ORC_SIGMA_T * 2.0 * sb;
+    pc.which = 0; double sy = los_integral(los_integrand, &pc, rp, rf, radii, 2);
+    pc.which = 1; double sb = los_integral(los_integrand, &pc, rp, rf, radii, 2);
+    *ty = ORC_SIGMA_T / ORC_ME_C2 * sy;
+    *tb = ORC_SIGMA_T * sb;
+}
+
+/* Test entry point: the same sight-line integral through a model profile with
+ * a known projection, so the integration itself is pinned by closed forms.
+ *   kind 0: uniform sphere, f = 1 for r < rmax;
+ *   kind 1: beta model, f = (1 + (r/rc)^2)^(-3 beta / 2), beta = par1, rc = par2;
+ *   kind 2: two shells, f = 1 for r < par1, f = par2 for par1 <= r < rmax
+ *           (a jump at par1, given to the integral as a split radius).
+ * Lengths in any unit; returns 2 int f dl in that unit. */
+static double model_profile(double r, void *vctx)
+{
+    const double *m = (const double *)vctx;   /* kind, par1, par2 */
+    int kind = (int)m[0];
+    if (kind == 0) return 1.0;
+    if (kind == 1) return pow(1.0 + (r / m[2]) * (r / m[2]), -1.5 * m[1]);
+    return r < m[1] ? 1.0 : m[2];
+}
+double orc_los_model(int kind, double par1, double par2, double rmax, double rp)
+{
+    double m[3] = {(double)kind, par1, par2};
+    double radii[1] = {par1};
+    return los_integral(model_profile, m, rp, rmax, radii, kind == 2 ? 1 : 0);
 }
 
 /* ======================================================================== */

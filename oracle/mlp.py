@@ -81,3 +81,38 @@ def backward(w, cache, dy, bf=True):
     W1[:, :NIN] = d1.T @ cache["x"][:, :NIN]
     g["W1"] = W1
     return np.concatenate([g[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")])
+
+
+def adam(w, m, v, g, lr, beta1, beta2, eps, t):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) in FP64 from the given state:
+    m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2;
+    w <- w - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps).  Returns (w, m, v)."""
+    w, m, v, g = (np.asarray(a, np.float64) for a in (w, m, v, g))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return w - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+AUX_WEIGHT = 16.0
+
+
+def weighted_mse(y, t, mean, std):
+    """Training loss of the surrogate over the NOUT used outputs: residual r_c = y_c - (t_c - mean_c)/std_c,
+    weight 1 for the 2x64 table entries and AUX_WEIGHT for each of the three scalars (ln x_f and the two
+    amplitude ratios, which scale a whole footprint).  L = sum_i sum_c w_c r_c^2 / (n sum_c w_c).
+    Returns (dL/dy [n, OUT], per-row sum_c w_c r_c^2 [n]); a row with a non-finite target contributes
+    nothing (zero gradient), its row sum is not defined and is returned as NaN."""
+    y, t = np.asarray(y, np.float64), np.asarray(t, np.float64)
+    mean, std = np.asarray(mean, np.float64), np.asarray(std, np.float64)
+    n = y.shape[0]
+    wc = np.zeros(OUT)
+    wc[:NOUT] = 1.0
+    wc[NOUT - 3:NOUT] = AUX_WEIGHT
+    r = np.zeros_like(y)
+    r[:, :NOUT] = y[:, :NOUT] - (t[:, :NOUT] - mean[:NOUT]) / std[:NOUT]
+    ok = np.all(np.isfinite(t[:, :NOUT]), axis=1)
+    dy = np.where(ok[:, None], 2.0 * wc * r / (n * wc.sum()), 0.0)
+    rows = np.where(ok, (wc * r * r).sum(1), np.nan)
+    return dy, rows
