@@ -217,3 +217,39 @@ def test_los_profile_with_a_jump(orc, R):
     if R < r1:
         want += 2 * (1 - f2) * math.sqrt(r1 ** 2 - R ** 2)
     assert abs(orc.los_model(2, r1, f2, rmax, R) / want - 1) < 1e-12
+
+
+# ------------------------------------------------------------ cross-method (Sec. 3.3 vs Sec. 3.4) --
+def test_pp_of_a_sampled_halo_converges_to_hp(orc):
+    """Particle-based pasting of a spherical NFW halo sampled with 1e6 particles against halo-based
+    pasting of the same solved halo.  Each particle carries P_e(r_i) M_p / rho_NFW(r_i) (Sec. 3.4), an
+    unbiased Monte Carlo estimate of the gas integral that the HP projection (Sec. 3.3) integrates
+    exactly; each particle footprint's weights sum to one, so the PP map total is the sum of the
+    amplitudes.  The footprint cut is moved past r_f so both methods see all of the gas."""
+    p = orc.default_params(trunc_r500=1e3)
+    h = orc.solve_halo(p, 1e14, 5.0, 0.3)
+    assert h.status == 0 and h.R_t == h.r_f
+    rng = np.random.default_rng(7)
+    n = 1_000_000
+    m = lambda x: np.log1p(x) - x / (1 + x)
+    xmax = h.r_f / h.r_s
+    target = rng.uniform(size=n) * m(xmax)          # radii from the NFW enclosed-mass CDF inside r_f
+    lo, hi = np.zeros(n), np.full(n, xmax)
+    for _ in range(64):
+        mid = 0.5 * (lo + hi)
+        above = m(mid) > target
+        hi, lo = np.where(above, mid, hi), np.where(above, lo, mid)
+    r = 0.5 * (lo + hi) * h.r_s
+    M_p = h.M * m(xmax) / m(h.c) / n                # untruncated NFW mass inside r_f, shared out
+    pix = 2 * h.R_t / h.D_A / 300                    # footprint radius 150 pixels
+    ay, ab = orc.pp_amplitudes(p, (orc.Halo * 1)(h), np.full(n, h.z), np.full(n, 300.0), np.zeros(n, np.int32), r,
+                               M_p, pix)
+    npix = 320
+    cat = dict(theta_x=np.array([npix / 2 * pix]), theta_y=np.array([npix / 2 * pix]), v_los=np.array([300.0]))
+    y, b = orc.hp_flat_solved(p, (orc.Halo * 1)(h), cat, npix, pix)
+    for amp, hp in ((ay, y.sum()), (ab, b.sum())):
+        sigma = amp.std() / math.sqrt(n) / amp.mean()
+        err = amp.sum() / hp - 1
+        # Monte Carlo error (about 2e-4 here) plus the pixel-centre sum of the HP map (about 1e-4)
+        assert abs(err) < 4 * sigma + 2e-4, (err, sigma)
+        assert sigma < 5e-4
