@@ -181,22 +181,28 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
         bp.hp_paste_flat(params, npix, pix, d["theta_x"], d["theta_y"], d["v_los"], sol, st, tab, meta, ye, be, ws=ws)
 
     nout = [0]
+    mode = ["exact"]
 
-    def surrogate():
-        ys.zero_(); bs.zero_()
-        nout[0] = S.paste_flat(d, npix, pix, ys, bs, ws)
+    def surrogate(y=ys, b=bs):
+        y.zero_(); b.zero_()
+        nout[0] = S.paste_flat(d, npix, pix, y, b, ws, tables=mode[0])
 
+    sur_names = ("MLP_FWD", "SURR_SOLVE", "SURR_APPLY", "FLAT_PLAN", "FLATQ_DEPOSIT", "ICM", "TABLES", "FLAT_DEPOSIT")
     ms_exact = timed(exact, steps, warmup, bp)
     k_exact = kernel_times(bp, ("ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT"), steps)
     print(f"# exact path on {n_halos} halos: {ms_exact:.1f} ms", file=sys.stderr, flush=True)
     ms_sur = timed(surrogate, steps, warmup, bp)
-    k_sur = kernel_times(bp, ("MLP_FWD", "SURR_APPLY", "FLAT_PLAN", "FLATQ_DEPOSIT", "ICM", "TABLES", "FLAT_DEPOSIT"),
-                         steps)
+    k_sur = kernel_times(bp, sur_names, steps)
+    print(f"# surrogate path (exact q-tables): {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    mode[0] = "network"
+    yn, bn = torch.zeros_like(ye), torch.zeros_like(ye)
+    ms_net = timed(lambda: surrogate(yn, bn), steps, warmup, bp)
+    k_net = kernel_times(bp, sur_names, steps)
     bp._lib.bp_profiling(0)
-    print(f"# surrogate path: {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    print(f"# surrogate path (network tables): {ms_net:.1f} ms", file=sys.stderr, flush=True)
     if profile_pass:
-        return {"exact_ms": round(ms_exact, 2), "surrogate_ms": round(ms_sur, 2), "kernel_ms_exact": k_exact,
-                "kernel_ms_surrogate": k_sur}, S
+        return {"exact_ms": round(ms_exact, 2), "surrogate_ms": round(ms_sur, 2), "network_tables_ms": round(ms_net, 2),
+                "kernel_ms_exact": k_exact, "kernel_ms_surrogate": k_sur}, S
     # scale of the kSZ map: the exact paste with |v| (outside the timed region)
     vabs = d["v_los"].abs()
     yabs = torch.zeros_like(ye)
@@ -207,16 +213,20 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
     del sol, st, tab, meta, yabs
     err_y = map_errors(ys, ye)
     err_b = map_errors(bs, be, babs)
+    net = {"surrogate_halos_per_s": round(n_halos / (ms_net * 1e-3), 1), "surrogate_ms": round(ms_net, 2),
+           "speedup": round(ms_exact / ms_net, 3), "y_err": map_errors(yn, ye), "b_err": map_errors(bn, be, babs),
+           "kernel_ms_surrogate": k_net}
     return {"workload": f"HP flat-sky 5x5 deg, 4096^2 pixels, {n_halos} halos (log10 M in [12.5,15.5], "
                         "dN/dlnM ~ M^-0.9, z in [0.1,1]); surrogate trained on "
-                        f"{n_train} exact solves over log10 M in [12.5,15.5], c in [2,15], z in [0.05,3]",
+                        f"{n_train} exact solves over log10 M in [12.5,15.5], c in [2,15], z in [0.05,3]; "
+                        "surrogate path: network-seeded FP64 solve + q-tables by quadrature of the solved profile",
             "exact_halos_per_s": round(n_halos / (ms_exact * 1e-3), 1), "exact_ms": round(ms_exact, 2),
             "surrogate_halos_per_s": round(n_halos / (ms_sur * 1e-3), 1), "surrogate_ms": round(ms_sur, 2),
             "speedup": round(ms_exact / ms_sur, 3), "fallback_halos": int(nout[0]),
-            "y_err": err_y, "b_err": err_b, "train_s": round(train_s, 1), "train_steps": train_steps,
-            "train_loss": hist[-1][1] if hist else None,
+            "y_err": err_y, "b_err": err_b, "network_tables": net, "train_s": round(train_s, 1),
+            "train_steps": train_steps, "train_loss": hist[-1][1] if hist else None,
             "kernel_ms_exact": k_exact, "kernel_ms_surrogate": k_sur,
-            "dtype": "bf16 MFMA (fp32 accumulate) + f32 deposit"}, S
+            "dtype": "bf16 MFMA (fp32 accumulate) + f64 seeded solve + f32 deposit"}, S
 
 
 def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, profile_pass=False):
@@ -241,6 +251,7 @@ def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, p
     bs = torch.zeros_like(ye)
     ws = bp.Workspace(dev)
     nout = [0]
+    mode = ["exact"]
 
     def exact(vkey="v_los", y=ye, b=be):
         y.zero_(); b.zero_()
@@ -251,32 +262,41 @@ def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, p
             bp.hp_paste_healpix(params, nside, d["theta"], d["phi"], v, sol, st, tab, meta, y, b, ws=ws)
             del sol, st, tab, meta
 
-    def surrogate():
-        ys.zero_(); bs.zero_()
+    def surrogate(y=ys, b=bs):
+        y.zero_(); b.zero_()
         nout[0] = 0
         for d in batches:
-            nout[0] += sur.paste_healpix(d, nside, ys, bs, ws)
+            nout[0] += sur.paste_healpix(d, nside, y, b, ws, tables=mode[0])
 
+    sur_names = ("MLP_FWD", "SURR_SOLVE", "SURR_APPLY", "HPX_PLAN", "HPXQ_DEPOSIT", "ICM", "TABLES", "HPX_DEPOSIT")
     ms_sur = timed(surrogate, steps, warmup, bp)
-    k_sur = kernel_times(bp, ("MLP_FWD", "SURR_APPLY", "HPX_PLAN", "HPXQ_DEPOSIT", "ICM", "TABLES", "HPX_DEPOSIT"),
-                         steps)
-    print(f"# all-sky surrogate path: {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    k_sur = kernel_times(bp, sur_names, steps)
+    print(f"# all-sky surrogate path (exact q-tables): {ms_sur:.1f} ms", file=sys.stderr, flush=True)
+    mode[0] = "network"
+    yn, bn = torch.zeros_like(ye), torch.zeros_like(ye)
+    ms_net = timed(lambda: surrogate(yn, bn), steps, warmup, bp)
+    k_net = kernel_times(bp, sur_names, steps)
+    print(f"# all-sky surrogate path (network tables): {ms_net:.1f} ms", file=sys.stderr, flush=True)
     ms_exact = timed(exact, steps, warmup, bp)
     k_exact = kernel_times(bp, ("ICM", "TABLES", "HPX_PLAN", "HPX_DEPOSIT"), steps)
     bp._lib.bp_profiling(0)
     print(f"# all-sky exact path: {ms_exact:.1f} ms", file=sys.stderr, flush=True)
     if profile_pass:
-        return {"exact_ms": round(ms_exact, 2), "surrogate_ms": round(ms_sur, 2), "kernel_ms_exact": k_exact,
-                "kernel_ms_surrogate": k_sur}
+        return {"exact_ms": round(ms_exact, 2), "surrogate_ms": round(ms_sur, 2), "network_tables_ms": round(ms_net, 2),
+                "kernel_ms_exact": k_exact, "kernel_ms_surrogate": k_sur}
     yabs = torch.zeros_like(ye)
     babs = torch.zeros_like(ye)
     exact("abs", yabs, babs)
     del yabs
     err_y = map_errors(ys, ye)
     err_b = map_errors(bs, be, babs)
+    net = {"surrogate_halos_per_s": round(n_halos / (ms_net * 1e-3), 1), "surrogate_ms": round(ms_net, 2),
+           "speedup": round(ms_exact / ms_net, 3), "y_err": map_errors(yn, ye), "b_err": map_errors(bn, be, babs),
+           "kernel_ms_surrogate": k_net}
     return {"workload": f"all-sky HP, HEALPix N_side {nside} RING ({npx} pixels), {n_halos} halos isotropic on the "
                         "sphere (log10 M in [12.5,15.5], dN/dlnM ~ M^-0.9, z in [0.01,3]), batches of "
-                        f"{batch}; surrogate tables with exact fallback vs exact solve",
+                        f"{batch}; surrogate (network-seeded FP64 solve + q-tables by quadrature) with exact "
+                        "fallback vs exact solve", "network_tables": net,
             "surrogate_halos_per_s": round(n_halos / (ms_sur * 1e-3), 1), "surrogate_ms": round(ms_sur, 2),
             "exact_halos_per_s": round(n_halos / (ms_exact * 1e-3), 1), "exact_ms": round(ms_exact, 2),
             "speedup": round(ms_exact / ms_sur, 3), "fallback_halos": int(nout[0]),

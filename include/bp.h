@@ -378,13 +378,36 @@ int bp_mlp_infer(const float *w, const uint16_t *w_bf16, int64_t n, const float 
  * loss_rows[i] = sum_c w_c r_c^2.  Rows with a non-finite target get dy = 0. */
 int bp_surrogate_mse(int64_t n, const float *y, const float *targets, const float *mean, const float *std, float *dy,
                      float *loss_rows, void *stream);
-/* Apply the network output: completes sol (XF, RF, RT) for in-domain halos
- * whose structure came from bp_halo_structure, writes q-tables
- * [n][2*BP_MLP_NQ] (G values, not logs) and meta (PE0, NE0; the grid and
- * profile-constant fields 0).  y, mean, std and qtables must be 16-byte
- * aligned (as every device allocation is); otherwise BP_E_ARG. */
+/* The ICM solve of bp_icm_solve with the network's estimate of the gas boundary in place of the
+ * x_f scan (Sec. 2.2: the energy condition fixes r_f; the surrogate only says where to look).  For
+ * each halo inside the training domain (log10 M in [12.5, 15.5], c in [2, 15], z in [0.05, 3]) the
+ * estimate x_f = exp(y[128] std[128] + mean[128]) (y: the network output rows [n][BP_MLP_OUT], device)
+ * and a point 0.2% away start secant steps that widen until the energy residual changes sign (at
+ * most 8); Brent's method then refines the root to 1e-13 relative, with the moment integrals built
+ * as bp_icm_solve builds them, so x_f, a, rho0 and P0 agree with bp_icm_solve's to its tolerance
+ * wherever the root is unique.  Every sol field is written as by bp_icm_solve.  status: 0; or
+ * BP_S_OUT_OF_DOMAIN outside the domain (sol then holds only what bp_halo_structure writes);
+ * BP_S_NO_BRACKET if no sign change was found (paste such halos with the exact path);
+ * BP_S_MULTI_ROOT is never set (the root nearest the estimate is taken).  n may be 0. */
+int bp_surrogate_solve(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,
+                       const float *y, const float *mean, const float *std, double *sol, int32_t *status,
+                       void *stream);
+/* Apply the network output to halos solved by bp_surrogate_solve (status 0): writes q-tables
+ * [n][2*BP_MLP_NQ] (G values, not logs) from outputs 0..127 and meta (PE0, NE0 from the solved P0
+ * and rho0; the grid and profile-constant fields 0).  Halos with a non-zero status are left
+ * untouched.  y, mean, std and qtables must be 16-byte aligned (as every device allocation is);
+ * otherwise BP_E_ARG. */
 int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
-                       double *sol, const int32_t *status, float *qtables, float *meta, void *stream);
+                       const double *sol, const int32_t *status, float *qtables, float *meta, void *stream);
+/* Exact q-tables for halos solved by bp_surrogate_solve (status 0): the projected profiles at the 64
+ * q nodes by sight-line quadrature of the solved profile (Sec. 3.3), with the exact tables' own
+ * integration (Gauss-Legendre in s along l = r_perp sinh s, split at r_vir, FP32 integrand, FP64
+ * sums), in the layout and normalisation bp_surrogate_apply writes (G = Y / (P_e0 R_t E)); meta's PE0
+ * and NE0 as bp_surrogate_apply.  This is the surrogate path's table mode that does not use the
+ * network's table outputs: with it the surrogate's map error is that of the 64-node interpolation
+ * (about 1e-4).  Halos with a non-zero status are left untouched.  n may be 0. */
+int bp_surrogate_qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                               float *qtables, float *meta, void *stream);
 /* Device-side training loop: `steps` Adam steps on batches of `batch` rows drawn
  * from (x, targets) by a counter-based hash of (seed, step0 + k, row) -- no host
  * synchronisation.  Learning rate follows a cosine from lr0 to lr1 over the
@@ -438,6 +461,7 @@ enum {
     BP_PROF_NGP_PLAN,       /* K13 pixel indices + tile counting sort + amplitudes */
     BP_PROF_NGP_DEPOSIT,    /* K13 k_ngp_deposit */
     BP_PROF_SPECTRUM,       /* K14 flat-sky power spectrum */
+    BP_PROF_SURR_SOLVE,     /* K1 seeded by the surrogate (bp_surrogate_solve) */
     BP_PROF_NKERNELS
 };
 int bp_profiling(int enable);

@@ -101,6 +101,8 @@ _SIGS = {
     "bp_gather_rows": (C.c_int, [C.c_int64, C.c_int32, _VP, _VP, _VP, _VP]),
     "bp_surrogate_mse": (C.c_int, [C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_surrogate_apply": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_solve": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_qtables_exact": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
     "bp_mlp_infer": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP, _VP]),
     "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                      _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
@@ -115,7 +117,7 @@ _SIGS = {
 PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DEPOSIT", "HPX_PLAN", "HPX_DEPOSIT",
                                           "PP_SORT", "PP_KNN", "PP_PLAN", "PP_DEPOSIT", "MLP_FWD", "MLP_BWD",
                                           "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT", "PP_NEFF", "NGP_PLAN",
-                                          "NGP_DEPOSIT", "SPECTRUM"])}
+                                          "NGP_DEPOSIT", "SPECTRUM", "SURR_SOLVE"])}
 MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
 S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
@@ -157,6 +159,21 @@ def icm_solve(params: Params, M: torch.Tensor, c: torch.Tensor, z: torch.Tensor)
     if n:
         _check(_lib.bp_icm_solve(C.byref(params), n, _ptr(M), _ptr(c), _ptr(z), _ptr(sol), _ptr(status),
                                  _stream()), "bp_icm_solve")
+    return sol, status
+
+
+def surrogate_solve(params: Params, M: torch.Tensor, c: torch.Tensor, z: torch.Tensor, y: torch.Tensor,
+                    mean: torch.Tensor, std: torch.Tensor):
+    """K1 seeded by the surrogate network's output rows y [n, MLP_OUT] (standardised by mean, std):
+    returns (sol [SOL_NFIELDS, n] float64, status [n] int32) on the device."""
+    n = M.numel()
+    dev = M.device
+    sol = torch.empty((SOL_NFIELDS, n), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    if n:
+        assert y.dtype == torch.float32 and y.shape == (n, MLP_OUT), "network output rows [n, 144] float32 expected"
+        _check(_lib.bp_surrogate_solve(C.byref(params), n, _ptr(M), _ptr(c), _ptr(z), _ptr(y), _ptr(mean), _ptr(std),
+                                       _ptr(sol), _ptr(status), _stream()), "bp_surrogate_solve")
     return sol, status
 
 

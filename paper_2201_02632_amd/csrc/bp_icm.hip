@@ -43,7 +43,7 @@ __device__ inline double binom(int n, int k) {
 // Inner part (r < r_vir): x = r/r_s, integrated in s = ln(1+x) by Gauss-Legendre, accumulated
 // into mu over [Xa, Xb].
 template <int NG>
-__device__ inline void inner_moments(const HaloSolve &H, const double *gx, const double *gw, double Xa, double Xb,
+__device__ __attribute__((always_inline)) inline void inner_moments(const HaloSolve &H, const double *gx, const double *gw, double Xa, double Xb,
                                      double mu[7]) {
     const double fourpi = 4.0 * kPi;
     const double Sa = log1p(Xa), Sb = log1p(Xb), hs = 0.5 * (Sb - Sa);
@@ -192,15 +192,59 @@ __device__ void distances(const bp_params &P, const GaussRules &G, double z, dou
     *tauint = 0.5 * z * a2;
 }
 
+// Brent's method (bisection / secant / inverse quadratic interpolation) for the energy residual on a
+// bracket [a, b] with f(a) f(b) < 0, stopping at |b - c| <= 2 eps |b| + xtol; `trial(x, a_guess)`
+// evaluates the residual at x (aguess carries the slope a from one trial to the next).  Returns b.
+template <class F>
+__device__ double brent_xf(F &&trial, double a, double b, double fa, double fbv, double xtol, double &aguess2) {
+    double cc = a, fc = fa, d = b - a, e = d;
+    for (int it = 0; it < 200; ++it) {
+        if ((fbv > 0 && fc > 0) || (fbv < 0 && fc < 0)) { cc = a; fc = fa; d = b - a; e = d; }
+        if (fabs(fc) < fabs(fbv)) { a = b; b = cc; cc = a; fa = fbv; fbv = fc; fc = fa; }
+        double tol = 2.0 * 2.220446049250313e-16 * fabs(b) + 0.5 * xtol;
+        double m = 0.5 * (cc - b);
+        if (fabs(m) <= tol || fbv == 0.0) break;
+        if (fabs(e) >= tol && fabs(fa) > fabs(fbv)) {
+            double s = fbv / fa, p, q;
+            if (a == cc) { p = 2.0 * m * s; q = 1.0 - s; }
+            else {
+                double qq = fa / fc, r = fbv / fc;
+                p = s * (2.0 * m * qq * (qq - r) - (b - a) * (r - 1.0));
+                q = (qq - 1.0) * (r - 1.0) * (s - 1.0);
+            }
+            if (p > 0) q = -q; else p = -p;
+            if (2.0 * p < fmin(3.0 * m * q - fabs(tol * q), fabs(e * q))) { e = d; d = p / q; }
+            else { d = m; e = m; }
+        } else { d = m; e = m; }
+        a = b; fa = fbv;
+        b += (fabs(d) > tol) ? d : (m > 0 ? tol : -tol);
+        Trial T = trial(b, aguess2);
+        aguess2 = T.a;
+        fbv = T.res;
+    }
+    return b;
+}
+
 #define NSCAN 47
+// scan grid of the gas boundary x_f = r_f / r_vir: NSCAN points uniform on [0.4, 5]
+__device__ inline double scan_x(int k) { return 0.4 + (5.0 - 0.4) * k / (NSCAN - 1); }
+
+enum { kSolveScan = 0, kSolveStructure = 1, kSolveSeeded = 2 };
 
 // Two waves per SIMD (at most 256 VGPRs, a few spilled): with one lane per halo the launch is only a
 // few waves deep per SIMD, and at the unconstrained 262 VGPRs a single resident wave leaves every
 // FP64 latency exposed (2.47 ms against 1.81 ms for 5e5 halos; three waves spill 110 VGPRs, 1.97 ms).
-template <bool kStructureOnly>
+//   kSolveScan:      the exact solve (first sign change of the energy residual on the scan, then Brent);
+//   kSolveStructure: the halo structure only (the surrogate's domain test; no boundary conditions);
+//   kSolveSeeded:    the exact solve's root, found from the surrogate network's estimate of ln x_f
+//                    (output 2 BP_MLP_NQ of yseed, standardised by ymean / ysd) instead of the scan:
+//                    a bracket is widened from the estimate, then Brent to the same tolerance.  Halos
+//                    outside the network's training domain get the structure and BP_S_OUT_OF_DOMAIN.
+template <int kMode>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min, const double *__restrict__ cin,
-            const double *__restrict__ zin, double *__restrict__ sol, int32_t *__restrict__ status) {
+            const double *__restrict__ zin, const float *__restrict__ yseed, const float *__restrict__ ymean,
+            const float *__restrict__ ysd, double *__restrict__ sol, int32_t *__restrict__ status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double M = Min[i], c = cin[i], z = zin[i];
@@ -241,28 +285,31 @@ k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min
     double x500 = exp(lx);
     double r500 = x500 * rs, M500 = 4.0 * kPi * rhos * rs * rs * rs * nfw_m(x500);
     S(BP_SOL_R500) = r500; S(BP_SOL_M500) = M500;
-    if (kStructureOnly) {
-        // the surrogate replaces everything from here to the tables; keep the exact geometry
-        double chi_u, tau_u;
-        distances(P, G, z, &chi_u, &tau_u);
-        double cH = kCkms / 100.0, chi = cH * chi_u;
-        S(BP_SOL_CHI) = chi;
-        S(BP_SOL_DA) = chi / zp;
-        double H0 = 100.0 * h * 1e5 / kMpc;
-        double rho_cr0 = 3.0 * H0 * H0 / (8.0 * kPi * kG);
-        double ne_bar = P.Omega_b * rho_cr0 / (2.0 / (1.0 + P.X_H) * kMp);
-        S(BP_SOL_TAU) = kSigmaT * ne_bar * (kC / H0) * tau_u;
-        double fmax = pow(4.0, -P.n_nt) / P.alpha_nt;
-        S(BP_SOL_FNT) = fmin(pow(zp, P.beta_nt), (fmax - 1.0) * tanh(P.beta_nt * z) + 1.0);
-        // surface pressure (the surrogate predicts the central pressure relative to it)
-        const double fb0 = P.Omega_b / P.Omega_m;
-        const double u_len0 = kMpc / h, u_mass0 = kMsun / h;
-        S(BP_SOL_PS) = fb0 * 4.0 * kPi * kGastro * rhos * rhos * rs * rs * jeans_I_dev(c, G) * u_mass0 /
-                       (u_len0 * u_len0 * u_len0) * 1e10;
-        double lm = log10(M);
-        bool in = lm >= 12.5 && lm <= 15.5 && c >= 2.0 && c <= 15.0 && z >= 0.05 && z <= 3.0;
-        status[i] = in ? 0 : BP_S_OUT_OF_DOMAIN;
-        return;
+    if (kMode != kSolveScan) {
+        // the surrogate's training domain (log10 M, c, z)
+        const double lm = log10(M);
+        const bool in = lm >= 12.5 && lm <= 15.5 && c >= 2.0 && c <= 15.0 && z >= 0.05 && z <= 3.0;
+        if (kMode == kSolveStructure || !in) {
+            // the surrogate replaces everything from here to the tables; keep the exact geometry
+            double chi_u, tau_u;
+            distances(P, G, z, &chi_u, &tau_u);
+            double cH = kCkms / 100.0, chi = cH * chi_u;
+            S(BP_SOL_CHI) = chi;
+            S(BP_SOL_DA) = chi / zp;
+            double H0 = 100.0 * h * 1e5 / kMpc;
+            double rho_cr0 = 3.0 * H0 * H0 / (8.0 * kPi * kG);
+            double ne_bar = P.Omega_b * rho_cr0 / (2.0 / (1.0 + P.X_H) * kMp);
+            S(BP_SOL_TAU) = kSigmaT * ne_bar * (kC / H0) * tau_u;
+            double fmax = pow(4.0, -P.n_nt) / P.alpha_nt;
+            S(BP_SOL_FNT) = fmin(pow(zp, P.beta_nt), (fmax - 1.0) * tanh(P.beta_nt * z) + 1.0);
+            // surface pressure (the surrogate predicts the central pressure relative to it)
+            const double fb0 = P.Omega_b / P.Omega_m;
+            const double u_len0 = kMpc / h, u_mass0 = kMsun / h;
+            S(BP_SOL_PS) = fb0 * 4.0 * kPi * kGastro * rhos * rhos * rs * rs * jeans_I_dev(c, G) * u_mass0 /
+                           (u_len0 * u_len0 * u_len0) * 1e10;
+            status[i] = in ? 0 : BP_S_OUT_OF_DOMAIN;
+            return;
+        }
     }
 
     // --- stars (Sec. 2.2); the 3e14 Msun pivot is in Msun ---
@@ -306,95 +353,142 @@ k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min
     S(BP_SOL_PS) = H.Ps * u_P;
     S(BP_SOL_EGI) = H.Egi * u_mass * 1e10;
 
-    // --- scan x_f, then Brent on the first sign change ---
-    // Moments of [0, r_f]: the inner part is carried along the increasing scan points up to
-    // x_f = 1 (GL16 on the first piece, GL8 on each step), frozen at r_vir beyond, where the
-    // outer shell has a closed form.  A Brent trial starts from the moments at its bracket's
-    // lower end.
-    double mu_cur[7] = {0, 0, 0, 0, 0, 0, 0}, x_cur = 0.4;
-    inner_moments<16>(H, G.x16, G.w16, 0.0, 0.4 * c, mu_cur);
-    double mu_vir[7];
-    bool have_vir = false;
-    auto moments_at = [&](const double base[7], double xbase, double xf, double mu[7]) {
-        if (xf <= 1.0) {
-            for (int k = 0; k < 7; ++k) mu[k] = base[k];
-            if (xf > xbase) inner_moments<8>(H, G.x8, G.w8, xbase * c, xf * c, mu);
-        } else {
-            if (!have_vir) {
-                for (int k = 0; k < 7; ++k) mu_vir[k] = mu_cur[k];
-                if (x_cur < 1.0) inner_moments<8>(H, G.x8, G.w8, x_cur * c, c, mu_vir);
-                have_vir = true;
+    double xf;
+    Trial T;
+    if (kMode == kSolveScan) {
+        // --- scan x_f, then Brent on the first sign change ---
+        // Moments of [0, r_f]: the inner part is carried along the increasing scan points up to
+        // x_f = 1 (GL16 on the first piece, GL8 on each step), frozen at r_vir beyond, where the
+        // outer shell has a closed form.  A Brent trial starts from the moments at its bracket's
+        // lower end.
+        double mu_cur[7] = {0, 0, 0, 0, 0, 0, 0}, x_cur = 0.4;
+        inner_moments<16>(H, G.x16, G.w16, 0.0, 0.4 * c, mu_cur);
+        double mu_vir[7];
+        bool have_vir = false;
+        auto moments_at = [&](const double base[7], double xbase, double xf, double mu[7]) {
+            if (xf <= 1.0) {
+                for (int k = 0; k < 7; ++k) mu[k] = base[k];
+                if (xf > xbase) inner_moments<8>(H, G.x8, G.w8, xbase * c, xf * c, mu);
+            } else {
+                if (!have_vir) {
+                    for (int k = 0; k < 7; ++k) mu_vir[k] = mu_cur[k];
+                    if (x_cur < 1.0) inner_moments<8>(H, G.x8, G.w8, x_cur * c, c, mu_vir);
+                    have_vir = true;
+                }
+                for (int k = 0; k < 7; ++k) mu[k] = mu_vir[k];
+                outer_moments(H, xf, mu);
             }
-            for (int k = 0; k < 7; ++k) mu[k] = mu_vir[k];
-            outer_moments(H, xf, mu);
-        }
-    };
-    double xprev = 0.0, rprev = 0.0, aprev = 0.0;
-    double bx0 = 0.0, bx1 = 0.0, br0 = 0.0, br1 = 0.0, ba = 0.0;
-    double mu_prev[7] = {0, 0, 0, 0, 0, 0, 0}, mu_b[7] = {0, 0, 0, 0, 0, 0, 0};
-    int nchg = 0;
-    double aguess = 0.0;
-    for (int k = 0; k < NSCAN; ++k) {
-        double xf = 0.4 + (5.0 - 0.4) * k / (NSCAN - 1);
-        double mu[7];
-        if (xf <= 1.0) {
-            moments_at(mu_cur, x_cur, xf, mu);
-            for (int q = 0; q < 7; ++q) mu_cur[q] = mu[q];
-            x_cur = xf;
-        } else {
-            moments_at(mu_cur, x_cur, xf, mu);
-        }
-        Trial T = energy_trial(H, mu, xf, aguess);
-        // the next point starts from the linear extrapolation of a along the uniform scan
-        aguess = k > 0 ? 2.0 * T.a - aprev : T.a;
-        if (!isfinite(T.res)) { st |= BP_S_NONFINITE; break; }
-        if (k > 0 && ((rprev < 0) != (T.res < 0))) {
-            if (nchg == 0) {
-                bx0 = xprev; bx1 = xf; br0 = rprev; br1 = T.res; ba = aprev;
-                for (int q = 0; q < 7; ++q) mu_b[q] = mu_prev[q];
+        };
+        double xprev = 0.0, rprev = 0.0, aprev = 0.0;
+        double bx0 = 0.0, bx1 = 0.0, br0 = 0.0, br1 = 0.0, ba = 0.0;
+        double mu_prev[7] = {0, 0, 0, 0, 0, 0, 0}, mu_b[7] = {0, 0, 0, 0, 0, 0, 0};
+        int nchg = 0;
+        double aguess = 0.0;
+        for (int k = 0; k < NSCAN; ++k) {
+            double xf = scan_x(k);
+            double mu[7];
+            if (xf <= 1.0) {
+                moments_at(mu_cur, x_cur, xf, mu);
+                for (int q = 0; q < 7; ++q) mu_cur[q] = mu[q];
+                x_cur = xf;
+            } else {
+                moments_at(mu_cur, x_cur, xf, mu);
             }
-            ++nchg;
+            Trial T = energy_trial(H, mu, xf, aguess);
+            // the next point starts from the linear extrapolation of a along the uniform scan
+            aguess = k > 0 ? 2.0 * T.a - aprev : T.a;
+            if (!isfinite(T.res)) { st |= BP_S_NONFINITE; break; }
+            if (k > 0 && ((rprev < 0) != (T.res < 0))) {
+                if (nchg == 0) {
+                    bx0 = xprev; bx1 = xf; br0 = rprev; br1 = T.res; ba = aprev;
+                    for (int q = 0; q < 7; ++q) mu_b[q] = mu_prev[q];
+                }
+                ++nchg;
+            }
+            xprev = xf; rprev = T.res; aprev = T.a;
+            for (int q = 0; q < 7; ++q) mu_prev[q] = mu[q];
         }
-        xprev = xf; rprev = T.res; aprev = T.a;
-        for (int q = 0; q < 7; ++q) mu_prev[q] = mu[q];
+        if (!st && nchg == 0) st |= BP_S_NO_BRACKET;
+        if (st) { status[i] = st; return; }
+        if (nchg > 1) st |= BP_S_MULTI_ROOT;
+        auto trial_at = [&](double x, double ag) {
+            double mu[7];
+            moments_at(mu_b, bx0, x, mu);
+            return energy_trial(H, mu, x, ag);
+        };
+        double xtol = 1e-13 * bx0, aguess2 = ba;
+        xf = brent_xf(trial_at, bx0, bx1, br0, br1, xtol, aguess2);
+        T = trial_at(xf, aguess2);
+    } else {
+        // --- seeded: the network's x_f, a bracket widened from it, then Brent ---
+        // Each trial's moments are built exactly as the scan builds them (GL16 on [0, 0.4 c], one GL8
+        // step per scan interval, GL8 from the last grid point below x_f), so the root agrees with the
+        // scan's to the Brent tolerance.
+        double mu_g[7] = {0, 0, 0, 0, 0, 0, 0}, mu_v[7];
+        int kg_have = -1;
+        bool have_v = false;
+        auto grid_to = [&](int kg) __attribute__((always_inline)) {   // inner moments of [0, scan_x(kg)], kg <= the last point <= 1
+            if (kg_have < 0 || kg < kg_have) {
+                for (int q = 0; q < 7; ++q) mu_g[q] = 0.0;
+                inner_moments<16>(H, G.x16, G.w16, 0.0, 0.4 * c, mu_g);
+                kg_have = 0;
+            }
+            for (; kg_have < kg; ++kg_have)
+                inner_moments<8>(H, G.x8, G.w8, scan_x(kg_have) * c, scan_x(kg_have + 1) * c, mu_g);
+        };
+        int kv = 0;                         // the last scan point at or below r_vir
+        while (kv + 1 < NSCAN && scan_x(kv + 1) <= 1.0) ++kv;
+        auto trial_s = [&](double x, double ag) __attribute__((always_inline)) {
+            double mu[7];
+            if (x <= 1.0) {
+                int kg = 0;
+                while (kg < kv && scan_x(kg + 1) <= x) ++kg;
+                grid_to(kg);
+                for (int q = 0; q < 7; ++q) mu[q] = mu_g[q];
+                if (x > scan_x(kg)) inner_moments<8>(H, G.x8, G.w8, scan_x(kg) * c, x * c, mu);
+            } else {
+                if (!have_v) {
+                    grid_to(kv);
+                    for (int q = 0; q < 7; ++q) mu_v[q] = mu_g[q];
+                    if (scan_x(kv) < 1.0) inner_moments<8>(H, G.x8, G.w8, scan_x(kv) * c, c, mu_v);
+                    have_v = true;
+                }
+                for (int q = 0; q < 7; ++q) mu[q] = mu_v[q];
+                outer_moments(H, x, mu);
+            }
+            return energy_trial(H, mu, x, ag);
+        };
+        const int c0 = 2 * BP_MLP_NQ;
+        const double xg = exp((double)(yseed[i * BP_MLP_OUT + c0] * ysd[c0] + ymean[c0]));
+        const double xs_lo = scan_x(0), xs_hi = scan_x(NSCAN - 1);
+        double xa = isfinite(xg) ? fmin(fmax(xg, xs_lo), xs_hi) : 1.5;
+        Trial Ta = trial_s(xa, 0.0);
+        double fa = Ta.res;
+        // second point 0.2% away (the network's x_f is typically within 1e-3); then secant steps that
+        // overshoot by half until the residual changes sign (at most 8)
+        double xb = xa * 1.002 <= xs_hi ? xa * 1.002 : xa * 0.998;
+        Trial Tb = trial_s(xb, Ta.a);
+        double fbv = Tb.res, agb = Tb.a;
+        bool ok = isfinite(fa) && isfinite(fbv);
+        for (int widen = 0; ok && ((fa < 0) == (fbv < 0)); ++widen) {
+            const double slope = (fbv - fa) / (xb - xa), xsec = xb - fbv / slope;
+            double xn = (isfinite(xsec) && slope != 0.0) ? xb + 1.5 * (xsec - xb) : xb + 2.0 * (xb - xa);
+            xn = fmin(fmax(xn, xs_lo), xs_hi);
+            if (widen >= 8 || xn == xb) { ok = false; break; }
+            Trial Tn = trial_s(xn, agb);
+            xa = xb; fa = fbv;
+            xb = xn; fbv = Tn.res; agb = Tn.a;
+            ok = isfinite(fbv);
+        }
+        if (!ok) {
+            st |= isfinite(fa) && isfinite(fbv) ? BP_S_NO_BRACKET : BP_S_NONFINITE;
+            status[i] = st;
+            return;
+        }
+        double aguess2 = agb;
+        xf = brent_xf(trial_s, xb, xa, fbv, fa, 1e-13 * fmin(xa, xb), aguess2);
+        T = trial_s(xf, aguess2);
     }
-    if (!st && nchg == 0) st |= BP_S_NO_BRACKET;
-    if (st) { status[i] = st; return; }
-    if (nchg > 1) st |= BP_S_MULTI_ROOT;
-    auto trial_at = [&](double xf, double ag) {
-        double mu[7];
-        moments_at(mu_b, bx0, xf, mu);
-        return energy_trial(H, mu, xf, ag);
-    };
-    // Brent's method (bisection / secant / inverse quadratic interpolation)
-    double a = bx0, b = bx1, fa = br0, fbv = br1, cc = a, fc = fa, d = b - a, e = d;
-    double xtol = 1e-13 * bx0, aguess2 = ba;
-    for (int it = 0; it < 200; ++it) {
-        if ((fbv > 0 && fc > 0) || (fbv < 0 && fc < 0)) { cc = a; fc = fa; d = b - a; e = d; }
-        if (fabs(fc) < fabs(fbv)) { a = b; b = cc; cc = a; fa = fbv; fbv = fc; fc = fa; }
-        double tol = 2.0 * 2.220446049250313e-16 * fabs(b) + 0.5 * xtol;
-        double m = 0.5 * (cc - b);
-        if (fabs(m) <= tol || fbv == 0.0) break;
-        if (fabs(e) >= tol && fabs(fa) > fabs(fbv)) {
-            double s = fbv / fa, p, q;
-            if (a == cc) { p = 2.0 * m * s; q = 1.0 - s; }
-            else {
-                double qq = fa / fc, r = fbv / fc;
-                p = s * (2.0 * m * qq * (qq - r) - (b - a) * (r - 1.0));
-                q = (qq - 1.0) * (r - 1.0) * (s - 1.0);
-            }
-            if (p > 0) q = -q; else p = -p;
-            if (2.0 * p < fmin(3.0 * m * q - fabs(tol * q), fabs(e * q))) { e = d; d = p / q; }
-            else { d = m; e = m; }
-        } else { d = m; e = m; }
-        a = b; fa = fbv;
-        b += (fabs(d) > tol) ? d : (m > 0 ? tol : -tol);
-        Trial T = trial_at(b, aguess2);
-        aguess2 = T.a;
-        fbv = T.res;
-    }
-    double xf = b;
-    Trial T = trial_at(xf, aguess2);
     S(BP_SOL_A) = T.a;
     S(BP_SOL_XF) = xf;
     S(BP_SOL_RF) = xf * rv;
@@ -684,6 +778,109 @@ __global__ void __launch_bounds__(128) k_tables_sb(GaussRules G, int64_t n, cons
     table_node(G, n, sol, status, meta, tab, n_nt, i, BP_TAB_NA + zone * BP_TAB_NS + (threadIdx.x & 31));
 }
 
+// Projected profiles of solved halos at the surrogate's q nodes, by the exact tables' sight-line
+// quadratures (Sec. 3.3): for r_perp = q_k R_t below r_a the part of the line inside r_a (Gauss-Legendre
+// in s, l = r_perp sinh s, the order chosen by the length of the s-interval as for zone A) plus the
+// shell r_vir < r < r_f (8 points); at or beyond r_a the line through the shell alone (8 points).  The
+// integrand is the FP32 profile of the exact tables with the same FP32 constants.  Output per halo:
+// qt[i][k] = Y_P / (P_e0 R_t E), qt[i][BP_MLP_NQ + k] = Y_n / (n_e0 R_t E), E = sqrt(1 - (q_k R_t / r_f)^2),
+// q_k = (1 - cos(pi k / 63)) / 2 (the last node the limit from inside, q = 1 - 1e-6; the innermost sight
+// line no closer than 1e-5 r_a, as in the zone tables); meta's PE0 and NE0 from the solved P0 and rho0.
+// Layout of the work: a block takes 64 consecutive halos, lane = halo, and each of its four wavefronts
+// takes every fourth node, so that the lanes of a wavefront share one node (and nearly one quadrature
+// order) and read their halos' constants with coalesced loads from the SoA solution.  The values
+// gather in LDS and leave as contiguous rows.
+struct QNodes { double q[BP_MLP_NQ]; };
+constexpr int kQH = 64;                     // halos per block
+__global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G, QNodes QN, int64_t n,
+                                                       const double *__restrict__ sol,
+                                                       const int32_t *__restrict__ status, float *__restrict__ qt,
+                                                       float *__restrict__ meta) {
+    __shared__ float tile[kQH][2 * BP_MLP_NQ + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * kQH, i = i0 + lane;
+    const bool live = i < n && status[i] == 0;
+    if (live) {
+        auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
+        const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), Rt = S(BP_SOL_RT), c = S(BP_SOL_C), mc = nfw_m(c);
+        if (wave == 0) {
+            const double X = P.X_H;
+            meta[(int64_t)BP_META_PE0 * n + i] = (float)((2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0));
+            meta[(int64_t)BP_META_NE0 * n + i] = (float)(S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp));
+            for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
+            for (int f = BP_META_PR_RV; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = 0.0f;
+        }
+        Prof Q;   // the constants k_table_setup stores for the zone tables, rounded the same way
+        Q.rv = (float)rv; Q.inv_rs = (float)(1.0 / S(BP_SOL_RS)); Q.rf = (float)rf;
+        Q.cm = (float)(c / mc); Q.phi_out0 = (float)(c * c / ((1.0 + c) * mc));
+        Q.a = (float)S(BP_SOL_A); Q.inv_r500 = (float)(1.0 / S(BP_SOL_R500));
+        Q.ant_f = (float)(P.alpha_nt * S(BP_SOL_FNT)); Q.n_nt = (float)P.n_nt;
+        const double ra = fmin(rv, rf);
+        const bool shell = rf > rv;           // then r_a = r_vir and the shell starts where zone A ends
+        const float raf = (float)ra;
+        for (int k = wave; k < BP_MLP_NQ; k += 4) {
+            const double q = QN.q[k];
+            const double rp = fmax(q * Rt, 1e-5 * ra);
+            const float rpf = (float)rp;
+            double accP = 0.0, accN = 0.0;
+            if (rp < ra) {
+                const double xi = acosh(ra / rp);
+                const int ng = xi > 9.0 ? 20 : xi > 7.6 ? 16 : xi > 6.0 ? 14 : xi > 4.6 ? 12 : xi > 3.2 ? 10
+                                                                                   : xi > 1.4 ? 8 : 6;
+                const float *gu = ng == 20 ? G.u20 : ng == 16 ? G.u16 : ng == 14 ? G.u14 : ng == 12 ? G.u12
+                                  : ng == 10 ? G.u10 : ng == 8 ? G.u8 : G.u6;
+                const double *gw = ng == 20 ? G.w20 : ng == 16 ? G.w16 : ng == 14 ? G.w14 : ng == 12 ? G.w12
+                                   : ng == 10 ? G.w10 : ng == 8 ? G.w8 : G.w6;
+                const float xif = (float)xi;
+                double sP = 0.0, sN = 0.0;
+                for (int j = 0; j < ng; ++j) {
+                    float r = fminf(rpf * cosh_f(xif * gu[j]), raf);
+                    float pe, ne;
+                    prof_eval(Q, r, &pe, &ne);
+                    const double w = gw[j] * (double)r;
+                    sP += w * pe; sN += w * ne;
+                }
+                accP = xi * sP; accN = xi * sN;
+                if (shell) {   // the shell r_vir < r < r_f crossed by the same line: s from xi to acosh(r_f / r_perp)
+                    const double hs = 0.5 * (acosh(rf / rp) - xi);
+                    double tP = 0.0, tN = 0.0;
+                    for (int j = 0; j < 8; ++j) {
+                        float r = fminf(fmaxf(rpf * cosh_f((float)(xi + hs * (G.x8[j] + 1.0))), Q.rv), Q.rf);
+                        float pe, ne;
+                        prof_eval(Q, r, &pe, &ne);
+                        const double w = G.w8[j] * (double)r;
+                        tP += w * pe; tN += w * ne;
+                    }
+                    accP += 2.0 * hs * tP; accN += 2.0 * hs * tN;
+                }
+            } else if (rp < rf) {
+                const double ze = acosh(rf / rp);
+                const float zef = (float)ze;
+                double sP = 0.0, sN = 0.0;
+                for (int j = 0; j < 8; ++j) {
+                    float r = fmaxf(fminf(rpf * cosh_f(zef * G.u8[j]), Q.rf), Q.rv);
+                    float pe, ne;
+                    prof_eval(Q, r, &pe, &ne);
+                    const double w = G.w8[j] * (double)r;
+                    sP += w * pe; sN += w * ne;
+                }
+                accP = ze * sP; accN = ze * sN;
+            }
+            const double x = q * Rt / rf;
+            const double norm = 1.0 / (Rt * sqrt(fmax(1.0 - x * x, 0.0)));
+            tile[lane][k] = (float)(accP * norm);
+            tile[lane][BP_MLP_NQ + k] = (float)(accN * norm);
+        }
+    }
+    __syncthreads();
+    // rows of the live halos out, 2 BP_MLP_NQ consecutive floats each
+    const int nh = (int)min((int64_t)kQH, n - i0);
+    for (int e = threadIdx.x; e < nh * 2 * BP_MLP_NQ; e += 256) {
+        const int h = e / (2 * BP_MLP_NQ), k = e - h * 2 * BP_MLP_NQ;
+        if (status[i0 + h] == 0) qt[(i0 + h) * 2 * BP_MLP_NQ + k] = tile[h][k];
+    }
+}
+
 // ------------------------------------------------------- Gauss-Legendre --
 // Nodes and weights of the n-point rule on [-1,1] by Newton iteration on P_n.
 static void gauss_legendre(int n, double *x, double *w) {
@@ -760,8 +957,8 @@ extern "C" int bp_icm_solve(const bp_params *p, int64_t n, const double *M, cons
     int64_t blocks = (n + 63) / 64;
     if (blocks > 0x7fffffff) return BP_E_OVERFLOW;
     prof_begin(BP_PROF_ICM, s);
-    hipLaunchKernelGGL(k_icm_solve<false>, dim3((unsigned)blocks), dim3(64), 0, s, *p, gauss_rules(), n, M, c, z, sol,
-                       status);
+    hipLaunchKernelGGL(k_icm_solve<kSolveScan>, dim3((unsigned)blocks), dim3(64), 0, s, *p, gauss_rules(), n, M, c, z,
+                       nullptr, nullptr, nullptr, sol, status);
     prof_end(BP_PROF_ICM, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
@@ -796,7 +993,44 @@ extern "C" int bp_halo_structure(const bp_params *p, int64_t n, const double *M,
     if (!M || !c || !z || !sol || !status) return BP_E_ARG;
     int64_t blocks = (n + 63) / 64;
     if (blocks > 0x7fffffff) return BP_E_OVERFLOW;
-    hipLaunchKernelGGL(k_icm_solve<true>, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, *p, gauss_rules(),
-                       n, M, c, z, sol, status);
+    hipLaunchKernelGGL(k_icm_solve<kSolveStructure>, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, *p,
+                       gauss_rules(), n, M, c, z, nullptr, nullptr, nullptr, sol, status);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_solve(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,
+                                  const float *y, const float *mean, const float *std, double *sol, int32_t *status,
+                                  void *stream) {
+    int e = check_params(p);
+    if (e) return e;
+    if (n < 0) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if (!M || !c || !z || !y || !mean || !std || !sol || !status) return BP_E_ARG;
+    int64_t blocks = (n + 63) / 64;
+    if (blocks > 0x7fffffff) return BP_E_OVERFLOW;
+    hipStream_t s = (hipStream_t)stream;
+    prof_begin(BP_PROF_SURR_SOLVE, s);
+    hipLaunchKernelGGL(k_icm_solve<kSolveSeeded>, dim3((unsigned)blocks), dim3(64), 0, s, *p, gauss_rules(), n, M, c,
+                       z, y, mean, std, sol, status);
+    prof_end(BP_PROF_SURR_SOLVE, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                                          float *qtables, float *meta, void *stream) {
+    int e = check_params(p);
+    if (e) return e;
+    if (n < 0) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if (!sol || !status || !qtables || !meta) return BP_E_ARG;
+    if (n > ((int64_t)1 << 40)) return BP_E_OVERFLOW;
+    hipStream_t s = (hipStream_t)stream;
+    QNodes QN;
+    for (int k = 0; k < BP_MLP_NQ; ++k) QN.q[k] = 0.5 * (1.0 - cos(kPi * k / (BP_MLP_NQ - 1)));
+    QN.q[BP_MLP_NQ - 1] = 1.0 - 1e-6;
+    prof_begin(BP_PROF_SURR_APPLY, s);
+    hipLaunchKernelGGL(k_qtables_exact, dim3((unsigned)((n + kQH - 1) / kQH)), dim3(256), 0, s, *p, gauss_rules(), QN, n,
+                       sol, status, qtables, meta);
+    prof_end(BP_PROF_SURR_APPLY, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -214,24 +214,17 @@ __global__ void k_apply_q(int64_t n, const float *__restrict__ y, const float *_
     *reinterpret_cast<float4 *>(qt + i * 2 * BP_MLP_NQ + k) = g;
 }
 
-// network output -> sol (XF, RF, RT) and meta (PE0, NE0): one thread per halo.  A launch of its
-// own, so that this FP64 work does not run on one lane of a wavefront while the other 63 wait.
-__global__ void k_apply_halo(bp_params P, int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
-                             const float *__restrict__ sd, double *__restrict__ sol,
-                             const int32_t *__restrict__ status, float *__restrict__ meta) {
+// meta (PE0, NE0) of a halo solved by the seeded solve: the central electron pressure and density of
+// Sec. 3.2 from the solved P0 and rho0, as the exact tables' set-up writes them.  One thread per halo:
+// a launch of its own, so that this FP64 work does not run on one lane of a wavefront while the
+// other 63 wait.
+__global__ void k_apply_halo(bp_params P, int64_t n, const double *__restrict__ sol, const int32_t *__restrict__ status,
+                             float *__restrict__ meta) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || status[i]) return;
-    const float *row = y + i * BP_MLP_OUT;
-    const int c0 = 2 * BP_MLP_NQ;
-    double xf = exp((double)(row[c0] * sd[c0] + mean[c0]));
-    double rv = sol[(int64_t)BP_SOL_RVIR * n + i];
-    sol[(int64_t)BP_SOL_XF * n + i] = xf;
-    sol[(int64_t)BP_SOL_RF * n + i] = xf * rv;
-    sol[(int64_t)BP_SOL_RT * n + i] = fmin(xf * rv, P.trunc_r500 * sol[(int64_t)BP_SOL_R500 * n + i]);
-    meta[(int64_t)BP_META_PE0 * n + i] =
-        (float)(sol[(int64_t)BP_SOL_PS * n + i] * exp((double)(row[c0 + 1] * sd[c0 + 1] + mean[c0 + 1])));
-    meta[(int64_t)BP_META_NE0 * n + i] =
-        (float)(ne_scale(P, sol[(int64_t)BP_SOL_M * n + i], rv) * exp((double)(row[c0 + 2] * sd[c0 + 2] + mean[c0 + 2])));
+    const double X = P.X_H;
+    meta[(int64_t)BP_META_PE0 * n + i] = (float)((2.0 * X + 2.0) / (5.0 * X + 3.0) * sol[(int64_t)BP_SOL_P0 * n + i]);
+    meta[(int64_t)BP_META_NE0 * n + i] = (float)(sol[(int64_t)BP_SOL_RHO0 * n + i] / (2.0 / (1.0 + X) * kMp));
     for (int f = 0; f < BP_META_PE0; ++f) meta[(int64_t)f * n + i] = 0.0f;
     for (int f = BP_META_PR_RV; f < BP_META_NFIELDS; ++f) meta[(int64_t)f * n + i] = 0.0f;
 }
@@ -281,7 +274,7 @@ extern "C" int bp_surrogate_mse(int64_t n, const float *y, const float *targets,
 }
 
 extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
-                                  double *sol, const int32_t *status, float *qtables, float *meta, void *stream) {
+                                  const double *sol, const int32_t *status, float *qtables, float *meta, void *stream) {
     if (check_params(p) || n < 0 || (n > 0 && (!y || !mean || !std || !sol || !status || !qtables || !meta)))
         return BP_E_ARG;
     if (n == 0) return BP_OK;
@@ -289,7 +282,7 @@ extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y,
     hipStream_t s = (hipStream_t)stream;
     prof_begin(BP_PROF_SURR_APPLY, s);
     hipLaunchKernelGGL(k_apply_q, dim3(nblk(n * 2 * BP_MLP_NQ / 4)), dim3(256), 0, s, n, y, mean, std, status, qtables);
-    hipLaunchKernelGGL(k_apply_halo, dim3(nblk(n)), dim3(256), 0, s, *p, n, y, mean, std, sol, status, meta);
+    hipLaunchKernelGGL(k_apply_halo, dim3(nblk(n)), dim3(256), 0, s, *p, n, sol, status, meta);
     prof_end(BP_PROF_SURR_APPLY, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -15,7 +15,7 @@ import torch
 
 from . import (MLP_IN, MLP_OUT, S_OUT_OF_DOMAIN, SOL_NFIELDS, META_NFIELDS, MLP_NQ, _check, _lib, _ptr, _stream,
                Workspace, default_params, hp_paste_flat, hp_paste_flat_q, hp_paste_healpix, hp_paste_healpix_q,
-               icm_solve, profile_tables)
+               icm_solve, profile_tables, surrogate_solve)
 
 
 def _f64(a, dev):
@@ -165,20 +165,26 @@ class Surrogate:
         return hist
 
     # -- inference -------------------------------------------------------------
-    def infer(self, M, c, z):
-        """Structure (exact) + network tables.  Returns sol, status (OUT_OF_DOMAIN bit set where the exact
-        path must be used), q-tables [n, 128], meta."""
+    def infer(self, M, c, z, tables="exact"):
+        """Network outputs, then the ICM solve seeded by the network's x_f (bp_surrogate_solve) and the
+        q-tables: tables="exact" integrates the solved profiles at the 64 q nodes
+        (bp_surrogate_qtables_exact); tables="network" takes the network's own table outputs
+        (bp_surrogate_apply).  Returns sol, status (non-zero where the exact path must be used: outside
+        the training domain or no root near the estimate), q-tables [n, 128], meta."""
+        if tables not in ("exact", "network"):
+            raise ValueError(f"tables must be 'exact' or 'network', not {tables!r}")
         n = M.numel()
-        sol = torch.empty((SOL_NFIELDS, n), dtype=torch.float64, device=self.dev)
-        st = torch.empty(n, dtype=torch.int32, device=self.dev)
-        _check(_lib.bp_halo_structure(C.byref(self.params), n, _ptr(M), _ptr(c), _ptr(z), _ptr(sol), _ptr(st),
-                                      _stream()), "bp_halo_structure")
         x = self.features(M, c, z)
         y = self.predict(x)
+        sol, st = surrogate_solve(self.params, M, c, z, y, self.mean, self.std)
         qt = torch.zeros((n, 2 * MLP_NQ), dtype=torch.float32, device=self.dev)
         meta = torch.zeros((META_NFIELDS, n), dtype=torch.float32, device=self.dev)
-        _check(_lib.bp_surrogate_apply(C.byref(self.params), n, _ptr(y), _ptr(self.mean), _ptr(self.std), _ptr(sol),
-                                       _ptr(st), _ptr(qt), _ptr(meta), _stream()), "bp_surrogate_apply")
+        if tables == "exact":
+            _check(_lib.bp_surrogate_qtables_exact(C.byref(self.params), n, _ptr(sol), _ptr(st), _ptr(qt), _ptr(meta),
+                                                   _stream()), "bp_surrogate_qtables_exact")
+        else:
+            _check(_lib.bp_surrogate_apply(C.byref(self.params), n, _ptr(y), _ptr(self.mean), _ptr(self.std),
+                                           _ptr(sol), _ptr(st), _ptr(qt), _ptr(meta), _stream()), "bp_surrogate_apply")
         return sol, st, qt, meta
 
     def _fallback(self, cat_dev, st, paste):
@@ -192,19 +198,19 @@ class Surrogate:
             paste(sub, s2, st2, tb2, mt2)
         return nout
 
-    def paste_healpix(self, cat_dev, nside, y_map, b_map, ws: Workspace | None = None):
+    def paste_healpix(self, cat_dev, nside, y_map, b_map, ws: Workspace | None = None, tables="exact"):
         """Surrogate HP paste onto HEALPix RING maps, exact fallback for halos outside the training domain.
         cat_dev holds M, c, z, theta, phi, v_los."""
-        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"])
+        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"], tables)
         hp_paste_healpix_q(self.params, nside, cat_dev["theta"], cat_dev["phi"], cat_dev["v_los"], sol, st, qt, meta,
                            y_map, b_map, ws)
         del sol, qt, meta
         return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_healpix(
             self.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map, ws))
 
-    def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None):
+    def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None, tables="exact"):
         """Surrogate HP paste with exact fallback for halos outside the training domain."""
-        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"])
+        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"], tables)
         hp_paste_flat_q(self.params, npix, pix_rad, cat_dev["theta_x"], cat_dev["theta_y"], cat_dev["v_los"], sol,
                         st, qt, meta, y_map, b_map, ws)
         del sol, qt, meta
