@@ -253,20 +253,23 @@ def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, p
     nout = [0]
     mode = ["exact"]
 
+    # the batches add into the maps as one Kahan-compensated sum (compensation maps carried between calls)
+    yc, bc = torch.zeros_like(ye), torch.zeros_like(ye)
+
     def exact(vkey="v_los", y=ye, b=be):
-        y.zero_(); b.zero_()
+        y.zero_(); b.zero_(); yc.zero_(); bc.zero_()
         for d in batches:
             sol, st = bp.icm_solve(params, d["M"], d["c"], d["z"])
             tab, meta = bp.profile_tables(params, sol, st)
             v = d[vkey] if vkey == "v_los" else d["v_los"].abs()
-            bp.hp_paste_healpix(params, nside, d["theta"], d["phi"], v, sol, st, tab, meta, y, b, ws=ws)
+            bp.hp_paste_healpix(params, nside, d["theta"], d["phi"], v, sol, st, tab, meta, y, b, ws=ws, comp=(yc, bc))
             del sol, st, tab, meta
 
     def surrogate(y=ys, b=bs):
-        y.zero_(); b.zero_()
+        y.zero_(); b.zero_(); yc.zero_(); bc.zero_()
         nout[0] = 0
         for d in batches:
-            nout[0] += sur.paste_healpix(d, nside, y, b, ws, tables=mode[0])
+            nout[0] += sur.paste_healpix(d, nside, y, b, ws, tables=mode[0], comp=(yc, bc))
 
     sur_names = ("MLP_FWD", "SURR_SOLVE", "SURR_APPLY", "HPX_PLAN", "HPXQ_DEPOSIT", "ICM", "TABLES", "HPX_DEPOSIT")
     ms_sur = timed(surrogate, steps, warmup, bp)
@@ -295,8 +298,8 @@ def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, p
            "kernel_ms_surrogate": k_net}
     return {"workload": f"all-sky HP, HEALPix N_side {nside} RING ({npx} pixels), {n_halos} halos isotropic on the "
                         "sphere (log10 M in [12.5,15.5], dN/dlnM ~ M^-0.9, z in [0.01,3]), batches of "
-                        f"{batch}; surrogate (network-seeded FP64 solve + q-tables by quadrature) with exact "
-                        "fallback vs exact solve", "network_tables": net,
+                        f"{batch} accumulated with carried Kahan compensation; surrogate (network-seeded FP64 solve + "
+                        "q-tables by quadrature) with exact fallback vs exact solve", "network_tables": net,
             "surrogate_halos_per_s": round(n_halos / (ms_sur * 1e-3), 1), "surrogate_ms": round(ms_sur, 2),
             "exact_halos_per_s": round(n_halos / (ms_exact * 1e-3), 1), "exact_ms": round(ms_exact, 2),
             "speedup": round(ms_exact / ms_sur, 3), "fallback_halos": int(nout[0]),

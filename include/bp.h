@@ -181,6 +181,10 @@ int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const in
  *   theta_x, theta_y : device, n doubles [rad];  v_los: device, n doubles [km/s]
  *   sol, status, tables, meta : outputs of the two calls above
  *   y_map, b_map     : device float maps, ACCUMULATED
+ *   y_comp, b_comp   : NULL, or device float maps of the same shape holding each pixel's Kahan
+ *                      compensation between calls: the call resumes every touched pixel's compensated
+ *                      sum from (map, comp) and stores both back, so a sequence of calls (halo batches)
+ *                      adds up as one compensated sum.  The caller zeroes them with the maps.
  *   ws, ws_bytes     : device workspace.  If ws_bytes is too small nothing is
  *                      enqueued, *ws_needed receives the size and the call
  *                      returns BP_E_WORKSPACE.  The size depends on the
@@ -191,8 +195,8 @@ int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const in
 int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n,
                      const double *theta_x, const double *theta_y, const double *v_los,
                      const double *sol, const int32_t *status, const float *tables, const float *meta,
-                     float *y_map, float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed,
-                     void *stream);
+                     float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
+                     size_t *ws_needed, void *stream);
 
 /* ------------------------------------------------------- HEALPix (K9, K4) */
 /* HEALPix RING pixel index of each direction (Gorski et al. 2005).
@@ -209,8 +213,8 @@ int bp_healpix_ang2pix_ring(int64_t nside, int64_t n, const double *theta, const
 int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n,
                         const double *theta, const double *phi, const double *v_los,
                         const double *sol, const int32_t *status, const float *tables, const float *meta,
-                        float *y_map, float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed,
-                        void *stream);
+                        float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
+                        size_t *ws_needed, void *stream);
 
 /* ------------------------------------------------------- PP (K5-K8) */
 /* Smoothing lengths for particle-based pasting (Sec. 3.4): h_i is the
@@ -425,14 +429,14 @@ int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *gr
  * skipped (paste them with the exact path). */
 int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
                        const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
-                       const float *qtables, const float *meta, float *y_map, float *b_map, void *ws,
-                       size_t ws_bytes, size_t *ws_needed, void *stream);
+                       const float *qtables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                       float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream);
 /* The same for HEALPix RING maps (bp_hp_paste_healpix with surrogate q-tables; same arguments,
  * layouts, workspace protocol and errors as bp_hp_paste_healpix, tables as bp_hp_paste_flat_q). */
 int bp_hp_paste_healpix_q(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
                           const double *v_los, const double *sol, const int32_t *status, const float *qtables,
-                          const float *meta, float *y_map, float *b_map, void *ws, size_t ws_bytes,
-                          size_t *ws_needed, void *stream);
+                          const float *meta, float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
+                          size_t ws_bytes, size_t *ws_needed, void *stream);
 
 /* ------------------------------------------------------------- profiling */
 /* Optional timing of the library's main kernels with HIP events recorded on

@@ -69,10 +69,10 @@ _SIGS = {
     "bp_icm_solve": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_profile_tables": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
-                                   _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+                                   _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_healpix_ang2pix_ring": (C.c_int, [C.c_int64, C.c_int64, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_healpix": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
-                                      _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+                                      _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_pp_smoothing_length": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, C.c_int32, C.c_double, _VP, _VP,
                                          C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_pp_smoothing_length_eff": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, C.c_double, C.c_double, _VP, _VP,
@@ -105,9 +105,9 @@ _SIGS = {
     "bp_surrogate_qtables_exact": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
     "bp_mlp_infer": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP, _VP]),
     "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
-                                     _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+                                   _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_hp_paste_healpix_q": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
-                                        _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+                                      _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_surrogate_train_ws_bytes": (C.c_size_t, [C.c_int64]),
     "bp_surrogate_train": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_int64, _VP, _VP, C.c_int64, C.c_int64,
                                      C.c_float, C.c_float, C.c_uint64, C.c_int64, _VP, _VP, C.c_size_t, _VP]),
@@ -227,40 +227,53 @@ def _with_workspace(fn, what, ws, args):
     raise BPError(f"{what}: workspace negotiation did not converge")
 
 
+def _comp_ptrs(comp, y_map):
+    """Optional (y_comp, b_comp) Kahan compensation maps kept by the caller across calls."""
+    if comp is None:
+        return C.c_void_p(0), C.c_void_p(0)
+    yc, bc = comp
+    assert yc.shape == y_map.shape and bc.shape == y_map.shape and yc.dtype == torch.float32
+    return _ptr(yc), _ptr(bc)
+
+
 def hp_paste_flat(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v_los, sol, status, tables, meta,
-                  y_map, b_map, ws: Workspace | None = None):
-    """K3: accumulate the HP footprints of all halos into y_map, b_map ([npix, npix] float32)."""
+                  y_map, b_map, ws: Workspace | None = None, comp=None):
+    """K3: accumulate the HP footprints of all halos into y_map, b_map ([npix, npix] float32); comp = (y_comp, b_comp)
+    carries the Kahan compensation between calls."""
     ws = ws or _ws_for(y_map.device)
     _with_workspace(_lib.bp_hp_paste_flat, "bp_hp_paste_flat", ws,
                     (C.byref(params), int(npix), float(pix_rad), theta_x.numel(), _ptr(theta_x), _ptr(theta_y),
-                     _ptr(v_los), _ptr(sol), _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+                     _ptr(v_los), _ptr(sol), _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map),
+                     *_comp_ptrs(comp, y_map)))
 
 
 def hp_paste_flat_q(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v_los, sol, status, qtables, meta,
-                    y_map, b_map, ws: Workspace | None = None):
+                    y_map, b_map, ws: Workspace | None = None, comp=None):
     """K3 with surrogate q-tables (halos with a non-zero status are skipped)."""
     ws = ws or _ws_for(y_map.device)
     _with_workspace(_lib.bp_hp_paste_flat_q, "bp_hp_paste_flat_q", ws,
                     (C.byref(params), int(npix), float(pix_rad), theta_x.numel(), _ptr(theta_x), _ptr(theta_y),
-                     _ptr(v_los), _ptr(sol), _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+                     _ptr(v_los), _ptr(sol), _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map),
+                     *_comp_ptrs(comp, y_map)))
 
 
 def hp_paste_healpix_q(params: Params, nside: int, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map,
-                       ws: Workspace | None = None):
+                       ws: Workspace | None = None, comp=None):
     """K4 with surrogate q-tables (halos with a non-zero status are skipped)."""
     ws = ws or _ws_for(y_map.device)
     _with_workspace(_lib.bp_hp_paste_healpix_q, "bp_hp_paste_healpix_q", ws,
                     (C.byref(params), int(nside), theta.numel(), _ptr(theta), _ptr(phi), _ptr(v_los), _ptr(sol),
-                     _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+                     _ptr(status), _ptr(qtables), _ptr(meta), _ptr(y_map), _ptr(b_map), *_comp_ptrs(comp, y_map)))
 
 
 def hp_paste_healpix(params: Params, nside: int, theta, phi, v_los, sol, status, tables, meta, y_map, b_map,
-                     ws: Workspace | None = None):
-    """K4: accumulate the HP footprints into HEALPix RING maps (12 nside^2 float32)."""
+                     ws: Workspace | None = None, comp=None):
+    """K4: accumulate the HP footprints into HEALPix RING maps (12 nside^2 float32); comp = (y_comp, b_comp) carries
+    the Kahan compensation between calls."""
     ws = ws or _ws_for(y_map.device)
     _with_workspace(_lib.bp_hp_paste_healpix, "bp_hp_paste_healpix", ws,
                     (C.byref(params), int(nside), theta.numel(), _ptr(theta), _ptr(phi), _ptr(v_los), _ptr(sol),
-                     _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map)))
+                     _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map), *_comp_ptrs(comp, y_map)))
 
 
 def healpix_ang2pix_ring(nside: int, theta: torch.Tensor, phi: torch.Tensor) -> torch.Tensor:

@@ -216,7 +216,8 @@ template <bool kQ>
 __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, const FlatRec *__restrict__ rec,
                                                       const float *__restrict__ tables, const uint32_t *__restrict__ vals,
                                                       const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
-                                                      float *__restrict__ ymap, float *__restrict__ bmap, int ntiles) {
+                                                      float *__restrict__ ymap, float *__restrict__ bmap,
+                                                      float *__restrict__ ycomp, float *__restrict__ bcomp, int ntiles) {
     // the tile, its pair range and every halo record are wave-uniform (scalar registers)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int tile = blockIdx.x * 4 + wave;
@@ -236,7 +237,9 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
         int64_t idx = (int64_t)pj * Gm.npix + pi;
         ys[q] = inmap[q] ? ymap[idx] : 0.0f;
         bs[q] = inmap[q] ? bmap[idx] : 0.0f;
-        yc[q] = 0.0f; bc[q] = 0.0f;
+        // the compensation carried over from earlier calls, when the caller keeps it
+        yc[q] = (ycomp && inmap[q]) ? ycomp[idx] : 0.0f;
+        bc[q] = (bcomp && inmap[q]) ? bcomp[idx] : 0.0f;
     }
     for (uint32_t p = p0; p < p1; ++p) {
         const uint32_t h = __builtin_amdgcn_readfirstlane(vals[p]);
@@ -288,6 +291,8 @@ __global__ void __launch_bounds__(256) k_flat_deposit(FlatGeom Gm, int64_t n, co
         int64_t idx = (int64_t)pj * Gm.npix + pi;
         ymap[idx] = ys[q];
         bmap[idx] = bs[q];
+        if (ycomp) ycomp[idx] = yc[q];
+        if (bcomp) bcomp[idx] = bc[q];
     }
 }
 
@@ -298,8 +303,8 @@ using namespace bp;
 template <bool kQ>
 static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
                                 const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
-                                const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
-                                size_t ws_bytes, size_t *ws_needed, void *stream) {
+                                const float *tables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                                float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
     if (check_params(p) || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta_x || !theta_y || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
@@ -374,23 +379,23 @@ static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int
     prof_end(BP_PROF_FLAT_PLAN, s);
     prof_begin(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
     hipLaunchKernelGGL(k_flat_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, Gm, n, rec, tables, vs,
-                       tst, ten, y_map, b_map, (int)ntiles);
+                       tst, ten, y_map, b_map, y_comp, b_comp, (int)ntiles);
     prof_end(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
 extern "C" int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
                                 const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
-                                const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
-                                size_t ws_bytes, size_t *ws_needed, void *stream) {
+                                const float *tables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                                float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
     return paste_flat_impl<false>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, tables, meta, y_map,
-                                  b_map, ws, ws_bytes, ws_needed, stream);
+                                  b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream);
 }
 
 extern "C" int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
                                   const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
-                                  const float *qtables, const float *meta, float *y_map, float *b_map, void *ws,
-                                  size_t ws_bytes, size_t *ws_needed, void *stream) {
+                                  const float *qtables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                                  float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
     return paste_flat_impl<true>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, qtables, meta, y_map,
-                                 b_map, ws, ws_bytes, ws_needed, stream);
+                                 b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream);
 }

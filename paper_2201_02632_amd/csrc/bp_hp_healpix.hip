@@ -294,7 +294,8 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
                                                      const RingRec *__restrict__ rtab,
                                                      const double *__restrict__ thin, const double *__restrict__ phin,
                                                      const double *__restrict__ sol, float *__restrict__ ymap,
-                                                     float *__restrict__ bmap, uint32_t ntiles) {
+                                                     float *__restrict__ bmap, float *__restrict__ ycomp,
+                                                     float *__restrict__ bcomp, uint32_t ntiles) {
     // the tile, its pair range and every halo record are wave-uniform (scalar registers)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + wave;
@@ -323,7 +324,9 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
     const double phj = step * ((double)(jl + 1) - sh);
     const double sthr = Rr.sth, st2 = Rr.st2, ct2 = Rr.ct2;
     const float inv_pix2 = (float)(1.0 / (G.pixang * G.pixang));
-    float ys = valid ? ymap[pix] : 0.0f, bs = valid ? bmap[pix] : 0.0f, yc = 0.0f, bc = 0.0f;
+    float ys = valid ? ymap[pix] : 0.0f, bs = valid ? bmap[pix] : 0.0f;
+    // the compensation carried over from earlier calls, when the caller keeps it
+    float yc = (ycomp && valid) ? ycomp[pix] : 0.0f, bc = (bcomp && valid) ? bcomp[pix] : 0.0f;
     for (uint32_t p = p0; p < p1; ++p) {
         const uint32_t h = __builtin_amdgcn_readfirstlane(vals[p]);
         if (h >= (uint32_t)n) continue;
@@ -368,7 +371,11 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
             kahan_add(bs, bc, R.amp_b * vn);
         }
     }
-    if (valid) { ymap[pix] = ys; bmap[pix] = bs; }
+    if (valid) {
+        ymap[pix] = ys; bmap[pix] = bs;
+        if (ycomp) ycomp[pix] = yc;
+        if (bcomp) bcomp[pix] = bc;
+    }
 }
 
 }  // namespace bp
@@ -378,8 +385,8 @@ using namespace bp;
 template <bool kQ>
 static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
                               const double *v_los, const double *sol, const int32_t *status, const float *tables,
-                              const float *meta, float *y_map, float *b_map, void *ws, size_t ws_bytes,
-                              size_t *ws_needed, void *stream) {
+                              const float *meta, float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
+                              size_t ws_bytes, size_t *ws_needed, void *stream) {
     if (check_params(p) || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta || !phi || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
@@ -465,23 +472,25 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     prof_end(BP_PROF_HPX_PLAN, s);
     prof_begin(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
     hipLaunchKernelGGL(k_hpx_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, G, n, rec, tables, vs,
-                       tst, ten, btile0, nbands, rtab, theta, phi, sol, y_map, b_map, (uint32_t)ntiles);
+                       tst, ten, btile0, nbands, rtab, theta, phi, sol, y_map, b_map, y_comp, b_comp,
+                       (uint32_t)ntiles);
     prof_end(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
 extern "C" int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n, const double *theta,
                                    const double *phi, const double *v_los, const double *sol, const int32_t *status,
-                                   const float *tables, const float *meta, float *y_map, float *b_map, void *ws,
-                                   size_t ws_bytes, size_t *ws_needed, void *stream) {
-    return paste_healpix_impl<false>(p, nside, n, theta, phi, v_los, sol, status, tables, meta, y_map, b_map, ws,
-                                     ws_bytes, ws_needed, stream);
+                                   const float *tables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                                   float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
+    return paste_healpix_impl<false>(p, nside, n, theta, phi, v_los, sol, status, tables, meta, y_map, b_map, y_comp,
+                                     b_comp, ws, ws_bytes, ws_needed, stream);
 }
 
 extern "C" int bp_hp_paste_healpix_q(const bp_params *p, int64_t nside, int64_t n, const double *theta,
                                      const double *phi, const double *v_los, const double *sol,
                                      const int32_t *status, const float *qtables, const float *meta, float *y_map,
-                                     float *b_map, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
-    return paste_healpix_impl<true>(p, nside, n, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map, ws,
-                                    ws_bytes, ws_needed, stream);
+                                     float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
+                                     size_t *ws_needed, void *stream) {
+    return paste_healpix_impl<true>(p, nside, n, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map, y_comp,
+                                    b_comp, ws, ws_bytes, ws_needed, stream);
 }

@@ -198,22 +198,22 @@ class Surrogate:
             paste(sub, s2, st2, tb2, mt2)
         return nout
 
-    def paste_healpix(self, cat_dev, nside, y_map, b_map, ws: Workspace | None = None, tables="exact"):
+    def paste_healpix(self, cat_dev, nside, y_map, b_map, ws: Workspace | None = None, tables="exact", comp=None):
         """Surrogate HP paste onto HEALPix RING maps, exact fallback for halos outside the training domain.
-        cat_dev holds M, c, z, theta, phi, v_los."""
+        cat_dev holds M, c, z, theta, phi, v_los; comp = (y_comp, b_comp) carries the Kahan compensation."""
         sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"], tables)
         hp_paste_healpix_q(self.params, nside, cat_dev["theta"], cat_dev["phi"], cat_dev["v_los"], sol, st, qt, meta,
-                           y_map, b_map, ws)
+                           y_map, b_map, ws, comp)
         del sol, qt, meta
         return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_healpix(
-            self.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map, ws))
+            self.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map, ws, comp))
 
-    def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None, tables="exact"):
+    def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None, tables="exact", comp=None):
         """Surrogate HP paste with exact fallback for halos outside the training domain."""
         sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"], tables)
         hp_paste_flat_q(self.params, npix, pix_rad, cat_dev["theta_x"], cat_dev["theta_y"], cat_dev["v_los"], sol,
-                        st, qt, meta, y_map, b_map, ws)
+                        st, qt, meta, y_map, b_map, ws, comp)
         del sol, qt, meta
         return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_flat(
             self.params, npix, pix_rad, sub["theta_x"], sub["theta_y"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map,
-            ws))
+            ws, comp))

@@ -72,9 +72,9 @@ def test_gamma_other_than_the_papers_is_rejected():
             L.bp_halo_structure(ctypes.byref(p), 0, fake, fake, fake, fake, fake, None),
             L.bp_profile_tables(ctypes.byref(p), 0, fake, fake, fake, fake, None),
             L.bp_hp_paste_flat(ctypes.byref(p), 64, 1e-4, 0, fake, fake, fake, fake, fake, fake, fake, fake, fake,
-                               None, 0, ctypes.byref(need), None),
+                               None, None, None, 0, ctypes.byref(need), None),
             L.bp_hp_paste_healpix(ctypes.byref(p), 16, 0, fake, fake, fake, fake, fake, fake, fake, fake, fake, None,
-                                  0, ctypes.byref(need), None),
+                                  None, None, 0, ctypes.byref(need), None),
             L.bp_pp_paste_flat(ctypes.byref(p), 64, 1e-4, 0, fake, fake, fake, fake, fake, fake, fake, 1e10, 0, None,
                                None, fake, fake, None, 0, ctypes.byref(need), None),
             L.bp_pp_paste_healpix_ngp(ctypes.byref(p), 16, 0, fake, fake, fake, fake, 1e10, fake, None, 0,

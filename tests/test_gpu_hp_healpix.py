@@ -90,3 +90,28 @@ def test_hp_healpix_sign_and_determinism(bp):
     torch.cuda.synchronize()
     assert torch.equal(y1, y2) and torch.equal(b1, b2)
     assert torch.equal(y1, y3) and torch.equal(b3, -b1)
+
+
+def test_hp_healpix_batches_with_compensation_equal_one_call(bp):
+    """All-sky maps accumulate over halo batches: carrying the Kahan compensation maps between calls makes
+    consecutive batches reproduce one call over the whole catalogue bit for bit."""
+    import torch
+    cat = sky_case(5, 300, 256)
+    params = bp.default_params()
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    t = {k: T(v) for k, v in cat.items()}
+    npx = 12 * 256 * 256
+    sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
+    tab, meta = bp.profile_tables(params, sol, st)
+    y1 = torch.zeros(npx, device="cuda")
+    b1 = torch.zeros_like(y1)
+    bp.hp_paste_healpix(params, 256, t["theta"], t["phi"], t["v_los"], sol, st, tab, meta, y1, b1)
+    yb, bb, yc, bc = (torch.zeros_like(y1) for _ in range(4))
+    for a, e in ((0, 77), (77, 78), (78, 250), (250, 300)):
+        sub = {k: v[a:e].contiguous() for k, v in t.items()}
+        s2, st2 = bp.icm_solve(params, sub["M"], sub["c"], sub["z"])
+        tb2, mt2 = bp.profile_tables(params, s2, st2)
+        bp.hp_paste_healpix(params, 256, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, yb, bb,
+                            comp=(yc, bc))
+    torch.cuda.synchronize()
+    assert torch.equal(yb, y1) and torch.equal(bb, b1)
