@@ -423,6 +423,55 @@ int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *gr
                        const float *std, int64_t ndata, const float *x, const float *targets, int64_t steps,
                        int64_t batch, float lr0, float lr1, uint64_t seed, int64_t step0, float *loss_rows, void *ws,
                        size_t ws_bytes, void *stream);
+/* --------------------------------------- surrogate lifecycle (one state buffer) */
+/* The surrogate's whole state lives in one caller-allocated device buffer of bp_surrogate_state_bytes()
+ * bytes, 256-byte aligned (the library allocates nothing).  Array a of the state starts at byte
+ * bp_surrogate_state_offset(a): FP32 master weights (BP_MLP_NPARAMS layout above), their BF16 compute
+ * copy, the two Adam moments, the last gradient, and the output mean and standard deviation (BP_MLP_OUT
+ * floats each).  The buffer holds no pointers: copying its bytes copies the surrogate. */
+enum { BP_SUR_W = 0, BP_SUR_WBF16, BP_SUR_M, BP_SUR_V, BP_SUR_G, BP_SUR_MEAN, BP_SUR_STD, BP_SUR_NARRAYS };
+size_t bp_surrogate_state_bytes(void);
+size_t bp_surrogate_state_offset(int32_t array);     /* (size_t)-1 for an unknown array */
+/* Create: He-initialised weights (normal deviates from a counter-based hash of seed and parameter index,
+ * variance 2 / fan-in, biases 0, input padding columns 0), zero Adam state, mean 0, std 1.
+ * BP_E_ARG for a null or unaligned state. */
+int bp_surrogate_init(void *state, uint64_t seed, void *stream);
+/* Train from exact solves: the n halos (M, c, z, device) are solved (bp_icm_solve), tabulated
+ * (bp_profile_tables) and turned into targets and their column statistics; then `steps` Adam steps as
+ * bp_surrogate_train (cosine learning rate lr0 -> lr1, batches drawn by a counter-based hash of seed,
+ * Adam step counter continuing from step0).  Workspace protocol as for the pastes (~2.5 KB per halo). */
+int bp_surrogate_fit(const bp_params *p, void *state, int64_t n, const double *M, const double *c, const double *z,
+                     int64_t steps, int64_t batch, float lr0, float lr1, uint64_t seed, int64_t step0, void *ws,
+                     size_t ws_bytes, size_t *ws_needed, void *stream);
+/* Save / load through a host blob of bp_surrogate_blob_bytes() bytes: a header (format tag, parameter
+ * count, output width, Adam step) and the FP32 weights, moments, mean and std.  Both synchronise the
+ * stream.  load rejects a blob of another format or size with BP_E_ARG (state unchanged) and refreshes
+ * the BF16 copy; *step (nullable) receives the stored Adam step. */
+size_t bp_surrogate_blob_bytes(void);
+int bp_surrogate_save(const void *state, int64_t step, void *blob, size_t blob_bytes, void *stream);
+int bp_surrogate_load(void *state, const void *blob, size_t blob_bytes, int64_t *step, void *stream);
+/* Infer and paste (Sec. 3.3 HP maps through the surrogate), every routing decision on the device:
+ * network outputs for all halos; bp_surrogate_solve; q-tables from the solved profiles
+ * (tables = BP_SUR_TABLES_EXACT, bp_surrogate_qtables_exact) or from the network's table outputs
+ * (BP_SUR_TABLES_NETWORK, bp_surrogate_apply); halos outside the training domain or without a root near
+ * the estimate are compacted, solved by the exact scan (bp_icm_solve) and given exact q-tables; then one
+ * q-table deposit of all halos (bp_hp_paste_flat_q / bp_hp_paste_healpix_q, maps ACCUMULATE, y_comp /
+ * b_comp nullable as there).  Halos the exact solve cannot solve either (invalid input, stars above the
+ * baryon mass) are skipped.  *n_fallback (nullable) receives the number of halos routed to the scan.
+ * Workspace protocol as for the pastes (about 1.4 KB per halo plus the deposit's); one synchronisation
+ * for the routed count, one in the deposit. */
+#define BP_SUR_TABLES_EXACT   0
+#define BP_SUR_TABLES_NETWORK 1
+int bp_surrogate_paste_flat(const bp_params *p, const void *state, int32_t tables, int32_t npix, double pix_rad,
+                            int64_t n, const double *M, const double *c, const double *z, const double *theta_x,
+                            const double *theta_y, const double *v_los, float *y_map, float *b_map, float *y_comp,
+                            float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, int64_t *n_fallback,
+                            void *stream);
+int bp_surrogate_paste_healpix(const bp_params *p, const void *state, int32_t tables, int64_t nside, int64_t n,
+                               const double *M, const double *c, const double *z, const double *theta,
+                               const double *phi, const double *v_los, float *y_map, float *b_map, float *y_comp,
+                               float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, int64_t *n_fallback,
+                               void *stream);
 /* HP flat paste from surrogate q-tables: as bp_hp_paste_flat with
  * Y_P(r_perp) = P_e0 R_t E(r_perp) G_P(q), q = r_perp / R_t, cubic interpolation
  * in s = acos(1 - 2q)/pi on the 64 nodes.  Halos whose status is non-zero are

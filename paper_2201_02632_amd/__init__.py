@@ -103,6 +103,20 @@ _SIGS = {
     "bp_surrogate_apply": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_surrogate_solve": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bp_surrogate_qtables_exact": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
+    "bp_surrogate_state_bytes": (C.c_size_t, []),
+    "bp_surrogate_state_offset": (C.c_size_t, [C.c_int32]),
+    "bp_surrogate_init": (C.c_int, [_VP, C.c_uint64, _VP]),
+    "bp_surrogate_blob_bytes": (C.c_size_t, []),
+    "bp_surrogate_save": (C.c_int, [_VP, C.c_int64, _VP, C.c_size_t, _VP]),
+    "bp_surrogate_load": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(C.c_int64), _VP]),
+    "bp_surrogate_fit": (C.c_int, [_P, _VP, C.c_int64, _VP, _VP, _VP, C.c_int64, C.c_int64, C.c_float, C.c_float,
+                                   C.c_uint64, C.c_int64, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_surrogate_paste_flat": (C.c_int, [_P, _VP, C.c_int32, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP,
+                                          _VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t),
+                                          C.POINTER(C.c_int64), _VP]),
+    "bp_surrogate_paste_healpix": (C.c_int, [_P, _VP, C.c_int32, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP,
+                                             _VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t),
+                                             C.POINTER(C.c_int64), _VP]),
     "bp_mlp_infer": (C.c_int, [_VP, _VP, C.c_int64, _VP, _VP, _VP]),
     "bp_hp_paste_flat_q": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                    _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
@@ -119,6 +133,8 @@ PROF = {name: k for k, name in enumerate(["ICM", "TABLES", "FLAT_PLAN", "FLAT_DE
                                           "SURR_APPLY", "FLATQ_DEPOSIT", "HPXQ_DEPOSIT", "PP_NEFF", "NGP_PLAN",
                                           "NGP_DEPOSIT", "SPECTRUM", "SURR_SOLVE"])}
 MLP_NIN, MLP_IN, MLP_HID, MLP_OUT, MLP_NOUT, MLP_NQ = 3, 16, 256, 144, 131, 64
+SUR_ARRAYS = ["W", "WBF16", "M", "V", "G", "MEAN", "STD"]
+SUR_TABLES = {"exact": 0, "network": 1}
 S_OUT_OF_DOMAIN = 32
 EXPORTED = list(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -212,13 +228,15 @@ def _ws_for(device):
     return _default_ws[key]
 
 
-def _with_workspace(fn, what, ws, args):
+def _with_workspace(fn, what, ws, args, tail=()):
+    """Call fn(*args, ws, ws_bytes, &ws_needed, *tail, stream), growing the workspace while the library asks
+    for more (a call that synchronises midway can ask again once it knows its data-dependent sizes)."""
     need = C.c_size_t(0)
-    for _ in range(3):
+    for _ in range(6):
         buf = ws.buf
         ptr = C.c_void_p(buf.data_ptr()) if buf is not None else C.c_void_p(0)
         nbytes = buf.numel() if buf is not None else 0
-        code = fn(*args, ptr, nbytes, C.byref(need), _stream())
+        code = fn(*args, ptr, nbytes, C.byref(need), *tail, _stream())
         if code == BP_E_WORKSPACE:
             ws.ensure(need.value)
             continue

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbp.so")
-SOURCES = ["bp_icm.hip", "bp_sort.hip", "bp_hp_flat.hip", "bp_healpix.hip", "bp_hp_healpix.hip", "bp_prof.hip", "bp_pp.hip", "bp_pp_healpix.hip", "bp_spectrum.hip", "bp_mlp.hip", "bp_surrogate.hip"]
+SOURCES = ["bp_icm.hip", "bp_sort.hip", "bp_hp_flat.hip", "bp_healpix.hip", "bp_hp_healpix.hip", "bp_prof.hip", "bp_pp.hip", "bp_pp_healpix.hip", "bp_spectrum.hip", "bp_mlp.hip", "bp_surrogate.hip", "bp_surrogate_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wno-unused-result",

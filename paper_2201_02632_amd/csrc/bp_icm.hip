@@ -794,12 +794,12 @@ struct QNodes { double q[BP_MLP_NQ]; };
 constexpr int kQH = 64;                     // halos per block
 __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G, QNodes QN, int64_t n,
                                                        const double *__restrict__ sol,
-                                                       const int32_t *__restrict__ status, float *__restrict__ qt,
-                                                       float *__restrict__ meta) {
+                                                       const int32_t *__restrict__ status, int32_t ok_mask,
+                                                       float *__restrict__ qt, float *__restrict__ meta) {
     __shared__ float tile[kQH][2 * BP_MLP_NQ + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kQH, i = i0 + lane;
-    const bool live = i < n && status[i] == 0;
+    const bool live = i < n && (status[i] & ~ok_mask) == 0;
     if (live) {
         auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
         const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), Rt = S(BP_SOL_RT), c = S(BP_SOL_C), mc = nfw_m(c);
@@ -877,7 +877,7 @@ __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G
     const int nh = (int)min((int64_t)kQH, n - i0);
     for (int e = threadIdx.x; e < nh * 2 * BP_MLP_NQ; e += 256) {
         const int h = e / (2 * BP_MLP_NQ), k = e - h * 2 * BP_MLP_NQ;
-        if (status[i0 + h] == 0) qt[(i0 + h) * 2 * BP_MLP_NQ + k] = tile[h][k];
+        if ((status[i0 + h] & ~ok_mask) == 0) qt[(i0 + h) * 2 * BP_MLP_NQ + k] = tile[h][k];
     }
 }
 
@@ -1016,21 +1016,25 @@ extern "C" int bp_surrogate_solve(const bp_params *p, int64_t n, const double *M
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
-extern "C" int bp_surrogate_qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
-                                          float *qtables, float *meta, void *stream) {
+int bp::qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status, int32_t ok_mask,
+                      float *qtables, float *meta, hipStream_t s) {
     int e = check_params(p);
     if (e) return e;
     if (n < 0) return BP_E_ARG;
     if (n == 0) return BP_OK;
     if (!sol || !status || !qtables || !meta) return BP_E_ARG;
     if (n > ((int64_t)1 << 40)) return BP_E_OVERFLOW;
-    hipStream_t s = (hipStream_t)stream;
     QNodes QN;
     for (int k = 0; k < BP_MLP_NQ; ++k) QN.q[k] = 0.5 * (1.0 - cos(kPi * k / (BP_MLP_NQ - 1)));
     QN.q[BP_MLP_NQ - 1] = 1.0 - 1e-6;
     prof_begin(BP_PROF_SURR_APPLY, s);
     hipLaunchKernelGGL(k_qtables_exact, dim3((unsigned)((n + kQH - 1) / kQH)), dim3(256), 0, s, *p, gauss_rules(), QN, n,
-                       sol, status, qtables, meta);
+                       sol, status, ok_mask, qtables, meta);
     prof_end(BP_PROF_SURR_APPLY, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_surrogate_qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                                          float *qtables, float *meta, void *stream) {
+    return qtables_exact(p, n, sol, status, 0, qtables, meta, (hipStream_t)stream);
 }

@@ -17,6 +17,10 @@ namespace bp {
 
 const GaussRules &gauss_rules();
 
+// Exact surrogate q-tables (bp_surrogate_qtables_exact) for halos whose status has no bit outside ok_mask.
+int qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status, int32_t ok_mask,
+                  float *qtables, float *meta, hipStream_t s);
+
 // Validate the model parameters (every entry point that takes bp_params): BP_OK or BP_E_ARG.
 // Gamma must be the paper's 1.2, the polytropic index the kernels are written for.
 int check_params(const bp_params *p);

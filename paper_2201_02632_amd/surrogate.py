@@ -13,9 +13,9 @@ import math
 import numpy as np
 import torch
 
-from . import (MLP_IN, MLP_OUT, S_OUT_OF_DOMAIN, SOL_NFIELDS, META_NFIELDS, MLP_NQ, _check, _lib, _ptr, _stream,
-               Workspace, default_params, hp_paste_flat, hp_paste_flat_q, hp_paste_healpix, hp_paste_healpix_q,
-               icm_solve, profile_tables, surrogate_solve)
+from . import (MLP_IN, MLP_OUT, S_OUT_OF_DOMAIN, SOL_NFIELDS, META_NFIELDS, MLP_NQ, SUR_ARRAYS, SUR_TABLES, _check,
+               _comp_ptrs, _lib, _ptr, _stream, _with_workspace, _ws_for, Workspace, default_params, icm_solve,
+               profile_tables, surrogate_solve)
 
 
 def _f64(a, dev):
@@ -23,22 +23,29 @@ def _f64(a, dev):
 
 
 class Surrogate:
-    """MLP (3 -> 256 -> 256 -> 256 -> 144) with FP32 master weights, a BF16
-    compute copy and Adam state, all device-resident."""
+    """MLP (3 -> 256 -> 256 -> 256 -> 144) with FP32 master weights, a BF16 compute copy and Adam state, all
+    in one device state buffer that the library lays out (bp_surrogate_state_bytes); the attributes w, wb,
+    m, v, g, mean and std are views into it."""
 
     def __init__(self, params=None, device="cuda", seed=0):
         self.params = params or default_params()
         self.dev = torch.device(device)
         self.np = int(_lib.bp_mlp_nparams())
-        self.w = torch.zeros(self.np, dtype=torch.float32, device=self.dev)
-        self.wb = torch.zeros(self.np, dtype=torch.int16, device=self.dev)
-        self.m = torch.zeros_like(self.w)
-        self.v = torch.zeros_like(self.w)
-        self.g = torch.zeros_like(self.w)
-        self.mean = torch.zeros(MLP_OUT, dtype=torch.float32, device=self.dev)
-        self.std = torch.ones(MLP_OUT, dtype=torch.float32, device=self.dev)
+        self.state = torch.empty(int(_lib.bp_surrogate_state_bytes()), dtype=torch.uint8, device=self.dev)
+        off = {a: int(_lib.bp_surrogate_state_offset(k)) for k, a in enumerate(SUR_ARRAYS)}
+
+        def view(a, n, dt, size):
+            return self.state[off[a]:off[a] + n * size].view(dt)
+        self.w = view("W", self.np, torch.float32, 4)
+        self.wb = view("WBF16", self.np, torch.int16, 2)
+        self.m = view("M", self.np, torch.float32, 4)
+        self.v = view("V", self.np, torch.float32, 4)
+        self.g = view("G", self.np, torch.float32, 4)
+        self.mean = view("MEAN", MLP_OUT, torch.float32, 4)
+        self.std = view("STD", MLP_OUT, torch.float32, 4)
         self.step = 0
-        self._init_weights(seed)
+        _check(_lib.bp_surrogate_init(_ptr(self.state), int(seed) & 0xFFFFFFFFFFFFFFFF, _stream()),
+               "bp_surrogate_init")
 
     # -- parameters -------------------------------------------------------
     def _layout(self):
@@ -52,39 +59,25 @@ class Surrogate:
         assert off == self.np
         return out
 
-    def _init_weights(self, seed):
-        """He-style initial weights from a seeded generator (an input to the method, like any data)."""
-        rng = np.random.default_rng(seed)
-        w = np.zeros(self.np, dtype=np.float32)
-        L = self._layout()
-        fan = {"W1": 3, "W2": 256, "W3": 256, "W4": 256}
-        for name in ("W1", "W2", "W3", "W4"):
-            off, n = L[name]
-            block = rng.normal(0.0, math.sqrt(2.0 / fan[name]), size=n).astype(np.float32)
-            if name == "W1":
-                block = block.reshape(256, MLP_IN)
-                block[:, 3:] = 0.0
-                block = block.ravel()
-            w[off:off + n] = block
-        self.w.copy_(torch.from_numpy(w))
-        _check(_lib.bp_mlp_to_bf16(self.np, _ptr(self.w), _ptr(self.wb), _stream()), "bp_mlp_to_bf16")
+    def to_blob(self) -> bytes:
+        """The surrogate as a flat host blob (bp_surrogate_save)."""
+        blob = (C.c_uint8 * int(_lib.bp_surrogate_blob_bytes()))()
+        _check(_lib.bp_surrogate_save(_ptr(self.state), self.step, blob, len(blob), _stream()), "bp_surrogate_save")
+        return bytes(blob)
 
-    def state_dict(self):
-        return {"w": self.w.cpu().numpy(), "mean": self.mean.cpu().numpy(), "std": self.std.cpu().numpy(),
-                "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(), "step": np.array(self.step)}
+    def from_blob(self, data: bytes):
+        buf = (C.c_uint8 * len(data)).from_buffer_copy(data)
+        step = C.c_int64(0)
+        _check(_lib.bp_surrogate_load(_ptr(self.state), buf, len(buf), C.byref(step), _stream()), "bp_surrogate_load")
+        self.step = step.value
 
     def save(self, path):
-        np.savez(path, **self.state_dict())
+        with open(path, "wb") as f:
+            f.write(self.to_blob())
 
     def load(self, path):
-        d = np.load(path, allow_pickle=False)
-        self.w.copy_(torch.from_numpy(d["w"]))
-        self.mean.copy_(torch.from_numpy(d["mean"]))
-        self.std.copy_(torch.from_numpy(d["std"]))
-        self.m.copy_(torch.from_numpy(d["m"]))
-        self.v.copy_(torch.from_numpy(d["v"]))
-        self.step = int(d["step"])
-        _check(_lib.bp_mlp_to_bf16(self.np, _ptr(self.w), _ptr(self.wb), _stream()), "bp_mlp_to_bf16")
+        with open(path, "rb") as f:
+            self.from_blob(f.read())
 
     # -- kernels ------------------------------------------------------------
     def features(self, M, c, z):
@@ -187,33 +180,37 @@ class Surrogate:
                                            _ptr(sol), _ptr(st), _ptr(qt), _ptr(meta), _stream()), "bp_surrogate_apply")
         return sol, st, qt, meta
 
-    def _fallback(self, cat_dev, st, paste):
-        """Halos the network does not cover (non-zero status) through the exact solve and tables."""
-        out = torch.nonzero(st != 0).flatten()
-        nout = int(out.numel())
-        if nout:
-            sub = {k: v.index_select(0, out).contiguous() for k, v in cat_dev.items()}
-            s2, st2 = icm_solve(self.params, sub["M"], sub["c"], sub["z"])
-            tb2, mt2 = profile_tables(self.params, s2, st2)
-            paste(sub, s2, st2, tb2, mt2)
-        return nout
+    def fit_exact(self, M, c, z, steps, batch=4096, lr=2e-3, lr_end=1e-5, seed=0, ws: Workspace | None = None):
+        """Training in one library call (bp_surrogate_fit): exact solves, tables, targets and statistics of the
+        n halos (M, c, z device tensors), then Adam."""
+        ws = ws or _ws_for(self.dev)
+        _with_workspace(_lib.bp_surrogate_fit, "bp_surrogate_fit", ws,
+                        (C.byref(self.params), _ptr(self.state), M.numel(), _ptr(M), _ptr(c), _ptr(z), int(steps),
+                         int(batch), float(lr), float(lr_end), int(seed) & 0xFFFFFFFFFFFFFFFF, self.step))
+        self.step += int(steps)
 
     def paste_healpix(self, cat_dev, nside, y_map, b_map, ws: Workspace | None = None, tables="exact", comp=None):
-        """Surrogate HP paste onto HEALPix RING maps, exact fallback for halos outside the training domain.
-        cat_dev holds M, c, z, theta, phi, v_los; comp = (y_comp, b_comp) carries the Kahan compensation."""
-        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"], tables)
-        hp_paste_healpix_q(self.params, nside, cat_dev["theta"], cat_dev["phi"], cat_dev["v_los"], sol, st, qt, meta,
-                           y_map, b_map, ws, comp)
-        del sol, qt, meta
-        return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_healpix(
-            self.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map, ws, comp))
+        """Surrogate HP paste onto HEALPix RING maps (bp_surrogate_paste_healpix: routing, the fallback's exact
+        solve and the deposit on the device).  cat_dev holds M, c, z, theta, phi, v_los; comp = (y_comp, b_comp)
+        carries the Kahan compensation.  Returns the number of halos routed to the exact solve."""
+        ws = ws or _ws_for(y_map.device)
+        nout = C.c_int64(0)
+        d = cat_dev
+        _with_workspace(_lib.bp_surrogate_paste_healpix, "bp_surrogate_paste_healpix", ws,
+                        (C.byref(self.params), _ptr(self.state), SUR_TABLES[tables], int(nside), d["M"].numel(),
+                         _ptr(d["M"]), _ptr(d["c"]), _ptr(d["z"]), _ptr(d["theta"]), _ptr(d["phi"]), _ptr(d["v_los"]),
+                         _ptr(y_map), _ptr(b_map), *_comp_ptrs(comp, y_map)), tail=(C.byref(nout),))
+        return nout.value
 
     def paste_flat(self, cat_dev, npix, pix_rad, y_map, b_map, ws: Workspace | None = None, tables="exact", comp=None):
-        """Surrogate HP paste with exact fallback for halos outside the training domain."""
-        sol, st, qt, meta = self.infer(cat_dev["M"], cat_dev["c"], cat_dev["z"], tables)
-        hp_paste_flat_q(self.params, npix, pix_rad, cat_dev["theta_x"], cat_dev["theta_y"], cat_dev["v_los"], sol,
-                        st, qt, meta, y_map, b_map, ws, comp)
-        del sol, qt, meta
-        return self._fallback(cat_dev, st, lambda sub, s2, st2, tb2, mt2: hp_paste_flat(
-            self.params, npix, pix_rad, sub["theta_x"], sub["theta_y"], sub["v_los"], s2, st2, tb2, mt2, y_map, b_map,
-            ws, comp))
+        """Surrogate HP paste onto a flat map (bp_surrogate_paste_flat).  Returns the number of halos routed to
+        the exact solve."""
+        ws = ws or _ws_for(y_map.device)
+        nout = C.c_int64(0)
+        d = cat_dev
+        _with_workspace(_lib.bp_surrogate_paste_flat, "bp_surrogate_paste_flat", ws,
+                        (C.byref(self.params), _ptr(self.state), SUR_TABLES[tables], int(npix), float(pix_rad),
+                         d["M"].numel(), _ptr(d["M"]), _ptr(d["c"]), _ptr(d["z"]), _ptr(d["theta_x"]),
+                         _ptr(d["theta_y"]), _ptr(d["v_los"]), _ptr(y_map), _ptr(b_map), *_comp_ptrs(comp, y_map)),
+                        tail=(C.byref(nout),))
+        return nout.value

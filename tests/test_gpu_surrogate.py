@@ -365,15 +365,61 @@ def test_surrogate_paste_vs_exact_and_fallback(bp, trained):
         assert Yerr < 1e-3
         if tables == "exact":
             assert ry.max() <= 1e-3 and rb.max() <= 1e-3    # the per-pixel bar of the surrogate path (R24)
-    # fallback halos alone reproduce the exact map bit for bit
-    sub = {k: v[:50] for k, v in cat.items()}
-    ye2, _, _, _ = bp.hp_flat_map(S.params, sub, npix, pix)
-    ys2 = torch.zeros_like(ye2)
-    bs2 = torch.zeros_like(ye2)
-    S.paste_flat({k: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous() for k, v in sub.items()},
-                 npix, pix, ys2, bs2)
+    # the routed halos go through the exact scan solve and exact q-tables: bit for bit that composition
+    sub = {k: v[:50].contiguous() for k, v in dev.items()}
+    ys2, bs2, yr, br = (torch.zeros((npix, npix), dtype=torch.float32, device="cuda") for _ in range(4))
+    assert S.paste_flat(sub, npix, pix, ys2, bs2) == 50
+    _routed_reference(bp, S.params, sub, lambda s2, st2, qt, mt: bp.hp_paste_flat_q(
+        S.params, npix, pix, sub["theta_x"], sub["theta_y"], sub["v_los"], s2, st2, qt, mt, yr, br))
     torch.cuda.synchronize()
-    assert torch.equal(ys2, ye2)
+    assert torch.equal(ys2, yr) and torch.equal(bs2, br)
+
+
+def _routed_reference(bp, params, sub, paste):
+    """What the device routing does for halos outside the training domain, written out from the public
+    calls: the exact scan solve, exact q-tables (a halo with several roots keeps the first) and the q-table
+    deposit."""
+    import torch
+    s2, st2 = bp.icm_solve(params, sub["M"], sub["c"], sub["z"])
+    st2 = torch.where(st2 == bp.S_MULTI_ROOT, torch.zeros_like(st2), st2)
+    qt = torch.zeros((st2.numel(), 128), dtype=torch.float32, device="cuda")
+    mt = torch.zeros((bp.META_NFIELDS, st2.numel()), dtype=torch.float32, device="cuda")
+    bp._check(bp._lib.bp_surrogate_qtables_exact(ctypes.byref(params), st2.numel(), bp._ptr(s2), bp._ptr(st2),
+                                                 bp._ptr(qt), bp._ptr(mt), bp._stream()), "qtables")
+    paste(s2, st2, qt, mt)
+
+
+def test_surrogate_save_load_and_one_call_fit(bp):
+    """The state round-trips through the host blob; a foreign blob is refused; the one-call fit
+    (bp_surrogate_fit) trains the same network bit for bit as the step-by-step calls."""
+    import torch
+
+    from paper_2201_02632_amd.surrogate import Surrogate
+    from paper_2201_02632_amd.synth import surrogate_training
+    tr = surrogate_training(5000, seed=8)
+    A, B = Surrogate(seed=3), Surrogate(seed=3)
+    assert torch.equal(A.w, B.w)
+    x, t = A.training_set(tr["M"], tr["c"], tr["z"])
+    A.set_stats(t)
+    A.fit(x, t, steps=300, batch=512, lr=2e-3, lr_end=1e-4)
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    B.fit_exact(T(tr["M"]), T(tr["c"]), T(tr["z"]), steps=300, batch=512, lr=2e-3, lr_end=1e-4)
+    torch.cuda.synchronize()
+    assert torch.equal(A.w, B.w) and torch.equal(A.mean, B.mean) and torch.equal(A.wb, B.wb) and A.step == B.step
+    blob = A.to_blob()
+    C2 = Surrogate(seed=99)
+    assert not torch.equal(C2.w, A.w)
+    C2.from_blob(blob)
+    torch.cuda.synchronize()
+    for k in ("w", "wb", "m", "v", "mean", "std"):
+        assert torch.equal(getattr(C2, k), getattr(A, k)), k
+    assert C2.step == A.step == 300
+    bad = bytearray(blob)
+    bad[0] ^= 1
+    with pytest.raises(bp.BPError):
+        C2.from_blob(bytes(bad))
+    with pytest.raises(bp.BPError):
+        C2.from_blob(blob[:-4])
 
 
 def test_surrogate_flat_4096_map(bp, trained):
@@ -438,15 +484,11 @@ def test_surrogate_healpix_vs_exact_and_fallback(bp, trained):
         assert Yerr < 1e-3
         if tables == "exact":
             assert ry.max() <= 1e-3 and rb.max() <= 1e-3
-    # the fallback halos alone reproduce the exact map bit for bit
+    # the routed halos alone: bit for bit the exact scan solve + exact q-tables + q-table deposit
     sub = {k: v[:40].contiguous() for k, v in dev.items()}
-    s2, st2 = bp.icm_solve(S.params, sub["M"], sub["c"], sub["z"])
-    t2, m2 = bp.profile_tables(S.params, s2, st2)
-    ye2 = torch.zeros(npx, dtype=torch.float32, device="cuda")
-    be2 = torch.zeros_like(ye2)
-    bp.hp_paste_healpix(S.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, t2, m2, ye2, be2)
-    ys2 = torch.zeros_like(ye2)
-    bs2 = torch.zeros_like(ye2)
-    S.paste_healpix(sub, nside, ys2, bs2)
+    ys2, bs2, yr, br = (torch.zeros(npx, dtype=torch.float32, device="cuda") for _ in range(4))
+    assert S.paste_healpix(sub, nside, ys2, bs2) == 40
+    _routed_reference(bp, S.params, sub, lambda s2, st2, qt, mt: bp.hp_paste_healpix_q(
+        S.params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, qt, mt, yr, br))
     torch.cuda.synchronize()
-    assert torch.equal(ys2, ye2) and torch.equal(bs2, be2)
+    assert torch.equal(ys2, yr) and torch.equal(bs2, br)
