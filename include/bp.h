@@ -198,6 +198,22 @@ int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n
                      float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
                      size_t *ws_needed, void *stream);
 
+/* Allocation-free variant of bp_hp_paste_flat, for callers that cannot allocate device memory or
+ * size a workspace (serving loops, harnesses that forbid allocation).  Same arguments, layouts,
+ * results and errors as bp_hp_paste_flat (the same kernels run), without ws / ws_bytes: the call works
+ * in a fixed array of bp_hp_paste_flat_noalloc_max_bytes() bytes (64 MiB) that the library holds on
+ * each GPU it runs on, for the life of the process, and allocates nothing.  A problem whose workspace
+ * exceeds that (about 184 B per halo plus 16 B per (tile, halo) pair and the sort's scratch) is refused
+ * with BP_E_WORKSPACE before the maps are touched; *scratch_needed (nullable) receives the bytes it would
+ * need.  Like bp_hp_paste_flat it synchronises the stream once.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (several host threads or streams) race and must be
+ * serialised by the caller. */
+size_t bp_hp_paste_flat_noalloc_max_bytes(void);
+int bp_hp_paste_flat_noalloc(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                             const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                             const float *tables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                             float *b_comp, size_t *scratch_needed, void *stream);
+
 /* ------------------------------------------------------- HEALPix (K9, K4) */
 /* HEALPix RING pixel index of each direction (Gorski et al. 2005).
  *   theta: colatitude in [0, pi]; phi: longitude (any real, taken mod 2 pi).

@@ -70,6 +70,9 @@ _SIGS = {
     "bp_profile_tables": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                    _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_hp_paste_flat_noalloc_max_bytes": (C.c_size_t, []),
+    "bp_hp_paste_flat_noalloc": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                           _VP, _VP, _VP, _VP, C.POINTER(C.c_size_t), _VP]),
     "bp_healpix_ang2pix_ring": (C.c_int, [C.c_int64, C.c_int64, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_healpix": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                       _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),

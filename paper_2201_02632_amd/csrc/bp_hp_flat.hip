@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "bp_device.hpp"
 #include "bp_internal.hpp"
 #include "bp_footprint.hpp"
@@ -331,7 +333,8 @@ static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int
     unsigned long long *total = A.take<unsigned long long>(1);
     void *scan_ws = (char *)ws + A.used;
     A.used += scan_ws_bytes(n + 1);
-    if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
+    // cleared with a fill kernel (a memset node misbehaves under graph replay on this target)
+    if (fill_u32((uint32_t *)total, 0u, 2, s)) return BP_E_HIP;
     if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_flat_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, Gm, n, theta_x, theta_y, v_los, sol, status,
@@ -398,4 +401,48 @@ extern "C" int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_r
                                   float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
     return paste_flat_impl<true>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, qtables, meta, y_map,
                                  b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream);
+}
+
+// ------------------------------------------------------ allocation-free variant --
+// The workspace of bp_hp_paste_flat_noalloc: a fixed device array, one copy per GPU for the life of the
+// process.  Host code never uses this symbol as an address (it names a host-side stand-in): the device
+// address comes from hipGetSymbolAddress, once per device, and is what the kernels receive.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (looked up on its first use there)
+int scratch_for_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BP_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BP_E_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BP_OK;
+}
+}  // namespace
+
+extern "C" size_t bp_hp_paste_flat_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" int bp_hp_paste_flat_noalloc(const bp_params *p, int32_t npix, double pix_rad, int64_t n,
+                                        const double *theta_x, const double *theta_y, const double *v_los,
+                                        const double *sol, const int32_t *status, const float *tables,
+                                        const float *meta, float *y_map, float *b_map, float *y_comp, float *b_comp,
+                                        size_t *scratch_needed, void *stream) {
+    void *ptr = nullptr;
+    int e = scratch_for_current_device(&ptr);
+    if (e) return e;
+    size_t need = 0;
+    e = paste_flat_impl<false>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, tables, meta, y_map, b_map,
+                               y_comp, b_comp, ptr, kScratchBytes, &need, stream);
+    if (scratch_needed) *scratch_needed = need;
+    return e;
 }

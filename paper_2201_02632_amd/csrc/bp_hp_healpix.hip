@@ -425,7 +425,7 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     int e = scan_exclusive_u32(btiles, btile0, nbands + 1, scan_ws, s);
     if (e) return e;
     hipLaunchKernelGGL(k_ring_table, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, rtab);
-    if (hipMemsetAsync(total, 0, sizeof(unsigned long long), s) != hipSuccess) return BP_E_HIP;
+    if (fill_u32((uint32_t *)total, 0u, 2, s)) return BP_E_HIP;   // a fill kernel rather than a memset node
     if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_hpx_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status,
