@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     steps must be reproducible)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-               "-o", LIB + ".tmp", SRC, "-lm"]
+               "-o", LIB + ".tmp", SRC, "-lquadmath", "-lm"]
         subprocess.check_call(cmd)
         os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -409,3 +409,39 @@ def pp_flat(p, halos, parts, M_p, npix, pix_rad, k=32):
     ay, ab = pp_amplitudes(p, halos, z, parts["v_los"], parts["halo_id"], parts["r_i"], M_p, pix_rad)
     y, b = pp_deposit(tx, ty, H, ay, ab, npix, pix_rad)
     return y, b, h, H, ay, ab
+
+
+def _solve_chunk(args):
+    """Worker of solve_halos_parallel: plain tuples cross the process boundary."""
+    pd, M, c, z = args
+    p = default_params(**pd)
+    out = []
+    for k in range(len(M)):
+        h = solve_halo(p, M[k], c[k], z[k])
+        out.append(tuple(getattr(h, f) for f in HALO_FIELDS) + (h.status, h.n_sign_changes))
+    return out
+
+
+def solve_halos_parallel(p, M, c, z, workers=None):
+    """solve_halos over a pool of fresh single-threaded processes (spawned, so a caller that has
+    initialised a GPU is never forked).  Returns the same ctypes array of Halo as solve_halos."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    M, c, z = _f64(M), _f64(c), _f64(z)
+    n = len(M)
+    workers = workers or min(16, os.cpu_count() or 1)
+    if n < 64 or workers <= 1:
+        return solve_halos(p, M, c, z)
+    pd = {f: getattr(p, f) for f, _ in Params._fields_ if f != "pad_"}
+    chunks = [(pd, M[a:a + 256], c[a:a + 256], z[a:a + 256]) for a in range(0, n, 256)]
+    out = (Halo * n)()
+    k = 0
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        for res in ex.map(_solve_chunk, chunks):
+            for vals in res:
+                h = out[k]
+                for f, v in zip(HALO_FIELDS, vals[:len(HALO_FIELDS)]):
+                    setattr(h, f, v)
+                h.status, h.n_sign_changes = vals[-2], vals[-1]
+                k += 1
+    return out

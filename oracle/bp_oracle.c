@@ -24,6 +24,7 @@
  * value.
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -885,10 +886,16 @@ void orc_hp_flat_pixels(const orc_params *p, int64_t n, const orc_halo *halos, c
 /* Floating-point steps are kept in a fixed order (no contraction) so that   */
 /* the integer result is reproducible bit for bit.                           */
 /* ======================================================================== */
+/* Reading: the pixel of a direction is the one its cos(theta) and sin(theta), rounded correctly to
+ * FP64, select.  Next to a pixel edge the last bit of either decides the index, and libm's cos and sin
+ * are not always correctly rounded; here both are evaluated in quad precision and rounded once. */
+static double cos_cr(double t) { return (double)cosq((__float128)t); }
+static double sin_cr(double t) { return (double)sinq((__float128)t); }
+
 int64_t orc_ang2pix_ring(int64_t nside, double theta, double phi)
 {
     const double halfpi = 1.5707963267948966;
-    double z = cos(theta), za = fabs(z);
+    double z = cos_cr(theta), za = fabs(z);
     double tt = phi / halfpi;                     /* in [0,4) for phi in [0,2pi) */
     tt = tt - 4.0 * floor(tt / 4.0);
     if (tt >= 4.0) tt = 0.0;
@@ -905,7 +912,7 @@ int64_t orc_ang2pix_ring(int64_t nside, double theta, double phi)
         return 2 * N * (N - 1) + (ir - 1) * 4 * N + ip;
     }
     double tf = tt - floor(tt);
-    double s = sin(theta);
+    double s = sin_cr(theta);
     double tmp = (double)N * (s * sqrt(3.0 / (1.0 + za)));   /* = N sqrt(3(1-|z|)) */
     int64_t jp = (int64_t)floor(tf * tmp);
     int64_t jm = (int64_t)floor((1.0 - tf) * tmp);

@@ -35,7 +35,37 @@ def reach_bound_rad(M, z, om=0.3):
     return 3.0 * r500_max / DA_low
 
 
+def _ring_pixels(cx, cy, R, npix, frac_lo, frac_hi, limit, rng):
+    """Pixels (i, j) whose centre lies at a distance r from (cx, cy) (pixel units) with
+    frac_lo <= r / R - 1 < frac_hi, found by walking the rows the circle crosses; at most `limit` of them,
+    drawn at random."""
+    out = []
+    for j in range(max(0, int(cy - R) - 2), min(npix, int(cy + R) + 3)):
+        dy = j + 0.5 - cy
+        w2 = R * R - dy * dy
+        if w2 < -4 * R:
+            continue
+        w = math.sqrt(max(w2, 0.0))
+        for side in (-1, 1):
+            i0 = int(math.floor(cx + side * w - 0.5))
+            for i in range(i0 - 2, i0 + 3):
+                if 0 <= i < npix:
+                    r = math.hypot(i + 0.5 - cx, dy)
+                    if frac_lo <= r / R - 1 < frac_hi:
+                        out.append((i, j))
+    out = sorted(set(out))
+    if len(out) > limit:
+        out = [out[k] for k in rng.choice(len(out), limit, replace=False)]
+    return out
+
+
 def test_hp_flat_fullsize_sampled_pixels(bp, orc):
+    """The 5e5-halo, 4096^2 benchmark map (the benchmark's call) against the oracle on 1,000 pixels in ten
+    random 10x10 patches, plus pixels the plan of the deposit treats specially, at the footprints of the
+    five largest halos: inside the band next to the footprint edge where membership is re-decided in FP64
+    (reading R23), just inside and just outside that edge, and on either side of r_a where the zone of the
+    projection table changes.  Each pixel is recomputed by the oracle from every halo within a reach bound
+    that does not depend on the GPU's solution."""
     import torch
 
     from paper_2201_02632_amd.synth import hp_flat_large, subsample
@@ -52,38 +82,57 @@ def test_hp_flat_fullsize_sampled_pixels(bp, orc):
     torch.cuda.synchronize()
     y = y.cpu().numpy()
     b = b.cpu().numpy()
+    solc = sol.cpu().numpy()
     print(f"pasted {len(cat['M'])} halos onto {npix}^2 pixels", flush=True)
 
     rng = np.random.default_rng(20)
-    pi = list(rng.integers(0, npix, 6))
-    pj = list(rng.integers(0, npix, 6))
-    big = int(np.argmax(cat["M"]))                               # the brightest footprint's centre
-    pi += [int(cat["theta_x"][big] / pix), 0, npix - 1]
-    pj += [int(cat["theta_y"][big] / pix), 0, npix // 2]
-    pi = np.array(pi, dtype=np.int32)
-    pj = np.array(pj, dtype=np.int32)
+    pix_list, kinds = [], []
+    for _ in range(10):                                            # ten 10x10 patches
+        i0, j0 = rng.integers(0, npix - 10, 2)
+        for dj in range(10):
+            for di in range(10):
+                pix_list.append((int(i0 + di), int(j0 + dj)))
+                kinds.append("patch")
+    # special pixels at the five largest footprints (located with the GPU's geometry: only where to look)
+    Rpx = solc[bp.SOL["RT"]] / solc[bp.SOL["DA"]] / pix
+    for hidx in np.argsort(Rpx)[::-1][:5]:
+        cx, cy, R = cat["theta_x"][hidx] / pix, cat["theta_y"][hidx] / pix, Rpx[hidx]
+        for (lo, hi, lim, kind) in ((-2e-6, 2e-6, 12, "edge band"), (-3e-4, -2e-6, 4, "edge inside"),
+                                    (2e-6, 3e-4, 4, "edge outside")):
+            for q in _ring_pixels(cx, cy, R, npix, lo, hi, lim, rng):
+                pix_list.append(q); kinds.append(kind)
+        ra = min(solc[bp.SOL["RVIR"], hidx], solc[bp.SOL["RF"], hidx]) / solc[bp.SOL["DA"], hidx] / pix
+        if ra < 0.999 * R:
+            for (lo, hi, kind) in ((-1e-3, 0.0, "r_a inside"), (0.0, 1e-3, "r_a outside")):
+                for q in _ring_pixels(cx, cy, ra, npix, lo, hi, 4, rng):
+                    pix_list.append(q); kinds.append(kind)
+    pi = np.array([q[0] for q in pix_list], dtype=np.int32)
+    pj = np.array([q[1] for q in pix_list], dtype=np.int32)
+    kinds = np.array(kinds)
 
     bound = reach_bound_rad(cat["M"], cat["z"])
     cand = np.zeros(len(cat["M"]), dtype=bool)
-    for i, j in zip(pi, pj):
+    for i, j in set(zip(pi.tolist(), pj.tolist())):
         dx = (i + 0.5) * pix - cat["theta_x"]
         dy = (j + 0.5) * pix - cat["theta_y"]
         cand |= dx * dx + dy * dy < bound * bound
     idx = np.nonzero(cand)[0]
-    print(f"oracle: {len(idx)} candidate halos for {len(pi)} pixels", flush=True)
+    print(f"oracle: {len(idx)} candidate halos for {len(pi)} pixels "
+          f"({', '.join(f'{k}: {(kinds == k).sum()}' for k in dict.fromkeys(kinds))})", flush=True)
     sub = subsample(cat, idx)
     p = orc.default_params()
-    halos = orc.solve_halos(p, sub["M"], sub["c"], sub["z"])
+    halos = orc.solve_halos_parallel(p, sub["M"], sub["c"], sub["z"])
     oy, ob = orc.hp_flat_pixels(p, halos, sub, pix, pi, pj)
     _, obabs = orc.hp_flat_pixels(p, halos, dict(sub, v_los=np.abs(sub["v_los"])), pix, pi, pj)
     gy = y[pj, pi].astype(np.float64)
     gb = b[pj, pi].astype(np.float64)
     ey = np.abs(gy - oy) / (np.abs(oy) + 1e-6 * np.abs(oy).max())
     eb = np.abs(gb - ob) / (obabs + 1e-6 * obabs.max())
-    print("pixel  y_gpu  y_oracle  rel_err_y  rel_err_b")
-    for k in range(len(pi)):
-        print(f"({pi[k]},{pj[k]}) {gy[k]:.6e} {oy[k]:.6e} {ey[k]:.2e} {eb[k]:.2e}")
-    assert np.all(oy > 0), "every sampled pixel should lie inside some footprint"
+    for k in dict.fromkeys(kinds):
+        m = kinds == k
+        print(f"{k:13s} {m.sum():5d} pixels: max rel err y {ey[m].max():.2e} b {eb[m].max():.2e}")
+    assert len(pi) >= 1000 and (kinds == "edge band").sum() >= 10
+    assert np.all(oy[kinds == "patch"] >= 0)
     assert ey.max() < 1e-5 and eb.max() < 1e-5
 
 
@@ -165,6 +214,105 @@ def test_pp_fullsize_sampled_smoothing_lengths(bp, orc):
         print(f"box L={L}: N_eff = 64 smoothing h {hoe.min():.3g}-{hoe.max():.3g} Mpc/h, max rel err {erre:.2e}",
               flush=True)
         assert np.all(np.isfinite(hge)) and erre < 2e-6
+
+
+def test_pp_fullsize_sampled_pixels(bp, orc):
+    """The PP maps of the 2e8-particle light cone (the benchmark's draws and calls: 32-NN smoothing lengths,
+    then the paste), checked at full size.
+    y: 200 pixels in two 10x10 patches, on the most massive halo and on a random halo above 1e14 Msun/h, are
+    recomputed from every halo particle whose footprint can reach them (field gas carries no y here, Eq.
+    field_y).  Each such particle's smoothing length is the 32nd-neighbour distance among all particles
+    (halo and field) within a comoving box around the candidates, found with scipy's cKDTree (the library
+    routine the oracle's brute-force search is pinned to), positions from the oracle's chi(z); its amplitude
+    is the oracle's (Sec. 3.4, from the oracle's own solution of its halo) and its weights the oracle's
+    integrated kernel (Eq. integrated_kernel).  The GPU's smoothing lengths only choose the candidates: a
+    particle is one while its 2H square with twice the GPU's H touches the patch, and each candidate's
+    own footprint must stay inside that bound.
+    b: field particles (b only) reach across degrees, so b is checked by an exact property at full size: the
+    same paste with every velocity negated gives -b bit for bit and leaves y unchanged."""
+    import torch
+    from scipy.interpolate import CubicSpline
+    from scipy.spatial import cKDTree
+
+    from paper_2201_02632_amd.synth import pp_large_device
+    params = bp.default_params()
+    halos, parts, M_p, npix, pix = pp_large_device(device="cuda")
+    th = {k: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous() for k, v in halos.items()}
+    sol, st = bp.icm_solve(params, th["M"], th["c"], th["z"])
+    ws = bp.Workspace(torch.device("cuda"))
+    h = bp.pp_smoothing_length(params, parts["theta_x"], parts["theta_y"], parts["z"], 32, 0.0, ws=ws)
+    y = torch.zeros((npix, npix), dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(y)
+    bp.pp_paste_flat(params, npix, pix, parts, h, M_p, sol, st, y, b, ws=ws)
+    y2, b2 = torch.zeros_like(y), torch.zeros_like(y)
+    bp.pp_paste_flat(params, npix, pix, dict(parts, v_los=-parts["v_los"]), h, M_p, sol, st, y2, b2, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(y2, y) and torch.equal(b2, -b)
+    print(f"{parts['z'].numel()} particles pasted onto {npix}^2 pixels; b(-v) = -b(v) bit for bit", flush=True)
+    y = y.cpu().numpy()
+    del y2, b2, b, sol, st, ws
+    # the oracle's chi(z) through a cubic spline on a fine grid (interpolation error ~1e-12 relative)
+    p = orc.default_params()
+    zg = np.linspace(0.0, 1.6, 16001)
+    chi_of = CubicSpline(zg, [orc.chi(p, float(v)) for v in zg])
+    zz, chit = _chi_table()
+    zt, ct = torch.as_tensor(zz, device="cuda"), torch.as_tensor(chit, device="cuda")
+    zd = parts["z"].double()
+    k = torch.clamp(torch.searchsorted(zt, zd), 1, len(zz) - 1)
+    chi_d = ct[k - 1] + (ct[k] - ct[k - 1]) * (zd - zt[k - 1]) / (zt[k] - zt[k - 1])   # selection only
+    Hs = 2.0 * h.double() / chi_d + pix
+    txd, tyd = parts["theta_x"].double(), parts["theta_y"].double()
+    rng = np.random.default_rng(31)
+    big = int(np.argmax(halos["M"]))
+    heavy = np.nonzero(halos["M"] > 1e14)[0]
+    other = int(heavy[rng.integers(0, len(heavy))])
+    worst = 0.0
+    for hidx in (big, other):
+        i0 = int(halos["theta_x"][hidx] / pix) - 5
+        j0 = int(halos["theta_y"][hidx] / pix) - 5
+        xlo, xhi, ylo, yhi = i0 * pix, (i0 + 10) * pix, j0 * pix, (j0 + 10) * pix
+        mc = (parts["halo_id"] >= 0) & (txd + Hs > xlo) & (txd - Hs < xhi) & (tyd + Hs > ylo) & (tyd - Hs < yhi) \
+            & torch.isfinite(Hs)
+        cand = torch.nonzero(mc).flatten()
+        # comoving box around the candidates, widened by the largest neighbour distance allowed
+        cx, cy, cz = (chi_d * txd)[cand], (chi_d * tyd)[cand], chi_d[cand]
+        margin = max(4.0 * float(h[cand].max()), 1.0)
+        lo = [float(v.min()) - margin for v in (cx, cy, cz)]
+        hi = [float(v.max()) + margin for v in (cx, cy, cz)]
+        X, Y, Z = chi_d * txd, chi_d * tyd, chi_d
+        mb = (X > lo[0]) & (X < hi[0]) & (Y > lo[1]) & (Y < hi[1]) & (Z > lo[2]) & (Z < hi[2])
+        nbr = torch.nonzero(mb).flatten()
+        cand_h, nbr_h = cand.cpu().numpy(), nbr.cpu().numpy()
+        hp = {kk: v[nbr].cpu().numpy() for kk, v in (("tx", parts["theta_x"]), ("ty", parts["theta_y"]), ("z", parts["z"]))}
+        chi_n = chi_of(hp["z"].astype(np.float64))
+        P = np.stack([chi_n * hp["tx"].astype(np.float64), chi_n * hp["ty"].astype(np.float64), chi_n], 1)
+        pos = np.searchsorted(nbr_h, cand_h)
+        assert np.all(nbr_h[pos] == cand_h)
+        dist, _ = cKDTree(P).query(P[pos], k=33, workers=16)      # itself, then its 32 nearest others
+        ho = dist[:, 32]
+        # every neighbour the search could need lies in the box
+        edge = np.min(np.stack([P[pos] - np.array(lo), np.array(hi) - P[pos]], 0), axis=(0, 2))
+        assert np.all(ho < edge), "neighbour box too small"
+        Ho = ho / chi_n[pos]
+        assert np.all(Ho < Hs[cand].cpu().numpy()), "a candidate's footprint leaves its selection bound"
+        hid = parts["halo_id"][cand].cpu().numpy()
+        used = np.unique(hid)
+        solved = orc.solve_halos_parallel(p, halos["M"][used], halos["c"][used], halos["z"][used])
+        remap = np.full(len(halos["M"]), -1, dtype=np.int64)
+        remap[used] = np.arange(len(used))
+        zc = parts["z"][cand].cpu().numpy()
+        ay, _ = orc.pp_amplitudes(p, solved, zc, parts["v_los"][cand].cpu().numpy(), remap[hid].astype(np.int32),
+                                  parts["r_i"][cand].cpu().numpy(), M_p, pix)
+        oy, _ = orc.pp_deposit(hp["tx"][pos], hp["ty"][pos], Ho, ay, np.zeros_like(ay), npix, pix)
+        sl = np.s_[j0:j0 + 10, i0:i0 + 10]
+        gy, oy = y[sl].astype(np.float64), oy[sl]
+        ey = np.abs(gy - oy) / (np.abs(oy) + 1e-6 * np.abs(oy).max())
+        worst = max(worst, ey.max())
+        print(f"patch on halo {hidx} (M {halos['M'][hidx]:.2e}): {len(cand_h)} candidate particles of {len(used)} "
+              f"halos, {len(nbr_h)} in the neighbour box, h {ho.min():.3g}-{ho.max():.3g} Mpc/h; "
+              f"max rel err y {ey.max():.2e}", flush=True)
+        assert oy.min() > 0
+    assert worst < 1e-5
 
 
 def test_hp_healpix_fullsize_sampled_pixels(bp, orc):

@@ -297,6 +297,70 @@ def test_ang2pix_bit_exact(bp, orc):
         bp.healpix_ang2pix_ring(0, T(th), T(ph))
 
 
+def _ulp_steps(x, k):
+    """x moved by k units in the last place (k may be negative)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = x.copy()
+    for _ in range(abs(k)):
+        out = np.nextafter(out, np.inf if k > 0 else -np.inf)
+    return out
+
+
+def test_ang2pix_boundary_directions_nside_8192(bp, orc):
+    """Directions within +-4 ulp of every boundary family of the RING scheme at N_side 8192 (Gorski et al.
+    2005): the cap/belt transition |z| = 2/3; the ascending and descending pixel edges of the belt
+    (N(1/2 + t) -+ (3/4) N z an integer, t = phi / (pi/2)); the edges of the polar caps (t' N sqrt(3(1 - |z|))
+    an integer, t' = t mod 1), in colatitude and in longitude.  The integer results depend on the FP64 cos
+    and sin of the colatitude on both sides, so this is where the device's and the host's libm would part."""
+    import torch
+    N = 8192
+    rng = np.random.default_rng(11)
+    th_b, ph_b = [], []
+    m = 300
+    # cap / belt transition
+    tt = rng.uniform(0, 4, m)
+    th_b += [np.full(m // 2, math.acos(2 / 3)), np.full(m - m // 2, math.acos(-2 / 3))]
+    ph_b += [tt * math.pi / 2]
+    # belt edges in colatitude: z = (N (1/2 + t) - k) / (3N/4) and z = (k - N (1/2 + t)) / (3N/4)
+    tt = rng.uniform(0, 4, m)
+    zb = (N * (0.5 + tt) - rng.integers(0, 5 * N, m)) / (0.75 * N)
+    ok = np.abs(zb) < 2 / 3
+    th_b.append(np.arccos(zb[ok])); ph_b.append(tt[ok] * math.pi / 2)
+    tt = rng.uniform(0, 4, m)
+    zb = (rng.integers(0, 5 * N, m) - N * (0.5 + tt)) / (0.75 * N)
+    ok = np.abs(zb) < 2 / 3
+    th_b.append(np.arccos(zb[ok])); ph_b.append(tt[ok] * math.pi / 2)
+    # cap edges in colatitude: N sqrt(3 (1 - |z|)) t' = k  ->  |z| = 1 - (k / (N t'))^2 / 3
+    tf = rng.uniform(0.01, 0.99, m)
+    kk = rng.integers(1, N, m)
+    za = 1 - (kk / (N * tf)) ** 2 / 3
+    ok = za > 2 / 3
+    north = rng.random(m) < 0.5
+    thc = np.where(north, np.arccos(za.clip(-1, 1)), math.pi - np.arccos(za.clip(-1, 1)))
+    th_b.append(thc[ok]); ph_b.append((rng.integers(0, 4, m) + tf)[ok] * math.pi / 2)
+    # belt edges in longitude: t = (k + (3/4) N z) / N - 1/2, and cap edges in longitude: t = k / ring
+    zr = rng.uniform(-2 / 3, 2 / 3, m)
+    tb = ((rng.integers(0, 5 * N, m) + 0.75 * N * zr) / N - 0.5) % 4
+    th_lon = [np.arccos(zr)]
+    ph_lon = [tb * math.pi / 2]
+    ring = rng.integers(1, N, m)
+    zc = 1 - (ring / N) ** 2 / 3 - 1e-9
+    th_lon.append(np.arccos(zc)); ph_lon.append((rng.integers(0, 4 * ring) / ring) * math.pi / 2)
+    th_b, ph_b = np.concatenate(th_b), np.concatenate(ph_b)
+    th_l, ph_l = np.concatenate(th_lon), np.concatenate(ph_lon)
+    th = np.concatenate([_ulp_steps(th_b, k) for k in range(-4, 5)] + [np.tile(th_l, 9)])
+    ph = np.concatenate([np.tile(ph_b, 9)] + [_ulp_steps(ph_l, k) for k in range(-4, 5)])
+    keep = (th >= 0) & (th <= math.pi) & np.isfinite(ph)
+    th, ph = th[keep], ph[keep]
+    got = bp.healpix_ang2pix_ring(N, T(th), T(ph)).cpu().numpy()
+    exp = orc.ang2pix_ring(N, th, ph)
+    bad = np.nonzero(got != exp)[0]
+    print(f"{len(th)} boundary directions at N_side {N}: {len(bad)} differ")
+    for k in bad[:10]:
+        print(f"  theta {th[k]!r} phi {ph[k]!r}: gpu {got[k]} oracle {exp[k]}")
+    assert len(bad) == 0
+
+
 def test_workspace_protocol(bp):
     import ctypes as C
     import torch

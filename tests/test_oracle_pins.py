@@ -555,3 +555,15 @@ def test_spectrum_white_noise_and_mode_counts():
     assert ok.sum() >= 5
     assert np.all(np.abs(cnt[ok] - expect[ok]) < 4 * np.sqrt(t[1:][ok]) + 4)
     assert np.all((lb[cnt > 0] >= edges[:-1][cnt > 0]) & (lb[cnt > 0] < edges[1:][cnt > 0]))
+
+
+def test_parallel_solve_equals_serial(orc, params):
+    # the process pool used by the full-size parity tests returns exactly the serial solutions
+    rng = np.random.default_rng(5)
+    M = 10 ** rng.uniform(12.5, 15.5, 300)
+    c = rng.uniform(2, 15, 300)
+    z = rng.uniform(0.05, 3, 300)
+    a = orc.solve_halos(params, M, c, z)
+    b = orc.solve_halos_parallel(params, M, c, z, workers=4)
+    for f in ("x_f", "rho0", "P0", "R_t", "D_A", "tau", "status"):
+        assert [getattr(h, f) for h in a] == [getattr(h, f) for h in b], f
