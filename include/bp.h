@@ -116,10 +116,12 @@ enum {
  * with r_perp >= r_vir).  Each zone is tabulated on a uniform grid of a
  * variable that makes the projected profile analytic, with the edge factor
  * divided out:
- *   zone A:  eta  = ln(1 + acosh(r_a / r_perp)),   Y = P_e0 u g_A(eta),
- *            u = sqrt(r_a^2 - r_perp^2)
- *   zone S:  omega = asinh(u_v / sqrt(D)),         Y = P_e0 (S - u_v) g_S(omega),
- *            u_v = sqrt(r_vir^2 - r_perp^2), D = r_f^2 - r_vir^2, S = sqrt(u_v^2 + D)
+ *   zone A:  eta  = ln(1 + acosh(r_a / r_perp)),   Y = P_e0 S g_T(eta),
+ *            u = sqrt(r_a^2 - r_perp^2), S = sqrt(u^2 + D), D = r_f^2 - r_vir^2 when the gas
+ *            extends past r_vir (else 0, S = u): the whole sight line, its shell part included
+ *   zone S:  omega = asinh(u_v / sqrt(D)),         Y_S = P_e0 (S - u_v) g_S(omega),
+ *            u_v = sqrt(r_vir^2 - r_perp^2): the shell r_vir < r < r_f alone, from which zone A's
+ *            shell part is interpolated (the deposits read zones A and B only)
  *   zone B:  zeta = acosh(r_f / r_perp),           Y = P_e0 U g_B(zeta),
  *            U = sqrt(r_f^2 - r_perp^2)
  * (same with n_e0 for the density).  P_e0 and n_e0 are the central electron

@@ -56,8 +56,9 @@ __device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 // unit), in units of the central electron pressure / density times that
 // length.  u2 = r_a^2 - r2 and U2 = r_f^2 - r2 are passed in so the caller can
 // form them without cancellation next to the footprint edge.
-//   zone A (r < r_a):  Y = u g_A(eta),  eta = ln(1 + acosh(r_a / r)),  u = sqrt(r_a^2 - r^2)
-//                      plus, for a gas shell beyond r_vir, (S - u) g_S(omega)
+//   zone A (r < r_a):  Y = S g_T(eta),  eta = ln(1 + acosh(r_a / r)),  S = sqrt(u^2 + D),
+//                      u = sqrt(r_a^2 - r^2), D = r_f^2 - r_vir^2 for a gas shell beyond r_vir (else 0):
+//                      the table holds the whole line, the shell's part folded in
 //   zone B (r >= r_a): Y = U g_B(zeta), zeta = acosh(r_f / r),        U = sqrt(r_f^2 - r^2)
 // A and B share one interpolation with a per-lane table offset, so a wave that straddles r_a
 // does not run both branches.  The grid coordinates are kept in log2 units (set_zone_grids), so
@@ -107,16 +108,10 @@ __device__ inline void footprint_value(const Rec &R, const float *__restrict__ t
     const int nn = zA ? BP_TAB_NA : BP_TAB_NB;
     float gp, gn;
     lagr4x2(tab, BP_TAB_ZONE, off, nn, sidx, &gp, &gn);
-    float P = gp * w, N = gn * w;
-    if ((R.flags & 1) && zA) {
-        const float S = hw_sqrt(fmaf(w, w, R.D));
-        const float om = __builtin_amdgcn_logf((w + S) * R.isqD);                 // asinh(u / sqrt(D)) / ln 2
-        float sp, sn;
-        lagr4x2(tab, BP_TAB_ZONE, BP_TAB_NA, BP_TAB_NS, (om - R.om_lo) * R.om_ih, &sp, &sn);
-        const float e = R.D * hw_rcp(S + w);
-        P += sp * e; N += sn * e;
-    }
-    *vp = P; *vn = N;
+    // zone A holds the whole sight line, its shell part included: Y = S g_T with S = sqrt(u^2 + D)
+    // (D = 0 without a shell, S = u); zone B: Y = U g_B
+    const float e = zA ? hw_sqrt(fmaf(w, w, R.D)) : w;
+    *vp = gp * e; *vn = gn * e;
 }
 
 

@@ -17,6 +17,7 @@
 
 #include "bp_device.hpp"
 #include "bp_internal.hpp"
+#include "bp_footprint.hpp"
 
 namespace bp {
 
@@ -524,7 +525,6 @@ k_icm_solve(bp_params P, GaussRules G, int64_t n, const double *__restrict__ Min
 struct Prof {
     float rv, inv_rs, rf, cm, phi_out0, a, inv_r500, ant_f, n_nt;
 };
-__device__ inline float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ inline float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -663,10 +663,11 @@ __device__ inline void table_node(const GaussRules &G, int64_t n, const double *
     double accP = 0.0, accN = 0.0;
     if (node < BP_TAB_NA) {
         // zone A: g_A = Y_A / (P_e0 u), Y_A = 2 int_0^xi P(r_perp cosh s) r_perp cosh s ds
-        double xi, rp, f;
+        double xi, rp, f, th;             // th = tanh(xi) = u / r_a
         if (eta_lo == 0.0) {
             xi = g_nodeA[node][0];
             rp = ra * g_nodeA[node][1];
+            th = g_nodeA[node][2];
             f = g_nodeA[node][3] / ra;   // 2 * (xi/2) / u
         } else {
             const double eta = eta_lo + (eta_hi - eta_lo) * node / (BP_TAB_NA - 1);
@@ -674,7 +675,8 @@ __device__ inline void table_node(const GaussRules &G, int64_t n, const double *
             // cosh and tanh of xi from one expm1 (no cancellation for small xi)
             const double em = expm1(xi), e = 1.0 + em, q = e * e + 1.0;
             rp = ra * (2.0 * e / q);
-            f = xi / (ra * (em * (2.0 + em) / q));
+            th = em * (2.0 + em) / q;
+            f = xi / (ra * th);
         }
         if (xi < 1e-7) {  // limit r_perp -> r_a
             float pe, ne;
@@ -700,6 +702,25 @@ __device__ inline void table_node(const GaussRules &G, int64_t n, const double *
                 accP += w * pe; accN += w * ne;
             }
             accP *= f; accN *= f;
+        }
+        if (shell) {
+            // Fold the shell r_vir < r < r_f that the same sight line crosses into the node, so the deposit
+            // reads one table: g_T = (u g_A + (S - u) g_S) / S with S = sqrt(u^2 + D) and g_S interpolated
+            // from zone S (cubic Lagrange in omega; written by the zone S/B kernel, which runs first).
+            // FP32 with the forms the deposit used per pixel when it read zone S itself.  Y is smooth across
+            // zone A; its only kink, where the line grazes r_vir, sits at the zone's end as (r_vir - r_perp)^(5/2).
+            const float u = (float)(ra * th), Df = (float)D, isqD = (float)(1.0 / sD);
+            const float S = __builtin_amdgcn_sqrtf(fmaf(u, u, Df));
+            const double l2e = 1.4426950408889634;
+            const float om2_lo = (float)(om_lo * l2e);
+            const float om2_ih = om_hi > om_lo ? (float)((BP_TAB_NS - 1) / ((om_hi - om_lo) * l2e)) : 0.0f;
+            const float om = __builtin_amdgcn_logf((u + S) * isqD);          // asinh(u / sqrt(D)) / ln 2
+            float gSP, gSN;
+            lagr4x2(tP, BP_TAB_ZONE, BP_TAB_NA, BP_TAB_NS, (om - om2_lo) * om2_ih, &gSP, &gSN);
+            const float sh = Df * __builtin_amdgcn_rcpf(S + u);             // S - u without cancellation
+            const float inv = __builtin_amdgcn_rcpf(S);
+            accP = (double)((u * (float)accP + sh * gSP) * inv);
+            accN = (double)((u * (float)accN + sh * gSN) * inv);
         }
     } else if (node < BP_TAB_NA + BP_TAB_NS) {
         // zone S: g_S = Y_S / (P_e0 (S - u_v)), Y_S over the shell r_vir < r < r_f
@@ -976,10 +997,11 @@ extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *so
     prof_begin(BP_PROF_TABLES, s);
     hipLaunchKernelGGL(k_node_geom, dim3(1), dim3(BP_TAB_NA), 0, s, (double)(float)G.eta_top);
     hipLaunchKernelGGL(k_table_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, *p, G, n, sol, status, meta);
-    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_NA), 0, s, G, n, sol, status, meta, tables,
-                       (float)p->n_nt);
+    // zones S and B first: zone A folds the shell part of each of its sight lines in from zone S
     hipLaunchKernelGGL(k_tables_sb, dim3((unsigned)((n + 1) / 2)), dim3(128), 0, s, G, n, sol, status, meta,
                        tables, (float)p->n_nt);
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)n), dim3(BP_TAB_NA), 0, s, G, n, sol, status, meta, tables,
+                       (float)p->n_nt);
     prof_end(BP_PROF_TABLES, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -143,13 +143,15 @@ def test_tables_against_los(bp, orc):
         rv, rf, Rt = h.r_vir, h.r_f, h.R_t
         ra = min(rv, rf)
         checks = []
-        if rf <= rv:   # zone A alone is the full sight line
-            lo, hi = meta[bp.META["ETA_LO"], i], meta[bp.META["ETA_HI"], i]
-            for k in range(0, bp.TAB_NA, 7):
-                xi = math.expm1(lo + (hi - lo) * k / (bp.TAB_NA - 1))
-                rp = ra / math.cosh(xi)
-                u = math.sqrt(max(ra * ra - rp * rp, 0))
-                checks.append((rp, tab[i, k] * u, tab[i, bp.TAB_ZONE + k] * u))
+        # zone A: the whole sight line, Y = S g_T with S = sqrt(u^2 + D), D = r_f^2 - r_vir^2 for a gas shell
+        lo, hi = meta[bp.META["ETA_LO"], i], meta[bp.META["ETA_HI"], i]
+        D = rf * rf - rv * rv if rf > rv else 0.0
+        for k in range(0, bp.TAB_NA, 7):
+            xi = math.expm1(lo + (hi - lo) * k / (bp.TAB_NA - 1))
+            rp = ra / math.cosh(xi)
+            u = math.sqrt(max(ra * ra - rp * rp, 0))
+            S = math.sqrt(u * u + D)
+            checks.append((rp, tab[i, k] * S, tab[i, bp.TAB_ZONE + k] * S))
         if Rt > rv:    # zone B nodes
             lo, hi = meta[bp.META["ZE_LO"], i], meta[bp.META["ZE_HI"], i]
             for k in range(bp.TAB_NB):
@@ -165,8 +167,11 @@ def test_tables_against_los(bp, orc):
             ty, tb = orc.los(p, h, rp)
             yo = ty / (orc.SIGMA_T / orc.ME_C2) / units / Pe0
             no = tb / orc.SIGMA_T / units / ne0
-            assert abs(gy / yo - 1) < 2e-6, (i, rp / rv, gy, yo)
-            assert abs(gn / no - 1) < 2e-6, (i, rp / rv, gn, no)
+            # a zone-A node of a halo with a shell carries the shell part interpolated from the 32-node zone S
+            # (the interpolation the deposit applied per pixel before the fold): 4e-6; else 2e-6
+            tol = 4e-6 if (rf > rv and rp < ra) else 2e-6
+            assert abs(gy / yo - 1) < tol, (i, rp / rv, gy, yo)
+            assert abs(gn / no - 1) < tol, (i, rp / rv, gn, no)
 
 
 def test_hp_flat_small_full_map(bp, orc):
