@@ -6,9 +6,10 @@
 //   z2 = W2 h1 + b2, h2 = bf16(silu(z2)) BF16 MFMA, FP32 accumulation
 //   z3 = W3 h2 + b3, h3 = bf16(silu(z3))
 //   y  = W4 h3 + b4                      FP32 output
-// The hidden-layer products run on v_mfma_f32_16x16x16_bf16: a workgroup
-// computes a 64x64 output tile with four wavefronts (2x2 blocks of 16x16
-// each), staging 64x16 slices of both operands in LDS per K step.  Weight
+// The hidden-layer products run on gfx950's v_mfma_f32_16x16x32_bf16 (a 16x16
+// block over 32 k per instruction): a workgroup computes a 128x64 output tile
+// with four wavefronts (2x4 blocks of 16x16 each), staging 32-wide k slices of
+// both operands in LDS per K step.  Weight
 // gradients reduce over the batch with split-K partial tiles summed in a
 // fixed order, so training is deterministic.
 #include <hip/hip_runtime.h>
@@ -21,6 +22,13 @@ namespace bp {
 
 typedef short sx4 __attribute__((ext_vector_type(4)));
 typedef float fx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// D (16x16, FP32) += A (16x32) B (32x16) in BF16.  Lane l supplies A[l % 16][8 (l / 16) .. + 7] and
+// B[8 (l / 16) .. + 7][l % 16] (eight consecutive k each) and holds D[4 (l / 16) + j][l % 16], j < 4.
+__device__ inline fx4 mfma32(const bf16x8 &a, const bf16x8 &b, const fx4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 // round-to-nearest-even FP32 -> BF16 (gfx950 converts in hardware, v_cvt_pk_bf16_f32)
 __device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
@@ -48,8 +56,8 @@ struct GemmArgs {
 };
 
 // 128x64 output tile per workgroup; wavefront w owns rows 32w..32w+31 (2x4 blocks of 16x16).
-// K advances 32 at a time; both operands are staged in LDS with k contiguous (B transposed),
-// so each MFMA fragment is a single 8-byte LDS read.  All vectorised operand dimensions in this
+// K advances 32 at a time, one MFMA per block; both operands are staged in LDS with k contiguous
+// (B transposed), so each MFMA fragment is a single 16-byte LDS read.  All vectorised operand dimensions in this
 // library are multiples of 8 (K, the 256/144 layer widths); the batch dimension M is guarded per row.
 constexpr int kBM = 128, kBN = 64, kBK = 32, kLdk = kBK + 8;   // +8 bf16 of padding per row
 
@@ -107,15 +115,15 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
             for (int j = 0; j < 8; ++j) Bs[bn + j][bk] = v[j];
         }
         __syncthreads();
-        for (int ks = 0; ks < kBK; ks += 16) {
-            sx4 af[2], bfr[4];
+        {
+            static_assert(kBK == 32, "one 16x16x32 MFMA per block and K step");
+            bf16x8 af[2], bfr[4];
             for (int bi = 0; bi < 2; ++bi)
-                af[bi] = *(const sx4 *)&As[32 * w + 16 * bi + (lane & 15)][ks + 4 * (lane >> 4)];
+                af[bi] = *(const bf16x8 *)&As[32 * w + 16 * bi + (lane & 15)][8 * (lane >> 4)];
             for (int bj = 0; bj < 4; ++bj)
-                bfr[bj] = *(const sx4 *)&Bs[16 * bj + (lane & 15)][ks + 4 * (lane >> 4)];
+                bfr[bj] = *(const bf16x8 *)&Bs[16 * bj + (lane & 15)][8 * (lane >> 4)];
             for (int bi = 0; bi < 2; ++bi)
-                for (int bj = 0; bj < 4; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[bi], bfr[bj], acc[bi][bj], 0, 0, 0);
+                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma32(af[bi], bfr[bj], acc[bi][bj]);
         }
         __syncthreads();
     }
@@ -297,17 +305,19 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
 // ------------------------------------------------------------ fused inference --
 // All four layers for a block of 64 rows in one kernel; activations never leave the CU.
 // Each layer is computed transposed, out^T = W h^T: the weights are the MFMA A operand and the
-// activations the B operand.  With v_mfma_f32_16x16x16bf16 a lane's accumulator holds outputs
-// (4 (l/16) + j, l % 16) of a 16x16 block, i.e. four consecutive features of one row -- the same
-// (k, n) positions it reads as B of the next layer -- so each wavefront keeps its 16 rows'
-// activations in its own LDS rows (BF16, written by the epilogue, read as B fragments) and never
-// needs a transpose.  The weights stream through LDS in 16-column k-slices, double-buffered and
+// activations the B operand.  A lane's accumulator holds outputs (4 (l/16) + j, l % 16) of a 16x16
+// block, i.e. four consecutive features of one row, which the epilogue writes to the wavefront's
+// own LDS activation rows (BF16); the next layer reads them back as B fragments of eight
+// consecutive features.  The weights stream through LDS in 32-column k slices, double-buffered and
 // shared by the four wavefronts.  The k order of every sum is that of bp_mlp_forward.
-constexpr int kFR = 16;                 // rows per wavefront
+constexpr int kFRB = 2;                 // 16-row blocks per wavefront: each weight fragment feeds kFRB MFMAs
+constexpr int kFR = 16 * kFRB;          // rows per wavefront
 constexpr int kFBM = 4 * kFR;           // rows per workgroup
-constexpr int kFKB = BP_MLP_HID / 16;   // 16-wide k slices of a hidden-layer input
-constexpr int kFLd = 20;                // LDS row stride of a weight k-slice in bf16 (16 + 4)
-constexpr int kFALd = BP_MLP_HID + 4;   // LDS row stride of the activations in bf16 (256 + 4)
+constexpr int kFK = 32;                 // k per slice (one 16x16x32 MFMA)
+constexpr int kFKB = BP_MLP_HID / kFK;  // k slices of a hidden-layer input
+constexpr int kFOB = BP_MLP_HID / 16;   // 16-feature output blocks of a hidden layer
+constexpr int kFLd = kFK + 8;           // LDS row stride of a weight k slice in bf16 (32 + 8)
+constexpr int kFALd = BP_MLP_HID + 8;   // LDS row stride of the activations in bf16 (256 + 8)
 
 __device__ inline sx4 pack_bf4(float a, float b, float c, float d) {
     sx4 r;
@@ -315,41 +325,46 @@ __device__ inline sx4 pack_bf4(float a, float b, float c, float d) {
     return r;
 }
 
-// One layer: acc[ob] = sum_k W[16 ob + .][k] h[row][k] over the wavefront's 16 rows (held in act).
+// One layer: acc[rb][ob] = sum_k W[16 ob + .][k] h[16 rb + row][k] over the wavefront's rows (held in act),
+// for the first NOB output blocks.
 template <int NOB>
 __device__ inline void fused_layer(const uint16_t *__restrict__ W, const uint16_t *__restrict__ act,
-                                   fx4 (&acc)[NOB], uint16_t *__restrict__ wsl, int t, int lane) {
+                                   fx4 (&acc)[kFRB][kFOB], uint16_t *__restrict__ wsl, int t, int lane) {
 #pragma unroll
-    for (int ob = 0; ob < NOB; ++ob) acc[ob] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int rb = 0; rb < kFRB; ++rb)
+#pragma unroll
+        for (int ob = 0; ob < NOB; ++ob) acc[rb][ob] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
     constexpr int kRows = NOB * 16;                  // weight rows (output features)
     constexpr int kBuf = BP_MLP_HID * kFLd;          // one k slice, room for 256 rows
-    // thread t < kRows moves row t of a k slice: 16 bf16 = two 16-byte loads
-    uint4 st0 = {0, 0, 0, 0}, st1 = {0, 0, 0, 0};
+    // thread t < kRows moves row t of a k slice: 32 bf16 = four 16-byte loads
+    uint4 st0 = {}, st1 = {}, st2 = {}, st3 = {};   // (separate values: an array here is placed in LDS)
     auto fetch = [&](int kb) {
         if (t < kRows) {
-            const uint4 *src = (const uint4 *)(W + (int64_t)t * BP_MLP_HID + kb * 16);
-            st0 = src[0]; st1 = src[1];
+            const uint4 *src = (const uint4 *)(W + (int64_t)t * BP_MLP_HID + kb * kFK);
+            st0 = src[0]; st1 = src[1]; st2 = src[2]; st3 = src[3];
         }
     };
     auto put = [&](int buf) {
         if (t < kRows) {
-            uint2 *dst = (uint2 *)(wsl + buf * kBuf + t * kFLd);
-            dst[0] = uint2{st0.x, st0.y}; dst[1] = uint2{st0.z, st0.w};
-            dst[2] = uint2{st1.x, st1.y}; dst[3] = uint2{st1.z, st1.w};
+            uint4 *dst = (uint4 *)(wsl + buf * kBuf + t * kFLd);
+            dst[0] = st0; dst[1] = st1; dst[2] = st2; dst[3] = st3;
         }
     };
     fetch(0);
     put(0);
     __syncthreads();
-    const uint16_t *bsrc = act + (lane & 15) * kFALd + 4 * (lane >> 4);
+    const uint16_t *bsrc = act + (lane & 15) * kFALd + 8 * (lane >> 4);
     for (int kb = 0; kb < kFKB; ++kb) {
         if (kb + 1 < kFKB) fetch(kb + 1);
-        const sx4 bfr = *(const sx4 *)(bsrc + 16 * kb);
-        const uint16_t *sl = wsl + (kb & 1) * kBuf + (lane & 15) * kFLd + 4 * (lane >> 4);
+        bf16x8 bfr[kFRB];
+#pragma unroll
+        for (int rb = 0; rb < kFRB; ++rb) bfr[rb] = *(const bf16x8 *)(bsrc + 16 * rb * kFALd + kFK * kb);
+        const uint16_t *sl = wsl + (kb & 1) * kBuf + (lane & 15) * kFLd + 8 * (lane >> 4);
 #pragma unroll
         for (int ob = 0; ob < NOB; ++ob) {
-            const sx4 a = *(const sx4 *)(sl + ob * 16 * kFLd);
-            acc[ob] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bfr, acc[ob], 0, 0, 0);
+            const bf16x8 a = *(const bf16x8 *)(sl + ob * 16 * kFLd);
+#pragma unroll
+            for (int rb = 0; rb < kFRB; ++rb) acc[rb][ob] = mfma32(a, bfr[rb], acc[rb][ob]);
         }
         if (kb + 1 < kFKB) put((kb + 1) & 1);
         __syncthreads();
@@ -364,52 +379,62 @@ __global__ void __launch_bounds__(256) k_mlp_infer(int64_t n, const float *__res
     __shared__ __attribute__((aligned(16))) uint16_t acts[4 * kFR * kFALd];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     uint16_t *act = acts + wv * kFR * kFALd;
-    const int64_t row = (int64_t)blockIdx.x * kFBM + wv * kFR + (lane & 15);
-    // this lane's slot in the activation rows: row l%16, features 4 (l/16) + 16 kb .. + 3
+    const int64_t row0 = (int64_t)blockIdx.x * kFBM + wv * kFR + (lane & 15);   // row of block rb: row0 + 16 rb
+    // this lane's slot in the activation rows of block rb: row 16 rb + l%16, features 4 (l/16) + 16 kb .. + 3
     uint16_t *aslot = act + (lane & 15) * kFALd + 4 * (lane >> 4);
     // layer 1 (FP32)
     {
         const float *W1 = w + oW1, *b1 = w + ob1;
-        float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-        if (row < n) { x0 = x[row * BP_MLP_IN]; x1 = x[row * BP_MLP_IN + 1]; x2 = x[row * BP_MLP_IN + 2]; }
-        for (int kb = 0; kb < kFKB; ++kb) {
-            float h[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = 16 * kb + 4 * (lane >> 4) + j;
-                float z = b1[o];
-                z += W1[o * BP_MLP_IN] * x0;
-                z += W1[o * BP_MLP_IN + 1] * x1;
-                z += W1[o * BP_MLP_IN + 2] * x2;
-                h[j] = silu(z);
+        for (int rb = 0; rb < kFRB; ++rb) {
+            const int64_t row = row0 + 16 * rb;
+            float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+            if (row < n) { x0 = x[row * BP_MLP_IN]; x1 = x[row * BP_MLP_IN + 1]; x2 = x[row * BP_MLP_IN + 2]; }
+            for (int kb = 0; kb < kFOB; ++kb) {
+                float h[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = 16 * kb + 4 * (lane >> 4) + j;
+                    float z = b1[o];
+                    z += W1[o * BP_MLP_IN] * x0;
+                    z += W1[o * BP_MLP_IN + 1] * x1;
+                    z += W1[o * BP_MLP_IN + 2] * x2;
+                    h[j] = silu(z);
+                }
+                *(sx4 *)(aslot + 16 * rb * kFALd + 16 * kb) = pack_bf4(h[0], h[1], h[2], h[3]);
             }
-            *(sx4 *)(aslot + 16 * kb) = pack_bf4(h[0], h[1], h[2], h[3]);
         }
     }
     // hidden layers 2 and 3
-    fx4 acc[kFKB];
+    fx4 acc[kFRB][kFOB];
     for (int layer = 0; layer < 2; ++layer) {
         const uint16_t *W = wb + (layer == 0 ? oW2 : oW3);
         const float *bias = w + (layer == 0 ? ob2 : ob3);
-        fused_layer<kFKB>(W, act, acc, wsl, t, lane);
+        fused_layer<kFOB>(W, act, acc, wsl, t, lane);
 #pragma unroll
-        for (int ob = 0; ob < kFKB; ++ob) {
-            const int o = 16 * ob + 4 * (lane >> 4);
-            const fx4 v = acc[ob];
-            *(sx4 *)(aslot + 16 * ob) = pack_bf4(silu(v[0] + bias[o]), silu(v[1] + bias[o + 1]),
-                                                 silu(v[2] + bias[o + 2]), silu(v[3] + bias[o + 3]));
-        }
+        for (int rb = 0; rb < kFRB; ++rb)
+#pragma unroll
+            for (int ob = 0; ob < kFOB; ++ob) {
+                const int o = 16 * ob + 4 * (lane >> 4);
+                const fx4 v = acc[rb][ob];
+                *(sx4 *)(aslot + 16 * rb * kFALd + 16 * ob) =
+                    pack_bf4(silu(v[0] + bias[o]), silu(v[1] + bias[o + 1]), silu(v[2] + bias[o + 2]),
+                             silu(v[3] + bias[o + 3]));
+            }
     }
     // output layer (144 features = 9 blocks)
     constexpr int kOB = BP_MLP_OUT / 16;
-    fx4 out[kOB];
+    fx4 (&out)[kFRB][kFOB] = acc;
     fused_layer<kOB>(wb + oW4, act, out, wsl, t, lane);
-    if (row < n) {
-        const float *b4 = w + ob4;
+    const float *b4 = w + ob4;
+#pragma unroll
+    for (int rb = 0; rb < kFRB; ++rb) {
+        const int64_t row = row0 + 16 * rb;
+        if (row >= n) continue;
 #pragma unroll
         for (int ob = 0; ob < kOB; ++ob) {
             const int o = 16 * ob + 4 * (lane >> 4);
-            const fx4 v = out[ob];
+            const fx4 v = out[rb][ob];
             *(float4 *)(y + row * BP_MLP_OUT + o) = float4{v[0] + b4[o], v[1] + b4[o + 1], v[2] + b4[o + 2],
                                                            v[3] + b4[o + 3]};
         }
