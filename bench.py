@@ -35,9 +35,9 @@ DEPOSIT_OPS_PER_PX_DESIGN = 35
 # HBM bytes per deposit launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99994, WRITE x 1.0).
 # Valid only for the deposit sources they were measured on.
-DEPOSIT_TRAFFIC = {"bytes": 2683816617,
-                   "sources_sha256": {"bp_hp_flat.hip": "cf34621bcd32c6473760a4457cdd1b18d78b1a3dd9f7be635cd7abf6c0d2545b",
-                                      "bp_footprint.hpp": "42c816bea0bc9eadcecc24576c949ee7c9eb52d8ea63cbea0813c080b6544c4f"}}
+DEPOSIT_TRAFFIC = {"bytes": 2271351107,
+                   "sources_sha256": {"bp_hp_flat.hip": "8957fad3f5de9fe1de48427f54e27e1bb374676234063febc269422758bd9af4",
+                                      "bp_footprint.hpp": "7b3efc5f312cb6d1de2754b93b33bee558a3fd0c221587bf447053aec84eee6c"}}
 
 
 def deposit_traffic():
