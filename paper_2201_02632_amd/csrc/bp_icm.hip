@@ -678,17 +678,21 @@ __device__ inline void table_node(const GaussRules &G, int64_t n, const double *
             th = em * (2.0 + em) / q;
             f = xi / (ra * th);
         }
+        // Gauss-Legendre order by the length xi of the s-interval: over the benchmark's halo
+        // population the worst relative quadrature error stays below 3e-8 (under the FP32
+        // rounding of the integrand) with 6 points up to xi = 1.4, 8 up to 3.2, 10 up to 4.6,
+        // 12 up to 6.0, 14 up to 7.6, 16 up to 9.0 and 20 beyond.  A wavefront runs the largest
+        // order among its lanes anyway, so every lane takes that order: the rule is then the same
+        // for the whole wavefront and its nodes and weights are scalar loads.
+        int ngl = xi > 9.0 ? 20 : xi > 7.6 ? 16 : xi > 6.0 ? 14 : xi > 4.6 ? 12 : xi > 3.2 ? 10 : xi > 1.4 ? 8 : 6;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) ngl = max(ngl, __shfl_xor(ngl, o, 64));
+        const int ng = __builtin_amdgcn_readfirstlane(ngl);
         if (xi < 1e-7) {  // limit r_perp -> r_a
             float pe, ne;
             prof_eval(Q, (float)ra, &pe, &ne);
             accP = 2.0 * pe; accN = 2.0 * ne;
         } else {
-            // Gauss-Legendre order by the length xi of the s-interval: over the benchmark's halo
-            // population the worst relative quadrature error stays below 3e-8 (under the FP32
-            // rounding of the integrand) with 6 points up to xi = 1.4, 8 up to 3.2, 10 up to 4.6,
-            // 12 up to 6.0, 14 up to 7.6, 16 up to 9.0 and 20 beyond
-            const int ng = xi > 9.0 ? 20 : xi > 7.6 ? 16 : xi > 6.0 ? 14 : xi > 4.6 ? 12 : xi > 3.2 ? 10
-                                                                                   : xi > 1.4 ? 8 : 6;
             const float *gu = ng == 20 ? G.u20 : ng == 16 ? G.u16 : ng == 14 ? G.u14 : ng == 12 ? G.u12
                               : ng == 10 ? G.u10 : ng == 8 ? G.u8 : G.u6;
             const double *gw = ng == 20 ? G.w20 : ng == 16 ? G.w16 : ng == 14 ? G.w14 : ng == 12 ? G.w12
