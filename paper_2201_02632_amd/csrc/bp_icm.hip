@@ -825,10 +825,15 @@ __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kQH, i = i0 + lane;
     const bool live = i < n && (status[i] & ~ok_mask) == 0;
-    if (live) {
-        auto S = [&](int f) { return sol[(int64_t)f * n + i]; };
-        const double rv = S(BP_SOL_RVIR), rf = S(BP_SOL_RF), Rt = S(BP_SOL_RT), c = S(BP_SOL_C), mc = nfw_m(c);
-        if (wave == 0) {
+    // Every lane runs the node loop (a lane without a live halo computes on stand-in values and stores
+    // nothing), so that the wavefront can agree on one Gauss-Legendre order per node: it runs the
+    // largest order among its lanes anyway, and one order for all makes the rule's nodes and weights
+    // scalar loads.
+    {
+        auto S = [&](int f) { return live ? sol[(int64_t)f * n + i] : 1.0; };
+        const double rv = S(BP_SOL_RVIR), rf = live ? S(BP_SOL_RF) : 2.0, Rt = S(BP_SOL_RT), c = S(BP_SOL_C);
+        const double mc = nfw_m(c);
+        if (live && wave == 0) {
             const double X = P.X_H;
             meta[(int64_t)BP_META_PE0 * n + i] = (float)((2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0));
             meta[(int64_t)BP_META_NE0 * n + i] = (float)(S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp));
@@ -848,10 +853,14 @@ __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G
             const double rp = fmax(q * Rt, 1e-5 * ra);
             const float rpf = (float)rp;
             double accP = 0.0, accN = 0.0;
-            if (rp < ra) {
-                const double xi = acosh(ra / rp);
-                const int ng = xi > 9.0 ? 20 : xi > 7.6 ? 16 : xi > 6.0 ? 14 : xi > 4.6 ? 12 : xi > 3.2 ? 10
-                                                                                   : xi > 1.4 ? 8 : 6;
+            const bool za = live && rp < ra;
+            const double xi = za ? acosh(ra / rp) : 0.0;
+            int ngl = xi > 9.0 ? 20 : xi > 7.6 ? 16 : xi > 6.0 ? 14 : xi > 4.6 ? 12 : xi > 3.2 ? 10 : xi > 1.4 ? 8 : 6;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) ngl = max(ngl, __shfl_xor(ngl, o, 64));
+            const int ng = __builtin_amdgcn_readfirstlane(ngl);
+            if (!live) continue;
+            if (za) {
                 const float *gu = ng == 20 ? G.u20 : ng == 16 ? G.u16 : ng == 14 ? G.u14 : ng == 12 ? G.u12
                                   : ng == 10 ? G.u10 : ng == 8 ? G.u8 : G.u6;
                 const double *gw = ng == 20 ? G.w20 : ng == 16 ? G.w16 : ng == 14 ? G.w14 : ng == 12 ? G.w12
