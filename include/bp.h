@@ -446,7 +446,9 @@ int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *gr
  * bytes, 256-byte aligned (the library allocates nothing).  Array a of the state starts at byte
  * bp_surrogate_state_offset(a): FP32 master weights (BP_MLP_NPARAMS layout above), their BF16 compute
  * copy, the two Adam moments, the last gradient, and the output mean and standard deviation (BP_MLP_OUT
- * floats each).  The buffer holds no pointers: copying its bytes copies the surrogate. */
+ * floats each).  The buffer holds no pointers: copying its bytes copies the surrogate.  Every call
+ * below that takes the state returns BP_E_ARG for a null or not 256-byte aligned state, before any
+ * device work. */
 enum { BP_SUR_W = 0, BP_SUR_WBF16, BP_SUR_M, BP_SUR_V, BP_SUR_G, BP_SUR_MEAN, BP_SUR_STD, BP_SUR_NARRAYS };
 size_t bp_surrogate_state_bytes(void);
 size_t bp_surrogate_state_offset(int32_t array);     /* (size_t)-1 for an unknown array */

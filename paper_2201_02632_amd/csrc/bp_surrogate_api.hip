@@ -179,13 +179,17 @@ using namespace bp;
 
 extern "C" size_t bp_surrogate_state_bytes(void) { return sur_layout().total; }
 
+// the state buffer: non-null and 256-byte aligned (its arrays are then 16-byte aligned for the
+// kernels' vector accesses)
+static bool state_ok(const void *state) { return state && !((uintptr_t)state & 255); }
+
 extern "C" size_t bp_surrogate_state_offset(int32_t array) {
     if (array < 0 || array >= BP_SUR_NARRAYS) return (size_t)-1;
     return sur_layout().off[array];
 }
 
 extern "C" int bp_surrogate_init(void *state, uint64_t seed, void *stream) {
-    if (!state || ((uintptr_t)state & 255)) return BP_E_ARG;
+    if (!state_ok(state)) return BP_E_ARG;
     SurViews V = views(state);
     const int64_t np = bp_mlp_nparams();
     hipStream_t s = (hipStream_t)stream;
@@ -209,7 +213,7 @@ size_t blob_bytes() {
 extern "C" size_t bp_surrogate_blob_bytes(void) { return blob_bytes(); }
 
 extern "C" int bp_surrogate_save(const void *state, int64_t step, void *blob, size_t blob_bytes_, void *stream) {
-    if (!state || !blob || blob_bytes_ < blob_bytes() || step < 0) return BP_E_ARG;
+    if (!state_ok(state) || !blob || blob_bytes_ < blob_bytes() || step < 0) return BP_E_ARG;
     SurViews V = views((void *)state);
     const int64_t np = bp_mlp_nparams();
     BlobHead H = {kBlobMagic, 1, (uint64_t)np, BP_MLP_OUT, (uint64_t)step, {0, 0, 0}};
@@ -226,7 +230,7 @@ extern "C" int bp_surrogate_save(const void *state, int64_t step, void *blob, si
 }
 
 extern "C" int bp_surrogate_load(void *state, const void *blob, size_t blob_bytes_, int64_t *step, void *stream) {
-    if (!state || !blob || blob_bytes_ < sizeof(BlobHead)) return BP_E_ARG;
+    if (!state_ok(state) || !blob || blob_bytes_ < sizeof(BlobHead)) return BP_E_ARG;
     BlobHead H;
     memcpy(&H, blob, sizeof(H));
     const int64_t np = bp_mlp_nparams();
@@ -252,7 +256,7 @@ extern "C" int bp_surrogate_load(void *state, const void *blob, size_t blob_byte
 extern "C" int bp_surrogate_fit(const bp_params *p, void *state, int64_t n, const double *M, const double *c,
                                 const double *z, int64_t steps, int64_t batch, float lr0, float lr1, uint64_t seed,
                                 int64_t step0, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
-    if (check_params(p) || !state || n <= 0 || !M || !c || !z || steps < 0 || batch <= 0 || step0 < 0 || !ws_needed)
+    if (check_params(p) || !state_ok(state) || n <= 0 || !M || !c || !z || steps < 0 || batch <= 0 || step0 < 0 || !ws_needed)
         return BP_E_ARG;
     if (n > ((int64_t)1 << 31)) return BP_E_OVERFLOW;
     SurViews V = views(state);
@@ -281,7 +285,7 @@ extern "C" int bp_surrogate_paste_flat(const bp_params *p, const void *state, in
                                        const double *theta_x, const double *theta_y, const double *v_los,
                                        float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
                                        size_t ws_bytes, size_t *ws_needed, int64_t *n_fallback, void *stream) {
-    if (check_params(p) || !state || (tables != BP_SUR_TABLES_EXACT && tables != BP_SUR_TABLES_NETWORK) || npix <= 0 ||
+    if (check_params(p) || !state_ok(state) || (tables != BP_SUR_TABLES_EXACT && tables != BP_SUR_TABLES_NETWORK) || npix <= 0 ||
         npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed || !y_map || !b_map)
         return BP_E_ARG;
     if (n > 0 && (!M || !c || !z || !theta_x || !theta_y || !v_los)) return BP_E_ARG;
@@ -308,7 +312,7 @@ extern "C" int bp_surrogate_paste_healpix(const bp_params *p, const void *state,
                                           const double *theta, const double *phi, const double *v_los, float *y_map,
                                           float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
                                           size_t *ws_needed, int64_t *n_fallback, void *stream) {
-    if (check_params(p) || !state || (tables != BP_SUR_TABLES_EXACT && tables != BP_SUR_TABLES_NETWORK) || nside < 1 ||
+    if (check_params(p) || !state_ok(state) || (tables != BP_SUR_TABLES_EXACT && tables != BP_SUR_TABLES_NETWORK) || nside < 1 ||
         nside > 8192 || n < 0 || !ws_needed || !y_map || !b_map)
         return BP_E_ARG;
     if (n > 0 && (!M || !c || !z || !theta || !phi || !v_los)) return BP_E_ARG;

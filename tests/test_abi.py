@@ -108,3 +108,62 @@ def test_ngp_selfcheck_asks_for_its_workspace():
     assert bp._lib.bp_pp_healpix_ngp_selfcheck(1024, out, None, 0, ctypes.byref(need), None) == bp.BP_E_WORKSPACE
     assert need.value >= 8
     assert bp._lib.bp_pp_healpix_ngp_selfcheck(4096, out, None, 0, ctypes.byref(need), None) == bp.BP_E_ARG
+
+
+def _own_handle(bp):
+    """A separate handle on the library with the binding's prototypes, so that a test never changes
+    the binding's own function objects."""
+    L = ctypes.CDLL(bp.LIB_PATH)
+    for name, (res, args) in bp._SIGS.items():
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = res, args
+    return L
+
+
+def test_surrogate_state_layout_and_blob_size():
+    # one caller-allocated state buffer: every array inside it, 256-byte aligned offsets, no overlap
+    import paper_2201_02632_amd as bp
+    L = _own_handle(bp)
+    total = L.bp_surrogate_state_bytes()
+    npar = L.bp_mlp_nparams()
+    sizes = [4 * npar, 2 * npar, 4 * npar, 4 * npar, 4 * npar, 4 * 144, 4 * 144]   # w, w_bf16, m, v, g, mean, std
+    offs = [L.bp_surrogate_state_offset(a) for a in range(len(sizes))]
+    assert all(o % 256 == 0 for o in offs)
+    spans = sorted(zip(offs, sizes))
+    assert all(a + sa <= b for (a, sa), (b, _) in zip(spans, spans[1:]))
+    assert spans[-1][0] + spans[-1][1] <= total
+    assert L.bp_surrogate_state_offset(len(sizes)) == ctypes.c_size_t(-1).value
+    assert L.bp_surrogate_state_offset(-1) == ctypes.c_size_t(-1).value
+    # the blob: a header plus the FP32 weights, both moments, mean and std
+    assert L.bp_surrogate_blob_bytes() >= 4 * (3 * npar + 2 * 144)
+
+
+def test_surrogate_lifecycle_rejects_bad_state_and_blobs_on_the_host():
+    import paper_2201_02632_amd as bp
+    L = _own_handle(bp)
+    p = bp.default_params()
+    aligned, odd = 0x100000, 0x100040     # never dereferenced: the checks return first
+    assert L.bp_surrogate_init(None, 1, None) == bp.BP_E_ARG
+    assert L.bp_surrogate_init(odd, 1, None) == bp.BP_E_ARG
+    nb = L.bp_surrogate_blob_bytes()
+    blob = (ctypes.c_char * nb)()
+    assert L.bp_surrogate_save(odd, 0, blob, nb, None) == bp.BP_E_ARG
+    assert L.bp_surrogate_save(aligned, 0, blob, nb - 1, None) == bp.BP_E_ARG
+    assert L.bp_surrogate_save(aligned, -1, blob, nb, None) == bp.BP_E_ARG
+    assert L.bp_surrogate_load(odd, blob, nb, None, None) == bp.BP_E_ARG
+    # a blob of zeros has no valid header: refused before any copy to the device
+    assert L.bp_surrogate_load(aligned, blob, nb, None, None) == bp.BP_E_ARG
+    assert L.bp_surrogate_load(aligned, blob, 16, None, None) == bp.BP_E_ARG
+    need = ctypes.c_size_t(0)
+    f64 = ctypes.c_void_p(aligned)
+    assert L.bp_surrogate_fit(ctypes.byref(p), ctypes.c_void_p(odd), 10, f64, f64, f64, 10, 16, ctypes.c_float(1e-3),
+                              ctypes.c_float(1e-4), ctypes.c_uint64(0), 0, None, ctypes.c_size_t(0),
+                              ctypes.byref(need), None) == bp.BP_E_ARG
+    for tables in (0, 1):
+        assert L.bp_surrogate_paste_flat(ctypes.byref(p), ctypes.c_void_p(odd), tables, 64, ctypes.c_double(1e-4), 10,
+                                         f64, f64, f64, f64, f64, f64, f64, f64, None, None, None, ctypes.c_size_t(0),
+                                         ctypes.byref(need), None, None) == bp.BP_E_ARG
+    # an unknown table mode
+    assert L.bp_surrogate_paste_flat(ctypes.byref(p), ctypes.c_void_p(aligned), 7, 64, ctypes.c_double(1e-4), 10,
+                                     f64, f64, f64, f64, f64, f64, f64, f64, None, None, None, ctypes.c_size_t(0),
+                                     ctypes.byref(need), None, None) == bp.BP_E_ARG
