@@ -21,6 +21,22 @@ const GaussRules &gauss_rules();
 int qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status, int32_t ok_mask,
                   float *qtables, float *meta, hipStream_t s);
 
+// The surrogate network's gradient as partial sums that their consumer reduces in a fixed order:
+// split-K slices of the weight-gradient products (W4, W3, W2) and row-chunk column sums (b4, b3, b2,
+// and the first layer's bias and input columns).
+struct GradParts {
+    const float *w4, *w3, *w2;   // [ks][rows * 256]
+    const float *b4, *b3, *b2;   // [nchunk][cols]
+    const float *l1;             // [nchunk][1 + BP_MLP_NIN][256]
+    int ks, nchunk;
+};
+// bp_mlp_backward up to the partials (same arguments and workspace), and one Adam step from them
+// (bp_mlp_adam's update with the gradient reduced on the fly; the gradient is also written to g).
+int mlp_backward_parts(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
+                       const float *dy, GradParts *P, void *ws, size_t ws_bytes, hipStream_t s);
+int mlp_adam_parts(const GradParts &P, float *w, float *m, float *v, float *g, uint16_t *wb, float lr, float b1,
+                   float b2, float eps, int64_t step, hipStream_t s);
+
 // Validate the model parameters (every entry point that takes bp_params): BP_OK or BP_E_ARG.
 // Gamma must be the paper's 1.2, the polytropic index the kernels are written for.
 int check_params(const bp_params *p);

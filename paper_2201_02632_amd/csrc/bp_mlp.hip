@@ -182,14 +182,6 @@ __global__ void k_layer1(int64_t n, const float *__restrict__ W1, const float *_
 }
 
 // sum over split-K partials in fixed order: out[i] = sum_s part[s][i]
-__global__ void k_reduce_partials(int64_t count, int ks, const float *__restrict__ part, float *__restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float s = 0.0f;
-    for (int q = 0; q < ks; ++q) s += part[(int64_t)q * count + i];
-    out[i] = s;
-}
-
 // Batch reductions in two fixed-order stages.  Stage 1: block (bx, y) covers 64 columns and the rows
 // [64 y, 64 y + 64); its four waves take every fourth row and are combined in wave order, giving
 // part[y][j][c] = sum_m a[m][c] * (j == 0 ? 1 : x[m][j - 1]).  Stage 2 sums the chunks in order.
@@ -220,20 +212,6 @@ __global__ __launch_bounds__(256) void k_colsum_part(int64_t n, int cols, const 
             part[((int64_t)blockIdx.y * kSums + j) * cols + c] =
                 ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
 }
-// stage 2 for the first layer: part[y][0][o] -> db1[o], part[y][1 + k][o] -> dW1[o][k] (padded k are 0)
-__global__ void k_reduce_layer1(int nchunk, const float *__restrict__ part, float *__restrict__ gb1,
-                                float *__restrict__ gW1) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= BP_MLP_HID) return;
-    float acc[1 + BP_MLP_NIN] = {};
-    for (int y = 0; y < nchunk; ++y)
-#pragma unroll
-        for (int j = 0; j <= BP_MLP_NIN; ++j) acc[j] += part[((int64_t)y * (1 + BP_MLP_NIN) + j) * BP_MLP_HID + o];
-    gb1[o] = acc[0];
-#pragma unroll
-    for (int k = 0; k < BP_MLP_IN; ++k) gW1[o * BP_MLP_IN + k] = k < BP_MLP_NIN ? acc[1 + k] : 0.0f;
-}
-
 __global__ void k_to_bf16(int64_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = f2bf(a[i]);
@@ -463,22 +441,97 @@ static int wgrad_splits(int64_t n) {
     return (int)(ks < 1 ? 1 : ks > 64 ? 64 : ks);
 }
 
+// The gradient as partial sums that the consumer reduces in a fixed order (GradParts): all of them
+// coexist, so one kernel reduces every parameter.
+static int64_t nchunks(int64_t n) { return (n + kRowChunk - 1) / kRowChunk; }
+
 static size_t part_floats(int64_t n) {
-    int64_t ks = wgrad_splits(n);
-    int64_t nchunk = (n + kRowChunk - 1) / kRowChunk;
-    int64_t a = ks * BP_MLP_HID * BP_MLP_HID, b = nchunk * BP_MLP_HID * (1 + BP_MLP_NIN);
-    return (size_t)(a > b ? a : b);
+    const int64_t ks = wgrad_splits(n), nc = nchunks(n);
+    return (size_t)(ks * (BP_MLP_OUT + 2 * BP_MLP_HID) * BP_MLP_HID +
+                    nc * (BP_MLP_OUT + 2 * BP_MLP_HID + (1 + BP_MLP_NIN) * BP_MLP_HID)) + 64;
+}
+
+// the partials' places in a workspace of part_floats(n) floats
+static GradParts parts_layout(float *part, int64_t n) {
+    GradParts P;
+    P.ks = wgrad_splits(n);
+    P.nchunk = (int)nchunks(n);
+    float *q = part;
+    P.w4 = q; q += (int64_t)P.ks * BP_MLP_OUT * BP_MLP_HID;
+    P.w3 = q; q += (int64_t)P.ks * BP_MLP_HID * BP_MLP_HID;
+    P.w2 = q; q += (int64_t)P.ks * BP_MLP_HID * BP_MLP_HID;
+    P.b4 = q; q += (int64_t)P.nchunk * BP_MLP_OUT;
+    P.b3 = q; q += (int64_t)P.nchunk * BP_MLP_HID;
+    P.b2 = q; q += (int64_t)P.nchunk * BP_MLP_HID;
+    P.l1 = q;
+    return P;
+}
+
+// Gradient of parameter p from the partials, each group summed in slice / chunk order from zero.
+__device__ inline float grad_of(const GradParts &P, const Off &o, int64_t p) {
+    float s = 0.0f;
+    if (p >= o.b4) {
+        const int64_t c = p - o.b4;
+        for (int y = 0; y < P.nchunk; ++y) s += P.b4[(int64_t)y * BP_MLP_OUT + c];
+    } else if (p >= o.W4) {
+        const int64_t i = p - o.W4, cnt = (int64_t)BP_MLP_OUT * BP_MLP_HID;
+        for (int q = 0; q < P.ks; ++q) s += P.w4[q * cnt + i];
+    } else if (p >= o.b3) {
+        const int64_t c = p - o.b3;
+        for (int y = 0; y < P.nchunk; ++y) s += P.b3[(int64_t)y * BP_MLP_HID + c];
+    } else if (p >= o.W3) {
+        const int64_t i = p - o.W3, cnt = (int64_t)BP_MLP_HID * BP_MLP_HID;
+        for (int q = 0; q < P.ks; ++q) s += P.w3[q * cnt + i];
+    } else if (p >= o.b2) {
+        const int64_t c = p - o.b2;
+        for (int y = 0; y < P.nchunk; ++y) s += P.b2[(int64_t)y * BP_MLP_HID + c];
+    } else if (p >= o.W2) {
+        const int64_t i = p - o.W2, cnt = (int64_t)BP_MLP_HID * BP_MLP_HID;
+        for (int q = 0; q < P.ks; ++q) s += P.w2[q * cnt + i];
+    } else if (p >= o.b1) {
+        const int64_t c = p - o.b1;
+        for (int y = 0; y < P.nchunk; ++y) s += P.l1[((int64_t)y * (1 + BP_MLP_NIN)) * BP_MLP_HID + c];
+    } else {
+        const int64_t row = p / BP_MLP_IN, k = p - row * BP_MLP_IN;   // W1[row][k]; inputs past NIN are padding
+        if (k < BP_MLP_NIN)
+            for (int y = 0; y < P.nchunk; ++y)
+                s += P.l1[((int64_t)y * (1 + BP_MLP_NIN) + 1 + k) * BP_MLP_HID + row];
+    }
+    return s;
+}
+
+__global__ void k_reduce_grad(GradParts P, Off o, float *__restrict__ grad) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < o.total) grad[p] = grad_of(P, o, p);
+}
+
+// one Adam step straight from the partials (the reduction of k_reduce_grad, then the update of
+// k_adam); the gradient is also written to g
+__global__ void k_adam_parts(GradParts P, Off o, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                             float *__restrict__ g, uint16_t *__restrict__ wb, float lr, float b1, float b2, float eps,
+                             float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= o.total) return;
+    const float gi = grad_of(P, o, i);
+    g[i] = gi;
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi; v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
 }
 
 extern "C" size_t bp_mlp_backward_ws_bytes(int64_t n) {
     return (size_t)n * BP_MLP_OUT * 2 + (size_t)n * BP_MLP_HID * (2 + 4) * 2 + part_floats(n) * 4 + 4096;
 }
 
-extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
-                               const float *dy, float *grad, void *ws, size_t ws_bytes, void *stream) {
-    if (n <= 0 || !w || !wb || !x || !act || !dy || !grad || !ws) return BP_E_ARG;
+namespace bp {
+// The backward pass up to the partials (workspace as bp_mlp_backward); *P receives their places.
+int mlp_backward_parts(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
+                       const float *dy, GradParts *P, void *ws, size_t ws_bytes, hipStream_t s) {
+    if (n <= 0 || !w || !wb || !x || !act || !dy || !ws) return BP_E_ARG;
     if (ws_bytes < bp_mlp_backward_ws_bytes(n)) return BP_E_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
     Off o = offsets();
     const float *Z1 = (const float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
     const uint16_t *H1 = (const uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
@@ -489,34 +542,27 @@ extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, co
     uint16_t *Gb = A.take<uint16_t>(n * BP_MLP_HID), *Gc = A.take<uint16_t>(n * BP_MLP_HID);
     float *Df = A.take<float>(n * BP_MLP_HID), *Dg = A.take<float>(n * BP_MLP_HID);
     float *part = A.take<float>((int64_t)part_floats(n));
-    prof_begin(BP_PROF_MLP_BWD, s);
+    *P = parts_layout(part, n);
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * BP_MLP_OUT + 255) / 256)), dim3(256), 0, s, n * BP_MLP_OUT, dy,
                        G4);
-    // output layer: dW4 = g4^T h3, db4 = sum dy
-    auto wgrad = [&](const uint16_t *Gt, int64_t ldg, int64_t rows, const uint16_t *Hin, int64_t gw_off) -> int {
+    // dW = g^T h over the batch, in ks split-K slices
+    auto wgrad = [&](const uint16_t *Gt, int64_t ldg, int64_t rows, const uint16_t *Hin, const float *dst) -> int {
         GemmArgs g = {};
         g.M = rows; g.N = BP_MLP_HID; g.K = n; g.kchunk = kchunk;
         g.A = Gt; g.a_m = 1; g.a_k = ldg;          // A(m=o, k=s) = G[s][o]
         g.B = Hin; g.b_k = BP_MLP_HID; g.b_n = 1;  // B(k=s, n=i) = h[s][i]
-        g.F = part;
-        int r = launch_gemm(EPI_PARTIAL, g, ks, s);
-        if (r) return r;
-        int64_t cnt = rows * BP_MLP_HID;
-        hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, cnt, ks, part,
-                           grad + gw_off);
-        return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+        g.F = (float *)dst;
+        return launch_gemm(EPI_PARTIAL, g, ks, s);
     };
-    const int nchunk = (int)((n + kRowChunk - 1) / kRowChunk);
-    auto colsum = [&](const float *a, int cols, float *out) -> int {
+    const int nchunk = P->nchunk;
+    auto colsum = [&](const float *a, int cols, const float *dst) -> int {
         hipLaunchKernelGGL(k_colsum_part<1>, dim3((cols + 63) / 64, nchunk), dim3(256), 0, s, n, cols, a,
-                           (const float *)nullptr, part);
-        hipLaunchKernelGGL(k_reduce_partials, dim3((cols + 255) / 256), dim3(256), 0, s, (int64_t)cols, nchunk, part,
-                           out);
+                           (const float *)nullptr, (float *)dst);
         return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
     };
-    int r = wgrad(G4, BP_MLP_OUT, BP_MLP_OUT, H3, o.W4);
+    int r = wgrad(G4, BP_MLP_OUT, BP_MLP_OUT, H3, P->w4);
     if (r) return r;
-    r = colsum(dy, BP_MLP_OUT, grad + o.b4);
+    r = colsum(dy, BP_MLP_OUT, P->b4);
     if (r) return r;
     // dh3 = g4 W4 ; d3 = dh3 * silu'(z3)
     auto dgrad = [&](const uint16_t *Gin, int64_t kdim, const uint16_t *W, const float *Z, uint16_t *Gout,
@@ -530,22 +576,45 @@ extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, co
     };
     r = dgrad(G4, BP_MLP_OUT, wb + o.W4, Z3, Gb, Df);
     if (r) return r;
-    r = colsum(Df, BP_MLP_HID, grad + o.b3);
+    r = colsum(Df, BP_MLP_HID, P->b3);
     if (r) return r;
-    r = wgrad(Gb, BP_MLP_HID, BP_MLP_HID, H2, o.W3);
+    r = wgrad(Gb, BP_MLP_HID, BP_MLP_HID, H2, P->w3);
     if (r) return r;
     r = dgrad(Gb, BP_MLP_HID, wb + o.W3, Z2, Gc, Dg);
     if (r) return r;
-    r = colsum(Dg, BP_MLP_HID, grad + o.b2);
+    r = colsum(Dg, BP_MLP_HID, P->b2);
     if (r) return r;
-    r = wgrad(Gc, BP_MLP_HID, BP_MLP_HID, H1, o.W2);
+    r = wgrad(Gc, BP_MLP_HID, BP_MLP_HID, H1, P->w2);
     if (r) return r;
     r = dgrad(Gc, BP_MLP_HID, wb + o.W2, Z1, Gb, Df);   // d1 in Df (fp32); its bf16 copy is unused
     if (r) return r;
     // db1 and dW1 in one pass over d1
     hipLaunchKernelGGL(k_colsum_part<1 + BP_MLP_NIN>, dim3(BP_MLP_HID / 64, nchunk), dim3(256), 0, s, n, BP_MLP_HID,
-                       Df, x, part);
-    hipLaunchKernelGGL(k_reduce_layer1, dim3(1), dim3(BP_MLP_HID), 0, s, nchunk, part, grad + o.b1, grad + o.W1);
+                       Df, x, (float *)P->l1);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+// Adam from the partials of mlp_backward_parts, the bias corrections for `step` (>= 1).
+int mlp_adam_parts(const GradParts &P, float *w, float *m, float *v, float *g, uint16_t *wb, float lr, float b1,
+                   float b2, float eps, int64_t step, hipStream_t s) {
+    const Off o = offsets();
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam_parts, dim3((unsigned)((o.total + 255) / 256)), dim3(256), 0, s, P, o, w, m, v, g, wb, lr,
+                       b1, b2, eps, c1, c2);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+}  // namespace bp
+
+extern "C" int bp_mlp_backward(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
+                               const float *dy, float *grad, void *ws, size_t ws_bytes, void *stream) {
+    if (n <= 0 || !w || !wb || !x || !act || !dy || !grad || !ws) return BP_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    GradParts P;
+    prof_begin(BP_PROF_MLP_BWD, s);
+    int r = mlp_backward_parts(w, wb, n, x, act, dy, &P, ws, ws_bytes, s);
+    if (r) return r;
+    const Off o = offsets();
+    hipLaunchKernelGGL(k_reduce_grad, dim3((unsigned)((o.total + 255) / 256)), dim3(256), 0, s, P, o, grad);
     prof_end(BP_PROF_MLP_BWD, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

@@ -309,18 +309,19 @@ extern "C" int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v
     void *act = A.take<char>(bp_mlp_act_bytes(batch));
     size_t bwb = bp_mlp_backward_ws_bytes(batch);
     void *bws = A.take<char>(bwb);
-    const int64_t np = bp_mlp_nparams();
     for (int64_t k = 0; k < steps; ++k) {
         hipLaunchKernelGGL(k_gather_rand, dim3(nblk(batch * (BP_MLP_IN + BP_MLP_OUT))), dim3(256), 0, s, batch, ndata,
                            seed, step0 + k, x, targets, xb, tb);
         int e = bp_mlp_forward(w, w_bf16, batch, xb, y, act, stream);
         if (e) return e;
         hipLaunchKernelGGL(k_mse, dim3((unsigned)((batch + 3) / 4)), dim3(256), 0, s, batch, y, tb, mean, std, dy, loss);
-        e = bp_mlp_backward(w, w_bf16, batch, xb, act, dy, grad, bws, bwb, stream);
+        // backward to the gradient's partial sums, reduced inside the Adam step (one launch for both)
+        GradParts parts;
+        e = mlp_backward_parts(w, w_bf16, batch, xb, act, dy, &parts, bws, bwb, s);
         if (e) return e;
         double frac = steps > 1 ? (double)k / (double)(steps - 1) : 1.0;
         float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(kPi * frac)));
-        e = bp_mlp_adam(np, w, m, v, grad, w_bf16, lr, 0.9f, 0.999f, 1e-8f, step0 + k + 1, stream);
+        e = mlp_adam_parts(parts, w, m, v, grad, w_bf16, lr, 0.9f, 0.999f, 1e-8f, step0 + k + 1, s);
         if (e) return e;
     }
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
