@@ -359,11 +359,14 @@ int64_t bp_mlp_nparams(void);
 size_t bp_mlp_act_bytes(int64_t n);
 size_t bp_mlp_backward_ws_bytes(int64_t n);
 /* forward: x [n][16] FP32 features (bp_surrogate_features), y [n][144] FP32;
- * act (bp_mlp_act_bytes(n) bytes) receives the activations backward needs. */
+ * act (bp_mlp_act_bytes(n) bytes) receives the activations backward needs.
+ * y, act and w_bf16 must be 16-byte aligned (BP_E_ARG otherwise). */
 int bp_mlp_forward(const float *w, const uint16_t *w_bf16, int64_t n, const float *x, float *y, void *act,
                    void *stream);
 /* backward: dy [n][144] = dL/dy; grad receives dL/dw (BP_MLP_NPARAMS floats,
- * overwritten).  Deterministic (fixed-order reductions). */
+ * overwritten).  Deterministic (fixed-order reductions).  x, act and w_bf16 16-byte aligned and
+ * ws 256-byte aligned (BP_E_ARG otherwise); ws of at least bp_mlp_backward_ws_bytes(n) bytes
+ * (BP_E_WORKSPACE otherwise). */
 int bp_mlp_backward(const float *w, const uint16_t *w_bf16, int64_t n, const float *x, const void *act,
                     const float *dy, float *grad, void *ws, size_t ws_bytes, void *stream);
 /* Adam step on the FP32 master weights; refreshes the BF16 copy. */
@@ -435,7 +438,8 @@ int bp_surrogate_qtables_exact(const bp_params *p, int64_t n, const double *sol,
  * synchronisation.  Learning rate follows a cosine from lr0 to lr1 over the
  * call; the Adam step counter continues from step0.  loss_rows (nullable,
  * batch floats) receives the last batch's per-row weighted squared error.
- * Workspace: bp_surrogate_train_ws_bytes(batch). */
+ * Workspace: bp_surrogate_train_ws_bytes(batch) bytes, 256-byte aligned; x and w_bf16 16-byte
+ * aligned (BP_E_ARG otherwise). */
 size_t bp_surrogate_train_ws_bytes(int64_t batch);
 int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *grad, const float *mean,
                        const float *std, int64_t ndata, const float *x, const float *targets, int64_t steps,

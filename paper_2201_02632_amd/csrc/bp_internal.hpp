@@ -34,6 +34,32 @@ struct GradParts {
 // (bp_mlp_adam's update with the gradient reduced on the fly; the gradient is also written to g).
 int mlp_backward_parts(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
                        const float *dy, GradParts *P, void *ws, size_t ws_bytes, hipStream_t s);
+// The places in a backward workspace (bp_mlp_backward_ws_bytes(n) bytes) of the BF16 output
+// gradient [n][BP_MLP_OUT] and of the partials; the b4 partials are the producer's of that gradient.
+int mlp_backward_layout(void *ws, size_t ws_bytes, int64_t n, uint16_t **g4, GradParts *P);
+// The backward from the BF16 output gradient and the b4 partials already in the workspace.
+int mlp_backward_g4(const uint16_t *wb, int64_t n, const float *x, const void *act, void *ws, size_t ws_bytes,
+                    hipStream_t s);
+// The forward pass of a training batch drawn by train_row from xdata [ndata][BP_MLP_IN]; the drawn
+// rows are also written to xb [n][BP_MLP_IN] for the backward.
+int mlp_forward_train(const float *w, const uint16_t *wb, int64_t n, int64_t ndata, uint64_t seed, int64_t step,
+                      const float *xdata, float *xb, void *act, float *y, hipStream_t s);
+
+// SplitMix64 (Steele, Lea & Flood 2014), a counter-based generator: row i of the training batch of
+// step `step` is data row (splitmix64(seed ^ splitmix64(step * 0x100000001B3 + i)) >> 11) mod ndata.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ inline int64_t train_row(uint64_t seed, int64_t step, int64_t i, int64_t ndata) {
+    const uint64_t h = splitmix64(seed ^ splitmix64((uint64_t)step * 0x100000001B3ull + (uint64_t)i));
+    return (int64_t)((h >> 11) % (uint64_t)ndata);
+}
+
+// round-to-nearest-even FP32 -> BF16 (gfx950 converts in hardware, v_cvt_pk_bf16_f32)
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 int mlp_adam_parts(const GradParts &P, float *w, float *m, float *v, float *g, uint16_t *wb, float lr, float b1,
                    float b2, float eps, int64_t step, hipStream_t s);
 

@@ -30,8 +30,11 @@ __device__ inline fx4 mfma32(const bf16x8 &a, const bf16x8 &b, const fx4 &c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// round-to-nearest-even FP32 -> BF16 (gfx950 converts in hardware, v_cvt_pk_bf16_f32)
-__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ inline sx4 pack_bf4(float a, float b, float c, float d) {
+    sx4 r;
+    r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
+    return r;
+}
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // SiLU and its derivative with the hardware exponential and reciprocal (about 1 ulp each)
@@ -53,135 +56,296 @@ struct GemmArgs {
     uint16_t *H; int64_t ldh;               // bf16 output (EPI_BIAS_SILU, EPI_DSILU)
     float *F; int64_t ldf;                  // fp32 output (EPI_BIAS: y; EPI_DSILU: g*silu'(z) optional; PARTIAL)
     int64_t kchunk;                         // split-K chunk (PARTIAL), else K
+    float *cs;                              // EPI_DSILU: per-64-row column sums of the output (optional)
+    const float *xs;                        // EPI_DSILU with cs: also sums weighted by inputs x[m][0..2]
 };
 
-// 128x64 output tile per workgroup; wavefront w owns rows 32w..32w+31 (2x4 blocks of 16x16).
-// K advances 32 at a time, one MFMA per block; both operands are staged in LDS with k contiguous
-// (B transposed), so each MFMA fragment is a single 16-byte LDS read.  All vectorised operand dimensions in this
-// library are multiples of 8 (K, the 256/144 layer widths); the batch dimension M is guarded per row.
-constexpr int kBM = 128, kBN = 64, kBK = 32, kLdk = kBK + 8;   // +8 bf16 of padding per row
+// 64x64 output tile per workgroup; the four wavefronts cover it 2x2, 32x32 each (2x2 blocks of 16x16).
+// A tile's K range is staged in LDS kGKC = 256 k at a time, all loads of a stage issued together, so
+// a tile waits on memory once per 256 k rather than once per MFMA step (the K of every product here
+// is 144 or 256, or a split-K slice of the batch of at most 256).  Both operands sit in LDS with k
+// contiguous; an operand contiguous in m (or n) is transposed 8x8 in registers on its way in.  The
+// MFMA takes the B tile as its first operand, so a lane's accumulator holds four consecutive output
+// columns of one row and the epilogue moves them as one vector.  Every operand dimension that is
+// loaded 16 bytes at a time is a multiple of 8 (checked at launch); k beyond K and rows beyond M are
+// zero-filled.
+constexpr int kGM = 64, kGN = 64, kGKC = 256, kGLd = kGKC + 8;   // +8 bf16 of padding per LDS row
+constexpr int kBK = 32;                                           // k per MFMA step
 
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[kBM][kLdk];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[kBN][kLdk];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * kBN;
-    const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
-    const int64_t ke = min(g.K, kb + g.kchunk);
-    fx4 acc[2][4];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 4; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+// Rows r0 .. r0+63 of an operand contiguous in k (element (r, k) at src[r * ld + k]), k in
+// [k0, k0 + 256) clipped to kend, into dst[r][k - k0].
+__device__ inline void stage_kmajor(const uint16_t *__restrict__ src, int64_t ld, int64_t r0, int64_t rend,
+                                    int64_t k0, int64_t kend, uint16_t (*dst)[kGLd], int t) {
+    u16x8 v[8];
     const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
-        // ---- stage A tile (128 x 32) into As[m][k]
-        if (g.a_k == 1) {
-            // rows contiguous in k: thread t loads 16 elements of row t/2
-            int am = t >> 1, ak = (t & 1) * 16;
-            int64_t gm = m0 + am;
-            for (int h = 0; h < 2; ++h) {
-                int64_t gk = k0 + ak + 8 * h;
-                u16x8 v = zero8;
-                if (gm < g.M && gk < ke) v = *(const u16x8 *)(g.A + gm * g.a_m + gk);
-                *(u16x8 *)&As[am][ak + 8 * h] = v;
-            }
-        } else {
-            // columns contiguous in m (a_m == 1): thread t loads 8 m-values at k = t/8 ... twice
-            for (int h = 0; h < 2; ++h) {
-                int e = t + 256 * h;
-                int ak = e >> 4, am = (e & 15) * 8;
-                int64_t gk = k0 + ak, gm = m0 + am;
-                u16x8 v = zero8;
-                if (gk < ke && gm + 7 < g.M) v = *(const u16x8 *)(g.A + gk * g.a_k + gm);
-                else if (gk < ke)
-                    for (int j = 0; j < 8; ++j) v[j] = (gm + j < g.M) ? g.A[gk * g.a_k + gm + j] : (uint16_t)0;
-                for (int j = 0; j < 8; ++j) As[am + j][ak] = v[j];
-            }
-        }
-        // ---- stage B tile (32 x 64) into Bs[n][k]
-        if (g.b_k == 1) {
-            int bn = t >> 2, bk = (t & 3) * 8;
-            int64_t gn = n0 + bn, gk = k0 + bk;
-            u16x8 v = zero8;
-            if (gn < g.N && gk < ke) v = *(const u16x8 *)(g.B + gn * g.b_n + gk);
-            *(u16x8 *)&Bs[bn][bk] = v;
-        } else {
-            int bk = t >> 3, bn = (t & 7) * 8;
-            int64_t gk = k0 + bk, gn = n0 + bn;
-            u16x8 v = zero8;
-            if (gk < ke && gn < g.N) v = *(const u16x8 *)(g.B + gk * g.b_k + gn);
-            for (int j = 0; j < 8; ++j) Bs[bn + j][bk] = v[j];
-        }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = t + 256 * i, r = e >> 5, kq = (e & 31) * 8;
+        const int64_t gr = r0 + r, gk = k0 + kq;
+        v[i] = (gr < rend && gk < kend) ? *(const u16x8 *)(src + gr * ld + gk) : zero8;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int e = t + 256 * i, r = e >> 5, kq = (e & 31) * 8;
+        *(u16x8 *)&dst[r][kq] = v[i];
+    }
+}
+
+// The same for an operand contiguous in r (element (r, k) at src[k * ld + r]): thread t reads the
+// 8x8 block of rows 8 (t % 8) .. + 7 and k 8 (t / 8) .. + 7 and writes it transposed.
+__device__ inline void stage_rmajor(const uint16_t *__restrict__ src, int64_t ld, int64_t r0, int64_t rend,
+                                    int64_t k0, int64_t kend, uint16_t (*dst)[kGLd], int t) {
+    const int rq = (t & 7) * 8, kq = (t >> 3) * 8;
+    const int64_t gr = r0 + rq;
+    u16x8 v[8];
+    const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int64_t gk = k0 + kq + i;
+        v[i] = (gr < rend && gk < kend) ? *(const u16x8 *)(src + gk * ld + gr) : zero8;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        u16x8 o;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = v[i][j];
+        *(u16x8 *)&dst[rq + j][kq] = o;
+    }
+}
+
+__device__ inline void st_bf4(uint16_t *p, float a, float b, float c, float d) { *(sx4 *)p = pack_bf4(a, b, c, d); }
+
+// One 64x64 tile (linear index id over M tiles, then N tiles, then split-K slices).
+// kAK: A contiguous in k (a_k == 1), else in m (a_m == 1); kBK1: B contiguous in k (b_k == 1), else in n.
+template <int EPI, bool kAK, bool kBK1>
+__device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[kGLd], uint16_t (*Bs)[kGLd]) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const int64_t mt = (g.M + kGM - 1) / kGM, nt = (g.N + kGN - 1) / kGN;
+    const int64_t bx = id % mt, by = (id / mt) % nt, bz = id / (mt * nt);
+    const int64_t m0 = bx * kGM, n0 = by * kGN;
+    const int64_t kb = bz * g.kchunk, ke = min(g.K, kb + g.kchunk);
+    fx4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t k0 = kb; k0 < ke; k0 += kGKC) {
+        const int64_t kend = min(ke, k0 + kGKC);
+        if (kAK) stage_kmajor(g.A, g.a_m, m0, g.M, k0, kend, As, t);
+        else stage_rmajor(g.A, g.a_k, m0, g.M, k0, kend, As, t);
+        if (kBK1) stage_kmajor(g.B, g.b_n, n0, g.N, k0, kend, Bs, t);
+        else stage_rmajor(g.B, g.b_k, n0, g.N, k0, kend, Bs, t);
         __syncthreads();
-        {
-            static_assert(kBK == 32, "one 16x16x32 MFMA per block and K step");
-            bf16x8 af[2], bfr[4];
+        const int steps = (int)((kend - k0 + kBK - 1) / kBK);
+        const uint16_t *pa = &As[32 * wm + (lane & 15)][8 * (lane >> 4)];
+        const uint16_t *pb = &Bs[32 * wn + (lane & 15)][8 * (lane >> 4)];
+        for (int ks = 0; ks < steps; ++ks) {
+            bf16x8 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                af[i] = *(const bf16x8 *)(pa + 16 * i * kGLd + kBK * ks);
+                bfr[i] = *(const bf16x8 *)(pb + 16 * i * kGLd + kBK * ks);
+            }
+#pragma unroll
             for (int bi = 0; bi < 2; ++bi)
-                af[bi] = *(const bf16x8 *)&As[32 * w + 16 * bi + (lane & 15)][8 * (lane >> 4)];
-            for (int bj = 0; bj < 4; ++bj)
-                bfr[bj] = *(const bf16x8 *)&Bs[16 * bj + (lane & 15)][8 * (lane >> 4)];
-            for (int bi = 0; bi < 2; ++bi)
-                for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma32(af[bi], bfr[bj], acc[bi][bj]);
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma32(bfr[bj], af[bi], acc[bi][bj]);
         }
         __syncthreads();
     }
-    // epilogue: lane holds D[4*(lane>>4)+j][lane&15] of each 16x16 block
-    for (int bi = 0; bi < 2; ++bi)
-        for (int bj = 0; bj < 4; ++bj)
-            for (int j = 0; j < 4; ++j) {
-                int64_t m = m0 + 32 * w + 16 * bi + 4 * (lane >> 4) + j;
-                int64_t n = n0 + 16 * bj + (lane & 15);
-                if (m >= g.M || n >= g.N) continue;
-                float v = acc[bi][bj][j];
-                if (EPI == EPI_BIAS_SILU) {
-                    float z = v + g.bias[n];
-                    if (g.Z) g.Z[m * g.ldz + n] = z;
-                    g.H[m * g.ldh + n] = f2bf(silu(z));
-                } else if (EPI == EPI_BIAS) {
-                    g.F[m * g.ldf + n] = v + g.bias[n];
-                } else if (EPI == EPI_DSILU) {
-                    float d = v * dsilu(g.Z[m * g.ldz + n]);
-                    if (g.F) g.F[m * g.ldf + n] = d;
-                    g.H[m * g.ldh + n] = f2bf(d);
-                } else {
-                    g.F[(int64_t)blockIdx.z * g.M * g.N + m * g.N + n] = v;
+    // epilogue: acc[bi][bj][j] is row m0 + 32 wm + 16 bi + lane % 16, column n0 + 32 wn + 16 bj + 4 (lane / 16) + j
+    float csum[2][4][1 + BP_MLP_NIN];   // EPI_DSILU column sums over this lane's two rows
+    const int ns = g.xs ? 1 + BP_MLP_NIN : 1;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+        const int64_t m = m0 + 32 * wm + 16 * bi + (lane & 15);
+        const bool mok = m < g.M;
+        float xr[BP_MLP_NIN] = {};
+        if (EPI == EPI_DSILU && g.xs && mok)
+#pragma unroll
+            for (int q = 0; q < BP_MLP_NIN; ++q) xr[q] = g.xs[m * BP_MLP_IN + q];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int64_t n = n0 + 32 * wn + 16 * bj + 4 * (lane >> 4);
+            const bool ok = mok && n < g.N;   // N % 8 == 0: a group of four is all in or all out
+            const fx4 v = acc[bi][bj];
+            if (EPI == EPI_BIAS_SILU) {
+                if (!ok) continue;
+                const fx4 z = v + fx4{g.bias[n], g.bias[n + 1], g.bias[n + 2], g.bias[n + 3]};
+                if (g.Z) *(fx4 *)(g.Z + m * g.ldz + n) = z;
+                st_bf4(g.H + m * g.ldh + n, silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3]));
+            } else if (EPI == EPI_BIAS) {
+                if (!ok) continue;
+                *(fx4 *)(g.F + m * g.ldf + n) = v + fx4{g.bias[n], g.bias[n + 1], g.bias[n + 2], g.bias[n + 3]};
+            } else if (EPI == EPI_DSILU) {
+                fx4 d = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (ok) {
+                    const fx4 z = *(const fx4 *)(g.Z + m * g.ldz + n);
+                    d = fx4{v[0] * dsilu(z[0]), v[1] * dsilu(z[1]), v[2] * dsilu(z[2]), v[3] * dsilu(z[3])};
+                    if (g.F) *(fx4 *)(g.F + m * g.ldf + n) = d;
+                    if (g.H) st_bf4(g.H + m * g.ldh + n, d[0], d[1], d[2], d[3]);
                 }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float prev0 = bi ? csum[bj][j][0] : 0.0f;
+                    csum[bj][j][0] = prev0 + d[j];
+#pragma unroll
+                    for (int q = 0; q < BP_MLP_NIN; ++q) {
+                        const float prev = bi ? csum[bj][j][1 + q] : 0.0f;
+                        csum[bj][j][1 + q] = prev + d[j] * xr[q];
+                    }
+                }
+            } else {
+                if (!ok) continue;
+                *(fx4 *)(g.F + (bz * g.M + m) * g.N + n) = v;
             }
+        }
+    }
+    if (EPI == EPI_DSILU && g.cs) {
+        // per-column sums over the tile's 64 rows (fixed order: the two rows of a lane, a butterfly over
+        // the 16 lanes of one column group, then the two row halves of the tile), written as the chunk
+        // partial cs[(bx * ns + s) * N + n], s = 0 for the plain sum and 1 + q for the sum weighted by
+        // input q
+        float (*red)[1 + BP_MLP_NIN][kGN] = (float (*)[1 + BP_MLP_NIN][kGN])&As[0][0];   // [2][ns][64]
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                for (int s = 0; s < ns; ++s) {
+                    float c = csum[bj][j][s];
+#pragma unroll
+                    for (int o = 1; o < 16; o <<= 1) c += __shfl_xor(c, o, 64);
+                    if ((lane & 15) == 0) red[wm][s][32 * wn + 16 * bj + 4 * (lane >> 4) + j] = c;
+                }
+        __syncthreads();
+        if (t < ns * kGN) {
+            const int s = t / kGN, nl = t % kGN;
+            if (n0 + nl < g.N) g.cs[(bx * ns + s) * g.N + n0 + nl] = red[0][s][nl] + red[1][s][nl];
+        }
+    }
+}
+
+template <int EPI, bool kAK, bool kBK1>
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kGM][kGLd];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kGN][kGLd];
+    gemm_tile<EPI, kAK, kBK1>(g, blockIdx.x, As, Bs);
+}
+
+// Two independent products in one launch: blocks below nb0 take g0's tiles, the rest g1's.
+template <int E0, bool A0, bool B0, int E1, bool A1, bool B1>
+__global__ void __launch_bounds__(256) k_gemm_pair(GemmArgs g0, int64_t nb0, GemmArgs g1) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kGM][kGLd];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kGN][kGLd];
+    if ((int64_t)blockIdx.x < nb0) gemm_tile<E0, A0, B0>(g0, blockIdx.x, As, Bs);
+    else gemm_tile<E1, A1, B1>(g1, blockIdx.x - nb0, As, Bs);
+}
+
+static bool al(const void *p, int bytes) { return ((uintptr_t)p % bytes) == 0; }
+
+// Layout and alignment checks of one product; its tile count in *tiles.
+static int check_gemm(int epi, const GemmArgs &g, int ksplit, int64_t *tiles) {
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || ksplit < 1 || g.kchunk <= 0 || (g.kchunk % kBK)) return BP_E_ARG;
+    if ((int64_t)ksplit * g.kchunk < g.K) return BP_E_ARG;
+    const bool ak = g.a_k == 1, bk = g.b_k == 1;
+    // 16-byte loads along the contiguous dimension of each operand
+    if (ak ? (g.a_m % 8 || g.K % 8) : (g.a_m != 1 || g.a_k % 8 || g.M % 8)) return BP_E_ARG;
+    if (bk ? (g.b_n % 8 || g.K % 8) : (g.b_n != 1 || g.b_k % 8)) return BP_E_ARG;
+    if (g.N % 8 || !al(g.A, 16) || !al(g.B, 16)) return BP_E_ARG;
+    // vector epilogue: four FP32 (16 bytes) or four BF16 (8 bytes) per lane
+    if (epi == EPI_BIAS_SILU && (!g.bias || !g.H || !al(g.H, 8) || g.ldh % 4 || (g.Z && (!al(g.Z, 16) || g.ldz % 4))))
+        return BP_E_ARG;
+    if (epi == EPI_BIAS && (!g.bias || !g.F || !al(g.F, 16) || g.ldf % 4)) return BP_E_ARG;
+    if (epi == EPI_DSILU && (!g.Z || !al(g.Z, 16) || g.ldz % 4 || (g.H && (!al(g.H, 8) || g.ldh % 4)) ||
+                             (g.F && (!al(g.F, 16) || g.ldf % 4))))
+        return BP_E_ARG;
+    if (epi == EPI_PARTIAL && (!g.F || !al(g.F, 16))) return BP_E_ARG;
+    if (g.xs && epi != EPI_DSILU) return BP_E_ARG;
+    *tiles = ((g.M + kGM - 1) / kGM) * ((g.N + kGN - 1) / kGN) * ksplit;
+    return *tiles > 0x7fffffffLL ? BP_E_OVERFLOW : BP_OK;
 }
 
 static int launch_gemm(int epi, const GemmArgs &g, int ksplit, hipStream_t s) {
-    if ((g.M + kBM - 1) / kBM > 0x7fffffffLL) return BP_E_OVERFLOW;
-    // the vectorised staging needs 16-byte aligned rows along the contiguous dimension
-    if ((g.a_k == 1 && (g.a_m % 8)) || (g.a_k != 1 && (g.a_k % 8 || g.a_m != 1)) || (g.b_k == 1 && (g.b_n % 8)) ||
-        (g.b_k != 1 && (g.b_k % 8 || g.b_n != 1)) || (g.kchunk % kBK) ||
-        ((g.a_k == 1 || g.b_k == 1) && (g.K % 8)) || (g.N % 8))
-        return BP_E_ARG;
-    dim3 grid((unsigned)((g.M + kBM - 1) / kBM), (unsigned)((g.N + kBN - 1) / kBN), (unsigned)ksplit);
+    int64_t tiles = 0;
+    const int r = check_gemm(epi, g, ksplit, &tiles);
+    if (r) return r;
+    const dim3 grid((unsigned)tiles);
+    const bool ak = g.a_k == 1, bk = g.b_k == 1;
+#define BP_GEMM_LAUNCH(E)                                                                                   \
+    do {                                                                                                     \
+        if (ak && bk) hipLaunchKernelGGL((k_gemm_bf16<E, true, true>), grid, dim3(256), 0, s, g);           \
+        else if (ak) hipLaunchKernelGGL((k_gemm_bf16<E, true, false>), grid, dim3(256), 0, s, g);           \
+        else if (bk) hipLaunchKernelGGL((k_gemm_bf16<E, false, true>), grid, dim3(256), 0, s, g);           \
+        else hipLaunchKernelGGL((k_gemm_bf16<E, false, false>), grid, dim3(256), 0, s, g);                  \
+    } while (0)
     switch (epi) {
-        case EPI_BIAS_SILU: hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS_SILU>, grid, dim3(256), 0, s, g); break;
-        case EPI_BIAS: hipLaunchKernelGGL(k_gemm_bf16<EPI_BIAS>, grid, dim3(256), 0, s, g); break;
-        case EPI_DSILU: hipLaunchKernelGGL(k_gemm_bf16<EPI_DSILU>, grid, dim3(256), 0, s, g); break;
-        default: hipLaunchKernelGGL(k_gemm_bf16<EPI_PARTIAL>, grid, dim3(256), 0, s, g); break;
+        case EPI_BIAS_SILU: BP_GEMM_LAUNCH(EPI_BIAS_SILU); break;
+        case EPI_BIAS: BP_GEMM_LAUNCH(EPI_BIAS); break;
+        case EPI_DSILU: BP_GEMM_LAUNCH(EPI_DSILU); break;
+        default: BP_GEMM_LAUNCH(EPI_PARTIAL); break;
     }
+#undef BP_GEMM_LAUNCH
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
-// first layer in FP32: z1 = W1 x + b1, h1 = bf16(silu(z1)); x has BP_MLP_IN columns (only BP_MLP_NIN used)
-__global__ void k_layer1(int64_t n, const float *__restrict__ W1, const float *__restrict__ b1,
-                         const float *__restrict__ x, float *__restrict__ Z1, uint16_t *__restrict__ H1) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * BP_MLP_HID) return;
-    int64_t m = e / BP_MLP_HID;
-    int o = (int)(e % BP_MLP_HID);
-    float z = b1[o];
-    for (int k = 0; k < BP_MLP_NIN; ++k) z += W1[o * BP_MLP_IN + k] * x[m * BP_MLP_IN + k];
-    if (Z1) Z1[e] = z;
-    H1[e] = f2bf(silu(z));
+// A weight gradient (EPI_PARTIAL, both operands contiguous in m / n) and the data gradient of the
+// layer below (EPI_DSILU, A contiguous in k, B in n) in one launch: the two read the same upstream
+// gradient and are independent.
+static int launch_wgrad_dgrad(const GemmArgs &gw, int ksplit, const GemmArgs &gd, hipStream_t s) {
+    int64_t tw = 0, td = 0;
+    int r = check_gemm(EPI_PARTIAL, gw, ksplit, &tw);
+    if (r) return r;
+    r = check_gemm(EPI_DSILU, gd, 1, &td);
+    if (r) return r;
+    if (gw.a_k == 1 || gw.b_k == 1 || gd.a_k != 1 || gd.b_k == 1) return BP_E_ARG;
+    if (tw + td > 0x7fffffffLL) return BP_E_OVERFLOW;
+    hipLaunchKernelGGL((k_gemm_pair<EPI_PARTIAL, false, false, EPI_DSILU, true, false>), dim3((unsigned)(tw + td)),
+                       dim3(256), 0, s, gw, tw, gd);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
-// sum over split-K partials in fixed order: out[i] = sum_s part[s][i]
+// first layer in FP32: z1 = W1 x + b1, h1 = bf16(silu(z1)) for outputs o .. o+3 of one row (x has
+// BP_MLP_IN columns, the first BP_MLP_NIN used)
+__device__ inline void layer1_quad(const float *__restrict__ W1, const float *__restrict__ b1, const float *xr, int o,
+                                   float *__restrict__ z1, uint16_t *__restrict__ h1) {
+    fx4 z;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float v = b1[o + j];
+        for (int k = 0; k < BP_MLP_NIN; ++k) v += W1[(o + j) * BP_MLP_IN + k] * xr[k];
+        z[j] = v;
+    }
+    if (z1) *(fx4 *)z1 = z;
+    *(sx4 *)h1 = pack_bf4(silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3]));
+}
+__global__ void k_layer1(int64_t n, const float *__restrict__ W1, const float *__restrict__ b1,
+                         const float *__restrict__ x, float *__restrict__ Z1, uint16_t *__restrict__ H1) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * (BP_MLP_HID / 4)) return;
+    const int64_t m = e / (BP_MLP_HID / 4);
+    const int o = 4 * (int)(e % (BP_MLP_HID / 4));
+    float xr[BP_MLP_NIN];
+    for (int k = 0; k < BP_MLP_NIN; ++k) xr[k] = x[m * BP_MLP_IN + k];
+    layer1_quad(W1, b1, xr, o, Z1 ? Z1 + m * BP_MLP_HID + o : nullptr, H1 + m * BP_MLP_HID + o);
+}
+// the same for the training batch of one step: row m is data row train_row(seed, step, m, ndata),
+// which is also copied to xb
+__global__ void k_layer1_train(int64_t n, int64_t ndata, uint64_t seed, int64_t step, const float *__restrict__ W1,
+                               const float *__restrict__ b1, const float *__restrict__ xdata, float *__restrict__ xb,
+                               float *__restrict__ Z1, uint16_t *__restrict__ H1) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * (BP_MLP_HID / 4)) return;
+    const int64_t m = e / (BP_MLP_HID / 4);
+    const int o = 4 * (int)(e % (BP_MLP_HID / 4));
+    const int64_t r = train_row(seed, step, m, ndata);
+    float xr[BP_MLP_NIN];
+    for (int k = 0; k < BP_MLP_NIN; ++k) xr[k] = xdata[r * BP_MLP_IN + k];
+    if (o < BP_MLP_IN) *(fx4 *)(xb + m * BP_MLP_IN + o) = *(const fx4 *)(xdata + r * BP_MLP_IN + o);
+    layer1_quad(W1, b1, xr, o, Z1 + m * BP_MLP_HID + o, H1 + m * BP_MLP_HID + o);
+}
+
 // Batch reductions in two fixed-order stages.  Stage 1: block (bx, y) covers 64 columns and the rows
 // [64 y, 64 y + 64); its four waves take every fourth row and are combined in wave order, giving
 // part[y][j][c] = sum_m a[m][c] * (j == 0 ? 1 : x[m][j - 1]).  Stage 2 sums the chunks in order.
@@ -253,17 +417,12 @@ using namespace bp;
 extern "C" int64_t bp_mlp_nparams(void) { return offsets().total; }
 extern "C" size_t bp_mlp_act_bytes(int64_t n) { return n < 0 ? 0 : act_bytes(n); }
 
-extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, const float *x, float *y, void *act,
-                              void *stream) {
-    if (n < 0 || !w || !wb || !x || !y || !act) return BP_E_ARG;
-    if (n == 0) return BP_OK;
-    hipStream_t s = (hipStream_t)stream;
-    Off o = offsets();
+namespace bp {
+// layers 2-4 of the forward pass (layer 1 already in the activations)
+static int forward_gemms(const float *w, const uint16_t *wb, int64_t n, void *act, float *y, hipStream_t s) {
+    const Off o = offsets();
     float *Z1 = (float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
     uint16_t *H1 = (uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
-    prof_begin(BP_PROF_MLP_FWD, s);
-    int64_t e = n * BP_MLP_HID;
-    hipLaunchKernelGGL(k_layer1, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, n, w + o.W1, w + o.b1, x, Z1, H1);
     GemmArgs g = {};
     g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID;   // K = 256: one chunk
     // hidden layers: A = h (row-major [n][256]), B(k, n') = W[n'][k]
@@ -275,7 +434,36 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
     r = launch_gemm(EPI_BIAS_SILU, g, 1, s);
     if (r) return r;
     g.N = BP_MLP_OUT; g.A = H3; g.B = wb + o.W4; g.bias = w + o.b4; g.F = y; g.ldf = BP_MLP_OUT; g.Z = nullptr;
-    r = launch_gemm(EPI_BIAS, g, 1, s);
+    g.H = nullptr;
+    return launch_gemm(EPI_BIAS, g, 1, s);
+}
+
+int mlp_forward_train(const float *w, const uint16_t *wb, int64_t n, int64_t ndata, uint64_t seed, int64_t step,
+                      const float *xdata, float *xb, void *act, float *y, hipStream_t s) {
+    if (n <= 0 || ndata <= 0 || !w || !wb || !xdata || !xb || !act || !y) return BP_E_ARG;
+    if (((uintptr_t)xdata | (uintptr_t)xb | (uintptr_t)act) & 15) return BP_E_ARG;
+    const Off o = offsets();
+    float *Z1 = (float *)act;
+    uint16_t *H1 = (uint16_t *)(Z1 + 3 * n * BP_MLP_HID);
+    hipLaunchKernelGGL(k_layer1_train, dim3((unsigned)((n * (BP_MLP_HID / 4) + 255) / 256)), dim3(256), 0, s, n,
+                       ndata, seed, step, w + o.W1, w + o.b1, xdata, xb, Z1, H1);
+    return forward_gemms(w, wb, n, act, y, s);
+}
+}  // namespace bp
+
+extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, const float *x, float *y, void *act,
+                              void *stream) {
+    if (n < 0 || !w || !wb || !x || !y || !act) return BP_E_ARG;
+    if (n == 0) return BP_OK;
+    if (((uintptr_t)y | (uintptr_t)act | (uintptr_t)wb) & 15) return BP_E_ARG;   // 16-byte vector access
+    hipStream_t s = (hipStream_t)stream;
+    Off o = offsets();
+    float *Z1 = (float *)act;
+    uint16_t *H1 = (uint16_t *)(Z1 + 3 * n * BP_MLP_HID);
+    prof_begin(BP_PROF_MLP_FWD, s);
+    hipLaunchKernelGGL(k_layer1, dim3((unsigned)((n * (BP_MLP_HID / 4) + 255) / 256)), dim3(256), 0, s, n, w + o.W1,
+                       w + o.b1, x, Z1, H1);
+    const int r = forward_gemms(w, wb, n, act, y, s);
     prof_end(BP_PROF_MLP_FWD, s);
     return r;
 }
@@ -296,12 +484,6 @@ constexpr int kFKB = BP_MLP_HID / kFK;  // k slices of a hidden-layer input
 constexpr int kFOB = BP_MLP_HID / 16;   // 16-feature output blocks of a hidden layer
 constexpr int kFLd = kFK + 8;           // LDS row stride of a weight k slice in bf16 (32 + 8)
 constexpr int kFALd = BP_MLP_HID + 8;   // LDS row stride of the activations in bf16 (256 + 8)
-
-__device__ inline sx4 pack_bf4(float a, float b, float c, float d) {
-    sx4 r;
-    r[0] = (short)f2bf(a); r[1] = (short)f2bf(b); r[2] = (short)f2bf(c); r[3] = (short)f2bf(d);
-    return r;
-}
 
 // One layer: acc[rb][ob] = sum_k W[16 ob + .][k] h[16 rb + row][k] over the wavefront's rows (held in act),
 // for the first NOB output blocks.
@@ -434,15 +616,16 @@ extern "C" int bp_mlp_infer(const float *w, const uint16_t *wb, int64_t n, const
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
-// split-K factor of the weight-gradient GEMMs (K = batch): about 128 rows per slice, so that a
-// 4096-row batch already gives 256 workgroups
+// split-K factor of the weight-gradient products (K = batch): slices of at most 256 rows, one LDS
+// stage each, up to 64 slices
 static int wgrad_splits(int64_t n) {
-    int64_t ks = (n + 127) / 128;
+    int64_t ks = (n + kGKC - 1) / kGKC;
     return (int)(ks < 1 ? 1 : ks > 64 ? 64 : ks);
 }
 
 // The gradient as partial sums that the consumer reduces in a fixed order (GradParts): all of them
 // coexist, so one kernel reduces every parameter.
+static_assert(kRowChunk == kGM, "the data-gradient epilogue leaves one column partial per 64-row tile");
 static int64_t nchunks(int64_t n) { return (n + kRowChunk - 1) / kRowChunk; }
 
 static size_t part_floats(int64_t n) {
@@ -467,37 +650,35 @@ static GradParts parts_layout(float *part, int64_t n) {
     return P;
 }
 
+// sum_{q < count} p[q * stride] from zero in q order; the loads go out eight at a time ahead of the
+// adds, so a thread waits on memory count / 8 times rather than count times
+__device__ inline float sum_in_order(const float *__restrict__ p, int64_t stride, int count) {
+    float s = 0.0f;
+    int q = 0;
+    for (; q + 8 <= count; q += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p[(int64_t)(q + j) * stride];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; q < count; ++q) s += p[(int64_t)q * stride];
+    return s;
+}
+
 // Gradient of parameter p from the partials, each group summed in slice / chunk order from zero.
 __device__ inline float grad_of(const GradParts &P, const Off &o, int64_t p) {
-    float s = 0.0f;
-    if (p >= o.b4) {
-        const int64_t c = p - o.b4;
-        for (int y = 0; y < P.nchunk; ++y) s += P.b4[(int64_t)y * BP_MLP_OUT + c];
-    } else if (p >= o.W4) {
-        const int64_t i = p - o.W4, cnt = (int64_t)BP_MLP_OUT * BP_MLP_HID;
-        for (int q = 0; q < P.ks; ++q) s += P.w4[q * cnt + i];
-    } else if (p >= o.b3) {
-        const int64_t c = p - o.b3;
-        for (int y = 0; y < P.nchunk; ++y) s += P.b3[(int64_t)y * BP_MLP_HID + c];
-    } else if (p >= o.W3) {
-        const int64_t i = p - o.W3, cnt = (int64_t)BP_MLP_HID * BP_MLP_HID;
-        for (int q = 0; q < P.ks; ++q) s += P.w3[q * cnt + i];
-    } else if (p >= o.b2) {
-        const int64_t c = p - o.b2;
-        for (int y = 0; y < P.nchunk; ++y) s += P.b2[(int64_t)y * BP_MLP_HID + c];
-    } else if (p >= o.W2) {
-        const int64_t i = p - o.W2, cnt = (int64_t)BP_MLP_HID * BP_MLP_HID;
-        for (int q = 0; q < P.ks; ++q) s += P.w2[q * cnt + i];
-    } else if (p >= o.b1) {
-        const int64_t c = p - o.b1;
-        for (int y = 0; y < P.nchunk; ++y) s += P.l1[((int64_t)y * (1 + BP_MLP_NIN)) * BP_MLP_HID + c];
-    } else {
-        const int64_t row = p / BP_MLP_IN, k = p - row * BP_MLP_IN;   // W1[row][k]; inputs past NIN are padding
-        if (k < BP_MLP_NIN)
-            for (int y = 0; y < P.nchunk; ++y)
-                s += P.l1[((int64_t)y * (1 + BP_MLP_NIN) + 1 + k) * BP_MLP_HID + row];
-    }
-    return s;
+    constexpr int64_t kHH = (int64_t)BP_MLP_HID * BP_MLP_HID, kOH = (int64_t)BP_MLP_OUT * BP_MLP_HID;
+    if (p >= o.b4) return sum_in_order(P.b4 + (p - o.b4), BP_MLP_OUT, P.nchunk);
+    if (p >= o.W4) return sum_in_order(P.w4 + (p - o.W4), kOH, P.ks);
+    if (p >= o.b3) return sum_in_order(P.b3 + (p - o.b3), BP_MLP_HID, P.nchunk);
+    if (p >= o.W3) return sum_in_order(P.w3 + (p - o.W3), kHH, P.ks);
+    if (p >= o.b2) return sum_in_order(P.b2 + (p - o.b2), BP_MLP_HID, P.nchunk);
+    if (p >= o.W2) return sum_in_order(P.w2 + (p - o.W2), kHH, P.ks);
+    constexpr int64_t kL1 = (int64_t)(1 + BP_MLP_NIN) * BP_MLP_HID;   // one chunk of the layer-1 sums
+    if (p >= o.b1) return sum_in_order(P.l1 + (p - o.b1), kL1, P.nchunk);
+    const int64_t row = p / BP_MLP_IN, k = p - row * BP_MLP_IN;   // W1[row][k]; inputs past NIN are padding
+    return k < BP_MLP_NIN ? sum_in_order(P.l1 + (1 + k) * BP_MLP_HID + row, kL1, P.nchunk) : 0.0f;
 }
 
 __global__ void k_reduce_grad(GradParts P, Off o, float *__restrict__ grad) {
@@ -523,75 +704,94 @@ __global__ void k_adam_parts(GradParts P, Off o, float *__restrict__ w, float *_
 }
 
 extern "C" size_t bp_mlp_backward_ws_bytes(int64_t n) {
-    return (size_t)n * BP_MLP_OUT * 2 + (size_t)n * BP_MLP_HID * (2 + 4) * 2 + part_floats(n) * 4 + 4096;
+    if (n <= 0) return 0;
+    return ((size_t)n * BP_MLP_OUT * 2 + 255) / 256 * 256 + 2 * (((size_t)n * BP_MLP_HID * 2 + 255) / 256 * 256) +
+           part_floats(n) * 4 + 1024;
 }
 
 namespace bp {
+// workspace: G4 [n][144] bf16, Gb and Gc [n][256] bf16 (the upstream gradients of layers 3 and 2),
+// then the partials
+struct BwdWs {
+    uint16_t *G4, *Gb, *Gc;
+    float *part;
+};
+static bool bwd_ws(void *ws, size_t ws_bytes, int64_t n, BwdWs *B) {
+    Arena A(ws, ws_bytes);
+    B->G4 = A.take<uint16_t>(n * BP_MLP_OUT);
+    B->Gb = A.take<uint16_t>(n * BP_MLP_HID);
+    B->Gc = A.take<uint16_t>(n * BP_MLP_HID);
+    B->part = A.take<float>((int64_t)part_floats(n));
+    return A.fits() && ws_bytes >= bp_mlp_backward_ws_bytes(n);
+}
+
+int mlp_backward_layout(void *ws, size_t ws_bytes, int64_t n, uint16_t **g4, GradParts *P) {
+    if (n <= 0 || !ws || ((uintptr_t)ws % 256)) return BP_E_ARG;
+    BwdWs B;
+    if (!bwd_ws(ws, ws_bytes, n, &B)) return BP_E_WORKSPACE;
+    *g4 = B.G4;
+    *P = parts_layout(B.part, n);
+    return BP_OK;
+}
+
+// Three launches, each the weight gradient of one layer beside the data gradient of the layer below
+// (whose epilogue also leaves the bias partials, and for layer 1 the input-weighted sums).
+int mlp_backward_g4(const uint16_t *wb, int64_t n, const float *x, const void *act, void *ws, size_t ws_bytes,
+                    hipStream_t s) {
+    if (n <= 0 || !wb || !x || !act || !ws) return BP_E_ARG;
+    if ((((uintptr_t)x | (uintptr_t)act | (uintptr_t)wb) & 15) || ((uintptr_t)ws % 256)) return BP_E_ARG;
+    BwdWs B;
+    if (!bwd_ws(ws, ws_bytes, n, &B)) return BP_E_WORKSPACE;
+    const GradParts P = parts_layout(B.part, n);
+    const Off o = offsets();
+    const float *Z1 = (const float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
+    const uint16_t *H1 = (const uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
+    const int ks = P.ks;
+    const int64_t kchunk = (((n + ks - 1) / ks + kBK - 1) / kBK) * kBK;
+    // dW = G^T h over the batch in ks split-K slices: A(m = o, k = s) = G[s][o], B(k = s, n = i) = h[s][i]
+    auto wgrad = [&](const uint16_t *Gt, int64_t ldg, int64_t rows, const uint16_t *Hin, const float *dst) {
+        GemmArgs g = {};
+        g.M = rows; g.N = BP_MLP_HID; g.K = n; g.kchunk = kchunk;
+        g.A = Gt; g.a_m = 1; g.a_k = ldg;
+        g.B = Hin; g.b_k = BP_MLP_HID; g.b_n = 1;
+        g.F = (float *)dst;
+        return g;
+    };
+    // d = (G W) * silu'(z): A(s, o) = G[s][o], B(o, i) = W[o][i]; column sums into cs
+    auto dgrad = [&](const uint16_t *Gin, int64_t kdim, const uint16_t *W, const float *Z, uint16_t *Gout,
+                     const float *cs, const float *xs) {
+        GemmArgs g = {};
+        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = ((kdim + kBK - 1) / kBK) * kBK;
+        g.A = Gin; g.a_m = kdim; g.a_k = 1;
+        g.B = W; g.b_k = BP_MLP_HID; g.b_n = 1;
+        g.Z = (float *)Z; g.ldz = BP_MLP_HID; g.H = Gout; g.ldh = BP_MLP_HID;
+        g.cs = (float *)cs; g.xs = xs;
+        return g;
+    };
+    int r = launch_wgrad_dgrad(wgrad(B.G4, BP_MLP_OUT, BP_MLP_OUT, H3, P.w4), ks,
+                               dgrad(B.G4, BP_MLP_OUT, wb + o.W4, Z3, B.Gb, P.b3, nullptr), s);
+    if (r) return r;
+    r = launch_wgrad_dgrad(wgrad(B.Gb, BP_MLP_HID, BP_MLP_HID, H2, P.w3), ks,
+                           dgrad(B.Gb, BP_MLP_HID, wb + o.W3, Z2, B.Gc, P.b2, nullptr), s);
+    if (r) return r;
+    // layer 1: only the sums of d1 are needed (db1 and dW1), d1 itself is not stored
+    return launch_wgrad_dgrad(wgrad(B.Gc, BP_MLP_HID, BP_MLP_HID, H1, P.w2), ks,
+                              dgrad(B.Gc, BP_MLP_HID, wb + o.W2, Z1, nullptr, P.l1, x), s);
+}
+
 // The backward pass up to the partials (workspace as bp_mlp_backward); *P receives their places.
 int mlp_backward_parts(const float *w, const uint16_t *wb, int64_t n, const float *x, const void *act,
                        const float *dy, GradParts *P, void *ws, size_t ws_bytes, hipStream_t s) {
     if (n <= 0 || !w || !wb || !x || !act || !dy || !ws) return BP_E_ARG;
-    if (ws_bytes < bp_mlp_backward_ws_bytes(n)) return BP_E_WORKSPACE;
-    Off o = offsets();
-    const float *Z1 = (const float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
-    const uint16_t *H1 = (const uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
-    const int ks = wgrad_splits(n);
-    const int64_t kchunk = (((n + ks - 1) / ks + 31) / 32) * 32;
-    Arena A(ws, ws_bytes);
-    uint16_t *G4 = A.take<uint16_t>(n * BP_MLP_OUT);
-    uint16_t *Gb = A.take<uint16_t>(n * BP_MLP_HID), *Gc = A.take<uint16_t>(n * BP_MLP_HID);
-    float *Df = A.take<float>(n * BP_MLP_HID), *Dg = A.take<float>(n * BP_MLP_HID);
-    float *part = A.take<float>((int64_t)part_floats(n));
-    *P = parts_layout(part, n);
+    uint16_t *G4 = nullptr;
+    int r = mlp_backward_layout(ws, ws_bytes, n, &G4, P);
+    if (r) return r;
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * BP_MLP_OUT + 255) / 256)), dim3(256), 0, s, n * BP_MLP_OUT, dy,
                        G4);
-    // dW = g^T h over the batch, in ks split-K slices
-    auto wgrad = [&](const uint16_t *Gt, int64_t ldg, int64_t rows, const uint16_t *Hin, const float *dst) -> int {
-        GemmArgs g = {};
-        g.M = rows; g.N = BP_MLP_HID; g.K = n; g.kchunk = kchunk;
-        g.A = Gt; g.a_m = 1; g.a_k = ldg;          // A(m=o, k=s) = G[s][o]
-        g.B = Hin; g.b_k = BP_MLP_HID; g.b_n = 1;  // B(k=s, n=i) = h[s][i]
-        g.F = (float *)dst;
-        return launch_gemm(EPI_PARTIAL, g, ks, s);
-    };
-    const int nchunk = P->nchunk;
-    auto colsum = [&](const float *a, int cols, const float *dst) -> int {
-        hipLaunchKernelGGL(k_colsum_part<1>, dim3((cols + 63) / 64, nchunk), dim3(256), 0, s, n, cols, a,
-                           (const float *)nullptr, (float *)dst);
-        return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
-    };
-    int r = wgrad(G4, BP_MLP_OUT, BP_MLP_OUT, H3, P->w4);
-    if (r) return r;
-    r = colsum(dy, BP_MLP_OUT, P->b4);
-    if (r) return r;
-    // dh3 = g4 W4 ; d3 = dh3 * silu'(z3)
-    auto dgrad = [&](const uint16_t *Gin, int64_t kdim, const uint16_t *W, const float *Z, uint16_t *Gout,
-                     float *Dout) -> int {
-        GemmArgs g = {};
-        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = ((kdim + 31) / 32) * 32;
-        g.A = Gin; g.a_m = kdim; g.a_k = 1;               // A(s, o) = G[s][o]
-        g.B = W; g.b_k = BP_MLP_HID; g.b_n = 1;           // B(o, i) = W[o][i]
-        g.Z = (float *)Z; g.ldz = BP_MLP_HID; g.H = Gout; g.ldh = BP_MLP_HID; g.F = Dout; g.ldf = BP_MLP_HID;
-        return launch_gemm(EPI_DSILU, g, 1, s);
-    };
-    r = dgrad(G4, BP_MLP_OUT, wb + o.W4, Z3, Gb, Df);
-    if (r) return r;
-    r = colsum(Df, BP_MLP_HID, P->b3);
-    if (r) return r;
-    r = wgrad(Gb, BP_MLP_HID, BP_MLP_HID, H2, P->w3);
-    if (r) return r;
-    r = dgrad(Gb, BP_MLP_HID, wb + o.W3, Z2, Gc, Dg);
-    if (r) return r;
-    r = colsum(Dg, BP_MLP_HID, P->b2);
-    if (r) return r;
-    r = wgrad(Gc, BP_MLP_HID, BP_MLP_HID, H1, P->w2);
-    if (r) return r;
-    r = dgrad(Gc, BP_MLP_HID, wb + o.W2, Z1, Gb, Df);   // d1 in Df (fp32); its bf16 copy is unused
-    if (r) return r;
-    // db1 and dW1 in one pass over d1
-    hipLaunchKernelGGL(k_colsum_part<1 + BP_MLP_NIN>, dim3(BP_MLP_HID / 64, nchunk), dim3(256), 0, s, n, BP_MLP_HID,
-                       Df, x, (float *)P->l1);
-    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+    hipLaunchKernelGGL(k_colsum_part<1>, dim3((BP_MLP_OUT + 63) / 64, P->nchunk), dim3(256), 0, s, n, BP_MLP_OUT, dy,
+                       (const float *)nullptr, (float *)P->b4);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    return mlp_backward_g4(wb, n, x, act, ws, ws_bytes, s);
 }
 
 // Adam from the partials of mlp_backward_parts, the bias corrections for `step` (>= 1).

@@ -133,24 +133,6 @@ __global__ void k_gather(int64_t n, int cols, const float *__restrict__ in, cons
 
 // counter-based batch sampling (SplitMix64 of seed, step, row): row i of the batch is data row
 // (hash >> 11) mod n_data
-__device__ inline uint64_t splitmix64(uint64_t x) {
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    return x ^ (x >> 31);
-}
-__global__ void k_gather_rand(int64_t nb, int64_t ndata, uint64_t seed, int64_t step, const float *__restrict__ x,
-                              const float *__restrict__ t, float *__restrict__ xb, float *__restrict__ tb) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nb * (BP_MLP_IN + BP_MLP_OUT)) return;
-    int64_t i = e / (BP_MLP_IN + BP_MLP_OUT);
-    int c = (int)(e % (BP_MLP_IN + BP_MLP_OUT));
-    uint64_t hsh = splitmix64(seed ^ splitmix64((uint64_t)step * 0x100000001B3ull + (uint64_t)i));
-    int64_t r = (int64_t)((hsh >> 11) % (uint64_t)ndata);
-    if (c < BP_MLP_IN) xb[i * BP_MLP_IN + c] = x[r * BP_MLP_IN + c];
-    else tb[i * BP_MLP_OUT + (c - BP_MLP_IN)] = t[r * BP_MLP_OUT + (c - BP_MLP_IN)];
-}
-
 // loss gradient for the standardised targets, one wave per row (lanes stride the columns);
 // rows with a non-finite target contribute nothing
 __global__ void k_mse(int64_t n, const float *__restrict__ y, const float *__restrict__ t,
@@ -190,6 +172,91 @@ __global__ void k_mse(int64_t n, const float *__restrict__ y, const float *__res
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) loss[i] = acc;
+}
+
+// The loss of one training step, fused: rows drawn by train_row (targets gathered here), the loss
+// gradient written straight as the BF16 operand of the backward, and the b4 gradient left as
+// per-64-row column partials b4p[chunk][c] (wavefront w of the chunk's eight takes rows w, w + 8, ..,
+// in order, and the wavefronts are combined in order).  Same weights and formula as k_mse.  One
+// workgroup of 512 threads per 64-row chunk.
+constexpr int kMseWaves = 8, kMseRows = 64 / kMseWaves;
+__global__ void __launch_bounds__(512) k_mse_train(int64_t n, int64_t ndata, uint64_t seed, int64_t step,
+                                                   const float *__restrict__ y, const float *__restrict__ tdata,
+                                                   const float *__restrict__ mean, const float *__restrict__ sd,
+                                                   uint16_t *__restrict__ g4, float *__restrict__ b4p,
+                                                   float *__restrict__ loss) {
+    __shared__ float red[kMseWaves][BP_MLP_OUT];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int kPer = (BP_MLP_OUT + 63) / 64;
+    const float kAuxWeight = 16.0f;
+    const float wsum = 2.0f * BP_MLP_NQ + 3.0f * kAuxWeight;
+    const float scale = 2.0f / ((float)n * wsum);
+    float mc[kPer], sdc[kPer], wc[kPer], col[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int c = lane + 64 * j;
+        const bool used = c < BP_MLP_NOUT;
+        mc[j] = used ? mean[c] : 0.0f;
+        sdc[j] = used ? sd[c] : 1.0f;
+        wc[j] = (c >= 2 * BP_MLP_NQ) ? kAuxWeight : 1.0f;
+        col[j] = 0.0f;
+    }
+    const int64_t r0 = (int64_t)blockIdx.x * 64 + w;   // this wavefront's rows: r0 + kMseWaves q
+    // lane q < kMseRows draws the data row of row q (one 64-bit modulo per lane), read back by shuffles
+    const int64_t mine = r0 + kMseWaves * (int64_t)lane;
+    const int64_t src_l = (lane < kMseRows && mine < n) ? train_row(seed, step, mine, ndata) : 0;
+    float tv[kMseRows][kPer], yv[kMseRows][kPer];
+#pragma unroll
+    for (int q = 0; q < kMseRows; ++q) {
+        const int64_t i = r0 + kMseWaves * q;
+        const int64_t src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)(src_l >> 32), q, 64) << 32) |
+                                      (uint32_t)__shfl((int)src_l, q, 64));
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int c = lane + 64 * j;
+            const bool ld = i < n && c < BP_MLP_NOUT;
+            tv[q][j] = ld ? tdata[src * BP_MLP_OUT + c] : 0.0f;
+            yv[q][j] = ld ? y[i * BP_MLP_OUT + c] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kMseRows; ++q) {
+        const int64_t i = r0 + kMseWaves * q;
+        if (i >= n) break;   // wave-uniform
+        bool fin = true;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) fin = fin && isfinite(tv[q][j]);
+        const bool ok = __all(fin);
+        float acc = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int c = lane + 64 * j;
+            if (c >= BP_MLP_OUT) break;
+            float d = 0.0f;
+            if (ok && c < BP_MLP_NOUT) {
+                const float r = yv[q][j] - (tv[q][j] - mc[j]) / sdc[j];
+                acc += wc[j] * r * r;
+                d = scale * wc[j] * r;
+            }
+            g4[i * BP_MLP_OUT + c] = f2bf(d);
+            col[j] += d;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) loss[i] = acc;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int c = lane + 64 * j;
+        if (c < BP_MLP_OUT) red[w][c] = col[j];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < BP_MLP_OUT; c += blockDim.x) {
+        float t = red[0][c];
+#pragma unroll
+        for (int v = 1; v < kMseWaves; ++v) t += red[v][c];
+        b4p[(int64_t)blockIdx.x * BP_MLP_OUT + c] = t;
+    }
 }
 
 // network output -> q-tables (G values): one thread per (halo, 4 q nodes), 16-byte loads and
@@ -289,10 +356,12 @@ extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y,
 
 extern "C" size_t bp_surrogate_train_ws_bytes(int64_t batch) {
     if (batch <= 0) return 0;
-    return (size_t)batch * (BP_MLP_IN + 3 * BP_MLP_OUT + 1) * 4 + bp_mlp_act_bytes(batch) +
+    return (size_t)batch * (BP_MLP_IN + BP_MLP_OUT + 1) * 4 + bp_mlp_act_bytes(batch) +
            bp_mlp_backward_ws_bytes(batch) + 8 * 256;
 }
 
+// One step: forward of the drawn batch (layer 1 gathers its rows), the fused loss, the backward in
+// three launches, and Adam from the gradient's partials: nine launches.
 extern "C" int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v, float *grad, const float *mean,
                                   const float *std, int64_t ndata, const float *x, const float *targets, int64_t steps,
                                   int64_t batch, float lr0, float lr1, uint64_t seed, int64_t step0, float *loss_rows,
@@ -301,23 +370,25 @@ extern "C" int bp_surrogate_train(float *w, uint16_t *w_bf16, float *m, float *v
         batch <= 0 || step0 < 0)
         return BP_E_ARG;
     if (ws_bytes < bp_surrogate_train_ws_bytes(batch)) return BP_E_WORKSPACE;
+    if (((uintptr_t)ws % 256) || ((uintptr_t)x % 16)) return BP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
     Arena A(ws, ws_bytes);
-    float *xb = A.take<float>(batch * BP_MLP_IN), *tb = A.take<float>(batch * BP_MLP_OUT);
-    float *y = A.take<float>(batch * BP_MLP_OUT), *dy = A.take<float>(batch * BP_MLP_OUT);
+    float *xb = A.take<float>(batch * BP_MLP_IN), *y = A.take<float>(batch * BP_MLP_OUT);
     float *loss = loss_rows ? loss_rows : A.take<float>(batch);
     void *act = A.take<char>(bp_mlp_act_bytes(batch));
-    size_t bwb = bp_mlp_backward_ws_bytes(batch);
+    const size_t bwb = bp_mlp_backward_ws_bytes(batch);
     void *bws = A.take<char>(bwb);
+    uint16_t *g4 = nullptr;
+    GradParts parts;
+    int e = mlp_backward_layout(bws, bwb, batch, &g4, &parts);
+    if (e) return e;
+    const unsigned chunks = (unsigned)((batch + 63) / 64);
     for (int64_t k = 0; k < steps; ++k) {
-        hipLaunchKernelGGL(k_gather_rand, dim3(nblk(batch * (BP_MLP_IN + BP_MLP_OUT))), dim3(256), 0, s, batch, ndata,
-                           seed, step0 + k, x, targets, xb, tb);
-        int e = bp_mlp_forward(w, w_bf16, batch, xb, y, act, stream);
+        e = mlp_forward_train(w, w_bf16, batch, ndata, seed, step0 + k, x, xb, act, y, s);
         if (e) return e;
-        hipLaunchKernelGGL(k_mse, dim3((unsigned)((batch + 3) / 4)), dim3(256), 0, s, batch, y, tb, mean, std, dy, loss);
-        // backward to the gradient's partial sums, reduced inside the Adam step (one launch for both)
-        GradParts parts;
-        e = mlp_backward_parts(w, w_bf16, batch, xb, act, dy, &parts, bws, bwb, s);
+        hipLaunchKernelGGL(k_mse_train, dim3(chunks), dim3(64 * kMseWaves), 0, s, batch, ndata, seed, step0 + k, y, targets, mean,
+                           std, g4, (float *)parts.b4, loss);
+        e = mlp_backward_g4(w_bf16, batch, xb, act, bws, bwb, s);
         if (e) return e;
         double frac = steps > 1 ? (double)k / (double)(steps - 1) : 1.0;
         float lr = (float)(lr1 + 0.5 * (lr0 - lr1) * (1.0 + cos(kPi * frac)));
