@@ -41,7 +41,7 @@ int mlp_backward_layout(void *ws, size_t ws_bytes, int64_t n, uint16_t **g4, Gra
 int mlp_backward_g4(const uint16_t *wb, int64_t n, const float *x, const void *act, void *ws, size_t ws_bytes,
                     hipStream_t s);
 // The forward pass of a training batch drawn by train_row from xdata [ndata][BP_MLP_IN]; the drawn
-// rows are also written to xb [n][BP_MLP_IN] for the backward.
+// inputs (the first BP_MLP_NIN of each row) are also written to xb [n][BP_MLP_IN] for the backward.
 int mlp_forward_train(const float *w, const uint16_t *wb, int64_t n, int64_t ndata, uint64_t seed, int64_t step,
                       const float *xdata, float *xb, void *act, float *y, hipStream_t s);
 

@@ -58,6 +58,13 @@ struct GemmArgs {
     int64_t kchunk;                         // split-K chunk (PARTIAL), else K
     float *cs;                              // EPI_DSILU: per-64-row column sums of the output (optional)
     const float *xs;                        // EPI_DSILU with cs: also sums weighted by inputs x[m][0..2]
+    int64_t ks;                             // split-K slices (the grid's third tile dimension)
+    // Layer 1 fused into the A staging of layer 2 (A = h1 computed from x, K = 256):
+    const float *x1;                        // inputs [.][BP_MLP_IN]: row m, or row train_row(m) if ndata > 0
+    const float *W1, *b1;
+    float *Z1; uint16_t *H1;                // z1 and h1 [M][256], stored by the tiles of the first column block
+    float *xb;                              // with ndata > 0: the drawn rows' first BP_MLP_NIN inputs, [M][BP_MLP_IN]
+    int64_t ndata, step; uint64_t seed;
 };
 
 // 64x64 output tile per workgroup; the four wavefronts cover it 2x2, 32x32 each (2x2 blocks of 16x16).
@@ -117,13 +124,93 @@ __device__ inline void stage_rmajor(const uint16_t *__restrict__ src, int64_t ld
 
 __device__ inline void st_bf4(uint16_t *p, float a, float b, float c, float d) { *(sx4 *)p = pack_bf4(a, b, c, d); }
 
+// first layer in FP32: z1 = b1 + sum_q W1[.][q] x[q] (in q order), h1 = bf16(silu(z1))
+__device__ inline float layer1_z(float b, const float (&wq)[BP_MLP_NIN], const float (&x)[BP_MLP_NIN]) {
+    float v = b;
+#pragma unroll
+    for (int q = 0; q < BP_MLP_NIN; ++q) v += wq[q] * x[q];
+    return v;
+}
+
+// The A tile of layer 2 (rows r0 .. r0+63, all 256 k) computed from the inputs instead of loaded:
+// thread t always makes the eight outputs k = 8 (t % 32) .. + 7, for rows t / 32 + 8 i.  With
+// store set, z1 and h1 (and the drawn rows' first BP_MLP_NIN inputs) also go to memory for the
+// backward.  All input loads are issued before the first store.
+__device__ inline void stage_layer1(const GemmArgs &g, int64_t r0, bool store, uint16_t (*dst)[kGLd], int t) {
+    const int kq = (t & 31) * 8, lane = t & 63;
+    float bv[8], wv[8][BP_MLP_NIN];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        bv[j] = g.b1[kq + j];
+#pragma unroll
+        for (int q = 0; q < BP_MLP_NIN; ++q) wv[j][q] = g.W1[(kq + j) * BP_MLP_IN + q];
+    }
+    // the wavefront's rows are t / 32 + 8 i for its two values of t / 32: lane l < 16 draws the data
+    // row of row (2 (t / 64) + l % 2) + 8 (l / 2), read back by shuffles
+    int64_t src_l = 0;
+    if (g.ndata > 0 && lane < 16) {
+        const int64_t m = r0 + 2 * (t >> 6) + (lane & 1) + 8 * (lane >> 1);
+        if (m < g.M) src_l = train_row(g.seed, g.step, m, g.ndata);
+    }
+    float xr[8][BP_MLP_NIN];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int64_t m = r0 + (t >> 5) + 8 * i;
+        int64_t src = m;
+        if (g.ndata > 0) {
+            const int from = ((t >> 5) & 1) + 2 * i;
+            src = (int64_t)(((uint64_t)(uint32_t)__shfl((int)(src_l >> 32), from, 64) << 32) |
+                            (uint32_t)__shfl((int)src_l, from, 64));
+        }
+#pragma unroll
+        for (int q = 0; q < BP_MLP_NIN; ++q) xr[i][q] = m < g.M ? g.x1[src * BP_MLP_IN + q] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int r = (t >> 5) + 8 * i;
+        const int64_t m = r0 + r;
+        u16x8 h = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (m < g.M) {
+            fx4 z0, z1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                z0[j] = layer1_z(bv[j], wv[j], xr[i]);
+                z1[j] = layer1_z(bv[4 + j], wv[4 + j], xr[i]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                h[j] = f2bf(silu(z0[j]));
+                h[4 + j] = f2bf(silu(z1[j]));
+            }
+            if (store) {
+                *(fx4 *)(g.Z1 + m * BP_MLP_HID + kq) = z0;
+                *(fx4 *)(g.Z1 + m * BP_MLP_HID + kq + 4) = z1;
+                *(u16x8 *)(g.H1 + m * BP_MLP_HID + kq) = h;
+                if (g.xb && kq == 0)
+#pragma unroll
+                    for (int q = 0; q < BP_MLP_NIN; ++q) g.xb[m * BP_MLP_IN + q] = xr[i][q];
+            }
+        }
+        *(u16x8 *)&dst[r][kq] = h;
+    }
+}
+
 // One 64x64 tile (linear index id over M tiles, then N tiles, then split-K slices).
 // kAK: A contiguous in k (a_k == 1), else in m (a_m == 1); kBK1: B contiguous in k (b_k == 1), else in n.
-template <int EPI, bool kAK, bool kBK1>
+// Workgroups are dealt to the eight XCDs round-robin by id.  With ks a multiple of 8 the split-K
+// slices are dealt out whole: all tiles of slice bz run on XCD bz % 8, so each slice's operand rows
+// are fetched into one L2 only.  Otherwise the tiles of one row block (all column blocks) share an XCD
+// whenever the number of row blocks is a multiple of 8.
+template <int EPI, bool kAK, bool kBK1, bool kL1 = false>
 __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[kGLd], uint16_t (*Bs)[kGLd]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
     const int64_t mt = (g.M + kGM - 1) / kGM, nt = (g.N + kGN - 1) / kGN;
-    const int64_t bx = id % mt, by = (id / mt) % nt, bz = id / (mt * nt);
+    int64_t tile = id % (mt * nt), bz = id / (mt * nt);
+    if (g.ks % 8 == 0) {
+        bz = (id & 7) + 8 * ((id >> 3) / (mt * nt));
+        tile = (id >> 3) % (mt * nt);
+    }
+    const int64_t bx = tile % mt, by = tile / mt;
     const int64_t m0 = bx * kGM, n0 = by * kGN;
     const int64_t kb = bz * g.kchunk, ke = min(g.K, kb + g.kchunk);
     fx4 acc[2][2];
@@ -133,7 +220,8 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
         for (int b = 0; b < 2; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int64_t k0 = kb; k0 < ke; k0 += kGKC) {
         const int64_t kend = min(ke, k0 + kGKC);
-        if (kAK) stage_kmajor(g.A, g.a_m, m0, g.M, k0, kend, As, t);
+        if (kL1) stage_layer1(g, m0, by == 0, As, t);
+        else if (kAK) stage_kmajor(g.A, g.a_m, m0, g.M, k0, kend, As, t);
         else stage_rmajor(g.A, g.a_k, m0, g.M, k0, kend, As, t);
         if (kBK1) stage_kmajor(g.B, g.b_n, n0, g.N, k0, kend, Bs, t);
         else stage_rmajor(g.B, g.b_k, n0, g.N, k0, kend, Bs, t);
@@ -227,11 +315,11 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
     }
 }
 
-template <int EPI, bool kAK, bool kBK1>
+template <int EPI, bool kAK, bool kBK1, bool kL1 = false>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint16_t As[kGM][kGLd];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[kGN][kGLd];
-    gemm_tile<EPI, kAK, kBK1>(g, blockIdx.x, As, Bs);
+    gemm_tile<EPI, kAK, kBK1, kL1>(g, blockIdx.x, As, Bs);
 }
 
 // Two independent products in one launch: blocks below nb0 take g0's tiles, the rest g1's.
@@ -247,7 +335,8 @@ static bool al(const void *p, int bytes) { return ((uintptr_t)p % bytes) == 0; }
 
 // Layout and alignment checks of one product; its tile count in *tiles.
 static int check_gemm(int epi, const GemmArgs &g, int ksplit, int64_t *tiles) {
-    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || ksplit < 1 || g.kchunk <= 0 || (g.kchunk % kBK)) return BP_E_ARG;
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0 || ksplit < 1 || g.ks != ksplit || g.kchunk <= 0 || (g.kchunk % kBK))
+        return BP_E_ARG;
     if ((int64_t)ksplit * g.kchunk < g.K) return BP_E_ARG;
     const bool ak = g.a_k == 1, bk = g.b_k == 1;
     // 16-byte loads along the contiguous dimension of each operand
@@ -304,46 +393,6 @@ static int launch_wgrad_dgrad(const GemmArgs &gw, int ksplit, const GemmArgs &gd
     hipLaunchKernelGGL((k_gemm_pair<EPI_PARTIAL, false, false, EPI_DSILU, true, false>), dim3((unsigned)(tw + td)),
                        dim3(256), 0, s, gw, tw, gd);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
-}
-
-// first layer in FP32: z1 = W1 x + b1, h1 = bf16(silu(z1)) for outputs o .. o+3 of one row (x has
-// BP_MLP_IN columns, the first BP_MLP_NIN used)
-__device__ inline void layer1_quad(const float *__restrict__ W1, const float *__restrict__ b1, const float *xr, int o,
-                                   float *__restrict__ z1, uint16_t *__restrict__ h1) {
-    fx4 z;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        float v = b1[o + j];
-        for (int k = 0; k < BP_MLP_NIN; ++k) v += W1[(o + j) * BP_MLP_IN + k] * xr[k];
-        z[j] = v;
-    }
-    if (z1) *(fx4 *)z1 = z;
-    *(sx4 *)h1 = pack_bf4(silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3]));
-}
-__global__ void k_layer1(int64_t n, const float *__restrict__ W1, const float *__restrict__ b1,
-                         const float *__restrict__ x, float *__restrict__ Z1, uint16_t *__restrict__ H1) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * (BP_MLP_HID / 4)) return;
-    const int64_t m = e / (BP_MLP_HID / 4);
-    const int o = 4 * (int)(e % (BP_MLP_HID / 4));
-    float xr[BP_MLP_NIN];
-    for (int k = 0; k < BP_MLP_NIN; ++k) xr[k] = x[m * BP_MLP_IN + k];
-    layer1_quad(W1, b1, xr, o, Z1 ? Z1 + m * BP_MLP_HID + o : nullptr, H1 + m * BP_MLP_HID + o);
-}
-// the same for the training batch of one step: row m is data row train_row(seed, step, m, ndata),
-// which is also copied to xb
-__global__ void k_layer1_train(int64_t n, int64_t ndata, uint64_t seed, int64_t step, const float *__restrict__ W1,
-                               const float *__restrict__ b1, const float *__restrict__ xdata, float *__restrict__ xb,
-                               float *__restrict__ Z1, uint16_t *__restrict__ H1) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * (BP_MLP_HID / 4)) return;
-    const int64_t m = e / (BP_MLP_HID / 4);
-    const int o = 4 * (int)(e % (BP_MLP_HID / 4));
-    const int64_t r = train_row(seed, step, m, ndata);
-    float xr[BP_MLP_NIN];
-    for (int k = 0; k < BP_MLP_NIN; ++k) xr[k] = xdata[r * BP_MLP_IN + k];
-    if (o < BP_MLP_IN) *(fx4 *)(xb + m * BP_MLP_IN + o) = *(const fx4 *)(xdata + r * BP_MLP_IN + o);
-    layer1_quad(W1, b1, xr, o, Z1 + m * BP_MLP_HID + o, H1 + m * BP_MLP_HID + o);
 }
 
 // Batch reductions in two fixed-order stages.  Stage 1: block (bx, y) covers 64 columns and the rows
@@ -418,19 +467,31 @@ extern "C" int64_t bp_mlp_nparams(void) { return offsets().total; }
 extern "C" size_t bp_mlp_act_bytes(int64_t n) { return n < 0 ? 0 : act_bytes(n); }
 
 namespace bp {
-// layers 2-4 of the forward pass (layer 1 already in the activations)
-static int forward_gemms(const float *w, const uint16_t *wb, int64_t n, void *act, float *y, hipStream_t s) {
+// The forward pass in three launches: layers 1 and 2 (layer 1 made in layer 2's operand staging),
+// 3 and 4.  Input row m is x[m], or x[train_row(seed, step, m, ndata)] if ndata > 0 (the drawn
+// rows' first BP_MLP_NIN inputs then go to xb).
+static int forward(const float *w, const uint16_t *wb, int64_t n, const float *x, int64_t ndata, uint64_t seed,
+                   int64_t step, float *xb, void *act, float *y, hipStream_t s) {
     const Off o = offsets();
     float *Z1 = (float *)act, *Z2 = Z1 + n * BP_MLP_HID, *Z3 = Z2 + n * BP_MLP_HID;
     uint16_t *H1 = (uint16_t *)(Z3 + n * BP_MLP_HID), *H2 = H1 + n * BP_MLP_HID, *H3 = H2 + n * BP_MLP_HID;
     GemmArgs g = {};
-    g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID;   // K = 256: one chunk
+    g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID; g.ks = 1;   // K = 256: one chunk
     // hidden layers: A = h (row-major [n][256]), B(k, n') = W[n'][k]
-    g.N = BP_MLP_HID; g.A = H1; g.a_m = BP_MLP_HID; g.a_k = 1; g.B = wb + o.W2; g.b_k = 1; g.b_n = BP_MLP_HID;
+    g.N = BP_MLP_HID; g.A = nullptr; g.a_m = BP_MLP_HID; g.a_k = 1; g.B = wb + o.W2; g.b_k = 1; g.b_n = BP_MLP_HID;
     g.bias = w + o.b2; g.Z = Z2; g.ldz = BP_MLP_HID; g.H = H2; g.ldh = BP_MLP_HID;
-    int r = launch_gemm(EPI_BIAS_SILU, g, 1, s);
+    g.x1 = x; g.W1 = w + o.W1; g.b1 = w + o.b1; g.Z1 = Z1; g.H1 = H1; g.xb = xb;
+    g.ndata = ndata; g.seed = seed; g.step = step;
+    int64_t tiles = 0;
+    int r = check_gemm(EPI_BIAS_SILU, g, 1, &tiles);
     if (r) return r;
-    g.A = H2; g.B = wb + o.W3; g.bias = w + o.b3; g.Z = Z3; g.H = H3;
+    if (!x || (ndata > 0 && !xb)) return BP_E_ARG;
+    hipLaunchKernelGGL((k_gemm_bf16<EPI_BIAS_SILU, true, true, true>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    g = GemmArgs{};
+    g.M = n; g.K = BP_MLP_HID; g.kchunk = BP_MLP_HID; g.ks = 1;
+    g.N = BP_MLP_HID; g.A = H2; g.a_m = BP_MLP_HID; g.a_k = 1; g.B = wb + o.W3; g.b_k = 1; g.b_n = BP_MLP_HID;
+    g.bias = w + o.b3; g.Z = Z3; g.ldz = BP_MLP_HID; g.H = H3; g.ldh = BP_MLP_HID;
     r = launch_gemm(EPI_BIAS_SILU, g, 1, s);
     if (r) return r;
     g.N = BP_MLP_OUT; g.A = H3; g.B = wb + o.W4; g.bias = w + o.b4; g.F = y; g.ldf = BP_MLP_OUT; g.Z = nullptr;
@@ -441,13 +502,8 @@ static int forward_gemms(const float *w, const uint16_t *wb, int64_t n, void *ac
 int mlp_forward_train(const float *w, const uint16_t *wb, int64_t n, int64_t ndata, uint64_t seed, int64_t step,
                       const float *xdata, float *xb, void *act, float *y, hipStream_t s) {
     if (n <= 0 || ndata <= 0 || !w || !wb || !xdata || !xb || !act || !y) return BP_E_ARG;
-    if (((uintptr_t)xdata | (uintptr_t)xb | (uintptr_t)act) & 15) return BP_E_ARG;
-    const Off o = offsets();
-    float *Z1 = (float *)act;
-    uint16_t *H1 = (uint16_t *)(Z1 + 3 * n * BP_MLP_HID);
-    hipLaunchKernelGGL(k_layer1_train, dim3((unsigned)((n * (BP_MLP_HID / 4) + 255) / 256)), dim3(256), 0, s, n,
-                       ndata, seed, step, w + o.W1, w + o.b1, xdata, xb, Z1, H1);
-    return forward_gemms(w, wb, n, act, y, s);
+    if (((uintptr_t)xdata | (uintptr_t)xb | (uintptr_t)act | (uintptr_t)y | (uintptr_t)wb) & 15) return BP_E_ARG;
+    return forward(w, wb, n, xdata, ndata, seed, step, xb, act, y, s);
 }
 }  // namespace bp
 
@@ -457,13 +513,8 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
     if (n == 0) return BP_OK;
     if (((uintptr_t)y | (uintptr_t)act | (uintptr_t)wb) & 15) return BP_E_ARG;   // 16-byte vector access
     hipStream_t s = (hipStream_t)stream;
-    Off o = offsets();
-    float *Z1 = (float *)act;
-    uint16_t *H1 = (uint16_t *)(Z1 + 3 * n * BP_MLP_HID);
     prof_begin(BP_PROF_MLP_FWD, s);
-    hipLaunchKernelGGL(k_layer1, dim3((unsigned)((n * (BP_MLP_HID / 4) + 255) / 256)), dim3(256), 0, s, n, w + o.W1,
-                       w + o.b1, x, Z1, H1);
-    const int r = forward_gemms(w, wb, n, act, y, s);
+    const int r = forward(w, wb, n, x, 0, 0, 0, nullptr, act, y, s);
     prof_end(BP_PROF_MLP_FWD, s);
     return r;
 }
@@ -751,7 +802,7 @@ int mlp_backward_g4(const uint16_t *wb, int64_t n, const float *x, const void *a
     // dW = G^T h over the batch in ks split-K slices: A(m = o, k = s) = G[s][o], B(k = s, n = i) = h[s][i]
     auto wgrad = [&](const uint16_t *Gt, int64_t ldg, int64_t rows, const uint16_t *Hin, const float *dst) {
         GemmArgs g = {};
-        g.M = rows; g.N = BP_MLP_HID; g.K = n; g.kchunk = kchunk;
+        g.M = rows; g.N = BP_MLP_HID; g.K = n; g.kchunk = kchunk; g.ks = ks;
         g.A = Gt; g.a_m = 1; g.a_k = ldg;
         g.B = Hin; g.b_k = BP_MLP_HID; g.b_n = 1;
         g.F = (float *)dst;
@@ -761,7 +812,7 @@ int mlp_backward_g4(const uint16_t *wb, int64_t n, const float *x, const void *a
     auto dgrad = [&](const uint16_t *Gin, int64_t kdim, const uint16_t *W, const float *Z, uint16_t *Gout,
                      const float *cs, const float *xs) {
         GemmArgs g = {};
-        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = ((kdim + kBK - 1) / kBK) * kBK;
+        g.M = n; g.N = BP_MLP_HID; g.K = kdim; g.kchunk = ((kdim + kBK - 1) / kBK) * kBK; g.ks = 1;
         g.A = Gin; g.a_m = kdim; g.a_k = 1;
         g.B = W; g.b_k = BP_MLP_HID; g.b_n = 1;
         g.Z = (float *)Z; g.ldz = BP_MLP_HID; g.H = Gout; g.ldh = BP_MLP_HID;
