@@ -76,13 +76,21 @@ struct GemmArgs {
 // columns of one row and the epilogue moves them as one vector.  Every operand dimension that is
 // loaded 16 bytes at a time is a multiple of 8 (checked at launch); k beyond K and rows beyond M are
 // zero-filled.
-constexpr int kGM = 64, kGN = 64, kGKC = 256, kGLd = kGKC + 8;   // +8 bf16 of padding per LDS row
-constexpr int kBK = 32;                                           // k per MFMA step
+constexpr int kGM = 64, kGN = 64, kGKC = 256, kGLd = kGKC;   // LDS row: 256 bf16 = 32 groups of 16 bytes
+constexpr int kBK = 32;                                       // k per MFMA step
 
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+// The 16-byte group g of LDS row r is stored at group g ^ swz(r).  LDS serves a 16-byte access 16
+// lanes at a time over 64 four-byte banks, so the 16 lanes must touch 16 different groups mod 16; with
+// this swizzle they do for every pattern used here: 16 consecutive rows at one group (the MFMA
+// fragments), one row at 16 consecutive groups (row-major staging), and the rows 8a + j (a < 8) at
+// two neighbouring groups (transposed staging).
+__device__ inline int swz(int r) { return (r ^ (r >> 3)) & 15; }
+__device__ inline uint16_t *lds_at(uint16_t (*s)[kGLd], int r, int k) { return &s[r][((k >> 3) ^ swz(r)) << 3]; }
+
 // Rows r0 .. r0+63 of an operand contiguous in k (element (r, k) at src[r * ld + k]), k in
-// [k0, k0 + 256) clipped to kend, into dst[r][k - k0].
+// [k0, k0 + 256) clipped to kend, into row r, column k - k0 of dst (swizzled, lds_at).
 __device__ inline void stage_kmajor(const uint16_t *__restrict__ src, int64_t ld, int64_t r0, int64_t rend,
                                     int64_t k0, int64_t kend, uint16_t (*dst)[kGLd], int t) {
     u16x8 v[8];
@@ -96,7 +104,7 @@ __device__ inline void stage_kmajor(const uint16_t *__restrict__ src, int64_t ld
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int e = t + 256 * i, r = e >> 5, kq = (e & 31) * 8;
-        *(u16x8 *)&dst[r][kq] = v[i];
+        *(u16x8 *)lds_at(dst, r, kq) = v[i];
     }
 }
 
@@ -118,7 +126,7 @@ __device__ inline void stage_rmajor(const uint16_t *__restrict__ src, int64_t ld
         u16x8 o;
 #pragma unroll
         for (int i = 0; i < 8; ++i) o[i] = v[i][j];
-        *(u16x8 *)&dst[rq + j][kq] = o;
+        *(u16x8 *)lds_at(dst, rq + j, kq) = o;
     }
 }
 
@@ -191,7 +199,7 @@ __device__ inline void stage_layer1(const GemmArgs &g, int64_t r0, bool store, u
                     for (int q = 0; q < BP_MLP_NIN; ++q) g.xb[m * BP_MLP_IN + q] = xr[i][q];
             }
         }
-        *(u16x8 *)&dst[r][kq] = h;
+        *(u16x8 *)lds_at(dst, r, kq) = h;
     }
 }
 
@@ -218,6 +226,26 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // the epilogue's own operands (z for EPI_DSILU, the bias otherwise, and the inputs of the
+    // layer-1 sums) are loaded before the main loop, so that their latency overlaps the staging
+    fx4 pre[2][2];
+    float xr[2][BP_MLP_NIN];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+        const int64_t m = m0 + 32 * wm + 16 * bi + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < BP_MLP_NIN; ++q)
+            xr[bi][q] = (EPI == EPI_DSILU && g.xs && m < g.M) ? g.xs[m * BP_MLP_IN + q] : 0.0f;
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int64_t n = n0 + 32 * wn + 16 * bj + 4 * (lane >> 4);
+            const bool ok = m < g.M && n < g.N;
+            pre[bi][bj] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (EPI == EPI_DSILU && ok) pre[bi][bj] = *(const fx4 *)(g.Z + m * g.ldz + n);
+            if ((EPI == EPI_BIAS_SILU || EPI == EPI_BIAS) && ok)
+                pre[bi][bj] = fx4{g.bias[n], g.bias[n + 1], g.bias[n + 2], g.bias[n + 3]};
+        }
+    }
     for (int64_t k0 = kb; k0 < ke; k0 += kGKC) {
         const int64_t kend = min(ke, k0 + kGKC);
         if (kL1) stage_layer1(g, m0, by == 0, As, t);
@@ -227,14 +255,16 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
         else stage_rmajor(g.B, g.b_k, n0, g.N, k0, kend, Bs, t);
         __syncthreads();
         const int steps = (int)((kend - k0 + kBK - 1) / kBK);
-        const uint16_t *pa = &As[32 * wm + (lane & 15)][8 * (lane >> 4)];
-        const uint16_t *pb = &Bs[32 * wn + (lane & 15)][8 * (lane >> 4)];
+        // fragment rows of this lane and their swizzles
+        const int ra0 = 32 * wm + (lane & 15), rb0 = 32 * wn + (lane & 15);
+        const int sa[2] = {swz(ra0), swz(ra0 + 16)}, sb[2] = {swz(rb0), swz(rb0 + 16)};
         for (int ks = 0; ks < steps; ++ks) {
+            const int grp = (lane >> 4) + 4 * ks;   // 16-byte group of k 32 ks + 8 (lane / 16)
             bf16x8 af[2], bfr[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                af[i] = *(const bf16x8 *)(pa + 16 * i * kGLd + kBK * ks);
-                bfr[i] = *(const bf16x8 *)(pb + 16 * i * kGLd + kBK * ks);
+                af[i] = *(const bf16x8 *)&As[ra0 + 16 * i][(grp ^ sa[i]) << 3];
+                bfr[i] = *(const bf16x8 *)&Bs[rb0 + 16 * i][(grp ^ sb[i]) << 3];
             }
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
@@ -250,10 +280,6 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
     for (int bi = 0; bi < 2; ++bi) {
         const int64_t m = m0 + 32 * wm + 16 * bi + (lane & 15);
         const bool mok = m < g.M;
-        float xr[BP_MLP_NIN] = {};
-        if (EPI == EPI_DSILU && g.xs && mok)
-#pragma unroll
-            for (int q = 0; q < BP_MLP_NIN; ++q) xr[q] = g.xs[m * BP_MLP_IN + q];
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             const int64_t n = n0 + 32 * wn + 16 * bj + 4 * (lane >> 4);
@@ -261,16 +287,16 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
             const fx4 v = acc[bi][bj];
             if (EPI == EPI_BIAS_SILU) {
                 if (!ok) continue;
-                const fx4 z = v + fx4{g.bias[n], g.bias[n + 1], g.bias[n + 2], g.bias[n + 3]};
+                const fx4 z = v + pre[bi][bj];
                 if (g.Z) *(fx4 *)(g.Z + m * g.ldz + n) = z;
                 st_bf4(g.H + m * g.ldh + n, silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3]));
             } else if (EPI == EPI_BIAS) {
                 if (!ok) continue;
-                *(fx4 *)(g.F + m * g.ldf + n) = v + fx4{g.bias[n], g.bias[n + 1], g.bias[n + 2], g.bias[n + 3]};
+                *(fx4 *)(g.F + m * g.ldf + n) = v + pre[bi][bj];
             } else if (EPI == EPI_DSILU) {
                 fx4 d = fx4{0.0f, 0.0f, 0.0f, 0.0f};
                 if (ok) {
-                    const fx4 z = *(const fx4 *)(g.Z + m * g.ldz + n);
+                    const fx4 z = pre[bi][bj];
                     d = fx4{v[0] * dsilu(z[0]), v[1] * dsilu(z[1]), v[2] * dsilu(z[2]), v[3] * dsilu(z[3])};
                     if (g.F) *(fx4 *)(g.F + m * g.ldf + n) = d;
                     if (g.H) st_bf4(g.H + m * g.ldh + n, d[0], d[1], d[2], d[3]);
@@ -282,7 +308,7 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
 #pragma unroll
                     for (int q = 0; q < BP_MLP_NIN; ++q) {
                         const float prev = bi ? csum[bj][j][1 + q] : 0.0f;
-                        csum[bj][j][1 + q] = prev + d[j] * xr[q];
+                        csum[bj][j][1 + q] = prev + d[j] * xr[bi][q];
                     }
                 }
             } else {
