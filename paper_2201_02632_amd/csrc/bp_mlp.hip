@@ -7,11 +7,11 @@
 //   z3 = W3 h2 + b3, h3 = bf16(silu(z3))
 //   y  = W4 h3 + b4                      FP32 output
 // The hidden-layer products run on gfx950's v_mfma_f32_16x16x32_bf16 (a 16x16
-// block over 32 k per instruction): a workgroup computes a 128x64 output tile
-// with four wavefronts (2x4 blocks of 16x16 each), staging 32-wide k slices of
-// both operands in LDS per K step.  Weight
-// gradients reduce over the batch with split-K partial tiles summed in a
-// fixed order, so training is deterministic.
+// block over 32 k per instruction): a workgroup computes a 64x64 output tile
+// with four wavefronts (2x2 blocks of 16x16 each), staging the tile's whole K
+// range in LDS at once.  Weight gradients reduce over the batch with split-K
+// partial tiles, bias gradients with per-64-row column partials, all summed in
+// a fixed order, so training is deterministic.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -226,8 +226,8 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
-    // the epilogue's own operands (z for EPI_DSILU, the bias otherwise, and the inputs of the
-    // layer-1 sums) are loaded before the main loop, so that their latency overlaps the staging
+    // the epilogue's own operands (z for EPI_DSILU and the inputs of the layer-1 sums) are loaded
+    // before the main loop, so that their latency overlaps the staging
     fx4 pre[2][2];
     float xr[2][BP_MLP_NIN];
 #pragma unroll
@@ -244,6 +244,8 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
             if (EPI == EPI_DSILU && ok) pre[bi][bj] = *(const fx4 *)(g.Z + m * g.ldz + n);
             if ((EPI == EPI_BIAS_SILU || EPI == EPI_BIAS) && ok)
                 pre[bi][bj] = fx4{g.bias[n], g.bias[n + 1], g.bias[n + 2], g.bias[n + 3]};
+            // a bias is the accumulators' starting value (as in the fused inference kernel)
+            if (EPI == EPI_BIAS_SILU || EPI == EPI_BIAS) acc[bi][bj] = pre[bi][bj];
         }
     }
     for (int64_t k0 = kb; k0 < ke; k0 += kGKC) {
@@ -287,12 +289,12 @@ __device__ inline void gemm_tile(const GemmArgs &g, int64_t id, uint16_t (*As)[k
             const fx4 v = acc[bi][bj];
             if (EPI == EPI_BIAS_SILU) {
                 if (!ok) continue;
-                const fx4 z = v + pre[bi][bj];
+                const fx4 z = v;
                 if (g.Z) *(fx4 *)(g.Z + m * g.ldz + n) = z;
                 st_bf4(g.H + m * g.ldh + n, silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3]));
             } else if (EPI == EPI_BIAS) {
                 if (!ok) continue;
-                *(fx4 *)(g.F + m * g.ldf + n) = v + pre[bi][bj];
+                *(fx4 *)(g.F + m * g.ldf + n) = v;
             } else if (EPI == EPI_DSILU) {
                 fx4 d = fx4{0.0f, 0.0f, 0.0f, 0.0f};
                 if (ok) {
@@ -421,35 +423,24 @@ static int launch_wgrad_dgrad(const GemmArgs &gw, int ksplit, const GemmArgs &gd
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
-// Batch reductions in two fixed-order stages.  Stage 1: block (bx, y) covers 64 columns and the rows
-// [64 y, 64 y + 64); its four waves take every fourth row and are combined in wave order, giving
-// part[y][j][c] = sum_m a[m][c] * (j == 0 ? 1 : x[m][j - 1]).  Stage 2 sums the chunks in order.
+// Column sums of the output gradient dy (the b4 gradient, for bp_mlp_backward) in fixed order:
+// block (bx, y) covers 64 columns and the rows [64 y, 64 y + 64); its four waves take every fourth
+// row and are combined in wave order, giving the chunk partial part[y][c], which Adam and
+// k_reduce_grad sum in chunk order.
 constexpr int kRowChunk = 64;
-template <int kSums>
 __global__ __launch_bounds__(256) void k_colsum_part(int64_t n, int cols, const float *__restrict__ a,
-                                                     const float *__restrict__ x, float *__restrict__ part) {
-    __shared__ float red[4][kSums][64];
+                                                     float *__restrict__ part) {
+    __shared__ float red[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int c = blockIdx.x * 64 + lane;
     const int64_t m0 = (int64_t)blockIdx.y * kRowChunk, m1 = min(n, m0 + kRowChunk);
-    float acc[kSums];
-#pragma unroll
-    for (int j = 0; j < kSums; ++j) acc[j] = 0.0f;
+    float acc = 0.0f;
     if (c < cols)
-        for (int64_t m = m0 + w; m < m1; m += 4) {
-            float v = a[m * cols + c];
-            acc[0] += v;
-#pragma unroll
-            for (int j = 1; j < kSums; ++j) acc[j] += v * x[m * BP_MLP_IN + j - 1];
-        }
-#pragma unroll
-    for (int j = 0; j < kSums; ++j) red[w][j][lane] = acc[j];
+        for (int64_t m = m0 + w; m < m1; m += 4) acc += a[m * cols + c];
+    red[w][lane] = acc;
     __syncthreads();
     if (w == 0 && c < cols)
-#pragma unroll
-        for (int j = 0; j < kSums; ++j)
-            part[((int64_t)blockIdx.y * kSums + j) * cols + c] =
-                ((red[0][j][lane] + red[1][j][lane]) + red[2][j][lane]) + red[3][j][lane];
+        part[(int64_t)blockIdx.y * cols + c] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 __global__ void k_to_bf16(int64_t n, const float *__restrict__ a, uint16_t *__restrict__ b) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,135 +537,144 @@ extern "C" int bp_mlp_forward(const float *w, const uint16_t *wb, int64_t n, con
 }
 
 // ------------------------------------------------------------ fused inference --
-// All four layers for a block of 64 rows in one kernel; activations never leave the CU.
-// Each layer is computed transposed, out^T = W h^T: the weights are the MFMA A operand and the
-// activations the B operand.  A lane's accumulator holds outputs (4 (l/16) + j, l % 16) of a 16x16
-// block, i.e. four consecutive features of one row, which the epilogue writes to the wavefront's
-// own LDS activation rows (BF16); the next layer reads them back as B fragments of eight
-// consecutive features.  The weights stream through LDS in 32-column k slices, double-buffered and
-// shared by the four wavefronts.  The k order of every sum is that of bp_mlp_forward.
-constexpr int kFRB = 2;                 // 16-row blocks per wavefront: each weight fragment feeds kFRB MFMAs
-constexpr int kFR = 16 * kFRB;          // rows per wavefront
-constexpr int kFBM = 4 * kFR;           // rows per workgroup
-constexpr int kFK = 32;                 // k per slice (one 16x16x32 MFMA)
-constexpr int kFKB = BP_MLP_HID / kFK;  // k slices of a hidden-layer input
-constexpr int kFOB = BP_MLP_HID / 16;   // 16-feature output blocks of a hidden layer
-constexpr int kFLd = kFK + 8;           // LDS row stride of a weight k slice in bf16 (32 + 8)
-constexpr int kFALd = BP_MLP_HID + 8;   // LDS row stride of the activations in bf16 (256 + 8)
+// All four layers for a block of 128 rows in one kernel; activations never leave the CU (one
+// 128 x 256 BF16 buffer in LDS, rewritten in place by each layer).  Each layer is computed
+// transposed, out^T = W h^T: the weights are the MFMA A operand, read by each wavefront straight from
+// memory (they stay in L2), and the activations are the B operand, read from LDS.  Each of the
+// eight wavefronts owns two 16-feature output blocks of a hidden layer (2w, 2w + 1; w and w + 8 of
+// the 9 output blocks) for all 128 rows, so no weight fragment is fetched twice within a workgroup;
+// the fragments run kIPf k slices ahead of the MFMAs.  A lane's accumulator holds four consecutive
+// features of one row, starting from the bias, and the epilogue writes them back as BF16 once every
+// wavefront has read the layer's input.  The 66 KB of LDS and at most 128 registers per lane let
+// two workgroups (sixteen wavefronts) share a CU, so that one wavefront's SiLU work overlaps
+// another's MFMAs.  The k order of every sum is that of bp_mlp_forward, so the outputs are the same
+// bit for bit.
+constexpr int kIR = 128;                 // rows per workgroup
+constexpr int kIRB = kIR / 16;           // 16-row blocks
+constexpr int kIW = 8;                   // wavefronts per workgroup
+constexpr int kIOB = BP_MLP_HID / 16 / kIW;   // output blocks per wavefront in a hidden layer (2)
+constexpr int kIK = 32;                  // k per MFMA
+constexpr int kIKB = BP_MLP_HID / kIK;   // k slices of a layer
+constexpr int kIPf = 2;                  // k slices of weight fragments in flight
+constexpr int kIALd = BP_MLP_HID + 8;    // LDS row stride of the activations (bf16)
+constexpr int kIOutB = BP_MLP_OUT / 16;  // output blocks of the last layer
+static_assert(kIKB % kIPf == 0 && kIOutB <= 2 * kIW, "prefetch ring and output-block assignment");
 
-// One layer: acc[rb][ob] = sum_k W[16 ob + .][k] h[16 rb + row][k] over the wavefront's rows (held in act),
-// for the first NOB output blocks.
+// acc[rb][j] += sum_k W[16 ob_j + .][k] h[16 rb + .][k] for the wavefront's blocks ob_j = ob0 + ostride j,
+// j < NOB; W is [.][256] BF16 row-major.  (MFMAs ignore the execution mask, so a block count below
+// kIOB is a separate instance rather than a masked one.)
 template <int NOB>
-__device__ inline void fused_layer(const uint16_t *__restrict__ W, const uint16_t *__restrict__ act,
-                                   fx4 (&acc)[kFRB][kFOB], uint16_t *__restrict__ wsl, int t, int lane) {
+__device__ inline void infer_layer(const uint16_t *__restrict__ W, int ob0, int ostride,
+                                   const uint16_t *__restrict__ acts, fx4 (&acc)[kIRB][kIOB], int lane) {
+    const uint16_t *wbase = W + (int64_t)__builtin_amdgcn_readfirstlane(16 * ob0) * BP_MLP_HID;
+    const int jstride = 16 * ostride * BP_MLP_HID, loff = (lane & 15) * BP_MLP_HID + 8 * (lane >> 4);
+    bf16x8 pf[kIPf][NOB];
 #pragma unroll
-    for (int rb = 0; rb < kFRB; ++rb)
+    for (int p = 0; p < kIPf; ++p)
 #pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) acc[rb][ob] = fx4{0.0f, 0.0f, 0.0f, 0.0f};
-    constexpr int kRows = NOB * 16;                  // weight rows (output features)
-    constexpr int kBuf = BP_MLP_HID * kFLd;          // one k slice, room for 256 rows
-    // thread t < kRows moves row t of a k slice: 32 bf16 = four 16-byte loads
-    uint4 st0 = {}, st1 = {}, st2 = {}, st3 = {};   // (separate values: an array here is placed in LDS)
-    auto fetch = [&](int kb) {
-        if (t < kRows) {
-            const uint4 *src = (const uint4 *)(W + (int64_t)t * BP_MLP_HID + kb * kFK);
-            st0 = src[0]; st1 = src[1]; st2 = src[2]; st3 = src[3];
+        for (int j = 0; j < NOB; ++j) pf[p][j] = *(const bf16x8 *)(wbase + j * jstride + loff + kIK * p);
+    const uint16_t *bsrc = acts + (lane & 15) * kIALd + 8 * (lane >> 4);
+#pragma unroll
+    for (int kb = 0; kb < kIKB; ++kb) {
+        bf16x8 a[NOB];
+#pragma unroll
+        for (int j = 0; j < NOB; ++j) a[j] = pf[kb % kIPf][j];
+        if (kb + kIPf < kIKB)
+#pragma unroll
+            for (int j = 0; j < NOB; ++j)
+                pf[kb % kIPf][j] = *(const bf16x8 *)(wbase + j * jstride + loff + kIK * (kb + kIPf));
+#pragma unroll
+        for (int rb = 0; rb < kIRB; ++rb) {
+            const bf16x8 b = *(const bf16x8 *)(bsrc + 16 * rb * kIALd + kIK * kb);
+#pragma unroll
+            for (int j = 0; j < NOB; ++j) acc[rb][j] = mfma32(a[j], b, acc[rb][j]);
         }
-    };
-    auto put = [&](int buf) {
-        if (t < kRows) {
-            uint4 *dst = (uint4 *)(wsl + buf * kBuf + t * kFLd);
-            dst[0] = st0; dst[1] = st1; dst[2] = st2; dst[3] = st3;
-        }
-    };
-    fetch(0);
-    put(0);
-    __syncthreads();
-    const uint16_t *bsrc = act + (lane & 15) * kFALd + 8 * (lane >> 4);
-    for (int kb = 0; kb < kFKB; ++kb) {
-        if (kb + 1 < kFKB) fetch(kb + 1);
-        bf16x8 bfr[kFRB];
-#pragma unroll
-        for (int rb = 0; rb < kFRB; ++rb) bfr[rb] = *(const bf16x8 *)(bsrc + 16 * rb * kFALd + kFK * kb);
-        const uint16_t *sl = wsl + (kb & 1) * kBuf + (lane & 15) * kFLd + 8 * (lane >> 4);
-#pragma unroll
-        for (int ob = 0; ob < NOB; ++ob) {
-            const bf16x8 a = *(const bf16x8 *)(sl + ob * 16 * kFLd);
-#pragma unroll
-            for (int rb = 0; rb < kFRB; ++rb) acc[rb][ob] = mfma32(a, bfr[rb], acc[rb][ob]);
-        }
-        if (kb + 1 < kFKB) put((kb + 1) & 1);
-        __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(256) k_mlp_infer(int64_t n, const float *__restrict__ w,
-                                                   const uint16_t *__restrict__ wb, const float *__restrict__ x,
-                                                   float *__restrict__ y, int64_t oW1, int64_t ob1, int64_t oW2,
-                                                   int64_t ob2, int64_t oW3, int64_t ob3, int64_t oW4, int64_t ob4) {
-    __shared__ __attribute__((aligned(16))) uint16_t wsl[2 * BP_MLP_HID * kFLd];
-    __shared__ __attribute__((aligned(16))) uint16_t acts[4 * kFR * kFALd];
+__global__ void __launch_bounds__(64 * kIW) __attribute__((amdgpu_waves_per_eu(4))) k_mlp_infer(int64_t n, const float *__restrict__ w,
+                                                           const uint16_t *__restrict__ wb,
+                                                           const float *__restrict__ x, float *__restrict__ y,
+                                                           int64_t oW1, int64_t ob1, int64_t oW2, int64_t ob2,
+                                                           int64_t oW3, int64_t ob3, int64_t oW4, int64_t ob4) {
+    __shared__ __attribute__((aligned(16))) uint16_t acts[kIR * kIALd];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    uint16_t *act = acts + wv * kFR * kFALd;
-    const int64_t row0 = (int64_t)blockIdx.x * kFBM + wv * kFR + (lane & 15);   // row of block rb: row0 + 16 rb
-    // this lane's slot in the activation rows of block rb: row 16 rb + l%16, features 4 (l/16) + 16 kb .. + 3
-    uint16_t *aslot = act + (lane & 15) * kFALd + 4 * (lane >> 4);
-    // layer 1 (FP32)
+    const int64_t row0 = (int64_t)blockIdx.x * kIR;
+    // layer 1 (FP32): thread t makes features 4 (t % 64) .. + 3 of rows t / 64 + kIW i
     {
-        const float *W1 = w + oW1, *b1 = w + ob1;
+        const int fq = 4 * lane;
+        float bv[4], wq[4][BP_MLP_NIN];
 #pragma unroll
-        for (int rb = 0; rb < kFRB; ++rb) {
-            const int64_t row = row0 + 16 * rb;
-            float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
-            if (row < n) { x0 = x[row * BP_MLP_IN]; x1 = x[row * BP_MLP_IN + 1]; x2 = x[row * BP_MLP_IN + 2]; }
-            for (int kb = 0; kb < kFOB; ++kb) {
-                float h[4];
+        for (int j = 0; j < 4; ++j) {
+            bv[j] = w[ob1 + fq + j];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int o = 16 * kb + 4 * (lane >> 4) + j;
-                    float z = b1[o];
-                    z += W1[o * BP_MLP_IN] * x0;
-                    z += W1[o * BP_MLP_IN + 1] * x1;
-                    z += W1[o * BP_MLP_IN + 2] * x2;
-                    h[j] = silu(z);
-                }
-                *(sx4 *)(aslot + 16 * rb * kFALd + 16 * kb) = pack_bf4(h[0], h[1], h[2], h[3]);
-            }
+            for (int q = 0; q < BP_MLP_NIN; ++q) wq[j][q] = w[oW1 + (fq + j) * BP_MLP_IN + q];
+        }
+        // the wavefront's kIR / kIW rows of inputs in one load: lane 3 i + q holds x[row i][q]
+        static_assert(BP_MLP_NIN * (kIR / kIW) <= 64, "one input per lane");
+        float xl = 0.0f;
+        {
+            const int i = lane / BP_MLP_NIN, q = lane - BP_MLP_NIN * i;
+            const int64_t row = row0 + wv + kIW * i;
+            if (i < kIR / kIW && row < n) xl = x[row * BP_MLP_IN + q];
+        }
+#pragma unroll
+        for (int i = 0; i < kIR / kIW; ++i) {
+            const int r = wv + kIW * i;   // one row per wavefront
+            float xr[BP_MLP_NIN];
+#pragma unroll
+            for (int q = 0; q < BP_MLP_NIN; ++q)
+                xr[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xl), BP_MLP_NIN * i + q));
+            float h[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) h[j] = silu(layer1_z(bv[j], wq[j], xr));
+            *(sx4 *)(acts + r * kIALd + fq) = pack_bf4(h[0], h[1], h[2], h[3]);
         }
     }
+    __syncthreads();
     // hidden layers 2 and 3
-    fx4 acc[kFRB][kFOB];
+    const int frow = lane & 15, fcol = 4 * (lane >> 4);   // a lane's row in a 16-row block, feature in a 16-block
+    fx4 acc[kIRB][kIOB];
     for (int layer = 0; layer < 2; ++layer) {
-        const uint16_t *W = wb + (layer == 0 ? oW2 : oW3);
         const float *bias = w + (layer == 0 ? ob2 : ob3);
-        fused_layer<kFOB>(W, act, acc, wsl, t, lane);
 #pragma unroll
-        for (int rb = 0; rb < kFRB; ++rb)
+        for (int j = 0; j < kIOB; ++j) {
+            const int f = 16 * (kIOB * wv + j) + fcol;
+            const fx4 bb = fx4{bias[f], bias[f + 1], bias[f + 2], bias[f + 3]};
 #pragma unroll
-            for (int ob = 0; ob < kFOB; ++ob) {
-                const int o = 16 * ob + 4 * (lane >> 4);
-                const fx4 v = acc[rb][ob];
-                *(sx4 *)(aslot + 16 * rb * kFALd + 16 * ob) =
-                    pack_bf4(silu(v[0] + bias[o]), silu(v[1] + bias[o + 1]), silu(v[2] + bias[o + 2]),
-                             silu(v[3] + bias[o + 3]));
+            for (int rb = 0; rb < kIRB; ++rb) acc[rb][j] = bb;
+        }
+        infer_layer<kIOB>(wb + (layer == 0 ? oW2 : oW3), kIOB * wv, 1, acts, acc, lane);
+        __syncthreads();   // every wavefront has read the layer's input
+#pragma unroll
+        for (int rb = 0; rb < kIRB; ++rb)
+#pragma unroll
+            for (int j = 0; j < kIOB; ++j) {
+                const fx4 z = acc[rb][j];
+                *(sx4 *)(acts + (16 * rb + frow) * kIALd + 16 * (kIOB * wv + j) + fcol) =
+                    pack_bf4(silu(z[0]), silu(z[1]), silu(z[2]), silu(z[3]));
             }
+        __syncthreads();
     }
-    // output layer (144 features = 9 blocks)
-    constexpr int kOB = BP_MLP_OUT / 16;
-    fx4 (&out)[kFRB][kFOB] = acc;
-    fused_layer<kOB>(wb + oW4, act, out, wsl, t, lane);
-    const float *b4 = w + ob4;
+    // output layer: blocks wv and wv + kIW (< 9)
+    const int nob = __builtin_amdgcn_readfirstlane((wv + kIW < kIOutB) ? 2 : 1);
 #pragma unroll
-    for (int rb = 0; rb < kFRB; ++rb) {
-        const int64_t row = row0 + 16 * rb;
+    for (int j = 0; j < kIOB; ++j) {
+        const int f = 16 * (wv + kIW * j) + fcol;
+        const fx4 bb = j < nob ? fx4{w[ob4 + f], w[ob4 + f + 1], w[ob4 + f + 2], w[ob4 + f + 3]}
+                               : fx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int rb = 0; rb < kIRB; ++rb) acc[rb][j] = bb;
+    }
+    if (nob == 2) infer_layer<2>(wb + oW4, wv, kIW, acts, acc, lane);
+    else infer_layer<1>(wb + oW4, wv, kIW, acts, acc, lane);
+#pragma unroll
+    for (int rb = 0; rb < kIRB; ++rb) {
+        const int64_t row = row0 + 16 * rb + frow;
         if (row >= n) continue;
 #pragma unroll
-        for (int ob = 0; ob < kOB; ++ob) {
-            const int o = 16 * ob + 4 * (lane >> 4);
-            const fx4 v = out[rb][ob];
-            *(float4 *)(y + row * BP_MLP_OUT + o) = float4{v[0] + b4[o], v[1] + b4[o + 1], v[2] + b4[o + 2],
-                                                           v[3] + b4[o + 3]};
-        }
+        for (int j = 0; j < kIOB; ++j)
+            if (j < nob) *(fx4 *)(y + row * BP_MLP_OUT + 16 * (wv + kIW * j) + fcol) = acc[rb][j];
     }
 }
 
@@ -682,12 +682,12 @@ extern "C" int bp_mlp_infer(const float *w, const uint16_t *wb, int64_t n, const
     if (n < 0 || !w || !wb || !x || !y) return BP_E_ARG;
     if (n == 0) return BP_OK;
     if ((((uintptr_t)y) & 15) || (((uintptr_t)wb) & 15)) return BP_E_ARG;   // 16-byte vector access
-    const int64_t blocks = (n + kFBM - 1) / kFBM;
+    const int64_t blocks = (n + kIR - 1) / kIR;
     if (blocks > 0x7fffffffLL) return BP_E_OVERFLOW;
     hipStream_t s = (hipStream_t)stream;
     Off o = offsets();
     prof_begin(BP_PROF_MLP_FWD, s);
-    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(256), 0, s, n, w, wb, x, y, o.W1, o.b1, o.W2, o.b2,
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)blocks), dim3(64 * kIW), 0, s, n, w, wb, x, y, o.W1, o.b1, o.W2, o.b2,
                        o.W3, o.b3, o.W4, o.b4);
     prof_end(BP_PROF_MLP_FWD, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
@@ -865,8 +865,8 @@ int mlp_backward_parts(const float *w, const uint16_t *wb, int64_t n, const floa
     if (r) return r;
     hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * BP_MLP_OUT + 255) / 256)), dim3(256), 0, s, n * BP_MLP_OUT, dy,
                        G4);
-    hipLaunchKernelGGL(k_colsum_part<1>, dim3((BP_MLP_OUT + 63) / 64, P->nchunk), dim3(256), 0, s, n, BP_MLP_OUT, dy,
-                       (const float *)nullptr, (float *)P->b4);
+    hipLaunchKernelGGL(k_colsum_part, dim3((BP_MLP_OUT + 63) / 64, P->nchunk), dim3(256), 0, s, n, BP_MLP_OUT, dy,
+                       (float *)P->b4);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     return mlp_backward_g4(wb, n, x, act, ws, ws_bytes, s);
 }
