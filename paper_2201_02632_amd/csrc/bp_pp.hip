@@ -256,13 +256,24 @@ k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint3
         const float uz = fminf(fmaxf((float)((mez - g.z0) / s - (double)gz), 0.0f), 1.0f);
         const float mface = fminf(fminf(fminf(ux, 1.0f - ux), fminf(uy, 1.0f - uy)), fminf(uz, 1.0f - uz));
         const float s2 = (float)(s * s);
-        // all particles of a contiguous sorted range
+        // all particles of a contiguous sorted range, four at a time: the positions of a group are
+        // loaded before its insertions, so their latencies overlap
+        auto dist2 = [&](uint32_t j) {
+            const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
+            return ddx * ddx + ddy * ddy + ddz * ddz;
+        };
         auto scan = [&](uint32_t a0, uint32_t b0) {
-            for (uint32_t j = a0; j < b0; ++j) {
-                if (j == (uint32_t)i) continue;
-                const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
-                T.push(ddx * ddx + ddy * ddy + ddz * ddz);
+            uint32_t j = a0;
+            for (; j + 4 <= b0; j += 4) {
+                float d2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) d2[u] = dist2(j + u);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j + u != (uint32_t)i) T.push(d2[u]);
             }
+            for (; j < b0; ++j)
+                if (j != (uint32_t)i) T.push(dist2(j));
         };
         T.init(k);
         for (int r = 0; r <= kShells && !done; ++r) {
