@@ -163,6 +163,14 @@ __global__ void k_pp_gather(int64_t n, Grid g, const double *__restrict__ pos, c
     if (i == n - 1 || (key[i + 1] >> 30) != c) cend[c] = (uint32_t)(i + 1);
 }
 
+// particles per coarse cell (cend - cstart, 0 for an empty cell), in place in cend: its exclusive
+// prefix sum is the lower-bound array lb[c] = first sorted particle of a cell >= c, so that any run of
+// consecutive cells c0 .. c1 - 1 holds exactly the particles [lb[c0], lb[c1])
+__global__ void k_pp_cell_counts(int64_t ncells, const uint32_t *__restrict__ cstart, uint32_t *__restrict__ cend) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells) cend[c] -= cstart[c];
+}
+
 // ------------------------------------------------------------ K6 kNN --
 constexpr int kKmax = 64;
 
@@ -199,6 +207,36 @@ __device__ inline uint32_t lower_bound64(const uint64_t *__restrict__ key, uint3
         if (key[mid] < target) lo = mid + 1; else hi = mid;
     }
     return lo;
+}
+
+// The lower bounds of t1 and of t2 in [lo, hi) at once (the Morton block [t1, t2) of a cell): both
+// searches are four-way, three probes per step, and step together, so each step's six loads are in
+// flight at the same time and the chain of dependent loads is log4 of the range long, not twice its
+// log2.
+__device__ inline void lower_bound_pair(const uint64_t *__restrict__ key, uint32_t lo, uint32_t hi, uint64_t t1,
+                                        uint64_t t2, uint32_t &r1, uint32_t &r2) {
+    uint32_t l1 = lo, h1 = hi, l2 = lo, h2 = hi;
+    while (h1 - l1 >= 4 || h2 - l2 >= 4) {
+        const uint32_t q1 = (h1 - l1) >> 2, q2 = (h2 - l2) >> 2;
+        const bool s1 = q1 > 0, s2 = q2 > 0;
+        uint64_t a1 = 0, b1 = 0, c1 = 0, a2 = 0, b2 = 0, c2 = 0;
+        if (s1) { a1 = key[l1 + q1]; b1 = key[l1 + 2 * q1]; c1 = key[l1 + 3 * q1]; }
+        if (s2) { a2 = key[l2 + q2]; b2 = key[l2 + 2 * q2]; c2 = key[l2 + 3 * q2]; }
+        if (s1) {
+            if (c1 < t1) l1 += 3 * q1 + 1;
+            else if (b1 < t1) { h1 = l1 + 3 * q1; l1 += 2 * q1 + 1; }
+            else if (a1 < t1) { h1 = l1 + 2 * q1; l1 += q1 + 1; }
+            else h1 = l1 + q1;
+        }
+        if (s2) {
+            if (c2 < t2) l2 += 3 * q2 + 1;
+            else if (b2 < t2) { h2 = l2 + 3 * q2; l2 += 2 * q2 + 1; }
+            else if (a2 < t2) { h2 = l2 + 2 * q2; l2 += q2 + 1; }
+            else h2 = l2 + q2;
+        }
+    }
+    r1 = lower_bound64(key, l1, h1, t1);
+    r2 = lower_bound64(key, l2, h2, t2);
 }
 
 // One lane per particle, in sorted (cell, Morton) order.  Level-l cells have size cell * 2^(l-10):
@@ -306,21 +344,19 @@ k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint3
                                                lz = (uint32_t)(az - (ccz << sh)) << lev;
                                 const uint64_t klo = (cc << 30) | morton3(lx, ly, lz);
                                 const uint64_t khi = klo + (1ull << (3 * lev));
-                                const uint32_t a1 = lower_bound64(key, a0, b0, klo);
-                                b0 = lower_bound64(key, a1, b0, khi);
-                                a0 = a1;
+                                lower_bound_pair(key, a0, b0, klo, khi, a0, b0);
                             }
                             scan(a0, b0);
                         } else {
+                            // a row of coarse cells along x is one run of the sorted particles
                             const int up = lev - 10;
-                            const int x1 = min((ax + 1) << up, g.nx), y1 = min((ay + 1) << up, g.ny),
+                            const int x0 = ax << up, x1 = min((ax + 1) << up, g.nx), y1 = min((ay + 1) << up, g.ny),
                                       z1 = min((az + 1) << up, g.nz);
                             for (int qz = az << up; qz < z1; ++qz)
-                                for (int qy = ay << up; qy < y1; ++qy)
-                                    for (int qx = ax << up; qx < x1; ++qx) {
-                                        const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + qx;
-                                        scan(cstart[cc], cend[cc]);
-                                    }
+                                for (int qy = ay << up; qy < y1; ++qy) {
+                                    const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + x0;
+                                    scan(cstart[cc], cstart[cc + (x1 - x0)]);
+                                }
                         }
                     }
                 }
@@ -405,16 +441,28 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
         const int rmax = (int)ceilf(h / sf);
         if (rmax > kNeffMaxShell) { ok = false; break; }
         float sw = 0.0f, ss = 0.0f, sc = 0.0f;
-        auto scan = [&](uint32_t a0, uint32_t b0) {
-            for (uint32_t j = a0; j < b0; ++j) {
-                const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
-                const float r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                if (r2 < h2) {
-                    float w, gs, cs;
-                    wsph_slope(sqrtf(r2) * ih, w, gs, cs);
-                    sw += w; ss += gs; sc += cs;
-                }
+        auto dist2 = [&](uint32_t j) {
+            const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
+            return ddx * ddx + ddy * ddy + ddz * ddz;
+        };
+        auto add = [&](float r2) {
+            if (r2 < h2) {
+                float w, gs, cs;
+                wsph_slope(sqrtf(r2) * ih, w, gs, cs);
+                sw += w; ss += gs; sc += cs;
             }
+        };
+        // candidates four at a time (positions loaded ahead of the sums, which stay in order)
+        auto scan = [&](uint32_t a0, uint32_t b0) {
+            uint32_t j = a0;
+            for (; j + 4 <= b0; j += 4) {
+                float r2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r2[u] = dist2(j + u);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) add(r2[u]);
+            }
+            for (; j < b0; ++j) add(dist2(j));
         };
         for (int dz = -rmax; dz <= rmax; ++dz) {
             const int az = gz + dz;
@@ -441,20 +489,19 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
                                            lz = (uint32_t)(az - (ccz << sh)) << lev;
                             const uint64_t klo = (cc << 30) | morton3(lx, ly, lz);
                             const uint64_t khi = klo + (1ull << (3 * lev));
-                            const uint32_t a1 = lower_bound64(key, a0, b0, klo);
-                            b0 = lower_bound64(key, a1, b0, khi);
-                            a0 = a1;
+                            lower_bound_pair(key, a0, b0, klo, khi, a0, b0);
                         }
                         scan(a0, b0);
                     } else {
+                        // a row of coarse cells along x is one run of the sorted particles
                         const int up = lev - 10;
-                        const int x1 = min((ax + 1) << up, g.nx), y1 = min((ay + 1) << up, g.ny), z1 = min((az + 1) << up, g.nz);
+                        const int x0 = ax << up, x1 = min((ax + 1) << up, g.nx), y1 = min((ay + 1) << up, g.ny),
+                                  z1 = min((az + 1) << up, g.nz);
                         for (int qz = az << up; qz < z1; ++qz)
-                            for (int qy = ay << up; qy < y1; ++qy)
-                                for (int qx = ax << up; qx < x1; ++qx) {
-                                    const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + qx;
-                                    scan(cstart[cc], cend[cc]);
-                                }
+                            for (int qy = ay << up; qy < y1; ++qy) {
+                                const uint64_t cc = ((uint64_t)qz * g.ny + qy) * g.nx + x0;
+                                scan(cstart[cc], cstart[cc + (x1 - x0)]);
+                            }
                     }
                 }
             }
@@ -860,15 +907,16 @@ static int smoothing_length_impl(const bp_params *p, int64_t n, const float *the
     {
         Arena B(nullptr, 0);
         B.take<uint64_t>(n); B.take<uint64_t>(n); B.take<uint32_t>(n); B.take<uint32_t>(n);
-        B.take<double>(3 * n); B.take<uint32_t>(g.ncells); B.take<uint32_t>(g.ncells); B.take<int>(1);
-        need += B.used + radix_ws_bytes(n) + 256;
+        B.take<double>(3 * n); B.take<uint32_t>(g.ncells + 1); B.take<uint32_t>(g.ncells); B.take<int>(1);
+        const size_t rw = radix_ws_bytes(n), sw = scan_ws_bytes(g.ncells);
+        need += B.used + (rw > sw ? rw : sw) + 256;
     }
     if (ws_bytes < need) { *ws_needed = need; return BP_E_WORKSPACE; }
     *ws_needed = need;
     uint64_t *k0 = A.take<uint64_t>(n), *k1 = A.take<uint64_t>(n);
     uint32_t *v0 = A.take<uint32_t>(n), *v1 = A.take<uint32_t>(n);
     double *sp = A.take<double>(3 * n);
-    uint32_t *cs = A.take<uint32_t>(g.ncells), *ce = A.take<uint32_t>(g.ncells);
+    uint32_t *cs = A.take<uint32_t>(g.ncells + 1), *ce = A.take<uint32_t>(g.ncells);
     int *fail = A.take<int>(1);
     void *sws = (char *)ws + A.used;
     prof_begin(BP_PROF_PP_SORT, s);
@@ -881,6 +929,13 @@ static int smoothing_length_impl(const bp_params *p, int64_t n, const float *the
     if (fill_u32(cs, 0u, g.ncells, s) || fill_u32(ce, 0u, g.ncells, s) || fill_u32((uint32_t *)fail, 0u, 1, s))
         return BP_E_HIP;
     hipLaunchKernelGGL(k_pp_gather, dim3(blocks), dim3(256), 0, s, n, g, pos, ks, vs, sp, cs, ce);
+    // cell starts as a lower-bound array (cs[c] for every cell, cs[ncells] = n), cell ends = cs + 1
+    hipLaunchKernelGGL(k_pp_cell_counts, dim3((unsigned)((g.ncells + 255) / 256)), dim3(256), 0, s, g.ncells, cs, ce);
+    if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+    e = scan_exclusive_u32(ce, cs, g.ncells, sws, s);
+    if (e) return e;
+    if (fill_u32(cs + g.ncells, (uint32_t)n, 1, s)) return BP_E_HIP;
+    ce = cs + 1;
     prof_end(BP_PROF_PP_SORT, s);
     prof_begin(BP_PROF_PP_KNN, s);
     if (k <= 16)
