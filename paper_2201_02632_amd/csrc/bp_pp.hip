@@ -178,6 +178,7 @@ constexpr int kKmax = 64;
 // by compile-time constants (a runtime index would push the array into scratch memory).  The
 // lowest K - k slots hold -inf and never move, so the last slot is always the k-th smallest
 // (+inf until k values have arrived).  Insertion shifts the larger entries up by one, branch-free.
+// (All values are finite distances or the +-inf sentinels, never NaN.)
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 template <int K>
 struct TopK {
@@ -191,11 +192,10 @@ struct TopK {
     __device__ float kth() const { return at(K - 1); }
     __device__ void push(float x) {
         if (!(x < kth())) return;
+        // slot q becomes x clamped to [slot q-1, slot q] (old values, the array being sorted): the
+        // median of the three, one v_med3_f32 per slot
 #pragma unroll
-        for (int q = K - 1; q > 0; --q) {
-            const float lo = at(q - 1), cur = at(q);
-            v[q >> 4][q & 15] = (x < lo) ? lo : ((x < cur) ? x : cur);
-        }
+        for (int q = K - 1; q > 0; --q) v[q >> 4][q & 15] = __builtin_amdgcn_fmed3f(at(q - 1), x, at(q));
         v[0][0] = fminf(v[0][0], x);
     }
 };
@@ -294,14 +294,22 @@ k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint3
         const float uz = fminf(fmaxf((float)((mez - g.z0) / s - (double)gz), 0.0f), 1.0f);
         const float mface = fminf(fminf(fminf(ux, 1.0f - ux), fminf(uy, 1.0f - uy)), fminf(uz, 1.0f - uz));
         const float s2 = (float)(s * s);
-        // all particles of a contiguous sorted range, four at a time: the positions of a group are
-        // loaded before its insertions, so their latencies overlap
+        // all particles of a contiguous sorted range, eight (then four) at a time: the positions of a
+        // group are loaded before its insertions, so their latencies overlap
         auto dist2 = [&](uint32_t j) {
             const float ddx = (float)(sp[j] - mex), ddy = (float)(sp[n + j] - mey), ddz = (float)(sp[2 * n + j] - mez);
             return ddx * ddx + ddy * ddy + ddz * ddz;
         };
         auto scan = [&](uint32_t a0, uint32_t b0) {
             uint32_t j = a0;
+            for (; j + 8 <= b0; j += 8) {
+                float d2[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) d2[u] = dist2(j + u);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (j + u != (uint32_t)i) T.push(d2[u]);
+            }
             for (; j + 4 <= b0; j += 4) {
                 float d2[4];
 #pragma unroll
