@@ -98,6 +98,92 @@ def test_adam_step_vs_oracle(bp):
     assert np.array_equal(mlp.bf16(wd.cpu().numpy()), wb_f)
 
 
+_M64 = (1 << 64) - 1
+
+
+def _splitmix64(x):
+    """SplitMix64's output function (Steele, Lea & Flood 2014) on integers mod 2^64."""
+    x = (x + 0x9E3779B97F4A7C15) & _M64
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & _M64
+    return x ^ (x >> 31)
+
+
+def _drawn_rows(seed, step, n, ndata):
+    """The rows bp_surrogate_train draws for one step (its documented counter-based draw)."""
+    return np.array([(_splitmix64(seed ^ _splitmix64((step * 0x100000001B3 + i) & _M64)) >> 11) % ndata
+                     for i in range(n)], dtype=np.int64)
+
+
+def test_training_step_vs_oracle(bp):
+    """One bp_surrogate_train step (drawn batch, fused forward, loss, backward and Adam) against the
+    oracle's forward, weighted MSE and backward on the same rows, and Adam from the step's gradient.
+    A ragged batch (300 rows: 4 full 64-row chunks and a 44-row tail, two split-K slices) and a data
+    row with a non-finite target."""
+    import torch
+
+    from oracle import mlp
+    from paper_2201_02632_amd.surrogate import Surrogate
+    S = Surrogate(seed=8)
+    rng = np.random.default_rng(23)
+    w = S.w.cpu().numpy().astype(np.float64)
+    L = S._layout()
+    for name in ("b1", "b2", "b3", "b4"):
+        off, nb = L[name]
+        w[off:off + nb] = rng.normal(0, 0.1, nb)
+    S.w.copy_(torch.from_numpy(w.astype(np.float32)))
+    bp._check(bp._lib.bp_mlp_to_bf16(S.np, bp._ptr(S.w), bp._ptr(S.wb), bp._stream()), "to_bf16")
+    S.m.zero_()
+    S.v.zero_()
+    ndata, batch, seed, step0, lr = 700, 300, 12345, 41, 1e-3
+    x = np.zeros((ndata, 16), np.float32)
+    x[:, :3] = rng.uniform(-1.2, 1.2, (ndata, 3))
+    t = rng.normal(size=(ndata, 144)).astype(np.float32)
+    rows = _drawn_rows(seed, step0, batch, ndata)
+    bad = int(rows[7])
+    t[bad, 60] = np.nan   # a drawn row with a non-finite target
+    mean = rng.normal(size=144).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, 144).astype(np.float32)
+    S.mean.copy_(torch.as_tensor(mean))
+    S.std.copy_(torch.as_tensor(std))
+    xd, td = torch.as_tensor(x, device="cuda"), torch.as_tensor(t, device="cuda")
+    w0 = S.w.cpu().numpy().astype(np.float64)
+    ws = torch.empty(int(bp._lib.bp_surrogate_train_ws_bytes(batch)), dtype=torch.uint8, device="cuda")
+    loss = torch.empty(batch, dtype=torch.float32, device="cuda")
+    bp._check(bp._lib.bp_surrogate_train(bp._ptr(S.w), bp._ptr(S.wb), bp._ptr(S.m), bp._ptr(S.v), bp._ptr(S.g),
+                                         bp._ptr(S.mean), bp._ptr(S.std), ndata, bp._ptr(xd), bp._ptr(td), 1, batch,
+                                         lr, lr, seed, step0, bp._ptr(loss), bp._ptr(ws), ws.numel(), bp._stream()),
+              "bp_surrogate_train")
+    torch.cuda.synchronize()
+    g = S.g.cpu().numpy().astype(np.float64)
+    w1 = S.w.cpu().numpy().astype(np.float64)
+    # oracle on the drawn rows
+    yo, cache = mlp.forward(w0, x[rows])
+    dy, lrows = mlp.weighted_mse(yo, t[rows], mean, std)
+    go = mlp.backward(w0, cache, dy)
+    errs = {}
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"):
+        off, nb = L[name]
+        a, o = g[off:off + nb], go[off:off + nb]
+        errs[name] = np.linalg.norm(a - o) / max(np.linalg.norm(o), 1e-300)
+    print("training-step gradient, relative L2 error per group:", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 1e-3
+    lg = loss.cpu().numpy().astype(np.float64)
+    ok = np.isfinite(lrows)
+    assert not ok[7]
+    el = np.max(np.abs(lg[ok] - lrows[ok]) / np.abs(lrows[ok]))
+    print(f"per-row loss: max relative error {el:.2e}")
+    assert el <= 1e-3
+    # Adam from the step's own gradient (state zero, step counter step0 + 1)
+    f32 = lambda v: float(np.float32(v))
+    wo, _, _ = mlp.adam(w0, np.zeros_like(w0), np.zeros_like(w0), g, f32(lr), f32(0.9), f32(0.999), f32(1e-8),
+                        step0 + 1)
+    bound = 4e-6 * np.abs(wo - w0) + 2.0 ** -24 * np.abs(wo) + 1e-30
+    ew = np.max(np.abs(w1 - wo) / bound)
+    print(f"Adam after the step: max |w err| / bound {ew:.2e}")
+    assert ew <= 1.0
+
+
 def test_weighted_mse_vs_oracle(bp):
     """bp_surrogate_mse against the loss written out in FP64: gradient and per-row loss, a row with a
     non-finite target left out."""
