@@ -763,43 +763,67 @@ __global__ void __launch_bounds__(256) k_pp_deposit_narrow(int npix, double pix,
     }
 }
 
-// wide particles: one 256-lane workgroup per 64x64 tile; lane owns column (t & 63), rows (t >> 6) + 4k.
+// wide particles: one 256-lane workgroup per 64x64 tile, 16 pixels per lane (the MFMA output layout).
 // Per batch of 8 particles the 64 x- and 64 y-weights of each are staged in LDS.
 constexpr int kBatch = 8;
+constexpr int kRecWords = sizeof(PPRec) / 4;
+typedef float fx4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, int ntx, const PPRec *__restrict__ rec,
                                                          const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ts,
                                                          const uint32_t *__restrict__ te, float *__restrict__ ymap,
                                                          float *__restrict__ bmap) {
-    // x-weights by particle; y-weights by row, a row's batch contiguous (16-byte reads)
+    // x-weights by particle; y-weights by row (a row's batch contiguous, padded against bank conflicts)
     __shared__ float wxs[kBatch][kWT];
-    __shared__ __attribute__((aligned(16))) float wys[kWT][kBatch];
+    __shared__ float wys[kWT][kBatch + 1];
     __shared__ float amp[kBatch][2];
+    __shared__ uint32_t rsw[kBatch * kRecWords];   // the batch's records
     const uint32_t tile = blockIdx.x;
     const uint32_t p0 = ts[tile], p1 = te[tile];
     if (p0 >= p1) return;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // the records of the next batch are fetched (one word per thread) while the current batch runs
+    uint32_t pw = 0u;
+    auto fetch = [&](uint32_t pb) {
+        if (t < kBatch * kRecWords) {
+            const uint32_t b = (uint32_t)t / kRecWords, k = (uint32_t)t % kRecWords;
+            pw = (pb + b < p1) ? reinterpret_cast<const uint32_t *>(rec + vals[pb + b])[k] : 0u;
+        }
+    };
+    fetch(p0);
     const int tx = tile % ntx, ty = tile / ntx;
-    const int pi = tx * kWT + (t & 63), pj0 = ty * kWT + (t >> 6);
+    // The batch's update of the tile is the product Wy^T (amp Wx) over its particles, one MFMA
+    // (v_mfma_f32_16x16x4_f32, four particles) per 16x16 block and map.  Wavefront w owns the tile
+    // rows 16 w .. 16 w + 15; lane l holds the pixels (row 16 w + 4 (l / 16) + j, column 16 bj + l % 16),
+    // j, bj < 4, as the MFMA leaves them.
+    const int li = lane & 15, lq = lane >> 4;
+    const int pi0 = tx * kWT + li, pj0 = ty * kWT + 16 * w + 4 * lq;
     float ys[16], yc[16], bs[16], bc[16];
-    for (int k = 0; k < 16; ++k) {
-        int pj = pj0 + 4 * k;
-        bool in = pi < npix && pj < npix;
-        int64_t id = (int64_t)pj * npix + pi;
-        ys[k] = in ? ymap[id] : 0.0f; bs[k] = in ? bmap[id] : 0.0f; yc[k] = 0.0f; bc[k] = 0.0f;
-    }
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * bj + j, pi = pi0 + 16 * bj, pj = pj0 + j;
+            const bool in = pi < npix && pj < npix;
+            const int64_t id = (int64_t)pj * npix + pi;
+            ys[k] = in ? ymap[id] : 0.0f; bs[k] = in ? bmap[id] : 0.0f; yc[k] = 0.0f; bc[k] = 0.0f;
+        }
     for (uint32_t pb = p0; pb < p1; pb += kBatch) {
         const int nb = (int)min((uint32_t)kBatch, p1 - pb);
         __syncthreads();
+        if (t < kBatch * kRecWords) rsw[t] = pw;
+        __syncthreads();
+        if (pb + kBatch < p1) fetch(pb + kBatch);
         // stage weights: threads 0..255 cover 8 particles x (64 x-weights or 64 y-weights) in two passes
         for (int q = t; q < kBatch * 2 * kWT; q += 256) {
             int b = q / (2 * kWT), r = q % (2 * kWT);
             float v = 0.0f;
             if (b < nb) {
-                const PPRec R = rec[vals[pb + b]];
+                PPRec R;
+                __builtin_memcpy(&R, &rsw[b * kRecWords], sizeof(PPRec));
                 if (r < kWT) {
                     int c = tx * kWT + r;
-                    int w = R.wh & 0xffff;
-                    if (c >= R.i0 && c < R.i0 + w) {
+                    int wd = R.wh & 0xffff;
+                    if (c >= R.i0 && c < R.i0 + wd) {
                         float e0 = (float)(c - R.ipx) - R.fpx;
                         v = cell_weight(e0 * R.ih, (e0 + 1.0f) * R.ih);
                     }
@@ -820,42 +844,42 @@ __global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, i
             }
         }
         __syncthreads();
-        // per pixel: the batch's contributions summed in order in FP32, then one compensated
-        // update of the pixel's running sum per batch (unused batch slots have zero weights)
-        float ax[kBatch], bx[kBatch];
+        // the batch's sums per pixel in FP32 (MFMA), then one compensated update of the pixel's
+        // running sum per batch (unused batch slots have zero weights)
+        fx4 dy[4], db[4];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const float wx = wxs[b][t & 63];
-            ax[b] = amp[b][0] * wx;
-            bx[b] = amp[b][1] * wx;
-        }
+        for (int bj = 0; bj < 4; ++bj) { dy[bj] = fx4{0.0f, 0.0f, 0.0f, 0.0f}; db[bj] = dy[bj]; }
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int rr = (t >> 6) + 4 * k;   // wave-uniform: the row's weights are broadcast reads
-            float wy[kBatch];
+        for (int s4 = 0; s4 < kBatch / 4; ++s4) {
+            const int p = 4 * s4 + lq;                    // this lane's particle of the k step
+            const float a = wys[16 * w + li][p];          // A[row][p] = Wy[p][row]
+            const float ay = amp[p][0], ab = amp[p][1];
 #pragma unroll
-            for (int b = 0; b < kBatch; b += 4) {
-                const float4 w4 = *reinterpret_cast<const float4 *>(&wys[rr][b]);
-                wy[b] = w4.x; wy[b + 1] = w4.y; wy[b + 2] = w4.z; wy[b + 3] = w4.w;
+            for (int bj = 0; bj < 4; ++bj) {
+                const float wx = wxs[p][16 * bj + li];    // B[p][col] = amp Wx[p][col]
+                dy[bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ay * wx, dy[bj], 0, 0, 0);
+                db[bj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ab * wx, db[bj], 0, 0, 0);
             }
-            float sy = 0.0f, sb = 0.0f;
+        }
+        // rows that no particle of the batch reaches add an exact zero
 #pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                sy = fmaf(ax[b], wy[b], sy);
-                sb = fmaf(bx[b], wy[b], sb);
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                kahan(ys[4 * bj + j], yc[4 * bj + j], dy[bj][j]);
+                kahan(bs[4 * bj + j], bc[4 * bj + j], db[bj][j]);
             }
-            // rows that no particle of the batch reaches add an exact zero
-            kahan(ys[k], yc[k], sy);
-            kahan(bs[k], bc[k], sb);
-        }
     }
-    for (int k = 0; k < 16; ++k) {
-        int pj = pj0 + 4 * k;
-        if (pi < npix && pj < npix) {
-            int64_t id = (int64_t)pj * npix + pi;
-            ymap[id] = ys[k]; bmap[id] = bs[k];
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * bj + j, pi = pi0 + 16 * bj, pj = pj0 + j;
+            if (pi < npix && pj < npix) {
+                const int64_t id = (int64_t)pj * npix + pi;
+                ymap[id] = ys[k]; bmap[id] = bs[k];
+            }
         }
-    }
 }
 
 }  // namespace bp
