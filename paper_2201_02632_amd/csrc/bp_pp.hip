@@ -737,10 +737,9 @@ __global__ void __launch_bounds__(256) k_pp_deposit_narrow(int npix, double pix,
         int64_t id = (int64_t)pj * npix + pi;
         ys[k] = in ? ymap[id] : 0.0f; bs[k] = in ? bmap[id] : 0.0f; yc[k] = 0.0f; bc[k] = 0.0f;
     }
-    for (uint32_t p = p0; p < p1; ++p) {
-        const PPRec R = rec[vals[p]];
+    auto add = [&](const PPRec &R) {
         const int w = R.wh & 0xffff, h = R.wh >> 16;
-        if (pi < R.i0 || pi >= R.i0 + w) continue;
+        if (pi < R.i0 || pi >= R.i0 + w) return;
         // x weight of this lane's column: pixel edges relative to the particle, in units of H
         const float ex = (float)(pi - R.ipx) - R.fpx;
         const float wx = cell_weight(ex * R.ih, (ex + 1.0f) * R.ih);
@@ -753,7 +752,17 @@ __global__ void __launch_bounds__(256) k_pp_deposit_narrow(int npix, double pix,
             kahan(ys[k], yc[k], R.ay * f);
             kahan(bs[k], bc[k], R.ab * f);
         }
+    };
+    // records four at a time: their loads are in flight together, the sums stay in particle order
+    uint32_t p = p0;
+    for (; p + 4 <= p1; p += 4) {
+        PPRec R[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) R[u] = rec[vals[p + u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(R[u]);
     }
+    for (; p < p1; ++p) add(rec[vals[p]]);
     for (int k = 0; k < 4; ++k) {
         int pj = pj0 + 4 * k;
         if (pi < npix && pj < npix) {
