@@ -258,7 +258,9 @@ int bp_pp_smoothing_length(const bp_params *p, int64_t n, const float *theta_x, 
  * itself (the SPH density sum), i.e. (32/3) sum_j w(r_ij / h).  Positions, units, workspace and
  * errors as bp_pp_smoothing_length (which runs first, for the 32-NN distance that seeds a
  * bracketed Halley iteration on h, stopped after a step below 1e-3 relative,
- * which leaves an error of order 1e-9).  n_ngb in (32/3, 1024]
+ * which leaves an error of order 1e-9).  For n_ngb <= 64 (and n > 64) the search keeps the 64
+ * nearest neighbours and runs the iteration on their list, which is exact for a root up to the
+ * 64th distance; the other particles iterate over the cells as above.  n_ngb in (32/3, 1024]
  * (BP_E_ARG otherwise); n > 32.  A particle whose root is not found writes NaN. */
 int bp_pp_smoothing_length_eff(const bp_params *p, int64_t n, const float *theta_x, const float *theta_y,
                                const float *z, double n_ngb, double cell, float *h_comoving, void *ws,

@@ -239,6 +239,54 @@ __device__ inline void lower_bound_pair(const uint64_t *__restrict__ key, uint32
     r2 = lower_bound64(key, l2, h2, t2);
 }
 
+// ----------------------------------- K6b smoothing length from the effective neighbour number --
+// h solves N_eff(h) = (4 pi/3) h^3 sum_j W(r_ij, h) = (32/3) sum_j w(r_ij/h) = n_ngb (Sec. 3.4,
+// Eq. SPH_kernel), the particle itself included (the standard SPH density sum).  N_eff is continuous,
+// non-decreasing and once differentiable in h.  Halley's iteration on h, kept inside a bracket, starts
+// from the k-NN distance scaled to the target count; each evaluation sums the kernel and its h-derivatives over
+// the particles of every cell within h, on the level whose cells are between h/2 and h wide.
+// w(x), g(x) = -x w'(x) and g(x) + x g'(x), which give N_eff and its first two h-derivatives:
+// dN/dh = (32/3) sum g / h,  d2N/dh2 = -(32/3) sum (g + x g') / h^2
+__device__ inline void wsph_slope(float x, float &w, float &g, float &c) {
+    if (x < 0.5f) {
+        const float x2 = x * x;
+        w = fmaf(6.0f * x2, x - 1.0f, 1.0f);
+        g = x2 * fmaf(-18.0f, x, 12.0f);
+        c = x2 * fmaf(-72.0f, x, 36.0f);
+    } else if (x < 1.0f) {
+        const float t = 1.0f - x;
+        w = 2.0f * t * t * t;
+        g = 6.0f * x * t * t;
+        c = 12.0f * x * t * (1.0f - 2.0f * x);
+    } else {
+        w = 0.0f; g = 0.0f; c = 0.0f;
+    }
+}
+
+constexpr int kNeffIter = 60;
+constexpr double kNeffListMax = 64.0;   // n_ngb up to which the 64-NN list usually holds the root
+constexpr int kNeffMaxShell = 4;
+
+
+// One bracketed Halley step on N_eff(h) - nngb from F = N_eff(h) and its first two h-derivatives:
+// updates the bracket [lo, hi] and h, and returns whether the step converged.
+__device__ inline bool neff_step(float F, float dF, float d2F, float nngb, float &lo, float &hi, float &h) {
+    if (F < nngb) lo = h; else hi = h;
+    // Halley's step: third order, since N_eff(h) is twice continuously differentiable (the cubic
+    // spline's third derivative jumps where a neighbour crosses h/2, the fourth at h)
+    const float Fm = F - nngb, den = 2.0f * dF * dF - Fm * d2F;
+    float hn = (dF > 0.0f && den > 0.0f) ? h - 2.0f * Fm * dF / den : 2.0f * h;
+    const bool step = hn > lo && hn < hi && hn <= 2.0f * h;
+    if (!step) hn = isinf(hi) ? 2.0f * h : 0.5f * (lo + hi);
+    // a step below 1e-3 relative: the error left after it is of the order of its cube, ~1e-9,
+    // under the FP32 rounding of the sums (stopping at 1e-6 instead costs one more scan for
+    // most particles and changes no h by more than that rounding)
+    bool conv = step && fabsf(hn - h) <= 1e-3f * h;
+    if (!step && !isinf(hi) && hi - lo <= 1e-6f * hi) conv = true;
+    h = hn;
+    return conv;
+}
+
 // One lane per particle, in sorted (cell, Morton) order.  Level-l cells have size cell * 2^(l-10):
 // level 10 is the coarse grid, finer levels are aligned Morton blocks inside a coarse cell, and
 // coarser ones are blocks of 2^(l-10) coarse cells per axis.  Cells are scanned in Chebyshev shells
@@ -250,11 +298,15 @@ __device__ inline void lower_bound_pair(const uint64_t *__restrict__ key, uint32
 constexpr int kShells = 8;
 constexpr int kMaxLevel = 20;
 
-template <int K>
+// kNeff: after the 64 nearest neighbours (k = K = 64), solve N_eff(h) = nngb from their list (the
+// bracketed Halley steps of k_pp_neff, seeded alike from the 32-NN distance times seed_scale).  The
+// list holds every particle within h while h does not exceed the 64th distance, so a root at or
+// below it is the root; otherwise -(32-NN distance) is written for k_pp_neff to finish.
+template <int K, bool kNeff = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 32 ? 4 : 2)))
 k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
          const double *__restrict__ sp, const uint32_t *__restrict__ cstart, const uint32_t *__restrict__ cend,
-         float *__restrict__ h_out, int *__restrict__ fail) {
+         float *__restrict__ h_out, int *__restrict__ fail, float nngb = 0.0f, float seed_scale = 0.0f) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint64_t ki = key[i];
@@ -374,45 +426,51 @@ k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint3
         }
     }
     // a particle too isolated for the largest search gets NaN and raises the failure flag
-    const float h = done ? sqrtf(T.kth()) : __int_as_float(0x7fc00000);
-    if (!done) atomicOr(fail, 1);
-    h_out[idx[i]] = h;
-}
-
-// ----------------------------------- K6b smoothing length from the effective neighbour number --
-// h solves N_eff(h) = (4 pi/3) h^3 sum_j W(r_ij, h) = (32/3) sum_j w(r_ij/h) = n_ngb (Sec. 3.4,
-// Eq. SPH_kernel), the particle itself included (the standard SPH density sum).  N_eff is continuous,
-// non-decreasing and once differentiable in h.  Halley's iteration on h, kept inside a bracket, starts
-// from the k-NN distance scaled to the target count; each evaluation sums the kernel and its h-derivatives over
-// the particles of every cell within h, on the level whose cells are between h/2 and h wide.
-// w(x), g(x) = -x w'(x) and g(x) + x g'(x), which give N_eff and its first two h-derivatives:
-// dN/dh = (32/3) sum g / h,  d2N/dh2 = -(32/3) sum (g + x g') / h^2
-__device__ inline void wsph_slope(float x, float &w, float &g, float &c) {
-    if (x < 0.5f) {
-        const float x2 = x * x;
-        w = fmaf(6.0f * x2, x - 1.0f, 1.0f);
-        g = x2 * fmaf(-18.0f, x, 12.0f);
-        c = x2 * fmaf(-72.0f, x, 36.0f);
-    } else if (x < 1.0f) {
-        const float t = 1.0f - x;
-        w = 2.0f * t * t * t;
-        g = 6.0f * x * t * t;
-        c = 12.0f * x * t * (1.0f - 2.0f * x);
-    } else {
-        w = 0.0f; g = 0.0f; c = 0.0f;
+    if (!done) {
+        atomicOr(fail, 1);
+        h_out[idx[i]] = __int_as_float(0x7fc00000);
+        return;
     }
+    if (!kNeff) {
+        h_out[idx[i]] = sqrtf(T.kth());
+        return;
+    }
+    // N_eff from the list, the particle itself included (w(0) = 1)
+    const float r32 = sqrtf(T.at(31)), rmax2 = T.kth();
+    float h = r32 * seed_scale, lo = 0.0f, hi = __builtin_inff();
+    bool conv = false, exact = false;   // exact: the last evaluation was at h within the list
+    for (int it = 0; it < kNeffIter && !conv; ++it) {
+        const float h2 = h * h, ih = 1.0f / h;
+        exact = h2 <= rmax2;
+        float sw = 1.0f, ss = 0.0f, sc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const float d2 = T.at(q);
+            if (d2 < h2) {
+                float wq, gq, cq;
+                wsph_slope(sqrtf(d2) * ih, wq, gq, cq);
+                sw += wq; ss += gq; sc += cq;
+            }
+        }
+        const float F = (32.0f / 3.0f) * sw, dF = (32.0f / 3.0f) * ss * ih, d2F = -(32.0f / 3.0f) * sc * ih * ih;
+        conv = neff_step(F, dF, d2F, nngb, lo, hi, h);
+        if (lo * lo >= rmax2) break;   // the root is not below the list's last distance
+    }
+    // otherwise k_pp_neff finishes from the same seed as without the list (a seed above the root,
+    // such as one scaled from N_eff at the 64th distance, makes its first scans wider and slower)
+    h_out[idx[i]] = (conv && exact && h * h <= rmax2) ? h : -r32;
 }
 
-constexpr int kNeffIter = 60;
-constexpr int kNeffMaxShell = 4;
-
+// With fallback set only the particles whose h_io is negative run (those the 64-NN list could not
+// settle, h_io = -(32-NN distance)); the others keep their value.
 __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, float seed_scale,
                                                  const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
                                                  const double *__restrict__ sp, const uint32_t *__restrict__ cstart,
                                                  const uint32_t *__restrict__ cend, float *__restrict__ h_io,
-                                                 int *__restrict__ fail) {
+                                                 int *__restrict__ fail, int fallback) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (fallback && !(h_io[idx[i]] < 0.0f)) return;
     const uint64_t ki = key[i];
     const uint64_t c = ki >> 30;
     const int cx = (int)(c % g.nx), cy = (int)((c / g.nx) % g.ny), cz = (int)(c / ((uint64_t)g.nx * g.ny));
@@ -424,7 +482,7 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
         fz |= ((m >> (3 * b + 2)) & 1u) << b;
     }
     const uint32_t oi = idx[i];
-    float h = h_io[oi] * seed_scale;
+    float h = fabsf(h_io[oi]) * seed_scale;
     bool ok = h > 0.0f && isfinite(h);
     float lo = 0.0f, hi = __builtin_inff();
     bool conv = false;
@@ -515,19 +573,7 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
             }
         }
         const float F = (32.0f / 3.0f) * sw, dF = (32.0f / 3.0f) * ss * ih, d2F = -(32.0f / 3.0f) * sc * ih * ih;
-        if (F < nngb) lo = h; else hi = h;
-        // Halley's step: third order, since N_eff(h) is twice continuously differentiable (the cubic
-        // spline's third derivative jumps where a neighbour crosses h/2, the fourth at h)
-        const float Fm = F - nngb, den = 2.0f * dF * dF - Fm * d2F;
-        float hn = (dF > 0.0f && den > 0.0f) ? h - 2.0f * Fm * dF / den : 2.0f * h;
-        const bool step = hn > lo && hn < hi && hn <= 2.0f * h;
-        if (!step) hn = isinf(hi) ? 2.0f * h : 0.5f * (lo + hi);
-        // a step below 1e-3 relative: the error left after it is of the order of its cube, ~1e-9,
-        // under the FP32 rounding of the sums (stopping at 1e-6 instead costs one more scan for
-        // most particles and changes no h by more than that rounding)
-        conv = step && fabsf(hn - h) <= 1e-3f * h;
-        if (!step && !isinf(hi) && hi - lo <= 1e-6f * hi) conv = true;
-        h = hn;
+        conv = neff_step(F, dF, d2F, nngb, lo, hi, h);
     }
     if (!(ok && conv)) atomicOr(fail, 1);
     h_io[oi] = (ok && conv) ? h : __int_as_float(0x7fc00000);
@@ -979,7 +1025,12 @@ static int smoothing_length_impl(const bp_params *p, int64_t n, const float *the
     ce = cs + 1;
     prof_end(BP_PROF_PP_SORT, s);
     prof_begin(BP_PROF_PP_KNN, s);
-    if (k <= 16)
+    // the effective-neighbour length for n_ngb <= 64 starts from the 64-NN list (see k_pp_knn)
+    const bool list = n_ngb > 0.0 && n_ngb <= kNeffListMax && n > 64;
+    if (list)
+        hipLaunchKernelGGL((k_pp_knn<64, true>), dim3(blocks), dim3(256), 0, s, n, g, 64, ks, vs, sp, cs, ce,
+                           h_comoving, fail, (float)n_ngb, (float)cbrt(n_ngb / 32.0));
+    else if (k <= 16)
         hipLaunchKernelGGL(k_pp_knn<16>, dim3(blocks), dim3(256), 0, s, n, g, (int)k, ks, vs, sp, cs, ce, h_comoving,
                            fail);
     else if (k <= 32)
@@ -994,7 +1045,7 @@ static int smoothing_length_impl(const bp_params *p, int64_t n, const float *the
         const float seed = (float)cbrt(n_ngb / (double)k);
         prof_begin(BP_PROF_PP_NEFF, s);
         hipLaunchKernelGGL(k_pp_neff, dim3(blocks), dim3(256), 0, s, n, g, (float)n_ngb, seed, ks, vs, sp, cs, ce,
-                           h_comoving, fail);
+                           h_comoving, fail, list ? 1 : 0);
         prof_end(BP_PROF_PP_NEFF, s);
     }
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
