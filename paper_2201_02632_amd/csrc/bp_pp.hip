@@ -23,6 +23,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "bp_cosmo.hpp"
 #include "bp_device.hpp"
 #include "bp_internal.hpp"
@@ -461,16 +463,21 @@ k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint3
     h_out[idx[i]] = (conv && exact && h * h <= rmax2) ? h : -r32;
 }
 
-// With fallback set only the particles whose h_io is negative run (those the 64-NN list could not
-// settle, h_io = -(32-NN distance)); the others keep their value.
+// With a list, thread t runs the sorted particle list[t] for t < *nlist: the particles the 64-NN
+// list could not settle (h_io = -(32-NN distance)), packed so that a wavefront's lanes all work.
 __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, float seed_scale,
                                                  const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
                                                  const double *__restrict__ sp, const uint32_t *__restrict__ cstart,
                                                  const uint32_t *__restrict__ cend, float *__restrict__ h_io,
-                                                 int *__restrict__ fail, int fallback) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (fallback && !(h_io[idx[i]] < 0.0f)) return;
+                                                 int *__restrict__ fail, const uint32_t *__restrict__ list,
+                                                 const uint32_t *__restrict__ nlist) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (list) {
+        if (i >= (int64_t)*nlist) return;
+        i = list[i];
+    } else if (i >= n) {
+        return;
+    }
     const uint64_t ki = key[i];
     const uint64_t c = ki >> 30;
     const int cx = (int)(c % g.nx), cy = (int)((c / g.nx) % g.ny), cz = (int)(c / ((uint64_t)g.nx * g.ny));
@@ -577,6 +584,20 @@ __global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, 
     }
     if (!(ok && conv)) atomicOr(fail, 1);
     h_io[oi] = (ok && conv) ? h : __int_as_float(0x7fc00000);
+}
+
+// The particles left to k_pp_neff by the 64-NN list, packed in sorted order: flags (flag[n] = 0),
+// their exclusive prefix sum in place, then list[pos[i]] = i (pos[n] is the count).
+__global__ void k_pp_fb_flags(int64_t n, const uint32_t *__restrict__ idx, const float *__restrict__ h,
+                              uint32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = h[idx[i]] < 0.0f ? 1u : 0u;
+    else if (i == n) flag[n] = 0u;
+}
+__global__ void k_pp_fb_list(int64_t n, const uint32_t *__restrict__ idx, const float *__restrict__ h,
+                             const uint32_t *__restrict__ pos, uint32_t *__restrict__ list) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && h[idx[i]] < 0.0f) list[pos[i]] = (uint32_t)i;
 }
 
 // ---------------------------------------------------- K7 amplitudes --
@@ -995,8 +1016,8 @@ static int smoothing_length_impl(const bp_params *p, int64_t n, const float *the
         Arena B(nullptr, 0);
         B.take<uint64_t>(n); B.take<uint64_t>(n); B.take<uint32_t>(n); B.take<uint32_t>(n);
         B.take<double>(3 * n); B.take<uint32_t>(g.ncells + 1); B.take<uint32_t>(g.ncells); B.take<int>(1);
-        const size_t rw = radix_ws_bytes(n), sw = scan_ws_bytes(g.ncells);
-        need += B.used + (rw > sw ? rw : sw) + 256;
+        const size_t rw = radix_ws_bytes(n), sw = scan_ws_bytes(g.ncells), sn = scan_ws_bytes(n + 1);
+        need += B.used + std::max(rw, std::max(sw, sn)) + 256;
     }
     if (ws_bytes < need) { *ws_needed = need; return BP_E_WORKSPACE; }
     *ws_needed = need;
@@ -1044,8 +1065,22 @@ static int smoothing_length_impl(const bp_params *p, int64_t n, const float *the
         // seed: the k-NN distance scaled by (n_ngb / k)^(1/3), the uniform-density ratio
         const float seed = (float)cbrt(n_ngb / (double)k);
         prof_begin(BP_PROF_PP_NEFF, s);
+        const uint32_t *fl = nullptr, *nfl = nullptr;
+        if (list) {
+            // pack the particles left over (the sort's spare buffers: flags and positions in the
+            // other key array, the list in the other value array)
+            uint32_t *pos = (uint32_t *)(in1 ? k0 : k1), *fb = in1 ? v0 : v1;
+            hipLaunchKernelGGL(k_pp_fb_flags, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, n, vs,
+                               h_comoving, pos);
+            if (hipGetLastError() != hipSuccess) return BP_E_HIP;
+            e = scan_exclusive_u32(pos, pos, n + 1, sws, s);
+            if (e) return e;
+            hipLaunchKernelGGL(k_pp_fb_list, dim3(blocks), dim3(256), 0, s, n, vs, h_comoving, pos, fb);
+            fl = fb;
+            nfl = pos + n;
+        }
         hipLaunchKernelGGL(k_pp_neff, dim3(blocks), dim3(256), 0, s, n, g, (float)n_ngb, seed, ks, vs, sp, cs, ce,
-                           h_comoving, fail, list ? 1 : 0);
+                           h_comoving, fail, fl, nfl);
         prof_end(BP_PROF_PP_NEFF, s);
     }
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
