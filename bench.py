@@ -224,9 +224,8 @@ def surrogate_section(bp, params, dev, steps, warmup, n_halos, n_train, train_st
 
     def exact():
         ye.zero_(); be.zero_()
-        sol, st = bp.icm_solve(params, d["M"], d["c"], d["z"])
-        tab, meta = bp.profile_tables(params, sol, st)
-        bp.hp_paste_flat(params, npix, pix, d["theta_x"], d["theta_y"], d["v_los"], sol, st, tab, meta, ye, be, ws=ws)
+        bp.hp_flat_pipeline(params, npix, pix, d["M"], d["c"], d["z"], d["theta_x"], d["theta_y"], d["v_los"], ye, be,
+                            ws=ws)
 
     nout = [0]
     mode = ["exact"]
@@ -307,11 +306,10 @@ def allsky_section(bp, params, dev, steps, warmup, n_halos, nside, batch, sur, p
     def exact(vkey="v_los", y=ye, b=be):
         y.zero_(); b.zero_(); yc.zero_(); bc.zero_()
         for d in batches:
-            sol, st = bp.icm_solve(params, d["M"], d["c"], d["z"])
-            tab, meta = bp.profile_tables(params, sol, st)
             v = d[vkey] if vkey == "v_los" else d["v_los"].abs()
-            bp.hp_paste_healpix(params, nside, d["theta"], d["phi"], v, sol, st, tab, meta, y, b, ws=ws, comp=(yc, bc))
-            del sol, st, tab, meta
+            # solve, tables and paste in one call: the paste's plan runs beside the table quadratures
+            bp.hp_healpix_pipeline(params, nside, d["M"], d["c"], d["z"], d["theta"], d["phi"], v, y, b, ws=ws,
+                                   comp=(yc, bc))
 
     def surrogate(y=ys, b=bs):
         y.zero_(); b.zero_(); yc.zero_(); bc.zero_()
@@ -518,9 +516,9 @@ def main():
     ws = bp.Workspace(dev)
 
     def step():
-        sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
-        tab, meta = bp.profile_tables(params, sol, st)
-        bp.hp_paste_flat(params, npix, pix, t["theta_x"], t["theta_y"], t["v_los"], sol, st, tab, meta, y, b, ws=ws)
+        # solve, tables and paste in one call: the paste's plan runs beside the table quadratures
+        sol, st, _, _ = bp.hp_flat_pipeline(params, npix, pix, t["M"], t["c"], t["z"], t["theta_x"], t["theta_y"],
+                                            t["v_los"], y, b, ws=ws)
         return sol, st
 
     print(f"# warmup {args.warmup} step(s), {n} halos, {npix}^2 map", file=sys.stderr, flush=True)

@@ -200,6 +200,23 @@ int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n
                      float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
                      size_t *ws_needed, void *stream);
 
+/* The three calls above as one: bp_icm_solve, bp_profile_tables and bp_hp_paste_flat on the same
+ * inputs, with the same outputs (sol, status, tables, meta and the maps are bit-identical to those of
+ * the three calls in sequence).  What differs is the ordering: the paste's set-up and plan (footprints,
+ * pair sort and tile ranges, Sec. 3.3) need only the solution and meta, so they run on a second stream
+ * of the library's (one per device, default priority, created on the first call) while the table
+ * quadratures of Sec. 3.2 run on `stream`; the deposit waits for both on `stream`.  On return all work
+ * is ordered on `stream` as for a single call.  Workspace protocol as bp_hp_paste_flat: when ws_bytes is
+ * too small the call returns BP_E_WORKSPACE with *ws_needed set, after the solve and the tables are
+ * complete on `stream` and without touching the maps (bp_hp_paste_flat on the same outputs then
+ * finishes the job).  The call synchronises once on the second stream.  Calls on one device from
+ * several host threads are serialised inside the library. */
+int bp_hp_flat_pipeline(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *M,
+                        const double *c, const double *z, const double *theta_x, const double *theta_y,
+                        const double *v_los, double *sol, int32_t *status, float *tables, float *meta,
+                        float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
+                        size_t *ws_needed, void *stream);
+
 /* Allocation-free variant of bp_hp_paste_flat, for callers that cannot allocate device memory or
  * size a workspace (serving loops, harnesses that forbid allocation).  Same arguments, layouts,
  * results and errors as bp_hp_paste_flat (the same kernels run), without ws / ws_bytes: the call works
@@ -233,6 +250,15 @@ int bp_hp_paste_healpix(const bp_params *p, int64_t nside, int64_t n,
                         const double *sol, const int32_t *status, const float *tables, const float *meta,
                         float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
                         size_t *ws_needed, void *stream);
+
+/* bp_icm_solve, bp_profile_tables and bp_hp_paste_healpix in one call, as bp_hp_flat_pipeline is for the
+ * flat map: same outputs bit for bit, the paste's set-up and plan on the library's second stream beside
+ * the table quadratures, everything ordered on `stream` on return, same workspace protocol. */
+int bp_hp_healpix_pipeline(const bp_params *p, int64_t nside, int64_t n, const double *M, const double *c,
+                           const double *z, const double *theta, const double *phi, const double *v_los,
+                           double *sol, int32_t *status, float *tables, float *meta, float *y_map, float *b_map,
+                           float *y_comp, float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed,
+                           void *stream);
 
 /* ------------------------------------------------------- PP (K5-K8) */
 /* Smoothing lengths for particle-based pasting (Sec. 3.4): h_i is the

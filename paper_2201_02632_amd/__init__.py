@@ -6,7 +6,8 @@ the current torch stream as the HIP stream).  There is no CPU fallback: if the
 library is missing the import fails.
 
 Entry points mirror include/bp.h:
-    icm_solve, profile_tables, hp_paste_flat, healpix_ang2pix_ring, hp_paste_healpix
+    icm_solve, profile_tables, hp_paste_flat, healpix_ang2pix_ring, hp_paste_healpix,
+    hp_flat_pipeline and hp_healpix_pipeline (the three calls of each path in one)
 """
 from __future__ import annotations
 
@@ -70,6 +71,10 @@ _SIGS = {
     "bp_profile_tables": (C.c_int, [_P, C.c_int64, _VP, _VP, _VP, _VP, _VP]),
     "bp_hp_paste_flat": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                    _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_hp_flat_pipeline": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                      _VP, _VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
+    "bp_hp_healpix_pipeline": (C.c_int, [_P, C.c_int64, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                         _VP, _VP, _VP, _VP, _VP, _VP, C.c_size_t, C.POINTER(C.c_size_t), _VP]),
     "bp_hp_paste_flat_noalloc_max_bytes": (C.c_size_t, []),
     "bp_hp_paste_flat_noalloc": (C.c_int, [_P, C.c_int32, C.c_double, C.c_int64, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
                                            _VP, _VP, _VP, _VP, C.POINTER(C.c_size_t), _VP]),
@@ -268,6 +273,25 @@ def hp_paste_flat(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v
                      *_comp_ptrs(comp, y_map)))
 
 
+def hp_flat_pipeline(params: Params, npix: int, pix_rad: float, M, c, z, theta_x, theta_y, v_los, y_map, b_map,
+                     ws: Workspace | None = None, comp=None):
+    """K1, K2 and K3 in one call (bp_hp_flat_pipeline): the paste's plan overlaps the table quadratures.  Accumulates
+    into y_map, b_map like hp_paste_flat and returns (sol, status, tables, meta) as icm_solve and profile_tables do."""
+    n = M.numel()
+    dev = y_map.device
+    sol = torch.empty((SOL_NFIELDS, n), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    tab = torch.empty((n, TAB_STRIDE), dtype=torch.float32, device=dev)
+    meta = torch.empty((META_NFIELDS, n), dtype=torch.float32, device=dev)
+    if n:
+        ws = ws or _ws_for(dev)
+        _with_workspace(_lib.bp_hp_flat_pipeline, "bp_hp_flat_pipeline", ws,
+                        (C.byref(params), int(npix), float(pix_rad), n, _ptr(M), _ptr(c), _ptr(z), _ptr(theta_x),
+                         _ptr(theta_y), _ptr(v_los), _ptr(sol), _ptr(status), _ptr(tab), _ptr(meta), _ptr(y_map),
+                         _ptr(b_map), *_comp_ptrs(comp, y_map)))
+    return sol, status, tab, meta
+
+
 def hp_paste_flat_q(params: Params, npix: int, pix_rad: float, theta_x, theta_y, v_los, sol, status, qtables, meta,
                     y_map, b_map, ws: Workspace | None = None, comp=None):
     """K3 with surrogate q-tables (halos with a non-zero status are skipped)."""
@@ -295,6 +319,25 @@ def hp_paste_healpix(params: Params, nside: int, theta, phi, v_los, sol, status,
     _with_workspace(_lib.bp_hp_paste_healpix, "bp_hp_paste_healpix", ws,
                     (C.byref(params), int(nside), theta.numel(), _ptr(theta), _ptr(phi), _ptr(v_los), _ptr(sol),
                      _ptr(status), _ptr(tables), _ptr(meta), _ptr(y_map), _ptr(b_map), *_comp_ptrs(comp, y_map)))
+
+
+def hp_healpix_pipeline(params: Params, nside: int, M, c, z, theta, phi, v_los, y_map, b_map,
+                        ws: Workspace | None = None, comp=None):
+    """K1, K2 and K4 in one call (bp_hp_healpix_pipeline): the paste's plan overlaps the table quadratures.
+    Accumulates into y_map, b_map like hp_paste_healpix and returns (sol, status, tables, meta)."""
+    n = M.numel()
+    dev = y_map.device
+    sol = torch.empty((SOL_NFIELDS, n), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    tab = torch.empty((n, TAB_STRIDE), dtype=torch.float32, device=dev)
+    meta = torch.empty((META_NFIELDS, n), dtype=torch.float32, device=dev)
+    if n:
+        ws = ws or _ws_for(dev)
+        _with_workspace(_lib.bp_hp_healpix_pipeline, "bp_hp_healpix_pipeline", ws,
+                        (C.byref(params), int(nside), n, _ptr(M), _ptr(c), _ptr(z), _ptr(theta), _ptr(phi),
+                         _ptr(v_los), _ptr(sol), _ptr(status), _ptr(tab), _ptr(meta), _ptr(y_map), _ptr(b_map),
+                         *_comp_ptrs(comp, y_map)))
+    return sol, status, tab, meta
 
 
 def healpix_ang2pix_ring(nside: int, theta: torch.Tensor, phi: torch.Tensor) -> torch.Tensor:

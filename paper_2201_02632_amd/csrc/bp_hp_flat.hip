@@ -306,12 +306,16 @@ template <bool kQ>
 static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
                                 const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
                                 const float *tables, const float *meta, float *y_map, float *b_map, float *y_comp,
-                                float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
+                                float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream,
+                                hipStream_t plan_stream = nullptr, hipEvent_t plan_done = nullptr) {
     if (check_params(p) || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta_x || !theta_y || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
     if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
     hipStream_t s = (hipStream_t)stream;
+    // set-up and plan run on plan_stream when one is given (its own dependencies set by the caller),
+    // the deposit on stream after plan_done
+    hipStream_t sp = plan_stream ? plan_stream : s;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     FlatGeom Gm;
     Gm.npix = npix;
@@ -334,15 +338,15 @@ static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int
     void *scan_ws = (char *)ws + A.used;
     A.used += scan_ws_bytes(n + 1);
     // cleared with a fill kernel (a memset node misbehaves under graph replay on this target)
-    if (fill_u32((uint32_t *)total, 0u, 2, s)) return BP_E_HIP;
-    if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
+    if (fill_u32((uint32_t *)total, 0u, 2, sp)) return BP_E_HIP;
+    if (fill_u32(cnt + n, 0u, 1, sp)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_flat_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, Gm, n, theta_x, theta_y, v_los, sol, status,
+    hipLaunchKernelGGL(k_flat_setup<kQ>, dim3(blocks), dim3(256), 0, sp, *p, Gm, n, theta_x, theta_y, v_los, sol, status,
                        meta, rec, cnt, total);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long np64 = 0;
-    if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
+    if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, sp) != hipSuccess) return BP_E_HIP;
+    if (hipStreamSynchronize(sp) != hipSuccess) return BP_E_HIP;
     if (np64 >= 0x7fffffffULL) return BP_E_OVERFLOW;
     const int64_t np = (int64_t)np64;
     // phase-2 layout (after the phase-1 part)
@@ -364,22 +368,26 @@ static int paste_flat_impl(const bp_params *p, int32_t npix, double pix_rad, int
     uint32_t *k1 = A.take<uint32_t>(np), *v1 = A.take<uint32_t>(np);
     uint32_t *tst = A.take<uint32_t>(ntiles), *ten = A.take<uint32_t>(ntiles);
     void *sort_ws = (char *)ws + A.used;
-    prof_begin(BP_PROF_FLAT_PLAN, s);
-    int e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, s);
+    prof_begin(BP_PROF_FLAT_PLAN, sp);
+    int e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, sp);
     if (e) return e;
-    hipLaunchKernelGGL(k_flat_emit, dim3(blocks), dim3(256), 0, s, Gm, n, theta_x, theta_y, rec, off, k0, v0);
+    hipLaunchKernelGGL(k_flat_emit, dim3(blocks), dim3(256), 0, sp, Gm, n, theta_x, theta_y, rec, off, k0, v0);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     int bits = 1;
     while ((1LL << bits) < ntiles) ++bits;
     bool in1 = false;
-    e = radix_sort_u32(k0, v0, k1, v1, np, bits, sort_ws, s, &in1);
+    e = radix_sort_u32(k0, v0, k1, v1, np, bits, sort_ws, sp, &in1);
     if (e) return e;
     uint32_t *ks = in1 ? k1 : k0, *vs = in1 ? v1 : v0;
-    if (fill_u32(tst, 0u, ntiles, s) || fill_u32(ten, 0u, ntiles, s)) return BP_E_HIP;
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, ks, np, tst, ten,
+    if (fill_u32(tst, 0u, ntiles, sp) || fill_u32(ten, 0u, ntiles, sp)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, sp, ks, np, tst, ten,
                        (uint32_t)ntiles);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
-    prof_end(BP_PROF_FLAT_PLAN, s);
+    prof_end(BP_PROF_FLAT_PLAN, sp);
+    if (sp != s) {
+        if (hipEventRecord(plan_done, sp) != hipSuccess || hipStreamWaitEvent(s, plan_done, 0) != hipSuccess)
+            return BP_E_HIP;
+    }
     prof_begin(kQ ? BP_PROF_FLATQ_DEPOSIT : BP_PROF_FLAT_DEPOSIT, s);
     hipLaunchKernelGGL(k_flat_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, Gm, n, rec, tables, vs,
                        tst, ten, y_map, b_map, y_comp, b_comp, (int)ntiles);
@@ -401,6 +409,55 @@ extern "C" int bp_hp_paste_flat_q(const bp_params *p, int32_t npix, double pix_r
                                   float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, void *stream) {
     return paste_flat_impl<true>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, qtables, meta, y_map,
                                  b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream);
+}
+
+// ---------------------------------------------------------- one-call pipeline --
+namespace {
+constexpr int kMaxSideDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxSideDevices];
+}  // namespace
+
+int bp::side_stream_for_current_device(SideStream **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxSideDevices) return BP_E_HIP;
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    SideStream &S = g_side[dev];
+    if (!S.s) {
+        // default priority: only the ordering changes, never the scheduling class
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return BP_E_HIP;
+        if (hipEventCreateWithFlags(&S.meta_ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&S.plan_done, hipEventDisableTiming) != hipSuccess)
+            return BP_E_HIP;
+        S.s = st;
+    }
+    *out = &S;
+    return BP_OK;
+}
+
+extern "C" int bp_hp_flat_pipeline(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *M,
+                                   const double *c, const double *z, const double *theta_x, const double *theta_y,
+                                   const double *v_los, double *sol, int32_t *status, float *tables, float *meta,
+                                   float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
+                                   size_t ws_bytes, size_t *ws_needed, void *stream) {
+    if (check_params(p) || npix <= 0 || npix > 65536 || !(pix_rad > 0) || n < 0 || !ws_needed) return BP_E_ARG;
+    if (!y_map || !b_map) return BP_E_ARG;
+    if (n > 0 && (!M || !c || !z || !theta_x || !theta_y || !v_los || !sol || !status || !tables || !meta))
+        return BP_E_ARG;
+    if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
+    if (n == 0) { *ws_needed = 0; return BP_OK; }
+    SideStream *S = nullptr;
+    int e = side_stream_for_current_device(&S);
+    if (e) return e;
+    std::lock_guard<std::mutex> lock(S->mu);
+    hipStream_t s = (hipStream_t)stream;
+    if ((e = bp_icm_solve(p, n, M, c, z, sol, status, stream))) return e;
+    // the quadratures stay queued on `stream`; the paste's set-up needs only the solve and meta
+    if ((e = profile_tables_launch(p, n, sol, status, tables, meta, s, S->meta_ready))) return e;
+    if (hipStreamWaitEvent(S->s, S->meta_ready, 0) != hipSuccess) return BP_E_HIP;
+    return paste_flat_impl<false>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, tables, meta, y_map,
+                                  b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream, S->s, S->plan_done);
 }
 
 // ------------------------------------------------------ allocation-free variant --

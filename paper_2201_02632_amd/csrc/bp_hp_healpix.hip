@@ -386,13 +386,17 @@ template <bool kQ>
 static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
                               const double *v_los, const double *sol, const int32_t *status, const float *tables,
                               const float *meta, float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
-                              size_t ws_bytes, size_t *ws_needed, void *stream) {
+                              size_t ws_bytes, size_t *ws_needed, void *stream, hipStream_t plan_stream = nullptr,
+                              hipEvent_t plan_done = nullptr) {
     if (check_params(p) || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
     if (n > 0 && (!theta || !phi || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
     if (!y_map || !b_map) return BP_E_ARG;
     if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     hipStream_t s = (hipStream_t)stream;
+    // set-up and plan run on plan_stream when one is given (its own dependencies set by the caller),
+    // the deposit on stream after plan_done
+    hipStream_t sp = plan_stream ? plan_stream : s;
     HpxGeom G;
     G.N = nside;
     G.nrings = (int32_t)(4 * nside - 1);
@@ -419,24 +423,24 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     void *scan_ws = (char *)ws + A.used;
     A.used += scan_ws_bytes(n + 1) + scan_ws_bytes(nbands + 1);
     // tiles per band and their prefix (the total lands in btile0[nbands])
-    if (fill_u32(btiles + nbands, 0u, 1, s)) return BP_E_HIP;
-    hipLaunchKernelGGL(k_band_tiles, dim3((nbands + 255) / 256), dim3(256), 0, s, G.N, G.nrings, nbands, btiles);
+    if (fill_u32(btiles + nbands, 0u, 1, sp)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_band_tiles, dim3((nbands + 255) / 256), dim3(256), 0, sp, G.N, G.nrings, nbands, btiles);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
-    int e = scan_exclusive_u32(btiles, btile0, nbands + 1, scan_ws, s);
+    int e = scan_exclusive_u32(btiles, btile0, nbands + 1, scan_ws, sp);
     if (e) return e;
-    hipLaunchKernelGGL(k_ring_table, dim3((G.nrings + 255) / 256), dim3(256), 0, s, G.N, G.nrings, rtab);
-    if (fill_u32((uint32_t *)total, 0u, 2, s)) return BP_E_HIP;   // a fill kernel rather than a memset node
-    if (fill_u32(cnt + n, 0u, 1, s)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_ring_table, dim3((G.nrings + 255) / 256), dim3(256), 0, sp, G.N, G.nrings, rtab);
+    if (fill_u32((uint32_t *)total, 0u, 2, sp)) return BP_E_HIP;   // a fill kernel rather than a memset node
+    if (fill_u32(cnt + n, 0u, 1, sp)) return BP_E_HIP;
     unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_hpx_setup<kQ>, dim3(blocks), dim3(256), 0, s, *p, G, n, theta, phi, v_los, sol, status,
+    hipLaunchKernelGGL(k_hpx_setup<kQ>, dim3(blocks), dim3(256), 0, sp, *p, G, n, theta, phi, v_los, sol, status,
                        meta, rtab, btile0, rec, cnt, total);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     unsigned long long np64 = 0;
     uint32_t ntiles32 = 0;
-    if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, s) != hipSuccess) return BP_E_HIP;
-    if (hipMemcpyAsync(&ntiles32, btile0 + nbands, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (hipMemcpyAsync(&np64, total, sizeof(np64), hipMemcpyDeviceToHost, sp) != hipSuccess) return BP_E_HIP;
+    if (hipMemcpyAsync(&ntiles32, btile0 + nbands, sizeof(uint32_t), hipMemcpyDeviceToHost, sp) != hipSuccess)
         return BP_E_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
+    if (hipStreamSynchronize(sp) != hipSuccess) return BP_E_HIP;
     if (np64 >= 0x7fffffffULL) return BP_E_OVERFLOW;
     const int64_t np = (int64_t)np64, ntiles = ntiles32;
     size_t need = A.used;
@@ -454,22 +458,26 @@ static int paste_healpix_impl(const bp_params *p, int64_t nside, int64_t n, cons
     uint32_t *k1 = A.take<uint32_t>(np), *v1 = A.take<uint32_t>(np);
     uint32_t *tst = A.take<uint32_t>(ntiles), *ten = A.take<uint32_t>(ntiles);
     void *sort_ws = (char *)ws + A.used;
-    prof_begin(BP_PROF_HPX_PLAN, s);
-    e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, s);
+    prof_begin(BP_PROF_HPX_PLAN, sp);
+    e = scan_exclusive_u32(cnt, off, n + 1, scan_ws, sp);
     if (e) return e;
-    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, s, G, n, rec, rtab, btile0, off, k0, v0);
+    hipLaunchKernelGGL(k_hpx_emit, dim3(blocks), dim3(256), 0, sp, G, n, rec, rtab, btile0, off, k0, v0);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     int bits = 1;
     while ((1LL << bits) < ntiles) ++bits;
     bool in1 = false;
-    e = radix_sort_u32(k0, v0, k1, v1, np, bits, sort_ws, s, &in1);
+    e = radix_sort_u32(k0, v0, k1, v1, np, bits, sort_ws, sp, &in1);
     if (e) return e;
     uint32_t *ks = in1 ? k1 : k0, *vs = in1 ? v1 : v0;
-    if (fill_u32(tst, 0u, ntiles, s) || fill_u32(ten, 0u, ntiles, s)) return BP_E_HIP;
-    hipLaunchKernelGGL(k_hpx_ranges, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, ks, np, tst, ten,
+    if (fill_u32(tst, 0u, ntiles, sp) || fill_u32(ten, 0u, ntiles, sp)) return BP_E_HIP;
+    hipLaunchKernelGGL(k_hpx_ranges, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, sp, ks, np, tst, ten,
                        (uint32_t)ntiles);
     if (hipGetLastError() != hipSuccess) return BP_E_HIP;
-    prof_end(BP_PROF_HPX_PLAN, s);
+    prof_end(BP_PROF_HPX_PLAN, sp);
+    if (sp != s) {
+        if (hipEventRecord(plan_done, sp) != hipSuccess || hipStreamWaitEvent(s, plan_done, 0) != hipSuccess)
+            return BP_E_HIP;
+    }
     prof_begin(kQ ? BP_PROF_HPXQ_DEPOSIT : BP_PROF_HPX_DEPOSIT, s);
     hipLaunchKernelGGL(k_hpx_deposit<kQ>, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, s, G, n, rec, tables, vs,
                        tst, ten, btile0, nbands, rtab, theta, phi, sol, y_map, b_map, y_comp, b_comp,
@@ -493,4 +501,28 @@ extern "C" int bp_hp_paste_healpix_q(const bp_params *p, int64_t nside, int64_t 
                                      size_t *ws_needed, void *stream) {
     return paste_healpix_impl<true>(p, nside, n, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map, y_comp,
                                     b_comp, ws, ws_bytes, ws_needed, stream);
+}
+
+// ---------------------------------------------------------- one-call pipeline --
+extern "C" int bp_hp_healpix_pipeline(const bp_params *p, int64_t nside, int64_t n, const double *M, const double *c,
+                                      const double *z, const double *theta, const double *phi, const double *v_los,
+                                      double *sol, int32_t *status, float *tables, float *meta, float *y_map,
+                                      float *b_map, float *y_comp, float *b_comp, void *ws, size_t ws_bytes,
+                                      size_t *ws_needed, void *stream) {
+    if (check_params(p) || nside < 1 || nside > 8192 || n < 0 || !ws_needed) return BP_E_ARG;
+    if (!y_map || !b_map) return BP_E_ARG;
+    if (n > 0 && (!M || !c || !z || !theta || !phi || !v_los || !sol || !status || !tables || !meta)) return BP_E_ARG;
+    if (n >= 0x7fffffffLL) return BP_E_OVERFLOW;
+    if (n == 0) { *ws_needed = 0; return BP_OK; }
+    SideStream *S = nullptr;
+    int e = side_stream_for_current_device(&S);
+    if (e) return e;
+    std::lock_guard<std::mutex> lock(S->mu);
+    hipStream_t s = (hipStream_t)stream;
+    if ((e = bp_icm_solve(p, n, M, c, z, sol, status, stream))) return e;
+    // the quadratures stay queued on `stream`; the paste's set-up needs only the solve and meta
+    if ((e = profile_tables_launch(p, n, sol, status, tables, meta, s, S->meta_ready))) return e;
+    if (hipStreamWaitEvent(S->s, S->meta_ready, 0) != hipSuccess) return BP_E_HIP;
+    return paste_healpix_impl<false>(p, nside, n, theta, phi, v_los, sol, status, tables, meta, y_map, b_map, y_comp,
+                                     b_comp, ws, ws_bytes, ws_needed, stream, S->s, S->plan_done);
 }

@@ -997,19 +997,19 @@ extern "C" int bp_icm_solve(const bp_params *p, int64_t n, const double *M, cons
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
-extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
-                                 float *tables, float *meta, void *stream) {
+int bp::profile_tables_launch(const bp_params *p, int64_t n, const double *sol, const int32_t *status, float *tables,
+                              float *meta, hipStream_t s, hipEvent_t meta_ready) {
     int e = check_params(p);
     if (e) return e;
     if (n < 0) return BP_E_ARG;
     if (n == 0) return BP_OK;
     if (!sol || !status || !tables || !meta) return BP_E_ARG;
     if (n > 0x7fffffff) return BP_E_OVERFLOW;
-    hipStream_t s = (hipStream_t)stream;
     const GaussRules G = gauss_rules();
     prof_begin(BP_PROF_TABLES, s);
     hipLaunchKernelGGL(k_node_geom, dim3(1), dim3(BP_TAB_NA), 0, s, (double)(float)G.eta_top);
     hipLaunchKernelGGL(k_table_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, *p, G, n, sol, status, meta);
+    if (meta_ready && hipEventRecord(meta_ready, s) != hipSuccess) return BP_E_HIP;
     // zones S and B first: zone A folds the shell part of each of its sight lines in from zone S
     hipLaunchKernelGGL(k_tables_sb, dim3((unsigned)((n + 1) / 2)), dim3(128), 0, s, G, n, sol, status, meta,
                        tables, (float)p->n_nt);
@@ -1017,6 +1017,11 @@ extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *so
                        (float)p->n_nt);
     prof_end(BP_PROF_TABLES, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+extern "C" int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const int32_t *status,
+                                 float *tables, float *meta, void *stream) {
+    return profile_tables_launch(p, n, sol, status, tables, meta, (hipStream_t)stream, nullptr);
 }
 
 extern "C" int bp_halo_structure(const bp_params *p, int64_t n, const double *M, const double *c, const double *z,

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -16,6 +18,21 @@ int64_t bp_mlp_nparams(void);
 namespace bp {
 
 const GaussRules &gauss_rules();
+
+// bp_profile_tables on stream s; when meta_ready is given it is recorded on s after meta is written and
+// before the quadratures are enqueued.
+int profile_tables_launch(const bp_params *p, int64_t n, const double *sol, const int32_t *status, float *tables,
+                          float *meta, hipStream_t s, hipEvent_t meta_ready);
+
+// The second stream of the pipeline calls (solve, tables and paste in one call) and its two events, one set
+// per device, created on first use with default priority.  Holders of `mu` own them for a whole call, so
+// that the records and waits of two host threads never interleave.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t meta_ready = nullptr, plan_done = nullptr;
+    std::mutex mu;
+};
+int side_stream_for_current_device(SideStream **out);
 
 // Exact surrogate q-tables (bp_surrogate_qtables_exact) for halos whose status has no bit outside ok_mask.
 int qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status, int32_t ok_mask,

@@ -416,3 +416,88 @@ def test_batches_with_compensation_equal_one_call(bp):
     torch.cuda.synchronize()
     assert torch.equal(yb, y1) and torch.equal(bb, b1)
     print(f"batches without compensation differ from one call at {(yn != y1).sum().item()} of {npix * npix} pixels")
+
+
+def _three_calls(bp, params, t, npix, pix, comp=None):
+    import torch
+    sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
+    tab, meta = bp.profile_tables(params, sol, st)
+    y = torch.zeros((npix, npix), device="cuda")
+    b = torch.zeros_like(y)
+    bp.hp_paste_flat(params, npix, pix, t["theta_x"], t["theta_y"], t["v_los"], sol, st, tab, meta, y, b, comp=comp)
+    return sol, st, tab, meta, y, b
+
+
+@pytest.mark.parametrize("n,field,npix,seed", [(2000, 1.0, 203, 3), (7000, 2.0, 480, 4)])
+def test_pipeline_equals_three_calls(bp, n, field, npix, seed):
+    """The one-call pipeline (solve, tables, paste with the paste's plan on a second stream) returns the same
+    solution, tables and maps, bit for bit, as the three calls in sequence: twice in a row on one workspace
+    (the second call smaller), on a non-default stream, with and without the compensation maps."""
+    import torch
+    from paper_2201_02632_amd.synth import flat_catalogue
+    params = bp.default_params()
+    pix = field * math.pi / 180 / npix
+    ws = bp.Workspace("cuda")
+    side = torch.cuda.Stream()
+    for m in (n, n // 3 + 1):
+        cat = flat_catalogue(m, field, seed=seed + m)
+        t = {k: T(v) for k, v in cat.items()}
+        ref = _three_calls(bp, params, t, npix, pix)
+        with torch.cuda.stream(side):
+            side.wait_stream(torch.cuda.default_stream())
+            y = torch.zeros((npix, npix), device="cuda")
+            b = torch.zeros_like(y)
+            got = bp.hp_flat_pipeline(params, npix, pix, t["M"], t["c"], t["z"], t["theta_x"], t["theta_y"],
+                                      t["v_los"], y, b, ws=ws)
+        torch.cuda.synchronize()
+        for name, r, g in zip(("sol", "status", "tables", "meta", "y", "b"), ref, (*got, y, b)):
+            assert torch.equal(r, g), (m, name)
+        assert (ref[4] != 0).sum().item() > 0
+        yc, bc = torch.zeros_like(y), torch.zeros_like(y)
+        refc = _three_calls(bp, params, t, npix, pix, comp=(yc, bc))
+        y2, b2 = torch.zeros_like(y), torch.zeros_like(y)
+        yc2, bc2 = torch.zeros_like(y), torch.zeros_like(y)
+        bp.hp_flat_pipeline(params, npix, pix, t["M"], t["c"], t["z"], t["theta_x"], t["theta_y"], t["v_los"], y2, b2,
+                            ws=ws, comp=(yc2, bc2))
+        torch.cuda.synchronize()
+        assert torch.equal(refc[4], y2) and torch.equal(refc[5], b2)
+        assert torch.equal(yc, yc2) and torch.equal(bc, bc2)
+
+
+def test_pipeline_workspace_protocol(bp):
+    """Too small a workspace: BP_E_WORKSPACE with the size, the solve and tables complete, the maps untouched;
+    bp_hp_paste_flat on the returned outputs then gives the three-call maps."""
+    import ctypes as C
+    import torch
+    from paper_2201_02632_amd.synth import hp_flat_small
+    params = bp.default_params()
+    cat, npix, pix = hp_flat_small(1)
+    t = {k: T(v) for k, v in cat.items()}
+    ref = _three_calls(bp, params, t, npix, pix)
+    n = len(cat["M"])
+    sol = torch.empty_like(ref[0])
+    st = torch.empty_like(ref[1])
+    tab = torch.empty_like(ref[2])
+    meta = torch.empty_like(ref[3])
+    y = torch.zeros((npix, npix), device="cuda")
+    b = torch.zeros_like(y)
+    need = C.c_size_t(0)
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    code = bp._lib.bp_hp_flat_pipeline(C.byref(params), npix, pix, n, bp._ptr(t["M"]), bp._ptr(t["c"]),
+                                       bp._ptr(t["z"]), bp._ptr(t["theta_x"]), bp._ptr(t["theta_y"]),
+                                       bp._ptr(t["v_los"]), bp._ptr(sol), bp._ptr(st), bp._ptr(tab), bp._ptr(meta),
+                                       bp._ptr(y), bp._ptr(b), None, None, bp._ptr(small), 256, C.byref(need),
+                                       bp._stream())
+    assert code == bp.BP_E_WORKSPACE and need.value > 256
+    torch.cuda.synchronize()
+    assert torch.all(y == 0) and torch.all(b == 0)
+    assert torch.equal(sol, ref[0]) and torch.equal(st, ref[1]) and torch.equal(tab, ref[2])
+    assert torch.equal(meta, ref[3])
+    bp.hp_paste_flat(params, npix, pix, t["theta_x"], t["theta_y"], t["v_los"], sol, st, tab, meta, y, b)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref[4]) and torch.equal(b, ref[5])
+    # n = 0: nothing to do, nothing touched
+    e = bp._lib.bp_hp_flat_pipeline(C.byref(params), npix, pix, 0, None, None, None, None, None, None, None, None,
+                                    None, None, bp._ptr(y), bp._ptr(b), None, None, None, 0, C.byref(need),
+                                    bp._stream())
+    assert e == bp.BP_OK and need.value == 0

@@ -115,3 +115,41 @@ def test_hp_healpix_batches_with_compensation_equal_one_call(bp):
                             comp=(yc, bc))
     torch.cuda.synchronize()
     assert torch.equal(yb, y1) and torch.equal(bb, b1)
+
+
+def test_hp_healpix_pipeline_equals_three_calls(bp):
+    """bp_hp_healpix_pipeline returns the solution, tables and maps of the three calls bit for bit, also for
+    batches that carry the compensation maps and on a second, smaller call on the same workspace."""
+    import torch
+    params = bp.default_params()
+    T = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    nside = 256
+    npx = 12 * nside * nside
+    ws = bp.Workspace("cuda")
+    for n, seed in ((400, 8), (57, 9)):
+        t = {k: T(v) for k, v in sky_case(seed, n, nside).items()}
+        sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
+        tab, meta = bp.profile_tables(params, sol, st)
+        y1, b1 = torch.zeros(npx, device="cuda"), torch.zeros(npx, device="cuda")
+        bp.hp_paste_healpix(params, nside, t["theta"], t["phi"], t["v_los"], sol, st, tab, meta, y1, b1)
+        y2, b2 = torch.zeros_like(y1), torch.zeros_like(y1)
+        got = bp.hp_healpix_pipeline(params, nside, t["M"], t["c"], t["z"], t["theta"], t["phi"], t["v_los"], y2, b2,
+                                     ws=ws)
+        torch.cuda.synchronize()
+        for name, r, g in zip(("sol", "status", "tables", "meta", "y", "b"), (sol, st, tab, meta, y1, b1),
+                              (*got, y2, b2)):
+            assert torch.equal(r, g), (n, name)
+        assert (y1 != 0).sum().item() > 0
+        # batches with compensation: pipeline calls against paste calls
+        yb, bb, yc, bc = (torch.zeros_like(y1) for _ in range(4))
+        yp, bq, ycp, bcp = (torch.zeros_like(y1) for _ in range(4))
+        for a, e in ((0, n // 3), (n // 3, n)):
+            sub = {k: v[a:e].contiguous() for k, v in t.items()}
+            s2, st2 = bp.icm_solve(params, sub["M"], sub["c"], sub["z"])
+            tb2, mt2 = bp.profile_tables(params, s2, st2)
+            bp.hp_paste_healpix(params, nside, sub["theta"], sub["phi"], sub["v_los"], s2, st2, tb2, mt2, yb, bb,
+                                comp=(yc, bc))
+            bp.hp_healpix_pipeline(params, nside, sub["M"], sub["c"], sub["z"], sub["theta"], sub["phi"],
+                                   sub["v_los"], yp, bq, ws=ws, comp=(ycp, bcp))
+        torch.cuda.synchronize()
+        assert torch.equal(yb, yp) and torch.equal(bb, bq) and torch.equal(yc, ycp) and torch.equal(bc, bcp)
