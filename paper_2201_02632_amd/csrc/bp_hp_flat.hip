@@ -436,6 +436,12 @@ int bp::side_stream_for_current_device(SideStream **out) {
     return BP_OK;
 }
 
+int bp::join_side(SideStream *S, hipStream_t s, int e) {
+    if (hipEventRecord(S->plan_done, S->s) != hipSuccess || hipStreamWaitEvent(s, S->plan_done, 0) != hipSuccess)
+        return e ? e : BP_E_HIP;
+    return e;
+}
+
 extern "C" int bp_hp_flat_pipeline(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *M,
                                    const double *c, const double *z, const double *theta_x, const double *theta_y,
                                    const double *v_los, double *sol, int32_t *status, float *tables, float *meta,
@@ -456,8 +462,18 @@ extern "C" int bp_hp_flat_pipeline(const bp_params *p, int32_t npix, double pix_
     // the quadratures stay queued on `stream`; the paste's set-up needs only the solve and meta
     if ((e = profile_tables_launch(p, n, sol, status, tables, meta, s, S->meta_ready))) return e;
     if (hipStreamWaitEvent(S->s, S->meta_ready, 0) != hipSuccess) return BP_E_HIP;
-    return paste_flat_impl<false>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, tables, meta, y_map,
-                                  b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream, S->s, S->plan_done);
+    e = paste_flat_impl<false>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, tables, meta, y_map, b_map,
+                               y_comp, b_comp, ws, ws_bytes, ws_needed, stream, S->s, S->plan_done);
+    return e ? join_side(S, s, e) : BP_OK;
+}
+
+int bp::paste_flat_q_planned(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                             const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                             const float *qtables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                             float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, hipStream_t stream,
+                             hipStream_t plan_stream, hipEvent_t plan_done) {
+    return paste_flat_impl<true>(p, npix, pix_rad, n, theta_x, theta_y, v_los, sol, status, qtables, meta, y_map,
+                                 b_map, y_comp, b_comp, ws, ws_bytes, ws_needed, stream, plan_stream, plan_done);
 }
 
 // ------------------------------------------------------ allocation-free variant --

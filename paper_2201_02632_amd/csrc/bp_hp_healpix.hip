@@ -503,6 +503,15 @@ extern "C" int bp_hp_paste_healpix_q(const bp_params *p, int64_t nside, int64_t 
                                     b_comp, ws, ws_bytes, ws_needed, stream);
 }
 
+int bp::paste_healpix_q_planned(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
+                                const double *v_los, const double *sol, const int32_t *status, const float *qtables,
+                                const float *meta, float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
+                                size_t ws_bytes, size_t *ws_needed, hipStream_t stream, hipStream_t plan_stream,
+                                hipEvent_t plan_done) {
+    return paste_healpix_impl<true>(p, nside, n, theta, phi, v_los, sol, status, qtables, meta, y_map, b_map, y_comp,
+                                    b_comp, ws, ws_bytes, ws_needed, stream, plan_stream, plan_done);
+}
+
 // ---------------------------------------------------------- one-call pipeline --
 extern "C" int bp_hp_healpix_pipeline(const bp_params *p, int64_t nside, int64_t n, const double *M, const double *c,
                                       const double *z, const double *theta, const double *phi, const double *v_los,
@@ -523,6 +532,7 @@ extern "C" int bp_hp_healpix_pipeline(const bp_params *p, int64_t nside, int64_t
     // the quadratures stay queued on `stream`; the paste's set-up needs only the solve and meta
     if ((e = profile_tables_launch(p, n, sol, status, tables, meta, s, S->meta_ready))) return e;
     if (hipStreamWaitEvent(S->s, S->meta_ready, 0) != hipSuccess) return BP_E_HIP;
-    return paste_healpix_impl<false>(p, nside, n, theta, phi, v_los, sol, status, tables, meta, y_map, b_map, y_comp,
-                                     b_comp, ws, ws_bytes, ws_needed, stream, S->s, S->plan_done);
+    e = paste_healpix_impl<false>(p, nside, n, theta, phi, v_los, sol, status, tables, meta, y_map, b_map, y_comp,
+                                  b_comp, ws, ws_bytes, ws_needed, stream, S->s, S->plan_done);
+    return e ? join_side(S, s, e) : BP_OK;
 }

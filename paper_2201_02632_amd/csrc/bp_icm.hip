@@ -820,11 +820,14 @@ constexpr int kQH = 64;                     // halos per block
 __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G, QNodes QN, int64_t n,
                                                        const double *__restrict__ sol,
                                                        const int32_t *__restrict__ status, int32_t ok_mask,
+                                                       const uint32_t *__restrict__ skip, bool write_meta,
                                                        float *__restrict__ qt, float *__restrict__ meta) {
     __shared__ float tile[kQH][2 * BP_MLP_NQ + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kQH, i = i0 + lane;
-    const bool live = i < n && (status[i] & ~ok_mask) == 0;
+    // a halo marked in skip is left alone, its status not even read (another stream may be writing it)
+    auto take = [&](int64_t h) { return !(skip && skip[h]) && (status[h] & ~ok_mask) == 0; };
+    const bool live = i < n && take(i);
     // Every lane runs the node loop (a lane without a live halo computes on stand-in values and stores
     // nothing), so that the wavefront can agree on one Gauss-Legendre order per node: it runs the
     // largest order among its lanes anyway, and one order for all makes the rule's nodes and weights
@@ -833,7 +836,7 @@ __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G
         auto S = [&](int f) { return live ? sol[(int64_t)f * n + i] : 1.0; };
         const double rv = S(BP_SOL_RVIR), rf = live ? S(BP_SOL_RF) : 2.0, Rt = S(BP_SOL_RT), c = S(BP_SOL_C);
         const double mc = nfw_m(c);
-        if (live && wave == 0) {
+        if (live && wave == 0 && write_meta) {
             const double X = P.X_H;
             meta[(int64_t)BP_META_PE0 * n + i] = (float)((2.0 * X + 2.0) / (5.0 * X + 3.0) * S(BP_SOL_P0));
             meta[(int64_t)BP_META_NE0 * n + i] = (float)(S(BP_SOL_RHO0) / (2.0 / (1.0 + X) * kMp));
@@ -911,7 +914,7 @@ __global__ void __launch_bounds__(256) k_qtables_exact(bp_params P, GaussRules G
     const int nh = (int)min((int64_t)kQH, n - i0);
     for (int e = threadIdx.x; e < nh * 2 * BP_MLP_NQ; e += 256) {
         const int h = e / (2 * BP_MLP_NQ), k = e - h * 2 * BP_MLP_NQ;
-        if ((status[i0 + h] & ~ok_mask) == 0) qt[(i0 + h) * 2 * BP_MLP_NQ + k] = tile[h][k];
+        if (take(i0 + h)) qt[(i0 + h) * 2 * BP_MLP_NQ + k] = tile[h][k];
     }
 }
 
@@ -1057,7 +1060,7 @@ extern "C" int bp_surrogate_solve(const bp_params *p, int64_t n, const double *M
 }
 
 int bp::qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status, int32_t ok_mask,
-                      float *qtables, float *meta, hipStream_t s) {
+                      float *qtables, float *meta, hipStream_t s, const uint32_t *skip, bool write_meta) {
     int e = check_params(p);
     if (e) return e;
     if (n < 0) return BP_E_ARG;
@@ -1069,7 +1072,7 @@ int bp::qtables_exact(const bp_params *p, int64_t n, const double *sol, const in
     QN.q[BP_MLP_NQ - 1] = 1.0 - 1e-6;
     prof_begin(BP_PROF_SURR_APPLY, s);
     hipLaunchKernelGGL(k_qtables_exact, dim3((unsigned)((n + kQH - 1) / kQH)), dim3(256), 0, s, *p, gauss_rules(), QN, n,
-                       sol, status, ok_mask, qtables, meta);
+                       sol, status, ok_mask, skip, write_meta, qtables, meta);
     prof_end(BP_PROF_SURR_APPLY, s);
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }

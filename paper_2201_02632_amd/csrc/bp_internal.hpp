@@ -33,10 +33,35 @@ struct SideStream {
     std::mutex mu;
 };
 int side_stream_for_current_device(SideStream **out);
+// For an error return of a call that used the second stream: `s` waits for whatever the call put there,
+// so the caller may free or reuse the workspace in stream order.  Returns e (or BP_E_HIP if e is 0 and
+// the join fails).
+int join_side(SideStream *S, hipStream_t s, int e);
+
+// bp_hp_paste_flat_q and bp_hp_paste_healpix_q with the set-up and plan on plan_stream (its own
+// dependencies set by the caller) and the deposit on stream after plan_done and stream's own work.
+int paste_flat_q_planned(const bp_params *p, int32_t npix, double pix_rad, int64_t n, const double *theta_x,
+                         const double *theta_y, const double *v_los, const double *sol, const int32_t *status,
+                         const float *qtables, const float *meta, float *y_map, float *b_map, float *y_comp,
+                         float *b_comp, void *ws, size_t ws_bytes, size_t *ws_needed, hipStream_t stream,
+                         hipStream_t plan_stream, hipEvent_t plan_done);
+int paste_healpix_q_planned(const bp_params *p, int64_t nside, int64_t n, const double *theta, const double *phi,
+                            const double *v_los, const double *sol, const int32_t *status, const float *qtables,
+                            const float *meta, float *y_map, float *b_map, float *y_comp, float *b_comp, void *ws,
+                            size_t ws_bytes, size_t *ws_needed, hipStream_t stream, hipStream_t plan_stream,
+                            hipEvent_t plan_done);
 
 // Exact surrogate q-tables (bp_surrogate_qtables_exact) for halos whose status has no bit outside ok_mask.
+// Halos marked in skip (nullable) are left alone; without write_meta only the tables are written.
 int qtables_exact(const bp_params *p, int64_t n, const double *sol, const int32_t *status, int32_t ok_mask,
-                  float *qtables, float *meta, hipStream_t s);
+                  float *qtables, float *meta, hipStream_t s, const uint32_t *skip = nullptr,
+                  bool write_meta = true);
+// The two halves of bp_surrogate_apply: the network's q-tables for the halos with a zero status and
+// not marked in skip (nullable), and meta (PE0, NE0) for the halos with a zero status.
+int surrogate_apply_q(int64_t n, const float *y, const float *mean, const float *std, const int32_t *status,
+                      const uint32_t *skip, float *qtables, hipStream_t s);
+int surrogate_apply_meta(const bp_params *p, int64_t n, const double *sol, const int32_t *status, float *meta,
+                         hipStream_t s);
 
 // The surrogate network's gradient as partial sums that their consumer reduces in a fixed order:
 // split-K slices of the weight-gradient products (W4, W3, W2) and row-chunk column sums (b4, b3, b2,

@@ -263,13 +263,15 @@ __global__ void __launch_bounds__(512) k_mse_train(int64_t n, int64_t ndata, uin
 // stores (rows of BP_MLP_OUT and 2 BP_MLP_NQ floats keep every group of four aligned)
 static_assert(BP_MLP_OUT % 4 == 0 && (2 * BP_MLP_NQ) % 4 == 0, "16-byte groups");
 __global__ void k_apply_q(int64_t n, const float *__restrict__ y, const float *__restrict__ mean,
-                          const float *__restrict__ sd, const int32_t *__restrict__ status, float *__restrict__ qt) {
+                          const float *__restrict__ sd, const int32_t *__restrict__ status,
+                          const uint32_t *__restrict__ skip, float *__restrict__ qt) {
     constexpr int G4 = 2 * BP_MLP_NQ / 4;
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * G4) return;
     int64_t i = e / G4;
     int k = 4 * (int)(e % G4);
-    if (status[i]) return;
+    // a halo marked in skip is left alone, its status not even read (another stream may be writing it)
+    if ((skip && skip[i]) || status[i]) return;
     const float4 r = *reinterpret_cast<const float4 *>(y + i * BP_MLP_OUT + k);
     const float4 s = *reinterpret_cast<const float4 *>(sd + k);
     const float4 m = *reinterpret_cast<const float4 *>(mean + k);
@@ -340,6 +342,25 @@ extern "C" int bp_surrogate_mse(int64_t n, const float *y, const float *targets,
     return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
 }
 
+int bp::surrogate_apply_q(int64_t n, const float *y, const float *mean, const float *std, const int32_t *status,
+                          const uint32_t *skip, float *qtables, hipStream_t s) {
+    if (n == 0) return BP_OK;
+    prof_begin(BP_PROF_SURR_APPLY, s);
+    hipLaunchKernelGGL(k_apply_q, dim3(nblk(n * 2 * BP_MLP_NQ / 4)), dim3(256), 0, s, n, y, mean, std, status, skip,
+                       qtables);
+    prof_end(BP_PROF_SURR_APPLY, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
+int bp::surrogate_apply_meta(const bp_params *p, int64_t n, const double *sol, const int32_t *status, float *meta,
+                             hipStream_t s) {
+    if (n == 0) return BP_OK;
+    prof_begin(BP_PROF_SURR_APPLY, s);
+    hipLaunchKernelGGL(k_apply_halo, dim3(nblk(n)), dim3(256), 0, s, *p, n, sol, status, meta);
+    prof_end(BP_PROF_SURR_APPLY, s);
+    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+}
+
 extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y, const float *mean, const float *std,
                                   const double *sol, const int32_t *status, float *qtables, float *meta, void *stream) {
     if (check_params(p) || n < 0 || (n > 0 && (!y || !mean || !std || !sol || !status || !qtables || !meta)))
@@ -347,11 +368,8 @@ extern "C" int bp_surrogate_apply(const bp_params *p, int64_t n, const float *y,
     if (n == 0) return BP_OK;
     if (((uintptr_t)y | (uintptr_t)mean | (uintptr_t)std | (uintptr_t)qtables) & 15) return BP_E_ARG;
     hipStream_t s = (hipStream_t)stream;
-    prof_begin(BP_PROF_SURR_APPLY, s);
-    hipLaunchKernelGGL(k_apply_q, dim3(nblk(n * 2 * BP_MLP_NQ / 4)), dim3(256), 0, s, n, y, mean, std, status, qtables);
-    hipLaunchKernelGGL(k_apply_halo, dim3(nblk(n)), dim3(256), 0, s, *p, n, sol, status, meta);
-    prof_end(BP_PROF_SURR_APPLY, s);
-    return hipGetLastError() == hipSuccess ? BP_OK : BP_E_HIP;
+    int e = surrogate_apply_q(n, y, mean, std, status, nullptr, qtables, s);
+    return e ? e : surrogate_apply_meta(p, n, sol, status, meta, s);
 }
 
 extern "C" size_t bp_surrogate_train_ws_bytes(int64_t batch) {

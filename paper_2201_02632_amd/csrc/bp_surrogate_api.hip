@@ -119,6 +119,12 @@ static SurViews views(void *state) {
 
 // Everything up to the deposit: network, seeded solve, tables, the routed halos' exact solve and
 // tables.  Returns BP_OK with the arrays filled, or BP_E_WORKSPACE with *need set.
+//
+// The solution, status and meta of every halo are final before the q-tables of the halos solved by
+// the seeded solve are enqueued (the routed halos' own q-tables come with their exact solve), so the
+// paste's plan may run on a second stream hs beside those q-tables: `routed` is recorded on s at that
+// point and hs waits for it.  The q-table kernels skip the routed halos by their flag (their status is
+// zero again after the scatter); the caller orders the deposit after both streams.
 struct Routed {
     double *sol;
     int32_t *st;
@@ -128,7 +134,7 @@ struct Routed {
 };
 static int route_halos(const bp_params *p, const void *state, int32_t tables, int64_t n, const double *M,
                        const double *c, const double *z, void *ws, size_t ws_bytes, size_t *need, hipStream_t s,
-                       Routed *R) {
+                       hipStream_t hs, hipEvent_t routed, Routed *R) {
     SurViews V = views((void *)state);
     Arena A(ws, ws_bytes);
     float *x = A.take<float>(n * BP_MLP_IN), *y = A.take<float>(n * BP_MLP_OUT);
@@ -142,9 +148,7 @@ static int route_halos(const bp_params *p, const void *state, int32_t tables, in
     if ((e = bp_surrogate_features(n, M, c, z, x, s))) return e;
     if ((e = bp_mlp_infer(V.w, V.wb, n, x, y, s))) return e;
     if ((e = bp_surrogate_solve(p, n, M, c, z, y, V.mean, V.sd, sol, st, s))) return e;
-    if (tables == BP_SUR_TABLES_EXACT) e = bp_surrogate_qtables_exact(p, n, sol, st, qt, meta, s);
-    else e = bp_surrogate_apply(p, n, y, V.mean, V.sd, sol, st, qt, meta, s);
-    if (e) return e;
+    if ((e = surrogate_apply_meta(p, n, sol, st, meta, s))) return e;
     const unsigned nb = (unsigned)((n + 256) / 256);
     hipLaunchKernelGGL(k_route_flags, dim3(nb), dim3(256), 0, s, n, st, flag);
     if ((e = scan_exclusive_u32(flag, off, n + 1, scan_ws, s))) return e;
@@ -153,23 +157,36 @@ static int route_halos(const bp_params *p, const void *state, int32_t tables, in
     if (hipStreamSynchronize(s) != hipSuccess) return BP_E_HIP;
     const int64_t m = m32;
     R->sol = sol; R->st = st; R->qt = qt; R->meta = meta; R->nfall = m;
+    int64_t *idx = nullptr;
+    double *Ms = nullptr, *cs = nullptr, *zs = nullptr, *sol_s = nullptr;
+    int32_t *st_s = nullptr;
+    float *qt_s = nullptr, *meta_s = nullptr;
     if (m > 0) {
-        int64_t *idx = A.take<int64_t>(m);
-        double *Ms = A.take<double>(m), *cs = A.take<double>(m), *zs = A.take<double>(m);
-        double *sol_s = A.take<double>(m * BP_SOL_NFIELDS);
-        int32_t *st_s = A.take<int32_t>(m);
-        float *qt_s = A.take<float>(m * 2 * BP_MLP_NQ), *meta_s = A.take<float>(m * BP_META_NFIELDS);
+        idx = A.take<int64_t>(m);
+        Ms = A.take<double>(m); cs = A.take<double>(m); zs = A.take<double>(m);
+        sol_s = A.take<double>(m * BP_SOL_NFIELDS);
+        st_s = A.take<int32_t>(m);
+        qt_s = A.take<float>(m * 2 * BP_MLP_NQ); meta_s = A.take<float>(m * BP_META_NFIELDS);
         if (!A.fits()) { *need = A.used + 4096; return BP_E_WORKSPACE; }
+    }
+    R->used = A.used;
+    if (m > 0) {
         hipLaunchKernelGGL(k_route_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, flag, off, M, c, z,
                            idx, Ms, cs, zs);
         if ((e = bp_icm_solve(p, m, Ms, cs, zs, sol_s, st_s, s))) return e;
         // a halo with several roots is pasted with the first; the q-table kernel skips non-zero status
         if ((e = qtables_exact(p, m, sol_s, st_s, BP_S_MULTI_ROOT, qt_s, meta_s, s))) return e;
-        hipLaunchKernelGGL(k_route_scatter, dim3((unsigned)((m * 2 * BP_MLP_NQ + 255) / 256)), dim3(256), 0, s, n, m,
-                           idx, sol_s, st_s, qt_s, meta_s, sol, st, qt, meta);
+        hipLaunchKernelGGL(k_route_scatter, dim3((unsigned)((m * 2 * BP_MLP_NQ + 255) / 256)), dim3(256), 0, s, n,
+                           m, idx, sol_s, st_s, qt_s, meta_s, sol, st, qt, meta);
         if (hipGetLastError() != hipSuccess) return BP_E_HIP;
     }
-    R->used = A.used;
+    // solution, status and meta are final: the paste's plan may start on hs while the q-tables of the
+    // other halos run on s
+    if (hs != s && (hipEventRecord(routed, s) != hipSuccess || hipStreamWaitEvent(hs, routed, 0) != hipSuccess))
+        return BP_E_HIP;
+    if (tables == BP_SUR_TABLES_EXACT) e = qtables_exact(p, n, sol, st, 0, qt, meta, s, flag, false);
+    else e = surrogate_apply_q(n, y, V.mean, V.sd, st, flag, qt, s);
+    if (e) return e;
     return BP_OK;
 }
 
@@ -293,16 +310,20 @@ extern "C" int bp_surrogate_paste_flat(const bp_params *p, const void *state, in
     if (n_fallback) *n_fallback = 0;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     hipStream_t s = (hipStream_t)stream;
+    SideStream *S = nullptr;
+    int e = side_stream_for_current_device(&S);
+    if (e) return e;
+    std::lock_guard<std::mutex> lock(S->mu);
     Routed R;
     size_t need = 0;
-    int e = route_halos(p, state, tables, n, M, c, z, ws, ws_bytes, &need, s, &R);
-    if (e == BP_E_WORKSPACE) { *ws_needed = need; return e; }
-    if (e) return e;
+    e = route_halos(p, state, tables, n, M, c, z, ws, ws_bytes, &need, s, S->s, S->meta_ready, &R);
+    if (e == BP_E_WORKSPACE) *ws_needed = need;
+    if (e) return join_side(S, s, e);
     size_t dneed = 0;
-    e = bp_hp_paste_flat_q(p, npix, pix_rad, n, theta_x, theta_y, v_los, R.sol, R.st, R.qt, R.meta, y_map, b_map,
-                           y_comp, b_comp, (char *)ws + R.used, ws_bytes - R.used, &dneed, stream);
+    e = paste_flat_q_planned(p, npix, pix_rad, n, theta_x, theta_y, v_los, R.sol, R.st, R.qt, R.meta, y_map, b_map,
+                             y_comp, b_comp, (char *)ws + R.used, ws_bytes - R.used, &dneed, s, S->s, S->plan_done);
     *ws_needed = R.used + dneed;
-    if (e) return e;
+    if (e) return join_side(S, s, e);
     if (n_fallback) *n_fallback = R.nfall;
     return BP_OK;
 }
@@ -320,16 +341,20 @@ extern "C" int bp_surrogate_paste_healpix(const bp_params *p, const void *state,
     if (n_fallback) *n_fallback = 0;
     if (n == 0) { *ws_needed = 0; return BP_OK; }
     hipStream_t s = (hipStream_t)stream;
+    SideStream *S = nullptr;
+    int e = side_stream_for_current_device(&S);
+    if (e) return e;
+    std::lock_guard<std::mutex> lock(S->mu);
     Routed R;
     size_t need = 0;
-    int e = route_halos(p, state, tables, n, M, c, z, ws, ws_bytes, &need, s, &R);
-    if (e == BP_E_WORKSPACE) { *ws_needed = need; return e; }
-    if (e) return e;
+    e = route_halos(p, state, tables, n, M, c, z, ws, ws_bytes, &need, s, S->s, S->meta_ready, &R);
+    if (e == BP_E_WORKSPACE) *ws_needed = need;
+    if (e) return join_side(S, s, e);
     size_t dneed = 0;
-    e = bp_hp_paste_healpix_q(p, nside, n, theta, phi, v_los, R.sol, R.st, R.qt, R.meta, y_map, b_map, y_comp,
-                              b_comp, (char *)ws + R.used, ws_bytes - R.used, &dneed, stream);
+    e = paste_healpix_q_planned(p, nside, n, theta, phi, v_los, R.sol, R.st, R.qt, R.meta, y_map, b_map, y_comp,
+                                b_comp, (char *)ws + R.used, ws_bytes - R.used, &dneed, s, S->s, S->plan_done);
     *ws_needed = R.used + dneed;
-    if (e) return e;
+    if (e) return join_side(S, s, e);
     if (n_fallback) *n_fallback = R.nfall;
     return BP_OK;
 }
