@@ -511,7 +511,10 @@ int bp_surrogate_load(void *state, const void *blob, size_t blob_bytes, int64_t 
  * b_comp nullable as there).  Halos the exact solve cannot solve either (invalid input, stars above the
  * baryon mass) are skipped.  *n_fallback (nullable) receives the number of halos routed to the scan.
  * Workspace protocol as for the pastes (about 1.4 KB per halo plus the deposit's); one synchronisation
- * for the routed count, one in the deposit. */
+ * for the routed count, one in the deposit.  The deposit's set-up and plan run on the library's second
+ * stream (as in bp_hp_flat_pipeline) beside the q-tables of the halos the seeded solve solved; on
+ * return, error returns included, all work is ordered on `stream`, and calls on one device from
+ * several host threads are serialised inside the library. */
 #define BP_SUR_TABLES_EXACT   0
 #define BP_SUR_TABLES_NETWORK 1
 int bp_surrogate_paste_flat(const bp_params *p, const void *state, int32_t tables, int32_t npix, double pix_rad,
