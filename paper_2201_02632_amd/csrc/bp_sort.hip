@@ -109,14 +109,27 @@ __global__ void __launch_bounds__(256) k_radix_hist(const K *__restrict__ keys, 
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// One chunk per workgroup: the chunk is first ranked into LDS in digit order (stable: rounds in input
+// order, waves in order inside a round, ballot ranks inside a wave), then written out by consecutive
+// lanes, so each digit's run of the chunk (16 items on average) leaves as contiguous stores instead of
+// 256 scattered 4-byte stores per round, each in a different cache line.
 template <class K>
 __global__ void __launch_bounds__(256) k_radix_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                        K *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                       const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ offs, int64_t n, int shift, int nb) {
-    __shared__ uint32_t base[256];
+    __shared__ K skey[kChunk];
+    __shared__ uint32_t sval[kChunk];
+    __shared__ uint32_t gbase[256];   // first output slot of each digit for this chunk
+    __shared__ uint32_t lbase[256];   // first LDS slot of each digit (the chunk's own digit prefix)
+    __shared__ uint32_t run[256];     // items of each digit placed so far
     __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t lds[4];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    base[t] = offs[(int64_t)t * nb + blockIdx.x];
+    gbase[t] = offs[(int64_t)t * nb + blockIdx.x];
+    uint32_t tot;
+    lbase[t] = block_exclusive_scan(hist[(int64_t)t * nb + blockIdx.x], &tot, lds);
+    run[t] = 0;
     const int64_t start = (int64_t)blockIdx.x * kChunk;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int round = 0; round < kScanItems; ++round) {
@@ -138,12 +151,21 @@ __global__ void __launch_bounds__(256) k_radix_scatter(const K *__restrict__ kin
         if (valid) {
             uint32_t pre = 0;
             for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-            uint32_t pos = base[d] + pre + rank;
-            kout[pos] = key;
-            vout[pos] = val;
+            const uint32_t pos = lbase[d] + run[d] + pre + rank;
+            skey[pos] = key;
+            sval[pos] = val;
         }
         __syncthreads();
-        base[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    }
+    __syncthreads();
+    // tot = the chunk's item count (its digit counts summed)
+    for (uint32_t j = t; j < tot; j += 256) {
+        const K key = skey[j];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t pos = gbase[d] + (j - lbase[d]);
+        kout[pos] = key;
+        vout[pos] = sval[j];
     }
 }
 
@@ -170,8 +192,8 @@ static int radix_sort_impl(K *k0, uint32_t *v0, K *k1, uint32_t *v1, int64_t n, 
         hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(256), 0, s, ki, hist, n, shift, (int)nb);
         int e = scan_exclusive_u32(hist, offs, nb * 256, sws, s);
         if (e) return e;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(256), 0, s, ki, vi, ko, vo, offs, n, shift,
-                           (int)nb);
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(256), 0, s, ki, vi, ko, vo, hist, offs, n,
+                           shift, (int)nb);
         if (hipGetLastError() != hipSuccess) return BP_E_HIP;
         K *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
