@@ -501,3 +501,48 @@ def test_pipeline_workspace_protocol(bp):
                                     None, None, bp._ptr(y), bp._ptr(b), None, None, None, 0, C.byref(need),
                                     bp._stream())
     assert e == bp.BP_OK and need.value == 0
+
+
+def test_pipeline_from_two_host_threads(bp):
+    """Pipeline calls from two host threads, each on its own stream with its own workspace and maps: the
+    library serialises them on the shared second stream, and every map equals the single-thread result."""
+    import threading
+    import torch
+    from paper_2201_02632_amd.synth import flat_catalogue
+    params = bp.default_params()
+    npix = 256
+    pix = 1.0 * math.pi / 180 / npix
+    cats = [flat_catalogue(3000, 1.0, seed=21), flat_catalogue(1700, 1.0, seed=22)]
+    tens = [{k: T(v) for k, v in c.items()} for c in cats]
+    refs = [_three_calls(bp, params, t, npix, pix)[4:] for t in tens]
+    torch.cuda.synchronize()
+    out = [[None] * 4 for _ in tens]
+    errors = []
+
+    def work(k):
+        try:
+            st = torch.cuda.Stream()
+            ws = bp.Workspace("cuda")
+            t = tens[k]
+            with torch.cuda.stream(st):
+                for r in range(4):
+                    y = torch.zeros((npix, npix), device="cuda")
+                    b = torch.zeros_like(y)
+                    bp.hp_flat_pipeline(params, npix, pix, t["M"], t["c"], t["z"], t["theta_x"], t["theta_y"],
+                                        t["v_los"], y, b, ws=ws)
+                    out[k][r] = (y, b)
+            st.synchronize()
+        except Exception as e:   # reported below, in the test's own thread
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join(timeout=60)
+    assert not any(x.is_alive() for x in th), "a pipeline thread did not finish"
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for k in range(2):
+        for y, b in out[k]:
+            assert torch.equal(y, refs[k][0]) and torch.equal(b, refs[k][1]), k
