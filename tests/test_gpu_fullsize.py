@@ -376,6 +376,142 @@ def test_hp_healpix_fullsize_sampled_pixels(bp, orc):
     assert ey.max() < 1e-5 and eb.max() < 1e-5
 
 
+def _unit(theta, phi):
+    st = np.sin(theta)
+    return np.stack([st * np.cos(phi), st * np.sin(phi), np.cos(theta)], axis=-1)
+
+
+def _circle_dirs(theta0, phi0, psi, nalpha):
+    """Directions at angle psi from (theta0, phi0), at nalpha azimuths: (theta, phi) arrays."""
+    c = _unit(theta0, phi0)
+    e1 = np.array([math.cos(theta0) * math.cos(phi0), math.cos(theta0) * math.sin(phi0), -math.sin(theta0)])
+    e2 = np.array([-math.sin(phi0), math.cos(phi0), 0.0])
+    al = np.linspace(0.0, 2 * math.pi, nalpha, endpoint=False)
+    v = (c[None, :] * math.cos(psi) + (np.cos(al)[:, None] * e1[None, :] + np.sin(al)[:, None] * e2[None, :])
+         * math.sin(psi))
+    return np.arccos(np.clip(v[:, 2], -1.0, 1.0)), np.mod(np.arctan2(v[:, 1], v[:, 0]), 2 * math.pi)
+
+
+def test_hp_healpix_fullsize_edges_and_patch(bp, orc):
+    """All-sky HP at N_side 8192 through the one-call pipeline (the all-sky benchmark's form): the first
+    1e7-halo batch of the all-sky catalogue, checked at ~200 pixels chosen where the deposit takes its
+    special paths: centres within the FP64 membership re-test band |r^2 - R_t^2| <= 2e-6 R_t^2 and just
+    inside and just outside R_t of the 20 largest footprints, just inside r_a where u^2 is re-formed in
+    FP64, a 10 x 10 patch around the largest footprint's centre, and random pixels.  Each is summed by
+    the oracle over every halo that can reach it (r_perp = D_A sin psi, Sec. 5.2 maps)."""
+    import torch
+
+    from paper_2201_02632_amd.synth import sky_catalogue, subsample
+    nside = 8192
+    cat = sky_catalogue(10_000_000, seed=5000)
+    dev = torch.device("cuda")
+    t = {k: torch.as_tensor(v, dtype=torch.float64, device=dev).contiguous() for k, v in cat.items()}
+    params = bp.default_params()
+    npx = 12 * nside * nside
+    y = torch.zeros(npx, dtype=torch.float32, device=dev)
+    b = torch.zeros_like(y)
+    sol, st, _, _ = bp.hp_healpix_pipeline(params, nside, t["M"], t["c"], t["z"], t["theta"], t["phi"], t["v_los"],
+                                           y, b, ws=bp.Workspace(dev))
+    torch.cuda.synchronize()
+    S = bp.SOL
+    DA = sol[S["DA"]].cpu().numpy()
+    Rt = sol[S["RT"]].cpu().numpy()
+    ra = np.minimum(sol[S["RVIR"]].cpu().numpy(), sol[S["RF"]].cpu().numpy())
+    rv = sol[S["RVIR"]].cpu().numpy()
+    st_np = st.cpu().numpy()
+    del sol, t
+    ok = (st_np & ~2) == 0
+    psi_t = np.where(ok, np.arcsin(np.clip(Rt / DA, 0.0, 1.0)), 0.0)
+    big = np.argsort(-psi_t)[:20]
+    rng = np.random.default_rng(23)
+    pixang = math.sqrt(4 * math.pi / npx)
+
+    def r_over(pix, h, R):
+        th, ph = orc.pix2ang_ring(nside, pix)
+        cosd = np.clip(_unit(th, ph) @ _unit(cat["theta"][h], cat["phi"][h]), -1.0, 1.0)
+        return DA[h] * np.sin(np.arccos(cosd)) / R
+
+    band, inside, outside, near_ra = [], [], [], []
+    for h in big:
+        nal = int(min(40000, max(2000, 8 * math.pi * psi_t[h] / pixang)))
+        cand = set()
+        for f in (1.0 - 3e-4, 1.0, 1.0 + 3e-4):
+            th, ph = _circle_dirs(cat["theta"][h], cat["phi"][h], psi_t[h] * f, nal)
+            cand.update(orc.ang2pix_ring(nside, th, ph).tolist())
+        cand = np.array(sorted(cand), dtype=np.int64)
+        q = r_over(cand, h, Rt[h])
+        band += [(p, h) for p in cand[np.abs(q * q - 1.0) <= 2e-6]]
+        inside += [(p, h) for p in cand[(q < 1.0 - 1e-5) & (q > 1.0 - 2e-3)][:2]]
+        outside += [(p, h) for p in cand[(q > 1.0 + 1e-5) & (q < 1.0 + 2e-3)][:2]]
+    # the largest footprints with a zone B (R_t > r_vir, so r_a = r_vir lies inside the footprint)
+    for h in np.argsort(-np.where(Rt > rv, psi_t, 0.0))[:10]:
+        th, ph = _circle_dirs(cat["theta"][h], cat["phi"][h], math.asin(min(0.99 * ra[h] / DA[h], 1.0)), 64)
+        cp = np.unique(orc.ang2pix_ring(nside, th, ph))
+        qa = r_over(cp, h, ra[h])
+        near_ra += [(p, h) for p in cp[(qa > 0.95) & (qa < 1.0)][:2]]
+    band = band[:24]
+    print(f"band {len(band)}, inside {len(inside)}, outside {len(outside)}, near r_a {len(near_ra)}", flush=True)
+    assert len(band) >= 4 and len(inside) >= 20 and len(outside) >= 20 and len(near_ra) >= 10
+    h0 = big[0]
+    g = (np.arange(10) - 4.5) * pixang
+    gth = cat["theta"][h0] + np.repeat(g, 10)
+    gph = cat["phi"][h0] + np.tile(g, 10) / max(math.sin(cat["theta"][h0]), 1e-3)
+    patch = np.unique(orc.ang2pix_ring(nside, gth, np.mod(gph, 2 * math.pi)))
+    rand = rng.integers(0, npx, 30)
+    pix = np.unique(np.concatenate([[p for p, _ in band + inside + outside + near_ra], patch, rand]).astype(np.int64))
+    # candidate halos per pixel: the reach bound of the full-size HEALPix test, on unit vectors
+    om = 0.3
+    zz = np.linspace(0.0, 3.2, 320001)
+    fz = 1.0 / np.sqrt(om * (1 + zz) ** 3 + 1 - om)
+    chi = np.concatenate([[0.0], np.cumsum(0.5 * (fz[1:] + fz[:-1]) * np.diff(zz))]) * 2997.92458
+    DA_low = 0.999 * np.interp(cat["z"], zz, chi) / (1 + cat["z"])
+    rho_c = 2.775e11 * (om * (1 + cat["z"]) ** 3 + 1 - om)
+    bound = np.minimum(3.0 * (3 * cat["M"] / (4 * math.pi * 500.0 * rho_c)) ** (1.0 / 3.0) / DA_low, 1.5)
+    bound = np.where(ok, 1.01 * bound, -1.0)
+    hv = _unit(cat["theta"], cat["phi"])
+    pth, pph = orc.pix2ang_ring(nside, pix)
+    pv = _unit(pth, pph)
+    wide = np.nonzero(bound > 0.02)[0]
+    narrow = np.nonzero((bound > 0.0) & (bound <= 0.02))[0]
+    cand = set()
+    cosb_w = np.cos(bound[wide])
+    for v in pv:                                   # the few wide footprints: every pixel against all of them
+        cand.update(wide[hv[wide] @ v > cosb_w].tolist())
+    # the rest: pixels grouped by the nearest big halo (or alone), then a cap of 0.021 rad around each group
+    groups = {}
+    for k, v in enumerate(pv):
+        dots = hv[big] @ v
+        j = int(np.argmax(dots))
+        key = int(big[j]) if math.acos(min(dots[j], 1.0)) < psi_t[big[j]] * 1.01 + 20 * pixang else -1 - k
+        groups.setdefault(key, []).append(k)
+    hn = hv[narrow]
+    for key, ks in groups.items():
+        cen = pv[ks].mean(axis=0)
+        cen /= np.linalg.norm(cen)
+        rad = max(math.acos(min(float(pv[k] @ cen), 1.0)) for k in ks) + 0.021
+        sel = narrow[hn @ cen > math.cos(rad)]
+        if len(sel) == 0:
+            continue
+        cb = np.cos(bound[sel])
+        for k in ks:
+            cand.update(sel[hv[sel] @ pv[k] > cb].tolist())
+    idx = np.array(sorted(cand), dtype=np.int64)
+    print(f"{len(pix)} pixels, {len(idx)} candidate halos", flush=True)
+    sub = subsample(cat, idx)
+    p = orc.default_params()
+    halos = orc.solve_halos_parallel(p, sub["M"], sub["c"], sub["z"], workers=16)
+    oy, ob = orc.hp_healpix_pixels(p, halos, sub, nside, pix)
+    _, obabs = orc.hp_healpix_pixels(p, halos, dict(sub, v_los=np.abs(sub["v_los"])), nside, pix)
+    gy = y[torch.as_tensor(pix, device=dev)].cpu().numpy().astype(np.float64)
+    gb = b[torch.as_tensor(pix, device=dev)].cpu().numpy().astype(np.float64)
+    ey = np.abs(gy - oy) / (np.abs(oy) + 1e-6 * np.abs(oy).max())
+    eb = np.abs(gb - ob) / (obabs + 1e-6 * max(obabs.max(), 1e-300))
+    k = int(np.argmax(np.maximum(ey, eb)))
+    print(f"max rel err y {ey.max():.2e} b {eb.max():.2e} (pixel {pix[k]}); covered {(oy > 0).sum()} of {len(pix)}")
+    assert (oy > 0).sum() >= len(pix) // 2
+    assert ey.max() < 1e-5 and eb.max() < 1e-5
+
+
 def test_ngp_fullsize_whole_rings(bp, orc):
     # the all-sky nearest-pixel paste as the benchmark runs it (1e9 particles of the continuous light
     # cone, N_side 1024); every pixel of seven rings (polar, cap, the cap/belt boundary, belt,
