@@ -60,7 +60,8 @@ def _ring_pixels(cx, cy, R, npix, frac_lo, frac_hi, limit, rng):
 
 
 def test_hp_flat_fullsize_sampled_pixels(bp, orc):
-    """The 5e5-halo, 4096^2 benchmark map (the benchmark's call) against the oracle on 1,000 pixels in ten
+    """The 5e5-halo, 4096^2 benchmark map (the benchmark's one-call pipeline, which the three separate calls
+    reproduce bit for bit) against the oracle on 1,000 pixels in ten
     random 10x10 patches, plus pixels the plan of the deposit treats specially, at the footprints of the
     five largest halos: inside the band next to the footprint edge where membership is re-decided in FP64
     (reading R23), just inside and just outside that edge, and on either side of r_a where the zone of the
@@ -76,10 +77,17 @@ def test_hp_flat_fullsize_sampled_pixels(bp, orc):
     ws = bp.Workspace(dev)
     y = torch.zeros((npix, npix), dtype=torch.float32, device=dev)
     b = torch.zeros_like(y)
-    sol, st = bp.icm_solve(params, t["M"], t["c"], t["z"])
-    tab, meta = bp.profile_tables(params, sol, st)
-    bp.hp_paste_flat(params, npix, pix, t["theta_x"], t["theta_y"], t["v_los"], sol, st, tab, meta, y, b, ws=ws)
+    sol, st, _, _ = bp.hp_flat_pipeline(params, npix, pix, t["M"], t["c"], t["z"], t["theta_x"], t["theta_y"],
+                                        t["v_los"], y, b, ws=ws)
+    # the three separate calls give the same maps bit for bit
+    y3 = torch.zeros_like(y)
+    b3 = torch.zeros_like(y)
+    sol3, st3 = bp.icm_solve(params, t["M"], t["c"], t["z"])
+    tab3, meta3 = bp.profile_tables(params, sol3, st3)
+    bp.hp_paste_flat(params, npix, pix, t["theta_x"], t["theta_y"], t["v_los"], sol3, st3, tab3, meta3, y3, b3, ws=ws)
     torch.cuda.synchronize()
+    assert torch.equal(y, y3) and torch.equal(b, b3) and torch.equal(sol, sol3)
+    del y3, b3, sol3, st3, tab3, meta3
     y = y.cpu().numpy()
     b = b.cpu().numpy()
     solc = sol.cpu().numpy()
