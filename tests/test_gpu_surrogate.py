@@ -550,13 +550,13 @@ def test_surrogate_save_load_and_one_call_fit(bp):
 
 
 def test_surrogate_flat_4096_map(bp, trained):
-    """The flat-sky benchmark geometry (5x5 deg on 4096^2 pixels, the power-law mass function) with 1e6
-    halos: surrogate path (exact q-tables) against the exact path, per pixel (R24, R28)."""
+    """The flat-sky benchmark geometry and size (5x5 deg on 4096^2 pixels, the power-law mass function,
+    1e7 halos): surrogate path (exact q-tables) against the exact path, per pixel (R24, R28)."""
     import torch
 
     from paper_2201_02632_amd.synth import hp_flat_large
     S = trained
-    cat, npix, pix = hp_flat_large(n=1_000_000, seed=61)
+    cat, npix, pix = hp_flat_large(n=10_000_000, seed=61)
     d = {k: torch.as_tensor(v, dtype=torch.float64, device="cuda").contiguous() for k, v in cat.items()}
     del cat
     ye = torch.zeros((npix, npix), dtype=torch.float32, device="cuda")
@@ -571,7 +571,7 @@ def test_surrogate_flat_4096_map(bp, trained):
     ry = ((ys.double() - ye.double()).abs() / (ye.double().abs() + 1e-6 * ye.double().abs().max()))
     rb = ((bs.double() - be.double()).abs() / (babs.double() + 1e-6 * babs.double().max()))
     Yerr = abs(ys.double().sum() / ye.double().sum() - 1).item()
-    print(f"4096^2 map, 1e6 halos, surrogate (exact tables): integrated-Y err {Yerr:.2e}, per-pixel y max "
+    print(f"4096^2 map, 1e7 halos, surrogate (exact tables): integrated-Y err {Yerr:.2e}, per-pixel y max "
           f"{ry.max().item():.2e}, b max {rb.max().item():.2e}; {nout} fallback halos")
     assert Yerr < 1e-4
     assert ry.max().item() <= 1e-3 and rb.max().item() <= 1e-3
