@@ -336,10 +336,11 @@ __global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const
         // sin(dtheta/2) from the half-angle sines and cosines of the lane's ring
         const double sd = st2 * R.ch2 - ct2 * R.sh2;
         const float A = (float)(sd * sd), B = (float)(sthr * R.sth);
-        // dphi wrapped to [-pi, pi] in FP64 before it is rounded to FP32 (a small angle must not be
-        // carried as 2 pi minus itself)
+        // dphi reduced to [-pi, pi] in FP64 before it is rounded to FP32 (a small angle must not be
+        // carried as 2 pi minus itself): dphi - 2 pi k with k the nearest integer to dphi / (2 pi), one
+        // rounding like the subtraction of 2 pi itself
         double dph = phj - R.ph;
-        dph = (dph > kPi) ? dph - 2.0 * kPi : ((dph < -kPi) ? dph + 2.0 * kPi : dph);
+        dph = fma(-2.0 * kPi, rint(dph * (0.5 / kPi)), dph);
         const float xh = (float)(0.5 * dph);
         const float x2 = xh * xh;
         // sin(x) by its odd series below |x| = 0.1 (error < 2e-11 relative), sinf above
