@@ -35,8 +35,8 @@ DEPOSIT_OPS_PER_PX_DESIGN = 35
 # HBM bytes per deposit launch on this workload: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) scaled by the same counters on a 1 GiB device copy (FETCH x 1.99994, WRITE x 1.0).
 # Valid only for the deposit sources they were measured on.
-DEPOSIT_TRAFFIC = {"bytes": 2256094770,
-                   "sources_sha256": {"bp_hp_flat.hip": "d366f033c4e2e91cd7d983a772f47362ad8321497676156fd8efb9b238ba81e8",
+DEPOSIT_TRAFFIC = {"bytes": 2258189177,
+                   "sources_sha256": {"bp_hp_flat.hip": "e77057e81245cc1482137c6439de988c2b00c851eb605b0a45e3e7818aaa815f",
                                       "bp_footprint.hpp": "7b3efc5f312cb6d1de2754b93b33bee558a3fd0c221587bf447053aec84eee6c"}}
 
 

@@ -187,11 +187,14 @@ int bp_profile_tables(const bp_params *p, int64_t n, const double *sol, const in
  *                      compensation between calls: the call resumes every touched pixel's compensated
  *                      sum from (map, comp) and stores both back, so a sequence of calls (halo batches)
  *                      adds up as one compensated sum.  The caller zeroes them with the maps.
- *   ws, ws_bytes     : device workspace.  If ws_bytes is too small nothing is
- *                      enqueued, *ws_needed receives the size and the call
+ *   ws, ws_bytes     : device workspace.  If ws_bytes is too small the maps are
+ *                      not touched, *ws_needed receives the size and the call
  *                      returns BP_E_WORKSPACE.  The size depends on the
  *                      footprints, so this call synchronises `stream` once to
- *                      read the (halo, tile) pair count.
+ *                      read the (halo, tile) pair count (the pair count is
+ *                      taken in the workspace first, so a call with a
+ *                      workspace big enough for that but not for the pairs
+ *                      asks a second time, with the final size).
  * Each map pixel is owned by one lane; contributions are added in catalogue
  * order with Kahan compensation, so results are deterministic. */
 int bp_hp_paste_flat(const bp_params *p, int32_t npix, double pix_rad, int64_t n,

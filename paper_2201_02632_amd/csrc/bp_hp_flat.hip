@@ -426,10 +426,16 @@ int bp::side_stream_for_current_device(SideStream **out) {
     if (!S.s) {
         // default priority: only the ordering changes, never the scheduling class
         hipStream_t st = nullptr;
+        hipEvent_t e1 = nullptr, e2 = nullptr;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return BP_E_HIP;
-        if (hipEventCreateWithFlags(&S.meta_ready, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&S.plan_done, hipEventDisableTiming) != hipSuccess)
+        if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
+            if (e1) (void)hipEventDestroy(e1);
+            (void)hipStreamDestroy(st);
             return BP_E_HIP;
+        }
+        S.meta_ready = e1;
+        S.plan_done = e2;
         S.s = st;
     }
     *out = &S;
