@@ -286,6 +286,50 @@ def test_healpix_pixel_geometry_8192(orc):
     assert abs(gf["field_deg"] * 3600 / gf["n"] - gf["pixel_arcsec"]) < 5e-3
 
 
+def test_hp_healpix_conservation_and_sign(orc, params):
+    """The oracle's HEALPix HP map (r_perp = D_A sin psi on the sphere, Sec. 5.2 maps) for one nearby halo:
+    the sum of y over the pixels times the pixel solid angle is the integral of y over the solid angle of
+    the footprint, int_0^psi_t y(D_A sin psi) 2 pi sin psi dpsi, to the pixel-centre sampling error; the
+    pixel nearest the centre holds the line-of-sight integral at its own r_perp; the kSZ map changes sign
+    with v."""
+    M, c, z, th0, ph0 = 2e14, 5.0, 0.05, 1.0, 2.0
+    h = orc.solve_halo(params, M, c, z)
+    assert h.status == 0
+    nside = 4096
+    pixsize = math.sqrt(4 * math.pi / (12 * nside * nside))
+    psi_t = math.asin(h.R_t / h.D_A)
+    # every pixel whose centre can lie within psi_t: a grid of directions at a third of the pixel size
+    g = np.arange(-psi_t - 2 * pixsize, psi_t + 2 * pixsize, pixsize / 3)
+    gt = (th0 + g[:, None] + 0 * g[None, :]).ravel()
+    gp = (ph0 + g[None, :] / math.sin(th0) + 0 * g[:, None]).ravel()
+    pix = np.unique(orc.ang2pix_ring(nside, gt, gp))
+    pt, pp = orc.pix2ang_ring(nside, pix)
+    cospsi = np.sin(pt) * math.sin(th0) * np.cos(pp - ph0) + np.cos(pt) * math.cos(th0)
+    pix = pix[cospsi > math.cos(psi_t + pixsize)]
+    assert len(pix) > 3000
+    halos = orc.solve_halos(params, [M], [c], [z])
+    cat = dict(theta=[th0], phi=[ph0], v_los=[300.0])
+    y, b = orc.hp_healpix_pixels(params, halos, cat, nside, pix)
+    y2, b2 = orc.hp_healpix_pixels(params, halos, dict(cat, v_los=[-300.0]), nside, pix)
+    assert np.array_equal(y2, y) and np.array_equal(b2, -b)
+    # no footprint pixel left out: the ring of candidates beyond psi_t is empty
+    pt, pp = orc.pix2ang_ring(nside, pix)
+    cospsi = np.sin(pt) * math.sin(th0) * np.cos(pp - ph0) + np.cos(pt) * math.cos(th0)
+    psi = np.arccos(np.clip(cospsi, -1, 1))
+    assert np.all(y[psi > psi_t * (1 + 1e-9)] == 0) and np.all(y[psi < psi_t * (1 - 1e-6)] > 0)
+    ref = integrate.quad(lambda a: orc.los(params, h, h.D_A * math.sin(a))[0] * 2 * math.pi * math.sin(a), 0, psi_t,
+                         points=[math.asin(h.r_vir / h.D_A)] if h.r_vir < h.R_t else None, epsabs=0,
+                         epsrel=1e-10, limit=200)[0]
+    Ymap = y.sum() * 4 * math.pi / (12 * nside * nside)
+    assert abs(Ymap / ref - 1) < 2e-3
+    k = int(np.argmin(psi))
+    # sin(psi) of that pixel from the cross product of the unit vectors (arccos loses digits near 0)
+    pv = np.array([math.sin(pt[k]) * math.cos(pp[k]), math.sin(pt[k]) * math.sin(pp[k]), math.cos(pt[k])])
+    hv = np.array([math.sin(th0) * math.cos(ph0), math.sin(th0) * math.sin(ph0), math.cos(th0)])
+    sinpsi = float(np.linalg.norm(np.cross(pv, hv)))
+    assert abs(y[k] / orc.los(params, h, h.D_A * sinpsi)[0] - 1) < 1e-12
+
+
 # ----------------------------------------------------------------------- PP --
 def test_sph_kernel_integral(orc):
     g = GOLD["sph_kernel_norm"]
