@@ -123,8 +123,9 @@ __host__ __device__ inline int64_t tile_first_pixel(int64_t t, int64_t npr, int6
 
 // Visit the tiles a halo's disc can touch.  For each ring the disc reaches, the longitudes of
 // its pixels that can be members lie within dphi_max of the halo (padded by two pixel steps for
-// rounding); per band the union of these intervals (they all contain the halo's longitude) is
-// cut into the band's tiles.  f(first, last) is called for runs of consecutive tiles (inclusive)
+// rounding); per band an interval containing all of these (they are centred on the halo's
+// longitude: the band's largest dphi_max with the pad of its coarsest ring, so one arcsine per band)
+// is cut into the band's tiles.  f(first, last) is called for runs of consecutive tiles (inclusive)
 // in a deterministic order; count and emit use this same routine.  sin((theta_r - theta_h)/2) comes from the half-angle sines and cosines.
 template <class F>
 __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const RingRec *__restrict__ rtab,
@@ -139,12 +140,17 @@ __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const Ri
     if (ihi > 4 * G.N - 1) ihi = 4 * G.N - 1;
     int band = -1;
     bool any = false, whole = false;
-    double flo = 0.0, fhi = 0.0;
+    double qmax = 0.0;      // largest sin^2(dphi/2) bound over the band's rings
+    int64_t nprmin = 0;     // fewest pixels of a ring in the band (the widest rounding pad)
     auto flush = [&]() {
         if (!any) return;
         const int nmax = rtab[kBand * band].nmax;
         const int T = (nmax + kTw - 1) / kTw;
         const uint32_t base = btile0[band];
+        // one half-width for the whole band: the largest ring's, padded by two steps of its coarsest
+        // ring (a superset of the rings' own intervals, which all contain the halo's longitude)
+        const double w = whole ? kTwoPi : 2.0 * asin(sqrt(qmax)) + 2.0 * kTwoPi / (double)nprmin;
+        const double flo = R.ph - w, fhi = R.ph + w;
         if (!whole && fhi - flo < kTwoPi) {
             const double tpr = (double)nmax / (kTw * kTwoPi);   // tiles per radian
             auto tl = [&](double x) { return (int)fmin(fmax(floor(x * tpr), 0.0), (double)(T - 1)); };
@@ -175,10 +181,8 @@ __device__ inline void for_each_tile(const HpxGeom &G, const HpxRec &R, const Ri
         const double B = Rg.sth * R.sth;
         const double q = (B > 0.0) ? (hmax - A) / B : 2.0;
         if (q >= 1.0) { whole = true; any = true; continue; }
-        const double w = 2.0 * asin(sqrt(q)) + 2.0 * kTwoPi / (double)Rg.npr;
-        const double lo = R.ph - w, hi = R.ph + w;
-        if (!any) { flo = lo; fhi = hi; }
-        else { flo = fmin(flo, lo); fhi = fmax(fhi, hi); }
+        if (!any) { qmax = q; nprmin = Rg.npr; }
+        else { qmax = fmax(qmax, q); nprmin = min(nprmin, (int64_t)Rg.npr); }
         any = true;
     }
     flush();
