@@ -291,7 +291,7 @@ __device__ inline bool hpx_inside_fp64(double tp, double pp, double th, double p
 }
 
 template <bool kQ>
-__global__ void __launch_bounds__(256) k_hpx_deposit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_hpx_deposit(HpxGeom G, int64_t n, const HpxRec *__restrict__ rec,
                                                      const float *__restrict__ tables, const uint32_t *__restrict__ vals,
                                                      const uint32_t *__restrict__ tstart, const uint32_t *__restrict__ tend,
                                                      const uint32_t *__restrict__ btile0, int32_t nbands,
