@@ -465,12 +465,14 @@ k_pp_knn(int64_t n, Grid g, int k, const uint64_t *__restrict__ key, const uint3
 
 // With a list, thread t runs the sorted particle list[t] for t < *nlist: the particles the 64-NN
 // list could not settle (h_io = -(32-NN distance)), packed so that a wavefront's lanes all work.
-__global__ void __launch_bounds__(256) k_pp_neff(int64_t n, Grid g, float nngb, float seed_scale,
-                                                 const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
-                                                 const double *__restrict__ sp, const uint32_t *__restrict__ cstart,
-                                                 const uint32_t *__restrict__ cend, float *__restrict__ h_io,
-                                                 int *__restrict__ fail, const uint32_t *__restrict__ list,
-                                                 const uint32_t *__restrict__ nlist) {
+// 5 waves per SIMD: 96 VGPRs (104 unconstrained, four waves)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_pp_neff(int64_t n, Grid g, float nngb, float seed_scale,
+          const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
+          const double *__restrict__ sp, const uint32_t *__restrict__ cstart,
+          const uint32_t *__restrict__ cend, float *__restrict__ h_io,
+          int *__restrict__ fail, const uint32_t *__restrict__ list,
+          const uint32_t *__restrict__ nlist) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (list) {
         if (i >= (int64_t)*nlist) return;
@@ -786,10 +788,12 @@ __device__ inline void kahan(float &s, float &c, float v) {
 }
 
 // narrow particles: one wavefront per 16x16 tile, lane = column (l & 15) x 4 rows
-__global__ void __launch_bounds__(256) k_pp_deposit_narrow(int npix, double pix, int ntx, uint32_t ntiles,
-                                                           const PPRec *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                                           const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
-                                                           float *__restrict__ ymap, float *__restrict__ bmap) {
+// 7 waves per SIMD: 69 VGPRs (74 unconstrained, six waves)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7)))
+k_pp_deposit_narrow(int npix, double pix, int ntx, uint32_t ntiles,
+                    const PPRec *__restrict__ rec, const uint32_t *__restrict__ vals,
+                    const uint32_t *__restrict__ ts, const uint32_t *__restrict__ te,
+                    float *__restrict__ ymap, float *__restrict__ bmap) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + wave;
     if (tile >= ntiles) return;
@@ -844,10 +848,12 @@ __global__ void __launch_bounds__(256) k_pp_deposit_narrow(int npix, double pix,
 constexpr int kBatch = 8;
 constexpr int kRecWords = sizeof(PPRec) / 4;
 typedef float fx4 __attribute__((ext_vector_type(4)));
-__global__ void __launch_bounds__(256) k_pp_deposit_wide(int npix, double pix, int ntx, const PPRec *__restrict__ rec,
-                                                         const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ts,
-                                                         const uint32_t *__restrict__ te, float *__restrict__ ymap,
-                                                         float *__restrict__ bmap) {
+// 4 waves per SIMD: 121 VGPRs (144 unconstrained, three waves)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_pp_deposit_wide(int npix, double pix, int ntx, const PPRec *__restrict__ rec,
+                  const uint32_t *__restrict__ vals, const uint32_t *__restrict__ ts,
+                  const uint32_t *__restrict__ te, float *__restrict__ ymap,
+                  float *__restrict__ bmap) {
     // x-weights by particle; y-weights by row (a row's batch contiguous, padded against bank conflicts)
     __shared__ float wxs[kBatch][kWT];
     __shared__ float wys[kWT][kBatch + 1];
